@@ -1,0 +1,946 @@
+/*
+ * nbo.c -- CPU oracle for the bulb-model radial stepper: plain, slow FP64 C.
+ *
+ * TEST INFRASTRUCTURE ONLY (see nbo.h).  Nothing in the product path links this file.
+ *
+ * What is computed, and where the paper defines it:
+ *   - bins equal in E and in u = sin^2(theta_R)                    (Sec. 3.2)
+ *   - H_vac (2f form in Sec. 2; 3f = U diag(0,dm21,dm31) U^+/2E),
+ *     H_mat = sqrt2 G_F n_e diag(1,0[,0])                          (Sec. 2)
+ *   - H_nunu from the beam sum of Eq. Hnu with the weights of F;
+ *     the cos(theta') integral at radius r is done over the emission variable u,
+ *     d cos(theta') = (R^2/2r^2) du / cos(theta'), which factors H_nunu into two
+ *     moments J0 = sum g rho~/c and J1 = sum g rho~                (Eqs. Hnu, F)
+ *   - antineutrinos evolve with H_vac - H_mat - H_nunu^*           (Eq. eom)
+ *   - initial states: flavour eigenstates at the start radius      (Sec. 3.4)
+ *   - one-step propagator exp(-i H dl), dl = dr / cos(theta)       (Eq. U)
+ *     used as the exponential map of a Lie-group RK4 (Munthe-Kaas 1999):
+ *       F_i = -i (h/c) H(r_i, Y_i),  Y_1 = rho_n,
+ *       Y_2 = e^{F_1/2} rho_n e^{-F_1/2},
+ *       Y_3 = e^{F_2/2 - [F_1,F_2]/8} ...,  Y_4 = e^{F_3} ...,
+ *       rho_{n+1} = e^{Theta} rho_n e^{-Theta},
+ *       Theta = (F_1 + 2F_2 + 2F_3 + F_4)/6 - [F_1,F_4]/12.
+ *     Two flavours: rho = (1 + P.sigma)/2 and e^{F} rotates P about (h/c)B by |(h/c)B|,
+ *     with H = B.sigma/2 + trace (so [X,Y] maps to the cross product).
+ *     Three flavours: the state is the wavefunction psi of Eq. psi (rho = psi psi^+);
+ *     e^{-iK} psi is evaluated exactly (isolated eigenvector + a 2x2 block by Eq. U).
+ *
+ * Pins (tests/test_oracle_pins.py): units against hand values, spectra against
+ * quadrature, sin/cos against libm, rotations and exp(-iK) against SciPy, the fixed-point
+ * sum against exact rationals, vacuum and constant-density MSW closed forms (2f and 3f),
+ * the factored H_nunu against the direct beam-pair sum of Eq. Hnu, norm conservation,
+ * the flux-weighted polarisation invariant, single-angle = one angle bin, two tracked
+ * species = every flavour explicit, 4th-order convergence, plain RK4 agreement.
+ * The full nonlinear bulb evolution at benchmark scale has no external reference (the
+ * paper's result is a figure without data): parity unpinned beyond its parts.
+ *
+ * Arithmetic specification.  The GPU library implements the same operation order
+ * from its own sources, so that results agree bit for bit on any input:
+ *   - no contraction (built with -ffp-contract=off); fma() only where written;
+ *   - sin/cos: own Cody-Waite reduction + Taylor polynomials (sincos_spec);
+ *   - moment sums are exact fixed-point integer sums, independent of order.
+ */
+#include "nbo.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef __int128 i128;
+
+/* ---------------------------------------------------------------- constants */
+/* sqrt(2) G_F (hbar c)^3 expressed in km^-1 cm^3 (G_F = 1.1663787e-5 GeV^-2,
+ * hbar c = 1.973269804e-14 GeV cm = 1.973269804e-19 GeV km). */
+static double sqrt2gf_km_cm3(void) {
+  const double hc_cm = 1.973269804e-14, hc_km = 1.973269804e-19;
+  return (1.4142135623730951 * 1.1663787e-5) * ((hc_cm * hc_cm) * hc_cm) / hc_km;
+}
+#define VAC_K (1.0 / (4.0e6 * 1.973269804e-10)) /* dm^2[eV^2]/(4E[MeV]) -> km^-1 */
+#define ERG_MEV 624150.9074460763
+#define C_CM_S 2.99792458e10
+#define PI_D 3.141592653589793
+#define F2_0 1.8030853547393914  /* int x^2/(e^x+1) = 3 zeta(3)/2 */
+#define F3_0 5.682196976983475   /* int x^3/(e^x+1) = 7 pi^4/120 */
+#define TWO62 4611686018427387904.0
+#define TWO64 18446744073709551616.0
+
+/* --------------------------------------------------------------- sin / cos */
+/* Cody-Waite reduction by pi/2 (three-part split, fma), Taylor polynomials of
+ * degree 17 (sin) and 18 (cos) on |r| <= pi/4. */
+static const double TWO_OVER_PI = 0x1.45f306dc9c883p-1;
+static const double PIO2_HI = 0x1.921fb54442d18p+0;
+static const double PIO2_MID = 0x1.1a62633145c07p-54;
+static const double PIO2_LO = -0x1.f1976b7ed8fbcp-110;
+
+static void sincos_spec(double x, double *sn, double *cs) {
+  const double k = rint(x * TWO_OVER_PI);
+  double r = fma(-k, PIO2_HI, x);
+  r = fma(-k, PIO2_MID, r);
+  r = fma(-k, PIO2_LO, r);
+  const double r2 = r * r;
+  double ps = 1.0 / 355687428096000.0;
+  ps = fma(ps, r2, -1.0 / 1307674368000.0);
+  ps = fma(ps, r2, 1.0 / 6227020800.0);
+  ps = fma(ps, r2, -1.0 / 39916800.0);
+  ps = fma(ps, r2, 1.0 / 362880.0);
+  ps = fma(ps, r2, -1.0 / 5040.0);
+  ps = fma(ps, r2, 1.0 / 120.0);
+  ps = fma(ps, r2, -1.0 / 6.0);
+  const double s = fma(r2 * r, ps, r);
+  double pc = -1.0 / 6402373705728000.0;
+  pc = fma(pc, r2, 1.0 / 20922789888000.0);
+  pc = fma(pc, r2, -1.0 / 87178291200.0);
+  pc = fma(pc, r2, 1.0 / 479001600.0);
+  pc = fma(pc, r2, -1.0 / 3628800.0);
+  pc = fma(pc, r2, 1.0 / 40320.0);
+  pc = fma(pc, r2, -1.0 / 720.0);
+  pc = fma(pc, r2, 1.0 / 24.0);
+  pc = fma(pc, r2, -0.5);
+  const double c = fma(r2, pc, 1.0);
+  switch ((int)((long long)k & 3)) {
+    case 0: *sn = s; *cs = c; break;
+    case 1: *sn = c; *cs = -s; break;
+    case 2: *sn = -s; *cs = -c; break;
+    default: *sn = -c; *cs = s; break;
+  }
+}
+
+/* ------------------------------------------------------------- fixed point */
+/* One contribution v becomes the integer trunc(v 2^e); |v 2^e| < 2^62 is required. */
+static inline int64_t to_fix(double v, double scale, int *err) {
+  const double x = v * scale;
+  if (!(fabs(x) < TWO62)) { *err = 1; return 0; }
+  return (int64_t)x;
+}
+/* Integer -> double in sign-magnitude form: |x| = hi 2^64 + lo, each half converted
+ * (round to nearest) and added; the sign is applied last. */
+static inline double i128_to_double(i128 x) {
+  const int neg = x < 0;
+  const unsigned __int128 a = neg ? (unsigned __int128)(-x) : (unsigned __int128)x;
+  const uint64_t hi = (uint64_t)(a >> 64), lo = (uint64_t)a;
+  const double v = (double)hi * TWO64 + (double)lo;
+  return neg ? -v : v;
+}
+
+/* ---------------------------------------------------------- complex helpers */
+typedef struct { double re, im; } cx;
+static inline cx cx_make(double re, double im) { cx r; r.re = re; r.im = im; return r; }
+static inline cx cx_mul(cx a, cx b) {
+  return cx_make(fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re));
+}
+static inline cx cx_mulc(cx a, cx b) { /* a * conj(b) */
+  return cx_make(fma(a.re, b.re, a.im * b.im), fma(a.im, b.re, -(a.re * b.im)));
+}
+static inline cx cx_cjmul(cx a, cx b) { /* conj(a) * b */
+  return cx_make(fma(a.re, b.re, a.im * b.im), fma(a.re, b.im, -(a.im * b.re)));
+}
+static inline cx cx_rmul(double a, cx b) { return cx_make(a * b.re, a * b.im); }
+static inline cx cx_add(cx a, cx b) { return cx_make(a.re + b.re, a.im + b.im); }
+static inline cx cx_sub(cx a, cx b) { return cx_make(a.re - b.re, a.im - b.im); }
+static inline cx cx_conj(cx a) { return cx_make(a.re, -a.im); }
+static inline double cx_norm2(cx a) { return fma(a.re, a.re, a.im * a.im); }
+
+/* Hermitian 3x3: real diagonal d[0..2], upper off-diagonals o[0]=(0,1), o[1]=(0,2), o[2]=(1,2). */
+typedef struct { double d[3]; cx o[3]; } herm3;
+static inline cx h3_at(const herm3 *h, int a, int b) {
+  if (a == b) return cx_make(h->d[a], 0.0);
+  if (a < b) return h->o[a + b - 1];
+  return cx_conj(h->o[a + b - 1]);
+}
+
+/* C(A,B) = i [A,B] (Hermitian for Hermitian A, B). */
+static herm3 h3_icomm(const herm3 *A, const herm3 *B) {
+  cx X[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      X[a][b] = cx_add(cx_add(cx_mul(h3_at(A, a, 0), h3_at(B, 0, b)),
+                              cx_mul(h3_at(A, a, 1), h3_at(B, 1, b))),
+                       cx_mul(h3_at(A, a, 2), h3_at(B, 2, b)));
+  herm3 C;
+  for (int a = 0; a < 3; ++a) C.d[a] = -2.0 * X[a][a].im;
+  const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+  for (int t = 0; t < 3; ++t) {
+    const cx xab = X[pa[t]][pb[t]], xba = X[pb[t]][pa[t]];
+    const double dre = xab.re - xba.re, dim = xab.im + xba.im;
+    C.o[t] = cx_make(-dim, dre);
+  }
+  return C;
+}
+
+static inline cx cross_c(const cx u[3], const cx v[3], int comp) {
+  const int a = (comp + 1) % 3, b = (comp + 2) % 3;
+  return cx_sub(cx_mul(u[a], v[b]), cx_mul(u[b], v[a]));
+}
+static inline cx inner3(const cx u[3], const cx v[3]) { /* u^+ v */
+  return cx_add(cx_add(cx_cjmul(u[0], v[0]), cx_cjmul(u[1], v[1])), cx_cjmul(u[2], v[2]));
+}
+
+/* psi' = exp(-i K) psi up to a global phase, for Hermitian K.
+ * exp(-iK) = e^{-i l1} v1 v1^+ + W exp(-i K') W^+ with l1 the eigenvalue of largest
+ * magnitude of the traceless part (simple and well separated), v1 its eigenvector,
+ * W an orthonormal basis of the complement and K' = W^+ K W; exp(-iK') is the 2x2
+ * propagator of Eq. U.  The traces of K and K' only contribute global phases. */
+static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
+  const double tr = ((K->d[0] + K->d[1]) + K->d[2]) * (1.0 / 3.0);
+  const double a0 = K->d[0] - tr, a1 = K->d[1] - tr, a2 = K->d[2] - tr;
+  const cx x = K->o[0], y = K->o[1], z = K->o[2];
+  const double nx = cx_norm2(x), ny = cx_norm2(y), nz = cx_norm2(z);
+  const double s2 = fma(a0, a0, fma(a1, a1, a2 * a2));
+  const double p = fma(0.5, s2, (nx + ny) + nz);               /* Tr K0^2 / 2 */
+  const cx xz = cx_mul(x, z);
+  const double t = fma(xz.re, y.re, xz.im * y.im);             /* Re(x z conj(y)) */
+  const double q = fma(a0, fma(a1, a2, -nz), fma(-a1, ny, fma(-a2, nx, 2.0 * t))); /* det */
+  if (!(p > 0.0)) { out[0] = psi[0]; out[1] = psi[1]; out[2] = psi[2]; return; }
+  /* largest-magnitude root of l^3 - p l - q: Newton from 2 sqrt(p/3) on the |q| problem */
+  const double sg = (q < 0.0) ? -1.0 : 1.0;
+  const double qa = sg * q;
+  double lam = 2.0 * sqrt(p * (1.0 / 3.0));
+  for (int it = 0; it < 6; ++it) {
+    const double l2 = lam * lam;
+    const double fv = fma(lam, l2 - p, -qa);
+    const double dv = fma(3.0, l2, -p);
+    lam = lam - fv / dv;
+  }
+  const double l1 = sg * lam;
+  /* eigenvector: largest cross product of two rows of K0 - l1 I */
+  const cx r0[3] = {cx_make(a0 - l1, 0.0), x, y};
+  const cx r1[3] = {cx_conj(x), cx_make(a1 - l1, 0.0), z};
+  const cx r2[3] = {cx_conj(y), cx_conj(z), cx_make(a2 - l1, 0.0)};
+  cx c01[3], c02[3], c12[3];
+  for (int c = 0; c < 3; ++c) {
+    c01[c] = cross_c(r0, r1, c);
+    c02[c] = cross_c(r0, r2, c);
+    c12[c] = cross_c(r1, r2, c);
+  }
+  const double n01 = (cx_norm2(c01[0]) + cx_norm2(c01[1])) + cx_norm2(c01[2]);
+  const double n02 = (cx_norm2(c02[0]) + cx_norm2(c02[1])) + cx_norm2(c02[2]);
+  const double n12 = (cx_norm2(c12[0]) + cx_norm2(c12[1])) + cx_norm2(c12[2]);
+  const cx *best = c01;
+  double nb = n01;
+  if (n02 > nb) { best = c02; nb = n02; }
+  if (n12 > nb) { best = c12; nb = n12; }
+  if (!(nb > 0.0)) { out[0] = psi[0]; out[1] = psi[1]; out[2] = psi[2]; return; }
+  const double inb = 1.0 / sqrt(nb);
+  cx v1[3];
+  for (int c = 0; c < 3; ++c) v1[c] = cx_rmul(inb, best[c]);
+  /* complement: Gram-Schmidt of the axis where v1 is smallest, then conj(v1 x w2) */
+  double nc[3];
+  for (int c = 0; c < 3; ++c) nc[c] = cx_norm2(v1[c]);
+  int m = 0;
+  if (nc[1] < nc[m]) m = 1;
+  if (nc[2] < nc[m]) m = 2;
+  cx w[3];
+  for (int c = 0; c < 3; ++c) {
+    if (c == m) w[c] = cx_make(1.0 - nc[m], 0.0);
+    else {
+      const cx tm = cx_mulc(v1[c], v1[m]);
+      w[c] = cx_make(-tm.re, -tm.im);
+    }
+  }
+  const double nw = (cx_norm2(w[0]) + cx_norm2(w[1])) + cx_norm2(w[2]);
+  const double inw = 1.0 / sqrt(nw);
+  cx w2[3], w3[3];
+  for (int c = 0; c < 3; ++c) w2[c] = cx_rmul(inw, w[c]);
+  for (int c = 0; c < 3; ++c) w3[c] = cx_conj(cross_c(v1, w2, c));
+  /* K' = W^+ K0 W */
+  cx kw2[3], kw3[3];
+  const cx *vv[2] = {w2, w3};
+  cx *kv[2] = {kw2, kw3};
+  for (int i = 0; i < 2; ++i) {
+    const cx *v = vv[i];
+    kv[i][0] = cx_add(cx_add(cx_rmul(a0, v[0]), cx_mul(x, v[1])), cx_mul(y, v[2]));
+    kv[i][1] = cx_add(cx_add(cx_cjmul(x, v[0]), cx_rmul(a1, v[1])), cx_mul(z, v[2]));
+    kv[i][2] = cx_add(cx_add(cx_cjmul(y, v[0]), cx_cjmul(z, v[1])), cx_rmul(a2, v[2]));
+  }
+  const double k22 = inner3(w2, kw2).re, k33 = inner3(w3, kw3).re;
+  const cx k23 = inner3(w2, kw3);
+  const double hm = 0.5 * (k22 + k33), h11 = 0.5 * (k22 - k33);
+  const double phi = l1 - hm;
+  const double th = sqrt(fma(h11, h11, cx_norm2(k23)));
+  double sp, cp, st, ct;
+  sincos_spec(phi, &sp, &cp);
+  sincos_spec(th, &st, &ct);
+  const double sc = (th > 0.0) ? st / th : 0.0;
+  const cx al = cx_mul(inner3(v1, psi), cx_make(cp, -sp));
+  const cx b2 = inner3(w2, psi), b3 = inner3(w3, psi);
+  const double hs = h11 * sc;
+  const cx g = cx_make(k23.re * sc, k23.im * sc);
+  const cx t2 = cx_add(cx_rmul(hs, b2), cx_mul(g, b3));
+  const cx t3 = cx_sub(cx_cjmul(g, b2), cx_rmul(hs, b3));
+  const cx b2n = cx_make(ct * b2.re + t2.im, ct * b2.im - t2.re);
+  const cx b3n = cx_make(ct * b3.re + t3.im, ct * b3.im - t3.re);
+  for (int c = 0; c < 3; ++c)
+    out[c] = cx_add(cx_add(cx_mul(al, v1[c]), cx_mul(b2n, w2[c])), cx_mul(b3n, w3[c]));
+}
+
+/* Rotation of the Bloch vector P about x by the angle |x| (2x2 form of Eq. U as a
+ * unit quaternion (cos|x|/2, sin(|x|/2) x/|x|)). */
+static void rotate2(const double x[3], const double P[3], double out[3]) {
+  const double t2 = (x[0] * x[0] + x[1] * x[1]) + x[2] * x[2];
+  const double th = sqrt(t2);
+  if (th == 0.0) { out[0] = P[0]; out[1] = P[1]; out[2] = P[2]; return; }
+  double s, c;
+  sincos_spec(0.5 * th, &s, &c);
+  const double k = s / th;
+  const double v0 = x[0] * k, v1 = x[1] * k, v2 = x[2] * k;
+  double t0 = v1 * P[2] - v2 * P[1];
+  double t1 = v2 * P[0] - v0 * P[2];
+  double tt = v0 * P[1] - v1 * P[0];
+  t0 = t0 + t0; t1 = t1 + t1; tt = tt + tt;
+  const double u0 = v1 * tt - v2 * t1;
+  const double u1 = v2 * t0 - v0 * tt;
+  const double u2 = v0 * t1 - v1 * t0;
+  out[0] = (P[0] + c * t0) + u0;
+  out[1] = (P[1] + c * t1) + u1;
+  out[2] = (P[2] + c * tt) + u2;
+}
+
+/* ------------------------------------------------------------------- model */
+struct nbo_model {
+  nbo_params p;
+  int nf, ncomp, nsc;       /* flavours, moment components, state components */
+  int ns;                   /* species rows */
+  int anti[6], init_flav[6];
+  int64_t NE, NU, nb;
+  double dE, du, h, R, lam0, kappa0;
+  double *E, *w;            /* E[k]; w[s*NE + k] (includes kappa0 du dE) */
+  double *bv;               /* 2f: bx,bz per k; 3f: 6 per k (d0,d1,d2,o01,o02,o12) */
+  double s1, s0, p2e1, p2e0;/* fixed-point scales 2^e1, 2^e0 and their inverses */
+  int e1, e0;
+  double *X;                /* state [nb][nsc] */
+  double *Y;                /* stage scratch [nb][nsc] */
+  int64_t step;
+};
+
+typedef struct { double r, q, q2, lam, mu; } radial;
+
+static radial radial_at(const nbo_model *m, double r) {
+  radial g;
+  g.r = r;
+  g.q = m->R / r;
+  g.q2 = g.q * g.q;
+  double qp = 1.0;
+  for (int i = 0; i < m->p.ne_power; ++i) qp = qp * g.q;
+  g.lam = m->lam0 * qp;     /* sqrt2 G_F n_e(r) */
+  g.mu = 0.5 * g.q2;        /* R^2/(2 r^2): Jacobian of d cos(theta') -> du */
+  return g;
+}
+static inline double u_of(const nbo_model *m, int64_t j) { return ((double)j + 0.5) / (double)m->NU; }
+static inline double c_of(const radial *g, double u) { return sqrt(1.0 - u * g->q2); }
+
+static double fermi_dirac(double E, double T) {
+  return (E * E) / ((F2_0 * ((T * T) * T)) * (exp(E / T) + 1.0));
+}
+
+int nbo_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#endif
+  return n;
+}
+
+int nbo_create(const nbo_params *p, nbo_model **out) {
+  *out = NULL;
+  if (!p || (p->n_flavor != 2 && p->n_flavor != 3) || p->n_energy < 1 || p->n_u < 1 ||
+      p->n_steps < 1 || !(p->r_start_km >= p->r_nu_km) || !(p->r_end_km > p->r_start_km) ||
+      !(p->e_max_mev > p->e_min_mev) || !(p->e_min_mev > 0.0) || p->delta_cp != 0.0 ||
+      p->ne_power < 0 || p->ne_power > 8 || !(p->r_nu_km > 0.0))
+    return NBO_EINVAL;
+  for (int i = 0; i < 3; ++i)
+    if (!(p->temp_mev[i] > 0.0) || !(p->lum_erg_s[i] >= 0.0)) return NBO_EINVAL;
+  nbo_model *m = (nbo_model *)calloc(1, sizeof(nbo_model));
+  m->p = *p;
+  m->nf = p->n_flavor;
+  m->ncomp = (m->nf == 2) ? 3 : 8;
+  m->nsc = (m->nf == 2) ? 3 : 6;
+  m->NE = p->n_energy;
+  m->NU = p->n_u;
+  /* species rows: two tracked (nu_e-born, anti-nu_e-born) or every flavour explicitly */
+  if (!p->species4) {
+    m->ns = 2;
+    m->anti[0] = 0; m->init_flav[0] = 0;
+    m->anti[1] = 1; m->init_flav[1] = 0;
+  } else {
+    m->ns = 2 * m->nf;
+    for (int s = 0; s < m->ns; ++s) { m->anti[s] = s / m->nf; m->init_flav[s] = s % m->nf; }
+  }
+  m->nb = (int64_t)m->ns * m->NU * m->NE;
+  m->dE = (p->e_max_mev - p->e_min_mev) / (double)m->NE;
+  m->du = 1.0 / (double)m->NU;
+  m->h = (p->r_end_km - p->r_start_km) / (double)p->n_steps;
+  m->R = p->r_nu_km;
+  const double s2gf = sqrt2gf_km_cm3();
+  m->lam0 = s2gf * p->n0_cm3;
+  const double rcm = m->R * 1.0e5;
+  m->kappa0 = s2gf / (((2.0 * PI_D) * (rcm * rcm)) * C_CM_S);
+  m->E = (double *)malloc(sizeof(double) * m->NE);
+  m->w = (double *)malloc(sizeof(double) * m->NE * m->ns);
+  m->bv = (double *)malloc(sizeof(double) * m->NE * (m->nf == 2 ? 2 : 6));
+  m->X = (double *)malloc(sizeof(double) * m->nb * m->nsc);
+  m->Y = (double *)malloc(sizeof(double) * m->nb * m->nsc);
+  /* number luminosities N = L / <E>, <E> = T F3/F2 (Fermi-Dirac, zero chemical potential) */
+  double N[3];
+  for (int a = 0; a < 3; ++a) N[a] = p->lum_erg_s[a] * ERG_MEV / ((p->temp_mev[a] * F3_0) / F2_0);
+  const double pref = (m->kappa0 * m->du) * m->dE;
+  for (int64_t k = 0; k < m->NE; ++k) {
+    const double E = p->e_min_mev + ((double)k + 0.5) * m->dE;
+    m->E[k] = E;
+    const double fe = fermi_dirac(E, p->temp_mev[0]);
+    const double fb = fermi_dirac(E, p->temp_mev[1]);
+    const double fx = fermi_dirac(E, p->temp_mev[2]);
+    if (!p->species4) {
+      /* nu_x-born states are I - rho_e (unitarity), so they enter with -N_x f_x */
+      m->w[0 * m->NE + k] = pref * (N[0] * fe - N[2] * fx);
+      m->w[1 * m->NE + k] = pref * (N[1] * fb - N[2] * fx);
+    } else {
+      for (int s = 0; s < m->ns; ++s) {
+        const int a = m->anti[s], fl = m->init_flav[s];
+        double Nf;
+        if (fl == 0) Nf = a ? N[1] * fb : N[0] * fe;
+        else Nf = N[2] * fx;
+        m->w[s * m->NE + k] = pref * Nf;
+      }
+    }
+    if (m->nf == 2) {
+      const double om = (VAC_K * p->dm2_ev2[0]) / E;
+      const double s2 = sin(2.0 * p->theta[0]), c2 = cos(2.0 * p->theta[0]);
+      m->bv[2 * k + 0] = (2.0 * om) * s2;      /* B_vac = (2w sin2t, 0, -2w cos2t) */
+      m->bv[2 * k + 1] = -((2.0 * om) * c2);
+    } else {
+      const double c12 = cos(p->theta[0]), s12 = sin(p->theta[0]);
+      const double c13 = cos(p->theta[1]), s13 = sin(p->theta[1]);
+      const double c23 = cos(p->theta[2]), s23 = sin(p->theta[2]);
+      const double U[3][3] = {
+          {c12 * c13, s12 * c13, s13},
+          {-(s12 * c23) - (c12 * s23) * s13, c12 * c23 - (s12 * s23) * s13, s23 * c13},
+          {s12 * s23 - (c12 * c23) * s13, -(c12 * s23) - (s12 * c23) * s13, c23 * c13}};
+      const double w2 = ((2.0 * VAC_K) * p->dm2_ev2[0]) / E; /* dm21 / 2E */
+      const double w3 = ((2.0 * VAC_K) * p->dm2_ev2[1]) / E; /* dm31 / 2E */
+      const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+      for (int e = 0; e < 6; ++e)
+        m->bv[6 * k + e] = (U[ia[e]][1] * U[ib[e]][1]) * w2 + (U[ia[e]][2] * U[ib[e]][2]) * w3;
+    }
+  }
+  /* fixed-point scales: every contribution |w rho~| < 2^e1 ... < 2^61 */
+  double wmax = 0.0;
+  for (int64_t i = 0; i < m->NE * m->ns; ++i)
+    if (fabs(m->w[i]) > wmax) wmax = fabs(m->w[i]);
+  if (!(wmax > 0.0)) wmax = 1.0;
+  int ex;
+  frexp(wmax, &ex);
+  m->e1 = 61 - ex;
+  const double qs = m->R / p->r_start_km;
+  const double cmin = sqrt(1.0 - u_of(m, m->NU - 1) * (qs * qs));
+  const double b0 = (wmax * (double)m->NE) * (1.0 / cmin);
+  frexp(b0, &ex);
+  m->e0 = 61 - ex;
+  m->s1 = ldexp(1.0, m->e1); m->p2e1 = ldexp(1.0, -m->e1);
+  m->s0 = ldexp(1.0, m->e0); m->p2e0 = ldexp(1.0, -m->e0);
+  nbo_reset(m);
+  *out = m;
+  return NBO_OK;
+}
+
+void nbo_destroy(nbo_model *m) {
+  if (!m) return;
+  free(m->E); free(m->w); free(m->bv); free(m->X); free(m->Y);
+  free(m);
+}
+
+int64_t nbo_n_beams(const nbo_model *m) { return m->nb; }
+int nbo_n_species(const nbo_model *m) { return m->ns; }
+int nbo_state_comps(const nbo_model *m) { return m->nsc; }
+int64_t nbo_step_index(const nbo_model *m) { return m->step; }
+
+int nbo_reset(nbo_model *m) {
+  for (int64_t b = 0; b < m->nb; ++b) {
+    const int s = (int)(b / (m->NU * m->NE));
+    double *x = m->X + b * m->nsc;
+    const int fl = m->init_flav[s];
+    if (m->nf == 2) { x[0] = 0.0; x[1] = 0.0; x[2] = fl == 0 ? 1.0 : -1.0; }
+    else { for (int c = 0; c < 6; ++c) x[c] = 0.0; x[2 * fl] = 1.0; }
+  }
+  m->step = 0;
+  return NBO_OK;
+}
+
+/* rho~ of one beam: rho for neutrinos, -rho^* for antineutrinos (Eq. F), as the moment
+ * components (2f: Bloch vector; 3f: rho_ee-rho_tt, rho_mm-rho_tt, Re/Im rho_em, rho_et, rho_mt). */
+static void rho_tilde(const nbo_model *m, int s, const double *x, double *out) {
+  const int a = m->anti[s];
+  if (m->nf == 2) {
+    out[0] = a ? -x[0] : x[0];
+    out[1] = x[1];
+    out[2] = a ? -x[2] : x[2];
+    return;
+  }
+  const cx p0 = cx_make(x[0], x[1]), p1 = cx_make(x[2], x[3]), p2 = cx_make(x[4], x[5]);
+  const double n0 = cx_norm2(p0), n1 = cx_norm2(p1), n2 = cx_norm2(p2);
+  const cx em = cx_mulc(p0, p1), et = cx_mulc(p0, p2), mt = cx_mulc(p1, p2);
+  const double v[8] = {n0 - n2, n1 - n2, em.re, em.im, et.re, et.im, mt.re, mt.im};
+  if (!a) { for (int c = 0; c < 8; ++c) out[c] = v[c]; return; }
+  out[0] = -v[0]; out[1] = -v[1];
+  out[2] = -v[2]; out[3] = v[3];
+  out[4] = -v[4]; out[5] = v[5];
+  out[6] = -v[6]; out[7] = v[7];
+}
+
+/* J0 = sum_b g_b rho~_b / c_b(r), J1 = sum_b g_b rho~_b: the energy sum of each
+ * (species, angle) row is taken first, exactly in fixed point, then the angle sum. */
+static int moments(const nbo_model *m, const double *X, double r, double *J0, double *J1) {
+  const radial g = radial_at(m, r);
+  const int nc = m->ncomp;
+  const int64_t nrow = (int64_t)m->ns * m->NU;
+  i128 *T0 = (i128 *)calloc((size_t)nrow * nc, sizeof(i128));
+  i128 *T1 = (i128 *)calloc((size_t)nrow * nc, sizeof(i128));
+  int err = 0;
+#pragma omp parallel for schedule(static) reduction(| : err)
+  for (int64_t row = 0; row < nrow; ++row) {
+    const int s = (int)(row / m->NU);
+    const int64_t j = row % m->NU;
+    const double ic = 1.0 / c_of(&g, u_of(m, j));
+    i128 S[8] = {0};
+    for (int64_t k = 0; k < m->NE; ++k) {
+      const int64_t b = row * m->NE + k;
+      double v[8];
+      rho_tilde(m, s, X + b * m->nsc, v);
+      for (int c = 0; c < nc; ++c) S[c] += to_fix(m->w[s * m->NE + k] * v[c], m->s1, &err);
+    }
+    for (int c = 0; c < nc; ++c) {
+      T1[row * nc + c] = S[c];
+      T0[row * nc + c] = to_fix(ic * (i128_to_double(S[c]) * m->p2e1), m->s0, &err);
+    }
+  }
+  for (int c = 0; c < nc; ++c) {
+    i128 a0 = 0, a1 = 0;
+    for (int64_t row = 0; row < nrow; ++row) { a0 += T0[row * nc + c]; a1 += T1[row * nc + c]; }
+    J0[c] = i128_to_double(a0) * m->p2e0;
+    J1[c] = i128_to_double(a1) * m->p2e1;
+  }
+  free(T0); free(T1);
+  return err ? NBO_ENUMERIC : NBO_OK;
+}
+
+/* Hamiltonian of beam (s, k) in angle bin with cos(theta) = c (Eq. eom):
+ * nu:   H_vac + lam E_ee + mu (J0 - c J1)
+ * nubar: H_vac - lam E_ee - mu (J0 - c J1)^*                                          */
+static void beam_B2(const nbo_model *m, int s, int64_t k, const radial *g, double c,
+                    const double *J0, const double *J1, double B[3]) {
+  const double nx = g->mu * (J0[0] - c * J1[0]);
+  const double ny = g->mu * (J0[1] - c * J1[1]);
+  const double nz = g->mu * (J0[2] - c * J1[2]);
+  const double bx = m->bv[2 * k], bz = m->bv[2 * k + 1];
+  if (!m->anti[s]) { B[0] = bx + nx; B[1] = ny; B[2] = (bz + g->lam) + nz; }
+  else { B[0] = bx - nx; B[1] = ny; B[2] = (bz - g->lam) - nz; }
+}
+static void beam_H3(const nbo_model *m, int s, int64_t k, const radial *g, double c,
+                    const double *J0, const double *J1, herm3 *H) {
+  double nn[8];
+  for (int i = 0; i < 8; ++i) nn[i] = g->mu * (J0[i] - c * J1[i]);
+  const double *v = m->bv + 6 * k;
+  if (!m->anti[s]) {
+    H->d[0] = (v[0] + g->lam) + nn[0];
+    H->d[1] = v[1] + nn[1];
+    H->d[2] = v[2];
+    H->o[0] = cx_make(v[3] + nn[2], nn[3]);
+    H->o[1] = cx_make(v[4] + nn[4], nn[5]);
+    H->o[2] = cx_make(v[5] + nn[6], nn[7]);
+  } else {
+    H->d[0] = (v[0] - g->lam) - nn[0];
+    H->d[1] = v[1] - nn[1];
+    H->d[2] = v[2];
+    H->o[0] = cx_make(v[3] - nn[2], nn[3]);
+    H->o[1] = cx_make(v[4] - nn[4], nn[5]);
+    H->o[2] = cx_make(v[5] - nn[6], nn[7]);
+  }
+}
+static herm3 h3_scale(double a, const herm3 *H) {
+  herm3 K;
+  for (int i = 0; i < 3; ++i) K.d[i] = a * H->d[i];
+  for (int i = 0; i < 3; ++i) K.o[i] = cx_make(a * H->o[i].re, a * H->o[i].im);
+  return K;
+}
+
+/* Scaled stage generator of beam b at radius g: 2f f = (h/c) B; 3f K = (h/c) H. */
+static void stage_f2(const nbo_model *m, int64_t b, const radial *g, const double *J0,
+                     const double *J1, double f[3]) {
+  const int s = (int)(b / (m->NU * m->NE));
+  const int64_t j = (b / m->NE) % m->NU, k = b % m->NE;
+  const double c = c_of(g, u_of(m, j));
+  const double hc = m->h / c;
+  double B[3];
+  beam_B2(m, s, k, g, c, J0, J1, B);
+  f[0] = hc * B[0]; f[1] = hc * B[1]; f[2] = hc * B[2];
+}
+static herm3 stage_K3(const nbo_model *m, int64_t b, const radial *g, const double *J0,
+                      const double *J1) {
+  const int s = (int)(b / (m->NU * m->NE));
+  const int64_t j = (b / m->NE) % m->NU, k = b % m->NE;
+  const double c = c_of(g, u_of(m, j));
+  const double hc = m->h / c;
+  herm3 H;
+  beam_H3(m, s, k, g, c, J0, J1, &H);
+  return h3_scale(hc, &H);
+}
+
+static void renorm2(double *P) {
+  const double n2 = (P[0] * P[0] + P[1] * P[1]) + P[2] * P[2];
+  const double inv = 1.0 / sqrt(n2);
+  P[0] = P[0] * inv; P[1] = P[1] * inv; P[2] = P[2] * inv;
+}
+static void renorm3(double *x) {
+  const double n2 = (cx_norm2(cx_make(x[0], x[1])) + cx_norm2(cx_make(x[2], x[3]))) +
+                    cx_norm2(cx_make(x[4], x[5]));
+  const double inv = 1.0 / sqrt(n2);
+  for (int c = 0; c < 6; ++c) x[c] = x[c] * inv;
+}
+
+static inline void cross3(const double a[3], const double b[3], double o[3]) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+static void apply3(const herm3 *K, const double *x, double *y) {
+  const cx ps[3] = {cx_make(x[0], x[1]), cx_make(x[2], x[3]), cx_make(x[4], x[5])};
+  cx o[3];
+  exp3_apply(K, ps, o);
+  for (int c = 0; c < 3; ++c) { y[2 * c] = o[c].re; y[2 * c + 1] = o[c].im; }
+}
+
+/* One RKMK4 step (see the file header). */
+static int step_rkmk4(nbo_model *m) {
+  const double rs = m->p.r_start_km, h = m->h;
+  const double r0 = rs + (double)m->step * h;
+  const double rm = r0 + 0.5 * h;
+  const double r1 = rs + (double)(m->step + 1) * h;
+  const radial g0 = radial_at(m, r0), gm = radial_at(m, rm), g1 = radial_at(m, r1);
+  double J[4][2][8];
+  int st = moments(m, m->X, r0, J[0][0], J[0][1]);
+  const int64_t nb = m->nb;
+  const int nsc = m->nsc;
+  /* stage 2 */
+#pragma omp parallel for schedule(static)
+  for (int64_t b = 0; b < nb; ++b) {
+    const double *x = m->X + b * nsc;
+    double *y = m->Y + b * nsc;
+    if (m->nf == 2) {
+      double f1[3], o[3];
+      stage_f2(m, b, &g0, J[0][0], J[0][1], f1);
+      o[0] = 0.5 * f1[0]; o[1] = 0.5 * f1[1]; o[2] = 0.5 * f1[2];
+      rotate2(o, x, y);
+    } else {
+      herm3 K1 = stage_K3(m, b, &g0, J[0][0], J[0][1]);
+      herm3 O = h3_scale(0.5, &K1);
+      apply3(&O, x, y);
+    }
+  }
+  st |= moments(m, m->Y, rm, J[1][0], J[1][1]);
+  /* stage 3 */
+#pragma omp parallel for schedule(static)
+  for (int64_t b = 0; b < nb; ++b) {
+    const double *x = m->X + b * nsc;
+    double *y = m->Y + b * nsc;
+    if (m->nf == 2) {
+      double f1[3], f2[3], cr[3], o[3];
+      stage_f2(m, b, &g0, J[0][0], J[0][1], f1);
+      stage_f2(m, b, &gm, J[1][0], J[1][1], f2);
+      cross3(f1, f2, cr);
+      for (int c = 0; c < 3; ++c) o[c] = 0.5 * f2[c] - 0.125 * cr[c];
+      rotate2(o, x, y);
+    } else {
+      herm3 K1 = stage_K3(m, b, &g0, J[0][0], J[0][1]);
+      herm3 K2 = stage_K3(m, b, &gm, J[1][0], J[1][1]);
+      herm3 C = h3_icomm(&K1, &K2), O;
+      for (int i = 0; i < 3; ++i) O.d[i] = 0.5 * K2.d[i] + 0.125 * C.d[i];
+      for (int i = 0; i < 3; ++i)
+        O.o[i] = cx_make(0.5 * K2.o[i].re + 0.125 * C.o[i].re, 0.5 * K2.o[i].im + 0.125 * C.o[i].im);
+      apply3(&O, x, y);
+    }
+  }
+  st |= moments(m, m->Y, rm, J[2][0], J[2][1]);
+  /* stage 4 */
+#pragma omp parallel for schedule(static)
+  for (int64_t b = 0; b < nb; ++b) {
+    const double *x = m->X + b * nsc;
+    double *y = m->Y + b * nsc;
+    if (m->nf == 2) {
+      double f3[3];
+      stage_f2(m, b, &gm, J[2][0], J[2][1], f3);
+      rotate2(f3, x, y);
+    } else {
+      herm3 K3 = stage_K3(m, b, &gm, J[2][0], J[2][1]);
+      apply3(&K3, x, y);
+    }
+  }
+  st |= moments(m, m->Y, r1, J[3][0], J[3][1]);
+  /* final update */
+#pragma omp parallel for schedule(static)
+  for (int64_t b = 0; b < nb; ++b) {
+    double *x = m->X + b * nsc;
+    if (m->nf == 2) {
+      double f1[3], f2[3], f3[3], f4[3], cr[3], th[3], y[3];
+      stage_f2(m, b, &g0, J[0][0], J[0][1], f1);
+      stage_f2(m, b, &gm, J[1][0], J[1][1], f2);
+      stage_f2(m, b, &gm, J[2][0], J[2][1], f3);
+      stage_f2(m, b, &g1, J[3][0], J[3][1], f4);
+      cross3(f1, f4, cr);
+      for (int c = 0; c < 3; ++c)
+        th[c] = (((f1[c] + 2.0 * f2[c]) + 2.0 * f3[c]) + f4[c]) * (1.0 / 6.0) - cr[c] * (1.0 / 12.0);
+      rotate2(th, x, y);
+      if (m->p.renorm) renorm2(y);
+      x[0] = y[0]; x[1] = y[1]; x[2] = y[2];
+    } else {
+      herm3 K1 = stage_K3(m, b, &g0, J[0][0], J[0][1]);
+      herm3 K2 = stage_K3(m, b, &gm, J[1][0], J[1][1]);
+      herm3 K3 = stage_K3(m, b, &gm, J[2][0], J[2][1]);
+      herm3 K4 = stage_K3(m, b, &g1, J[3][0], J[3][1]);
+      herm3 C = h3_icomm(&K1, &K4), T;
+      for (int i = 0; i < 3; ++i)
+        T.d[i] = (((K1.d[i] + 2.0 * K2.d[i]) + 2.0 * K3.d[i]) + K4.d[i]) * (1.0 / 6.0) + C.d[i] * (1.0 / 12.0);
+      for (int i = 0; i < 3; ++i) {
+        const double re = (((K1.o[i].re + 2.0 * K2.o[i].re) + 2.0 * K3.o[i].re) + K4.o[i].re) * (1.0 / 6.0) + C.o[i].re * (1.0 / 12.0);
+        const double im = (((K1.o[i].im + 2.0 * K2.o[i].im) + 2.0 * K3.o[i].im) + K4.o[i].im) * (1.0 / 6.0) + C.o[i].im * (1.0 / 12.0);
+        T.o[i] = cx_make(re, im);
+      }
+      double y[6];
+      apply3(&T, x, y);
+      if (m->p.renorm) renorm3(y);
+      for (int c = 0; c < 6; ++c) x[c] = y[c];
+    }
+  }
+  m->step += 1;
+  return st;
+}
+
+/* Right-hand side for plain RK4: 2f dP/dr = (1/c) B x P; 3f dpsi/dr = -(i/c) H psi. */
+static int rhs(const nbo_model *m, const double *X, double r, double *D) {
+  double J0[8], J1[8];
+  int st = moments(m, X, r, J0, J1);
+  const radial g = radial_at(m, r);
+#pragma omp parallel for schedule(static)
+  for (int64_t b = 0; b < m->nb; ++b) {
+    const int s = (int)(b / (m->NU * m->NE));
+    const int64_t j = (b / m->NE) % m->NU, k = b % m->NE;
+    const double c = c_of(&g, u_of(m, j));
+    const double ic = 1.0 / c;
+    const double *x = X + b * m->nsc;
+    double *d = D + b * m->nsc;
+    if (m->nf == 2) {
+      double B[3], cr[3];
+      beam_B2(m, s, k, &g, c, J0, J1, B);
+      cross3(B, x, cr);
+      d[0] = ic * cr[0]; d[1] = ic * cr[1]; d[2] = ic * cr[2];
+    } else {
+      herm3 H;
+      beam_H3(m, s, k, &g, c, J0, J1, &H);
+      const cx ps[3] = {cx_make(x[0], x[1]), cx_make(x[2], x[3]), cx_make(x[4], x[5])};
+      for (int a = 0; a < 3; ++a) {
+        const cx hp = cx_add(cx_add(cx_mul(h3_at(&H, a, 0), ps[0]), cx_mul(h3_at(&H, a, 1), ps[1])),
+                             cx_mul(h3_at(&H, a, 2), ps[2]));
+        d[2 * a] = ic * hp.im;
+        d[2 * a + 1] = -(ic * hp.re);
+      }
+    }
+  }
+  return st;
+}
+
+static int step_rk4(nbo_model *m) {
+  const double rs = m->p.r_start_km, h = m->h;
+  const double r0 = rs + (double)m->step * h, rm = r0 + 0.5 * h;
+  const double r1 = rs + (double)(m->step + 1) * h;
+  const int64_t n = m->nb * m->nsc;
+  double *k1 = (double *)malloc(sizeof(double) * n), *k2 = (double *)malloc(sizeof(double) * n);
+  double *k3 = (double *)malloc(sizeof(double) * n), *k4 = (double *)malloc(sizeof(double) * n);
+  int st = rhs(m, m->X, r0, k1);
+  for (int64_t i = 0; i < n; ++i) m->Y[i] = m->X[i] + (0.5 * h) * k1[i];
+  st |= rhs(m, m->Y, rm, k2);
+  for (int64_t i = 0; i < n; ++i) m->Y[i] = m->X[i] + (0.5 * h) * k2[i];
+  st |= rhs(m, m->Y, rm, k3);
+  for (int64_t i = 0; i < n; ++i) m->Y[i] = m->X[i] + h * k3[i];
+  st |= rhs(m, m->Y, r1, k4);
+  for (int64_t i = 0; i < n; ++i)
+    m->X[i] = m->X[i] + (h / 6.0) * (((k1[i] + 2.0 * k2[i]) + 2.0 * k3[i]) + k4[i]);
+  if (m->p.renorm)
+    for (int64_t b = 0; b < m->nb; ++b) {
+      if (m->nf == 2) renorm2(m->X + b * 3);
+      else renorm3(m->X + b * 6);
+    }
+  free(k1); free(k2); free(k3); free(k4);
+  m->step += 1;
+  return st;
+}
+
+int nbo_step(nbo_model *m, int64_t n) {
+  for (int64_t i = 0; i < n; ++i) {
+    const int st = m->p.integrator ? step_rk4(m) : step_rkmk4(m);
+    if (st) return NBO_ENUMERIC;
+  }
+  return NBO_OK;
+}
+
+int nbo_read_pee(const nbo_model *m, double *out) {
+  for (int64_t b = 0; b < m->nb; ++b) {
+    const double *x = m->X + b * m->nsc;
+    out[b] = (m->nf == 2) ? 0.5 * (1.0 + x[2]) : cx_norm2(cx_make(x[0], x[1]));
+  }
+  return NBO_OK;
+}
+
+int nbo_get_state(const nbo_model *m, double *out) {
+  for (int c = 0; c < m->nsc; ++c)
+    for (int64_t b = 0; b < m->nb; ++b) out[c * m->nb + b] = m->X[b * m->nsc + c];
+  return NBO_OK;
+}
+int nbo_set_state(nbo_model *m, const double *in, int64_t step) {
+  if (step < 0) return NBO_EINVAL;
+  for (int c = 0; c < m->nsc; ++c)
+    for (int64_t b = 0; b < m->nb; ++b) m->X[b * m->nsc + c] = in[c * m->nb + b];
+  m->step = step;
+  return NBO_OK;
+}
+
+int nbo_tables(const nbo_model *m, double *out, int64_t cap) {
+  const int nv = (m->nf == 2) ? 2 : 6;
+  const int64_t need = m->NE + m->NE * m->ns + m->NE * nv + 7;
+  if (cap < need) return NBO_EINVAL;
+  int64_t o = 0;
+  for (int64_t k = 0; k < m->NE; ++k) out[o++] = m->E[k];
+  for (int64_t i = 0; i < m->NE * m->ns; ++i) out[o++] = m->w[i];
+  for (int64_t i = 0; i < m->NE * nv; ++i) out[o++] = m->bv[i];
+  out[o++] = m->lam0; out[o++] = m->kappa0; out[o++] = m->h;
+  out[o++] = m->p2e1; out[o++] = m->p2e0; out[o++] = m->e1; out[o++] = m->e0;
+  return NBO_OK;
+}
+
+int nbo_moments(const nbo_model *m, double r, double *j0, double *j1) {
+  return moments(m, m->X, r, j0, j1);
+}
+
+int nbo_hamiltonian(const nbo_model *m, double r, const double *j0, const double *j1,
+                    double *out) {
+  const radial g = radial_at(m, r);
+  for (int64_t b = 0; b < m->nb; ++b) {
+    const int s = (int)(b / (m->NU * m->NE));
+    const int64_t j = (b / m->NE) % m->NU, k = b % m->NE;
+    const double c = c_of(&g, u_of(m, j));
+    if (m->nf == 2) beam_B2(m, s, k, &g, c, j0, j1, out + 3 * b);
+    else {
+      herm3 H;
+      beam_H3(m, s, k, &g, c, j0, j1, &H);
+      double *o = out + 9 * b;
+      o[0] = H.d[0]; o[1] = H.d[1]; o[2] = H.d[2];
+      for (int i = 0; i < 3; ++i) { o[3 + 2 * i] = H.o[i].re; o[4 + 2 * i] = H.o[i].im; }
+    }
+  }
+  return NBO_OK;
+}
+
+int nbo_cos_theta(const nbo_model *m, double r, double *out) {
+  const radial g = radial_at(m, r);
+  for (int64_t j = 0; j < m->NU; ++j) out[j] = c_of(&g, u_of(m, j));
+  return NBO_OK;
+}
+
+void nbo_sincos(const double *x, int64_t n, double *s, double *c) {
+  for (int64_t i = 0; i < n; ++i) sincos_spec(x[i], s + i, c + i);
+}
+void nbo_exp3_apply(const double *k9, const double *psi6, double *out6) {
+  herm3 K;
+  K.d[0] = k9[0]; K.d[1] = k9[1]; K.d[2] = k9[2];
+  for (int i = 0; i < 3; ++i) K.o[i] = cx_make(k9[3 + 2 * i], k9[4 + 2 * i]);
+  apply3(&K, psi6, out6);
+}
+void nbo_rotate(const double *x3, const double *p3, double *out3) { rotate2(x3, p3, out3); }
+double nbo_fixed_sum(const double *v, int64_t n, int e) {
+  i128 a = 0;
+  int err = 0;
+  const double sc = ldexp(1.0, e);
+  for (int64_t i = 0; i < n; ++i) a += to_fix(v[i], sc, &err);
+  if (err) return NAN;
+  return i128_to_double(a) * ldexp(1.0, -e);
+}
+
+/* ------------------------------------------------------- single-angle solver */
+/* All beams at one emission bin u = 1/2.  Then J0 = J1/c and the neutrino-neutrino
+ * Hamiltonian reduces to mu (1/c - c) J1 for every beam: a direct E-only system. */
+int nbo_single_angle_run(const nbo_params *pin, double *pee_out) {
+  if (!pin || pin->n_flavor != 2) return NBO_EINVAL;
+  nbo_params p = *pin;
+  p.n_u = 1;
+  p.species4 = 0;
+  p.integrator = 0;
+  nbo_model *m;
+  int st = nbo_create(&p, &m);
+  if (st) return st;
+  const int64_t NE = m->NE;
+  double *P = (double *)malloc(sizeof(double) * 2 * NE * 3);
+  double *Y = (double *)malloc(sizeof(double) * 2 * NE * 3);
+  for (int64_t i = 0; i < 2 * NE; ++i) { P[3 * i] = 0.0; P[3 * i + 1] = 0.0; P[3 * i + 2] = 1.0; }
+  const double u = 0.5;
+  int err = 0;
+  for (int64_t n = 0; n < p.n_steps && !err; ++n) {
+    const double rs = p.r_start_km, h = m->h;
+    const double rr[4] = {rs + (double)n * h, rs + (double)n * h + 0.5 * h,
+                          rs + (double)n * h + 0.5 * h, rs + (double)(n + 1) * h};
+    double Jn[4][3];
+    double *F = (double *)malloc(sizeof(double) * 4 * 2 * NE * 3);
+    for (int st_i = 0; st_i < 4; ++st_i) {
+      /* moments of the stage state */
+      const double *src = (st_i == 0) ? P : Y;
+      i128 S[3] = {0, 0, 0};
+      for (int64_t i = 0; i < 2 * NE; ++i) {
+        const int s = (int)(i / NE);
+        const double *x = src + 3 * i;
+        const double v[3] = {s ? -x[0] : x[0], x[1], s ? -x[2] : x[2]};
+        for (int c = 0; c < 3; ++c) S[c] += to_fix(m->w[i] * v[c], m->s1, &err);
+      }
+      for (int c = 0; c < 3; ++c) Jn[st_i][c] = i128_to_double(S[c]) * m->p2e1;
+      const radial g = radial_at(m, rr[st_i]);
+      const double c = sqrt(1.0 - u * g.q2);
+      const double geo = g.mu * (1.0 / c - c);
+      for (int64_t i = 0; i < 2 * NE; ++i) {
+        const int s = (int)(i / NE);
+        const int64_t k = i % NE;
+        const double nn[3] = {geo * Jn[st_i][0], geo * Jn[st_i][1], geo * Jn[st_i][2]};
+        double B[3];
+        if (!s) { B[0] = m->bv[2 * k] + nn[0]; B[1] = nn[1]; B[2] = (m->bv[2 * k + 1] + g.lam) + nn[2]; }
+        else { B[0] = m->bv[2 * k] - nn[0]; B[1] = nn[1]; B[2] = (m->bv[2 * k + 1] - g.lam) - nn[2]; }
+        double *f = F + (st_i * 2 * NE + i) * 3;
+        for (int cc = 0; cc < 3; ++cc) f[cc] = (h / c) * B[cc];
+        double o[3];
+        const double *f1 = F + (0 * 2 * NE + i) * 3;
+        if (st_i == 0) { for (int cc = 0; cc < 3; ++cc) o[cc] = 0.5 * f[cc]; }
+        else if (st_i == 1) {
+          double cr[3];
+          cross3(f1, f, cr);
+          for (int cc = 0; cc < 3; ++cc) o[cc] = 0.5 * f[cc] - 0.125 * cr[cc];
+        } else if (st_i == 2) { for (int cc = 0; cc < 3; ++cc) o[cc] = f[cc]; }
+        else {
+          const double *f2 = F + (1 * 2 * NE + i) * 3, *f3 = F + (2 * 2 * NE + i) * 3;
+          double cr[3];
+          cross3(f1, f, cr);
+          for (int cc = 0; cc < 3; ++cc)
+            o[cc] = (((f1[cc] + 2.0 * f2[cc]) + 2.0 * f3[cc]) + f[cc]) * (1.0 / 6.0) - cr[cc] * (1.0 / 12.0);
+        }
+        double y[3];
+        rotate2(o, P + 3 * i, y);
+        if (st_i == 3) { renorm2(y); for (int cc = 0; cc < 3; ++cc) P[3 * i + cc] = y[cc]; }
+        else for (int cc = 0; cc < 3; ++cc) Y[3 * i + cc] = y[cc];
+      }
+    }
+    free(F);
+  }
+  for (int64_t i = 0; i < 2 * NE; ++i) pee_out[i] = 0.5 * (1.0 + P[3 * i + 2]);
+  free(P); free(Y);
+  nbo_destroy(m);
+  return err ? NBO_ENUMERIC : NBO_OK;
+}
+
+int nbo_adjoint(nbo_model *m, int32_t ckpt, double *grad, double *loss) {
+  (void)m; (void)ckpt; (void)grad; (void)loss;
+  return NBO_EINVAL;
+}

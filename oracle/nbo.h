@@ -1,0 +1,98 @@
+/*
+ * nbo.h -- CPU oracle for the bulb-model radial stepper (plain FP64 C).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the independent reference that the HIP
+ * path is checked against.  Only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it; the product path never does.
+ *
+ * Physics (paper, Sec. 2): every beam is labelled by species s (neutrino / antineutrino,
+ * optionally every initial flavour), emission bin u_j = sin^2(theta_R) and energy bin
+ * E_k.  Its flavour state evolves along the radius r by
+ *     i cos(theta) d/dr psi = H psi,   H = H_vac + H_mat + H_nunu          (Eq. eom)
+ * with H_nunu built from two energy/angle moments of all beams (Eqs. Hnu and F).
+ * The integrator is a Lie-group Runge-Kutta method of order 4 (classical RK4 tableau,
+ * Munthe-Kaas 1999) whose exponential map is the exact one-step propagator of Eq. U.
+ *
+ * All entry points return 0 on success and a negative code on failure.
+ */
+#ifndef NBO_H
+#define NBO_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { NBO_OK = 0, NBO_EINVAL = -1, NBO_ENUMERIC = -5 };
+
+typedef struct {
+  int32_t n_flavor;     /* 2 or 3 */
+  int32_t n_energy;     /* N_E energy bins, equal width over [e_min, e_max] */
+  int32_t n_u;          /* N_u emission bins, equal width in u = sin^2 theta_R over [0,1] */
+  int32_t ne_power;     /* n_e(r) = n0 (R/r)^ne_power; 3 for the bulb, 0 = constant density */
+  int32_t renorm;       /* 1: renormalise every beam after every step */
+  int32_t integrator;   /* 0: RKMK4 (exact exponentials); 1: plain RK4 on the ODE */
+  int32_t species4;     /* 0: track nu_e- and anti-nu_e-born beams only;
+                           1: track every initially populated flavour explicitly */
+  int32_t pad;
+  int64_t n_steps;
+  double e_min_mev, e_max_mev, r_nu_km, r_start_km, r_end_km;
+  double lum_erg_s[3];  /* nu_e, anti-nu_e, nu_x (= every heavy flavour and antiflavour) */
+  double temp_mev[3];
+  double dm2_ev2[2];    /* 2f: [0] = dm^2;  3f: dm^2_21, dm^2_31 */
+  double theta[3];      /* 2f: [0] = theta_v;  3f: theta_12, theta_13, theta_23 */
+  double delta_cp;      /* must be 0 */
+  double n0_cm3;
+} nbo_params;
+
+typedef struct nbo_model nbo_model;
+
+int  nbo_create(const nbo_params *p, nbo_model **out);
+void nbo_destroy(nbo_model *m);
+int  nbo_set_threads(int n);                     /* OpenMP threads (0 = default) */
+int64_t nbo_n_beams(const nbo_model *m);
+int  nbo_n_species(const nbo_model *m);
+int  nbo_state_comps(const nbo_model *m);         /* 3 (2f Bloch vector) or 6 (3f psi) */
+int  nbo_reset(nbo_model *m);
+int  nbo_step(nbo_model *m, int64_t n);
+int64_t nbo_step_index(const nbo_model *m);
+/* Re rho_ee of every beam, layout [species][n_u][n_energy]. */
+int  nbo_read_pee(const nbo_model *m, double *out);
+/* State exchange: [comp][beam] planes, beam = (s*n_u + j)*n_energy + k. */
+int  nbo_get_state(const nbo_model *m, double *out);
+int  nbo_set_state(nbo_model *m, const double *in, int64_t step);
+/* Tables, for comparison with the HIP path's host set-up:
+ * out[0..NE) = E_k, then weights [n_species][NE], then the per-energy vacuum terms
+ * (2f: bx, bz per k; 3f: 6 per k), then scalars {lam0, kappa0, h, 2^-e1, 2^-e0, e1, e0}. */
+int  nbo_tables(const nbo_model *m, double *out, int64_t cap);
+/* Moments J0 (ncomp) and J1 (ncomp) of the current state at radius r (Eq. F). */
+int  nbo_moments(const nbo_model *m, double r, double *j0, double *j1);
+/* Per-beam Hamiltonian at radius r for given moments (2f: B vector, 3 per beam;
+ * 3f: Hermitian matrix d0,d1,d2,Re/Im o01,o02,o12 = 9 per beam).  Not scaled by h/c. */
+int  nbo_hamiltonian(const nbo_model *m, double r, const double *j0, const double *j1,
+                     double *out);
+/* Geometry: c_j(r) for every angle bin. */
+int  nbo_cos_theta(const nbo_model *m, double r, double *out);
+
+/* Primitives of the arithmetic specification (exported for the pin tests). */
+void nbo_sincos(const double *x, int64_t n, double *s, double *c);
+/* psi' = exp(-i K) psi up to a global phase; K = 9 reals (as above), psi = 6 reals. */
+void nbo_exp3_apply(const double *k9, const double *psi6, double *out6);
+/* P' = R(x) P: rotation of the Bloch vector P about x by |x|. */
+void nbo_rotate(const double *x3, const double *p3, double *out3);
+/* Exact fixed-point sum of n doubles scaled by 2^e, returned as a double (tests). */
+double nbo_fixed_sum(const double *v, int64_t n, int e);
+
+/* Separately coded single-angle solver (2 flavours): one emission bin at u = 1/2. */
+int  nbo_single_angle_run(const nbo_params *p, double *pee_out /* [2][NE] */);
+
+/* Reverse-mode adjoint of the whole radial integration (2 flavours, RKMK4).
+ * Loss L = sum_s sum_k dE/N_u sum_j Pee(s,k,j).  Runs from the current state for
+ * n_steps - step steps (the forward run is redone internally), checkpointing every
+ * ckpt steps.  grad[5] = dL/d{L_e, L_ebar, L_x, theta_v, n0}; *loss = L. */
+int  nbo_adjoint(nbo_model *m, int32_t ckpt, double *grad, double *loss);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,358 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these compare the oracle with itself: each checks it against a closed form, a
+library routine (libm, SciPy expm / quadrature), a brute-force sum written from the
+paper's equations (tests/physref.py), an invariant, or a hand-computed value.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy import linalg
+from scipy.spatial.transform import Rotation
+
+import workloads
+from tests import physref as ref
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- units (Sec. 2)
+def _half_last_digit(s: str) -> float:
+    """Half a unit in the last printed digit of a hand value written as a string."""
+    mant, _, ex = s.partition("e")
+    dec = len(mant.split(".")[1]) if "." in mant else 0
+    return 0.5 * 10.0 ** (int(ex or 0) - dec) * 1.001
+
+
+def _close(x, g: str):
+    assert abs(x - float(g)) <= _half_last_digit(g), (x, g)
+
+
+def test_units_against_hand_values(oracle):
+    g = json.load(open(os.path.join(GOLD, "units.json")))
+    # omega = dm^2/4E at dm^2 = 2.4e-3 eV^2, E = 10 MeV: one energy bin centred on 10 MeV
+    d = workloads.base_params(n_energy=1, n_u=1, e_min_mev=9.5, e_max_mev=10.5,
+                              dm2_ev2=[2.4e-3, 0.0], n0_cm3=1e33, n_steps=1)
+    t = oracle.Model(d).tables()
+    bx, bz = t["bv"][0]
+    omega = 0.5 * math.hypot(bx, bz)            # |B_vac| = 2 omega
+    _close(omega, g["omega_km_at_dm2_2.4e-3_E_10MeV"])
+    _close(t["lam0"], g["lambda_km_at_n0_1e33"])
+    f2, f3 = ref.fd_moments()
+    _close(f3 / f2, g["mean_energy_over_T"])
+    # nu-nu scale sqrt2 G_F N/(2 pi R^2 c) at R for each species, N = L/<E>
+    for key, T in (("nue", 2.76), ("nuebar", 4.01), ("nux", 6.26)):
+        N = 1e51 * ref.ERG_MEV / (T * f3 / f2)
+        _close(t["kappa0"] * N, g[f"nunu_scale_km_{key}_L1e51_R10km"])
+
+
+def test_spectrum_weights_against_quadrature(oracle):
+    """Explicit-species weights / (kappa0 du dE N) are the normalised Fermi-Dirac spectra;
+    their midpoint sums match the quadrature of f over [1, 50] MeV."""
+    d = workloads.base_params(n_energy=2000, n_u=1, n_steps=1)
+    m = oracle.Model(d, species4=1)
+    t = m.tables()
+    E, dE, u, du = ref.bins(d)
+    f2, f3 = ref.fd_moments()
+    from scipy import integrate
+    for s, (a, T) in enumerate([(0, 2.76), (2, 6.26)]):   # nu_e and nu_x rows
+        N = d["lum_erg_s"][a] * ref.ERG_MEV / (T * f3 / f2)
+        f = t["w"][s] / (t["kappa0"] * du * dE * N)
+        np.testing.assert_allclose(f, ref.spectrum(E, T), rtol=1e-12)
+        exact = integrate.quad(lambda x: ref.spectrum(x, T), 1.0, 50.0, epsabs=1e-14)[0]
+        assert np.sum(f) * dE == pytest.approx(exact, rel=1e-6)     # midpoint rule, O(dE^2)
+
+
+# --------------------------------------------------------- primitives (Eq. U)
+def test_sincos_against_libm(oracle):
+    rng = np.random.default_rng(7)
+    x = np.concatenate([np.linspace(-8, 8, 20001), rng.uniform(-1e3, 1e3, 20000),
+                        rng.uniform(-4e6, 4e6, 20000), [0.0, -0.0, np.pi / 4, 1e-300]])
+    s, c = oracle.sincos(x)
+    assert np.max(np.abs(s - np.sin(x))) <= 2.3e-16
+    assert np.max(np.abs(c - np.cos(x))) <= 2.3e-16
+
+
+def test_rotation_against_scipy(oracle):
+    rng = np.random.default_rng(3)
+    for scale in (1e-9, 1e-3, 1.0, 30.0, 3e5):
+        for _ in range(20):
+            x = rng.normal(size=3) * scale
+            p = rng.normal(size=3); p /= np.linalg.norm(p)
+            want = Rotation.from_rotvec(x).apply(p)
+            got = oracle.rotate(x, p)
+            np.testing.assert_allclose(got, want, atol=4e-16 * max(1.0, scale) + 1e-15)
+    # zero rotation is the identity
+    np.testing.assert_array_equal(oracle.rotate(np.zeros(3), np.array([0.3, 0.4, 0.5])),
+                                  [0.3, 0.4, 0.5])
+
+
+def _herm(k9):
+    H = np.diag(k9[:3]).astype(complex)
+    for t, (a, b) in enumerate([(0, 1), (0, 2), (1, 2)]):
+        H[a, b] = k9[3 + 2 * t] + 1j * k9[4 + 2 * t]
+        H[b, a] = np.conj(H[a, b])
+    return H
+
+
+def _rho(psi6):
+    p = psi6[0::2] + 1j * psi6[1::2]
+    return np.outer(p, p.conj())
+
+
+@pytest.mark.parametrize("kind", ["random", "degenerate", "matter", "tiny", "diag"])
+def test_exp3_against_expm(oracle, kind):
+    """exp(-iK) psi (up to a global phase) against SciPy's expm, incl. degenerate spectra."""
+    rng = np.random.default_rng(11)
+    for scale in (1e-4, 0.3, 5.0, 2e3, 3e6):
+        for _ in range(10):
+            if kind == "random":
+                k9 = rng.normal(size=9) * scale
+            elif kind == "degenerate":     # eigenvalues (a, a, b) in a random basis
+                Q, _ = np.linalg.qr(rng.normal(size=(3, 3)) + 1j * rng.normal(size=(3, 3)))
+                a = rng.normal() * scale
+                H = Q @ np.diag([a, a, -2 * a + 0.1 * scale]) @ Q.conj().T
+                k9 = np.array([H[0, 0].real, H[1, 1].real, H[2, 2].real, H[0, 1].real,
+                               H[0, 1].imag, H[0, 2].real, H[0, 2].imag, H[1, 2].real,
+                               H[1, 2].imag])
+            elif kind == "matter":         # large e-e entry, small mixing (MSW-like)
+                k9 = np.zeros(9); k9[0] = scale
+                k9[3:] = rng.normal(size=6) * 0.1
+                k9[1:3] = rng.normal(size=2) * 0.05
+            elif kind == "tiny":
+                k9 = rng.normal(size=9) * 1e-12
+            else:
+                k9 = np.zeros(9); k9[:3] = rng.normal(size=3) * scale
+            psi = rng.normal(size=6); psi /= np.linalg.norm(psi)
+            got = oracle.exp3_apply(k9, psi)
+            U = linalg.expm(-1j * _herm(k9))
+            pv = psi[0::2] + 1j * psi[1::2]
+            want = np.outer(U @ pv, (U @ pv).conj())
+            kn = np.abs(k9).max()
+            np.testing.assert_allclose(_rho(got), want, atol=3e-15 * max(1.0, kn) + 1e-14)
+    # K = 0 is the identity
+    psi = np.array([0.6, 0.0, 0.0, 0.8, 0.0, 0.0])
+    np.testing.assert_array_equal(oracle.exp3_apply(np.zeros(9), psi), psi)
+
+
+def test_fixed_point_sum_exact_and_order_free(oracle):
+    rng = np.random.default_rng(5)
+    v = rng.normal(size=2000) * 10.0 ** rng.uniform(-8, 3, size=2000)
+    e = 40
+    got = oracle.fixed_sum(v, e)
+    exact = sum(Fraction(int(math.trunc(Fraction(x) * 2 ** e)), 2 ** e) for x in v.tolist())
+    assert abs(Fraction(got) - exact) <= abs(exact) * Fraction(1, 2 ** 52)
+    for _ in range(3):
+        assert oracle.fixed_sum(rng.permutation(v), e) == got      # bitwise, any order
+    assert got == pytest.approx(math.fsum(v), abs=len(v) * 2.0 ** -e)
+
+
+# ------------------------------------------------- closed forms (Sec. 2, Eq. U)
+def _vacuum_case(nf, n_u=3, ne=6, steps=400, **kw):
+    args = dict(n_flavor=nf, n_energy=ne, n_u=n_u, n_steps=steps, r_start_km=10.0,
+                r_end_km=40.0, lum_erg_s=[0.0, 0.0, 0.0], n0_cm3=0.0)
+    args.update(kw)
+    return workloads.small_params(**args)
+
+
+@pytest.mark.parametrize("nf", [2, 3])
+def test_vacuum_oscillation_closed_form(oracle, nf):
+    """No matter, no neutrinos: P_ee = 1 - sum 4|U_ei U_ej|^2 sin^2(dm_ij^2 L/4E) along the
+    beam's path length L (2 flavours: 1 - sin^2 2theta sin^2(dm^2 L/4E))."""
+    d = _vacuum_case(nf)
+    m = oracle.Model(d); m.run()
+    pee = m.pee()
+    E, dE, u, du = ref.bins(d)
+    L = ref.path_length(d["r_end_km"], d["r_start_km"], d["r_nu_km"], u)[:, None]
+    if nf == 2:
+        w = ref.omega_km(d["dm2_ev2"][0], E)[None, :]
+        want = 1.0 - np.sin(2 * d["theta"][0]) ** 2 * np.sin(w * L) ** 2
+    else:
+        U = ref.pmns(*d["theta"])
+        m2 = [0.0, d["dm2_ev2"][0], d["dm2_ev2"][1]]
+        want = np.ones((len(u), len(E)))
+        for i in range(3):
+            for j in range(i + 1, 3):
+                ph = (m2[j] - m2[i]) / (4.0 * E * 1e6) / ref.HBARC_EV_KM
+                want -= 4 * U[0, i] ** 2 * U[0, j] ** 2 * np.sin(ph[None, :] * L) ** 2
+    for s in range(2):       # antineutrinos: same vacuum Hamiltonian (real mixing)
+        np.testing.assert_allclose(pee[s], want, atol=2e-10)
+
+
+@pytest.mark.parametrize("nf", [2, 3])
+def test_msw_constant_density_closed_form(oracle, nf):
+    """Constant n_e: the textbook matter solution (2f: sin^2 2theta_m, dm^2_m with
+    A -> -A for antineutrinos; 3f: expm of the constant Hamiltonian)."""
+    d = _vacuum_case(nf, ne_power=0, n0_cm3=2.0e28, steps=400)
+    m = oracle.Model(d); m.run()
+    pee = m.pee()
+    E, dE, u, du = ref.bins(d)
+    lam = ref.sqrt2gf_km_cm3() * d["n0_cm3"]
+    L = ref.path_length(d["r_end_km"], d["r_start_km"], d["r_nu_km"], u)
+    for s, sign in ((0, 1.0), (1, -1.0)):
+        for k, e in enumerate(E):
+            if nf == 2:
+                th = d["theta"][0]
+                w = ref.omega_km(d["dm2_ev2"][0], e)
+                A = sign * lam / (2 * w)
+                s22m = np.sin(2 * th) ** 2 / ((np.cos(2 * th) - A) ** 2 + np.sin(2 * th) ** 2)
+                wm = w * np.sqrt((np.cos(2 * th) - A) ** 2 + np.sin(2 * th) ** 2)
+                want = 1 - s22m * np.sin(wm * L) ** 2
+            else:
+                H = ref.hvac3(d, e) + sign * np.diag([lam, 0, 0])
+                want = np.array([abs(ref.expm_apply(H, l, np.array([1, 0, 0]))[0]) ** 2
+                                 for l in L])
+            np.testing.assert_allclose(pee[s, :, k], want, atol=2e-10)
+
+
+# -------------------------------------------------- H_nunu (Eqs. Hnu and F)
+@pytest.mark.parametrize("nf", [2, 3])
+def test_factored_hamiltonian_equals_brute_pair_sum(oracle, nf):
+    """J0/J1 factorisation = direct O(N^2) beam-pair sum of Eq. Hnu with every initial
+    flavour explicit; also pins weights, the d cos(theta') Jacobian and the antineutrino
+    conjugation."""
+    d = workloads.small_params(n_flavor=nf, n_energy=3, n_u=4, n_steps=10,
+                               r_start_km=10.0, r_end_km=20.0)
+    m = oracle.Model(d)
+    rng = np.random.default_rng(21)
+    NE, NU, nb = 3, 4, 2 * 3 * 4
+    if nf == 2:
+        P = rng.normal(size=(3, nb)); P /= np.linalg.norm(P, axis=0)
+        m.set_state(P, 0)
+        rho = 0.5 * (np.eye(2)[None] + P[0][:, None, None] * np.array([[0, 1], [1, 0]])
+                     + P[1][:, None, None] * np.array([[0, -1j], [1j, 0]])
+                     + P[2][:, None, None] * np.array([[1, 0], [0, -1]]))
+    else:
+        psi = rng.normal(size=(6, nb)); psi /= np.linalg.norm(psi, axis=0)
+        m.set_state(psi, 0)
+        pv = (psi[0::2] + 1j * psi[1::2]).T
+        rho = np.einsum("bi,bj->bij", pv, pv.conj())
+    rho = rho.reshape(2, NU, NE, nf, nf)
+    r = 13.7
+    j0, j1 = m.moments(r)
+    H = m.hamiltonian(r, j0, j1).reshape(2, NU, NE, -1)
+    Hnn = ref.brute_h_nunu(d, r, rho[0], rho[1])
+    E, dE, u, du = ref.bins(d)
+    lam = ref.sqrt2gf_km_cm3() * d["n0_cm3"] * (d["r_nu_km"] / r) ** 3
+    for s in range(2):
+        sg = 1 if s == 0 else -1
+        for j in range(NU):
+            for k in range(NE):
+                if nf == 2:
+                    Ht = ref.hvac2(d, E[k]) + sg * np.diag([lam, 0]) + Hnn[s, j, k]
+                    np.testing.assert_allclose(H[s, j, k], ref.bvec(Ht), rtol=1e-12,
+                                               atol=1e-12 * np.abs(Ht).max())
+                else:
+                    Ht = ref.hvac3(d, E[k]) + sg * np.diag([lam, 0, 0]) + Hnn[s, j, k]
+                    Ho = _herm(H[s, j, k])
+                    # equal up to a multiple of the identity
+                    D = Ho - Ht
+                    D -= np.trace(D) / 3 * np.eye(3)
+                    assert np.abs(D).max() <= 1e-12 * np.abs(Ht).max()
+
+
+# ----------------------------------------------------- invariants, reductions
+@pytest.mark.parametrize("nf", [2, 3])
+def test_norm_conserved_without_renormalisation(oracle, nf):
+    d = workloads.small_params(n_flavor=nf, n_energy=7, n_u=3, n_steps=1000, renorm=0,
+                               r_start_km=60.0, r_end_km=70.0)
+    m = oracle.Model(d); m.run()
+    x = m.get_state()
+    nrm = np.sqrt(np.sum(x * x, axis=0))
+    assert np.max(np.abs(nrm - 1.0)) <= 1e-13
+
+
+def _tilted_nunu_only(oracle, steps, jac=True):
+    d = workloads.small_params(n_flavor=2, n_energy=6, n_u=5, n_steps=steps, renorm=1,
+                               r_start_km=30.0, r_end_km=60.0, dm2_ev2=[0.0, 0.0],
+                               n0_cm3=0.0, lum_erg_s=[1e49, 1e49, 1e49])
+    m = oracle.Model(d)
+    rng = np.random.default_rng(9)
+    P = rng.normal(size=(3, m.nb)) + np.array([[0.0], [0.0], [2.0]])
+    P /= np.linalg.norm(P, axis=0)
+    m.set_state(P, 0)
+    _, D0 = m.moments(d["r_start_km"])
+    m.run()
+    _, D1 = m.moments(d["r_end_km"])
+    return np.linalg.norm(D1 - D0) / np.linalg.norm(D0)
+
+
+def test_flux_weighted_polarisation_invariant(oracle):
+    """Pure nu-nu evolution conserves D = sum_b g_b P~_b (Eq. Hnu's kernel is symmetric
+    once the d cos(theta') Jacobian is in); the integrator keeps it to O(h^4)."""
+    e1 = _tilted_nunu_only(oracle, 200)
+    e2 = _tilted_nunu_only(oracle, 400)
+    e3 = _tilted_nunu_only(oracle, 800)
+    assert e3 < 2e-7
+    assert e1 / e2 > 12 and e2 / e3 > 12
+
+
+def test_single_angle_equals_one_angle_bin(oracle):
+    d = workloads.small_params(n_flavor=2, n_energy=9, n_u=1, n_steps=60)
+    m = oracle.Model(d); m.run()
+    sa = oracle.single_angle_run(d)
+    np.testing.assert_allclose(m.pee()[:, 0, :], sa, atol=1e-12)
+
+
+@pytest.mark.parametrize("nf", [2, 3])
+def test_two_tracked_species_equal_explicit_species(oracle, nf):
+    d = workloads.small_params(n_flavor=nf, n_energy=5, n_u=3, n_steps=40)
+    a = oracle.Model(d); a.run()
+    b = oracle.Model(d, species4=1); b.run()
+    pa, pb = a.pee(), b.pee()
+    np.testing.assert_allclose(pa[0], pb[0], atol=1e-11)        # nu_e-born
+    np.testing.assert_allclose(pa[1], pb[nf], atol=1e-11)       # anti-nu_e-born
+
+
+# ------------------------------------------------------------------ integrator
+def _err_at(oracle, steps, integrator=0, ref_steps=3200):
+    """Non-stiff setting (h |H| < 1) with O(1) flavour conversion."""
+    base = dict(n_flavor=2, n_energy=5, n_u=3, r_start_km=60.0, r_end_km=64.0,
+                lum_erg_s=[1e50, 6e49, 3e49], n0_cm3=1e30, theta=[0.5, 0.0, 0.0])
+    d = workloads.small_params(n_steps=steps, **base)
+    m = oracle.Model(d, integrator=integrator); m.run()
+    r = oracle.Model(workloads.small_params(n_steps=ref_steps, **base)); r.run()
+    assert np.max(np.abs(r.pee() - 1.0)) > 0.3           # the case is not trivial
+    return np.max(np.abs(m.pee() - r.pee()))
+
+
+def test_rkmk4_fourth_order(oracle):
+    e = [_err_at(oracle, n) for n in (50, 100, 200)]
+    assert e[0] / e[1] > 12 and e[1] / e[2] > 12
+    assert e[2] < 3e-6
+
+
+def test_plain_rk4_agrees_on_nonstiff(oracle):
+    ea = _err_at(oracle, 100, integrator=1)
+    eb = _err_at(oracle, 200, integrator=1)
+    assert ea / eb > 12 and eb < 3e-5
+
+
+def test_plain_rk4_fails_on_stiff_bulb(oracle):
+    """At the neutrinosphere the matter and nu-nu terms are ~1e5-1e6 km^-1 against a
+    0.1 km step: the explicit RK4 stability bound is violated by orders of magnitude."""
+    d = workloads.two_flavor_small()
+    d["renorm"] = 0
+    m = oracle.Model(d, integrator=1)
+    with pytest.raises(oracle.OracleError):
+        m.step(40)
+
+
+# ------------------------------------------------------------------ determinism
+def test_thread_count_and_restart_are_bitwise(oracle):
+    d = workloads.small_params(n_flavor=3, n_energy=11, n_u=4, n_steps=12)
+    outs = []
+    for t in (1, 2, 8):
+        oracle.set_threads(t)
+        m = oracle.Model(d); m.run(); outs.append(m.get_state())
+    oracle.set_threads(0)
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+    m = oracle.Model(d); m.step(5)
+    x = m.get_state()
+    m2 = oracle.Model(d); m2.set_state(x, 5); m2.step(7)
+    np.testing.assert_array_equal(m2.get_state(), outs[0])
