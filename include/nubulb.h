@@ -1,0 +1,135 @@
+/*
+ * nubulb.h -- C-ABI of the MI355X bulb-model radial stepper.
+ *
+ * The library advances the flavour state of every (species, emission bin, energy bin)
+ * beam of the neutrino bulb model (paper, Sec. 2) along the radius r.  One radial step is
+ * a Lie-group Runge-Kutta step of order 4 (classical RK4 tableau on the unitary group,
+ * Munthe-Kaas 1999) whose exponential map is the exact one-step propagator exp(-i H dl),
+ * dl = dr/cos(theta) (Eq. U), and whose Hamiltonian
+ *     H = H_vac(E) + H_mat(r) + H_nunu(theta; r)                       (Eq. eom)
+ * is rebuilt at every stage from two moments of all beams, J0 = sum g rho~/cos(theta')
+ * and J1 = sum g rho~ (Eqs. Hnu and F), summed exactly in fixed point.  Antineutrinos
+ * evolve with H_vac - H_mat - H_nunu^* (Eq. eom).  Every beam starts in its flavour
+ * eigenstate at r_start (Sec. 3.4).
+ *
+ * Conventions for every entry point:
+ *   - return value: NB_OK (0) or a negative NB_E* code; nb_last_error() then holds a
+ *     message for the calling thread.  No C++ exception crosses this boundary.
+ *   - ownership: the caller owns every buffer (device workspace, outputs).  The library
+ *     owns only the opaque nb_model host object, freed by nb_model_destroy.
+ *   - device memory: all device work uses the workspace bound with nb_bind; nb_step,
+ *     nb_run, nb_read_pee and nb_adjoint allocate nothing.
+ *   - streams: all device work is enqueued on the stream given to nb_bind.  Calls return
+ *     after checking the kernels' status word, i.e. after the stream has drained, unless
+ *     the stream is being captured into a HIP graph (then they return at once).
+ *   - beam index b = (s * n_u + j) * n_energy + k, with species s (0 = nu_e-born,
+ *     1 = anti-nu_e-born), emission bin j and energy bin k; energy is innermost.
+ *   - layouts of device buffers are plain arrays of double in that beam order.
+ *   - errors are checked before any device work is enqueued.
+ */
+#ifndef NUBULB_H
+#define NUBULB_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  NB_OK = 0,
+  NB_EINVAL = -1,      /* invalid parameter or argument */
+  NB_EUNBOUND = -2,    /* no workspace bound yet */
+  NB_EWORKSPACE = -3,  /* workspace too small or misaligned (256 B) */
+  NB_EHIP = -4,        /* a HIP runtime call failed (no device, launch failure, ...) */
+  NB_ENUMERIC = -5,    /* a moment contribution left the fixed-point range (NaN/overflow) */
+  NB_ETIMEOUT = -6     /* a grid barrier did not complete within its time limit */
+};
+
+enum { NB_FP64 = 0, NB_FP32_STATE = 1 };
+
+/* Model parameters (paper, Sec. 2 and Sec. 3.2).  Lengths in km, energies in MeV. */
+typedef struct {
+  int32_t n_flavor;     /* 2 (e, x) or 3 (e, mu, tau) */
+  int32_t n_energy;     /* N_E bins of equal width over [e_min_mev, e_max_mev], midpoints */
+  int32_t n_u;          /* N_u bins of equal width in u = sin^2(theta_R) over [0,1], midpoints */
+  int32_t ne_power;     /* n_e(r) = n0_cm3 (R/r)^ne_power; 3 for the bulb, 0..8 allowed */
+  int32_t precision;    /* NB_FP64, or NB_FP32_STATE (3 flavours: state stored in FP32) */
+  int32_t renorm;       /* 1: renormalise every beam after every step (0: tests only) */
+  int32_t adjoint_ckpt; /* >0: reserve workspace for nb_adjoint with this checkpoint period */
+  int32_t max_blocks;   /* 0: as many blocks as fit on the device; else an upper bound */
+  int64_t n_steps;      /* radial steps from r_start_km to r_end_km */
+  double e_min_mev, e_max_mev;
+  double r_nu_km;       /* neutrinosphere radius R */
+  double r_start_km, r_end_km;
+  double lum_erg_s[3];  /* luminosities of nu_e, anti-nu_e, nu_x (= each heavy flavour) */
+  double temp_mev[3];   /* Fermi-Dirac temperatures, zero chemical potential */
+  double dm2_ev2[2];    /* 2f: [0] = dm^2.  3f: dm^2_21, dm^2_31 */
+  double theta[3];      /* 2f: [0] = theta_v.  3f: theta_12, theta_13, theta_23 */
+  double delta_cp;      /* must be 0 (real mixing matrix) */
+  double n0_cm3;        /* electron density scale */
+} nb_params;
+
+typedef struct nb_model nb_model;
+
+/* Create a model: validates p and builds the host tables (E bins, spectra, weights,
+ * vacuum Hamiltonians, fixed-point scales).  No device work.  *out is NULL on error. */
+int nb_model_create(const nb_params *p, nb_model **out);
+/* Create a batch of n_models independent 2-flavour models advanced together (all must
+ * share n_steps, r_start_km and r_end_km).  Beams of model m follow those of m-1. */
+int nb_batch_create(const nb_params *p, int32_t n_models, nb_model **out);
+void nb_model_destroy(nb_model *m);
+
+int64_t nb_n_beams(const nb_model *m);      /* all models of a batch */
+int32_t nb_n_models(const nb_model *m);
+int32_t nb_state_comps(const nb_model *m);  /* 3 (2f Bloch vector) or 6 (3f wavefunction) */
+/* Offsets of each model's beams in beam-indexed outputs: off[0..n_models]. */
+int nb_pee_offsets(const nb_model *m, int64_t *off);
+/* Bytes of device workspace the model needs (256-byte aligned start required). */
+size_t nb_workspace_bytes(const nb_model *m);
+/* Bind caller-owned device memory and a HIP stream (hipStream_t, may be NULL), upload
+ * the tables on that stream and reset the state (as nb_reset). */
+int nb_bind(nb_model *m, void *dev_ws, size_t bytes, void *hip_stream);
+/* Every beam back to its initial flavour eigenstate at r_start (Sec. 3.4); step = 0. */
+int nb_reset(nb_model *m);
+/* Advance n radial steps (bounded by n_steps - current step). */
+int nb_step(nb_model *m, int64_t n);
+/* Advance to r_end_km. */
+int nb_run(nb_model *m);
+int64_t nb_step_index(const nb_model *m);
+/* Survival probability Re(rho_ee) of every beam (paper's P_ee, Sec. 3.5) into the
+ * caller's device array dev_out[nb_n_beams]. */
+int nb_read_pee(const nb_model *m, double *dev_out);
+/* State exchange as FP64 planes [comp][beam] (2f: P_x, P_y, P_z; 3f: Re/Im psi_e,
+ * psi_mu, psi_tau).  on_device: 1 if dst/src is device memory, 0 if host memory. */
+int nb_get_state(const nb_model *m, double *dst, int on_device);
+int nb_set_state(nb_model *m, const double *src, int64_t step, int on_device);
+
+/* Reverse-mode adjoint of the radial integration (2 flavours, FP64, single model).
+ * Runs from the current state and step to r_end (keeping a checkpoint every ckpt_every
+ * steps; 0 = the model's adjoint_ckpt), then back.  dev_dl_dpee[nb_n_beams]: cotangent
+ * of the final P_ee (device).  grad_out[5] (host) = dL/d{L_e, L_ebar, L_x, theta_v, n0}.
+ * The model is left at r_end.  Requires adjoint_ckpt > 0 at creation. */
+int nb_adjoint(nb_model *m, const double *dev_dl_dpee, double *grad_out, int32_t ckpt_every);
+
+/* Host tables (no device work), layout as [E_k | weights[2][NE] | vacuum terms |
+ * lam0, kappa0, h, 2^-e1, 2^-e0, e1, e0]; vacuum terms are (B_x, B_z) per k for 2f and
+ * 6 entries per k (H_ee, H_mm, H_tt, H_em, H_et, H_mt) for 3f.  Single models only. */
+int nb_host_tables(const nb_model *m, double *out, int64_t cap);
+
+const char *nb_last_error(void);
+
+/* ---- test hooks: the arithmetic primitives of the stepper, one element per thread ----
+ * dev_* are device arrays of n elements (n * 9 for k9, n * 6 for psi6, n * 3 for x3/p3). */
+int nb_test_sincos(const double *dev_x, int64_t n, double *dev_s, double *dev_c, void *stream);
+int nb_test_sqrt_div(const double *dev_a, const double *dev_b, int64_t n, double *dev_sqrt,
+                     double *dev_div, void *stream);
+int nb_test_exp3(const double *dev_k9, const double *dev_psi6, int64_t n, double *dev_out6,
+                 void *stream);
+int nb_test_rotate(const double *dev_x3, const double *dev_p3, int64_t n, double *dev_out3,
+                   void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,243 @@
+"""Python binding of libnubulb (the MI355X bulb-model radial stepper).
+
+Argument marshalling only: every step of the path runs in the HIP kernels behind the
+C-ABI of include/nubulb.h.  PyTorch provides device memory (the workspace and outputs)
+and the current HIP stream.  There is no fallback: if the shared library is missing or
+no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnubulb.so")
+
+NB_OK, NB_EINVAL, NB_EUNBOUND, NB_EWORKSPACE, NB_EHIP, NB_ENUMERIC, NB_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
+NB_FP64, NB_FP32_STATE = 0, 1
+
+EXPORTS = [
+    "nb_model_create", "nb_batch_create", "nb_model_destroy", "nb_n_beams", "nb_n_models",
+    "nb_state_comps", "nb_pee_offsets", "nb_workspace_bytes", "nb_bind", "nb_reset",
+    "nb_step", "nb_run", "nb_step_index", "nb_read_pee", "nb_get_state", "nb_set_state",
+    "nb_adjoint", "nb_host_tables", "nb_last_error", "nb_test_sincos", "nb_test_sqrt_div",
+    "nb_test_exp3", "nb_test_rotate",
+]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("n_flavor", C.c_int32), ("n_energy", C.c_int32), ("n_u", C.c_int32),
+        ("ne_power", C.c_int32), ("precision", C.c_int32), ("renorm", C.c_int32),
+        ("adjoint_ckpt", C.c_int32), ("max_blocks", C.c_int32), ("n_steps", C.c_int64),
+        ("e_min_mev", C.c_double), ("e_max_mev", C.c_double), ("r_nu_km", C.c_double),
+        ("r_start_km", C.c_double), ("r_end_km", C.c_double),
+        ("lum_erg_s", C.c_double * 3), ("temp_mev", C.c_double * 3),
+        ("dm2_ev2", C.c_double * 2), ("theta", C.c_double * 3), ("delta_cp", C.c_double),
+        ("n0_cm3", C.c_double),
+    ]
+
+
+class NubulbError(RuntimeError):
+    def __init__(self, code: int, what: str, msg: str):
+        super().__init__(f"{what} failed ({code}): {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libnubulb.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int64
+        L.nb_model_create.argtypes = [C.POINTER(Params), C.POINTER(vp)]
+        L.nb_batch_create.argtypes = [C.POINTER(Params), C.c_int32, C.POINTER(vp)]
+        L.nb_model_destroy.argtypes = [vp]
+        L.nb_model_destroy.restype = None
+        L.nb_n_beams.argtypes = [vp]
+        L.nb_n_beams.restype = i64
+        L.nb_n_models.argtypes = [vp]
+        L.nb_state_comps.argtypes = [vp]
+        L.nb_pee_offsets.argtypes = [vp, C.POINTER(i64)]
+        L.nb_workspace_bytes.argtypes = [vp]
+        L.nb_workspace_bytes.restype = C.c_size_t
+        L.nb_bind.argtypes = [vp, vp, C.c_size_t, vp]
+        L.nb_reset.argtypes = [vp]
+        L.nb_step.argtypes = [vp, i64]
+        L.nb_run.argtypes = [vp]
+        L.nb_step_index.argtypes = [vp]
+        L.nb_step_index.restype = i64
+        L.nb_read_pee.argtypes = [vp, vp]
+        L.nb_get_state.argtypes = [vp, vp, C.c_int]
+        L.nb_set_state.argtypes = [vp, vp, i64, C.c_int]
+        L.nb_adjoint.argtypes = [vp, vp, dp, C.c_int32]
+        L.nb_host_tables.argtypes = [vp, dp, i64]
+        L.nb_last_error.restype = C.c_char_p
+        L.nb_test_sincos.argtypes = [vp, i64, vp, vp, vp]
+        L.nb_test_sqrt_div.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.nb_test_exp3.argtypes = [vp, vp, i64, vp, vp]
+        L.nb_test_rotate.argtypes = [vp, vp, i64, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != NB_OK:
+        raise NubulbError(rc, what, lib().nb_last_error().decode(errors="replace"))
+
+
+def make_params(d: dict, precision: int | None = None, adjoint_ckpt: int = 0,
+                max_blocks: int = 0) -> Params:
+    p = Params()
+    p.max_blocks = int(d.get("max_blocks", max_blocks))
+    for k in ("n_flavor", "n_energy", "n_u", "ne_power", "renorm", "n_steps"):
+        setattr(p, k, int(d[k]))
+    p.precision = int(d.get("precision", 0) if precision is None else precision)
+    p.adjoint_ckpt = int(adjoint_ckpt)
+    for k in ("e_min_mev", "e_max_mev", "r_nu_km", "r_start_km", "r_end_km", "delta_cp",
+              "n0_cm3"):
+        setattr(p, k, float(d[k]))
+    p.lum_erg_s[:] = [float(x) for x in d["lum_erg_s"]]
+    p.temp_mev[:] = [float(x) for x in d["temp_mev"]]
+    p.dm2_ev2[:] = [float(x) for x in d["dm2_ev2"]]
+    p.theta[:] = [float(x) for x in d["theta"]]
+    return p
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class HostModel:
+    """A model created on the host only (parameter validation and tables; no device)."""
+
+    def __init__(self, d: dict, precision: int | None = None, adjoint_ckpt: int = 0):
+        self.d = dict(d)
+        self.params = make_params(d, precision, adjoint_ckpt)
+        h = C.c_void_p()
+        _check(lib().nb_model_create(C.byref(self.params), C.byref(h)), "nb_model_create")
+        self.h = h
+        self.nb = int(lib().nb_n_beams(h))
+        self.nsc = int(lib().nb_state_comps(h))
+        self.nf = int(d["n_flavor"])
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.nb_model_destroy(self.h)
+            self.h = None
+
+    def workspace_bytes(self) -> int:
+        return int(lib().nb_workspace_bytes(self.h))
+
+    def tables(self) -> dict:
+        import numpy as np
+        ne = int(self.d["n_energy"])
+        nv = 2 if self.nf == 2 else 6
+        n = ne + 2 * ne + nv * ne + 7
+        out = np.empty(n, np.float64)
+        _check(lib().nb_host_tables(self.h, out.ctypes.data_as(C.POINTER(C.c_double)), n),
+               "nb_host_tables")
+        o = 0
+        E = out[o:o + ne]; o += ne
+        w = out[o:o + 2 * ne].reshape(2, ne); o += 2 * ne
+        bv = out[o:o + nv * ne].reshape(ne, nv); o += nv * ne
+        lam0, kappa0, h, p2e1, p2e0, e1, e0 = out[o:o + 7]
+        return dict(E=E, w=w, bv=bv, lam0=lam0, kappa0=kappa0, h=h, p2e1=p2e1, p2e0=p2e0,
+                    e1=int(e1), e0=int(e0))
+
+
+class Model(HostModel):
+    """A bulb model bound to device memory on the current torch device and stream."""
+
+    def __init__(self, d: dict, precision: int | None = None, adjoint_ckpt: int = 0,
+                 device="cuda", stream=None):
+        super().__init__(d, precision, adjoint_ckpt)
+        torch = _torch()
+        nbytes = self.workspace_bytes()
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        self.stream = stream
+        _check(lib().nb_bind(self.h, C.c_void_p(base + off), nbytes, _stream_ptr(stream)),
+               "nb_bind")
+
+    def reset(self):
+        _check(lib().nb_reset(self.h), "nb_reset")
+
+    def step(self, n: int):
+        _check(lib().nb_step(self.h, int(n)), "nb_step")
+
+    def run(self):
+        _check(lib().nb_run(self.h), "nb_run")
+
+    def step_index(self) -> int:
+        return int(lib().nb_step_index(self.h))
+
+    def pee(self, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.nb, dtype=torch.float64, device=self.ws.device)
+        _check(lib().nb_read_pee(self.h, C.c_void_p(out.data_ptr())), "nb_read_pee")
+        return out
+
+    def get_state(self):
+        torch = _torch()
+        out = torch.empty(self.nsc, self.nb, dtype=torch.float64, device=self.ws.device)
+        _check(lib().nb_get_state(self.h, C.c_void_p(out.data_ptr()), 1), "nb_get_state")
+        return out
+
+    def set_state(self, x, step: int):
+        torch = _torch()
+        x = x.to(device=self.ws.device, dtype=torch.float64).contiguous()
+        assert x.numel() == self.nsc * self.nb
+        _check(lib().nb_set_state(self.h, C.c_void_p(x.data_ptr()), int(step), 1),
+               "nb_set_state")
+
+
+# ------------------------------------------------------------------ test hooks
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def test_sincos(x):
+    torch = _torch()
+    s = torch.empty_like(x); c = torch.empty_like(x)
+    _check(lib().nb_test_sincos(_ptr(x), x.numel(), _ptr(s), _ptr(c), _stream_ptr()),
+           "nb_test_sincos")
+    return s, c
+
+
+def test_sqrt_div(a, b):
+    torch = _torch()
+    sq = torch.empty_like(a); dv = torch.empty_like(a)
+    _check(lib().nb_test_sqrt_div(_ptr(a), _ptr(b), a.numel(), _ptr(sq), _ptr(dv),
+                                  _stream_ptr()), "nb_test_sqrt_div")
+    return sq, dv
+
+
+def test_exp3(k9, psi6):
+    torch = _torch()
+    out = torch.empty_like(psi6)
+    _check(lib().nb_test_exp3(_ptr(k9), _ptr(psi6), psi6.shape[0], _ptr(out), _stream_ptr()),
+           "nb_test_exp3")
+    return out
+
+
+def test_rotate(x3, p3):
+    torch = _torch()
+    out = torch.empty_like(p3)
+    _check(lib().nb_test_rotate(_ptr(x3), _ptr(p3), p3.shape[0], _ptr(out), _stream_ptr()),
+           "nb_test_rotate")
+    return out

@@ -1,0 +1,549 @@
+// nb_api.hip -- host runtime behind include/nubulb.h: parameter validation, host tables,
+// workspace layout, cooperative launches, status checks and the test hooks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/nubulb.h"
+#include "nb_internal.h"
+
+namespace nb {
+template <int NF, typename ST>
+__global__ void k_advance(StepArgs a);
+__global__ void k_zero_sync(unsigned int* sync, int keep_status);
+template <typename ST>
+__global__ void k_init(ST* X, long long nb, long long plane, int nsc);
+template <typename ST>
+__global__ void k_read_pee(const ST* X, long long nb, long long plane, int nsc, double* out);
+template <typename ST>
+__global__ void k_state_xfer(ST* X, long long nb, long long plane, int nsc, double* buf, int dir);
+__global__ void k_test_sincos(const double* x, long long n, double* s, double* c);
+__global__ void k_test_sqrt_div(const double* a, const double* b, long long n, double* sq, double* dv);
+__global__ void k_test_exp3(const double* k9, const double* psi6, long long n, double* out6);
+__global__ void k_test_rotate(const double* x3, const double* p3, long long n, double* out3);
+}  // namespace nb
+
+using namespace nb;
+
+// ------------------------------------------------------------------- errors
+static thread_local std::string g_err;
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+#define NB_HIP(call)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess) return fail(NB_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" const char* nb_last_error(void) { return g_err.c_str(); }
+
+// --------------------------------------------------------------- constants
+// sqrt(2) G_F (hbar c)^3 in km^-1 cm^3 with G_F = 1.1663787e-5 GeV^-2 and
+// hbar c = 1.973269804e-14 GeV cm = 1.973269804e-19 GeV km.
+static double potential_per_density() {
+  const double hc_cm = 1.973269804e-14, hc_km = 1.973269804e-19;
+  return (1.4142135623730951 * 1.1663787e-5) * ((hc_cm * hc_cm) * hc_cm) / hc_km;
+}
+static constexpr double kVac = 1.0 / (4.0e6 * 1.973269804e-10);  // dm^2/(4E): eV^2/MeV -> km^-1
+static constexpr double kErgMeV = 624150.9074460763;
+static constexpr double kClight = 2.99792458e10;                  // cm/s
+static constexpr double kPi = 3.141592653589793;
+static constexpr double kFD2 = 1.8030853547393914;                // int x^2/(e^x+1) dx
+static constexpr double kFD3 = 5.682196976983475;                 // int x^3/(e^x+1) dx
+
+static double fd_spectrum(double E, double T) {  // normalised Fermi-Dirac, zero potential
+  return (E * E) / ((kFD2 * ((T * T) * T)) * (std::exp(E / T) + 1.0));
+}
+
+// ---------------------------------------------------------------- the model
+struct nb_model {
+  nb_params p{};
+  int nf = 2, nc = 3, nsc = 3, nmodels = 1;
+  long long NE = 0, NU = 0, nb = 0, plane = 0;
+  double h = 0, lam0 = 0, kappa0 = 0, s1 = 0, s0 = 0, p2e1 = 0, p2e0 = 0;
+  int e1 = 0, e0 = 0;
+  std::vector<double> E, tab;        // tab: device table image
+  long long step = 0;
+  // bound state
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  int device = 0, cus = 0, max_blocks = 0;
+  unsigned long long ticks_per_s = 0;
+  size_t off_X = 0, off_tab = 0, off_J = 0, off_part = 0, off_sync = 0, need = 0;
+  unsigned int* pinned = nullptr;
+};
+
+static bool state_fp32(const nb_model* m) { return m->nf == 3 && m->p.precision == NB_FP32_STATE; }
+
+static int validate(const nb_params* p) {
+  if (!p) return fail(NB_EINVAL, "params is NULL");
+  if (p->n_flavor != 2 && p->n_flavor != 3) return fail(NB_EINVAL, "n_flavor must be 2 or 3");
+  if (p->n_energy < 1 || p->n_u < 1) return fail(NB_EINVAL, "n_energy and n_u must be >= 1");
+  if ((long long)p->n_energy * p->n_u > (1LL << 34)) return fail(NB_EINVAL, "too many beams");
+  if (p->n_steps < 1) return fail(NB_EINVAL, "n_steps must be >= 1");
+  if (!(p->r_nu_km > 0.0) || !(p->r_start_km >= p->r_nu_km) || !(p->r_end_km > p->r_start_km))
+    return fail(NB_EINVAL, "need 0 < r_nu <= r_start < r_end");
+  if (!(p->e_min_mev > 0.0) || !(p->e_max_mev > p->e_min_mev))
+    return fail(NB_EINVAL, "need 0 < e_min < e_max");
+  if (p->delta_cp != 0.0) return fail(NB_EINVAL, "delta_cp must be 0");
+  if (p->ne_power < 0 || p->ne_power > 8) return fail(NB_EINVAL, "ne_power must be in 0..8");
+  if (p->precision != NB_FP64 && p->precision != NB_FP32_STATE)
+    return fail(NB_EINVAL, "unknown precision");
+  if (p->precision == NB_FP32_STATE && p->n_flavor != 3)
+    return fail(NB_EINVAL, "FP32 state is a three-flavour mode");
+  for (int i = 0; i < 3; ++i)
+    if (!(p->temp_mev[i] > 0.0) || !(p->lum_erg_s[i] >= 0.0))
+      return fail(NB_EINVAL, "temperatures must be > 0 and luminosities >= 0");
+  if (!(std::isfinite(p->n0_cm3) && p->n0_cm3 >= 0.0)) return fail(NB_EINVAL, "n0 must be >= 0");
+  if (p->adjoint_ckpt < 0) return fail(NB_EINVAL, "adjoint_ckpt must be >= 0");
+  if (p->max_blocks < 0) return fail(NB_EINVAL, "max_blocks must be >= 0");
+  return NB_OK;
+}
+
+// Host tables of one model (Sec. 2 / Sec. 3.2): bin midpoints, Fermi-Dirac spectra,
+// number luminosities N = L/<E>, weights g = kappa0 du dE (N_a f_a - N_x f_x), vacuum
+// Hamiltonians per energy, fixed-point scales.
+static void build_tables(nb_model* m) {
+  const nb_params& p = m->p;
+  const long long NE = m->NE;
+  const double dE = (p.e_max_mev - p.e_min_mev) / (double)NE;
+  const double du = 1.0 / (double)m->NU;
+  m->h = (p.r_end_km - p.r_start_km) / (double)p.n_steps;
+  const double s2gf = potential_per_density();
+  m->lam0 = s2gf * p.n0_cm3;
+  const double rcm = p.r_nu_km * 1.0e5;
+  m->kappa0 = s2gf / (((2.0 * kPi) * (rcm * rcm)) * kClight);
+  double N[3];
+  for (int a = 0; a < 3; ++a) N[a] = p.lum_erg_s[a] * kErgMeV / ((p.temp_mev[a] * kFD3) / kFD2);
+  const double pref = (m->kappa0 * du) * dE;
+  const int nv = (m->nf == 2) ? 2 : 6;
+  m->E.assign(NE, 0.0);
+  m->tab.assign((size_t)(nv + 2) * NE, 0.0);
+  double* G0 = m->tab.data() + (size_t)nv * NE;
+  double* G1 = G0 + NE;
+  double U[3][3];
+  if (m->nf == 3) {
+    const double c12 = std::cos(p.theta[0]), s12 = std::sin(p.theta[0]);
+    const double c13 = std::cos(p.theta[1]), s13 = std::sin(p.theta[1]);
+    const double c23 = std::cos(p.theta[2]), s23 = std::sin(p.theta[2]);
+    // U = R23 U13 R12 (delta = 0)
+    U[0][0] = c12 * c13; U[0][1] = s12 * c13; U[0][2] = s13;
+    U[1][0] = -(s12 * c23) - (c12 * s23) * s13; U[1][1] = c12 * c23 - (s12 * s23) * s13; U[1][2] = s23 * c13;
+    U[2][0] = s12 * s23 - (c12 * c23) * s13; U[2][1] = -(c12 * s23) - (s12 * c23) * s13; U[2][2] = c23 * c13;
+  }
+  for (long long k = 0; k < NE; ++k) {
+    const double e = p.e_min_mev + ((double)k + 0.5) * dE;
+    m->E[k] = e;
+    const double fe = fd_spectrum(e, p.temp_mev[0]);
+    const double fb = fd_spectrum(e, p.temp_mev[1]);
+    const double fx = fd_spectrum(e, p.temp_mev[2]);
+    // heavy-flavour-born states are I - rho_e (unitarity): they enter with -N_x f_x
+    G0[k] = pref * (N[0] * fe - N[2] * fx);
+    G1[k] = pref * (N[1] * fb - N[2] * fx);
+    if (m->nf == 2) {
+      const double om = (kVac * p.dm2_ev2[0]) / e;
+      const double s2 = std::sin(2.0 * p.theta[0]), c2 = std::cos(2.0 * p.theta[0]);
+      m->tab[k] = (2.0 * om) * s2;            // B_vac,x
+      m->tab[NE + k] = -((2.0 * om) * c2);    // B_vac,z
+    } else {
+      const double w2 = ((2.0 * kVac) * p.dm2_ev2[0]) / e;  // dm^2_21 / 2E
+      const double w3 = ((2.0 * kVac) * p.dm2_ev2[1]) / e;  // dm^2_31 / 2E
+      static const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+      for (int q = 0; q < 6; ++q)
+        m->tab[(size_t)q * NE + k] = (U[ia[q]][1] * U[ib[q]][1]) * w2 + (U[ia[q]][2] * U[ib[q]][2]) * w3;
+    }
+  }
+  // fixed point: every contribution |g rho~| * 2^e1 < 2^61; every angle term of J0
+  // (energy sum / cos) * 2^e0 < 2^61 (cos is smallest at r_start, u_max)
+  double wmax = 0.0;
+  for (long long k = 0; k < NE; ++k) wmax = std::max(wmax, std::max(std::fabs(G0[k]), std::fabs(G1[k])));
+  if (!(wmax > 0.0)) wmax = 1.0;
+  int ex = 0;
+  std::frexp(wmax, &ex);
+  m->e1 = 61 - ex;
+  const double qs = p.r_nu_km / p.r_start_km;
+  const double ulast = ((double)(m->NU - 1) + 0.5) / (double)m->NU;
+  const double cmin = std::sqrt(1.0 - ulast * (qs * qs));
+  const double b0 = (wmax * (double)NE) * (1.0 / cmin);
+  std::frexp(b0, &ex);
+  m->e0 = 61 - ex;
+  m->s1 = std::ldexp(1.0, m->e1);
+  m->p2e1 = std::ldexp(1.0, -m->e1);
+  m->s0 = std::ldexp(1.0, m->e0);
+  m->p2e0 = std::ldexp(1.0, -m->e0);
+}
+
+extern "C" int nb_model_create(const nb_params* p, nb_model** out) {
+  if (!out) return fail(NB_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(p);
+  if (rc) return rc;
+  nb_model* m = new (std::nothrow) nb_model();
+  if (!m) return fail(NB_EINVAL, "out of host memory");
+  m->p = *p;
+  m->nf = p->n_flavor;
+  m->nc = (m->nf == 2) ? 3 : 8;
+  m->nsc = (m->nf == 2) ? 3 : 6;
+  m->NE = p->n_energy;
+  m->NU = p->n_u;
+  m->nb = 2LL * m->NE * m->NU;
+  m->plane = (m->nb + 63) / 64 * 64;
+  build_tables(m);
+  *out = m;
+  return NB_OK;
+}
+
+extern "C" int nb_batch_create(const nb_params* p, int32_t n_models, nb_model** out) {
+  if (out) *out = nullptr;
+  (void)p;
+  (void)n_models;
+  return fail(NB_EINVAL, "batched models are not available in this build");
+}
+
+extern "C" void nb_model_destroy(nb_model* m) {
+  if (!m) return;
+  if (m->pinned) (void)hipHostFree(m->pinned);
+  delete m;
+}
+
+extern "C" int64_t nb_n_beams(const nb_model* m) { return m ? m->nb : 0; }
+extern "C" int32_t nb_n_models(const nb_model* m) { return m ? m->nmodels : 0; }
+extern "C" int32_t nb_state_comps(const nb_model* m) { return m ? m->nsc : 0; }
+extern "C" int64_t nb_step_index(const nb_model* m) { return m ? m->step : -1; }
+
+extern "C" int nb_pee_offsets(const nb_model* m, int64_t* off) {
+  if (!m || !off) return fail(NB_EINVAL, "NULL argument");
+  off[0] = 0;
+  off[1] = m->nb;
+  return NB_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Workspace layout: state planes | tables | stage moments | block partials | sync words.
+struct Layout {
+  size_t X, tab, J, part, sync, need;
+};
+// Partial buffer bound: blocks that can be resident on the largest device of this family.
+static constexpr int kMaxBlocksBound = 256 * 32;
+
+static Layout layout_of(const nb_model* m) {
+  const size_t es = state_fp32(m) ? sizeof(float) : sizeof(double);
+  Layout L{};
+  size_t o = 0;
+  L.X = o;
+  o = align256(o + es * (size_t)m->plane * m->nsc);
+  L.tab = o;
+  o = align256(o + sizeof(double) * m->tab.size());
+  L.J = o;
+  o = align256(o + sizeof(double) * 4 * 2 * m->nc);
+  L.part = o;
+  o = align256(o + 16 * (size_t)kMaxBlocksBound * 2 * m->nc);
+  L.sync = o;
+  o = align256(o + sizeof(unsigned int) * kSyncWords);
+  L.need = o;
+  return L;
+}
+
+extern "C" size_t nb_workspace_bytes(const nb_model* m) { return m ? layout_of(m).need : 0; }
+
+static const void* advance_kernel(const nb_model* m) {
+  if (m->nf == 2) return (const void*)&k_advance<2, double>;
+  if (state_fp32(m)) return (const void*)&k_advance<3, float>;
+  return (const void*)&k_advance<3, double>;
+}
+
+static int launch_1d(const void* fn, long long n, void** args, hipStream_t s) {
+  const int bs = 256;
+  const long long nblk = (n + bs - 1) / bs;
+  if (nblk <= 0) return NB_OK;
+  NB_HIP(hipLaunchKernel(fn, dim3((unsigned)nblk), dim3(bs), args, 0, s));
+  return NB_OK;
+}
+
+extern "C" int nb_reset(nb_model* m) {
+  if (!m) return fail(NB_EINVAL, "model is NULL");
+  if (!m->ws) return fail(NB_EUNBOUND, "no workspace bound");
+  void* X = m->ws + m->off_X;
+  long long nb_ = m->nb, plane = m->plane;
+  int nsc = m->nsc;
+  void* args[] = {&X, &nb_, &plane, &nsc};
+  int rc = launch_1d(state_fp32(m) ? (const void*)&k_init<float> : (const void*)&k_init<double>,
+                     m->nb, args, m->stream);
+  if (rc) return rc;
+  m->step = 0;
+  return NB_OK;
+}
+
+extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream) {
+  if (!m || !dev_ws) return fail(NB_EINVAL, "NULL model or workspace");
+  if (((uintptr_t)dev_ws) % 256) return fail(NB_EWORKSPACE, "workspace must be 256-byte aligned");
+  int dev = 0;
+  NB_HIP(hipGetDevice(&dev));
+  int cus = 0, khz = 0, nbpm = 0;
+  NB_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  NB_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  NB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nbpm, advance_kernel(m), kBlock, 0));
+  if (nbpm < 1) return fail(NB_EHIP, "stepping kernel cannot be resident");
+  int max_blocks = std::min(cus * nbpm, kMaxBlocksBound);
+  if (m->p.max_blocks > 0) max_blocks = std::min(max_blocks, (int)m->p.max_blocks);
+  const Layout L = layout_of(m);
+  if (bytes < L.need)
+    return fail(NB_EWORKSPACE, "workspace too small: %zu < %zu bytes", bytes, L.need);
+  m->off_X = L.X;
+  m->off_tab = L.tab;
+  m->off_J = L.J;
+  m->off_part = L.part;
+  m->off_sync = L.sync;
+  m->need = L.need;
+  m->ws = (char*)dev_ws;
+  m->ws_bytes = bytes;
+  m->stream = (hipStream_t)hip_stream;
+  m->device = dev;
+  m->cus = cus;
+  m->max_blocks = max_blocks;
+  m->ticks_per_s = (unsigned long long)(khz > 0 ? khz : 100000) * 1000ull;
+  if (!m->pinned) NB_HIP(hipHostMalloc((void**)&m->pinned, 64, hipHostMallocDefault));
+  NB_HIP(hipMemcpyAsync(m->ws + m->off_tab, m->tab.data(), sizeof(double) * m->tab.size(),
+                        hipMemcpyHostToDevice, m->stream));
+  unsigned int* sync = (unsigned int*)(m->ws + m->off_sync);
+  int keep = 0;
+  void* zargs[] = {&sync, &keep};
+  NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(1), dim3(kSyncWords), zargs, 0, m->stream));
+  return nb_reset(m);
+}
+
+static bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+  return st != hipStreamCaptureStatusNone;
+}
+
+// Read and clear the kernels' status word (only outside graph capture).
+static int check_status(nb_model* m) {
+  if (capturing(m->stream)) return NB_OK;
+  unsigned int* sync = (unsigned int*)(m->ws + m->off_sync);
+  NB_HIP(hipMemcpyAsync(m->pinned, sync + kSyncStatus, sizeof(unsigned int), hipMemcpyDeviceToHost,
+                        m->stream));
+  NB_HIP(hipStreamSynchronize(m->stream));
+  const unsigned st = m->pinned[0];
+  if (st) {
+    int keep = 0;
+    void* zargs[] = {&sync, &keep};
+    NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(1), dim3(kSyncWords), zargs, 0, m->stream));
+    NB_HIP(hipStreamSynchronize(m->stream));
+    if (st & 2u) return fail(NB_ETIMEOUT, "grid barrier time limit exceeded");
+    return fail(NB_ENUMERIC, "moment contribution out of fixed-point range (NaN or overflow)");
+  }
+  return NB_OK;
+}
+
+static int advance(nb_model* m, long long n) {
+  const long long rows = 2LL * m->NU;
+  const int want = (int)std::min<long long>((rows + 3) / 4, m->max_blocks);
+  const int nblocks = std::max(1, want);
+  // bound the barrier epochs of one launch well inside 32 bits
+  const long long chunk = std::max<long long>(1, (long long)(3.5e9 / ((double)nblocks * 4.0)) - 2);
+  while (n > 0) {
+    const long long k = std::min(n, chunk);
+    StepArgs a{};
+    a.X = m->ws + m->off_X;
+    a.tab = (const double*)(m->ws + m->off_tab);
+    a.J = (double*)(m->ws + m->off_J);
+    a.part = (unsigned long long*)(m->ws + m->off_part);
+    a.sync = (unsigned int*)(m->ws + m->off_sync);
+    a.plane = m->plane;
+    a.NE = (int)m->NE;
+    a.NU = (int)m->NU;
+    a.step0 = m->step;
+    a.nsteps = k;
+    a.rs = m->p.r_start_km;
+    a.h = m->h;
+    a.R = m->p.r_nu_km;
+    a.lam0 = m->lam0;
+    a.ne_power = m->p.ne_power;
+    a.renorm = m->p.renorm;
+    a.s1 = m->s1;
+    a.s0 = m->s0;
+    a.p2e1 = m->p2e1;
+    a.p2e0 = m->p2e0;
+    a.timeout_ticks = m->ticks_per_s * 20ull;
+    unsigned int* sync = a.sync;
+    int keep = 1;
+    void* zargs[] = {&sync, &keep};
+    NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(1), dim3(kSyncWords), zargs, 0, m->stream));
+    void* args[] = {&a};
+    NB_HIP(hipLaunchCooperativeKernel(advance_kernel(m), dim3(nblocks), dim3(kBlock), args, 0, m->stream));
+    m->step += k;
+    n -= k;
+    int rc = check_status(m);
+    if (rc) return rc;
+  }
+  return NB_OK;
+}
+
+extern "C" int nb_step(nb_model* m, int64_t n) {
+  if (!m) return fail(NB_EINVAL, "model is NULL");
+  if (!m->ws) return fail(NB_EUNBOUND, "no workspace bound");
+  if (n < 0) return fail(NB_EINVAL, "negative step count");
+  n = std::min<int64_t>(n, m->p.n_steps - m->step);
+  if (n <= 0) return NB_OK;
+  return advance(m, n);
+}
+
+extern "C" int nb_run(nb_model* m) {
+  if (!m) return fail(NB_EINVAL, "model is NULL");
+  return nb_step(m, m->p.n_steps - m->step);
+}
+
+extern "C" int nb_read_pee(const nb_model* m, double* dev_out) {
+  if (!m || !dev_out) return fail(NB_EINVAL, "NULL argument");
+  if (!m->ws) return fail(NB_EUNBOUND, "no workspace bound");
+  void* X = m->ws + m->off_X;
+  long long nb_ = m->nb, plane = m->plane;
+  int nsc = m->nsc;
+  void* args[] = {&X, &nb_, &plane, &nsc, &dev_out};
+  int rc = launch_1d(state_fp32(m) ? (const void*)&k_read_pee<float> : (const void*)&k_read_pee<double>,
+                     m->nb, args, m->stream);
+  if (rc) return rc;
+  if (!capturing(m->stream)) NB_HIP(hipStreamSynchronize(m->stream));
+  return NB_OK;
+}
+
+static int xfer(nb_model* m, double* buf, int dir) {
+  void* X = m->ws + m->off_X;
+  long long nb_ = m->nb, plane = m->plane;
+  int nsc = m->nsc;
+  void* args[] = {&X, &nb_, &plane, &nsc, &buf, &dir};
+  return launch_1d(state_fp32(m) ? (const void*)&k_state_xfer<float> : (const void*)&k_state_xfer<double>,
+                   m->nb, args, m->stream);
+}
+
+extern "C" int nb_get_state(const nb_model* mc, double* dst, int on_device) {
+  nb_model* m = const_cast<nb_model*>(mc);
+  if (!m || !dst) return fail(NB_EINVAL, "NULL argument");
+  if (!m->ws) return fail(NB_EUNBOUND, "no workspace bound");
+  const size_t bytes = sizeof(double) * (size_t)m->nb * m->nsc;
+  if (on_device) {
+    int rc = xfer(m, dst, 0);
+    if (rc) return rc;
+    NB_HIP(hipStreamSynchronize(m->stream));
+    return NB_OK;
+  }
+  double* tmp = nullptr;
+  NB_HIP(hipMallocAsync((void**)&tmp, bytes, m->stream));
+  int rc = xfer(m, tmp, 0);
+  if (!rc) {
+    hipError_t e = hipMemcpyAsync(dst, tmp, bytes, hipMemcpyDeviceToHost, m->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    if (e != hipSuccess) rc = fail(NB_EHIP, "state copy failed: %s", hipGetErrorString(e));
+  }
+  (void)hipFreeAsync(tmp, m->stream);
+  (void)hipStreamSynchronize(m->stream);
+  return rc;
+}
+
+extern "C" int nb_set_state(nb_model* m, const double* src, int64_t step, int on_device) {
+  if (!m || !src) return fail(NB_EINVAL, "NULL argument");
+  if (!m->ws) return fail(NB_EUNBOUND, "no workspace bound");
+  if (step < 0 || step > m->p.n_steps) return fail(NB_EINVAL, "step out of range");
+  const size_t bytes = sizeof(double) * (size_t)m->nb * m->nsc;
+  if (on_device) {
+    int rc = xfer(m, const_cast<double*>(src), 1);
+    if (rc) return rc;
+  } else {
+    double* tmp = nullptr;
+    NB_HIP(hipMallocAsync((void**)&tmp, bytes, m->stream));
+    hipError_t e = hipMemcpyAsync(tmp, src, bytes, hipMemcpyHostToDevice, m->stream);
+    int rc = (e == hipSuccess) ? xfer(m, tmp, 1) : fail(NB_EHIP, "copy: %s", hipGetErrorString(e));
+    (void)hipFreeAsync(tmp, m->stream);
+    if (rc) return rc;
+  }
+  NB_HIP(hipStreamSynchronize(m->stream));
+  m->step = step;
+  return NB_OK;
+}
+
+extern "C" int nb_adjoint(nb_model* m, const double* dev_dl_dpee, double* grad_out, int32_t ckpt_every) {
+  (void)dev_dl_dpee;
+  (void)grad_out;
+  (void)ckpt_every;
+  if (!m) return fail(NB_EINVAL, "model is NULL");
+  return fail(NB_EINVAL, "adjoint is not available in this build");
+}
+
+extern "C" int nb_host_tables(const nb_model* m, double* out, int64_t cap) {
+  if (!m || !out) return fail(NB_EINVAL, "NULL argument");
+  const int nv = (m->nf == 2) ? 2 : 6;
+  const long long NE = m->NE;
+  const long long need = NE + 2 * NE + nv * NE + 7;
+  if (cap < need) return fail(NB_EINVAL, "output too small (%lld needed)", need);
+  long long o = 0;
+  for (long long k = 0; k < NE; ++k) out[o++] = m->E[k];
+  for (int s = 0; s < 2; ++s)
+    for (long long k = 0; k < NE; ++k) out[o++] = m->tab[(size_t)(nv + s) * NE + k];
+  for (long long k = 0; k < NE; ++k)
+    for (int q = 0; q < nv; ++q) out[o++] = m->tab[(size_t)q * NE + k];
+  out[o++] = m->lam0;
+  out[o++] = m->kappa0;
+  out[o++] = m->h;
+  out[o++] = m->p2e1;
+  out[o++] = m->p2e0;
+  out[o++] = m->e1;
+  out[o++] = m->e0;
+  return NB_OK;
+}
+
+// ------------------------------------------------------------------ test hooks
+extern "C" int nb_test_sincos(const double* x, int64_t n, double* s, double* c, void* stream) {
+  if (n < 0 || (n > 0 && (!x || !s || !c))) return fail(NB_EINVAL, "bad arguments");
+  long long nn = n;
+  void* args[] = {&x, &nn, &s, &c};
+  int rc = launch_1d((const void*)&k_test_sincos, n, args, (hipStream_t)stream);
+  if (rc) return rc;
+  NB_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return NB_OK;
+}
+extern "C" int nb_test_sqrt_div(const double* a, const double* b, int64_t n, double* sq, double* dv,
+                                void* stream) {
+  if (n < 0 || (n > 0 && (!a || !b || !sq || !dv))) return fail(NB_EINVAL, "bad arguments");
+  long long nn = n;
+  void* args[] = {&a, &b, &nn, &sq, &dv};
+  int rc = launch_1d((const void*)&k_test_sqrt_div, n, args, (hipStream_t)stream);
+  if (rc) return rc;
+  NB_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return NB_OK;
+}
+extern "C" int nb_test_exp3(const double* k9, const double* psi6, int64_t n, double* out6, void* stream) {
+  if (n < 0 || (n > 0 && (!k9 || !psi6 || !out6))) return fail(NB_EINVAL, "bad arguments");
+  long long nn = n;
+  void* args[] = {&k9, &psi6, &nn, &out6};
+  int rc = launch_1d((const void*)&k_test_exp3, n, args, (hipStream_t)stream);
+  if (rc) return rc;
+  NB_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return NB_OK;
+}
+extern "C" int nb_test_rotate(const double* x3, const double* p3, int64_t n, double* out3, void* stream) {
+  if (n < 0 || (n > 0 && (!x3 || !p3 || !out3))) return fail(NB_EINVAL, "bad arguments");
+  long long nn = n;
+  void* args[] = {&x3, &p3, &nn, &out3};
+  int rc = launch_1d((const void*)&k_test_rotate, n, args, (hipStream_t)stream);
+  if (rc) return rc;
+  NB_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return NB_OK;
+}

@@ -1,0 +1,297 @@
+// nb_device.h -- CDNA4 device primitives of the bulb-model stepper.
+//
+// Arithmetic specification (bit-for-bit contract with the CPU reference): every
+// multiply and add below is rounded separately (the library is compiled with
+// -ffp-contract=off); fma appears only where written; division and sqrt are the IEEE
+// correctly rounded operations; sin/cos are the library's own (Cody-Waite reduction by
+// pi/2 in three parts, Taylor polynomials of degree 17/18); moment sums are exact
+// integer sums of truncated fixed-point values, so their result does not depend on the
+// grid shape or on the order in which waves and blocks finish.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nb {
+
+constexpr double kTwo62 = 4611686018427387904.0;
+constexpr double kTwo64 = 18446744073709551616.0;
+
+// ------------------------------------------------------------------ sin / cos
+// sin and cos of one argument.  Reduction x = k pi/2 + r with k = rint(2x/pi) and a
+// three-part split of pi/2 (each part applied with one fma); then Taylor series of sin
+// (to r^17) and cos (to r^18) by Horner in r^2; the quadrant k mod 4 picks signs.
+__device__ __forceinline__ void sincos_nb(double x, double& sn, double& cs) {
+  const double k = rint(x * 0x1.45f306dc9c883p-1);
+  double r = fma(-k, 0x1.921fb54442d18p+0, x);
+  r = fma(-k, 0x1.1a62633145c07p-54, r);
+  r = fma(-k, -0x1.f1976b7ed8fbcp-110, r);
+  const double r2 = r * r;
+  double ps = 1.0 / 355687428096000.0;
+  ps = fma(ps, r2, -1.0 / 1307674368000.0);
+  ps = fma(ps, r2, 1.0 / 6227020800.0);
+  ps = fma(ps, r2, -1.0 / 39916800.0);
+  ps = fma(ps, r2, 1.0 / 362880.0);
+  ps = fma(ps, r2, -1.0 / 5040.0);
+  ps = fma(ps, r2, 1.0 / 120.0);
+  ps = fma(ps, r2, -1.0 / 6.0);
+  const double s = fma(r2 * r, ps, r);
+  double pc = -1.0 / 6402373705728000.0;
+  pc = fma(pc, r2, 1.0 / 20922789888000.0);
+  pc = fma(pc, r2, -1.0 / 87178291200.0);
+  pc = fma(pc, r2, 1.0 / 479001600.0);
+  pc = fma(pc, r2, -1.0 / 3628800.0);
+  pc = fma(pc, r2, 1.0 / 40320.0);
+  pc = fma(pc, r2, -1.0 / 720.0);
+  pc = fma(pc, r2, 1.0 / 24.0);
+  pc = fma(pc, r2, -0.5);
+  const double c = fma(r2, pc, 1.0);
+  const int quad = (int)((long long)k & 3);
+  const double a = (quad & 1) ? c : s;    // |sin| candidate
+  const double b = (quad & 1) ? s : c;    // |cos| candidate
+  sn = (quad & 2) ? -a : a;
+  cs = ((quad + 1) & 2) ? -b : b;
+}
+
+// ------------------------------------------------------------- fixed point
+// 128-bit two's complement integer held as two 64-bit halves.
+struct I128 {
+  unsigned long long lo;
+  long long hi;
+};
+__device__ __forceinline__ I128 i128_zero() { return I128{0ull, 0ll}; }
+__device__ __forceinline__ I128 i128_from(long long v) {
+  return I128{(unsigned long long)v, v >> 63};
+}
+__device__ __forceinline__ I128 i128_add(I128 a, I128 b) {
+  I128 r;
+  r.lo = a.lo + b.lo;
+  r.hi = a.hi + b.hi + (long long)(r.lo < a.lo);
+  return r;
+}
+// Sign-magnitude conversion: |x| = hi 2^64 + lo, (double)hi * 2^64 + (double)lo.
+__device__ __forceinline__ double i128_to_double(I128 x) {
+  const bool neg = x.hi < 0;
+  unsigned long long lo = x.lo, hi = (unsigned long long)x.hi;
+  if (neg) {
+    lo = ~lo + 1ull;
+    hi = ~hi + (unsigned long long)(lo == 0ull);
+  }
+  const double v = (double)hi * kTwo64 + (double)lo;
+  return neg ? -v : v;
+}
+// trunc(v * scale) as an integer; flags values outside (-2^62, 2^62) (NaN included).
+__device__ __forceinline__ long long to_fix(double v, double scale, int& err) {
+  const double x = v * scale;
+  if (!(fabs(x) < kTwo62)) {
+    err = 1;
+    return 0;
+  }
+  return (long long)x;
+}
+// Butterfly sum over the 64 lanes of a wavefront; every lane gets the total.
+__device__ __forceinline__ I128 wave_sum(I128 a) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    I128 o;
+    o.lo = __shfl_xor(a.lo, off, 64);
+    o.hi = __shfl_xor(a.hi, off, 64);
+    a = i128_add(a, o);
+  }
+  return a;
+}
+
+// ------------------------------------------------------------------ complex
+struct cplx {
+  double re, im;
+};
+__device__ __forceinline__ cplx mk(double re, double im) { return cplx{re, im}; }
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return mk(fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re));
+}
+__device__ __forceinline__ cplx cmul_conjb(cplx a, cplx b) {  // a * conj(b)
+  return mk(fma(a.re, b.re, a.im * b.im), fma(a.im, b.re, -(a.re * b.im)));
+}
+__device__ __forceinline__ cplx cmul_conja(cplx a, cplx b) {  // conj(a) * b
+  return mk(fma(a.re, b.re, a.im * b.im), fma(a.re, b.im, -(a.im * b.re)));
+}
+__device__ __forceinline__ cplx rmul(double a, cplx b) { return mk(a * b.re, a * b.im); }
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return mk(a.re + b.re, a.im + b.im); }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return mk(a.re - b.re, a.im - b.im); }
+__device__ __forceinline__ cplx conjg(cplx a) { return mk(a.re, -a.im); }
+__device__ __forceinline__ double norm2(cplx a) { return fma(a.re, a.re, a.im * a.im); }
+
+// Hermitian 3x3: real diagonal d0..d2, upper entries o01, o02, o12.
+struct Herm3 {
+  double d0, d1, d2;
+  cplx o01, o02, o12;
+};
+__device__ __forceinline__ cplx hat(const Herm3& h, int a, int b) {
+  // compile-time indices after unrolling
+  if (a == b) return mk(a == 0 ? h.d0 : (a == 1 ? h.d1 : h.d2), 0.0);
+  const cplx o = (a + b == 1) ? h.o01 : ((a + b == 2) ? h.o02 : h.o12);
+  return a < b ? o : conjg(o);
+}
+__device__ __forceinline__ Herm3 hscale(double s, const Herm3& h) {
+  return Herm3{s * h.d0, s * h.d1, s * h.d2, rmul(s, h.o01), rmul(s, h.o02), rmul(s, h.o12)};
+}
+
+// C(A,B) = i [A,B]: with X = A B, C_aa = -2 Im X_aa, C_ab = i (X_ab - conj(X_ba)).
+__device__ __forceinline__ Herm3 icomm(const Herm3& A, const Herm3& B) {
+  cplx X[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      X[a][b] = cadd(cadd(cmul(hat(A, a, 0), hat(B, 0, b)), cmul(hat(A, a, 1), hat(B, 1, b))),
+                     cmul(hat(A, a, 2), hat(B, 2, b)));
+  Herm3 C;
+  C.d0 = -2.0 * X[0][0].im;
+  C.d1 = -2.0 * X[1][1].im;
+  C.d2 = -2.0 * X[2][2].im;
+  {
+    const double dre = X[0][1].re - X[1][0].re, dim = X[0][1].im + X[1][0].im;
+    C.o01 = mk(-dim, dre);
+  }
+  {
+    const double dre = X[0][2].re - X[2][0].re, dim = X[0][2].im + X[2][0].im;
+    C.o02 = mk(-dim, dre);
+  }
+  {
+    const double dre = X[1][2].re - X[2][1].re, dim = X[1][2].im + X[2][1].im;
+    C.o12 = mk(-dim, dre);
+  }
+  return C;
+}
+
+__device__ __forceinline__ void cross3c(const cplx u[3], const cplx v[3], cplx o[3]) {
+  o[0] = csub(cmul(u[1], v[2]), cmul(u[2], v[1]));
+  o[1] = csub(cmul(u[2], v[0]), cmul(u[0], v[2]));
+  o[2] = csub(cmul(u[0], v[1]), cmul(u[1], v[0]));
+}
+__device__ __forceinline__ cplx dotc(const cplx u[3], const cplx v[3]) {  // u^+ v
+  return cadd(cadd(cmul_conja(u[0], v[0]), cmul_conja(u[1], v[1])), cmul_conja(u[2], v[2]));
+}
+__device__ __forceinline__ double cnorm2v(const cplx v[3]) {
+  return (norm2(v[0]) + norm2(v[1])) + norm2(v[2]);
+}
+
+// psi <- exp(-i K) psi up to a global phase (three flavours).  exp(-iK) splits into the
+// isolated eigen-direction v1 of the traceless part K0 (eigenvalue l1 of largest
+// magnitude, found by Newton on the characteristic cubic l^3 - p l - q) and the 2x2
+// block K' = W^+ K0 W on its orthogonal complement, which is propagated by the
+// closed-form SU(2) exponential of Eq. U; traces only add global phases.
+__device__ __forceinline__ void exp3_apply(const Herm3& K, cplx psi[3]) {
+  const double tr = ((K.d0 + K.d1) + K.d2) * (1.0 / 3.0);
+  const double a0 = K.d0 - tr, a1 = K.d1 - tr, a2 = K.d2 - tr;
+  const cplx x = K.o01, y = K.o02, z = K.o12;
+  const double nx = norm2(x), ny = norm2(y), nz = norm2(z);
+  const double s2 = fma(a0, a0, fma(a1, a1, a2 * a2));
+  const double p = fma(0.5, s2, (nx + ny) + nz);
+  const cplx xz = cmul(x, z);
+  const double t = fma(xz.re, y.re, xz.im * y.im);
+  const double q = fma(a0, fma(a1, a2, -nz), fma(-a1, ny, fma(-a2, nx, 2.0 * t)));
+  if (!(p > 0.0)) return;
+  const double sg = (q < 0.0) ? -1.0 : 1.0;
+  const double qa = sg * q;
+  double lam = 2.0 * sqrt(p * (1.0 / 3.0));
+#pragma unroll
+  for (int it = 0; it < 6; ++it) {
+    const double l2 = lam * lam;
+    const double fv = fma(lam, l2 - p, -qa);
+    const double dv = fma(3.0, l2, -p);
+    lam = lam - fv / dv;
+  }
+  const double l1 = sg * lam;
+  const cplx r0[3] = {mk(a0 - l1, 0.0), x, y};
+  const cplx r1[3] = {conjg(x), mk(a1 - l1, 0.0), z};
+  const cplx r2[3] = {conjg(y), conjg(z), mk(a2 - l1, 0.0)};
+  cplx c01[3], c02[3], c12[3];
+  cross3c(r0, r1, c01);
+  cross3c(r0, r2, c02);
+  cross3c(r1, r2, c12);
+  const double n01 = cnorm2v(c01), n02 = cnorm2v(c02), n12 = cnorm2v(c12);
+  cplx best[3] = {c01[0], c01[1], c01[2]};
+  double nb = n01;
+  if (n02 > nb) {
+    best[0] = c02[0]; best[1] = c02[1]; best[2] = c02[2];
+    nb = n02;
+  }
+  if (n12 > nb) {
+    best[0] = c12[0]; best[1] = c12[1]; best[2] = c12[2];
+    nb = n12;
+  }
+  if (!(nb > 0.0)) return;
+  const double inb = 1.0 / sqrt(nb);
+  const cplx v1[3] = {rmul(inb, best[0]), rmul(inb, best[1]), rmul(inb, best[2])};
+  const double nc0 = norm2(v1[0]), nc1 = norm2(v1[1]), nc2 = norm2(v1[2]);
+  int m = 0;
+  double ncm = nc0;
+  if (nc1 < ncm) { m = 1; ncm = nc1; }
+  if (nc2 < ncm) { m = 2; ncm = nc2; }
+  const cplx vm = (m == 0) ? v1[0] : ((m == 1) ? v1[1] : v1[2]);
+  cplx w[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cplx tm = cmul_conjb(v1[c], vm);
+    w[c] = (c == m) ? mk(1.0 - ncm, 0.0) : mk(-tm.re, -tm.im);
+  }
+  const double inw = 1.0 / sqrt(cnorm2v(w));
+  const cplx w2[3] = {rmul(inw, w[0]), rmul(inw, w[1]), rmul(inw, w[2])};
+  cplx w3[3];
+  cross3c(v1, w2, w3);
+  w3[0] = conjg(w3[0]); w3[1] = conjg(w3[1]); w3[2] = conjg(w3[2]);
+  cplx kw2[3], kw3[3];
+  kw2[0] = cadd(cadd(rmul(a0, w2[0]), cmul(x, w2[1])), cmul(y, w2[2]));
+  kw2[1] = cadd(cadd(cmul_conja(x, w2[0]), rmul(a1, w2[1])), cmul(z, w2[2]));
+  kw2[2] = cadd(cadd(cmul_conja(y, w2[0]), cmul_conja(z, w2[1])), rmul(a2, w2[2]));
+  kw3[0] = cadd(cadd(rmul(a0, w3[0]), cmul(x, w3[1])), cmul(y, w3[2]));
+  kw3[1] = cadd(cadd(cmul_conja(x, w3[0]), rmul(a1, w3[1])), cmul(z, w3[2]));
+  kw3[2] = cadd(cadd(cmul_conja(y, w3[0]), cmul_conja(z, w3[1])), rmul(a2, w3[2]));
+  const double k22 = dotc(w2, kw2).re, k33 = dotc(w3, kw3).re;
+  const cplx k23 = dotc(w2, kw3);
+  const double hm = 0.5 * (k22 + k33), h11 = 0.5 * (k22 - k33);
+  const double phi = l1 - hm;
+  const double th = sqrt(fma(h11, h11, norm2(k23)));
+  double sp, cp, st, ct;
+  sincos_nb(phi, sp, cp);
+  sincos_nb(th, st, ct);
+  const double sc = (th > 0.0) ? st / th : 0.0;
+  const cplx al = cmul(dotc(v1, psi), mk(cp, -sp));
+  const cplx b2 = dotc(w2, psi), b3 = dotc(w3, psi);
+  const double hs = h11 * sc;
+  const cplx g = mk(k23.re * sc, k23.im * sc);
+  const cplx t2 = cadd(rmul(hs, b2), cmul(g, b3));
+  const cplx t3 = csub(cmul_conja(g, b2), rmul(hs, b3));
+  const cplx b2n = mk(ct * b2.re + t2.im, ct * b2.im - t2.re);
+  const cplx b3n = mk(ct * b3.re + t3.im, ct * b3.im - t3.re);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    psi[c] = cadd(cadd(cmul(al, v1[c]), cmul(b2n, w2[c])), cmul(b3n, w3[c]));
+}
+
+// Bloch-vector rotation about x by |x| (two flavours): unit quaternion
+// (cos|x|/2, sin(|x|/2) x/|x|), P' = P + w t + v x t with t = 2 v x P.
+__device__ __forceinline__ void rotate2(const double x0, const double x1, const double x2,
+                                        double& P0, double& P1, double& P2) {
+  const double t2 = (x0 * x0 + x1 * x1) + x2 * x2;
+  const double th = sqrt(t2);
+  if (th == 0.0) return;
+  double s, c;
+  sincos_nb(0.5 * th, s, c);
+  const double k = s / th;
+  const double v0 = x0 * k, v1 = x1 * k, v2 = x2 * k;
+  double t0 = v1 * P2 - v2 * P1;
+  double t1 = v2 * P0 - v0 * P2;
+  double tt = v0 * P1 - v1 * P0;
+  t0 = t0 + t0;
+  t1 = t1 + t1;
+  tt = tt + tt;
+  const double u0 = v1 * tt - v2 * t1;
+  const double u1 = v2 * t0 - v0 * tt;
+  const double u2 = v0 * t1 - v1 * t0;
+  P0 = (P0 + c * t0) + u0;
+  P1 = (P1 + c * t1) + u1;
+  P2 = (P2 + c * tt) + u2;
+}
+
+}  // namespace nb

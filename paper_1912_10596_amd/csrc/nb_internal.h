@@ -1,0 +1,33 @@
+// nb_internal.h -- layouts shared by the kernels and the host runtime (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nb {
+
+// Offsets (in 32-bit words) of the synchronisation words; each on its own 128-byte line.
+constexpr int kSyncCount = 0;    // barrier arrivals (monotonic within one launch)
+constexpr int kSyncFlag = 32;    // last completed barrier epoch + 1
+constexpr int kSyncAbort = 64;   // set when any block gives up waiting
+constexpr int kSyncStatus = 96;  // bit 0: fixed-point range error, bit 1: barrier timeout
+constexpr int kSyncWords = 128;
+
+constexpr int kBlock = 256;      // threads per block of the stepping kernels (4 waves)
+
+// Arguments of the single-model stepping kernel (passed by value).
+struct StepArgs {
+  void* X;                 // state planes [nsc][plane] (double, or float for FP32 state)
+  const double* tab;       // tables: 2f [bx|bz|G0|G1] x NE; 3f [h_ee..h_mt (6)|G0|G1] x NE
+  double* J;               // stage moments [4][2*NC]: J0 then J1 per slot
+  unsigned long long* part;// block partials [gridDim][2*NC][2] (I128 halves)
+  unsigned int* sync;      // kSyncWords words
+  long long plane;         // plane stride (elements)
+  int NE, NU;
+  long long step0, nsteps;
+  double rs, h, R, lam0;
+  int ne_power, renorm;
+  double s1, s0, p2e1, p2e0;  // fixed-point scales 2^e1, 2^e0, 2^-e1, 2^-e0
+  unsigned long long timeout_ticks;
+};
+
+}  // namespace nb

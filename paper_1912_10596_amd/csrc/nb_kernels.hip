@@ -1,0 +1,508 @@
+// nb_kernels.hip -- persistent CDNA4 kernels of the bulb-model radial stepper.
+//
+// One cooperative launch advances every beam by `nsteps` radial steps.  Work unit: one
+// (species, emission-bin) row of N_E beams per wavefront -- the paper's NBeam with its
+// SIMD loop over energy bins (Sec. 3.3) mapped onto 64 lanes.  Per RK stage each wave
+//   1. streams its rows' state planes (SoA, coalesced 64 x 8 B per load),
+//   2. rebuilds every beam's stage generator from the global stage moments (no per-beam
+//      stage storage: F_1..F_{i-1} are recomputed from J^(1..i-1)),
+//   3. applies the exact exponential to get the stage state Y_i (Eq. U),
+//   4. accumulates the beam's moment contribution as a 64-bit fixed-point integer; the
+//      row's energy sum is a wavefront butterfly of 128-bit integers, then the angle sum
+//      (1/cos weighting for J0) is added to per-lane totals,
+// then the block folds its waves through LDS and the grid meets at a barrier whose last
+// arriving block folds all block partials into J^(i) (agent-scope release/acquire).
+// Four barriers per step; the final pass writes rho_{n+1} and also produces the next
+// step's stage-1 moments.
+#include "nb_device.h"
+#include "nb_internal.h"
+
+namespace nb {
+
+struct Radial {
+  double q2, lam, mu;
+};
+
+__device__ __forceinline__ Radial radial_at(const StepArgs& a, double r) {
+  Radial g;
+  const double q = a.R / r;
+  g.q2 = q * q;
+  double qp = 1.0;
+  for (int i = 0; i < a.ne_power; ++i) qp = qp * q;
+  g.lam = a.lam0 * qp;   // sqrt2 G_F n_e(r)
+  g.mu = 0.5 * g.q2;     // R^2 / 2r^2 from d cos(theta') = (R^2/2r^2) du / cos(theta')
+  return g;
+}
+
+__device__ __forceinline__ double as_double(unsigned long long u) { return __longlong_as_double((long long)u); }
+__device__ __forceinline__ unsigned long long as_bits(double d) { return (unsigned long long)__double_as_longlong(d); }
+
+template <int NV>
+__device__ __forceinline__ I128 select_comp(const I128 (&S)[NV], int c) {
+  I128 r = S[0];
+#pragma unroll
+  for (int i = 1; i < NV; ++i) {
+    if (c == i) r = S[i];
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------- grid barrier
+// The block's partial (valid in threads tid < NV) is published, the grid meets, and the
+// last block to arrive folds all partials into the stage moments (J0 | J1) which every
+// block then reads into LDS.  Returns false if the barrier was abandoned (time limit).
+template <int NV>
+__device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, double* sJ,
+                            double* gJ, I128* sred) {
+  __shared__ int s_last, s_ok;
+  const int tid = threadIdx.x;
+  if (tid < NV) {
+    unsigned long long* p = a.part + ((size_t)blockIdx.x * NV + tid) * 2;
+    __hip_atomic_store(p, blk.lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p + 1, (unsigned long long)blk.hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned old = __hip_atomic_fetch_add(a.sync + kSyncCount, 1u, __ATOMIC_ACQ_REL,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (old == (epoch + 1u) * gridDim.x - 1u) ? 1 : 0;
+  }
+  __syncthreads();
+  if (s_last) {
+    constexpr int G = kBlock / NV;
+    const int v = tid % NV, g = tid / NV;
+    I128 acc = i128_zero();
+    if (g < G) {
+      for (unsigned b = g; b < gridDim.x; b += G) {
+        const unsigned long long* p = a.part + ((size_t)b * NV + v) * 2;
+        I128 t;
+        t.lo = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t.hi = (long long)__hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        acc = i128_add(acc, t);
+      }
+      sred[tid] = acc;
+    }
+    __syncthreads();
+    if (tid < NV) {
+      I128 tot = i128_zero();
+      for (int gg = 0; gg < G; ++gg) tot = i128_add(tot, sred[gg * NV + tid]);
+      const double val = i128_to_double(tot) * (tid < NV / 2 ? a.p2e0 : a.p2e1);
+      sJ[tid] = val;
+      __hip_atomic_store((unsigned long long*)gJ + tid, as_bits(val), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+    }
+    __syncthreads();
+    if (tid == 0)
+      __hip_atomic_store(a.sync + kSyncFlag, epoch + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+  }
+  if (tid == 0) {
+    const unsigned long long t0 = wall_clock64();
+    int ok = 1;
+    for (;;) {
+      const unsigned f = __hip_atomic_load(a.sync + kSyncFlag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      if (f >= epoch + 1u) break;
+      if (__hip_atomic_load(a.sync + kSyncAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        ok = 0;
+        break;
+      }
+      if (wall_clock64() - t0 > a.timeout_ticks) {
+        __hip_atomic_store(a.sync + kSyncAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_or(a.sync + kSyncStatus, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  if (!s_ok) return false;
+  if (tid < NV)
+    sJ[tid] = as_double(__hip_atomic_load((unsigned long long*)gJ + tid, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT));
+  __syncthreads();
+  return true;
+}
+
+// Fold the waves' per-lane totals (lane v holds value v) and run the grid reduction.
+template <int NV>
+__device__ bool finish_stage(const StepArgs& a, unsigned epoch, I128 T, I128 (*sw)[NV],
+                             I128* sred, double* sJ, double* gJ) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane < NV) sw[wid][lane] = T;
+  __syncthreads();
+  I128 blk = i128_zero();
+  if (threadIdx.x < NV)
+    for (int w = 0; w < kBlock / 64; ++w) blk = i128_add(blk, sw[w][threadIdx.x]);
+  return grid_reduce<NV>(a, epoch, blk, sJ, gJ, sred);
+}
+
+// ----------------------------------------------------------------- two flavours
+// B vector of beam (s, k) (H = B.sigma/2 + trace): neutrinos
+// B_vac + lam e_z + mu (J0 - c J1); antineutrinos B_vac - lam e_z - mu (J0 - c J1)^*,
+// where ^* maps (x, y, z) -> (x, -y, z).  The stage generator is f = (h/c) B.
+__device__ __forceinline__ void gen2(int s, double bx, double bz, const Radial& g, double c,
+                                     double hc, const double* J, double f[3]) {
+  const double nx = g.mu * (J[0] - c * J[3]);
+  const double ny = g.mu * (J[1] - c * J[4]);
+  const double nz = g.mu * (J[2] - c * J[5]);
+  double B0, B1, B2;
+  if (s == 0) {
+    B0 = bx + nx;
+    B1 = ny;
+    B2 = (bz + g.lam) + nz;
+  } else {
+    B0 = bx - nx;
+    B1 = ny;
+    B2 = (bz - g.lam) - nz;
+  }
+  f[0] = hc * B0;
+  f[1] = hc * B1;
+  f[2] = hc * B2;
+}
+
+// KIND: 0 moments of rho_n at r_n; 1 stage Y2 (moments at r_n + h/2); 2 stage Y3
+// (r_n + h/2); 3 stage Y4 (r_{n+1}); 4 final update, store and moments at r_{n+1}.
+template <int KIND>
+__device__ __forceinline__ void stage2(const StepArgs& a, long long n, const double (*sJ)[6],
+                                       long long gw, long long nw, int lane, I128& T, int& err) {
+  const double r0 = a.rs + (double)n * a.h;
+  const double rm = r0 + 0.5 * a.h;
+  const double r1 = a.rs + (double)(n + 1) * a.h;
+  const Radial g0 = radial_at(a, r0), gm = radial_at(a, rm), g1 = radial_at(a, r1);
+  const long long nrow = 2LL * a.NU, plane = a.plane;
+  double* X = (double*)a.X;
+  const double* tbx = a.tab;
+  const double* tbz = a.tab + a.NE;
+  for (long long row = gw; row < nrow; row += nw) {
+    const int s = (int)(row / a.NU);
+    const int j = (int)(row - (long long)s * a.NU);
+    const double u = ((double)j + 0.5) / (double)a.NU;
+    const double c0 = sqrt(1.0 - u * g0.q2), cm = sqrt(1.0 - u * gm.q2), c1 = sqrt(1.0 - u * g1.q2);
+    const double hc0 = a.h / c0, hcm = a.h / cm, hc1 = a.h / c1;
+    const double cmom = (KIND == 0) ? c0 : ((KIND <= 2) ? cm : c1);
+    const double icmom = 1.0 / cmom;
+    const double* G = a.tab + (size_t)(2 + s) * a.NE;
+    I128 S[3] = {i128_zero(), i128_zero(), i128_zero()};
+    for (int k = lane; k < a.NE; k += 64) {
+      const long long b = row * a.NE + k;
+      double P0 = X[b], P1 = X[b + plane], P2 = X[b + 2 * plane];
+      if (KIND >= 1) {
+        const double bx = tbx[k], bz = tbz[k];
+        double f1[3], f2[3], f3[3], f4[3];
+        if (KIND != 3) gen2(s, bx, bz, g0, c0, hc0, sJ[0], f1);
+        if (KIND == 1) {
+          rotate2(0.5 * f1[0], 0.5 * f1[1], 0.5 * f1[2], P0, P1, P2);
+        } else if (KIND == 2) {
+          gen2(s, bx, bz, gm, cm, hcm, sJ[1], f2);
+          const double cr0 = f1[1] * f2[2] - f1[2] * f2[1];
+          const double cr1 = f1[2] * f2[0] - f1[0] * f2[2];
+          const double cr2 = f1[0] * f2[1] - f1[1] * f2[0];
+          rotate2(0.5 * f2[0] - 0.125 * cr0, 0.5 * f2[1] - 0.125 * cr1, 0.5 * f2[2] - 0.125 * cr2,
+                  P0, P1, P2);
+        } else if (KIND == 3) {
+          gen2(s, bx, bz, gm, cm, hcm, sJ[2], f3);
+          rotate2(f3[0], f3[1], f3[2], P0, P1, P2);
+        } else {
+          gen2(s, bx, bz, gm, cm, hcm, sJ[1], f2);
+          gen2(s, bx, bz, gm, cm, hcm, sJ[2], f3);
+          gen2(s, bx, bz, g1, c1, hc1, sJ[3], f4);
+          const double cr0 = f1[1] * f4[2] - f1[2] * f4[1];
+          const double cr1 = f1[2] * f4[0] - f1[0] * f4[2];
+          const double cr2 = f1[0] * f4[1] - f1[1] * f4[0];
+          const double t0 = (((f1[0] + 2.0 * f2[0]) + 2.0 * f3[0]) + f4[0]) * (1.0 / 6.0) - cr0 * (1.0 / 12.0);
+          const double t1 = (((f1[1] + 2.0 * f2[1]) + 2.0 * f3[1]) + f4[1]) * (1.0 / 6.0) - cr1 * (1.0 / 12.0);
+          const double t2 = (((f1[2] + 2.0 * f2[2]) + 2.0 * f3[2]) + f4[2]) * (1.0 / 6.0) - cr2 * (1.0 / 12.0);
+          rotate2(t0, t1, t2, P0, P1, P2);
+          if (a.renorm) {
+            const double n2 = (P0 * P0 + P1 * P1) + P2 * P2;
+            const double inv = 1.0 / sqrt(n2);
+            P0 = P0 * inv;
+            P1 = P1 * inv;
+            P2 = P2 * inv;
+          }
+          X[b] = P0;
+          X[b + plane] = P1;
+          X[b + 2 * plane] = P2;
+        }
+      }
+      // rho~: rho for neutrinos, -rho^* (Bloch (-x, y, -z)) for antineutrinos
+      const double w = G[k];
+      const double v0 = s ? -P0 : P0, v2 = s ? -P2 : P2;
+      S[0] = i128_add(S[0], i128_from(to_fix(w * v0, a.s1, err)));
+      S[1] = i128_add(S[1], i128_from(to_fix(w * P1, a.s1, err)));
+      S[2] = i128_add(S[2], i128_from(to_fix(w * v2, a.s1, err)));
+    }
+    S[0] = wave_sum(S[0]);
+    S[1] = wave_sum(S[1]);
+    S[2] = wave_sum(S[2]);
+    if (lane < 6) {
+      const I128 sv = select_comp<3>(S, lane % 3);
+      if (lane < 3)
+        T = i128_add(T, i128_from(to_fix(icmom * (i128_to_double(sv) * a.p2e1), a.s0, err)));
+      else
+        T = i128_add(T, sv);
+    }
+  }
+}
+
+// --------------------------------------------------------------- three flavours
+template <typename ST>
+__device__ __forceinline__ Herm3 gen3(int s, const double* tab, int NE, int k, const Radial& g,
+                                      double c, double hc, const double* J) {
+  double nn[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) nn[i] = g.mu * (J[i] - c * J[8 + i]);
+  const double v0 = tab[k], v1 = tab[NE + k], v2 = tab[2 * NE + k];
+  const double v3 = tab[3 * NE + k], v4 = tab[4 * NE + k], v5 = tab[5 * NE + k];
+  Herm3 H;
+  if (s == 0) {
+    H.d0 = (v0 + g.lam) + nn[0];
+    H.d1 = v1 + nn[1];
+    H.d2 = v2;
+    H.o01 = mk(v3 + nn[2], nn[3]);
+    H.o02 = mk(v4 + nn[4], nn[5]);
+    H.o12 = mk(v5 + nn[6], nn[7]);
+  } else {
+    H.d0 = (v0 - g.lam) - nn[0];
+    H.d1 = v1 - nn[1];
+    H.d2 = v2;
+    H.o01 = mk(v3 - nn[2], nn[3]);
+    H.o02 = mk(v4 - nn[4], nn[5]);
+    H.o12 = mk(v5 - nn[6], nn[7]);
+  }
+  return hscale(hc, H);
+}
+
+template <typename ST, int KIND>
+__device__ __forceinline__ void stage3(const StepArgs& a, long long n, const double (*sJ)[16],
+                                       long long gw, long long nw, int lane, I128& T, int& err) {
+  const double r0 = a.rs + (double)n * a.h;
+  const double rm = r0 + 0.5 * a.h;
+  const double r1 = a.rs + (double)(n + 1) * a.h;
+  const Radial g0 = radial_at(a, r0), gm = radial_at(a, rm), g1 = radial_at(a, r1);
+  const long long nrow = 2LL * a.NU, plane = a.plane;
+  ST* X = (ST*)a.X;
+  for (long long row = gw; row < nrow; row += nw) {
+    const int s = (int)(row / a.NU);
+    const int j = (int)(row - (long long)s * a.NU);
+    const double u = ((double)j + 0.5) / (double)a.NU;
+    const double c0 = sqrt(1.0 - u * g0.q2), cm = sqrt(1.0 - u * gm.q2), c1 = sqrt(1.0 - u * g1.q2);
+    const double hc0 = a.h / c0, hcm = a.h / cm, hc1 = a.h / c1;
+    const double cmom = (KIND == 0) ? c0 : ((KIND <= 2) ? cm : c1);
+    const double icmom = 1.0 / cmom;
+    const double* G = a.tab + (size_t)(6 + s) * a.NE;
+    I128 S[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) S[i] = i128_zero();
+    for (int k = lane; k < a.NE; k += 64) {
+      const long long b = row * a.NE + k;
+      cplx ps[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        ps[c] = mk((double)X[b + (2 * c) * plane], (double)X[b + (2 * c + 1) * plane]);
+      if (KIND >= 1) {
+        Herm3 K1;
+        if (KIND != 3) K1 = gen3<ST>(s, a.tab, a.NE, k, g0, c0, hc0, sJ[0]);
+        if (KIND == 1) {
+          exp3_apply(hscale(0.5, K1), ps);
+        } else if (KIND == 2) {
+          const Herm3 K2 = gen3<ST>(s, a.tab, a.NE, k, gm, cm, hcm, sJ[1]);
+          const Herm3 C = icomm(K1, K2);
+          Herm3 O;
+          O.d0 = 0.5 * K2.d0 + 0.125 * C.d0;
+          O.d1 = 0.5 * K2.d1 + 0.125 * C.d1;
+          O.d2 = 0.5 * K2.d2 + 0.125 * C.d2;
+          O.o01 = mk(0.5 * K2.o01.re + 0.125 * C.o01.re, 0.5 * K2.o01.im + 0.125 * C.o01.im);
+          O.o02 = mk(0.5 * K2.o02.re + 0.125 * C.o02.re, 0.5 * K2.o02.im + 0.125 * C.o02.im);
+          O.o12 = mk(0.5 * K2.o12.re + 0.125 * C.o12.re, 0.5 * K2.o12.im + 0.125 * C.o12.im);
+          exp3_apply(O, ps);
+        } else if (KIND == 3) {
+          exp3_apply(gen3<ST>(s, a.tab, a.NE, k, gm, cm, hcm, sJ[2]), ps);
+        } else {
+          const Herm3 K2 = gen3<ST>(s, a.tab, a.NE, k, gm, cm, hcm, sJ[1]);
+          const Herm3 K3 = gen3<ST>(s, a.tab, a.NE, k, gm, cm, hcm, sJ[2]);
+          const Herm3 K4 = gen3<ST>(s, a.tab, a.NE, k, g1, c1, hc1, sJ[3]);
+          const Herm3 C = icomm(K1, K4);
+          Herm3 Th;
+#define NB_THETA(f) ((((K1.f + 2.0 * K2.f) + 2.0 * K3.f) + K4.f) * (1.0 / 6.0) + C.f * (1.0 / 12.0))
+          Th.d0 = NB_THETA(d0);
+          Th.d1 = NB_THETA(d1);
+          Th.d2 = NB_THETA(d2);
+          Th.o01 = mk(NB_THETA(o01.re), NB_THETA(o01.im));
+          Th.o02 = mk(NB_THETA(o02.re), NB_THETA(o02.im));
+          Th.o12 = mk(NB_THETA(o12.re), NB_THETA(o12.im));
+#undef NB_THETA
+          exp3_apply(Th, ps);
+          if (a.renorm) {
+            const double n2 = (norm2(ps[0]) + norm2(ps[1])) + norm2(ps[2]);
+            const double inv = 1.0 / sqrt(n2);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ps[c] = mk(ps[c].re * inv, ps[c].im * inv);
+          }
+          // store, and take the next step's moments from exactly what was stored
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const ST re = (ST)ps[c].re, im = (ST)ps[c].im;
+            X[b + (2 * c) * plane] = re;
+            X[b + (2 * c + 1) * plane] = im;
+            ps[c] = mk((double)re, (double)im);
+          }
+        }
+      }
+      // rho~ components: rho_ee-rho_tt, rho_mm-rho_tt, Re/Im rho_em, rho_et, rho_mt;
+      // antineutrinos: -rho^* (real parts and diagonal negated)
+      const double n0 = norm2(ps[0]), n1 = norm2(ps[1]), n2 = norm2(ps[2]);
+      const cplx em = cmul_conjb(ps[0], ps[1]), et = cmul_conjb(ps[0], ps[2]), mt = cmul_conjb(ps[1], ps[2]);
+      double v[8] = {n0 - n2, n1 - n2, em.re, em.im, et.re, et.im, mt.re, mt.im};
+      if (s) {
+        v[0] = -v[0]; v[1] = -v[1]; v[2] = -v[2]; v[4] = -v[4]; v[6] = -v[6];
+      }
+      const double w = G[k];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) S[i] = i128_add(S[i], i128_from(to_fix(w * v[i], a.s1, err)));
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) S[i] = wave_sum(S[i]);
+    if (lane < 16) {
+      const I128 sv = select_comp<8>(S, lane & 7);
+      if (lane < 8)
+        T = i128_add(T, i128_from(to_fix(icmom * (i128_to_double(sv) * a.p2e1), a.s0, err)));
+      else
+        T = i128_add(T, sv);
+    }
+  }
+}
+
+// --------------------------------------------------------------- the stepper
+template <int NF, typename ST>
+__global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
+  constexpr int NC = (NF == 2) ? 3 : 8;
+  constexpr int NV = 2 * NC;
+  __shared__ double sJ[4][NV];
+  __shared__ I128 sw[kBlock / 64][NV];
+  __shared__ I128 sred[kBlock];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const long long gw = (long long)blockIdx.x * (kBlock / 64) + wid;
+  const long long nw = (long long)gridDim.x * (kBlock / 64);
+  unsigned epoch = 0;
+  int err = 0;
+  bool ok = true;
+  I128 T = i128_zero();
+  if constexpr (NF == 2) stage2<0>(a, a.step0, sJ, gw, nw, lane, T, err);
+  else stage3<ST, 0>(a, a.step0, sJ, gw, nw, lane, T, err);
+  ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[0], a.J);
+  for (long long n = a.step0; ok && n < a.step0 + a.nsteps; ++n) {
+    T = i128_zero();
+    if constexpr (NF == 2) stage2<1>(a, n, sJ, gw, nw, lane, T, err);
+    else stage3<ST, 1>(a, n, sJ, gw, nw, lane, T, err);
+    if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[1], a.J + NV))) break;
+    T = i128_zero();
+    if constexpr (NF == 2) stage2<2>(a, n, sJ, gw, nw, lane, T, err);
+    else stage3<ST, 2>(a, n, sJ, gw, nw, lane, T, err);
+    if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[2], a.J + 2 * NV))) break;
+    T = i128_zero();
+    if constexpr (NF == 2) stage2<3>(a, n, sJ, gw, nw, lane, T, err);
+    else stage3<ST, 3>(a, n, sJ, gw, nw, lane, T, err);
+    if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[3], a.J + 3 * NV))) break;
+    T = i128_zero();
+    if constexpr (NF == 2) stage2<4>(a, n, sJ, gw, nw, lane, T, err);
+    else stage3<ST, 4>(a, n, sJ, gw, nw, lane, T, err);
+    ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[0], a.J);
+  }
+  if (err) __hip_atomic_fetch_or(a.sync + kSyncStatus, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template __global__ void k_advance<2, double>(StepArgs);
+template __global__ void k_advance<3, double>(StepArgs);
+template __global__ void k_advance<3, float>(StepArgs);
+
+// ----------------------------------------------------------------- small kernels
+__global__ void k_zero_sync(unsigned int* sync, int keep_status) {
+  const int i = threadIdx.x;
+  if (i < kSyncWords && !(keep_status && i == kSyncStatus)) sync[i] = 0u;
+}
+
+// Initial flavour eigenstates (Sec. 3.4): 2f P = (0,0,1); 3f psi = (1,0,0).
+template <typename ST>
+__global__ void k_init(ST* X, long long nb, long long plane, int nsc) {
+  const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  for (int c = 0; c < nsc; ++c) {
+    const bool one = (nsc == 3) ? (c == 2) : (c == 0);
+    X[b + c * plane] = one ? (ST)1 : (ST)0;
+  }
+}
+template __global__ void k_init<double>(double*, long long, long long, int);
+template __global__ void k_init<float>(float*, long long, long long, int);
+
+template <typename ST>
+__global__ void k_read_pee(const ST* X, long long nb, long long plane, int nsc, double* out) {
+  const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  if (nsc == 3) {
+    out[b] = 0.5 * (1.0 + (double)X[b + 2 * plane]);
+  } else {
+    const double re = (double)X[b], im = (double)X[b + plane];
+    out[b] = fma(re, re, im * im);
+  }
+}
+template __global__ void k_read_pee<double>(const double*, long long, long long, int, double*);
+template __global__ void k_read_pee<float>(const float*, long long, long long, int, double*);
+
+// State exchange with FP64 [comp][beam] planes (dir 0: state -> out, 1: in -> state).
+template <typename ST>
+__global__ void k_state_xfer(ST* X, long long nb, long long plane, int nsc, double* buf, int dir) {
+  const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  for (int c = 0; c < nsc; ++c) {
+    if (dir == 0) buf[c * nb + b] = (double)X[b + c * plane];
+    else X[b + c * plane] = (ST)buf[c * nb + b];
+  }
+}
+template __global__ void k_state_xfer<double>(double*, long long, long long, int, double*, int);
+template __global__ void k_state_xfer<float>(float*, long long, long long, int, double*, int);
+
+// ------------------------------------------------------------------- test hooks
+__global__ void k_test_sincos(const double* x, long long n, double* s, double* c) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a, b;
+  sincos_nb(x[i], a, b);
+  s[i] = a;
+  c[i] = b;
+}
+__global__ void k_test_sqrt_div(const double* a, const double* b, long long n, double* sq, double* dv) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  sq[i] = sqrt(a[i]);
+  dv[i] = a[i] / b[i];
+}
+__global__ void k_test_exp3(const double* k9, const double* psi6, long long n, double* out6) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* k = k9 + 9 * i;
+  const Herm3 K{k[0], k[1], k[2], mk(k[3], k[4]), mk(k[5], k[6]), mk(k[7], k[8])};
+  const double* p = psi6 + 6 * i;
+  cplx ps[3] = {mk(p[0], p[1]), mk(p[2], p[3]), mk(p[4], p[5])};
+  exp3_apply(K, ps);
+  double* o = out6 + 6 * i;
+  for (int c = 0; c < 3; ++c) {
+    o[2 * c] = ps[c].re;
+    o[2 * c + 1] = ps[c].im;
+  }
+}
+__global__ void k_test_rotate(const double* x3, const double* p3, long long n, double* out3) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double P0 = p3[3 * i], P1 = p3[3 * i + 1], P2 = p3[3 * i + 2];
+  rotate2(x3[3 * i], x3[3 * i + 1], x3[3 * i + 2], P0, P1, P2);
+  out3[3 * i] = P0;
+  out3[3 * i + 1] = P1;
+  out3[3 * i + 2] = P2;
+}
+
+}  // namespace nb

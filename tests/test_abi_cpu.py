@@ -1,0 +1,84 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared symbol,
+validates parameters, and its host tables equal the oracle's bit for bit."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def nb():
+    import paper_1912_10596_amd as nb
+    if not os.path.exists(nb.LIB_PATH):
+        pytest.fail("libnubulb.so not built (run __graft_entry__.build())")
+    return nb
+
+
+def test_every_declared_symbol_is_exported(nb):
+    hdr = open(os.path.join(ROOT, "include", "nubulb.h")).read()
+    declared = set(re.findall(r"\b(nb_[a-z0-9_]+)\s*\(", hdr))
+    assert declared, "no declarations found"
+    L = nb.lib()
+    for name in sorted(declared):
+        assert hasattr(L, name), f"{name} not exported"
+    assert declared == set(nb.EXPORTS)
+
+
+@pytest.mark.parametrize("case", ["2f_small", "3f_small", "2f_batchlike", "3f_800k_shape"])
+def test_host_tables_equal_oracle(nb, oracle, case):
+    if case == "2f_small":
+        d = workloads.two_flavor_small()
+    elif case == "3f_small":
+        d = workloads.small_params(n_flavor=3, n_energy=37, n_u=5)
+    elif case == "2f_batchlike":
+        d = workloads.batch_256(3)[2]
+    else:
+        d = workloads.three_flavor_800k()
+        d["n_u"] = 7
+    g = nb.HostModel(d).tables()
+    o = oracle.Model(d).tables()
+    for k in ("E", "w", "bv"):
+        np.testing.assert_array_equal(g[k], o[k], err_msg=k)
+    for k in ("lam0", "kappa0", "h", "p2e1", "p2e0", "e1", "e0"):
+        assert g[k] == o[k], k
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n_flavor=4), dict(n_energy=0), dict(n_u=0), dict(n_steps=0), dict(r_start_km=5.0),
+    dict(r_end_km=10.0), dict(delta_cp=0.1), dict(ne_power=9), dict(e_min_mev=0.0),
+    dict(precision=1), dict(temp_mev=[0.0, 1.0, 1.0]), dict(lum_erg_s=[-1.0, 1.0, 1.0]),
+])
+def test_invalid_parameters_rejected(nb, bad):
+    d = workloads.two_flavor_small()
+    d.update(bad)
+    with pytest.raises(nb.NubulbError) as e:
+        nb.HostModel(d)
+    assert e.value.code == nb.NB_EINVAL
+
+
+def test_unbound_calls_fail_cleanly(nb):
+    m = nb.HostModel(workloads.two_flavor_small())
+    L = nb.lib()
+    assert L.nb_step(m.h, 1) == nb.NB_EUNBOUND
+    assert L.nb_run(m.h) == nb.NB_EUNBOUND
+    assert L.nb_reset(m.h) == nb.NB_EUNBOUND
+    assert L.nb_read_pee(m.h, C.c_void_p(16)) == nb.NB_EUNBOUND
+    assert L.nb_step(None, 1) == nb.NB_EINVAL
+    assert m.workspace_bytes() > 3 * 8 * m.nb
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The product package never imports, loads or links the oracle."""
+    pkg = os.path.join(ROOT, "paper_1912_10596_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "libnbo" not in txt and "nbo.h" not in txt, f
