@@ -1,0 +1,192 @@
+#!/usr/bin/env python
+"""Benchmark of the MI355X bulb-model radial stepper.
+
+One "step" is one radial RKMK4 step of the whole hot path over every beam of the
+three-flavour 800k-beam model (400 E x 1000 u x 2 species, 10 -> 1000 km in 20000 steps):
+four stage moment reductions (J0, J1), the Hamiltonian assembly, the exact exponentials
+and the renormalised state update.  Inputs are synthetic (seeded parameters); the state
+is resident in HBM before timing starts.  Prints ONE JSON line on stdout.
+
+Algorithmic cost per beam-step (counted from the kernel's arithmetic, fma = 2 flops,
+div/sqrt = 1):
+  3 flavours: 4 exponentials exp(-iK) psi (~805 flops each: Newton cubic, eigenvector by
+  cross products, 2x2 block of Eq. U, two sin/cos), 8 Hamiltonian builds (39), two
+  commutators i[A,B] (207), Lie combinations (108), renormalisation (19), 4 moment
+  contributions (45)  ->  4253 flops.
+  2 flavours: 4 quaternion rotations (88), 8 B-vector builds (15), 2 cross products,
+  combinations, renormalisation, 4 moment contributions  ->  560 flops.
+Algorithmic HBM bytes per beam-step: the state is read at stages 2, 3, 4 and the final
+pass and written once: 5 x (state reals) x (bytes per real): 3f FP64 psi 240 B, 3f FP32
+psi 120 B, 2f Bloch vector 120 B.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOPS_PER_BEAM_STEP = {2: 560.0, 3: 4253.0}
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
+PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X FP64 vector, published (256 CU x 2.4 GHz x 128)
+METRIC = "beam-steps/sec + HBM GB/s (3-flavor 800k beams); adjoint/forward time ratio"
+KERNEL_SOURCES = ["paper_1912_10596_amd/csrc/nb_kernels.hip",
+                  "paper_1912_10596_amd/csrc/nb_device.h",
+                  "paper_1912_10596_amd/csrc/nb_internal.h"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bytes_per_beam_step(nf: int, fp32: bool) -> float:
+    nsc = 3 if nf == 2 else 6
+    return 5.0 * nsc * (4.0 if fp32 else 8.0)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def timed_steps(m, K: int, W: int):
+    """W untimed steps, then exactly K steps between synchronisations; HIP events on
+    the stream the kernels are launched on (torch's current stream, bound at nb_bind)."""
+    import torch
+    if W:
+        m.step(W)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    m.step(K)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, e0.elapsed_time(e1) / 1e3
+
+
+def traffic_from_profile(name: str, launch_steps: int, nb: int):
+    """HBM bytes per launch from committed counter runs, scaled by the copy-kernel
+    calibration, or None if missing or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    per_beam_step = t["hbm_bytes_per_beam_step"]
+    return per_beam_step * launch_steps * nb
+
+
+def cpu_baseline(d: dict, seconds: float):
+    """The oracle as it stands, on this host's cores, over a bounded prefix of the same
+    workload (whole steps of every beam until `seconds` of CPU time have passed)."""
+    import oracle
+    m = oracle.Model(d)
+    nb = m.nb
+    m.step(1)                          # first touch of the state arrays
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        m.step(1)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or n >= 200:
+            break
+    return dict(value=n * nb / el, unit="beam-steps/s", cores=oracle.get_threads(),
+                kind="oracle", sample=f"{n} radial steps of all {nb} beams (steps 2..{n + 1}) "
+                f"of the same workload, {el:.1f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this stepper runs on one GPU only (no multi-GPU path is built); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1912_10596_amd as nb
+    import workloads
+
+    assert torch.cuda.is_available(), "no HIP device"
+    torch.cuda.set_device(0)
+    d = workloads.three_flavor_800k()
+    K, W = args.steps, args.warmup
+    if K + W > d["n_steps"]:
+        raise SystemExit(f"steps + warmup must be <= {d['n_steps']}")
+    m = nb.Model(d)
+    log(f"3-flavour model: {m.nb} beams, warmup {W}, timed {K} steps")
+    wall, ev = timed_steps(m, K, W)
+    beam_steps = float(m.nb) * K
+    value = beam_steps / wall
+    ms_per_step = wall * 1e3 / K
+    # roofline of the dominant kernel (one cooperative launch for the K steps)
+    flops = FLOPS_PER_BEAM_STEP[3] * beam_steps
+    alg_bytes = bytes_per_beam_step(3, False) * beam_steps
+    tflops = flops / ev / 1e12
+    gbs = alg_bytes / ev / 1e9
+    f_alu, f_hbm = tflops / PEAK_FP64_VALU_TFLOPS, gbs / PEAK_HBM_GBS
+    traffic = traffic_from_profile("k_advance_3f_fp64_800k", K, m.nb)
+    if f_alu >= f_hbm:
+        roof = dict(bound="alu", achieved=round(tflops, 3), peak=PEAK_FP64_VALU_TFLOPS,
+                    unit="TFLOP/s", frac=round(f_alu, 4), traffic=traffic,
+                    other=dict(bound="hbm", achieved=round(gbs, 1), peak=PEAK_HBM_GBS,
+                               unit="GB/s", frac=round(f_hbm, 4)))
+    else:
+        roof = dict(bound="hbm", achieved=round(gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                    frac=round(f_hbm, 4), traffic=traffic,
+                    other=dict(bound="alu", achieved=round(tflops, 3),
+                               peak=PEAK_FP64_VALU_TFLOPS, unit="TFLOP/s", frac=round(f_alu, 4)))
+    roof["kernel"] = "nb::k_advance<3, double>"
+    roof["launch_ms"] = round(ev * 1e3, 3)
+    out = {
+        "metric": METRIC, "value": value, "unit": "beam-steps/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "3-flavour bulb model, 400 E x 1000 u x 2 species = 800000 "
+                               "beams, 10 -> 1000 km, 20000 RKMK4 steps (timed: a prefix)",
+                   "n_flavor": 3, "n_energy": 400, "n_u": 1000, "beams": m.nb,
+                   "n0_cm3": d["n0_cm3"], "state": "psi, FP64"},
+        "hbm_gbs_algorithmic": round(gbs, 1),
+        "adjoint_forward_ratio": None,
+        "roofline": roof,
+    }
+    del m
+    torch.cuda.empty_cache()
+    if args.copy_probe:
+        n = 1 << 27                      # 2^27 doubles = 1 GiB each way
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 1 GiB read + 1 GiB written")
+        del src, dst
+        torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -40,6 +40,7 @@ def lib():
         L.nbo_destroy.argtypes = [vp]
         L.nbo_destroy.restype = None
         L.nbo_set_threads.argtypes = [C.c_int]
+        L.nbo_get_threads.argtypes = []
         L.nbo_n_beams.argtypes = [vp]
         L.nbo_n_beams.restype = C.c_int64
         L.nbo_n_species.argtypes = [vp]
@@ -188,6 +189,10 @@ class Model:
 
 def set_threads(n: int):
     lib().nbo_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().nbo_get_threads())
 
 
 def sincos(x: np.ndarray):

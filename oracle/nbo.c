@@ -342,6 +342,14 @@ int nbo_set_threads(int n) {
   return n;
 }
 
+int nbo_get_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 int nbo_create(const nbo_params *p, nbo_model **out) {
   *out = NULL;
   if (!p || (p->n_flavor != 2 && p->n_flavor != 3) || p->n_energy < 1 || p->n_u < 1 ||

@@ -50,6 +50,7 @@ typedef struct nbo_model nbo_model;
 int  nbo_create(const nbo_params *p, nbo_model **out);
 void nbo_destroy(nbo_model *m);
 int  nbo_set_threads(int n);                     /* OpenMP threads (0 = default) */
+int  nbo_get_threads(void);                      /* threads a parallel region will use */
 int64_t nbo_n_beams(const nbo_model *m);
 int  nbo_n_species(const nbo_model *m);
 int  nbo_state_comps(const nbo_model *m);         /* 3 (2f Bloch vector) or 6 (3f psi) */
