@@ -23,7 +23,8 @@
  *     Two flavours: rho = (1 + P.sigma)/2 and e^{F} rotates P about (h/c)B by |(h/c)B|,
  *     with H = B.sigma/2 + trace (so [X,Y] maps to the cross product).
  *     Three flavours: the state is the wavefunction psi of Eq. psi (rho = psi psi^+);
- *     e^{-iK} psi is evaluated exactly (isolated eigenvector + a 2x2 block by Eq. U).
+ *     e^{-iK} psi is evaluated exactly (isolated eigenvector + the 2x2 propagator of
+ *     Eq. U on the orthogonal plane).
  *
  * Pins (tests/test_oracle_pins.py): units against hand values, spectra against
  * quadrature, sin/cos against libm, rotations and exp(-iK) against SciPy, the fixed-point
@@ -64,6 +65,7 @@ static double sqrt2gf_km_cm3(void) {
 #define PI_D 3.141592653589793
 #define F2_0 1.8030853547393914  /* int x^2/(e^x+1) = 3 zeta(3)/2 */
 #define F3_0 5.682196976983475   /* int x^3/(e^x+1) = 7 pi^4/120 */
+#define TWO58 288230376151711744.0
 #define TWO62 4611686018427387904.0
 #define TWO64 18446744073709551616.0
 
@@ -109,10 +111,11 @@ static void sincos_spec(double x, double *sn, double *cs) {
 }
 
 /* ------------------------------------------------------------- fixed point */
-/* One contribution v becomes the integer trunc(v 2^e); |v 2^e| < 2^62 is required. */
-static inline int64_t to_fix(double v, double scale, int *err) {
+/* One contribution v becomes the integer trunc(v 2^e); |v 2^e| < limit is required
+ * (2^58 for beam contributions, 2^62 for the per-angle terms of J0). */
+static inline int64_t to_fix(double v, double scale, double limit, int *err) {
   const double x = v * scale;
-  if (!(fabs(x) < TWO62)) { *err = 1; return 0; }
+  if (!(fabs(x) < limit)) { *err = 1; return 0; }
   return (int64_t)x;
 }
 /* Integer -> double in sign-magnitude form: |x| = hi 2^64 + lo, each half converted
@@ -179,10 +182,14 @@ static inline cx inner3(const cx u[3], const cx v[3]) { /* u^+ v */
 }
 
 /* psi' = exp(-i K) psi up to a global phase, for Hermitian K.
- * exp(-iK) = e^{-i l1} v1 v1^+ + W exp(-i K') W^+ with l1 the eigenvalue of largest
- * magnitude of the traceless part (simple and well separated), v1 its eigenvector,
- * W an orthonormal basis of the complement and K' = W^+ K W; exp(-iK') is the 2x2
- * propagator of Eq. U.  The traces of K and K' only contribute global phases. */
+ * With K0 the traceless part, l1 its eigenvalue of largest magnitude (simple and well
+ * separated from the other two), v1 its eigenvector and P the projector on the plane
+ * orthogonal to v1: on that plane K0 - hm (hm = -l1/2, the mean of the other two
+ * eigenvalues) squares to th^2 times the identity, so
+ *   exp(-i K0) psi = e^{-i l1} (v1^+ psi) v1
+ *                  + e^{-i hm} [cos(th) P psi - i sin(th)/th (K0 - hm) P psi],
+ * the 2x2 propagator of Eq. U on the plane.  th = |(K0 - hm) u| for a unit u in the
+ * plane.  The traces (of K, and e^{-i hm}) only contribute global phases. */
 static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
   const double tr = ((K->d[0] + K->d[1]) + K->d[2]) * (1.0 / 3.0);
   const double a0 = K->d[0] - tr, a1 = K->d[1] - tr, a2 = K->d[2] - tr;
@@ -205,7 +212,7 @@ static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
     lam = lam - fv / dv;
   }
   const double l1 = sg * lam;
-  /* eigenvector: largest cross product of two rows of K0 - l1 I */
+  /* eigenvector: largest cross product of two rows of K0 - l1 I (first wins ties) */
   const cx r0[3] = {cx_make(a0 - l1, 0.0), x, y};
   const cx r1[3] = {cx_conj(x), cx_make(a1 - l1, 0.0), z};
   const cx r2[3] = {cx_conj(y), cx_conj(z), cx_make(a2 - l1, 0.0)};
@@ -226,7 +233,7 @@ static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
   const double inb = 1.0 / sqrt(nb);
   cx v1[3];
   for (int c = 0; c < 3; ++c) v1[c] = cx_rmul(inb, best[c]);
-  /* complement: Gram-Schmidt of the axis where v1 is smallest, then conj(v1 x w2) */
+  /* unit vector of the plane: Gram-Schmidt of the axis where v1 is smallest */
   double nc[3];
   for (int c = 0; c < 3; ++c) nc[c] = cx_norm2(v1[c]);
   int m = 0;
@@ -242,38 +249,34 @@ static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
   }
   const double nw = (cx_norm2(w[0]) + cx_norm2(w[1])) + cx_norm2(w[2]);
   const double inw = 1.0 / sqrt(nw);
-  cx w2[3], w3[3];
-  for (int c = 0; c < 3; ++c) w2[c] = cx_rmul(inw, w[c]);
-  for (int c = 0; c < 3; ++c) w3[c] = cx_conj(cross_c(v1, w2, c));
-  /* K' = W^+ K0 W */
-  cx kw2[3], kw3[3];
-  const cx *vv[2] = {w2, w3};
-  cx *kv[2] = {kw2, kw3};
-  for (int i = 0; i < 2; ++i) {
-    const cx *v = vv[i];
-    kv[i][0] = cx_add(cx_add(cx_rmul(a0, v[0]), cx_mul(x, v[1])), cx_mul(y, v[2]));
-    kv[i][1] = cx_add(cx_add(cx_cjmul(x, v[0]), cx_rmul(a1, v[1])), cx_mul(z, v[2]));
-    kv[i][2] = cx_add(cx_add(cx_cjmul(y, v[0]), cx_cjmul(z, v[1])), cx_rmul(a2, v[2]));
-  }
-  const double k22 = inner3(w2, kw2).re, k33 = inner3(w3, kw3).re;
-  const cx k23 = inner3(w2, kw3);
-  const double hm = 0.5 * (k22 + k33), h11 = 0.5 * (k22 - k33);
+  cx u[3];
+  for (int c = 0; c < 3; ++c) u[c] = cx_rmul(inw, w[c]);
+  const double hm = -0.5 * l1;
+  const double d0 = a0 - hm, d1 = a1 - hm, d2 = a2 - hm;
+  /* (K0 - hm) v for a vector v */
+#define NB_KMV(v, o)                                                                    \
+  do {                                                                                \
+    (o)[0] = cx_add(cx_add(cx_rmul(d0, (v)[0]), cx_mul(x, (v)[1])), cx_mul(y, (v)[2])); \
+    (o)[1] = cx_add(cx_add(cx_cjmul(x, (v)[0]), cx_rmul(d1, (v)[1])), cx_mul(z, (v)[2])); \
+    (o)[2] = cx_add(cx_add(cx_cjmul(y, (v)[0]), cx_cjmul(z, (v)[1])), cx_rmul(d2, (v)[2])); \
+  } while (0)
+  cx ku[3];
+  NB_KMV(u, ku);
+  const double th = sqrt((cx_norm2(ku[0]) + cx_norm2(ku[1])) + cx_norm2(ku[2]));
+  const cx al = inner3(v1, psi);
+  cx pp[3], kp[3];
+  for (int c = 0; c < 3; ++c) pp[c] = cx_sub(psi[c], cx_mul(al, v1[c]));
+  NB_KMV(pp, kp);
+#undef NB_KMV
   const double phi = l1 - hm;
-  const double th = sqrt(fma(h11, h11, cx_norm2(k23)));
   double sp, cp, st, ct;
   sincos_spec(phi, &sp, &cp);
   sincos_spec(th, &st, &ct);
-  const double sc = (th > 0.0) ? st / th : 0.0;
-  const cx al = cx_mul(inner3(v1, psi), cx_make(cp, -sp));
-  const cx b2 = inner3(w2, psi), b3 = inner3(w3, psi);
-  const double hs = h11 * sc;
-  const cx g = cx_make(k23.re * sc, k23.im * sc);
-  const cx t2 = cx_add(cx_rmul(hs, b2), cx_mul(g, b3));
-  const cx t3 = cx_sub(cx_cjmul(g, b2), cx_rmul(hs, b3));
-  const cx b2n = cx_make(ct * b2.re + t2.im, ct * b2.im - t2.re);
-  const cx b3n = cx_make(ct * b3.re + t3.im, ct * b3.im - t3.re);
+  const double sc = (th > 0.0) ? st / th : 1.0;
+  const cx ap = cx_mul(al, cx_make(cp, -sp));
   for (int c = 0; c < 3; ++c)
-    out[c] = cx_add(cx_add(cx_mul(al, v1[c]), cx_mul(b2n, w2[c])), cx_mul(b3n, w3[c]));
+    out[c] = cx_add(cx_mul(ap, v1[c]),
+                    cx_make(ct * pp[c].re + sc * kp[c].im, ct * pp[c].im - sc * kp[c].re));
 }
 
 /* Rotation of the Bloch vector P about x by the angle |x| (2x2 form of Eq. U as a
@@ -432,14 +435,15 @@ int nbo_create(const nbo_params *p, nbo_model **out) {
         m->bv[6 * k + e] = (U[ia[e]][1] * U[ib[e]][1]) * w2 + (U[ia[e]][2] * U[ib[e]][2]) * w3;
     }
   }
-  /* fixed-point scales: every contribution |w rho~| < 2^e1 ... < 2^61 */
+  /* fixed-point scales: every beam contribution |w rho~| 2^e1 < 2^58 (so that 32 of them
+   * add up inside a signed 64-bit integer) and every angle term of J0 times 2^e0 < 2^62 */
   double wmax = 0.0;
   for (int64_t i = 0; i < m->NE * m->ns; ++i)
     if (fabs(m->w[i]) > wmax) wmax = fabs(m->w[i]);
   if (!(wmax > 0.0)) wmax = 1.0;
   int ex;
   frexp(wmax, &ex);
-  m->e1 = 61 - ex;
+  m->e1 = 57 - ex;
   const double qs = m->R / p->r_start_km;
   const double cmin = sqrt(1.0 - u_of(m, m->NU - 1) * (qs * qs));
   const double b0 = (wmax * (double)m->NE) * (1.0 / cmin);
@@ -515,11 +519,11 @@ static int moments(const nbo_model *m, const double *X, double r, double *J0, do
       const int64_t b = row * m->NE + k;
       double v[8];
       rho_tilde(m, s, X + b * m->nsc, v);
-      for (int c = 0; c < nc; ++c) S[c] += to_fix(m->w[s * m->NE + k] * v[c], m->s1, &err);
+      for (int c = 0; c < nc; ++c) S[c] += to_fix(m->w[s * m->NE + k] * v[c], m->s1, TWO58, &err);
     }
     for (int c = 0; c < nc; ++c) {
       T1[row * nc + c] = S[c];
-      T0[row * nc + c] = to_fix(ic * (i128_to_double(S[c]) * m->p2e1), m->s0, &err);
+      T0[row * nc + c] = to_fix(ic * (i128_to_double(S[c]) * m->p2e1), m->s0, TWO62, &err);
     }
   }
   for (int c = 0; c < nc; ++c) {
@@ -867,7 +871,7 @@ double nbo_fixed_sum(const double *v, int64_t n, int e) {
   i128 a = 0;
   int err = 0;
   const double sc = ldexp(1.0, e);
-  for (int64_t i = 0; i < n; ++i) a += to_fix(v[i], sc, &err);
+  for (int64_t i = 0; i < n; ++i) a += to_fix(v[i], sc, TWO62, &err);
   if (err) return NAN;
   return i128_to_double(a) * ldexp(1.0, -e);
 }
@@ -904,7 +908,7 @@ int nbo_single_angle_run(const nbo_params *pin, double *pee_out) {
         const int s = (int)(i / NE);
         const double *x = src + 3 * i;
         const double v[3] = {s ? -x[0] : x[0], x[1], s ? -x[2] : x[2]};
-        for (int c = 0; c < 3; ++c) S[c] += to_fix(m->w[i] * v[c], m->s1, &err);
+        for (int c = 0; c < 3; ++c) S[c] += to_fix(m->w[i] * v[c], m->s1, TWO58, &err);
       }
       for (int c = 0; c < 3; ++c) Jn[st_i][c] = i128_to_double(S[c]) * m->p2e1;
       const radial g = radial_at(m, rr[st_i]);

@@ -15,7 +15,7 @@
 #include "nb_internal.h"
 
 namespace nb {
-template <int NF, typename ST>
+template <int NF, typename ST, bool TLDS>
 __global__ void k_advance(StepArgs a);
 __global__ void k_zero_sync(unsigned int* sync, int keep_status);
 template <typename ST>
@@ -168,14 +168,15 @@ static void build_tables(nb_model* m) {
         m->tab[(size_t)q * NE + k] = (U[ia[q]][1] * U[ib[q]][1]) * w2 + (U[ia[q]][2] * U[ib[q]][2]) * w3;
     }
   }
-  // fixed point: every contribution |g rho~| * 2^e1 < 2^61; every angle term of J0
-  // (energy sum / cos) * 2^e0 < 2^61 (cos is smallest at r_start, u_max)
+  // fixed point: every beam contribution |g rho~| 2^e1 < 2^58, so a lane can add 32 of
+  // them in a signed 64-bit integer; every angle term of J0, (energy sum / cos) 2^e0,
+  // stays below 2^62 (cos is smallest at r_start, u_max)
   double wmax = 0.0;
   for (long long k = 0; k < NE; ++k) wmax = std::max(wmax, std::max(std::fabs(G0[k]), std::fabs(G1[k])));
   if (!(wmax > 0.0)) wmax = 1.0;
   int ex = 0;
   std::frexp(wmax, &ex);
-  m->e1 = 61 - ex;
+  m->e1 = 57 - ex;
   const double qs = p.r_nu_km / p.r_start_km;
   const double ulast = ((double)(m->NU - 1) + 0.5) / (double)m->NU;
   const double cmin = std::sqrt(1.0 - ulast * (qs * qs));
@@ -239,8 +240,6 @@ static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 struct Layout {
   size_t X, tab, J, part, sync, need;
 };
-// Partial buffer bound: blocks that can be resident on the largest device of this family.
-static constexpr int kMaxBlocksBound = 256 * 32;
 
 static Layout layout_of(const nb_model* m) {
   const size_t es = state_fp32(m) ? sizeof(float) : sizeof(double);
@@ -253,7 +252,7 @@ static Layout layout_of(const nb_model* m) {
   L.J = o;
   o = align256(o + sizeof(double) * 4 * 2 * m->nc);
   L.part = o;
-  o = align256(o + 16 * (size_t)kMaxBlocksBound * 2 * m->nc);
+  o = align256(o + 16 * (size_t)kMaxBlocks * 2 * m->nc);
   L.sync = o;
   o = align256(o + sizeof(unsigned int) * kSyncWords);
   L.need = o;
@@ -262,10 +261,18 @@ static Layout layout_of(const nb_model* m) {
 
 extern "C" size_t nb_workspace_bytes(const nb_model* m) { return m ? layout_of(m).need : 0; }
 
+// Energy tables are staged in LDS when they fit in this many bytes per block.
+static constexpr size_t kTabLdsMax = 64 * 1024;
+
+static size_t tab_bytes(const nb_model* m) { return sizeof(double) * m->tab.size(); }
+static bool tab_in_lds(const nb_model* m) { return tab_bytes(m) <= kTabLdsMax; }
+static size_t advance_dyn_lds(const nb_model* m) { return tab_in_lds(m) ? tab_bytes(m) : 0; }
+
 static const void* advance_kernel(const nb_model* m) {
-  if (m->nf == 2) return (const void*)&k_advance<2, double>;
-  if (state_fp32(m)) return (const void*)&k_advance<3, float>;
-  return (const void*)&k_advance<3, double>;
+  const bool l = tab_in_lds(m);
+  if (m->nf == 2) return l ? (const void*)&k_advance<2, double, true> : (const void*)&k_advance<2, double, false>;
+  if (state_fp32(m)) return l ? (const void*)&k_advance<3, float, true> : (const void*)&k_advance<3, float, false>;
+  return l ? (const void*)&k_advance<3, double, true> : (const void*)&k_advance<3, double, false>;
 }
 
 static int launch_1d(const void* fn, long long n, void** args, hipStream_t s) {
@@ -298,9 +305,10 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
   int cus = 0, khz = 0, nbpm = 0;
   NB_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   NB_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
-  NB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nbpm, advance_kernel(m), kBlock, 0));
+  NB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nbpm, advance_kernel(m), kBlock,
+                                                       advance_dyn_lds(m)));
   if (nbpm < 1) return fail(NB_EHIP, "stepping kernel cannot be resident");
-  int max_blocks = std::min(cus * nbpm, kMaxBlocksBound);
+  int max_blocks = std::min(cus * nbpm, kMaxBlocks);
   if (m->p.max_blocks > 0) max_blocks = std::min(max_blocks, (int)m->p.max_blocks);
   const Layout L = layout_of(m);
   if (bytes < L.need)
@@ -324,7 +332,7 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
   unsigned int* sync = (unsigned int*)(m->ws + m->off_sync);
   int keep = 0;
   void* zargs[] = {&sync, &keep};
-  NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(1), dim3(kSyncWords), zargs, 0, m->stream));
+  NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(8), dim3(256), zargs, 0, m->stream));
   return nb_reset(m);
 }
 
@@ -345,7 +353,7 @@ static int check_status(nb_model* m) {
   if (st) {
     int keep = 0;
     void* zargs[] = {&sync, &keep};
-    NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(1), dim3(kSyncWords), zargs, 0, m->stream));
+    NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(8), dim3(256), zargs, 0, m->stream));
     NB_HIP(hipStreamSynchronize(m->stream));
     if (st & 2u) return fail(NB_ETIMEOUT, "grid barrier time limit exceeded");
     return fail(NB_ENUMERIC, "moment contribution out of fixed-point range (NaN or overflow)");
@@ -355,7 +363,8 @@ static int check_status(nb_model* m) {
 
 static int advance(nb_model* m, long long n) {
   const long long rows = 2LL * m->NU;
-  const int want = (int)std::min<long long>((rows + 3) / 4, m->max_blocks);
+  const int wpb = kBlock / 64;
+  const int want = (int)std::min<long long>((rows + wpb - 1) / wpb, m->max_blocks);
   const int nblocks = std::max(1, want);
   // bound the barrier epochs of one launch well inside 32 bits
   const long long chunk = std::max<long long>(1, (long long)(3.5e9 / ((double)nblocks * 4.0)) - 2);
@@ -386,9 +395,10 @@ static int advance(nb_model* m, long long n) {
     unsigned int* sync = a.sync;
     int keep = 1;
     void* zargs[] = {&sync, &keep};
-    NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(1), dim3(kSyncWords), zargs, 0, m->stream));
+    NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(8), dim3(256), zargs, 0, m->stream));
     void* args[] = {&a};
-    NB_HIP(hipLaunchCooperativeKernel(advance_kernel(m), dim3(nblocks), dim3(kBlock), args, 0, m->stream));
+    NB_HIP(hipLaunchCooperativeKernel(advance_kernel(m), dim3(nblocks), dim3(kBlock), args,
+                                      (unsigned)advance_dyn_lds(m), m->stream));
     m->step += k;
     n -= k;
     int rc = check_status(m);

@@ -13,6 +13,7 @@
 
 namespace nb {
 
+constexpr double kTwo58 = 288230376151711744.0;
 constexpr double kTwo62 = 4611686018427387904.0;
 constexpr double kTwo64 = 18446744073709551616.0;
 
@@ -79,10 +80,12 @@ __device__ __forceinline__ double i128_to_double(I128 x) {
   const double v = (double)hi * kTwo64 + (double)lo;
   return neg ? -v : v;
 }
-// trunc(v * scale) as an integer; flags values outside (-2^62, 2^62) (NaN included).
-__device__ __forceinline__ long long to_fix(double v, double scale, int& err) {
+// trunc(v * scale) as an integer; flags values outside (-limit, limit) (NaN included).
+// Beam contributions use limit 2^58 (32 of them fit a signed 64-bit lane sum), the
+// per-angle J0 terms 2^62.
+__device__ __forceinline__ long long to_fix(double v, double scale, double limit, int& err) {
   const double x = v * scale;
-  if (!(fabs(x) < kTwo62)) {
+  if (!(fabs(x) < limit)) {
     err = 1;
     return 0;
   }
@@ -134,6 +137,23 @@ __device__ __forceinline__ cplx hat(const Herm3& h, int a, int b) {
 __device__ __forceinline__ Herm3 hscale(double s, const Herm3& h) {
   return Herm3{s * h.d0, s * h.d1, s * h.d2, rmul(s, h.o01), rmul(s, h.o02), rmul(s, h.o12)};
 }
+// acc <- acc + a * K, entry by entry (one multiply and one add per real entry).
+__device__ __forceinline__ void haxpy(Herm3& acc, double a, const Herm3& K) {
+  acc.d0 = acc.d0 + a * K.d0;
+  acc.d1 = acc.d1 + a * K.d1;
+  acc.d2 = acc.d2 + a * K.d2;
+  acc.o01 = mk(acc.o01.re + a * K.o01.re, acc.o01.im + a * K.o01.im);
+  acc.o02 = mk(acc.o02.re + a * K.o02.re, acc.o02.im + a * K.o02.im);
+  acc.o12 = mk(acc.o12.re + a * K.o12.re, acc.o12.im + a * K.o12.im);
+}
+__device__ __forceinline__ void hadd(Herm3& acc, const Herm3& K) {
+  acc.d0 = acc.d0 + K.d0;
+  acc.d1 = acc.d1 + K.d1;
+  acc.d2 = acc.d2 + K.d2;
+  acc.o01 = mk(acc.o01.re + K.o01.re, acc.o01.im + K.o01.im);
+  acc.o02 = mk(acc.o02.re + K.o02.re, acc.o02.im + K.o02.im);
+  acc.o12 = mk(acc.o12.re + K.o12.re, acc.o12.im + K.o12.im);
+}
 
 // C(A,B) = i [A,B]: with X = A B, C_aa = -2 Im X_aa, C_ab = i (X_ab - conj(X_ba)).
 __device__ __forceinline__ Herm3 icomm(const Herm3& A, const Herm3& B) {
@@ -175,11 +195,20 @@ __device__ __forceinline__ double cnorm2v(const cplx v[3]) {
   return (norm2(v[0]) + norm2(v[1])) + norm2(v[2]);
 }
 
-// psi <- exp(-i K) psi up to a global phase (three flavours).  exp(-iK) splits into the
-// isolated eigen-direction v1 of the traceless part K0 (eigenvalue l1 of largest
-// magnitude, found by Newton on the characteristic cubic l^3 - p l - q) and the 2x2
-// block K' = W^+ K0 W on its orthogonal complement, which is propagated by the
-// closed-form SU(2) exponential of Eq. U; traces only add global phases.
+// psi <- exp(-i K) psi up to a global phase (three flavours).  K0 = traceless part of K,
+// l1 its eigenvalue of largest magnitude (Newton on the characteristic cubic
+// l^3 - p l - q from 2 sqrt(p/3)), v1 its eigenvector (the largest cross product of two
+// rows of K0 - l1).  On the plane orthogonal to v1, K0 - hm with hm = -l1/2 squares to
+// th^2, so the plane is propagated by the closed-form 2x2 exponential of Eq. U:
+//   psi' = e^{-i (l1 - hm)} (v1^+ psi) v1 + cos(th) P psi - i sin(th)/th (K0 - hm) P psi,
+// P = I - v1 v1^+, th = |(K0 - hm) u| for a unit u in the plane.
+__device__ __forceinline__ void k0_minus(const cplx v[3], double d0, double d1, double d2,
+                                         cplx x, cplx y, cplx z, cplx o[3]) {
+  o[0] = cadd(cadd(rmul(d0, v[0]), cmul(x, v[1])), cmul(y, v[2]));
+  o[1] = cadd(cadd(cmul_conja(x, v[0]), rmul(d1, v[1])), cmul(z, v[2]));
+  o[2] = cadd(cadd(cmul_conja(y, v[0]), cmul_conja(z, v[1])), rmul(d2, v[2]));
+}
+
 __device__ __forceinline__ void exp3_apply(const Herm3& K, cplx psi[3]) {
   const double tr = ((K.d0 + K.d1) + K.d2) * (1.0 / 3.0);
   const double a0 = K.d0 - tr, a1 = K.d1 - tr, a2 = K.d2 - tr;
@@ -205,68 +234,73 @@ __device__ __forceinline__ void exp3_apply(const Herm3& K, cplx psi[3]) {
   const cplx r0[3] = {mk(a0 - l1, 0.0), x, y};
   const cplx r1[3] = {conjg(x), mk(a1 - l1, 0.0), z};
   const cplx r2[3] = {conjg(y), conjg(z), mk(a2 - l1, 0.0)};
-  cplx c01[3], c02[3], c12[3];
-  cross3c(r0, r1, c01);
-  cross3c(r0, r2, c02);
-  cross3c(r1, r2, c12);
-  const double n01 = cnorm2v(c01), n02 = cnorm2v(c02), n12 = cnorm2v(c12);
-  cplx best[3] = {c01[0], c01[1], c01[2]};
-  double nb = n01;
-  if (n02 > nb) {
-    best[0] = c02[0]; best[1] = c02[1]; best[2] = c02[2];
-    nb = n02;
+  // eigenvector: the largest of the three row cross products (first one wins ties)
+  cplx best[3];
+  double nb;
+  {
+    cplx c[3];
+    cross3c(r0, r1, c);
+    nb = cnorm2v(c);
+    best[0] = c[0]; best[1] = c[1]; best[2] = c[2];
   }
-  if (n12 > nb) {
-    best[0] = c12[0]; best[1] = c12[1]; best[2] = c12[2];
-    nb = n12;
+  {
+    cplx c[3];
+    cross3c(r0, r2, c);
+    const double n = cnorm2v(c);
+    if (n > nb) {
+      best[0] = c[0]; best[1] = c[1]; best[2] = c[2];
+      nb = n;
+    }
+  }
+  {
+    cplx c[3];
+    cross3c(r1, r2, c);
+    const double n = cnorm2v(c);
+    if (n > nb) {
+      best[0] = c[0]; best[1] = c[1]; best[2] = c[2];
+      nb = n;
+    }
   }
   if (!(nb > 0.0)) return;
   const double inb = 1.0 / sqrt(nb);
   const cplx v1[3] = {rmul(inb, best[0]), rmul(inb, best[1]), rmul(inb, best[2])};
-  const double nc0 = norm2(v1[0]), nc1 = norm2(v1[1]), nc2 = norm2(v1[2]);
-  int m = 0;
-  double ncm = nc0;
-  if (nc1 < ncm) { m = 1; ncm = nc1; }
-  if (nc2 < ncm) { m = 2; ncm = nc2; }
-  const cplx vm = (m == 0) ? v1[0] : ((m == 1) ? v1[1] : v1[2]);
-  cplx w[3];
+  const double hm = -0.5 * l1;
+  const double d0 = a0 - hm, d1 = a1 - hm, d2 = a2 - hm;
+  double th;
+  {
+    // unit vector of the plane: Gram-Schmidt of the axis where v1 is smallest
+    const double nc0 = norm2(v1[0]), nc1 = norm2(v1[1]), nc2 = norm2(v1[2]);
+    int m = 0;
+    double ncm = nc0;
+    if (nc1 < ncm) { m = 1; ncm = nc1; }
+    if (nc2 < ncm) { m = 2; ncm = nc2; }
+    const cplx vm = (m == 0) ? v1[0] : ((m == 1) ? v1[1] : v1[2]);
+    cplx w[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const cplx tm = cmul_conjb(v1[c], vm);
-    w[c] = (c == m) ? mk(1.0 - ncm, 0.0) : mk(-tm.re, -tm.im);
+    for (int c = 0; c < 3; ++c) {
+      const cplx tm = cmul_conjb(v1[c], vm);
+      w[c] = (c == m) ? mk(1.0 - ncm, 0.0) : mk(-tm.re, -tm.im);
+    }
+    const double inw = 1.0 / sqrt(cnorm2v(w));
+    const cplx u[3] = {rmul(inw, w[0]), rmul(inw, w[1]), rmul(inw, w[2])};
+    cplx ku[3];
+    k0_minus(u, d0, d1, d2, x, y, z, ku);
+    th = sqrt(cnorm2v(ku));
   }
-  const double inw = 1.0 / sqrt(cnorm2v(w));
-  const cplx w2[3] = {rmul(inw, w[0]), rmul(inw, w[1]), rmul(inw, w[2])};
-  cplx w3[3];
-  cross3c(v1, w2, w3);
-  w3[0] = conjg(w3[0]); w3[1] = conjg(w3[1]); w3[2] = conjg(w3[2]);
-  cplx kw2[3], kw3[3];
-  kw2[0] = cadd(cadd(rmul(a0, w2[0]), cmul(x, w2[1])), cmul(y, w2[2]));
-  kw2[1] = cadd(cadd(cmul_conja(x, w2[0]), rmul(a1, w2[1])), cmul(z, w2[2]));
-  kw2[2] = cadd(cadd(cmul_conja(y, w2[0]), cmul_conja(z, w2[1])), rmul(a2, w2[2]));
-  kw3[0] = cadd(cadd(rmul(a0, w3[0]), cmul(x, w3[1])), cmul(y, w3[2]));
-  kw3[1] = cadd(cadd(cmul_conja(x, w3[0]), rmul(a1, w3[1])), cmul(z, w3[2]));
-  kw3[2] = cadd(cadd(cmul_conja(y, w3[0]), cmul_conja(z, w3[1])), rmul(a2, w3[2]));
-  const double k22 = dotc(w2, kw2).re, k33 = dotc(w3, kw3).re;
-  const cplx k23 = dotc(w2, kw3);
-  const double hm = 0.5 * (k22 + k33), h11 = 0.5 * (k22 - k33);
+  const cplx al = dotc(v1, psi);
+  cplx pp[3], kp[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) pp[c] = csub(psi[c], cmul(al, v1[c]));
+  k0_minus(pp, d0, d1, d2, x, y, z, kp);
   const double phi = l1 - hm;
-  const double th = sqrt(fma(h11, h11, norm2(k23)));
   double sp, cp, st, ct;
   sincos_nb(phi, sp, cp);
   sincos_nb(th, st, ct);
-  const double sc = (th > 0.0) ? st / th : 0.0;
-  const cplx al = cmul(dotc(v1, psi), mk(cp, -sp));
-  const cplx b2 = dotc(w2, psi), b3 = dotc(w3, psi);
-  const double hs = h11 * sc;
-  const cplx g = mk(k23.re * sc, k23.im * sc);
-  const cplx t2 = cadd(rmul(hs, b2), cmul(g, b3));
-  const cplx t3 = csub(cmul_conja(g, b2), rmul(hs, b3));
-  const cplx b2n = mk(ct * b2.re + t2.im, ct * b2.im - t2.re);
-  const cplx b3n = mk(ct * b3.re + t3.im, ct * b3.im - t3.re);
+  const double sc = (th > 0.0) ? st / th : 1.0;
+  const cplx ap = cmul(al, mk(cp, -sp));
 #pragma unroll
   for (int c = 0; c < 3; ++c)
-    psi[c] = cadd(cadd(cmul(al, v1[c]), cmul(b2n, w2[c])), cmul(b3n, w3[c]));
+    psi[c] = cadd(cmul(ap, v1[c]), mk(ct * pp[c].re + sc * kp[c].im, ct * pp[c].im - sc * kp[c].re));
 }
 
 // Bloch-vector rotation about x by |x| (two flavours): unit quaternion

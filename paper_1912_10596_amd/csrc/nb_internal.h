@@ -5,14 +5,17 @@
 
 namespace nb {
 
-// Offsets (in 32-bit words) of the synchronisation words; each on its own 128-byte line.
-constexpr int kSyncCount = 0;    // barrier arrivals (monotonic within one launch)
-constexpr int kSyncFlag = 32;    // last completed barrier epoch + 1
-constexpr int kSyncAbort = 64;   // set when any block gives up waiting
-constexpr int kSyncStatus = 96;  // bit 0: fixed-point range error, bit 1: barrier timeout
-constexpr int kSyncWords = 128;
+constexpr int kMaxBlocks = 8192;  // upper bound on blocks of one stepping launch
 
-constexpr int kBlock = 256;      // threads per block of the stepping kernels (4 waves)
+// Offsets (in 32-bit words) of the synchronisation words; the singletons each on their
+// own 128-byte line, then one arrival word per block.
+constexpr int kSyncFlag = 32;     // epoch + 1 of the last barrier released by block 0
+constexpr int kSyncAbort = 64;    // set when any block gives up waiting
+constexpr int kSyncStatus = 96;   // bit 0: fixed-point range error, bit 1: barrier timeout
+constexpr int kSyncArrive = 128;  // [kMaxBlocks]: epoch + 1 of each block's last arrival
+constexpr int kSyncWords = kSyncArrive + kMaxBlocks;
+
+constexpr int kBlock = 512;       // threads per block of the stepping kernels (8 waves)
 
 // Arguments of the single-model stepping kernel (passed by value).
 struct StepArgs {

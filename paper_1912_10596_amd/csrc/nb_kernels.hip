@@ -48,14 +48,33 @@ __device__ __forceinline__ I128 select_comp(const I128 (&S)[NV], int c) {
 }
 
 // ---------------------------------------------------------------- grid barrier
-// The block's partial (valid in threads tid < NV) is published, the grid meets, and the
-// last block to arrive folds all partials into the stage moments (J0 | J1) which every
-// block then reads into LDS.  Returns false if the barrier was abandoned (time limit).
+// Spin until *w >= want (agent-scope acquire), giving up when another block has aborted
+// or the launch's time limit passes.  Returns false on give-up.
+__device__ __forceinline__ bool spin_until(const StepArgs& a, unsigned* w, unsigned want) {
+  const unsigned long long t0 = wall_clock64();
+  for (;;) {
+    if (__hip_atomic_load(w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= want) return true;
+    if (__hip_atomic_load(a.sync + kSyncAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    if (wall_clock64() - t0 > a.timeout_ticks) {
+      __hip_atomic_store(a.sync + kSyncAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_or(a.sync + kSyncStatus, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// Grid-wide reduction of the stage moments without read-modify-write contention: every
+// block publishes its partial (threads tid < NV) and then an arrival word of its own;
+// block 0 polls all arrival words in parallel, folds the partials exactly, stores the
+// stage moments (J0 | J1) and releases one flag that every other block polls.
+// Returns false if the barrier was abandoned (time limit or abort).
 template <int NV>
 __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, double* sJ,
                             double* gJ, I128* sred) {
-  __shared__ int s_last, s_ok;
+  __shared__ int s_ok;
   const int tid = threadIdx.x;
+  const unsigned want = epoch + 1u;
   if (tid < NV) {
     unsigned long long* p = a.part + ((size_t)blockIdx.x * NV + tid) * 2;
     __hip_atomic_store(p, blk.lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -63,67 +82,51 @@ __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, double*
     __threadfence();
   }
   __syncthreads();
-  if (tid == 0) {
-    const unsigned old = __hip_atomic_fetch_add(a.sync + kSyncCount, 1u, __ATOMIC_ACQ_REL,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (old == (epoch + 1u) * gridDim.x - 1u) ? 1 : 0;
-  }
-  __syncthreads();
-  if (s_last) {
-    constexpr int G = kBlock / NV;
-    const int v = tid % NV, g = tid / NV;
-    I128 acc = i128_zero();
-    if (g < G) {
-      for (unsigned b = g; b < gridDim.x; b += G) {
-        const unsigned long long* p = a.part + ((size_t)b * NV + v) * 2;
-        I128 t;
-        t.lo = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        t.hi = (long long)__hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        acc = i128_add(acc, t);
-      }
-      sred[tid] = acc;
-    }
-    __syncthreads();
-    if (tid < NV) {
-      I128 tot = i128_zero();
-      for (int gg = 0; gg < G; ++gg) tot = i128_add(tot, sred[gg * NV + tid]);
-      const double val = i128_to_double(tot) * (tid < NV / 2 ? a.p2e0 : a.p2e1);
-      sJ[tid] = val;
-      __hip_atomic_store((unsigned long long*)gJ + tid, as_bits(val), __ATOMIC_RELAXED,
+  if (blockIdx.x != 0) {
+    if (tid == 0) {
+      __hip_atomic_store(a.sync + kSyncArrive + blockIdx.x, want, __ATOMIC_RELEASE,
                          __HIP_MEMORY_SCOPE_AGENT);
-      __threadfence();
+      s_ok = spin_until(a, a.sync + kSyncFlag, want) ? 1 : 0;
     }
     __syncthreads();
-    if (tid == 0)
-      __hip_atomic_store(a.sync + kSyncFlag, epoch + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (!s_ok) return false;
+    if (tid < NV)
+      sJ[tid] = as_double(__hip_atomic_load((unsigned long long*)gJ + tid, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT));
+    __syncthreads();
     return true;
   }
-  if (tid == 0) {
-    const unsigned long long t0 = wall_clock64();
-    int ok = 1;
-    for (;;) {
-      const unsigned f = __hip_atomic_load(a.sync + kSyncFlag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-      if (f >= epoch + 1u) break;
-      if (__hip_atomic_load(a.sync + kSyncAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        ok = 0;
-        break;
-      }
-      if (wall_clock64() - t0 > a.timeout_ticks) {
-        __hip_atomic_store(a.sync + kSyncAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_or(a.sync + kSyncStatus, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ok = 0;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
+  // block 0: wait for every arrival word
+  int ok = 1;
+  for (unsigned b = 1 + tid; b < gridDim.x && ok; b += kBlock)
+    ok = spin_until(a, a.sync + kSyncArrive + b, want) ? 1 : 0;
+  if (__syncthreads_or(!ok)) return false;
+  constexpr int G = kBlock / NV;
+  const int v = tid % NV, g = tid / NV;
+  if (g < G) {
+    I128 acc = i128_zero();
+    for (unsigned b = g; b < gridDim.x; b += G) {
+      const unsigned long long* p = a.part + ((size_t)b * NV + v) * 2;
+      I128 t;
+      t.lo = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      t.hi = (long long)__hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      acc = i128_add(acc, t);
     }
-    s_ok = ok;
+    sred[tid] = acc;
   }
   __syncthreads();
-  if (!s_ok) return false;
-  if (tid < NV)
-    sJ[tid] = as_double(__hip_atomic_load((unsigned long long*)gJ + tid, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT));
+  if (tid < NV) {
+    I128 tot = i128_zero();
+    for (int gg = 0; gg < G; ++gg) tot = i128_add(tot, sred[gg * NV + tid]);
+    const double val = i128_to_double(tot) * (tid < NV / 2 ? a.p2e0 : a.p2e1);
+    sJ[tid] = val;
+    __hip_atomic_store((unsigned long long*)gJ + tid, as_bits(val), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+  }
   __syncthreads();
+  if (tid == 0)
+    __hip_atomic_store(a.sync + kSyncFlag, want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   return true;
 }
 
@@ -140,24 +143,63 @@ __device__ bool finish_stage(const StepArgs& a, unsigned epoch, I128 T, I128 (*s
   return grid_reduce<NV>(a, epoch, blk, sJ, gJ, sred);
 }
 
+// ------------------------------------------------------------- row helpers
+// Geometry of one emission bin at the three stage radii of a step.
+struct RowGeo {
+  double c0, cm, c1, hc0, hcm, hc1;
+};
+__device__ __forceinline__ RowGeo row_geo(const StepArgs& a, int j, const Radial& g0,
+                                          const Radial& gm, const Radial& g1) {
+  RowGeo r;
+  const double u = ((double)j + 0.5) / (double)a.NU;
+  r.c0 = sqrt(1.0 - u * g0.q2);
+  r.cm = sqrt(1.0 - u * gm.q2);
+  r.c1 = sqrt(1.0 - u * g1.q2);
+  r.hc0 = a.h / r.c0;
+  r.hcm = a.h / r.cm;
+  r.hc1 = a.h / r.c1;
+  return r;
+}
+// The neutrino-neutrino term mu (J0 - c J1) of a row: the same for every energy bin.
+template <int NC>
+__device__ __forceinline__ void nunu(const double* J, double mu, double c, double* nn) {
+#pragma unroll
+  for (int i = 0; i < NC; ++i) nn[i] = mu * (J[i] - c * J[NC + i]);
+}
+// End of a row segment: lane sums -> exact wave sums; lane v keeps component v % NC.
+template <int NC>
+__device__ __forceinline__ void fold_segment(const long long* acc, int lane, I128& mine) {
+#pragma unroll
+  for (int i = 0; i < NC; ++i) {
+    const I128 t = wave_sum(i128_from(acc[i]));
+    if (lane % NC == i) mine = i128_add(mine, t);
+  }
+}
+// End of a row: lanes v < NC add the J0 angle term (energy sum / cos), lanes
+// NC <= v < 2 NC the J1 energy sum, to their running totals.
+template <int NC>
+__device__ __forceinline__ void close_row(const StepArgs& a, int lane, const I128& mine,
+                                          double icmom, I128& T, int& err) {
+  if (lane < NC)
+    T = i128_add(T, i128_from(to_fix(icmom * (i128_to_double(mine) * a.p2e1), a.s0, kTwo62, err)));
+  else if (lane < 2 * NC)
+    T = i128_add(T, mine);
+}
+
 // ----------------------------------------------------------------- two flavours
-// B vector of beam (s, k) (H = B.sigma/2 + trace): neutrinos
-// B_vac + lam e_z + mu (J0 - c J1); antineutrinos B_vac - lam e_z - mu (J0 - c J1)^*,
-// where ^* maps (x, y, z) -> (x, -y, z).  The stage generator is f = (h/c) B.
-__device__ __forceinline__ void gen2(int s, double bx, double bz, const Radial& g, double c,
-                                     double hc, const double* J, double f[3]) {
-  const double nx = g.mu * (J[0] - c * J[3]);
-  const double ny = g.mu * (J[1] - c * J[4]);
-  const double nz = g.mu * (J[2] - c * J[5]);
+// Stage generator f = (h/c) B of beam (s, k) with B = B_vac + lam e_z + nn for
+// neutrinos and B_vac - lam e_z - nn^* (nn^* = (x, -y, z)) for antineutrinos.
+__device__ __forceinline__ void gen2(int s, double bx, double bz, double lam, const double* nn,
+                                     double hc, double f[3]) {
   double B0, B1, B2;
   if (s == 0) {
-    B0 = bx + nx;
-    B1 = ny;
-    B2 = (bz + g.lam) + nz;
+    B0 = bx + nn[0];
+    B1 = nn[1];
+    B2 = (bz + lam) + nn[2];
   } else {
-    B0 = bx - nx;
-    B1 = ny;
-    B2 = (bz - g.lam) - nz;
+    B0 = bx - nn[0];
+    B1 = nn[1];
+    B2 = (bz - lam) - nn[2];
   }
   f[0] = hc * B0;
   f[1] = hc * B1;
@@ -166,264 +208,312 @@ __device__ __forceinline__ void gen2(int s, double bx, double bz, const Radial& 
 
 // KIND: 0 moments of rho_n at r_n; 1 stage Y2 (moments at r_n + h/2); 2 stage Y3
 // (r_n + h/2); 3 stage Y4 (r_{n+1}); 4 final update, store and moments at r_{n+1}.
+// A lane adds the fixed-point contributions of up to 32 of its beams of a row in 64-bit
+// integers (each below 2^58) before they are folded into exact 128-bit wave sums.
 template <int KIND>
 __device__ __forceinline__ void stage2(const StepArgs& a, long long n, const double (*sJ)[6],
-                                       long long gw, long long nw, int lane, I128& T, int& err) {
+                                       const double* tab, long long gw, long long nw, int lane,
+                                       I128& T, int& err) {
   const double r0 = a.rs + (double)n * a.h;
   const double rm = r0 + 0.5 * a.h;
   const double r1 = a.rs + (double)(n + 1) * a.h;
   const Radial g0 = radial_at(a, r0), gm = radial_at(a, rm), g1 = radial_at(a, r1);
   const long long nrow = 2LL * a.NU, plane = a.plane;
+  const int NE = a.NE;
   double* X = (double*)a.X;
-  const double* tbx = a.tab;
-  const double* tbz = a.tab + a.NE;
   for (long long row = gw; row < nrow; row += nw) {
     const int s = (int)(row / a.NU);
     const int j = (int)(row - (long long)s * a.NU);
-    const double u = ((double)j + 0.5) / (double)a.NU;
-    const double c0 = sqrt(1.0 - u * g0.q2), cm = sqrt(1.0 - u * gm.q2), c1 = sqrt(1.0 - u * g1.q2);
-    const double hc0 = a.h / c0, hcm = a.h / cm, hc1 = a.h / c1;
-    const double cmom = (KIND == 0) ? c0 : ((KIND <= 2) ? cm : c1);
-    const double icmom = 1.0 / cmom;
-    const double* G = a.tab + (size_t)(2 + s) * a.NE;
-    I128 S[3] = {i128_zero(), i128_zero(), i128_zero()};
-    for (int k = lane; k < a.NE; k += 64) {
-      const long long b = row * a.NE + k;
-      double P0 = X[b], P1 = X[b + plane], P2 = X[b + 2 * plane];
-      if (KIND >= 1) {
-        const double bx = tbx[k], bz = tbz[k];
-        double f1[3], f2[3], f3[3], f4[3];
-        if (KIND != 3) gen2(s, bx, bz, g0, c0, hc0, sJ[0], f1);
-        if (KIND == 1) {
-          rotate2(0.5 * f1[0], 0.5 * f1[1], 0.5 * f1[2], P0, P1, P2);
-        } else if (KIND == 2) {
-          gen2(s, bx, bz, gm, cm, hcm, sJ[1], f2);
-          const double cr0 = f1[1] * f2[2] - f1[2] * f2[1];
-          const double cr1 = f1[2] * f2[0] - f1[0] * f2[2];
-          const double cr2 = f1[0] * f2[1] - f1[1] * f2[0];
-          rotate2(0.5 * f2[0] - 0.125 * cr0, 0.5 * f2[1] - 0.125 * cr1, 0.5 * f2[2] - 0.125 * cr2,
-                  P0, P1, P2);
-        } else if (KIND == 3) {
-          gen2(s, bx, bz, gm, cm, hcm, sJ[2], f3);
-          rotate2(f3[0], f3[1], f3[2], P0, P1, P2);
-        } else {
-          gen2(s, bx, bz, gm, cm, hcm, sJ[1], f2);
-          gen2(s, bx, bz, gm, cm, hcm, sJ[2], f3);
-          gen2(s, bx, bz, g1, c1, hc1, sJ[3], f4);
-          const double cr0 = f1[1] * f4[2] - f1[2] * f4[1];
-          const double cr1 = f1[2] * f4[0] - f1[0] * f4[2];
-          const double cr2 = f1[0] * f4[1] - f1[1] * f4[0];
-          const double t0 = (((f1[0] + 2.0 * f2[0]) + 2.0 * f3[0]) + f4[0]) * (1.0 / 6.0) - cr0 * (1.0 / 12.0);
-          const double t1 = (((f1[1] + 2.0 * f2[1]) + 2.0 * f3[1]) + f4[1]) * (1.0 / 6.0) - cr1 * (1.0 / 12.0);
-          const double t2 = (((f1[2] + 2.0 * f2[2]) + 2.0 * f3[2]) + f4[2]) * (1.0 / 6.0) - cr2 * (1.0 / 12.0);
-          rotate2(t0, t1, t2, P0, P1, P2);
-          if (a.renorm) {
-            const double n2 = (P0 * P0 + P1 * P1) + P2 * P2;
-            const double inv = 1.0 / sqrt(n2);
-            P0 = P0 * inv;
-            P1 = P1 * inv;
-            P2 = P2 * inv;
-          }
-          X[b] = P0;
-          X[b + plane] = P1;
-          X[b + 2 * plane] = P2;
-        }
+    const RowGeo rg = row_geo(a, j, g0, gm, g1);
+    const double icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
+    double n1[3], n2[3], n3[3], n4[3];
+    if (KIND == 1 || KIND == 2 || KIND == 4) nunu<3>(sJ[0], g0.mu, rg.c0, n1);
+    if (KIND == 2 || KIND == 4) nunu<3>(sJ[1], gm.mu, rg.cm, n2);
+    if (KIND >= 3) nunu<3>(sJ[2], gm.mu, rg.cm, n3);
+    if (KIND == 4) nunu<3>(sJ[3], g1.mu, rg.c1, n4);
+    const double* G = tab + (size_t)(2 + s) * NE;
+    const long long rb = row * NE;
+    I128 mine = i128_zero();
+    for (int k0 = lane; k0 - lane < NE; k0 += 64 * 32) {
+      const int kend = min(NE, k0 + 64 * 32);
+      long long acc[3] = {0, 0, 0};
+      double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+      if (k0 < kend) {
+        q0 = X[rb + k0]; q1 = X[rb + k0 + plane]; q2 = X[rb + k0 + 2 * plane];
       }
-      // rho~: rho for neutrinos, -rho^* (Bloch (-x, y, -z)) for antineutrinos
-      const double w = G[k];
-      const double v0 = s ? -P0 : P0, v2 = s ? -P2 : P2;
-      S[0] = i128_add(S[0], i128_from(to_fix(w * v0, a.s1, err)));
-      S[1] = i128_add(S[1], i128_from(to_fix(w * P1, a.s1, err)));
-      S[2] = i128_add(S[2], i128_from(to_fix(w * v2, a.s1, err)));
+      for (int k = k0; k < kend; k += 64) {
+        double P0 = q0, P1 = q1, P2 = q2;
+        if (k + 64 < kend) {    // prefetch the lane's next beam
+          q0 = X[rb + k + 64]; q1 = X[rb + k + 64 + plane]; q2 = X[rb + k + 64 + 2 * plane];
+        }
+        if (KIND >= 1) {
+          const double bx = tab[k], bz = tab[NE + k];
+          double f1[3], f2[3], f3[3], f4[3];
+          if (KIND != 3) gen2(s, bx, bz, g0.lam, n1, rg.hc0, f1);
+          if (KIND == 1) {
+            rotate2(0.5 * f1[0], 0.5 * f1[1], 0.5 * f1[2], P0, P1, P2);
+          } else if (KIND == 2) {
+            gen2(s, bx, bz, gm.lam, n2, rg.hcm, f2);
+            const double cr0 = f1[1] * f2[2] - f1[2] * f2[1];
+            const double cr1 = f1[2] * f2[0] - f1[0] * f2[2];
+            const double cr2 = f1[0] * f2[1] - f1[1] * f2[0];
+            rotate2(0.5 * f2[0] - 0.125 * cr0, 0.5 * f2[1] - 0.125 * cr1, 0.5 * f2[2] - 0.125 * cr2,
+                    P0, P1, P2);
+          } else if (KIND == 3) {
+            gen2(s, bx, bz, gm.lam, n3, rg.hcm, f3);
+            rotate2(f3[0], f3[1], f3[2], P0, P1, P2);
+          } else {
+            gen2(s, bx, bz, gm.lam, n2, rg.hcm, f2);
+            gen2(s, bx, bz, gm.lam, n3, rg.hcm, f3);
+            gen2(s, bx, bz, g1.lam, n4, rg.hc1, f4);
+            const double cr0 = f1[1] * f4[2] - f1[2] * f4[1];
+            const double cr1 = f1[2] * f4[0] - f1[0] * f4[2];
+            const double cr2 = f1[0] * f4[1] - f1[1] * f4[0];
+            const double t0 = (((f1[0] + 2.0 * f2[0]) + 2.0 * f3[0]) + f4[0]) * (1.0 / 6.0) - cr0 * (1.0 / 12.0);
+            const double t1 = (((f1[1] + 2.0 * f2[1]) + 2.0 * f3[1]) + f4[1]) * (1.0 / 6.0) - cr1 * (1.0 / 12.0);
+            const double t2 = (((f1[2] + 2.0 * f2[2]) + 2.0 * f3[2]) + f4[2]) * (1.0 / 6.0) - cr2 * (1.0 / 12.0);
+            rotate2(t0, t1, t2, P0, P1, P2);
+            if (a.renorm) {
+              const double nrm2 = (P0 * P0 + P1 * P1) + P2 * P2;
+              const double inv = 1.0 / sqrt(nrm2);
+              P0 = P0 * inv;
+              P1 = P1 * inv;
+              P2 = P2 * inv;
+            }
+            X[rb + k] = P0;
+            X[rb + k + plane] = P1;
+            X[rb + k + 2 * plane] = P2;
+          }
+        }
+        // rho~: rho for neutrinos, -rho^* (Bloch (-x, y, -z)) for antineutrinos
+        const double w = G[k];
+        const double v0 = s ? -P0 : P0, v2 = s ? -P2 : P2;
+        acc[0] += to_fix(w * v0, a.s1, kTwo58, err);
+        acc[1] += to_fix(w * P1, a.s1, kTwo58, err);
+        acc[2] += to_fix(w * v2, a.s1, kTwo58, err);
+      }
+      fold_segment<3>(acc, lane, mine);
     }
-    S[0] = wave_sum(S[0]);
-    S[1] = wave_sum(S[1]);
-    S[2] = wave_sum(S[2]);
-    if (lane < 6) {
-      const I128 sv = select_comp<3>(S, lane % 3);
-      if (lane < 3)
-        T = i128_add(T, i128_from(to_fix(icmom * (i128_to_double(sv) * a.p2e1), a.s0, err)));
-      else
-        T = i128_add(T, sv);
-    }
+    close_row<3>(a, lane, mine, icmom, T, err);
   }
 }
 
 // --------------------------------------------------------------- three flavours
-template <typename ST>
-__device__ __forceinline__ Herm3 gen3(int s, const double* tab, int NE, int k, const Radial& g,
-                                      double c, double hc, const double* J) {
-  double nn[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) nn[i] = g.mu * (J[i] - c * J[8 + i]);
-  const double v0 = tab[k], v1 = tab[NE + k], v2 = tab[2 * NE + k];
-  const double v3 = tab[3 * NE + k], v4 = tab[4 * NE + k], v5 = tab[5 * NE + k];
+// K = (h/c) H of beam (s, k): H = H_vac + lam E_ee + nn (neutrinos) or
+// H_vac - lam E_ee - nn^* (antineutrinos); v: the six vacuum entries of energy bin k.
+__device__ __forceinline__ Herm3 gen3(int s, const double* v, double lam, const double* nn,
+                                      double hc) {
   Herm3 H;
   if (s == 0) {
-    H.d0 = (v0 + g.lam) + nn[0];
-    H.d1 = v1 + nn[1];
-    H.d2 = v2;
-    H.o01 = mk(v3 + nn[2], nn[3]);
-    H.o02 = mk(v4 + nn[4], nn[5]);
-    H.o12 = mk(v5 + nn[6], nn[7]);
+    H.d0 = (v[0] + lam) + nn[0];
+    H.d1 = v[1] + nn[1];
+    H.d2 = v[2];
+    H.o01 = mk(v[3] + nn[2], nn[3]);
+    H.o02 = mk(v[4] + nn[4], nn[5]);
+    H.o12 = mk(v[5] + nn[6], nn[7]);
   } else {
-    H.d0 = (v0 - g.lam) - nn[0];
-    H.d1 = v1 - nn[1];
-    H.d2 = v2;
-    H.o01 = mk(v3 - nn[2], nn[3]);
-    H.o02 = mk(v4 - nn[4], nn[5]);
-    H.o12 = mk(v5 - nn[6], nn[7]);
+    H.d0 = (v[0] - lam) - nn[0];
+    H.d1 = v[1] - nn[1];
+    H.d2 = v[2];
+    H.o01 = mk(v[3] - nn[2], nn[3]);
+    H.o02 = mk(v[4] - nn[4], nn[5]);
+    H.o12 = mk(v[5] - nn[6], nn[7]);
   }
   return hscale(hc, H);
 }
 
+// Row-wise nn terms of the four stage slots live in LDS (one 32-double block per wave)
+// and are re-read per beam, so the compiler does not keep all of them in registers.
 template <typename ST, int KIND>
 __device__ __forceinline__ void stage3(const StepArgs& a, long long n, const double (*sJ)[16],
-                                       long long gw, long long nw, int lane, I128& T, int& err) {
+                                       const double* tab, double* snn, long long gw,
+                                       long long nw, int lane, I128& T, int& err) {
   const double r0 = a.rs + (double)n * a.h;
   const double rm = r0 + 0.5 * a.h;
   const double r1 = a.rs + (double)(n + 1) * a.h;
   const Radial g0 = radial_at(a, r0), gm = radial_at(a, rm), g1 = radial_at(a, r1);
   const long long nrow = 2LL * a.NU, plane = a.plane;
+  const int NE = a.NE;
   ST* X = (ST*)a.X;
   for (long long row = gw; row < nrow; row += nw) {
     const int s = (int)(row / a.NU);
     const int j = (int)(row - (long long)s * a.NU);
-    const double u = ((double)j + 0.5) / (double)a.NU;
-    const double c0 = sqrt(1.0 - u * g0.q2), cm = sqrt(1.0 - u * gm.q2), c1 = sqrt(1.0 - u * g1.q2);
-    const double hc0 = a.h / c0, hcm = a.h / cm, hc1 = a.h / c1;
-    const double cmom = (KIND == 0) ? c0 : ((KIND <= 2) ? cm : c1);
-    const double icmom = 1.0 / cmom;
-    const double* G = a.tab + (size_t)(6 + s) * a.NE;
-    I128 S[8];
+    const RowGeo rg = row_geo(a, j, g0, gm, g1);
+    const double icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
+    {
+      double t[8];
+      if (KIND == 1 || KIND == 2 || KIND == 4) {
+        nunu<8>(sJ[0], g0.mu, rg.c0, t);
+        for (int i = 0; i < 8; ++i) snn[i] = t[i];
+      }
+      if (KIND == 2 || KIND == 4) {
+        nunu<8>(sJ[1], gm.mu, rg.cm, t);
+        for (int i = 0; i < 8; ++i) snn[8 + i] = t[i];
+      }
+      if (KIND >= 3) {
+        nunu<8>(sJ[2], gm.mu, rg.cm, t);
+        for (int i = 0; i < 8; ++i) snn[16 + i] = t[i];
+      }
+      if (KIND == 4) {
+        nunu<8>(sJ[3], g1.mu, rg.c1, t);
+        for (int i = 0; i < 8; ++i) snn[24 + i] = t[i];
+      }
+    }
+    const double* G = tab + (size_t)(6 + s) * NE;
+    const long long rb = row * NE;
+    I128 mine = i128_zero();
+    for (int k0 = lane; k0 - lane < NE; k0 += 64 * 32) {
+      const int kend = min(NE, k0 + 64 * 32);
+      long long acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      ST q[6];
+      if (k0 < kend) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) S[i] = i128_zero();
-    for (int k = lane; k < a.NE; k += 64) {
-      const long long b = row * a.NE + k;
-      cplx ps[3];
+        for (int c = 0; c < 6; ++c) q[c] = X[rb + k0 + c * plane];
+      }
+      for (int k = k0; k < kend; k += 64) {
+        cplx ps[3] = {mk((double)q[0], (double)q[1]), mk((double)q[2], (double)q[3]),
+                      mk((double)q[4], (double)q[5])};
+        if (k + 64 < kend) {    // prefetch the lane's next beam
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
-        ps[c] = mk((double)X[b + (2 * c) * plane], (double)X[b + (2 * c + 1) * plane]);
-      if (KIND >= 1) {
-        Herm3 K1;
-        if (KIND != 3) K1 = gen3<ST>(s, a.tab, a.NE, k, g0, c0, hc0, sJ[0]);
-        if (KIND == 1) {
-          exp3_apply(hscale(0.5, K1), ps);
-        } else if (KIND == 2) {
-          const Herm3 K2 = gen3<ST>(s, a.tab, a.NE, k, gm, cm, hcm, sJ[1]);
-          const Herm3 C = icomm(K1, K2);
-          Herm3 O;
-          O.d0 = 0.5 * K2.d0 + 0.125 * C.d0;
-          O.d1 = 0.5 * K2.d1 + 0.125 * C.d1;
-          O.d2 = 0.5 * K2.d2 + 0.125 * C.d2;
-          O.o01 = mk(0.5 * K2.o01.re + 0.125 * C.o01.re, 0.5 * K2.o01.im + 0.125 * C.o01.im);
-          O.o02 = mk(0.5 * K2.o02.re + 0.125 * C.o02.re, 0.5 * K2.o02.im + 0.125 * C.o02.im);
-          O.o12 = mk(0.5 * K2.o12.re + 0.125 * C.o12.re, 0.5 * K2.o12.im + 0.125 * C.o12.im);
-          exp3_apply(O, ps);
-        } else if (KIND == 3) {
-          exp3_apply(gen3<ST>(s, a.tab, a.NE, k, gm, cm, hcm, sJ[2]), ps);
-        } else {
-          const Herm3 K2 = gen3<ST>(s, a.tab, a.NE, k, gm, cm, hcm, sJ[1]);
-          const Herm3 K3 = gen3<ST>(s, a.tab, a.NE, k, gm, cm, hcm, sJ[2]);
-          const Herm3 K4 = gen3<ST>(s, a.tab, a.NE, k, g1, c1, hc1, sJ[3]);
-          const Herm3 C = icomm(K1, K4);
-          Herm3 Th;
-#define NB_THETA(f) ((((K1.f + 2.0 * K2.f) + 2.0 * K3.f) + K4.f) * (1.0 / 6.0) + C.f * (1.0 / 12.0))
-          Th.d0 = NB_THETA(d0);
-          Th.d1 = NB_THETA(d1);
-          Th.d2 = NB_THETA(d2);
-          Th.o01 = mk(NB_THETA(o01.re), NB_THETA(o01.im));
-          Th.o02 = mk(NB_THETA(o02.re), NB_THETA(o02.im));
-          Th.o12 = mk(NB_THETA(o12.re), NB_THETA(o12.im));
-#undef NB_THETA
-          exp3_apply(Th, ps);
-          if (a.renorm) {
-            const double n2 = (norm2(ps[0]) + norm2(ps[1])) + norm2(ps[2]);
-            const double inv = 1.0 / sqrt(n2);
+          for (int c = 0; c < 6; ++c) q[c] = X[rb + k + 64 + c * plane];
+        }
+        __asm__ volatile("" ::: "memory");   // re-read the row's nn terms from LDS per beam
+        if (KIND >= 1) {
+          double v[6];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) ps[c] = mk(ps[c].re * inv, ps[c].im * inv);
-          }
-          // store, and take the next step's moments from exactly what was stored
+          for (int c = 0; c < 6; ++c) v[c] = tab[c * NE + k];
+          Herm3 K1;
+          if (KIND != 3) K1 = gen3(s, v, g0.lam, snn, rg.hc0);
+          if (KIND == 1) {
+            exp3_apply(hscale(0.5, K1), ps);
+          } else if (KIND == 2) {
+            const Herm3 K2 = gen3(s, v, gm.lam, snn + 8, rg.hcm);
+            const Herm3 C = icomm(K1, K2);
+            Herm3 O;
+            O.d0 = 0.5 * K2.d0 + 0.125 * C.d0;
+            O.d1 = 0.5 * K2.d1 + 0.125 * C.d1;
+            O.d2 = 0.5 * K2.d2 + 0.125 * C.d2;
+            O.o01 = mk(0.5 * K2.o01.re + 0.125 * C.o01.re, 0.5 * K2.o01.im + 0.125 * C.o01.im);
+            O.o02 = mk(0.5 * K2.o02.re + 0.125 * C.o02.re, 0.5 * K2.o02.im + 0.125 * C.o02.im);
+            O.o12 = mk(0.5 * K2.o12.re + 0.125 * C.o12.re, 0.5 * K2.o12.im + 0.125 * C.o12.im);
+            exp3_apply(O, ps);
+          } else if (KIND == 3) {
+            exp3_apply(gen3(s, v, gm.lam, snn + 16, rg.hcm), ps);
+          } else {
+            // Theta = (((K1 + 2 K2) + 2 K3) + K4)/6 + i[K1,K4]/12, accumulated in that order
+            Herm3 acc3 = K1;
+            haxpy(acc3, 2.0, gen3(s, v, gm.lam, snn + 8, rg.hcm));
+            haxpy(acc3, 2.0, gen3(s, v, gm.lam, snn + 16, rg.hcm));
+            const Herm3 K4 = gen3(s, v, g1.lam, snn + 24, rg.hc1);
+            hadd(acc3, K4);
+            const Herm3 C = icomm(K1, K4);
+            Herm3 Th;
+            Th.d0 = acc3.d0 * (1.0 / 6.0) + C.d0 * (1.0 / 12.0);
+            Th.d1 = acc3.d1 * (1.0 / 6.0) + C.d1 * (1.0 / 12.0);
+            Th.d2 = acc3.d2 * (1.0 / 6.0) + C.d2 * (1.0 / 12.0);
+            Th.o01 = mk(acc3.o01.re * (1.0 / 6.0) + C.o01.re * (1.0 / 12.0),
+                        acc3.o01.im * (1.0 / 6.0) + C.o01.im * (1.0 / 12.0));
+            Th.o02 = mk(acc3.o02.re * (1.0 / 6.0) + C.o02.re * (1.0 / 12.0),
+                        acc3.o02.im * (1.0 / 6.0) + C.o02.im * (1.0 / 12.0));
+            Th.o12 = mk(acc3.o12.re * (1.0 / 6.0) + C.o12.re * (1.0 / 12.0),
+                        acc3.o12.im * (1.0 / 6.0) + C.o12.im * (1.0 / 12.0));
+            exp3_apply(Th, ps);
+            if (a.renorm) {
+              const double nrm2 = (norm2(ps[0]) + norm2(ps[1])) + norm2(ps[2]);
+              const double inv = 1.0 / sqrt(nrm2);
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const ST re = (ST)ps[c].re, im = (ST)ps[c].im;
-            X[b + (2 * c) * plane] = re;
-            X[b + (2 * c + 1) * plane] = im;
-            ps[c] = mk((double)re, (double)im);
+              for (int c = 0; c < 3; ++c) ps[c] = mk(ps[c].re * inv, ps[c].im * inv);
+            }
+            // store, and take the next step's moments from exactly what was stored
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const ST re = (ST)ps[c].re, im = (ST)ps[c].im;
+              X[rb + k + (2 * c) * plane] = re;
+              X[rb + k + (2 * c + 1) * plane] = im;
+              ps[c] = mk((double)re, (double)im);
+            }
           }
         }
-      }
-      // rho~ components: rho_ee-rho_tt, rho_mm-rho_tt, Re/Im rho_em, rho_et, rho_mt;
-      // antineutrinos: -rho^* (real parts and diagonal negated)
-      const double n0 = norm2(ps[0]), n1 = norm2(ps[1]), n2 = norm2(ps[2]);
-      const cplx em = cmul_conjb(ps[0], ps[1]), et = cmul_conjb(ps[0], ps[2]), mt = cmul_conjb(ps[1], ps[2]);
-      double v[8] = {n0 - n2, n1 - n2, em.re, em.im, et.re, et.im, mt.re, mt.im};
-      if (s) {
-        v[0] = -v[0]; v[1] = -v[1]; v[2] = -v[2]; v[4] = -v[4]; v[6] = -v[6];
-      }
-      const double w = G[k];
+        // rho~ components: rho_ee-rho_tt, rho_mm-rho_tt, Re/Im rho_em, rho_et, rho_mt;
+        // antineutrinos: -rho^* (real parts and diagonal negated)
+        const double n0 = norm2(ps[0]), nm = norm2(ps[1]), nt = norm2(ps[2]);
+        const cplx em = cmul_conjb(ps[0], ps[1]), et = cmul_conjb(ps[0], ps[2]), mt = cmul_conjb(ps[1], ps[2]);
+        double v8[8] = {n0 - nt, nm - nt, em.re, em.im, et.re, et.im, mt.re, mt.im};
+        if (s) {
+          v8[0] = -v8[0]; v8[1] = -v8[1]; v8[2] = -v8[2]; v8[4] = -v8[4]; v8[6] = -v8[6];
+        }
+        const double w = G[k];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) S[i] = i128_add(S[i], i128_from(to_fix(w * v[i], a.s1, err)));
+        for (int i = 0; i < 8; ++i) acc[i] += to_fix(w * v8[i], a.s1, kTwo58, err);
+      }
+      fold_segment<8>(acc, lane, mine);
     }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) S[i] = wave_sum(S[i]);
-    if (lane < 16) {
-      const I128 sv = select_comp<8>(S, lane & 7);
-      if (lane < 8)
-        T = i128_add(T, i128_from(to_fix(icmom * (i128_to_double(sv) * a.p2e1), a.s0, err)));
-      else
-        T = i128_add(T, sv);
-    }
+    close_row<8>(a, lane, mine, icmom, T, err);
   }
 }
 
 // --------------------------------------------------------------- the stepper
-template <int NF, typename ST>
+// The energy tables (vacuum terms and weights) are staged into LDS once per launch
+// when TLDS (they are read by every row).
+template <int NF, typename ST, bool TLDS>
 __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   constexpr int NC = (NF == 2) ? 3 : 8;
   constexpr int NV = 2 * NC;
   __shared__ double sJ[4][NV];
   __shared__ I128 sw[kBlock / 64][NV];
   __shared__ I128 sred[kBlock];
+  __shared__ double snn_all[kBlock / 64][32];
+  extern __shared__ double dyn_tab[];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const long long gw = (long long)blockIdx.x * (kBlock / 64) + wid;
   const long long nw = (long long)gridDim.x * (kBlock / 64);
+  const double* tab = a.tab;
+  if constexpr (TLDS) {
+    const int ntab = ((NF == 2) ? 4 : 8) * a.NE;
+    for (int i = threadIdx.x; i < ntab; i += kBlock) dyn_tab[i] = a.tab[i];
+    __syncthreads();
+    tab = dyn_tab;
+  }
+  double* snn = snn_all[wid];
   unsigned epoch = 0;
   int err = 0;
   bool ok = true;
   I128 T = i128_zero();
-  if constexpr (NF == 2) stage2<0>(a, a.step0, sJ, gw, nw, lane, T, err);
-  else stage3<ST, 0>(a, a.step0, sJ, gw, nw, lane, T, err);
+  if constexpr (NF == 2) stage2<0>(a, a.step0, sJ, tab, gw, nw, lane, T, err);
+  else stage3<ST, 0>(a, a.step0, sJ, tab, snn, gw, nw, lane, T, err);
   ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[0], a.J);
   for (long long n = a.step0; ok && n < a.step0 + a.nsteps; ++n) {
     T = i128_zero();
-    if constexpr (NF == 2) stage2<1>(a, n, sJ, gw, nw, lane, T, err);
-    else stage3<ST, 1>(a, n, sJ, gw, nw, lane, T, err);
+    if constexpr (NF == 2) stage2<1>(a, n, sJ, tab, gw, nw, lane, T, err);
+    else stage3<ST, 1>(a, n, sJ, tab, snn, gw, nw, lane, T, err);
     if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[1], a.J + NV))) break;
     T = i128_zero();
-    if constexpr (NF == 2) stage2<2>(a, n, sJ, gw, nw, lane, T, err);
-    else stage3<ST, 2>(a, n, sJ, gw, nw, lane, T, err);
+    if constexpr (NF == 2) stage2<2>(a, n, sJ, tab, gw, nw, lane, T, err);
+    else stage3<ST, 2>(a, n, sJ, tab, snn, gw, nw, lane, T, err);
     if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[2], a.J + 2 * NV))) break;
     T = i128_zero();
-    if constexpr (NF == 2) stage2<3>(a, n, sJ, gw, nw, lane, T, err);
-    else stage3<ST, 3>(a, n, sJ, gw, nw, lane, T, err);
+    if constexpr (NF == 2) stage2<3>(a, n, sJ, tab, gw, nw, lane, T, err);
+    else stage3<ST, 3>(a, n, sJ, tab, snn, gw, nw, lane, T, err);
     if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[3], a.J + 3 * NV))) break;
     T = i128_zero();
-    if constexpr (NF == 2) stage2<4>(a, n, sJ, gw, nw, lane, T, err);
-    else stage3<ST, 4>(a, n, sJ, gw, nw, lane, T, err);
+    if constexpr (NF == 2) stage2<4>(a, n, sJ, tab, gw, nw, lane, T, err);
+    else stage3<ST, 4>(a, n, sJ, tab, snn, gw, nw, lane, T, err);
     ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[0], a.J);
   }
   if (err) __hip_atomic_fetch_or(a.sync + kSyncStatus, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template __global__ void k_advance<2, double>(StepArgs);
-template __global__ void k_advance<3, double>(StepArgs);
-template __global__ void k_advance<3, float>(StepArgs);
+template __global__ void k_advance<2, double, true>(StepArgs);
+template __global__ void k_advance<2, double, false>(StepArgs);
+template __global__ void k_advance<3, double, true>(StepArgs);
+template __global__ void k_advance<3, double, false>(StepArgs);
+template __global__ void k_advance<3, float, true>(StepArgs);
+template __global__ void k_advance<3, float, false>(StepArgs);
 
 // ----------------------------------------------------------------- small kernels
 __global__ void k_zero_sync(unsigned int* sync, int keep_status) {
-  const int i = threadIdx.x;
-  if (i < kSyncWords && !(keep_status && i == kSyncStatus)) sync[i] = 0u;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kSyncWords; i += gridDim.x * blockDim.x)
+    if (!(keep_status && i == kSyncStatus)) sync[i] = 0u;
 }
 
 // Initial flavour eigenstates (Sec. 3.4): 2f P = (0,0,1); 3f psi = (1,0,0).

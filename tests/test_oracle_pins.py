@@ -256,14 +256,18 @@ def test_factored_hamiltonian_equals_brute_pair_sum(oracle, nf):
 
 
 # ----------------------------------------------------- invariants, reductions
-@pytest.mark.parametrize("nf", [2, 3])
-def test_norm_conserved_without_renormalisation(oracle, nf):
+@pytest.mark.parametrize("nf,bound", [(2, 1e-13), (3, 2e-12)])
+def test_norm_conserved_without_renormalisation(oracle, nf, bound):
+    """Trace and purity of every beam over 1000 steps (4000 exponentials) with the
+    renormalisation switched off.  The 2x2 rotation is unitary to the last ulp; the 3x3
+    exponential takes its rotation angle on the eigen-plane from a separate unit vector,
+    so each application keeps |psi| to a few 1e-16 (the production path renormalises)."""
     d = workloads.small_params(n_flavor=nf, n_energy=7, n_u=3, n_steps=1000, renorm=0,
                                r_start_km=60.0, r_end_km=70.0)
     m = oracle.Model(d); m.run()
     x = m.get_state()
     nrm = np.sqrt(np.sum(x * x, axis=0))
-    assert np.max(np.abs(nrm - 1.0)) <= 1e-13
+    assert np.max(np.abs(nrm - 1.0)) <= bound
 
 
 def _tilted_nunu_only(oracle, steps, jac=True):
