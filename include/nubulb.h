@@ -105,6 +105,22 @@ int nb_read_pee(const nb_model *m, double *dev_out);
 int nb_get_state(const nb_model *m, double *dst, int on_device);
 int nb_set_state(nb_model *m, const double *src, int64_t step, int on_device);
 
+/* HIP graph of one stepping launch: nb_graph_capture records "advance n_steps from the
+ * device step counter" (n_steps >= 1) on the bound stream (which must not be the NULL
+ * stream) into a graph held by the model; nb_graph_launch replays it and checks the
+ * status word.  Every replay continues from where the previous one stopped and stops at
+ * r_end.  Rebinding, autotuning or destroying the model drops the graph.  Inside the graph
+ * the stepping kernel is an ordinary launch whose grid never exceeds the resident
+ * capacity measured at nb_bind. */
+int nb_graph_capture(nb_model *m, int64_t n_steps);
+int nb_graph_launch(nb_model *m);
+
+/* Autotuner: for each candidate launch shape (block count; for batches also the per-row
+ * overhead of the cost model that splits the rows among wavefronts) time trial_steps from
+ * the initial state with HIP events, keep the fastest, then reset the model.  *best_ms
+ * (may be NULL) receives the winning time.  Results never change the arithmetic. */
+int nb_autotune(nb_model *m, int32_t trial_steps, double *best_ms);
+
 /* Reverse-mode adjoint of the radial integration (2 flavours, FP64, single model).
  * Runs from the current state and step to r_end (keeping a checkpoint every ckpt_every
  * steps; 0 = the model's adjoint_ckpt), then back.  dev_dl_dpee[nb_n_beams]: cotangent

@@ -21,7 +21,7 @@ EXPORTS = [
     "nb_state_comps", "nb_pee_offsets", "nb_workspace_bytes", "nb_bind", "nb_reset",
     "nb_step", "nb_run", "nb_step_index", "nb_read_pee", "nb_get_state", "nb_set_state",
     "nb_adjoint", "nb_host_tables", "nb_last_error", "nb_test_sincos", "nb_test_sqrt_div",
-    "nb_test_exp3", "nb_test_rotate",
+    "nb_test_exp3", "nb_test_rotate", "nb_graph_capture", "nb_graph_launch", "nb_autotune",
 ]
 
 
@@ -82,6 +82,9 @@ def lib():
         L.nb_test_sqrt_div.argtypes = [vp, vp, i64, vp, vp, vp]
         L.nb_test_exp3.argtypes = [vp, vp, i64, vp, vp]
         L.nb_test_rotate.argtypes = [vp, vp, i64, vp, vp]
+        L.nb_graph_capture.argtypes = [vp, i64]
+        L.nb_graph_launch.argtypes = [vp]
+        L.nb_autotune.argtypes = [vp, C.c_int32, dp]
         _lib = L
     return _lib
 
@@ -121,17 +124,32 @@ def _stream_ptr(stream=None):
 
 
 class HostModel:
-    """A model created on the host only (parameter validation and tables; no device)."""
+    """A model (or, given a list of parameter dicts, a batch of two-flavour models)
+    created on the host only: parameter validation and tables, no device work."""
 
-    def __init__(self, d: dict, precision: int | None = None, adjoint_ckpt: int = 0):
-        self.d = dict(d)
-        self.params = make_params(d, precision, adjoint_ckpt)
+    def __init__(self, d, precision: int | None = None, adjoint_ckpt: int = 0):
         h = C.c_void_p()
-        _check(lib().nb_model_create(C.byref(self.params), C.byref(h)), "nb_model_create")
+        if isinstance(d, (list, tuple)):
+            self.ds = [dict(x) for x in d]
+            arr = (Params * len(d))(*[make_params(x, precision, adjoint_ckpt) for x in d])
+            self.params = arr
+            _check(lib().nb_batch_create(arr, len(d), C.byref(h)), "nb_batch_create")
+            d = d[0]
+        else:
+            self.ds = [dict(d)]
+            self.params = make_params(d, precision, adjoint_ckpt)
+            _check(lib().nb_model_create(C.byref(self.params), C.byref(h)), "nb_model_create")
+        self.d = dict(d)
         self.h = h
         self.nb = int(lib().nb_n_beams(h))
         self.nsc = int(lib().nb_state_comps(h))
         self.nf = int(d["n_flavor"])
+        self.n_models = int(lib().nb_n_models(h))
+
+    def offsets(self):
+        off = (C.c_int64 * (self.n_models + 1))()
+        _check(lib().nb_pee_offsets(self.h, off), "nb_pee_offsets")
+        return [int(x) for x in off]
 
     def __del__(self):
         if getattr(self, "h", None) is not None and _lib is not None:
@@ -197,6 +215,17 @@ class Model(HostModel):
         out = torch.empty(self.nsc, self.nb, dtype=torch.float64, device=self.ws.device)
         _check(lib().nb_get_state(self.h, C.c_void_p(out.data_ptr()), 1), "nb_get_state")
         return out
+
+    def graph_capture(self, n_steps: int):
+        _check(lib().nb_graph_capture(self.h, int(n_steps)), "nb_graph_capture")
+
+    def graph_launch(self):
+        _check(lib().nb_graph_launch(self.h), "nb_graph_launch")
+
+    def autotune(self, trial_steps: int = 10) -> float:
+        best = C.c_double()
+        _check(lib().nb_autotune(self.h, int(trial_steps), C.byref(best)), "nb_autotune")
+        return float(best.value)
 
     def set_state(self, x, step: int):
         torch = _torch()

@@ -17,7 +17,10 @@
 namespace nb {
 template <int NF, typename ST, bool TLDS>
 __global__ void k_advance(StepArgs a);
+__global__ void k_batch2(BatchArgs a);
 __global__ void k_zero_sync(unsigned int* sync, int keep_status);
+__global__ void k_zero_u64(unsigned long long* p, long long n);
+__global__ void k_set_step(long long* step_ctl, long long step);
 template <typename ST>
 __global__ void k_init(ST* X, long long nb, long long plane, int nsc);
 template <typename ST>
@@ -70,22 +73,38 @@ static double fd_spectrum(double E, double T) {  // normalised Fermi-Dirac, zero
 }
 
 // ---------------------------------------------------------------- the model
-struct nb_model {
+// One model (or, for a batch, one member): parameters and host tables.
+struct Sub {
   nb_params p{};
-  int nf = 2, nc = 3, nsc = 3, nmodels = 1;
-  long long NE = 0, NU = 0, nb = 0, plane = 0;
+  long long NE = 0, NU = 0, beam0 = 0, row0 = 0, tab0 = 0;
   double h = 0, lam0 = 0, kappa0 = 0, s1 = 0, s0 = 0, p2e1 = 0, p2e0 = 0;
-  int e1 = 0, e0 = 0;
-  std::vector<double> E, tab;        // tab: device table image
+  int e1 = 0, e0 = 0, nf = 2;
+  std::vector<double> E, tab;
+};
+
+struct nb_model {
+  nb_params p{};                     // the (first) model's parameters; the shared step grid
+  int nf = 2, nc = 3, nsc = 3, nmodels = 1;
+  bool batch = false;
+  long long nb = 0, plane = 0, rows = 0;
+  std::vector<Sub> subs;
+  std::vector<double> tab;           // concatenated device table image
   long long step = 0;
+  // tuning (autotuner results): block cap and the per-row overhead of the batch partition
+  int tune_blocks = 0;
+  double tune_row_cost = 1.0;
   // bound state
   char* ws = nullptr;
   size_t ws_bytes = 0;
   hipStream_t stream = nullptr;
-  int device = 0, cus = 0, max_blocks = 0;
+  int device = 0, cus = 0, max_blocks = 0, nblocks = 0;
   unsigned long long ticks_per_s = 0;
-  size_t off_X = 0, off_tab = 0, off_J = 0, off_part = 0, off_sync = 0, need = 0;
-  unsigned int* pinned = nullptr;
+  size_t off_X = 0, off_tab = 0, off_J = 0, off_part = 0, off_sync = 0, off_ctl = 0;
+  size_t off_models = 0, off_waves = 0, off_acc = 0, need = 0;
+  long long* pinned = nullptr;       // [0] status, [1] step (device read-back)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  long long graph_steps = 0;
 };
 
 static bool state_fp32(const nb_model* m) { return m->nf == 3 && m->p.precision == NB_FP32_STATE; }
@@ -118,9 +137,10 @@ static int validate(const nb_params* p) {
 // Host tables of one model (Sec. 2 / Sec. 3.2): bin midpoints, Fermi-Dirac spectra,
 // number luminosities N = L/<E>, weights g = kappa0 du dE (N_a f_a - N_x f_x), vacuum
 // Hamiltonians per energy, fixed-point scales.
-static void build_tables(nb_model* m) {
+static void build_tables(Sub* m) {
   const nb_params& p = m->p;
   const long long NE = m->NE;
+  m->nf = p.n_flavor;
   const double dE = (p.e_max_mev - p.e_min_mev) / (double)NE;
   const double du = 1.0 / (double)m->NU;
   m->h = (p.r_end_km - p.r_start_km) / (double)p.n_steps;
@@ -189,35 +209,93 @@ static void build_tables(nb_model* m) {
   m->p2e0 = std::ldexp(1.0, -m->e0);
 }
 
-extern "C" int nb_model_create(const nb_params* p, nb_model** out) {
-  if (!out) return fail(NB_EINVAL, "out is NULL");
-  *out = nullptr;
+static int make_sub(const nb_params* p, Sub* s) {
   int rc = validate(p);
   if (rc) return rc;
+  s->p = *p;
+  s->NE = p->n_energy;
+  s->NU = p->n_u;
+  build_tables(s);
+  return NB_OK;
+}
+
+static nb_model* new_model(const nb_params* p) {
   nb_model* m = new (std::nothrow) nb_model();
-  if (!m) return fail(NB_EINVAL, "out of host memory");
+  if (!m) return nullptr;
   m->p = *p;
   m->nf = p->n_flavor;
   m->nc = (m->nf == 2) ? 3 : 8;
   m->nsc = (m->nf == 2) ? 3 : 6;
-  m->NE = p->n_energy;
-  m->NU = p->n_u;
-  m->nb = 2LL * m->NE * m->NU;
+  return m;
+}
+
+static void finish_layout_host(nb_model* m) {
+  long long beam = 0, row = 0, t = 0;
+  m->tab.clear();
+  for (Sub& s : m->subs) {
+    s.beam0 = beam;
+    s.row0 = row;
+    s.tab0 = t;
+    beam += 2LL * s.NE * s.NU;
+    row += 2LL * s.NU;
+    t += (long long)s.tab.size();
+    m->tab.insert(m->tab.end(), s.tab.begin(), s.tab.end());
+  }
+  m->nb = beam;
+  m->rows = row;
   m->plane = (m->nb + 63) / 64 * 64;
-  build_tables(m);
+  m->nmodels = (int)m->subs.size();
+}
+
+extern "C" int nb_model_create(const nb_params* p, nb_model** out) {
+  if (!out) return fail(NB_EINVAL, "out is NULL");
+  *out = nullptr;
+  Sub s;
+  int rc = make_sub(p, &s);
+  if (rc) return rc;
+  nb_model* m = new_model(p);
+  if (!m) return fail(NB_EINVAL, "out of host memory");
+  m->subs.push_back(std::move(s));
+  finish_layout_host(m);
   *out = m;
   return NB_OK;
 }
 
 extern "C" int nb_batch_create(const nb_params* p, int32_t n_models, nb_model** out) {
-  if (out) *out = nullptr;
-  (void)p;
-  (void)n_models;
-  return fail(NB_EINVAL, "batched models are not available in this build");
+  if (!out) return fail(NB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!p || n_models < 1) return fail(NB_EINVAL, "need at least one model");
+  std::vector<Sub> subs((size_t)n_models);
+  for (int i = 0; i < n_models; ++i) {
+    const nb_params& q = p[i];
+    if (q.n_flavor != 2 || q.precision != NB_FP64)
+      return fail(NB_EINVAL, "batched models are two-flavour FP64 (model %d)", i);
+    if (q.n_steps != p[0].n_steps || q.r_start_km != p[0].r_start_km || q.r_end_km != p[0].r_end_km ||
+        q.r_nu_km != p[0].r_nu_km || q.ne_power != p[0].ne_power || q.renorm != p[0].renorm)
+      return fail(NB_EINVAL, "batched models must share the radial grid, R, ne_power and renorm (model %d)", i);
+    int rc = make_sub(&q, &subs[i]);
+    if (rc) return rc;
+  }
+  nb_model* m = new_model(p);
+  if (!m) return fail(NB_EINVAL, "out of host memory");
+  m->batch = true;
+  m->subs = std::move(subs);
+  finish_layout_host(m);
+  *out = m;
+  return NB_OK;
+}
+
+static void drop_graph(nb_model* m) {
+  if (m->graph_exec) (void)hipGraphExecDestroy(m->graph_exec);
+  if (m->graph) (void)hipGraphDestroy(m->graph);
+  m->graph_exec = nullptr;
+  m->graph = nullptr;
+  m->graph_steps = 0;
 }
 
 extern "C" void nb_model_destroy(nb_model* m) {
   if (!m) return;
+  drop_graph(m);
   if (m->pinned) (void)hipHostFree(m->pinned);
   delete m;
 }
@@ -229,16 +307,17 @@ extern "C" int64_t nb_step_index(const nb_model* m) { return m ? m->step : -1; }
 
 extern "C" int nb_pee_offsets(const nb_model* m, int64_t* off) {
   if (!m || !off) return fail(NB_EINVAL, "NULL argument");
-  off[0] = 0;
-  off[1] = m->nb;
+  for (int i = 0; i < m->nmodels; ++i) off[i] = m->subs[i].beam0;
+  off[m->nmodels] = m->nb;
   return NB_OK;
 }
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// Workspace layout: state planes | tables | stage moments | block partials | sync words.
+// Workspace: state planes | tables | stage moments | block partials | sync words | step
+// counter | (batches) model descriptors | wave row ranges | moment accumulators.
 struct Layout {
-  size_t X, tab, J, part, sync, need;
+  size_t X, tab, J, part, sync, ctl, models, waves, acc, need;
 };
 
 static Layout layout_of(const nb_model* m) {
@@ -255,6 +334,18 @@ static Layout layout_of(const nb_model* m) {
   o = align256(o + 16 * (size_t)kMaxBlocks * 2 * m->nc);
   L.sync = o;
   o = align256(o + sizeof(unsigned int) * kSyncWords);
+  L.ctl = o;
+  o = align256(o + 256);
+  L.models = o;
+  L.waves = o;
+  L.acc = o;
+  if (m->batch) {
+    o = align256(o + sizeof(BatchModel) * (size_t)m->nmodels);
+    L.waves = o;
+    o = align256(o + sizeof(long long) * ((size_t)kMaxBlocks * (kBlock / 64) + 1));
+    L.acc = o;
+    o = align256(o + sizeof(unsigned long long) * (size_t)kAccSets * m->nmodels * 6 * kAccLimbs);
+  }
   L.need = o;
   return L;
 }
@@ -265,10 +356,11 @@ extern "C" size_t nb_workspace_bytes(const nb_model* m) { return m ? layout_of(m
 static constexpr size_t kTabLdsMax = 64 * 1024;
 
 static size_t tab_bytes(const nb_model* m) { return sizeof(double) * m->tab.size(); }
-static bool tab_in_lds(const nb_model* m) { return tab_bytes(m) <= kTabLdsMax; }
+static bool tab_in_lds(const nb_model* m) { return !m->batch && tab_bytes(m) <= kTabLdsMax; }
 static size_t advance_dyn_lds(const nb_model* m) { return tab_in_lds(m) ? tab_bytes(m) : 0; }
 
 static const void* advance_kernel(const nb_model* m) {
+  if (m->batch) return (const void*)&k_batch2;
   const bool l = tab_in_lds(m);
   if (m->nf == 2) return l ? (const void*)&k_advance<2, double, true> : (const void*)&k_advance<2, double, false>;
   if (state_fp32(m)) return l ? (const void*)&k_advance<3, float, true> : (const void*)&k_advance<3, float, false>;
@@ -283,6 +375,19 @@ static int launch_1d(const void* fn, long long n, void** args, hipStream_t s) {
   return NB_OK;
 }
 
+static bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+  return st != hipStreamCaptureStatusNone;
+}
+
+static int set_device_step(nb_model* m, long long step) {
+  long long* ctl = (long long*)(m->ws + m->off_ctl);
+  void* args[] = {&ctl, &step};
+  NB_HIP(hipLaunchKernel((const void*)&k_set_step, dim3(1), dim3(1), args, 0, m->stream));
+  return NB_OK;
+}
+
 extern "C" int nb_reset(nb_model* m) {
   if (!m) return fail(NB_EINVAL, "model is NULL");
   if (!m->ws) return fail(NB_EUNBOUND, "no workspace bound");
@@ -293,7 +398,47 @@ extern "C" int nb_reset(nb_model* m) {
   int rc = launch_1d(state_fp32(m) ? (const void*)&k_init<float> : (const void*)&k_init<double>,
                      m->nb, args, m->stream);
   if (rc) return rc;
+  rc = set_device_step(m, 0);
+  if (rc) return rc;
   m->step = 0;
+  return NB_OK;
+}
+
+// Blocks of one stepping launch: at most one wavefront per row, at most the resident
+// capacity, at most the autotuned cap.
+static int launch_blocks(const nb_model* m) {
+  const int wpb = kBlock / 64;
+  long long want = (m->rows + wpb - 1) / wpb;
+  int nb_ = (int)std::min<long long>(want, m->max_blocks);
+  if (m->tune_blocks > 0) nb_ = std::min(nb_, m->tune_blocks);
+  return std::max(1, nb_);
+}
+
+// Contiguous row ranges per wavefront with balanced cost (64-lane chunks + row overhead).
+static int upload_partition(nb_model* m) {
+  const int waves = m->nblocks * (kBlock / 64);
+  std::vector<double> cost;
+  double total = 0.0;
+  for (const Sub& s : m->subs) {
+    const double c = (double)((s.NE + 63) / 64) + m->tune_row_cost;
+    total += c * 2.0 * (double)s.NU;
+  }
+  std::vector<long long> w0((size_t)waves + 1, m->rows);
+  long long row = 0;
+  double acc = 0.0;
+  int w = 0;
+  w0[0] = 0;
+  for (const Sub& s : m->subs) {
+    const double c = (double)((s.NE + 63) / 64) + m->tune_row_cost;
+    for (long long r = 0; r < 2LL * s.NU; ++r, ++row) {
+      while (w + 1 <= waves && acc >= total * (double)(w + 1) / (double)waves) w0[(size_t)(++w)] = row;
+      acc += c;
+    }
+  }
+  for (int i = w + 1; i <= waves; ++i) w0[(size_t)i] = m->rows;
+  NB_HIP(hipMemcpyAsync(m->ws + m->off_waves, w0.data(), sizeof(long long) * w0.size(),
+                        hipMemcpyHostToDevice, m->stream));
+  NB_HIP(hipStreamSynchronize(m->stream));
   return NB_OK;
 }
 
@@ -313,11 +458,16 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
   const Layout L = layout_of(m);
   if (bytes < L.need)
     return fail(NB_EWORKSPACE, "workspace too small: %zu < %zu bytes", bytes, L.need);
+  drop_graph(m);
   m->off_X = L.X;
   m->off_tab = L.tab;
   m->off_J = L.J;
   m->off_part = L.part;
   m->off_sync = L.sync;
+  m->off_ctl = L.ctl;
+  m->off_models = L.models;
+  m->off_waves = L.waves;
+  m->off_acc = L.acc;
   m->need = L.need;
   m->ws = (char*)dev_ws;
   m->ws_bytes = bytes;
@@ -325,31 +475,43 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
   m->device = dev;
   m->cus = cus;
   m->max_blocks = max_blocks;
+  m->nblocks = launch_blocks(m);
   m->ticks_per_s = (unsigned long long)(khz > 0 ? khz : 100000) * 1000ull;
   if (!m->pinned) NB_HIP(hipHostMalloc((void**)&m->pinned, 64, hipHostMallocDefault));
-  NB_HIP(hipMemcpyAsync(m->ws + m->off_tab, m->tab.data(), sizeof(double) * m->tab.size(),
-                        hipMemcpyHostToDevice, m->stream));
+  NB_HIP(hipMemcpyAsync(m->ws + m->off_tab, m->tab.data(), tab_bytes(m), hipMemcpyHostToDevice,
+                        m->stream));
+  if (m->batch) {
+    std::vector<BatchModel> md((size_t)m->nmodels);
+    for (int i = 0; i < m->nmodels; ++i) {
+      const Sub& s = m->subs[i];
+      md[i] = BatchModel{s.beam0, s.row0, s.tab0, (int)s.NE, (int)s.NU, s.lam0, s.s1, s.s0, s.p2e1, s.p2e0};
+    }
+    NB_HIP(hipMemcpyAsync(m->ws + m->off_models, md.data(), sizeof(BatchModel) * md.size(),
+                          hipMemcpyHostToDevice, m->stream));
+    NB_HIP(hipStreamSynchronize(m->stream));
+    int rc = upload_partition(m);
+    if (rc) return rc;
+  }
   unsigned int* sync = (unsigned int*)(m->ws + m->off_sync);
   int keep = 0;
   void* zargs[] = {&sync, &keep};
   NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(8), dim3(256), zargs, 0, m->stream));
+  NB_HIP(hipStreamSynchronize(m->stream));
   return nb_reset(m);
 }
 
-static bool capturing(hipStream_t s) {
-  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
-  return st != hipStreamCaptureStatusNone;
-}
-
-// Read and clear the kernels' status word (only outside graph capture).
+// Read and clear the kernels' status word and read back the device step counter (only
+// outside graph capture).
 static int check_status(nb_model* m) {
   if (capturing(m->stream)) return NB_OK;
   unsigned int* sync = (unsigned int*)(m->ws + m->off_sync);
   NB_HIP(hipMemcpyAsync(m->pinned, sync + kSyncStatus, sizeof(unsigned int), hipMemcpyDeviceToHost,
                         m->stream));
+  NB_HIP(hipMemcpyAsync(m->pinned + 1, m->ws + m->off_ctl, sizeof(long long), hipMemcpyDeviceToHost,
+                        m->stream));
   NB_HIP(hipStreamSynchronize(m->stream));
-  const unsigned st = m->pinned[0];
+  const unsigned st = (unsigned)(m->pinned[0] & 0xffffffffll);
+  m->step = m->pinned[1];
   if (st) {
     int keep = 0;
     void* zargs[] = {&sync, &keep};
@@ -361,48 +523,100 @@ static int check_status(nb_model* m) {
   return NB_OK;
 }
 
-static int advance(nb_model* m, long long n) {
-  const long long rows = 2LL * m->NU;
-  const int wpb = kBlock / 64;
-  const int want = (int)std::min<long long>((rows + wpb - 1) / wpb, m->max_blocks);
-  const int nblocks = std::max(1, want);
-  // bound the barrier epochs of one launch well inside 32 bits
-  const long long chunk = std::max<long long>(1, (long long)(3.5e9 / ((double)nblocks * 4.0)) - 2);
-  while (n > 0) {
-    const long long k = std::min(n, chunk);
-    StepArgs a{};
-    a.X = m->ws + m->off_X;
-    a.tab = (const double*)(m->ws + m->off_tab);
-    a.J = (double*)(m->ws + m->off_J);
-    a.part = (unsigned long long*)(m->ws + m->off_part);
-    a.sync = (unsigned int*)(m->ws + m->off_sync);
+// Largest step count of one launch: keeps the barrier epochs inside 32 bits.
+static long long launch_chunk(const nb_model* m) {
+  return std::max<long long>(1, (long long)(3.5e9 / ((double)m->nblocks * 4.0)) - 2);
+}
+
+// Enqueue one stepping launch of k steps (from the device step counter) on the stream.
+static int enqueue_advance(nb_model* m, long long k) {
+  unsigned int* sync = (unsigned int*)(m->ws + m->off_sync);
+  int keep = 1;
+  void* zargs[] = {&sync, &keep};
+  NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(8), dim3(256), zargs, 0, m->stream));
+  const unsigned long long timeout = m->ticks_per_s * 20ull;
+  if (m->batch) {
+    unsigned long long* acc = (unsigned long long*)(m->ws + m->off_acc);
+    long long nacc = (long long)kAccSets * m->nmodels * 6 * kAccLimbs;
+    void* zz[] = {&acc, &nacc};
+    NB_HIP(hipLaunchKernel((const void*)&k_zero_u64, dim3(64), dim3(256), zz, 0, m->stream));
+    BatchArgs a{};
+    a.X = (double*)(m->ws + m->off_X);
     a.plane = m->plane;
-    a.NE = (int)m->NE;
-    a.NU = (int)m->NU;
-    a.step0 = m->step;
+    a.tab = (const double*)(m->ws + m->off_tab);
+    a.models = (const BatchModel*)(m->ws + m->off_models);
+    a.nmodels = m->nmodels;
+    a.wave_row0 = (const long long*)(m->ws + m->off_waves);
+    a.total_rows = m->rows;
+    a.acc = acc;
+    a.sync = sync;
+    a.step_ctl = (long long*)(m->ws + m->off_ctl);
     a.nsteps = k;
+    a.total_steps = m->p.n_steps;
     a.rs = m->p.r_start_km;
-    a.h = m->h;
+    a.h = m->subs[0].h;
     a.R = m->p.r_nu_km;
-    a.lam0 = m->lam0;
     a.ne_power = m->p.ne_power;
     a.renorm = m->p.renorm;
-    a.s1 = m->s1;
-    a.s0 = m->s0;
-    a.p2e1 = m->p2e1;
-    a.p2e0 = m->p2e0;
-    a.timeout_ticks = m->ticks_per_s * 20ull;
-    unsigned int* sync = a.sync;
-    int keep = 1;
-    void* zargs[] = {&sync, &keep};
-    NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(8), dim3(256), zargs, 0, m->stream));
+    a.timeout_ticks = timeout;
     void* args[] = {&a};
-    NB_HIP(hipLaunchCooperativeKernel(advance_kernel(m), dim3(nblocks), dim3(kBlock), args,
-                                      (unsigned)advance_dyn_lds(m), m->stream));
-    m->step += k;
-    n -= k;
-    int rc = check_status(m);
+    // Inside graph capture the kernel node is an ordinary launch: the grid never exceeds
+    // the resident capacity measured at bind time, and every barrier wait is time-limited.
+    const hipError_t e =
+        capturing(m->stream)
+            ? hipLaunchKernel((const void*)&k_batch2, dim3(m->nblocks), dim3(kBlock), args, 0, m->stream)
+            : hipLaunchCooperativeKernel((const void*)&k_batch2, dim3(m->nblocks), dim3(kBlock), args, 0,
+                                         m->stream);
+    if (e != hipSuccess) return fail(NB_EHIP, "batch launch: %s", hipGetErrorString(e));
+    return NB_OK;
+  }
+  const Sub& s = m->subs[0];
+  StepArgs a{};
+  a.X = m->ws + m->off_X;
+  a.tab = (const double*)(m->ws + m->off_tab);
+  a.J = (double*)(m->ws + m->off_J);
+  a.part = (unsigned long long*)(m->ws + m->off_part);
+  a.sync = sync;
+  a.step_ctl = (long long*)(m->ws + m->off_ctl);
+  a.plane = m->plane;
+  a.NE = (int)s.NE;
+  a.NU = (int)s.NU;
+  a.nsteps = k;
+  a.total_steps = m->p.n_steps;
+  a.rs = m->p.r_start_km;
+  a.h = s.h;
+  a.R = m->p.r_nu_km;
+  a.lam0 = s.lam0;
+  a.ne_power = m->p.ne_power;
+  a.renorm = m->p.renorm;
+  a.s1 = s.s1;
+  a.s0 = s.s0;
+  a.p2e1 = s.p2e1;
+  a.p2e0 = s.p2e0;
+  a.timeout_ticks = timeout;
+  void* args[] = {&a};
+  const hipError_t e =
+      capturing(m->stream)
+          ? hipLaunchKernel(advance_kernel(m), dim3(m->nblocks), dim3(kBlock), args, advance_dyn_lds(m),
+                            m->stream)
+          : hipLaunchCooperativeKernel(advance_kernel(m), dim3(m->nblocks), dim3(kBlock), args,
+                                       (unsigned)advance_dyn_lds(m), m->stream);
+  if (e != hipSuccess) return fail(NB_EHIP, "stepping launch: %s", hipGetErrorString(e));
+  return NB_OK;
+}
+
+static int advance(nb_model* m, long long n) {
+  const long long chunk = launch_chunk(m);
+  while (n > 0) {
+    const long long k = std::min(n, chunk);
+    int rc = enqueue_advance(m, k);
     if (rc) return rc;
+    n -= k;
+    if (capturing(m->stream)) continue;
+    const long long before = m->step;
+    rc = check_status(m);
+    if (rc) return rc;
+    if (m->step != before + k) return fail(NB_EHIP, "device step counter out of step");
   }
   return NB_OK;
 }
@@ -419,6 +633,97 @@ extern "C" int nb_step(nb_model* m, int64_t n) {
 extern "C" int nb_run(nb_model* m) {
   if (!m) return fail(NB_EINVAL, "model is NULL");
   return nb_step(m, m->p.n_steps - m->step);
+}
+
+// ----------------------------------------------------------------- HIP graphs
+extern "C" int nb_graph_capture(nb_model* m, int64_t n_steps) {
+  if (!m) return fail(NB_EINVAL, "model is NULL");
+  if (!m->ws) return fail(NB_EUNBOUND, "no workspace bound");
+  if (n_steps < 1 || n_steps > launch_chunk(m)) return fail(NB_EINVAL, "bad step count for a graph");
+  if (!m->stream) return fail(NB_EINVAL, "graph capture needs a non-default stream");
+  drop_graph(m);
+  NB_HIP(hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal));
+  int rc = enqueue_advance(m, n_steps);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(m->stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(NB_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&m->graph_exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(NB_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  m->graph = g;
+  m->graph_steps = n_steps;
+  return NB_OK;
+}
+
+extern "C" int nb_graph_launch(nb_model* m) {
+  if (!m) return fail(NB_EINVAL, "model is NULL");
+  if (!m->graph_exec) return fail(NB_EINVAL, "no graph captured");
+  NB_HIP(hipGraphLaunch(m->graph_exec, m->stream));
+  return check_status(m);
+}
+
+// ------------------------------------------------------------------ autotuner
+// Times trial_steps from the initial state for each candidate launch shape (block cap;
+// for batches also the per-row overhead of the row partition), keeps the fastest and
+// resets the model.
+extern "C" int nb_autotune(nb_model* m, int32_t trial_steps, double* best_ms) {
+  if (!m) return fail(NB_EINVAL, "model is NULL");
+  if (!m->ws) return fail(NB_EUNBOUND, "no workspace bound");
+  if (trial_steps < 1) return fail(NB_EINVAL, "trial_steps must be >= 1");
+  drop_graph(m);
+  std::vector<std::pair<int, double>> cands;
+  const int full = launch_blocks(m);
+  std::vector<int> blocks = {full};
+  if (full >= 8) blocks.push_back(std::max(1, full * 3 / 4));
+  if (full >= 8) blocks.push_back(std::max(1, full / 2));
+  std::vector<double> costs = {m->tune_row_cost};
+  if (m->batch) costs = {0.25, 1.0, 3.0};
+  for (int b : blocks)
+    for (double c : costs) cands.push_back({b, c});
+  hipEvent_t e0, e1;
+  NB_HIP(hipEventCreate(&e0));
+  NB_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  std::pair<int, double> pick = cands[0];
+  int rc = NB_OK;
+  const long long steps = std::min<long long>(trial_steps, m->p.n_steps);
+  for (const auto& c : cands) {
+    m->nblocks = c.first;
+    m->tune_row_cost = c.second;
+    if (m->batch && (rc = upload_partition(m))) break;
+    if ((rc = nb_reset(m))) break;
+    if ((rc = nb_step(m, 1))) break;       // warm-up launch
+    if ((rc = nb_reset(m))) break;
+    NB_HIP(hipEventRecord(e0, m->stream));
+    if ((rc = nb_step(m, steps))) break;
+    NB_HIP(hipEventRecord(e1, m->stream));
+    NB_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    NB_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      pick = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  m->nblocks = pick.first;
+  m->tune_blocks = pick.first;
+  m->tune_row_cost = pick.second;
+  if (m->batch) {
+    int r2 = upload_partition(m);
+    if (!rc) rc = r2;
+  }
+  int r3 = nb_reset(m);
+  if (!rc) rc = r3;
+  if (best_ms) *best_ms = best;
+  return rc;
 }
 
 extern "C" int nb_read_pee(const nb_model* m, double* dev_out) {
@@ -484,6 +789,8 @@ extern "C" int nb_set_state(nb_model* m, const double* src, int64_t step, int on
     (void)hipFreeAsync(tmp, m->stream);
     if (rc) return rc;
   }
+  int rc = set_device_step(m, step);
+  if (rc) return rc;
   NB_HIP(hipStreamSynchronize(m->stream));
   m->step = step;
   return NB_OK;
@@ -499,23 +806,25 @@ extern "C" int nb_adjoint(nb_model* m, const double* dev_dl_dpee, double* grad_o
 
 extern "C" int nb_host_tables(const nb_model* m, double* out, int64_t cap) {
   if (!m || !out) return fail(NB_EINVAL, "NULL argument");
+  if (m->batch) return fail(NB_EINVAL, "host tables are reported for single models");
+  const Sub& s = m->subs[0];
   const int nv = (m->nf == 2) ? 2 : 6;
-  const long long NE = m->NE;
+  const long long NE = s.NE;
   const long long need = NE + 2 * NE + nv * NE + 7;
   if (cap < need) return fail(NB_EINVAL, "output too small (%lld needed)", need);
   long long o = 0;
-  for (long long k = 0; k < NE; ++k) out[o++] = m->E[k];
-  for (int s = 0; s < 2; ++s)
-    for (long long k = 0; k < NE; ++k) out[o++] = m->tab[(size_t)(nv + s) * NE + k];
+  for (long long k = 0; k < NE; ++k) out[o++] = s.E[k];
+  for (int sp = 0; sp < 2; ++sp)
+    for (long long k = 0; k < NE; ++k) out[o++] = s.tab[(size_t)(nv + sp) * NE + k];
   for (long long k = 0; k < NE; ++k)
-    for (int q = 0; q < nv; ++q) out[o++] = m->tab[(size_t)q * NE + k];
-  out[o++] = m->lam0;
-  out[o++] = m->kappa0;
-  out[o++] = m->h;
-  out[o++] = m->p2e1;
-  out[o++] = m->p2e0;
-  out[o++] = m->e1;
-  out[o++] = m->e0;
+    for (int q = 0; q < nv; ++q) out[o++] = s.tab[(size_t)q * NE + k];
+  out[o++] = s.lam0;
+  out[o++] = s.kappa0;
+  out[o++] = s.h;
+  out[o++] = s.p2e1;
+  out[o++] = s.p2e0;
+  out[o++] = s.e1;
+  out[o++] = s.e0;
   return NB_OK;
 }
 

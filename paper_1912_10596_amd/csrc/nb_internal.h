@@ -24,12 +24,44 @@ struct StepArgs {
   double* J;               // stage moments [4][2*NC]: J0 then J1 per slot
   unsigned long long* part;// block partials [gridDim][2*NC][2] (I128 halves)
   unsigned int* sync;      // kSyncWords words
+  long long* step_ctl;     // device step counter: read at launch start, advanced at the end
   long long plane;         // plane stride (elements)
   int NE, NU;
-  long long step0, nsteps;
+  long long nsteps, total_steps;  // requested steps (clamped to total_steps - start)
   double rs, h, R, lam0;
   int ne_power, renorm;
   double s1, s0, p2e1, p2e0;  // fixed-point scales 2^e1, 2^e0, 2^-e1, 2^-e0
+  unsigned long long timeout_ticks;
+};
+
+// One two-flavour model of a batch.
+struct BatchModel {
+  long long beam0;  // first beam of the model in the state planes
+  long long row0;   // first global row; the model owns rows [row0, row0 + 2 NU)
+  long long tab0;   // offset of its tables [bx|bz|G0|G1] x NE
+  int NE, NU;
+  double lam0;
+  double s1, s0, p2e1, p2e0;
+};
+
+constexpr int kAccSets = 6;   // moment accumulator sets, rotated by barrier epoch
+constexpr int kAccLimbs = 3;  // carry-save limbs of 42 bits per 128-bit sum
+
+// Arguments of the batched two-flavour stepping kernel.
+struct BatchArgs {
+  double* X;
+  long long plane;
+  const double* tab;
+  const BatchModel* models;
+  int nmodels;
+  const long long* wave_row0;   // [waves + 1]: each wavefront's contiguous row range
+  long long total_rows;
+  unsigned long long* acc;      // [kAccSets][nmodels][6][kAccLimbs]
+  unsigned int* sync;
+  long long* step_ctl;
+  long long nsteps, total_steps;
+  double rs, h, R;
+  int ne_power, renorm;
   unsigned long long timeout_ticks;
 };
 

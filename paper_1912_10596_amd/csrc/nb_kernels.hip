@@ -23,15 +23,18 @@ struct Radial {
   double q2, lam, mu;
 };
 
-__device__ __forceinline__ Radial radial_at(const StepArgs& a, double r) {
+__device__ __forceinline__ Radial radial(double R, int ne_power, double lam0, double r) {
   Radial g;
-  const double q = a.R / r;
+  const double q = R / r;
   g.q2 = q * q;
   double qp = 1.0;
-  for (int i = 0; i < a.ne_power; ++i) qp = qp * q;
-  g.lam = a.lam0 * qp;   // sqrt2 G_F n_e(r)
+  for (int i = 0; i < ne_power; ++i) qp = qp * q;
+  g.lam = lam0 * qp;     // sqrt2 G_F n_e(r)
   g.mu = 0.5 * g.q2;     // R^2 / 2r^2 from d cos(theta') = (R^2/2r^2) du / cos(theta')
   return g;
+}
+__device__ __forceinline__ Radial radial_at(const StepArgs& a, double r) {
+  return radial(a.R, a.ne_power, a.lam0, r);
 }
 
 __device__ __forceinline__ double as_double(unsigned long long u) { return __longlong_as_double((long long)u); }
@@ -144,22 +147,26 @@ __device__ bool finish_stage(const StepArgs& a, unsigned epoch, I128 T, I128 (*s
 }
 
 // ------------------------------------------------------------- row helpers
-// Geometry of one emission bin at the three stage radii of a step.
+// Fixed-point scales of one model: 2^e1, 2^e0, 2^-e1, 2^-e0.
+struct Scales {
+  double s1, s0, p2e1, p2e0;
+};
+// Geometry of one emission bin u at the three stage radii of a step.
 struct RowGeo {
   double c0, cm, c1, hc0, hcm, hc1;
 };
-__device__ __forceinline__ RowGeo row_geo(const StepArgs& a, int j, const Radial& g0,
-                                          const Radial& gm, const Radial& g1) {
+__device__ __forceinline__ RowGeo row_geo(double u, double h, const Radial& g0, const Radial& gm,
+                                          const Radial& g1) {
   RowGeo r;
-  const double u = ((double)j + 0.5) / (double)a.NU;
   r.c0 = sqrt(1.0 - u * g0.q2);
   r.cm = sqrt(1.0 - u * gm.q2);
   r.c1 = sqrt(1.0 - u * g1.q2);
-  r.hc0 = a.h / r.c0;
-  r.hcm = a.h / r.cm;
-  r.hc1 = a.h / r.c1;
+  r.hc0 = h / r.c0;
+  r.hcm = h / r.cm;
+  r.hc1 = h / r.c1;
   return r;
 }
+__device__ __forceinline__ double u_of(int j, int NU) { return ((double)j + 0.5) / (double)NU; }
 // The neutrino-neutrino term mu (J0 - c J1) of a row: the same for every energy bin.
 template <int NC>
 __device__ __forceinline__ void nunu(const double* J, double mu, double c, double* nn) {
@@ -178,10 +185,10 @@ __device__ __forceinline__ void fold_segment(const long long* acc, int lane, I12
 // End of a row: lanes v < NC add the J0 angle term (energy sum / cos), lanes
 // NC <= v < 2 NC the J1 energy sum, to their running totals.
 template <int NC>
-__device__ __forceinline__ void close_row(const StepArgs& a, int lane, const I128& mine,
+__device__ __forceinline__ void close_row(const Scales& sc, int lane, const I128& mine,
                                           double icmom, I128& T, int& err) {
   if (lane < NC)
-    T = i128_add(T, i128_from(to_fix(icmom * (i128_to_double(mine) * a.p2e1), a.s0, kTwo62, err)));
+    T = i128_add(T, i128_from(to_fix(icmom * (i128_to_double(mine) * sc.p2e1), sc.s0, kTwo62, err)));
   else if (lane < 2 * NC)
     T = i128_add(T, mine);
 }
@@ -206,10 +213,89 @@ __device__ __forceinline__ void gen2(int s, double bx, double bz, double lam, co
   f[2] = hc * B2;
 }
 
+// Stage stencil for one (species s, emission bin u) row of NE beams starting at beam rb.
 // KIND: 0 moments of rho_n at r_n; 1 stage Y2 (moments at r_n + h/2); 2 stage Y3
 // (r_n + h/2); 3 stage Y4 (r_{n+1}); 4 final update, store and moments at r_{n+1}.
-// A lane adds the fixed-point contributions of up to 32 of its beams of a row in 64-bit
-// integers (each below 2^58) before they are folded into exact 128-bit wave sums.
+// J[i]: stage moments J^(i+1) (J0 | J1, 6 doubles).  A lane adds the fixed-point
+// contributions of up to 32 of its beams in 64-bit integers (each below 2^58) before they
+// are folded into exact 128-bit wave sums.
+template <int KIND>
+__device__ __forceinline__ void row2(double* X, long long plane, long long rb, int NE, int s,
+                                     double u, double h, const double* tab, const Radial& g0,
+                                     const Radial& gm, const Radial& g1, const double* const* J,
+                                     const Scales& sc, int renorm, int lane, I128& T, int& err) {
+  const RowGeo rg = row_geo(u, h, g0, gm, g1);
+  const double icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
+  double n1[3], n2[3], n3[3], n4[3];
+  if (KIND == 1 || KIND == 2 || KIND == 4) nunu<3>(J[0], g0.mu, rg.c0, n1);
+  if (KIND == 2 || KIND == 4) nunu<3>(J[1], gm.mu, rg.cm, n2);
+  if (KIND >= 3) nunu<3>(J[2], gm.mu, rg.cm, n3);
+  if (KIND == 4) nunu<3>(J[3], g1.mu, rg.c1, n4);
+  const double* G = tab + (size_t)(2 + s) * NE;
+  I128 mine = i128_zero();
+  for (int k0 = lane; k0 - lane < NE; k0 += 64 * 32) {
+    const int kend = min(NE, k0 + 64 * 32);
+    long long acc[3] = {0, 0, 0};
+    double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+    if (k0 < kend) {
+      q0 = X[rb + k0]; q1 = X[rb + k0 + plane]; q2 = X[rb + k0 + 2 * plane];
+    }
+    for (int k = k0; k < kend; k += 64) {
+      double P0 = q0, P1 = q1, P2 = q2;
+      if (k + 64 < kend) {    // prefetch the lane's next beam
+        q0 = X[rb + k + 64]; q1 = X[rb + k + 64 + plane]; q2 = X[rb + k + 64 + 2 * plane];
+      }
+      if (KIND >= 1) {
+        const double bx = tab[k], bz = tab[NE + k];
+        double f1[3], f2[3], f3[3], f4[3];
+        if (KIND != 3) gen2(s, bx, bz, g0.lam, n1, rg.hc0, f1);
+        if (KIND == 1) {
+          rotate2(0.5 * f1[0], 0.5 * f1[1], 0.5 * f1[2], P0, P1, P2);
+        } else if (KIND == 2) {
+          gen2(s, bx, bz, gm.lam, n2, rg.hcm, f2);
+          const double cr0 = f1[1] * f2[2] - f1[2] * f2[1];
+          const double cr1 = f1[2] * f2[0] - f1[0] * f2[2];
+          const double cr2 = f1[0] * f2[1] - f1[1] * f2[0];
+          rotate2(0.5 * f2[0] - 0.125 * cr0, 0.5 * f2[1] - 0.125 * cr1, 0.5 * f2[2] - 0.125 * cr2,
+                  P0, P1, P2);
+        } else if (KIND == 3) {
+          gen2(s, bx, bz, gm.lam, n3, rg.hcm, f3);
+          rotate2(f3[0], f3[1], f3[2], P0, P1, P2);
+        } else {
+          gen2(s, bx, bz, gm.lam, n2, rg.hcm, f2);
+          gen2(s, bx, bz, gm.lam, n3, rg.hcm, f3);
+          gen2(s, bx, bz, g1.lam, n4, rg.hc1, f4);
+          const double cr0 = f1[1] * f4[2] - f1[2] * f4[1];
+          const double cr1 = f1[2] * f4[0] - f1[0] * f4[2];
+          const double cr2 = f1[0] * f4[1] - f1[1] * f4[0];
+          const double t0 = (((f1[0] + 2.0 * f2[0]) + 2.0 * f3[0]) + f4[0]) * (1.0 / 6.0) - cr0 * (1.0 / 12.0);
+          const double t1 = (((f1[1] + 2.0 * f2[1]) + 2.0 * f3[1]) + f4[1]) * (1.0 / 6.0) - cr1 * (1.0 / 12.0);
+          const double t2 = (((f1[2] + 2.0 * f2[2]) + 2.0 * f3[2]) + f4[2]) * (1.0 / 6.0) - cr2 * (1.0 / 12.0);
+          rotate2(t0, t1, t2, P0, P1, P2);
+          if (renorm) {
+            const double nrm2 = (P0 * P0 + P1 * P1) + P2 * P2;
+            const double inv = 1.0 / sqrt(nrm2);
+            P0 = P0 * inv;
+            P1 = P1 * inv;
+            P2 = P2 * inv;
+          }
+          X[rb + k] = P0;
+          X[rb + k + plane] = P1;
+          X[rb + k + 2 * plane] = P2;
+        }
+      }
+      // rho~: rho for neutrinos, -rho^* (Bloch (-x, y, -z)) for antineutrinos
+      const double w = G[k];
+      const double v0 = s ? -P0 : P0, v2 = s ? -P2 : P2;
+      acc[0] += to_fix(w * v0, sc.s1, kTwo58, err);
+      acc[1] += to_fix(w * P1, sc.s1, kTwo58, err);
+      acc[2] += to_fix(w * v2, sc.s1, kTwo58, err);
+    }
+    fold_segment<3>(acc, lane, mine);
+  }
+  close_row<3>(sc, lane, mine, icmom, T, err);
+}
+
 template <int KIND>
 __device__ __forceinline__ void stage2(const StepArgs& a, long long n, const double (*sJ)[6],
                                        const double* tab, long long gw, long long nw, int lane,
@@ -218,83 +304,14 @@ __device__ __forceinline__ void stage2(const StepArgs& a, long long n, const dou
   const double rm = r0 + 0.5 * a.h;
   const double r1 = a.rs + (double)(n + 1) * a.h;
   const Radial g0 = radial_at(a, r0), gm = radial_at(a, rm), g1 = radial_at(a, r1);
-  const long long nrow = 2LL * a.NU, plane = a.plane;
-  const int NE = a.NE;
-  double* X = (double*)a.X;
+  const Scales sc{a.s1, a.s0, a.p2e1, a.p2e0};
+  const double* J[4] = {sJ[0], sJ[1], sJ[2], sJ[3]};
+  const long long nrow = 2LL * a.NU;
   for (long long row = gw; row < nrow; row += nw) {
     const int s = (int)(row / a.NU);
     const int j = (int)(row - (long long)s * a.NU);
-    const RowGeo rg = row_geo(a, j, g0, gm, g1);
-    const double icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
-    double n1[3], n2[3], n3[3], n4[3];
-    if (KIND == 1 || KIND == 2 || KIND == 4) nunu<3>(sJ[0], g0.mu, rg.c0, n1);
-    if (KIND == 2 || KIND == 4) nunu<3>(sJ[1], gm.mu, rg.cm, n2);
-    if (KIND >= 3) nunu<3>(sJ[2], gm.mu, rg.cm, n3);
-    if (KIND == 4) nunu<3>(sJ[3], g1.mu, rg.c1, n4);
-    const double* G = tab + (size_t)(2 + s) * NE;
-    const long long rb = row * NE;
-    I128 mine = i128_zero();
-    for (int k0 = lane; k0 - lane < NE; k0 += 64 * 32) {
-      const int kend = min(NE, k0 + 64 * 32);
-      long long acc[3] = {0, 0, 0};
-      double q0 = 0.0, q1 = 0.0, q2 = 0.0;
-      if (k0 < kend) {
-        q0 = X[rb + k0]; q1 = X[rb + k0 + plane]; q2 = X[rb + k0 + 2 * plane];
-      }
-      for (int k = k0; k < kend; k += 64) {
-        double P0 = q0, P1 = q1, P2 = q2;
-        if (k + 64 < kend) {    // prefetch the lane's next beam
-          q0 = X[rb + k + 64]; q1 = X[rb + k + 64 + plane]; q2 = X[rb + k + 64 + 2 * plane];
-        }
-        if (KIND >= 1) {
-          const double bx = tab[k], bz = tab[NE + k];
-          double f1[3], f2[3], f3[3], f4[3];
-          if (KIND != 3) gen2(s, bx, bz, g0.lam, n1, rg.hc0, f1);
-          if (KIND == 1) {
-            rotate2(0.5 * f1[0], 0.5 * f1[1], 0.5 * f1[2], P0, P1, P2);
-          } else if (KIND == 2) {
-            gen2(s, bx, bz, gm.lam, n2, rg.hcm, f2);
-            const double cr0 = f1[1] * f2[2] - f1[2] * f2[1];
-            const double cr1 = f1[2] * f2[0] - f1[0] * f2[2];
-            const double cr2 = f1[0] * f2[1] - f1[1] * f2[0];
-            rotate2(0.5 * f2[0] - 0.125 * cr0, 0.5 * f2[1] - 0.125 * cr1, 0.5 * f2[2] - 0.125 * cr2,
-                    P0, P1, P2);
-          } else if (KIND == 3) {
-            gen2(s, bx, bz, gm.lam, n3, rg.hcm, f3);
-            rotate2(f3[0], f3[1], f3[2], P0, P1, P2);
-          } else {
-            gen2(s, bx, bz, gm.lam, n2, rg.hcm, f2);
-            gen2(s, bx, bz, gm.lam, n3, rg.hcm, f3);
-            gen2(s, bx, bz, g1.lam, n4, rg.hc1, f4);
-            const double cr0 = f1[1] * f4[2] - f1[2] * f4[1];
-            const double cr1 = f1[2] * f4[0] - f1[0] * f4[2];
-            const double cr2 = f1[0] * f4[1] - f1[1] * f4[0];
-            const double t0 = (((f1[0] + 2.0 * f2[0]) + 2.0 * f3[0]) + f4[0]) * (1.0 / 6.0) - cr0 * (1.0 / 12.0);
-            const double t1 = (((f1[1] + 2.0 * f2[1]) + 2.0 * f3[1]) + f4[1]) * (1.0 / 6.0) - cr1 * (1.0 / 12.0);
-            const double t2 = (((f1[2] + 2.0 * f2[2]) + 2.0 * f3[2]) + f4[2]) * (1.0 / 6.0) - cr2 * (1.0 / 12.0);
-            rotate2(t0, t1, t2, P0, P1, P2);
-            if (a.renorm) {
-              const double nrm2 = (P0 * P0 + P1 * P1) + P2 * P2;
-              const double inv = 1.0 / sqrt(nrm2);
-              P0 = P0 * inv;
-              P1 = P1 * inv;
-              P2 = P2 * inv;
-            }
-            X[rb + k] = P0;
-            X[rb + k + plane] = P1;
-            X[rb + k + 2 * plane] = P2;
-          }
-        }
-        // rho~: rho for neutrinos, -rho^* (Bloch (-x, y, -z)) for antineutrinos
-        const double w = G[k];
-        const double v0 = s ? -P0 : P0, v2 = s ? -P2 : P2;
-        acc[0] += to_fix(w * v0, a.s1, kTwo58, err);
-        acc[1] += to_fix(w * P1, a.s1, kTwo58, err);
-        acc[2] += to_fix(w * v2, a.s1, kTwo58, err);
-      }
-      fold_segment<3>(acc, lane, mine);
-    }
-    close_row<3>(a, lane, mine, icmom, T, err);
+    row2<KIND>((double*)a.X, a.plane, row * a.NE, a.NE, s, u_of(j, a.NU), a.h, tab, g0, gm, g1,
+               J, sc, a.renorm, lane, T, err);
   }
 }
 
@@ -338,7 +355,7 @@ __device__ __forceinline__ void stage3(const StepArgs& a, long long n, const dou
   for (long long row = gw; row < nrow; row += nw) {
     const int s = (int)(row / a.NU);
     const int j = (int)(row - (long long)s * a.NU);
-    const RowGeo rg = row_geo(a, j, g0, gm, g1);
+    const RowGeo rg = row_geo(u_of(j, a.NU), a.h, g0, gm, g1);
     const double icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
     {
       double t[8];
@@ -448,7 +465,7 @@ __device__ __forceinline__ void stage3(const StepArgs& a, long long n, const dou
       }
       fold_segment<8>(acc, lane, mine);
     }
-    close_row<8>(a, lane, mine, icmom, T, err);
+    close_row<8>(Scales{a.s1, a.s0, a.p2e1, a.p2e0}, lane, mine, icmom, T, err);
   }
 }
 
@@ -475,14 +492,16 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
     tab = dyn_tab;
   }
   double* snn = snn_all[wid];
+  const long long step0 = *a.step_ctl;
+  const long long nsteps = max(0LL, min(a.nsteps, a.total_steps - step0));
   unsigned epoch = 0;
   int err = 0;
   bool ok = true;
   I128 T = i128_zero();
-  if constexpr (NF == 2) stage2<0>(a, a.step0, sJ, tab, gw, nw, lane, T, err);
-  else stage3<ST, 0>(a, a.step0, sJ, tab, snn, gw, nw, lane, T, err);
+  if constexpr (NF == 2) stage2<0>(a, step0, sJ, tab, gw, nw, lane, T, err);
+  else stage3<ST, 0>(a, step0, sJ, tab, snn, gw, nw, lane, T, err);
   ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[0], a.J);
-  for (long long n = a.step0; ok && n < a.step0 + a.nsteps; ++n) {
+  for (long long n = step0; ok && n < step0 + nsteps; ++n) {
     T = i128_zero();
     if constexpr (NF == 2) stage2<1>(a, n, sJ, tab, gw, nw, lane, T, err);
     else stage3<ST, 1>(a, n, sJ, tab, snn, gw, nw, lane, T, err);
@@ -501,6 +520,8 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
     ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[0], a.J);
   }
   if (err) __hip_atomic_fetch_or(a.sync + kSyncStatus, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // every block read the start step before the first barrier; block 0 passes the last
+  if (ok && blockIdx.x == 0 && threadIdx.x == 0) *a.step_ctl = step0 + nsteps;
 }
 
 template __global__ void k_advance<2, double, true>(StepArgs);
@@ -510,7 +531,166 @@ template __global__ void k_advance<3, double, false>(StepArgs);
 template __global__ void k_advance<3, float, true>(StepArgs);
 template __global__ void k_advance<3, float, false>(StepArgs);
 
+// --------------------------------------------------------------- batched models
+// Many independent two-flavour models in one persistent launch (shared step grid).
+// Each wavefront owns a contiguous, cost-balanced range of the concatenated rows, so it
+// meets only a few models per stage.  Its per-model moment totals are added, as three
+// 42-bit limbs, to per-model integer accumulators with device atomics (exact, so the
+// result is the same integer as the single-model reduction); a reader rebuilds the
+// 128-bit sum from the limbs.  Accumulator sets rotate with the barrier epoch: set e % 6
+// collects epoch e, and set (e + 1) % 6 -- last read during epoch e - 1 -- is cleared
+// during epoch e.
+constexpr unsigned long long kMask42 = (1ull << 42) - 1ull;
+
+__device__ __forceinline__ void acc_add(unsigned long long* slot, const I128& v) {
+  const unsigned long long l0 = v.lo & kMask42;
+  const unsigned long long l1 = ((v.lo >> 42) | ((unsigned long long)v.hi << 22)) & kMask42;
+  const unsigned long long l2 = (unsigned long long)(v.hi >> 20);
+  __hip_atomic_fetch_add(slot + 0, l0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_add(slot + 1, l1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_add(slot + 2, l2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ I128 acc_read(const unsigned long long* slot) {
+  const unsigned long long s0 = __hip_atomic_load(slot + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned long long s1 = __hip_atomic_load(slot + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const long long s2 = (long long)__hip_atomic_load(slot + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  I128 t = I128{s0, 0ll};
+  t = i128_add(t, I128{s1 << 42, (long long)(s1 >> 22)});
+  t = i128_add(t, I128{0ull, s2 << 20});
+  return t;
+}
+__device__ __forceinline__ unsigned long long* acc_slot(const BatchArgs& a, unsigned epoch, int m) {
+  return a.acc + ((size_t)(epoch % kAccSets) * a.nmodels + m) * 6 * kAccLimbs;
+}
+
+// Flags-only grid barrier (the sums are already in the accumulators).
+__device__ bool grid_barrier(const BatchArgs& a, unsigned epoch) {
+  __shared__ int s_ok;
+  const unsigned want = epoch + 1u;
+  __threadfence();   // every wave's accumulator atomics complete before the arrival
+  __syncthreads();
+  StepArgs sa{};
+  sa.sync = a.sync;
+  sa.timeout_ticks = a.timeout_ticks;
+  if (blockIdx.x != 0) {
+    if (threadIdx.x == 0) {
+      __hip_atomic_store(a.sync + kSyncArrive + blockIdx.x, want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      s_ok = spin_until(sa, a.sync + kSyncFlag, want) ? 1 : 0;
+    }
+    __syncthreads();
+    return s_ok != 0;
+  }
+  int ok = 1;
+  for (unsigned b = 1 + threadIdx.x; b < gridDim.x && ok; b += kBlock)
+    ok = spin_until(sa, a.sync + kSyncArrive + b, want) ? 1 : 0;
+  if (__syncthreads_or(!ok)) return false;
+  if (threadIdx.x == 0)
+    __hip_atomic_store(a.sync + kSyncFlag, want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  return true;
+}
+
+template <int KIND>
+__device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, long long r0w,
+                            long long r1w, int lane, double (*Jv)[6], int& err) {
+  const double r0 = a.rs + (double)n * a.h;
+  const double rm = r0 + 0.5 * a.h;
+  const double r1 = a.rs + (double)(n + 1) * a.h;
+  // epoch of the slot holding J^(i+1) of this step: epoch - KIND + i
+  int m = -1;
+  long long mrow0 = 0, mrow1 = 0, mbeam0 = 0, mtab0 = 0;
+  int mNE = 0, mNU = 1;
+  Radial g0{}, gm{}, g1{};
+  Scales sc{};
+  const double* J[4] = {Jv[0], Jv[1], Jv[2], Jv[3]};   // this wave's LDS block
+  I128 T = i128_zero();
+  for (long long row = r0w; row < r1w; ++row) {
+    if (m < 0 || row >= mrow1) {
+      if (m >= 0 && lane < 6) acc_add(acc_slot(a, epoch, m) + lane * kAccLimbs, T);
+      T = i128_zero();
+      if (m < 0) {                      // first model of the range: binary search
+        int lo = 0, hi = a.nmodels - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (a.models[mid].row0 <= row) lo = mid; else hi = mid - 1;
+        }
+        m = lo;
+      } else {
+        while (row >= a.models[m].row0 + 2LL * a.models[m].NU) ++m;
+      }
+      const BatchModel* md = a.models + m;
+      mrow0 = md->row0;
+      mNE = md->NE;
+      mNU = md->NU;
+      mrow1 = mrow0 + 2LL * mNU;
+      mbeam0 = md->beam0;
+      mtab0 = md->tab0;
+      const double lam0 = md->lam0;
+      g0 = radial(a.R, a.ne_power, lam0, r0);
+      gm = radial(a.R, a.ne_power, lam0, rm);
+      g1 = radial(a.R, a.ne_power, lam0, r1);
+      sc = Scales{md->s1, md->s0, md->p2e1, md->p2e0};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const bool need = (i == 0) ? (KIND == 1 || KIND == 2 || KIND == 4)
+                                   : (i == 1 ? (KIND == 2 || KIND == 4) : (i == 2 ? KIND >= 3 : KIND == 4));
+        if (!need) continue;
+        const unsigned long long* sl = acc_slot(a, epoch - (unsigned)KIND + (unsigned)i, m);
+#pragma unroll
+        for (int v = 0; v < 6; ++v)
+          Jv[i][v] = i128_to_double(acc_read(sl + v * kAccLimbs)) * (v < 3 ? sc.p2e0 : sc.p2e1);
+      }
+    }
+    const long long lr = row - mrow0;
+    const int s = (int)(lr / mNU);
+    const int j = (int)(lr - (long long)s * mNU);
+    row2<KIND>(a.X, a.plane, mbeam0 + lr * mNE, mNE, s, u_of(j, mNU), a.h, a.tab + mtab0,
+               g0, gm, g1, J, sc, a.renorm, lane, T, err);
+  }
+  if (m >= 0 && lane < 6) acc_add(acc_slot(a, epoch, m) + lane * kAccLimbs, T);
+  // clear the set the next epoch will collect into
+  if (blockIdx.x == 0) {
+    unsigned long long* z = a.acc + (size_t)((epoch + 1u) % kAccSets) * a.nmodels * 6 * kAccLimbs;
+    for (int i = threadIdx.x; i < a.nmodels * 6 * kAccLimbs; i += kBlock)
+      __hip_atomic_store(z + i, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_batch2(BatchArgs a) {
+  __shared__ double sJw[kBlock / 64][4][6];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double (*Jv)[6] = sJw[wid];
+  const long long w = (long long)blockIdx.x * (kBlock / 64) + wid;
+  const long long r0w = min(max(a.wave_row0[w], 0LL), a.total_rows);
+  const long long r1w = min(max(a.wave_row0[w + 1], r0w), a.total_rows);
+  const long long step0 = *a.step_ctl;
+  const long long nsteps = max(0LL, min(a.nsteps, a.total_steps - step0));
+  unsigned epoch = 0;
+  int err = 0;
+  bool ok;
+  batch_stage<0>(a, step0, epoch, r0w, r1w, lane, Jv, err);
+  ok = grid_barrier(a, epoch++);
+  for (long long n = step0; ok && n < step0 + nsteps; ++n) {
+    batch_stage<1>(a, n, epoch, r0w, r1w, lane, Jv, err);
+    if (!(ok = grid_barrier(a, epoch++))) break;
+    batch_stage<2>(a, n, epoch, r0w, r1w, lane, Jv, err);
+    if (!(ok = grid_barrier(a, epoch++))) break;
+    batch_stage<3>(a, n, epoch, r0w, r1w, lane, Jv, err);
+    if (!(ok = grid_barrier(a, epoch++))) break;
+    batch_stage<4>(a, n, epoch, r0w, r1w, lane, Jv, err);
+    ok = grid_barrier(a, epoch++);
+  }
+  if (err) __hip_atomic_fetch_or(a.sync + kSyncStatus, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (ok && blockIdx.x == 0 && threadIdx.x == 0) *a.step_ctl = step0 + nsteps;
+}
+
 // ----------------------------------------------------------------- small kernels
+__global__ void k_zero_u64(unsigned long long* p, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+__global__ void k_set_step(long long* step_ctl, long long step) { *step_ctl = step; }
+
 __global__ void k_zero_sync(unsigned int* sync, int keep_status) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kSyncWords; i += gridDim.x * blockDim.x)
     if (!(keep_status && i == kSyncStatus)) sync[i] = 0u;
