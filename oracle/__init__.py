@@ -65,7 +65,7 @@ def lib():
         L.nbo_fixed_sum.argtypes = [dp, C.c_int64, C.c_int]
         L.nbo_fixed_sum.restype = C.c_double
         L.nbo_single_angle_run.argtypes = [C.POINTER(Params), dp]
-        L.nbo_adjoint.argtypes = [vp, C.c_int32, dp, dp]
+        L.nbo_adjoint.argtypes = [vp, C.c_int32, vp, dp, dp, vp]
         _lib = L
     return _lib
 
@@ -180,10 +180,21 @@ class Model:
         _check(lib().nbo_cos_theta(self.h, float(r), _dp(out)), "nbo_cos_theta")
         return out
 
-    def adjoint(self, ckpt: int = 64):
+    def adjoint(self, ckpt: int = 64, dl_dpee=None, want_state_bar: bool = False):
+        """Reverse-mode gradients of L = sum_b dl_dpee[b] Pee_b at r_end (default weights
+        dE/N_u) with respect to (L_e, L_ebar, L_x, theta_v, n0).  Returns (L, grad) or
+        (L, grad, state_bar) with state_bar = dL/d(initial state) as planes [3][nb]."""
         g = np.empty(5, np.float64)
         loss = C.c_double()
-        _check(lib().nbo_adjoint(self.h, int(ckpt), _dp(g), C.byref(loss)), "nbo_adjoint")
+        c = None
+        if dl_dpee is not None:
+            c = np.ascontiguousarray(dl_dpee, dtype=np.float64).reshape(-1)
+            assert c.size == self.nb
+        sb = np.empty((self.nb, 3), np.float64) if want_state_bar else None
+        _check(lib().nbo_adjoint(self.h, int(ckpt), None if c is None else _dp(c), _dp(g),
+                                 C.byref(loss), None if sb is None else _dp(sb)), "nbo_adjoint")
+        if want_state_bar:
+            return float(loss.value), g, np.ascontiguousarray(sb.T)
         return float(loss.value), g
 
 

@@ -32,6 +32,9 @@
  * the factored H_nunu against the direct beam-pair sum of Eq. Hnu, norm conservation,
  * the flux-weighted polarisation invariant, single-angle = one angle bin, two tracked
  * species = every flavour explicit, 4th-order convergence, plain RK4 agreement.
+ * Adjoint pins (tests/test_oracle_adjoint.py): central differences of the forward
+ * integration for all five parameters and for the initial state, the closed-form vacuum
+ * derivative in theta_v, linearity in the cotangent, checkpoint-period independence.
  * The full nonlinear bulb evolution at benchmark scale has no external reference (the
  * paper's result is a figure without data): parity unpinned beyond its parts.
  *
@@ -952,7 +955,301 @@ int nbo_single_angle_run(const nbo_params *pin, double *pee_out) {
   return err ? NBO_ENUMERIC : NBO_OK;
 }
 
-int nbo_adjoint(nbo_model *m, int32_t ckpt, double *grad, double *loss) {
-  (void)m; (void)ckpt; (void)grad; (void)loss;
-  return NBO_EINVAL;
+/* ------------------------------------------------------------------- adjoint */
+/* Reverse mode of the two-flavour RKMK4 integration.  The moment sums are treated as the
+ * exact sums they represent (the fixed-point truncation is below 2^-58 of the largest
+ * term).  Notation of the forward step (file header): f_i = (h/c_i) B(r_i, J^(i)),
+ * Y2 = R(f1/2)P, Y3 = R(Om3)P with Om3 = f2/2 - f1 x f2/8, Y4 = R(f3)P,
+ * Theta = (f1 + 2f2 + 2f3 + f4)/6 - f1 x f4/12, P' = R(Theta)P, P_{n+1} = P'/|P'|.
+ * For a rotation y = R(x)p: p-bar = R(-x) y-bar and x-bar = Jl(x)^T (y x y-bar), with the
+ * left Jacobian of SO(3), Jl(x) = I + a [x]x + b [x]x^2, a = (1-cos t)/t^2,
+ * b = (t - sin t)/t^3, t = |x|.  The parameters enter through the weights g (the three
+ * luminosities), the vacuum term (theta_v) and lambda(r) (n0). */
+
+static void jlt(const double x[3], const double v[3], double out[3]) {
+  const double t2 = (x[0] * x[0] + x[1] * x[1]) + x[2] * x[2];
+  const double t = sqrt(t2);
+  double a, b;
+  if (t < 0.05) {
+    a = 0.5 - t2 / 24.0 + t2 * t2 / 720.0;
+    b = 1.0 / 6.0 - t2 / 120.0 + t2 * t2 / 5040.0;
+  } else {
+    const double sh = sin(0.5 * t);
+    a = 2.0 * sh * sh / t2;
+    b = (t - sin(t)) / (t2 * t);
+  }
+  double c1[3], c2[3];
+  cross3(x, v, c1);
+  cross3(x, c1, c2);
+  for (int i = 0; i < 3; ++i) out[i] = v[i] - a * c1[i] + b * c2[i];
+}
+
+/* Forward quantities of step n from P_n: the four stage moment sets. */
+static int step_moments(nbo_model *m, const double *X, int64_t n, double J[4][2][8]) {
+  const double rs = m->p.r_start_km, h = m->h;
+  const double r0 = rs + (double)n * h, rm = r0 + 0.5 * h, r1 = rs + (double)(n + 1) * h;
+  const radial g0 = radial_at(m, r0), gm = radial_at(m, rm);
+  int st = moments(m, X, r0, J[0][0], J[0][1]);
+  for (int64_t b = 0; b < m->nb; ++b) {
+    double f1[3], o[3];
+    stage_f2(m, b, &g0, J[0][0], J[0][1], f1);
+    for (int c = 0; c < 3; ++c) o[c] = 0.5 * f1[c];
+    rotate2(o, X + 3 * b, m->Y + 3 * b);
+  }
+  st |= moments(m, m->Y, rm, J[1][0], J[1][1]);
+  for (int64_t b = 0; b < m->nb; ++b) {
+    double f1[3], f2[3], cr[3], o[3];
+    stage_f2(m, b, &g0, J[0][0], J[0][1], f1);
+    stage_f2(m, b, &gm, J[1][0], J[1][1], f2);
+    cross3(f1, f2, cr);
+    for (int c = 0; c < 3; ++c) o[c] = 0.5 * f2[c] - 0.125 * cr[c];
+    rotate2(o, X + 3 * b, m->Y + 3 * b);
+  }
+  st |= moments(m, m->Y, rm, J[2][0], J[2][1]);
+  for (int64_t b = 0; b < m->nb; ++b) {
+    double f3[3];
+    stage_f2(m, b, &gm, J[2][0], J[2][1], f3);
+    rotate2(f3, X + 3 * b, m->Y + 3 * b);
+  }
+  st |= moments(m, m->Y, r1, J[3][0], J[3][1]);
+  return st;
+}
+
+typedef struct {
+  double *dGe, *dGb, *dGx;   /* d w / d L per energy bin (for the species they enter) */
+  double *dbx, *dbz;         /* d B_vac / d theta_v per energy bin */
+  double s2gf;
+} adj_tables;
+
+/* B-bar of one beam at radius g: returns its contribution to the moment adjoints
+ * (J0-bar += mu S B-bar, J1-bar -= mu c S B-bar) and to theta_v-bar, n0-bar. */
+static void b_adjoint(const nbo_model *m, const adj_tables *t, int s, int64_t k, const radial *g,
+                      double c, const double Bb[3], double *J0b, double *J1b, double *gth,
+                      double *gn0) {
+  const double sg = m->anti[s] ? -1.0 : 1.0;
+  const double SB[3] = {sg * Bb[0], Bb[1], sg * Bb[2]};
+  for (int i = 0; i < 3; ++i) { J0b[i] += g->mu * SB[i]; J1b[i] -= g->mu * c * SB[i]; }
+  *gth += Bb[0] * t->dbx[k] + Bb[2] * t->dbz[k];
+  double qp = 1.0;
+  for (int i = 0; i < m->p.ne_power; ++i) qp *= g->q;
+  *gn0 += sg * Bb[2] * t->s2gf * qp;
+}
+
+/* Moment adjoint broadcast to beam b at radius g: y-bar += w S (J0b/c + J1b) and the
+ * weight adjoint w-bar += (S y).(J0b/c + J1b). */
+static void m_adjoint(const nbo_model *m, int s, int64_t k, double c, const double *J0b,
+                      const double *J1b, const double y[3], double yb[3], double *wb) {
+  const double sg = m->anti[s] ? -1.0 : 1.0;
+  const double w = m->w[s * m->NE + k];
+  const double v[3] = {J0b[0] / c + J1b[0], J0b[1] / c + J1b[1], J0b[2] / c + J1b[2]};
+  const double Sv[3] = {sg * v[0], v[1], sg * v[2]};
+  for (int i = 0; i < 3; ++i) yb[i] += w * Sv[i];
+  *wb += (sg * y[0]) * v[0] + y[1] * v[1] + (sg * y[2]) * v[2];
+}
+
+static void add_rot_adjoint(const double x[3], double scale, const double yb[3], double pb[3]) {
+  double mx[3] = {-x[0] * scale, -x[1] * scale, -x[2] * scale}, r[3];
+  rotate2(mx, yb, r);
+  for (int i = 0; i < 3; ++i) pb[i] += r[i];
+}
+
+/* One reverse step: Pb (in: adjoint of P_{n+1}; out: adjoint of P_n), wbar per beam
+ * accumulated, parameter gradients accumulated. */
+static void reverse_step(nbo_model *m, const adj_tables *t, const double *X, int64_t n,
+                         double *Pb, double *wbar, double *gth, double *gn0, double *Tb,
+                         double *F1b) {
+  double J[4][2][8];
+  step_moments(m, X, n, J);
+  const double rs = m->p.r_start_km, h = m->h;
+  const double r0 = rs + (double)n * h, rm = r0 + 0.5 * h, r1 = rs + (double)(n + 1) * h;
+  const radial g0 = radial_at(m, r0), gm = radial_at(m, rm), g1 = radial_at(m, r1);
+  double Jb[4][2][3];
+  memset(Jb, 0, sizeof Jb);
+  /* final update and f4 */
+  for (int64_t b = 0; b < m->nb; ++b) {
+    const int s = (int)(b / (m->NU * m->NE));
+    const int64_t j = (b / m->NE) % m->NU, k = b % m->NE;
+    const double u = u_of(m, j);
+    double f1[3], f2[3], f3[3], f4[3], cr[3], th[3], Pp[3];
+    stage_f2(m, b, &g0, J[0][0], J[0][1], f1);
+    stage_f2(m, b, &gm, J[1][0], J[1][1], f2);
+    stage_f2(m, b, &gm, J[2][0], J[2][1], f3);
+    stage_f2(m, b, &g1, J[3][0], J[3][1], f4);
+    cross3(f1, f4, cr);
+    for (int c = 0; c < 3; ++c)
+      th[c] = (((f1[c] + 2.0 * f2[c]) + 2.0 * f3[c]) + f4[c]) * (1.0 / 6.0) - cr[c] * (1.0 / 12.0);
+    rotate2(th, X + 3 * b, Pp);
+    double Ppb[3] = {Pb[3 * b], Pb[3 * b + 1], Pb[3 * b + 2]};
+    if (m->p.renorm) {
+      const double nr = sqrt((Pp[0] * Pp[0] + Pp[1] * Pp[1]) + Pp[2] * Pp[2]);
+      const double Pn[3] = {Pp[0] / nr, Pp[1] / nr, Pp[2] / nr};
+      const double d = Pn[0] * Ppb[0] + Pn[1] * Ppb[1] + Pn[2] * Ppb[2];
+      for (int c = 0; c < 3; ++c) Ppb[c] = (Ppb[c] - Pn[c] * d) / nr;
+    }
+    double pbn[3] = {0, 0, 0}, om[3], thb[3];
+    add_rot_adjoint(th, 1.0, Ppb, pbn);
+    cross3(Pp, Ppb, om);
+    jlt(th, om, thb);
+    double c4[3], c1[3];
+    cross3(f4, thb, c4);     /* f1-bar part */
+    cross3(thb, f1, c1);     /* f4-bar part */
+    double f4b[3];
+    for (int c = 0; c < 3; ++c) {
+      F1b[3 * b + c] = thb[c] / 6.0 - c4[c] / 12.0;
+      f4b[c] = thb[c] / 6.0 - c1[c] / 12.0;
+      Tb[3 * b + c] = thb[c];
+      Pb[3 * b + c] = pbn[c];
+    }
+    const double c1g = c_of(&g1, u);
+    const double Bb[3] = {(h / c1g) * f4b[0], (h / c1g) * f4b[1], (h / c1g) * f4b[2]};
+    b_adjoint(m, t, s, k, &g1, c1g, Bb, Jb[3][0], Jb[3][1], gth, gn0);
+  }
+  /* stage 4: Y4 = R(f3) P */
+  for (int64_t b = 0; b < m->nb; ++b) {
+    const int s = (int)(b / (m->NU * m->NE));
+    const int64_t j = (b / m->NE) % m->NU, k = b % m->NE;
+    const double u = u_of(m, j);
+    double f3[3], Y[3], Yb[3] = {0, 0, 0}, om[3], f3b[3];
+    stage_f2(m, b, &gm, J[2][0], J[2][1], f3);
+    rotate2(f3, X + 3 * b, Y);
+    m_adjoint(m, s, k, c_of(&g1, u), Jb[3][0], Jb[3][1], Y, Yb, &wbar[b]);
+    add_rot_adjoint(f3, 1.0, Yb, Pb + 3 * b);
+    cross3(Y, Yb, om);
+    jlt(f3, om, f3b);
+    for (int c = 0; c < 3; ++c) f3b[c] += Tb[3 * b + c] / 3.0;
+    const double cm = c_of(&gm, u);
+    const double Bb[3] = {(h / cm) * f3b[0], (h / cm) * f3b[1], (h / cm) * f3b[2]};
+    b_adjoint(m, t, s, k, &gm, cm, Bb, Jb[2][0], Jb[2][1], gth, gn0);
+  }
+  /* stage 3: Y3 = R(Om3) P */
+  for (int64_t b = 0; b < m->nb; ++b) {
+    const int s = (int)(b / (m->NU * m->NE));
+    const int64_t j = (b / m->NE) % m->NU, k = b % m->NE;
+    const double u = u_of(m, j);
+    double f1[3], f2[3], cr[3], o[3], Y[3], Yb[3] = {0, 0, 0}, om[3], ob[3];
+    stage_f2(m, b, &g0, J[0][0], J[0][1], f1);
+    stage_f2(m, b, &gm, J[1][0], J[1][1], f2);
+    cross3(f1, f2, cr);
+    for (int c = 0; c < 3; ++c) o[c] = 0.5 * f2[c] - 0.125 * cr[c];
+    rotate2(o, X + 3 * b, Y);
+    const double cm = c_of(&gm, u);
+    m_adjoint(m, s, k, cm, Jb[2][0], Jb[2][1], Y, Yb, &wbar[b]);
+    add_rot_adjoint(o, 1.0, Yb, Pb + 3 * b);
+    cross3(Y, Yb, om);
+    jlt(o, om, ob);
+    double a1[3], a2[3], f2b[3];
+    cross3(ob, f1, a1);      /* f2-bar: ob/2 - (ob x f1)/8 */
+    cross3(f2, ob, a2);      /* f1-bar: -(f2 x ob)/8 */
+    for (int c = 0; c < 3; ++c) {
+      f2b[c] = 0.5 * ob[c] - a1[c] / 8.0 + Tb[3 * b + c] / 3.0;
+      F1b[3 * b + c] -= a2[c] / 8.0;
+    }
+    const double Bb[3] = {(h / cm) * f2b[0], (h / cm) * f2b[1], (h / cm) * f2b[2]};
+    b_adjoint(m, t, s, k, &gm, cm, Bb, Jb[1][0], Jb[1][1], gth, gn0);
+  }
+  /* stage 2: Y2 = R(f1/2) P */
+  for (int64_t b = 0; b < m->nb; ++b) {
+    const int s = (int)(b / (m->NU * m->NE));
+    const int64_t j = (b / m->NE) % m->NU, k = b % m->NE;
+    const double u = u_of(m, j);
+    double f1[3], o[3], Y[3], Yb[3] = {0, 0, 0}, om[3], ob[3];
+    stage_f2(m, b, &g0, J[0][0], J[0][1], f1);
+    for (int c = 0; c < 3; ++c) o[c] = 0.5 * f1[c];
+    rotate2(o, X + 3 * b, Y);
+    m_adjoint(m, s, k, c_of(&gm, u), Jb[1][0], Jb[1][1], Y, Yb, &wbar[b]);
+    add_rot_adjoint(o, 1.0, Yb, Pb + 3 * b);
+    cross3(Y, Yb, om);
+    jlt(o, om, ob);
+    for (int c = 0; c < 3; ++c) F1b[3 * b + c] += 0.5 * ob[c];
+    const double c0 = c_of(&g0, u);
+    const double Bb[3] = {(h / c0) * F1b[3 * b], (h / c0) * F1b[3 * b + 1], (h / c0) * F1b[3 * b + 2]};
+    b_adjoint(m, t, s, k, &g0, c0, Bb, Jb[0][0], Jb[0][1], gth, gn0);
+  }
+  /* stage 1 moments: J^(1) = M(P_n) */
+  for (int64_t b = 0; b < m->nb; ++b) {
+    const int s = (int)(b / (m->NU * m->NE));
+    const int64_t j = (b / m->NE) % m->NU, k = b % m->NE;
+    m_adjoint(m, s, k, c_of(&g0, u_of(m, j)), Jb[0][0], Jb[0][1], X + 3 * b, Pb + 3 * b, &wbar[b]);
+  }
+}
+
+int nbo_adjoint(nbo_model *m, int32_t ckpt, const double *dl_dpee, double *grad, double *loss,
+                double *state_bar) {
+  if (!m || m->nf != 2 || m->p.species4 || m->p.integrator || ckpt < 1) return NBO_EINVAL;
+  const int64_t n0 = m->step, N = m->p.n_steps;
+  const int64_t nseg = (N - n0 + ckpt - 1) / ckpt;
+  const int64_t ns = m->nb * 3;
+  double *ck = (double *)malloc(sizeof(double) * ns * (size_t)(nseg > 0 ? nseg : 1));
+  double *fin = (double *)malloc(sizeof(double) * ns);
+  double *tape = (double *)malloc(sizeof(double) * ns * (size_t)ckpt);
+  double *Pb = (double *)calloc((size_t)ns, sizeof(double));
+  double *Tb = (double *)calloc((size_t)ns, sizeof(double));
+  double *F1b = (double *)calloc((size_t)ns, sizeof(double));
+  double *wbar = (double *)calloc((size_t)m->nb, sizeof(double));
+  int st = 0;
+  /* forward pass, keeping the state at the start of every segment */
+  for (int64_t sgi = 0; sgi < nseg; ++sgi) {
+    memcpy(ck + sgi * ns, m->X, sizeof(double) * ns);
+    const int64_t len = (sgi == nseg - 1) ? (N - n0) - sgi * ckpt : ckpt;
+    st |= nbo_step(m, len);
+  }
+  memcpy(fin, m->X, sizeof(double) * ns);
+  /* L = sum_b c_b Pee_b with Pee = (1 + P_z)/2; by default c_b = dE/N_u (energy-integrated,
+   * angle-averaged P_ee of both species) */
+  double L = 0.0;
+  const double wl = m->dE / (double)m->NU;
+  for (int64_t b = 0; b < m->nb; ++b) {
+    const double cb = dl_dpee ? dl_dpee[b] : wl;
+    L += cb * (0.5 * (1.0 + fin[3 * b + 2]));
+    Pb[3 * b + 2] = 0.5 * cb;
+  }
+  /* derivative tables: d w / d L_a and d B_vac / d theta_v per energy bin */
+  adj_tables t;
+  t.s2gf = sqrt2gf_km_cm3();
+  t.dGe = (double *)malloc(sizeof(double) * m->NE);
+  t.dGb = (double *)malloc(sizeof(double) * m->NE);
+  t.dGx = (double *)malloc(sizeof(double) * m->NE);
+  t.dbx = (double *)malloc(sizeof(double) * m->NE);
+  t.dbz = (double *)malloc(sizeof(double) * m->NE);
+  const double pref = (m->kappa0 * m->du) * m->dE;
+  for (int64_t k = 0; k < m->NE; ++k) {
+    const double E = m->E[k];
+    t.dGe[k] = pref * ERG_MEV / ((m->p.temp_mev[0] * F3_0) / F2_0) * fermi_dirac(E, m->p.temp_mev[0]);
+    t.dGb[k] = pref * ERG_MEV / ((m->p.temp_mev[1] * F3_0) / F2_0) * fermi_dirac(E, m->p.temp_mev[1]);
+    t.dGx[k] = -pref * ERG_MEV / ((m->p.temp_mev[2] * F3_0) / F2_0) * fermi_dirac(E, m->p.temp_mev[2]);
+    const double om = (VAC_K * m->p.dm2_ev2[0]) / E;
+    t.dbx[k] = 4.0 * om * cos(2.0 * m->p.theta[0]);
+    t.dbz[k] = 4.0 * om * sin(2.0 * m->p.theta[0]);
+  }
+  /* reverse pass: each segment is recomputed from its checkpoint, then walked backwards */
+  double gth = 0.0, gn0 = 0.0;
+  for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
+    const int64_t s0 = n0 + sgi * ckpt;
+    const int64_t len = (sgi == nseg - 1) ? (N - n0) - sgi * ckpt : ckpt;
+    memcpy(m->X, ck + sgi * ns, sizeof(double) * ns);
+    m->step = s0;
+    for (int64_t i = 0; i < len; ++i) {
+      memcpy(tape + i * ns, m->X, sizeof(double) * ns);
+      if (i + 1 < len) st |= nbo_step(m, 1);
+    }
+    for (int64_t i = len - 1; i >= 0; --i)
+      reverse_step(m, &t, tape + i * ns, s0 + i, Pb, wbar, &gth, &gn0, Tb, F1b);
+  }
+  double gLe = 0.0, gLb = 0.0, gLx = 0.0;
+  for (int64_t b = 0; b < m->nb; ++b) {
+    const int s = (int)(b / (m->NU * m->NE));
+    const int64_t k = b % m->NE;
+    if (!m->anti[s]) gLe += wbar[b] * t.dGe[k];
+    else gLb += wbar[b] * t.dGb[k];
+    gLx += wbar[b] * t.dGx[k];
+  }
+  grad[0] = gLe; grad[1] = gLb; grad[2] = gLx; grad[3] = gth; grad[4] = gn0;
+  *loss = L;
+  if (state_bar) memcpy(state_bar, Pb, sizeof(double) * ns);
+  /* the model is left at the end of the run, as after the forward pass */
+  memcpy(m->X, fin, sizeof(double) * ns);
+  m->step = N;
+  free(ck); free(fin); free(tape); free(Pb); free(Tb); free(F1b); free(wbar);
+  free(t.dGe); free(t.dGb); free(t.dGx); free(t.dbx); free(t.dbz);
+  return st ? NBO_ENUMERIC : NBO_OK;
 }

@@ -88,10 +88,13 @@ double nbo_fixed_sum(const double *v, int64_t n, int e);
 int  nbo_single_angle_run(const nbo_params *p, double *pee_out /* [2][NE] */);
 
 /* Reverse-mode adjoint of the whole radial integration (2 flavours, RKMK4).
- * Loss L = sum_s sum_k dE/N_u sum_j Pee(s,k,j).  Runs from the current state for
- * n_steps - step steps (the forward run is redone internally), checkpointing every
- * ckpt steps.  grad[5] = dL/d{L_e, L_ebar, L_x, theta_v, n0}; *loss = L. */
-int  nbo_adjoint(nbo_model *m, int32_t ckpt, double *grad, double *loss);
+ * Runs forward from the current state to n_steps, keeping the state every ckpt steps,
+ * then backwards segment by segment (each segment recomputed from its checkpoint).
+ * L = sum_b dl_dpee[b] Pee_b of the final state; dl_dpee = NULL takes the energy-integrated
+ * loss dl_dpee[b] = dE/N_u.  grad[5] = dL/d{L_e, L_ebar, L_x, theta_v, n0}; *loss = L;
+ * state_bar (NULL or [nb][3]) = dL/d(initial Bloch vectors).  The model ends at n_steps. */
+int  nbo_adjoint(nbo_model *m, int32_t ckpt, const double *dl_dpee, double *grad, double *loss,
+                 double *state_bar);
 
 #ifdef __cplusplus
 }
