@@ -18,7 +18,8 @@
  *   - ownership: the caller owns every buffer (device workspace, outputs).  The library
  *     owns only the opaque nb_model host object, freed by nb_model_destroy.
  *   - device memory: all device work uses the workspace bound with nb_bind; nb_step,
- *     nb_run, nb_read_pee and nb_adjoint allocate nothing.
+ *     nb_run, nb_read_pee and nb_adjoint allocate nothing (the adjoint's checkpoints and
+ *     tape are part of the workspace when adjoint_ckpt > 0).
  *   - streams: all device work is enqueued on the stream given to nb_bind.  Calls return
  *     after checking the kernels' status word, i.e. after the stream has drained, unless
  *     the stream is being captured into a HIP graph (then they return at once).
@@ -121,12 +122,23 @@ int nb_graph_launch(nb_model *m);
  * (may be NULL) receives the winning time.  Results never change the arithmetic. */
 int nb_autotune(nb_model *m, int32_t trial_steps, double *best_ms);
 
-/* Reverse-mode adjoint of the radial integration (2 flavours, FP64, single model).
- * Runs from the current state and step to r_end (keeping a checkpoint every ckpt_every
- * steps; 0 = the model's adjoint_ckpt), then back.  dev_dl_dpee[nb_n_beams]: cotangent
- * of the final P_ee (device).  grad_out[5] (host) = dL/d{L_e, L_ebar, L_x, theta_v, n0}.
- * The model is left at r_end.  Requires adjoint_ckpt > 0 at creation. */
-int nb_adjoint(nb_model *m, const double *dev_dl_dpee, double *grad_out, int32_t ckpt_every);
+/* Reverse-mode adjoint of the radial integration (2 flavours, FP64, single model created
+ * with adjoint_ckpt > 0).  The gradients are those of the final survival probabilities
+ * (Sec. 3.5) with respect to the luminosities, the vacuum mixing angle (Sec. 2) and the
+ * electron density scale of n_e(r) (Sec. 3.2), for L = sum_b dL/dPee_b Pee_b at r_end.
+ * Runs forward from the current state and step to r_end, keeping the state every
+ * ckpt_every steps (0: the model's adjoint_ckpt) and recording every stage's moments,
+ * then backwards one segment at a time, each segment recomputed from its checkpoint.
+ *   dev_dl_dpee    [nb_n_beams] device, dL/dPee per beam; NULL: dE/N_u for every beam (the
+ *                  energy-integrated, angle-averaged P_ee of both species).
+ *   grad_out[5]    host, dL/d{L_e, L_ebar, L_x (erg/s), theta_v (rad), n0 (cm^-3)}.
+ *   dev_state_bar  NULL, or [3][nb_n_beams] device: dL/d(Bloch vectors at the start step).
+ * The period must fit the workspace: ceil(steps/ckpt) + min(ckpt, steps) state slots, no
+ * more than ceil(n_steps/adjoint_ckpt) + min(adjoint_ckpt, n_steps).  The model is left at
+ * r_end with the forward run's state.  Moment adjoints are summed in FP64 in a fixed
+ * order, so results repeat bit for bit.  Not capturable into a graph (it synchronises). */
+int nb_adjoint(nb_model *m, const double *dev_dl_dpee, double *grad_out, int32_t ckpt_every,
+               double *dev_state_bar);
 
 /* Host tables (no device work), layout as [E_k | weights[2][NE] | vacuum terms |
  * lam0, kappa0, h, 2^-e1, 2^-e0, e1, e0]; vacuum terms are (B_x, B_z) per k for 2f and

@@ -75,7 +75,7 @@ def lib():
         L.nb_read_pee.argtypes = [vp, vp]
         L.nb_get_state.argtypes = [vp, vp, C.c_int]
         L.nb_set_state.argtypes = [vp, vp, i64, C.c_int]
-        L.nb_adjoint.argtypes = [vp, vp, dp, C.c_int32]
+        L.nb_adjoint.argtypes = [vp, vp, dp, C.c_int32, vp]
         L.nb_host_tables.argtypes = [vp, dp, i64]
         L.nb_last_error.restype = C.c_char_p
         L.nb_test_sincos.argtypes = [vp, i64, vp, vp, vp]
@@ -233,6 +233,68 @@ class Model(HostModel):
         assert x.numel() == self.nsc * self.nb
         _check(lib().nb_set_state(self.h, C.c_void_p(x.data_ptr()), int(step), 1),
                "nb_set_state")
+
+    def adjoint(self, dl_dpee=None, ckpt: int = 0, want_state_bar: bool = False):
+        """Reverse-mode gradients of L = sum_b dl_dpee[b] Pee_b at r_end (default
+        cotangent dE/N_u) with respect to (L_e, L_ebar, L_x, theta_v, n0), from the current
+        state; the model ends at r_end.  Returns a float64 numpy array of 5, or
+        (grad, state_bar) with state_bar = dL/d(state at the start) as [3][nb] planes."""
+        import numpy as np
+        torch = _torch()
+        c = None
+        if dl_dpee is not None:
+            c = dl_dpee.to(device=self.ws.device, dtype=torch.float64).contiguous()
+            assert c.numel() == self.nb
+        sb = None
+        if want_state_bar:
+            sb = torch.empty(3, self.nb, dtype=torch.float64, device=self.ws.device)
+        g = np.empty(5, np.float64)
+        _check(lib().nb_adjoint(self.h, None if c is None else _ptr(c),
+                                g.ctypes.data_as(C.POINTER(C.c_double)), int(ckpt),
+                                None if sb is None else _ptr(sb)), "nb_adjoint")
+        return (g, sb) if want_state_bar else g
+
+
+PARAM_NAMES = ("L_e", "L_ebar", "L_x", "theta_v", "n0")
+
+
+def _with_params(d: dict, x) -> dict:
+    q = {k: (list(v) if isinstance(v, list) else v) for k, v in d.items()}
+    q["lum_erg_s"] = [float(x[0]), float(x[1]), float(x[2])]
+    q["theta"] = [float(x[3])] + list(d["theta"][1:])
+    q["n0_cm3"] = float(x[4])
+    return q
+
+
+def _bulb_fn():
+    torch = _torch()
+
+    class BulbPee(torch.autograd.Function):
+        """Final P_ee of every beam of a two-flavour bulb model as a differentiable
+        function of x = (L_e, L_ebar, L_x, theta_v, n0); backward runs the library's
+        reverse-mode adjoint with the given checkpoint period."""
+
+        @staticmethod
+        def forward(ctx, x, d, ckpt):
+            m = Model(_with_params(d, x.detach().cpu().tolist()), adjoint_ckpt=int(ckpt))
+            m.run()
+            ctx.model = m
+            return m.pee()
+
+        @staticmethod
+        def backward(ctx, g):
+            m = ctx.model
+            m.reset()
+            grad = m.adjoint(g.detach())
+            return torch.as_tensor(grad, dtype=torch.float64), None, None
+
+    return BulbPee
+
+
+def bulb_pee(x, d: dict, ckpt: int = 64):
+    """Differentiable final P_ee (device tensor [nb]) of the two-flavour model d with its
+    luminosities, theta_v and n0 replaced by the float64 tensor x (5 entries, CPU)."""
+    return _bulb_fn().apply(x, d, ckpt)
 
 
 # ------------------------------------------------------------------ test hooks

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnubulb.so")
-SOURCES = ["nb_kernels.hip", "nb_api.hip"]
+SOURCES = ["nb_kernels.hip", "nb_adjoint.hip", "nb_api.hip"]
 ARCH = os.environ.get("NB_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",

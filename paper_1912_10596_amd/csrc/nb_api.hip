@@ -18,6 +18,8 @@ namespace nb {
 template <int NF, typename ST, bool TLDS>
 __global__ void k_advance(StepArgs a);
 __global__ void k_batch2(BatchArgs a);
+template <int BPT>
+__global__ void k_adjoint2(AdjArgs a);
 __global__ void k_zero_sync(unsigned int* sync, int keep_status);
 __global__ void k_zero_u64(unsigned long long* p, long long n);
 __global__ void k_set_step(long long* step_ctl, long long step);
@@ -80,6 +82,7 @@ struct Sub {
   double h = 0, lam0 = 0, kappa0 = 0, s1 = 0, s0 = 0, p2e1 = 0, p2e0 = 0;
   int e1 = 0, e0 = 0, nf = 2;
   std::vector<double> E, tab;
+  std::vector<double> dtab;          // 2f: [dG0/dL_e | dG1/dL_ebar | dG/dL_x | dbx/dth | dbz/dth] x NE
 };
 
 struct nb_model {
@@ -101,7 +104,10 @@ struct nb_model {
   unsigned long long ticks_per_s = 0;
   size_t off_X = 0, off_tab = 0, off_J = 0, off_part = 0, off_sync = 0, off_ctl = 0;
   size_t off_models = 0, off_waves = 0, off_acc = 0, need = 0;
-  long long* pinned = nullptr;       // [0] status, [1] step (device read-back)
+  size_t off_adj = 0, off_jhist = 0, off_dtab = 0, off_apart = 0, off_aout = 0;
+  double* jhist = nullptr;           // set while the adjoint's forward pass records moments
+  int adj_blocks = 0, adj_bpt = 0;
+  long long* pinned = nullptr;       // [0] status, [1] step, [8..12] adjoint gradients
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   long long graph_steps = 0;
@@ -130,6 +136,8 @@ static int validate(const nb_params* p) {
       return fail(NB_EINVAL, "temperatures must be > 0 and luminosities >= 0");
   if (!(std::isfinite(p->n0_cm3) && p->n0_cm3 >= 0.0)) return fail(NB_EINVAL, "n0 must be >= 0");
   if (p->adjoint_ckpt < 0) return fail(NB_EINVAL, "adjoint_ckpt must be >= 0");
+  if (p->adjoint_ckpt > 0 && (p->n_flavor != 2 || p->precision != NB_FP64))
+    return fail(NB_EINVAL, "the adjoint is a two-flavour FP64 mode");
   if (p->max_blocks < 0) return fail(NB_EINVAL, "max_blocks must be >= 0");
   return NB_OK;
 }
@@ -154,6 +162,7 @@ static void build_tables(Sub* m) {
   const int nv = (m->nf == 2) ? 2 : 6;
   m->E.assign(NE, 0.0);
   m->tab.assign((size_t)(nv + 2) * NE, 0.0);
+  m->dtab.assign(m->nf == 2 ? (size_t)5 * NE : 0, 0.0);
   double* G0 = m->tab.data() + (size_t)nv * NE;
   double* G1 = G0 + NE;
   double U[3][3];
@@ -180,6 +189,13 @@ static void build_tables(Sub* m) {
       const double s2 = std::sin(2.0 * p.theta[0]), c2 = std::cos(2.0 * p.theta[0]);
       m->tab[k] = (2.0 * om) * s2;            // B_vac,x
       m->tab[NE + k] = -((2.0 * om) * c2);    // B_vac,z
+      // derivatives for the adjoint: dg/dL_a = pref f_a / <E_a> (erg -> MeV), the
+      // heavy-flavour term entering both species with a minus sign; dB_vac/dtheta_v
+      m->dtab[k] = pref * kErgMeV / ((p.temp_mev[0] * kFD3) / kFD2) * fe;
+      m->dtab[NE + k] = pref * kErgMeV / ((p.temp_mev[1] * kFD3) / kFD2) * fb;
+      m->dtab[2 * NE + k] = -(pref * kErgMeV / ((p.temp_mev[2] * kFD3) / kFD2) * fx);
+      m->dtab[3 * NE + k] = (4.0 * om) * c2;
+      m->dtab[4 * NE + k] = (4.0 * om) * s2;
     } else {
       const double w2 = ((2.0 * kVac) * p.dm2_ev2[0]) / e;  // dm^2_21 / 2E
       const double w3 = ((2.0 * kVac) * p.dm2_ev2[1]) / e;  // dm^2_31 / 2E
@@ -270,6 +286,7 @@ extern "C" int nb_batch_create(const nb_params* p, int32_t n_models, nb_model** 
     const nb_params& q = p[i];
     if (q.n_flavor != 2 || q.precision != NB_FP64)
       return fail(NB_EINVAL, "batched models are two-flavour FP64 (model %d)", i);
+    if (q.adjoint_ckpt != 0) return fail(NB_EINVAL, "batched models have no adjoint (model %d)", i);
     if (q.n_steps != p[0].n_steps || q.r_start_km != p[0].r_start_km || q.r_end_km != p[0].r_end_km ||
         q.r_nu_km != p[0].r_nu_km || q.ne_power != p[0].ne_power || q.renorm != p[0].renorm)
       return fail(NB_EINVAL, "batched models must share the radial grid, R, ne_power and renorm (model %d)", i);
@@ -317,8 +334,17 @@ static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 // Workspace: state planes | tables | stage moments | block partials | sync words | step
 // counter | (batches) model descriptors | wave row ranges | moment accumulators.
 struct Layout {
-  size_t X, tab, J, part, sync, ctl, models, waves, acc, need;
+  size_t X, tab, J, part, sync, ctl, models, waves, acc, adj, jhist, dtab, apart, aout, need;
 };
+
+// The adjoint (single two-flavour model with adjoint_ckpt = K > 0) reserves state slots
+// for ceil(n_steps / K) checkpoints plus a tape of K states, the recorded stage moments of
+// every step, its derivative tables, block partials and its outputs.
+static bool adjoint_enabled(const nb_model* m) { return !m->batch && m->nf == 2 && m->p.adjoint_ckpt > 0; }
+static long long adjoint_slots(const nb_model* m) {
+  const long long K = m->p.adjoint_ckpt, N = m->p.n_steps;
+  return (N + K - 1) / K + std::min(K, N);
+}
 
 static Layout layout_of(const nb_model* m) {
   const size_t es = state_fp32(m) ? sizeof(float) : sizeof(double);
@@ -345,6 +371,18 @@ static Layout layout_of(const nb_model* m) {
     o = align256(o + sizeof(long long) * ((size_t)kMaxBlocks * (kBlock / 64) + 1));
     L.acc = o;
     o = align256(o + sizeof(unsigned long long) * (size_t)kAccSets * m->nmodels * 6 * kAccLimbs);
+  }
+  L.adj = L.jhist = L.dtab = L.apart = L.aout = o;
+  if (adjoint_enabled(m)) {
+    o = align256(o + sizeof(double) * (size_t)adjoint_slots(m) * 3 * m->plane);
+    L.jhist = o;
+    o = align256(o + sizeof(double) * (size_t)(m->p.n_steps + 1) * 24);
+    L.dtab = o;
+    o = align256(o + sizeof(double) * m->subs[0].dtab.size());
+    L.apart = o;
+    o = align256(o + sizeof(double) * (size_t)kMaxBlocks * 8);
+    L.aout = o;
+    o = align256(o + sizeof(double) * 16);
   }
   L.need = o;
   return L;
@@ -468,7 +506,31 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
   m->off_models = L.models;
   m->off_waves = L.waves;
   m->off_acc = L.acc;
+  m->off_adj = L.adj;
+  m->off_jhist = L.jhist;
+  m->off_dtab = L.dtab;
+  m->off_apart = L.apart;
+  m->off_aout = L.aout;
   m->need = L.need;
+  m->adj_bpt = 0;
+  m->adj_blocks = 0;
+  if (adjoint_enabled(m)) {
+    // smallest beams-per-thread variant whose resident grid covers every beam
+    static const int bpts[3] = {1, 2, 4};
+    static const void* fns[3] = {(const void*)&k_adjoint2<1>, (const void*)&k_adjoint2<2>,
+                                 (const void*)&k_adjoint2<4>};
+    for (int i = 0; i < 3 && !m->adj_bpt; ++i) {
+      int per = 0;
+      NB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fns[i], kBlock, 0));
+      int blocks = std::min(cus * per, kMaxBlocks);
+      if (m->p.max_blocks > 0) blocks = std::min(blocks, (int)m->p.max_blocks);
+      const long long need_blocks = (m->nb + (long long)bpts[i] * kBlock - 1) / ((long long)bpts[i] * kBlock);
+      if (per >= 1 && need_blocks <= blocks) {
+        m->adj_bpt = bpts[i];
+        m->adj_blocks = (int)std::max<long long>(1, need_blocks);
+      }
+    }
+  }
   m->ws = (char*)dev_ws;
   m->ws_bytes = bytes;
   m->stream = (hipStream_t)hip_stream;
@@ -477,9 +539,12 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
   m->max_blocks = max_blocks;
   m->nblocks = launch_blocks(m);
   m->ticks_per_s = (unsigned long long)(khz > 0 ? khz : 100000) * 1000ull;
-  if (!m->pinned) NB_HIP(hipHostMalloc((void**)&m->pinned, 64, hipHostMallocDefault));
+  if (!m->pinned) NB_HIP(hipHostMalloc((void**)&m->pinned, 256, hipHostMallocDefault));
   NB_HIP(hipMemcpyAsync(m->ws + m->off_tab, m->tab.data(), tab_bytes(m), hipMemcpyHostToDevice,
                         m->stream));
+  if (adjoint_enabled(m))
+    NB_HIP(hipMemcpyAsync(m->ws + m->off_dtab, m->subs[0].dtab.data(), sizeof(double) * m->subs[0].dtab.size(),
+                          hipMemcpyHostToDevice, m->stream));
   if (m->batch) {
     std::vector<BatchModel> md((size_t)m->nmodels);
     for (int i = 0; i < m->nmodels; ++i) {
@@ -594,6 +659,7 @@ static int enqueue_advance(nb_model* m, long long k) {
   a.p2e1 = s.p2e1;
   a.p2e0 = s.p2e0;
   a.timeout_ticks = timeout;
+  a.Jhist = m->jhist;
   void* args[] = {&a};
   const hipError_t e =
       capturing(m->stream)
@@ -796,12 +862,92 @@ extern "C" int nb_set_state(nb_model* m, const double* src, int64_t step, int on
   return NB_OK;
 }
 
-extern "C" int nb_adjoint(nb_model* m, const double* dev_dl_dpee, double* grad_out, int32_t ckpt_every) {
-  (void)dev_dl_dpee;
-  (void)grad_out;
-  (void)ckpt_every;
-  if (!m) return fail(NB_EINVAL, "model is NULL");
-  return fail(NB_EINVAL, "adjoint is not available in this build");
+extern "C" int nb_adjoint(nb_model* m, const double* dev_dl_dpee, double* grad_out, int32_t ckpt_every,
+                          double* dev_state_bar) {
+  if (!m || !grad_out) return fail(NB_EINVAL, "NULL model or gradient output");
+  if (!m->ws) return fail(NB_EUNBOUND, "no workspace bound");
+  if (!adjoint_enabled(m))
+    return fail(NB_EINVAL, "the adjoint needs a single two-flavour model created with adjoint_ckpt > 0");
+  if (ckpt_every < 0) return fail(NB_EINVAL, "ckpt_every must be >= 0");
+  if (capturing(m->stream)) return fail(NB_EINVAL, "the adjoint cannot be captured into a graph");
+  if (!m->adj_bpt) return fail(NB_EINVAL, "too many beams (%lld) for one resident adjoint grid", m->nb);
+  const long long K = ckpt_every > 0 ? ckpt_every : m->p.adjoint_ckpt;
+  const long long n0 = m->step, N = m->p.n_steps, ns = N - n0;
+  const long long nseg = (ns + K - 1) / K;
+  if (nseg + std::min(K, ns) > adjoint_slots(m))
+    return fail(NB_EINVAL, "checkpoint period %lld needs %lld state slots; the workspace holds %lld", K,
+                nseg + std::min(K, ns), adjoint_slots(m));
+  const size_t pl3 = (size_t)3 * m->plane;
+  double* ck = (double*)(m->ws + m->off_adj);
+  double* tape = ck + (size_t)nseg * pl3;
+  // forward pass: checkpoint at the start of every segment, every stage's moments recorded
+  m->jhist = (double*)(m->ws + m->off_jhist);
+  for (long long sg = 0; sg < nseg; ++sg) {
+    const hipError_t e = hipMemcpyAsync(ck + sg * pl3, m->ws + m->off_X, sizeof(double) * pl3,
+                                        hipMemcpyDeviceToDevice, m->stream);
+    if (e != hipSuccess) {
+      m->jhist = nullptr;
+      return fail(NB_EHIP, "checkpoint copy: %s", hipGetErrorString(e));
+    }
+    const int rc = advance(m, std::min(K, ns - sg * K));
+    if (rc) {
+      m->jhist = nullptr;
+      return rc;
+    }
+  }
+  m->jhist = nullptr;
+  // reverse pass
+  unsigned int* sync = (unsigned int*)(m->ws + m->off_sync);
+  int keep = 1;
+  void* zargs[] = {&sync, &keep};
+  NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(8), dim3(256), zargs, 0, m->stream));
+  const Sub& s = m->subs[0];
+  AdjArgs a{};
+  a.tab = (const double*)(m->ws + m->off_tab);
+  a.dtab = (const double*)(m->ws + m->off_dtab);
+  a.Jhist = (const double*)(m->ws + m->off_jhist);
+  a.ck = ck;
+  a.tape = tape;
+  a.cot = dev_dl_dpee;
+  a.cot_const = ((s.p.e_max_mev - s.p.e_min_mev) / (double)s.NE) / (double)s.NU;
+  a.state_bar = dev_state_bar;
+  a.part = (double*)(m->ws + m->off_apart);
+  a.out = (double*)(m->ws + m->off_aout);
+  a.sync = sync;
+  a.plane = m->plane;
+  a.nb = m->nb;
+  a.NE = (int)s.NE;
+  a.NU = (int)s.NU;
+  a.n0 = n0;
+  a.nsteps = ns;
+  a.ckpt = K;
+  a.nseg = nseg;
+  a.rs = m->p.r_start_km;
+  a.h = s.h;
+  a.R = m->p.r_nu_km;
+  a.lam0 = s.lam0;
+  a.s2gf = potential_per_density();
+  a.ne_power = m->p.ne_power;
+  a.renorm = m->p.renorm;
+  a.timeout_ticks = m->ticks_per_s * 20ull;
+  void* args[] = {&a};
+  const void* fn = m->adj_bpt == 1 ? (const void*)&k_adjoint2<1>
+                 : m->adj_bpt == 2 ? (const void*)&k_adjoint2<2>
+                                   : (const void*)&k_adjoint2<4>;
+  const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(m->adj_blocks), dim3(kBlock), args, 0, m->stream);
+  if (e != hipSuccess) return fail(NB_EHIP, "adjoint launch: %s", hipGetErrorString(e));
+  const long long before = m->step;
+  int rc = check_status(m);
+  if (rc) return rc;
+  if (m->step != before) return fail(NB_EHIP, "device step counter moved during the reverse pass");
+  double* host = (double*)(m->pinned + 8);
+  NB_HIP(hipMemcpyAsync(host, a.out, sizeof(double) * 5, hipMemcpyDeviceToHost, m->stream));
+  NB_HIP(hipStreamSynchronize(m->stream));
+  for (int i = 0; i < 5; ++i) {
+    grad_out[i] = host[i];
+    if (!std::isfinite(host[i])) return fail(NB_ENUMERIC, "non-finite gradient component %d", i);
+  }
+  return NB_OK;
 }
 
 extern "C" int nb_host_tables(const nb_model* m, double* out, int64_t cap) {

@@ -32,6 +32,7 @@ struct StepArgs {
   int ne_power, renorm;
   double s1, s0, p2e1, p2e0;  // fixed-point scales 2^e1, 2^e0, 2^-e1, 2^-e0
   unsigned long long timeout_ticks;
+  double* Jhist;           // nullptr, or [step][4][2*NC]: every stage's moments (adjoint tape)
 };
 
 // One two-flavour model of a batch.
@@ -61,6 +62,28 @@ struct BatchArgs {
   long long* step_ctl;
   long long nsteps, total_steps;
   double rs, h, R;
+  int ne_power, renorm;
+  unsigned long long timeout_ticks;
+};
+
+// Arguments of the two-flavour reverse (adjoint) kernel.  Beam b belongs to thread
+// b mod (grid threads); its adjoint state stays in registers for the whole launch.
+struct AdjArgs {
+  const double* tab;       // [bx|bz|G0|G1] x NE
+  const double* dtab;      // [dG0/dL_e | dG1/dL_ebar | dG/dL_x | dbx/dtheta | dbz/dtheta] x NE
+  const double* Jhist;     // [step][4][6] stage moments recorded by the forward pass
+  const double* ck;        // [nseg][3][plane] state at the start of every segment
+  double* tape;            // [ckpt][3][plane] states of the segment being reversed
+  const double* cot;       // dL/dPee per beam, or nullptr: cot_const for every beam
+  double cot_const;
+  double* state_bar;       // nullptr, or [3][nb]: dL/d(state at the first step)
+  double* part;            // [gridDim][8] block partials of the reductions
+  double* out;             // [8] final reduction: dL/d{L_e, L_ebar, L_x, theta_v, n0}
+  unsigned int* sync;
+  long long plane, nb;
+  int NE, NU;
+  long long n0, nsteps, ckpt, nseg;  // first step, steps, checkpoint period, segments
+  double rs, h, R, lam0, s2gf;
   int ne_power, renorm;
   unsigned long long timeout_ticks;
 };

@@ -16,29 +16,16 @@
 // step's stage-1 moments.
 #include "nb_device.h"
 #include "nb_internal.h"
+#include "nb_stage.h"
 
 namespace nb {
 
-struct Radial {
-  double q2, lam, mu;
-};
-
-__device__ __forceinline__ Radial radial(double R, int ne_power, double lam0, double r) {
-  Radial g;
-  const double q = R / r;
-  g.q2 = q * q;
-  double qp = 1.0;
-  for (int i = 0; i < ne_power; ++i) qp = qp * q;
-  g.lam = lam0 * qp;     // sqrt2 G_F n_e(r)
-  g.mu = 0.5 * g.q2;     // R^2 / 2r^2 from d cos(theta') = (R^2/2r^2) du / cos(theta')
-  return g;
-}
 __device__ __forceinline__ Radial radial_at(const StepArgs& a, double r) {
   return radial(a.R, a.ne_power, a.lam0, r);
 }
-
-__device__ __forceinline__ double as_double(unsigned long long u) { return __longlong_as_double((long long)u); }
-__device__ __forceinline__ unsigned long long as_bits(double d) { return (unsigned long long)__double_as_longlong(d); }
+__device__ __forceinline__ bool spin_until(const StepArgs& a, unsigned* w, unsigned want) {
+  return spin_wait(a.sync, a.timeout_ticks, w, want);
+}
 
 template <int NV>
 __device__ __forceinline__ I128 select_comp(const I128 (&S)[NV], int c) {
@@ -48,23 +35,6 @@ __device__ __forceinline__ I128 select_comp(const I128 (&S)[NV], int c) {
     if (c == i) r = S[i];
   }
   return r;
-}
-
-// ---------------------------------------------------------------- grid barrier
-// Spin until *w >= want (agent-scope acquire), giving up when another block has aborted
-// or the launch's time limit passes.  Returns false on give-up.
-__device__ __forceinline__ bool spin_until(const StepArgs& a, unsigned* w, unsigned want) {
-  const unsigned long long t0 = wall_clock64();
-  for (;;) {
-    if (__hip_atomic_load(w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= want) return true;
-    if (__hip_atomic_load(a.sync + kSyncAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
-    if (wall_clock64() - t0 > a.timeout_ticks) {
-      __hip_atomic_store(a.sync + kSyncAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_or(a.sync + kSyncStatus, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return false;
-    }
-    __builtin_amdgcn_s_sleep(1);
-  }
 }
 
 // Grid-wide reduction of the stage moments without read-modify-write contention: every
@@ -151,28 +121,6 @@ __device__ bool finish_stage(const StepArgs& a, unsigned epoch, I128 T, I128 (*s
 struct Scales {
   double s1, s0, p2e1, p2e0;
 };
-// Geometry of one emission bin u at the three stage radii of a step.
-struct RowGeo {
-  double c0, cm, c1, hc0, hcm, hc1;
-};
-__device__ __forceinline__ RowGeo row_geo(double u, double h, const Radial& g0, const Radial& gm,
-                                          const Radial& g1) {
-  RowGeo r;
-  r.c0 = sqrt(1.0 - u * g0.q2);
-  r.cm = sqrt(1.0 - u * gm.q2);
-  r.c1 = sqrt(1.0 - u * g1.q2);
-  r.hc0 = h / r.c0;
-  r.hcm = h / r.cm;
-  r.hc1 = h / r.c1;
-  return r;
-}
-__device__ __forceinline__ double u_of(int j, int NU) { return ((double)j + 0.5) / (double)NU; }
-// The neutrino-neutrino term mu (J0 - c J1) of a row: the same for every energy bin.
-template <int NC>
-__device__ __forceinline__ void nunu(const double* J, double mu, double c, double* nn) {
-#pragma unroll
-  for (int i = 0; i < NC; ++i) nn[i] = mu * (J[i] - c * J[NC + i]);
-}
 // End of a row segment: lane sums -> exact wave sums; lane v keeps component v % NC.
 template <int NC>
 __device__ __forceinline__ void fold_segment(const long long* acc, int lane, I128& mine) {
@@ -194,25 +142,6 @@ __device__ __forceinline__ void close_row(const Scales& sc, int lane, const I128
 }
 
 // ----------------------------------------------------------------- two flavours
-// Stage generator f = (h/c) B of beam (s, k) with B = B_vac + lam e_z + nn for
-// neutrinos and B_vac - lam e_z - nn^* (nn^* = (x, -y, z)) for antineutrinos.
-__device__ __forceinline__ void gen2(int s, double bx, double bz, double lam, const double* nn,
-                                     double hc, double f[3]) {
-  double B0, B1, B2;
-  if (s == 0) {
-    B0 = bx + nn[0];
-    B1 = nn[1];
-    B2 = (bz + lam) + nn[2];
-  } else {
-    B0 = bx - nn[0];
-    B1 = nn[1];
-    B2 = (bz - lam) - nn[2];
-  }
-  f[0] = hc * B0;
-  f[1] = hc * B1;
-  f[2] = hc * B2;
-}
-
 // Stage stencil for one (species s, emission bin u) row of NE beams starting at beam rb.
 // KIND: 0 moments of rho_n at r_n; 1 stage Y2 (moments at r_n + h/2); 2 stage Y3
 // (r_n + h/2); 3 stage Y4 (r_{n+1}); 4 final update, store and moments at r_{n+1}.
@@ -501,23 +430,33 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   if constexpr (NF == 2) stage2<0>(a, step0, sJ, tab, gw, nw, lane, T, err);
   else stage3<ST, 0>(a, step0, sJ, tab, snn, gw, nw, lane, T, err);
   ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[0], a.J);
+  // the adjoint's forward pass records every stage's moments: [step][slot][NV]
+  auto record = [&](long long step, int slot) {
+    if (a.Jhist && ok && blockIdx.x == 0 && threadIdx.x < NV)
+      a.Jhist[((size_t)step * 4 + slot) * NV + threadIdx.x] = sJ[slot][threadIdx.x];
+  };
+  record(step0, 0);
   for (long long n = step0; ok && n < step0 + nsteps; ++n) {
     T = i128_zero();
     if constexpr (NF == 2) stage2<1>(a, n, sJ, tab, gw, nw, lane, T, err);
     else stage3<ST, 1>(a, n, sJ, tab, snn, gw, nw, lane, T, err);
     if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[1], a.J + NV))) break;
+    record(n, 1);
     T = i128_zero();
     if constexpr (NF == 2) stage2<2>(a, n, sJ, tab, gw, nw, lane, T, err);
     else stage3<ST, 2>(a, n, sJ, tab, snn, gw, nw, lane, T, err);
     if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[2], a.J + 2 * NV))) break;
+    record(n, 2);
     T = i128_zero();
     if constexpr (NF == 2) stage2<3>(a, n, sJ, tab, gw, nw, lane, T, err);
     else stage3<ST, 3>(a, n, sJ, tab, snn, gw, nw, lane, T, err);
     if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[3], a.J + 3 * NV))) break;
+    record(n, 3);
     T = i128_zero();
     if constexpr (NF == 2) stage2<4>(a, n, sJ, tab, gw, nw, lane, T, err);
     else stage3<ST, 4>(a, n, sJ, tab, snn, gw, nw, lane, T, err);
     ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[0], a.J);
+    record(n + 1, 0);
   }
   if (err) __hip_atomic_fetch_or(a.sync + kSyncStatus, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   // every block read the start step before the first barrier; block 0 passes the last

@@ -1,0 +1,89 @@
+// nb_stage.h -- device helpers shared by the stepping kernels and the adjoint kernel:
+// radial profiles, emission-bin geometry, the nu-nu term of a row, the two-flavour stage
+// generator and the time-limited barrier wait.
+#pragma once
+#include "nb_device.h"
+#include "nb_internal.h"
+
+namespace nb {
+
+struct Radial {
+  double q2, lam, mu, qp;  // (R/r)^2, sqrt2 G_F n_e(r), R^2/2r^2, (R/r)^ne_power
+};
+
+__device__ __forceinline__ Radial radial(double R, int ne_power, double lam0, double r) {
+  Radial g;
+  const double q = R / r;
+  g.q2 = q * q;
+  double qp = 1.0;
+  for (int i = 0; i < ne_power; ++i) qp = qp * q;
+  g.lam = lam0 * qp;     // sqrt2 G_F n_e(r)
+  g.mu = 0.5 * g.q2;     // R^2 / 2r^2 from d cos(theta') = (R^2/2r^2) du / cos(theta')
+  g.qp = qp;
+  return g;
+}
+__device__ __forceinline__ double as_double(unsigned long long u) { return __longlong_as_double((long long)u); }
+__device__ __forceinline__ unsigned long long as_bits(double d) { return (unsigned long long)__double_as_longlong(d); }
+
+// Spin until *w >= want (agent-scope acquire), giving up when another block has aborted
+// or the launch's time limit passes (then the abort word and status bit 1 are set).
+// Returns false on give-up.
+__device__ __forceinline__ bool spin_wait(unsigned* sync, unsigned long long timeout_ticks, unsigned* w,
+                                          unsigned want) {
+  const unsigned long long t0 = wall_clock64();
+  for (;;) {
+    if (__hip_atomic_load(w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= want) return true;
+    if (__hip_atomic_load(sync + kSyncAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    if (wall_clock64() - t0 > timeout_ticks) {
+      __hip_atomic_store(sync + kSyncAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_or(sync + kSyncStatus, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// Geometry of one emission bin u at the three stage radii of a step.
+struct RowGeo {
+  double c0, cm, c1, hc0, hcm, hc1;
+};
+__device__ __forceinline__ RowGeo row_geo(double u, double h, const Radial& g0, const Radial& gm,
+                                          const Radial& g1) {
+  RowGeo r;
+  r.c0 = sqrt(1.0 - u * g0.q2);
+  r.cm = sqrt(1.0 - u * gm.q2);
+  r.c1 = sqrt(1.0 - u * g1.q2);
+  r.hc0 = h / r.c0;
+  r.hcm = h / r.cm;
+  r.hc1 = h / r.c1;
+  return r;
+}
+__device__ __forceinline__ double u_of(int j, int NU) { return ((double)j + 0.5) / (double)NU; }
+// The neutrino-neutrino term mu (J0 - c J1) of a row: the same for every energy bin.
+template <int NC>
+__device__ __forceinline__ void nunu(const double* J, double mu, double c, double* nn) {
+#pragma unroll
+  for (int i = 0; i < NC; ++i) nn[i] = mu * (J[i] - c * J[NC + i]);
+}
+// ----------------------------------------------------------------- two flavours
+// Stage generator f = (h/c) B of beam (s, k) with B = B_vac + lam e_z + nn for
+// neutrinos and B_vac - lam e_z - nn^* (nn^* = (x, -y, z)) for antineutrinos.
+__device__ __forceinline__ void gen2(int s, double bx, double bz, double lam, const double* nn,
+                                     double hc, double f[3]) {
+  double B0, B1, B2;
+  if (s == 0) {
+    B0 = bx + nn[0];
+    B1 = nn[1];
+    B2 = (bz + lam) + nn[2];
+  } else {
+    B0 = bx - nn[0];
+    B1 = nn[1];
+    B2 = (bz - lam) - nn[2];
+  }
+  f[0] = hc * B0;
+  f[1] = hc * B1;
+  f[2] = hc * B2;
+}
+
+
+}  // namespace nb

@@ -1,0 +1,183 @@
+"""Reverse-mode adjoint on the GPU: against the oracle's adjoint, against central
+differences of the GPU forward integration, checkpoint-period invariance, the autograd
+wrapper, and a prefix of the 200k-beam adjoint workload.
+
+Tolerance against the oracle: the forward states are the same bits on both sides, and
+the reverse passes differ only in the order of the FP64 sums of the moment adjoints (a
+grid-wide sum per stage on the GPU, a sequential sum in the oracle) and in the sin/cos of
+the rotation Jacobians (the library's own against libm).  Those are rounding-level
+differences of a linear recursion, so gradients agree to 1e-9 relative, far inside the
+1e-6 that central differences can confirm.
+"""
+import copy
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-9
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def nb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device visible")
+    import paper_1912_10596_amd as nb
+    nb.lib()
+    return nb
+
+
+def _case(**kw):
+    args = dict(n_flavor=2, n_energy=13, n_u=4, n_steps=60, r_start_km=60.0, r_end_km=80.0,
+                n0_cm3=1e31, lum_erg_s=[3e50, 2e50, 1e50], theta=[0.5, 0.0, 0.0])
+    args.update(kw)
+    return workloads.small_params(**args)
+
+
+CASES = {
+    "fd104": (_case(), 7),
+    "ragged1260": (_case(n_energy=70, n_u=9, n_steps=40, r_end_km=75.0), 16),
+    # the 1024-beam shape with its step length, started where the step resolves it
+    "resolved1024": (workloads.resolved(dict(workloads.two_flavor_small(), n_steps=90), 700.0), 64),
+}
+
+
+def _cot(nb_beams, seed):
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, nb_beams) / nb_beams
+
+
+def _gpu_adjoint(nb, d, ckpt, c=None, state_bar=True):
+    import torch
+    m = nb.Model(d, adjoint_ckpt=ckpt)
+    ct = None if c is None else torch.as_tensor(c, device="cuda")
+    g, sb = m.adjoint(ct, want_state_bar=True)
+    return m, g, sb.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_adjoint_matches_oracle(nb, oracle, name):
+    d, ckpt = CASES[name]
+    _say(f"adjoint vs oracle: {name}")
+    o = oracle.Model(d)
+    c = _cot(o.nb, 11)
+    Lo, go, sbo = o.adjoint(ckpt, c, want_state_bar=True)
+    m, g, sb = _gpu_adjoint(nb, d, ckpt, c)
+    assert m.step_index() == d["n_steps"]
+    # same forward bits: the loss and the final state agree exactly
+    pee = m.pee().cpu().numpy()
+    np.testing.assert_array_equal(pee, o.pee().reshape(-1))
+    assert float(c @ pee) == pytest.approx(Lo, rel=1e-13)    # numpy and the oracle sum in different orders
+    np.testing.assert_allclose(g, go, rtol=RTOL, atol=0)
+    np.testing.assert_allclose(sb, sbo, rtol=RTOL, atol=RTOL * np.abs(sbo).max())
+
+
+def test_adjoint_default_cotangent_matches_oracle(nb, oracle):
+    d, ckpt = CASES["ragged1260"]
+    _, go = oracle.Model(d).adjoint(ckpt)
+    m = nb.Model(d, adjoint_ckpt=ckpt)
+    np.testing.assert_allclose(m.adjoint(), go, rtol=RTOL, atol=0)
+
+
+def test_adjoint_matches_central_differences(nb):
+    """dL/d{L_e, L_ebar, L_x, theta_v, n0} from the GPU adjoint against central
+    differences of GPU forward runs, step 1e-6 of each parameter."""
+    import torch
+    d, ckpt = CASES["fd104"]
+    m = nb.Model(d, adjoint_ckpt=ckpt)
+    c = _cot(m.nb, 3)
+    g = m.adjoint(torch.as_tensor(c, device="cuda"))
+    x0 = [*d["lum_erg_s"], d["theta"][0], d["n0_cm3"]]
+
+    def loss(x):
+        f = nb.Model(nb._with_params(d, x))
+        f.run()
+        return float(c @ f.pee().cpu().numpy())
+
+    for i in range(5):
+        h = 1e-6 * abs(x0[i])
+        xp = list(x0); xp[i] += h
+        xm = list(x0); xm[i] -= h
+        fd = (loss(xp) - loss(xm)) / (2 * h)
+        assert g[i] == pytest.approx(fd, rel=1e-6), (nb.PARAM_NAMES[i], g[i], fd)
+
+
+def test_adjoint_checkpoint_periods_bitwise(nb):
+    """Every checkpoint period recomputes the same forward bits and sums the moment
+    adjoints in the same order: identical gradients and state adjoints."""
+    d = _case(n_steps=23, r_end_km=70.0)
+    fwd = nb.Model(d); fwd.run()
+    ref = None
+    for k in (1, 5, 23, 64):
+        m = nb.Model(d, adjoint_ckpt=64)
+        g, sb = m.adjoint(None, ckpt=k, want_state_bar=True)
+        np.testing.assert_array_equal(m.get_state().cpu().numpy(), fwd.get_state().cpu().numpy())
+        if ref is None:
+            ref = (g, sb.cpu().numpy())
+        else:
+            np.testing.assert_array_equal(g, ref[0], err_msg=f"ckpt {k}")
+            np.testing.assert_array_equal(sb.cpu().numpy(), ref[1], err_msg=f"ckpt {k}")
+
+
+def test_adjoint_from_mid_run_and_repeat(nb, oracle):
+    d, ckpt = CASES["ragged1260"]
+    o = oracle.Model(d); o.step(13)
+    _, go = o.adjoint(ckpt)
+    m = nb.Model(d, adjoint_ckpt=ckpt)
+    m.step(13)
+    g1 = m.adjoint()
+    np.testing.assert_allclose(g1, go, rtol=RTOL, atol=0)
+    m.reset(); m.step(13)
+    np.testing.assert_array_equal(m.adjoint(), g1)      # bit-for-bit repeatable
+    g_end = m.adjoint()                                   # already at r_end: nothing to do
+    np.testing.assert_array_equal(g_end, np.zeros(5))
+
+
+def test_autograd_function(nb):
+    import torch
+    d, ckpt = CASES["fd104"]
+    x = torch.tensor([*d["lum_erg_s"], d["theta"][0], d["n0_cm3"]], dtype=torch.float64,
+                     requires_grad=True)
+    pee = nb.bulb_pee(x, d, ckpt)
+    c = torch.as_tensor(_cot(pee.numel(), 5), device=pee.device)
+    (c * pee).sum().backward()
+    m = nb.Model(d, adjoint_ckpt=ckpt)
+    np.testing.assert_array_equal(x.grad.numpy(), m.adjoint(c))
+
+
+def test_adjoint_rejects_unsupported(nb):
+    d3 = workloads.small_params(n_flavor=3, n_steps=4)
+    with pytest.raises(nb.NubulbError):
+        nb.Model(d3, adjoint_ckpt=2)
+    m = nb.Model(_case(n_steps=8))                        # created without adjoint_ckpt
+    with pytest.raises(nb.NubulbError):
+        m.adjoint()
+    m = nb.Model(_case(n_steps=40), adjoint_ckpt=8)       # 5 + 8 slots reserved
+    with pytest.raises(nb.NubulbError):
+        m.adjoint(ckpt=20)                                 # 2 + 20 slots needed
+    assert m.step_index() == 0
+
+
+def test_adjoint_200k_prefix(nb, oracle):
+    """The 200k-beam adjoint workload (200 E x 500 u x 2) in its resolved variant, its
+    first 70 steps with checkpoints every 64 steps (a full and a ragged segment)."""
+    d = copy.deepcopy(workloads.adjoint_200k_resolved())
+    h = (d["r_end_km"] - d["r_start_km"]) / d["n_steps"]
+    d["n_steps"] = 70
+    d["r_end_km"] = d["r_start_km"] + 70 * h
+    _say("adjoint 200k prefix: oracle")
+    _, go = oracle.Model(d).adjoint(64)
+    _say("adjoint 200k prefix: gpu")
+    m = nb.Model(d, adjoint_ckpt=64)
+    g = m.adjoint()
+    _say(f"grad gpu {g} oracle {go}")
+    np.testing.assert_allclose(g, go, rtol=RTOL, atol=0)

@@ -141,3 +141,19 @@ def test_adjoint_rejects_unsupported_modes(oracle):
         oracle.Model(workloads.small_params(n_flavor=3, n_steps=4)).adjoint(2)
     with pytest.raises(oracle.OracleError):
         oracle.Model(_case(n_steps=4)).adjoint(0)
+
+
+def test_resolved_adjoint_workload_is_resolved(oracle):
+    """At the start of the resolved adjoint variant every beam's first-stage rotation
+    angle h |B| / cos(theta) is below one radian (vacuum, matter and nu-nu terms of the
+    initial state), while at the neutrinosphere it is far above: there the step does not
+    resolve the Hamiltonian."""
+    d = dict(workloads.adjoint_200k_resolved(), n_energy=20, n_u=50)
+    h = (d["r_end_km"] - d["r_start_km"]) / d["n_steps"]
+    for r, resolved in ((d["r_start_km"], True), (d["r_nu_km"], False)):
+        m = oracle.Model(d)
+        j0, j1 = m.moments(r)
+        B = m.hamiltonian(r, j0, j1)
+        c = np.tile(np.repeat(m.cos_theta(r), d["n_energy"]), 2)
+        angle = h * np.linalg.norm(B, axis=1) / c
+        assert (angle.max() < 1.0) == resolved, (r, angle.max())

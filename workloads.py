@@ -84,6 +84,19 @@ def adjoint_200k() -> dict:
                        n0_cm3=draw_n0())
 
 
+# Start radius of the resolved adjoint variant: with the 200k workload's step length
+# (0.058 km) every beam's per-step rotation angle is below one radian from here on (matter
+# term included); nearer the neutrinosphere the step does not resolve the Hamiltonian and
+# the linearised dynamics, hence the gradients, overflow.
+ADJOINT_RESOLVED_START_KM = 500.0
+
+
+def adjoint_200k_resolved() -> dict:
+    """The 200k adjoint workload with its step length and step count kept and the start
+    moved out to ADJOINT_RESOLVED_START_KM (500 -> 790 km)."""
+    return resolved(adjoint_200k(), ADJOINT_RESOLVED_START_KM)
+
+
 def three_flavor_6m() -> dict:
     """3 flavours, 1000 E x 3000 u x 2 = 6M beams, 10 -> 500 km in 10000 steps."""
     return base_params(n_flavor=3, n_energy=1000, n_u=3000, r_end_km=500.0, n_steps=10000,
