@@ -38,6 +38,7 @@ PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X FP64 vector, published (256 CU x 2.4 GHz
 METRIC = "beam-steps/sec + HBM GB/s (3-flavor 800k beams); adjoint/forward time ratio"
 KERNEL_SOURCES = ["paper_1912_10596_amd/csrc/nb_kernels.hip",
                   "paper_1912_10596_amd/csrc/nb_device.h",
+                  "paper_1912_10596_amd/csrc/nb_stage.h",
                   "paper_1912_10596_amd/csrc/nb_internal.h"]
 
 
@@ -87,6 +88,38 @@ def traffic_from_profile(name: str, launch_steps: int, nb: int):
         return None
     per_beam_step = t["hbm_bytes_per_beam_step"]
     return per_beam_step * launch_steps * nb
+
+
+def adjoint_timing(nb, workloads):
+    """Forward run and reverse-mode adjoint (which redoes the forward pass with
+    checkpoints every 64 steps, then runs backwards) of the 200k-beam two-flavour workload
+    in its resolved variant: same shapes, step length and 5000 steps, started at 500 km
+    (nearer the neutrinosphere the step does not resolve the Hamiltonian and the gradients
+    overflow).  Wall-clock with the stream drained on both sides."""
+    import torch
+    d = workloads.adjoint_200k_resolved()
+    m = nb.Model(d, adjoint_ckpt=64)
+    m.step(8)                          # warm-up launch
+    m.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.run()
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    m.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = m.adjoint()
+    torch.cuda.synchronize()
+    ta = time.perf_counter() - t0
+    x = [*d["lum_erg_s"], d["theta"][0], d["n0_cm3"]]
+    return dict(workload=f"2-flavour bulb model, {d['n_energy']} E x {d['n_u']} u x 2 = "
+                         f"{m.nb} beams, {d['n_steps']} steps, {d['r_start_km']:g} -> "
+                         f"{d['r_end_km']:g} km (resolved variant of 10 -> 300 km)",
+                ckpt=64, forward_s=round(tf, 4), adjoint_s=round(ta, 4),
+                ratio=round(ta / tf, 3), loss="sum of dE/N_u Pee over all beams",
+                grad={k: float(v) for k, v in zip(nb.PARAM_NAMES, g)},
+                grad_times_param={k: float(v * xi) for k, v, xi in zip(nb.PARAM_NAMES, g, x)})
 
 
 def cpu_baseline(d: dict, seconds: float):
@@ -174,6 +207,12 @@ def main():
     }
     del m
     torch.cuda.empty_cache()
+    if not args.no_extras:
+        log("adjoint timing (200k beams) ...")
+        adj = adjoint_timing(nb, workloads)
+        out["adjoint"] = adj
+        out["adjoint_forward_ratio"] = adj["ratio"]
+        torch.cuda.empty_cache()
     if args.copy_probe:
         n = 1 << 27                      # 2^27 doubles = 1 GiB each way
         src = torch.ones(n, dtype=torch.float64, device="cuda")
