@@ -112,10 +112,9 @@ __device__ __forceinline__ double wave_sum_f64(double x) {
 template <int NV>
 __device__ bool grid_sum(const AdjArgs& a, unsigned epoch, double (&v)[NV], double* res,
                          double (*sw)[8], double* sred) {
-  __shared__ int s_ok;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const unsigned want = epoch + 1u;
-  double* gres = a.out + 8;
+  unsigned long long* gres = reinterpret_cast<unsigned long long*>(a.out + 8);
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     const double t = wave_sum_f64(v[i]);
@@ -125,35 +124,31 @@ __device__ bool grid_sum(const AdjArgs& a, unsigned epoch, double (&v)[NV], doub
   if (tid < NV) {
     double blk = 0.0;
     for (int w = 0; w < kBlock / 64; ++w) blk += sw[w][tid];
-    __hip_atomic_store((unsigned long long*)(a.part + (size_t)blockIdx.x * 8 + tid), as_bits(blk),
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(a.part) + (size_t)blockIdx.x * 8 + tid,
+                       as_bits(blk), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  __syncthreads();
   if (blockIdx.x != 0) {
-    if (tid == 0) {
-      __hip_atomic_store(a.sync + kSyncArrive + blockIdx.x, want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      s_ok = spin_wait(a.sync, a.timeout_ticks, a.sync + kSyncFlag, want) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!s_ok) return false;
-    if (tid < NV)
-      res[tid] = as_double(__hip_atomic_load((unsigned long long*)gres + tid, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT));
+    if (!arrive_and_wait(a.sync, a.timeout_ticks, want)) return false;
+    if (tid < NV) res[tid] = as_double(__hip_atomic_load(gres + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     __syncthreads();
     return true;
   }
-  int ok = 1;
-  for (unsigned b = 1 + tid; b < gridDim.x && ok; b += kBlock)
-    ok = spin_wait(a.sync, a.timeout_ticks, a.sync + kSyncArrive + b, want) ? 1 : 0;
-  if (__syncthreads_or(!ok)) return false;
+  if (!wait_arrivals(a.sync, a.timeout_ticks, want)) return false;
+  // fold in ascending block order (four loads in flight)
   constexpr int G = kBlock / NV;
   const int vi = tid % NV, g = tid / NV;
   if (g < G) {
+    const unsigned long long* P = reinterpret_cast<const unsigned long long*>(a.part) + vi;
+    auto ld = [&](unsigned b) {
+      return as_double(__hip_atomic_load(P + (size_t)b * 8, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    };
     double acc = 0.0;
-    for (unsigned b = g; b < gridDim.x; b += G)
-      acc += as_double(__hip_atomic_load((unsigned long long*)(a.part + (size_t)b * 8 + vi),
-                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    unsigned b = g;
+    for (; b + 3 * G < gridDim.x; b += 4 * G) {
+      const double t0 = ld(b), t1 = ld(b + G), t2 = ld(b + 2 * G), t3 = ld(b + 3 * G);
+      acc = (((acc + t0) + t1) + t2) + t3;
+    }
+    for (; b < gridDim.x; b += G) acc += ld(b);
     sred[tid] = acc;
   }
   __syncthreads();
@@ -161,13 +156,9 @@ __device__ bool grid_sum(const AdjArgs& a, unsigned epoch, double (&v)[NV], doub
     double tot = 0.0;
     for (int gg = 0; gg < G; ++gg) tot += sred[gg * NV + tid];
     res[tid] = tot;
-    __hip_atomic_store((unsigned long long*)gres + tid, as_bits(tot), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
+    __hip_atomic_store(gres + tid, as_bits(tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  __syncthreads();
-  if (tid == 0)
-    __hip_atomic_store(a.sync + kSyncFlag, want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  release_grid(a.sync, want);
   return true;
 }
 

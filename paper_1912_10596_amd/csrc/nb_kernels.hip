@@ -23,9 +23,6 @@ namespace nb {
 __device__ __forceinline__ Radial radial_at(const StepArgs& a, double r) {
   return radial(a.R, a.ne_power, a.lam0, r);
 }
-__device__ __forceinline__ bool spin_until(const StepArgs& a, unsigned* w, unsigned want) {
-  return spin_wait(a.sync, a.timeout_ticks, w, want);
-}
 
 template <int NV>
 __device__ __forceinline__ I128 select_comp(const I128 (&S)[NV], int c) {
@@ -39,52 +36,45 @@ __device__ __forceinline__ I128 select_comp(const I128 (&S)[NV], int c) {
 
 // Grid-wide reduction of the stage moments without read-modify-write contention: every
 // block publishes its partial (threads tid < NV) and then an arrival word of its own;
-// block 0 polls all arrival words in parallel, folds the partials exactly, stores the
-// stage moments (J0 | J1) and releases one flag that every other block polls.
+// block 0 waits for all arrival words, folds the partials exactly, stores the stage
+// moments (J0 | J1) and releases one flag that every other block polls.
 // Returns false if the barrier was abandoned (time limit or abort).
 template <int NV>
 __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, double* sJ,
                             double* gJ, I128* sred) {
-  __shared__ int s_ok;
   const int tid = threadIdx.x;
   const unsigned want = epoch + 1u;
   if (tid < NV) {
     unsigned long long* p = a.part + ((size_t)blockIdx.x * NV + tid) * 2;
     __hip_atomic_store(p, blk.lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(p + 1, (unsigned long long)blk.hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
   }
-  __syncthreads();
   if (blockIdx.x != 0) {
-    if (tid == 0) {
-      __hip_atomic_store(a.sync + kSyncArrive + blockIdx.x, want, __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
-      s_ok = spin_until(a, a.sync + kSyncFlag, want) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!s_ok) return false;
+    if (!arrive_and_wait(a.sync, a.timeout_ticks, want)) return false;
     if (tid < NV)
       sJ[tid] = as_double(__hip_atomic_load((unsigned long long*)gJ + tid, __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT));
     __syncthreads();
     return true;
   }
-  // block 0: wait for every arrival word
-  int ok = 1;
-  for (unsigned b = 1 + tid; b < gridDim.x && ok; b += kBlock)
-    ok = spin_until(a, a.sync + kSyncArrive + b, want) ? 1 : 0;
-  if (__syncthreads_or(!ok)) return false;
+  if (!wait_arrivals(a.sync, a.timeout_ticks, want)) return false;
+  // fold: thread (v, g) adds partial v of blocks g, g + G, ... (four loads in flight)
   constexpr int G = kBlock / NV;
   const int v = tid % NV, g = tid / NV;
   if (g < G) {
+    const unsigned long long* P = a.part + (size_t)v * 2;
+    auto ld = [&](unsigned b) {
+      const unsigned long long* q = P + (size_t)b * NV * 2;
+      return I128{__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                  (long long)__hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
+    };
     I128 acc = i128_zero();
-    for (unsigned b = g; b < gridDim.x; b += G) {
-      const unsigned long long* p = a.part + ((size_t)b * NV + v) * 2;
-      I128 t;
-      t.lo = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      t.hi = (long long)__hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      acc = i128_add(acc, t);
+    unsigned b = g;
+    for (; b + 3 * G < gridDim.x; b += 4 * G) {
+      const I128 t0 = ld(b), t1 = ld(b + G), t2 = ld(b + 2 * G), t3 = ld(b + 3 * G);
+      acc = i128_add(i128_add(i128_add(i128_add(acc, t0), t1), t2), t3);
     }
+    for (; b < gridDim.x; b += G) acc = i128_add(acc, ld(b));
     sred[tid] = acc;
   }
   __syncthreads();
@@ -95,11 +85,8 @@ __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, double*
     sJ[tid] = val;
     __hip_atomic_store((unsigned long long*)gJ + tid, as_bits(val), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
   }
-  __syncthreads();
-  if (tid == 0)
-    __hip_atomic_store(a.sync + kSyncFlag, want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  release_grid(a.sync, want);
   return true;
 }
 
@@ -502,30 +489,13 @@ __device__ __forceinline__ unsigned long long* acc_slot(const BatchArgs& a, unsi
   return a.acc + ((size_t)(epoch % kAccSets) * a.nmodels + m) * 6 * kAccLimbs;
 }
 
-// Flags-only grid barrier (the sums are already in the accumulators).
+// Flags-only grid barrier (the sums are already in the accumulators, added with
+// agent-scope atomics before the workgroup barrier inside the arrival).
 __device__ bool grid_barrier(const BatchArgs& a, unsigned epoch) {
-  __shared__ int s_ok;
   const unsigned want = epoch + 1u;
-  __threadfence();   // every wave's accumulator atomics complete before the arrival
-  __syncthreads();
-  StepArgs sa{};
-  sa.sync = a.sync;
-  sa.timeout_ticks = a.timeout_ticks;
-  if (blockIdx.x != 0) {
-    if (threadIdx.x == 0) {
-      __hip_atomic_store(a.sync + kSyncArrive + blockIdx.x, want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      s_ok = spin_until(sa, a.sync + kSyncFlag, want) ? 1 : 0;
-    }
-    __syncthreads();
-    return s_ok != 0;
-  }
-  int ok = 1;
-  for (unsigned b = 1 + threadIdx.x; b < gridDim.x && ok; b += kBlock)
-    ok = spin_until(sa, a.sync + kSyncArrive + b, want) ? 1 : 0;
-  if (__syncthreads_or(!ok)) return false;
-  if (threadIdx.x == 0)
-    __hip_atomic_store(a.sync + kSyncFlag, want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
+  if (blockIdx.x != 0) return arrive_and_wait(a.sync, a.timeout_ticks, want);
+  if (!wait_arrivals(a.sync, a.timeout_ticks, want)) return false;
+  release_grid(a.sync, want);
   return true;
 }
 

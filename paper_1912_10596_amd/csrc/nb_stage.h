@@ -25,14 +25,20 @@ __device__ __forceinline__ Radial radial(double R, int ne_power, double lam0, do
 __device__ __forceinline__ double as_double(unsigned long long u) { return __longlong_as_double((long long)u); }
 __device__ __forceinline__ unsigned long long as_bits(double d) { return (unsigned long long)__double_as_longlong(d); }
 
-// Spin until *w >= want (agent-scope acquire), giving up when another block has aborted
-// or the launch's time limit passes (then the abort word and status bit 1 are set).
-// Returns false on give-up.
-__device__ __forceinline__ bool spin_wait(unsigned* sync, unsigned long long timeout_ticks, unsigned* w,
-                                          unsigned want) {
+// Grid barriers.  Cross-block data (block partials, reduced moments, arrival words and
+// the release flag) are written and read only with agent-scope atomics.  A block
+// publishes its partials, meets its other threads at a workgroup barrier, and one thread
+// stores the block's arrival word with release semantics; the waiting side polls with
+// relaxed loads and issues one acquire fence once the word is seen.  So each block pays
+// one L2 write-back and one invalidate per barrier, not one per polling iteration.
+
+// Poll *w (relaxed) until it reaches want; gives up when another block has aborted or the
+// launch's time limit passes (then it sets the abort word and status bit 1).
+__device__ __forceinline__ bool poll_until(unsigned* sync, unsigned long long timeout_ticks, unsigned* w,
+                                           unsigned want) {
   const unsigned long long t0 = wall_clock64();
   for (;;) {
-    if (__hip_atomic_load(w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= want) return true;
+    if (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want) return true;
     if (__hip_atomic_load(sync + kSyncAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
     if (wall_clock64() - t0 > timeout_ticks) {
       __hip_atomic_store(sync + kSyncAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -41,6 +47,44 @@ __device__ __forceinline__ bool spin_wait(unsigned* sync, unsigned long long tim
     }
     __builtin_amdgcn_s_sleep(1);
   }
+}
+// Poll, then acquire (one thread).
+__device__ __forceinline__ bool spin_wait(unsigned* sync, unsigned long long timeout_ticks, unsigned* w,
+                                          unsigned want) {
+  const bool ok = poll_until(sync, timeout_ticks, w, want);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return ok;
+}
+// Block 0 of a barrier (all its threads call this): the first wavefront waits until every
+// other block's arrival word has reached want, then acquires.  Returns false on give-up.
+__device__ __forceinline__ bool wait_arrivals(unsigned* sync, unsigned long long timeout_ticks,
+                                              unsigned want) {
+  int ok = 1;
+  if (threadIdx.x < 64) {
+    for (unsigned b = 1 + threadIdx.x; b < gridDim.x && ok; b += 64)
+      ok = poll_until(sync, timeout_ticks, sync + kSyncArrive + b, want) ? 1 : 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  return !__syncthreads_or(!ok);
+}
+// A non-zero block arrives (all its threads call this, after their partial stores) and
+// waits for block 0's release flag.  Returns false on give-up.
+__device__ __forceinline__ bool arrive_and_wait(unsigned* sync, unsigned long long timeout_ticks,
+                                                unsigned want) {
+  __shared__ int s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(sync + kSyncArrive + blockIdx.x, want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    s_ok = spin_wait(sync, timeout_ticks, sync + kSyncFlag, want) ? 1 : 0;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+// Block 0 releases the grid (all its threads call this, after their result stores).
+__device__ __forceinline__ void release_grid(unsigned* sync, unsigned want) {
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_store(sync + kSyncFlag, want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Geometry of one emission bin u at the three stage radii of a step.
