@@ -58,7 +58,7 @@ __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, double*
     return true;
   }
   if (!wait_arrivals(a.sync, a.timeout_ticks, want)) return false;
-  // fold: thread (v, g) adds partial v of blocks g, g + G, ... (four loads in flight)
+  // fold: thread (v, g) adds partial v of blocks g, g + G, ... (eight loads in flight)
   constexpr int G = kBlock / NV;
   const int v = tid % NV, g = tid / NV;
   if (g < G) {
@@ -70,9 +70,12 @@ __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, double*
     };
     I128 acc = i128_zero();
     unsigned b = g;
-    for (; b + 3 * G < gridDim.x; b += 4 * G) {
-      const I128 t0 = ld(b), t1 = ld(b + G), t2 = ld(b + 2 * G), t3 = ld(b + 3 * G);
-      acc = i128_add(i128_add(i128_add(i128_add(acc, t0), t1), t2), t3);
+    for (; b + 7 * G < gridDim.x; b += 8 * G) {
+      I128 t[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) t[i] = ld(b + i * G);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc = i128_add(acc, t[i]);
     }
     for (; b < gridDim.x; b += G) acc = i128_add(acc, ld(b));
     sred[tid] = acc;

@@ -25,12 +25,15 @@ __device__ __forceinline__ Radial radial(double R, int ne_power, double lam0, do
 __device__ __forceinline__ double as_double(unsigned long long u) { return __longlong_as_double((long long)u); }
 __device__ __forceinline__ unsigned long long as_bits(double d) { return (unsigned long long)__double_as_longlong(d); }
 
-// Grid barriers.  Cross-block data (block partials, reduced moments, arrival words and
-// the release flag) are written and read only with agent-scope atomics.  A block
-// publishes its partials, meets its other threads at a workgroup barrier, and one thread
-// stores the block's arrival word with release semantics; the waiting side polls with
-// relaxed loads and issues one acquire fence once the word is seen.  So each block pays
-// one L2 write-back and one invalidate per barrier, not one per polling iteration.
+// Grid barriers.  Within one launch a beam's state is touched only by the wavefront that
+// owns its row, so the only data that crosses blocks are the block partials, the reduced
+// moments and the barrier words -- and every one of those is written and read with
+// agent-scope atomics, which are coherent at the device level without L2 write-back or
+// invalidation.  Ordering comes from the protocol itself: a block's partial stores
+// complete before its arrival word is stored (the workgroup barrier in between waits for
+// all of the block's outstanding memory operations), and a waiter issues its loads of the
+// published data only after it has read the word that announces them.  So the barrier
+// needs no cache maintenance at all: the state written in the same stage stays in L2.
 
 // Poll *w (relaxed) until it reaches want; gives up when another block has aborted or the
 // launch's time limit passes (then it sets the abort word and status bit 1).
@@ -48,22 +51,32 @@ __device__ __forceinline__ bool poll_until(unsigned* sync, unsigned long long ti
     __builtin_amdgcn_s_sleep(1);
   }
 }
-// Poll, then acquire (one thread).
-__device__ __forceinline__ bool spin_wait(unsigned* sync, unsigned long long timeout_ticks, unsigned* w,
-                                          unsigned want) {
-  const bool ok = poll_until(sync, timeout_ticks, w, want);
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return ok;
-}
-// Block 0 of a barrier (all its threads call this): the first wavefront waits until every
-// other block's arrival word has reached want, then acquires.  Returns false on give-up.
+// Block 0 of a barrier (all its threads call this): the first wavefront polls every other
+// block's arrival word, all of a lane's words per round so that their loads overlap.
+// Returns false on give-up.
 __device__ __forceinline__ bool wait_arrivals(unsigned* sync, unsigned long long timeout_ticks,
                                               unsigned want) {
   int ok = 1;
   if (threadIdx.x < 64) {
-    for (unsigned b = 1 + threadIdx.x; b < gridDim.x && ok; b += 64)
-      ok = poll_until(sync, timeout_ticks, sync + kSyncArrive + b, want) ? 1 : 0;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const unsigned long long t0 = wall_clock64();
+    for (;;) {
+      unsigned lowest = 0xffffffffu;
+      for (unsigned b = 1 + threadIdx.x; b < gridDim.x; b += 64)
+        lowest = min(lowest, __hip_atomic_load(sync + kSyncArrive + b, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT));
+      if (lowest >= want) break;
+      if (__hip_atomic_load(sync + kSyncAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        ok = 0;
+        break;
+      }
+      if (wall_clock64() - t0 > timeout_ticks) {
+        __hip_atomic_store(sync + kSyncAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_or(sync + kSyncStatus, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
   }
   return !__syncthreads_or(!ok);
 }
@@ -74,8 +87,8 @@ __device__ __forceinline__ bool arrive_and_wait(unsigned* sync, unsigned long lo
   __shared__ int s_ok;
   __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_store(sync + kSyncArrive + blockIdx.x, want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    s_ok = spin_wait(sync, timeout_ticks, sync + kSyncFlag, want) ? 1 : 0;
+    __hip_atomic_store(sync + kSyncArrive + blockIdx.x, want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_ok = poll_until(sync, timeout_ticks, sync + kSyncFlag, want) ? 1 : 0;
   }
   __syncthreads();
   return s_ok != 0;
@@ -84,7 +97,7 @@ __device__ __forceinline__ bool arrive_and_wait(unsigned* sync, unsigned long lo
 __device__ __forceinline__ void release_grid(unsigned* sync, unsigned want) {
   __syncthreads();
   if (threadIdx.x == 0)
-    __hip_atomic_store(sync + kSyncFlag, want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(sync + kSyncFlag, want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Geometry of one emission bin u at the three stage radii of a step.
