@@ -111,14 +111,37 @@ __device__ bool finish_stage(const StepArgs& a, unsigned epoch, I128 T, I128 (*s
 struct Scales {
   double s1, s0, p2e1, p2e0;
 };
-// End of a row segment: lane sums -> exact wave sums; lane v keeps component v % NC.
+// End of a row segment: the lanes' 64-bit sums -> exact per-component wave sums, added to
+// `mine` of lanes v < 2 NC (component v % NC).  Through this wave's LDS scratch fl
+// ((NC + 2) x 64 words): every lane stores its NC sums; lane (g, c) of G = 64/NC groups adds
+// component c of L = ceil(64/G) lanes as a 128-bit integer; lanes v < 2 NC add the G group
+// sums of component v % NC.  Integer sums, so the order does not matter.
 template <int NC>
-__device__ __forceinline__ void fold_segment(const long long* acc, int lane, I128& mine) {
+__device__ __forceinline__ void fold_segment(const long long* acc, int lane, long long* fl, I128& mine) {
+  constexpr int G = 64 / NC, L = (64 + G - 1) / G;
 #pragma unroll
-  for (int i = 0; i < NC; ++i) {
-    const I128 t = wave_sum(i128_from(acc[i]));
-    if (lane % NC == i) mine = i128_add(mine, t);
+  for (int i = 0; i < NC; ++i) fl[i * 64 + lane] = acc[i];
+  __asm__ volatile("" ::: "memory");   // the wave's LDS operations complete in program order
+  I128* gs = reinterpret_cast<I128*>(fl + NC * 64);
+  const int c = lane % NC, g = lane / NC;
+  if (g < G) {
+    I128 part = i128_zero();
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      const int src = g * L + i;
+      if (src < 64) part = i128_add(part, i128_from(fl[c * 64 + src]));
+    }
+    gs[g * NC + c] = part;
   }
+  __asm__ volatile("" ::: "memory");
+  if (lane < 2 * NC) {
+    const int cc = lane % NC;
+    I128 t = i128_zero();
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) t = i128_add(t, gs[gg * NC + cc]);
+    mine = i128_add(mine, t);
+  }
+  __asm__ volatile("" ::: "memory");
 }
 // End of a row: lanes v < NC add the J0 angle term (energy sum / cos), lanes
 // NC <= v < 2 NC the J1 energy sum, to their running totals.
@@ -142,7 +165,8 @@ template <int KIND>
 __device__ __forceinline__ void row2(double* X, long long plane, long long rb, int NE, int s,
                                      double u, double h, const double* tab, const Radial& g0,
                                      const Radial& gm, const Radial& g1, const double* const* J,
-                                     const Scales& sc, int renorm, int lane, I128& T, int& err) {
+                                     const Scales& sc, int renorm, int lane, long long* fl, I128& T,
+                                     int& err) {
   const RowGeo rg = row_geo(u, h, g0, gm, g1);
   const double icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
   double n1[3], n2[3], n3[3], n4[3];
@@ -210,7 +234,7 @@ __device__ __forceinline__ void row2(double* X, long long plane, long long rb, i
       acc[1] += to_fix(w * P1, sc.s1, kTwo58, err);
       acc[2] += to_fix(w * v2, sc.s1, kTwo58, err);
     }
-    fold_segment<3>(acc, lane, mine);
+    fold_segment<3>(acc, lane, fl, mine);
   }
   close_row<3>(sc, lane, mine, icmom, T, err);
 }
@@ -218,7 +242,7 @@ __device__ __forceinline__ void row2(double* X, long long plane, long long rb, i
 template <int KIND>
 __device__ __forceinline__ void stage2(const StepArgs& a, long long n, const double (*sJ)[6],
                                        const double* tab, long long gw, long long nw, int lane,
-                                       I128& T, int& err) {
+                                       long long* fl, I128& T, int& err) {
   const double r0 = a.rs + (double)n * a.h;
   const double rm = r0 + 0.5 * a.h;
   const double r1 = a.rs + (double)(n + 1) * a.h;
@@ -230,7 +254,7 @@ __device__ __forceinline__ void stage2(const StepArgs& a, long long n, const dou
     const int s = (int)(row / a.NU);
     const int j = (int)(row - (long long)s * a.NU);
     row2<KIND>((double*)a.X, a.plane, row * a.NE, a.NE, s, u_of(j, a.NU), a.h, tab, g0, gm, g1,
-               J, sc, a.renorm, lane, T, err);
+               J, sc, a.renorm, lane, fl, T, err);
   }
 }
 
@@ -263,7 +287,7 @@ __device__ __forceinline__ Herm3 gen3(int s, const double* v, double lam, const 
 template <typename ST, int KIND>
 __device__ __forceinline__ void stage3(const StepArgs& a, long long n, const double (*sJ)[16],
                                        const double* tab, double* snn, long long gw,
-                                       long long nw, int lane, I128& T, int& err) {
+                                       long long nw, int lane, long long* fl, I128& T, int& err) {
   const double r0 = a.rs + (double)n * a.h;
   const double rm = r0 + 0.5 * a.h;
   const double r1 = a.rs + (double)(n + 1) * a.h;
@@ -382,7 +406,7 @@ __device__ __forceinline__ void stage3(const StepArgs& a, long long n, const dou
 #pragma unroll
         for (int i = 0; i < 8; ++i) acc[i] += to_fix(w * v8[i], a.s1, kTwo58, err);
       }
-      fold_segment<8>(acc, lane, mine);
+      fold_segment<8>(acc, lane, fl, mine);
     }
     close_row<8>(Scales{a.s1, a.s0, a.p2e1, a.p2e0}, lane, mine, icmom, T, err);
   }
@@ -399,6 +423,7 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   __shared__ I128 sw[kBlock / 64][NV];
   __shared__ I128 sred[kBlock];
   __shared__ double snn_all[kBlock / 64][32];
+  __shared__ long long sfold[kBlock / 64][(NC + 2) * 64];
   extern __shared__ double dyn_tab[];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const long long gw = (long long)blockIdx.x * (kBlock / 64) + wid;
@@ -411,14 +436,15 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
     tab = dyn_tab;
   }
   double* snn = snn_all[wid];
+  long long* fl = sfold[wid];
   const long long step0 = *a.step_ctl;
   const long long nsteps = max(0LL, min(a.nsteps, a.total_steps - step0));
   unsigned epoch = 0;
   int err = 0;
   bool ok = true;
   I128 T = i128_zero();
-  if constexpr (NF == 2) stage2<0>(a, step0, sJ, tab, gw, nw, lane, T, err);
-  else stage3<ST, 0>(a, step0, sJ, tab, snn, gw, nw, lane, T, err);
+  if constexpr (NF == 2) stage2<0>(a, step0, sJ, tab, gw, nw, lane, fl, T, err);
+  else stage3<ST, 0>(a, step0, sJ, tab, snn, gw, nw, lane, fl, T, err);
   ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[0], a.J);
   // the adjoint's forward pass records every stage's moments: [step][slot][NV]
   auto record = [&](long long step, int slot) {
@@ -428,23 +454,23 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   record(step0, 0);
   for (long long n = step0; ok && n < step0 + nsteps; ++n) {
     T = i128_zero();
-    if constexpr (NF == 2) stage2<1>(a, n, sJ, tab, gw, nw, lane, T, err);
-    else stage3<ST, 1>(a, n, sJ, tab, snn, gw, nw, lane, T, err);
+    if constexpr (NF == 2) stage2<1>(a, n, sJ, tab, gw, nw, lane, fl, T, err);
+    else stage3<ST, 1>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
     if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[1], a.J + NV))) break;
     record(n, 1);
     T = i128_zero();
-    if constexpr (NF == 2) stage2<2>(a, n, sJ, tab, gw, nw, lane, T, err);
-    else stage3<ST, 2>(a, n, sJ, tab, snn, gw, nw, lane, T, err);
+    if constexpr (NF == 2) stage2<2>(a, n, sJ, tab, gw, nw, lane, fl, T, err);
+    else stage3<ST, 2>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
     if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[2], a.J + 2 * NV))) break;
     record(n, 2);
     T = i128_zero();
-    if constexpr (NF == 2) stage2<3>(a, n, sJ, tab, gw, nw, lane, T, err);
-    else stage3<ST, 3>(a, n, sJ, tab, snn, gw, nw, lane, T, err);
+    if constexpr (NF == 2) stage2<3>(a, n, sJ, tab, gw, nw, lane, fl, T, err);
+    else stage3<ST, 3>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
     if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[3], a.J + 3 * NV))) break;
     record(n, 3);
     T = i128_zero();
-    if constexpr (NF == 2) stage2<4>(a, n, sJ, tab, gw, nw, lane, T, err);
-    else stage3<ST, 4>(a, n, sJ, tab, snn, gw, nw, lane, T, err);
+    if constexpr (NF == 2) stage2<4>(a, n, sJ, tab, gw, nw, lane, fl, T, err);
+    else stage3<ST, 4>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
     ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[0], a.J);
     record(n + 1, 0);
   }
@@ -504,7 +530,7 @@ __device__ bool grid_barrier(const BatchArgs& a, unsigned epoch) {
 
 template <int KIND>
 __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, long long r0w,
-                            long long r1w, int lane, double (*Jv)[6], int& err) {
+                            long long r1w, int lane, double (*Jv)[6], long long* fl, int& err) {
   const double r0 = a.rs + (double)n * a.h;
   const double rm = r0 + 0.5 * a.h;
   const double r1 = a.rs + (double)(n + 1) * a.h;
@@ -557,7 +583,7 @@ __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, lon
     const int s = (int)(lr / mNU);
     const int j = (int)(lr - (long long)s * mNU);
     row2<KIND>(a.X, a.plane, mbeam0 + lr * mNE, mNE, s, u_of(j, mNU), a.h, a.tab + mtab0,
-               g0, gm, g1, J, sc, a.renorm, lane, T, err);
+               g0, gm, g1, J, sc, a.renorm, lane, fl, T, err);
   }
   if (m >= 0 && lane < 6) acc_add(acc_slot(a, epoch, m) + lane * kAccLimbs, T);
   // clear the set the next epoch will collect into
@@ -570,6 +596,7 @@ __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, lon
 
 __global__ void __launch_bounds__(kBlock) k_batch2(BatchArgs a) {
   __shared__ double sJw[kBlock / 64][4][6];
+  __shared__ long long sfold[kBlock / 64][(3 + 2) * 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   double (*Jv)[6] = sJw[wid];
   const long long w = (long long)blockIdx.x * (kBlock / 64) + wid;
@@ -580,16 +607,16 @@ __global__ void __launch_bounds__(kBlock) k_batch2(BatchArgs a) {
   unsigned epoch = 0;
   int err = 0;
   bool ok;
-  batch_stage<0>(a, step0, epoch, r0w, r1w, lane, Jv, err);
+  batch_stage<0>(a, step0, epoch, r0w, r1w, lane, Jv, sfold[wid], err);
   ok = grid_barrier(a, epoch++);
   for (long long n = step0; ok && n < step0 + nsteps; ++n) {
-    batch_stage<1>(a, n, epoch, r0w, r1w, lane, Jv, err);
+    batch_stage<1>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], err);
     if (!(ok = grid_barrier(a, epoch++))) break;
-    batch_stage<2>(a, n, epoch, r0w, r1w, lane, Jv, err);
+    batch_stage<2>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], err);
     if (!(ok = grid_barrier(a, epoch++))) break;
-    batch_stage<3>(a, n, epoch, r0w, r1w, lane, Jv, err);
+    batch_stage<3>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], err);
     if (!(ok = grid_barrier(a, epoch++))) break;
-    batch_stage<4>(a, n, epoch, r0w, r1w, lane, Jv, err);
+    batch_stage<4>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], err);
     ok = grid_barrier(a, epoch++);
   }
   if (err) __hip_atomic_fetch_or(a.sync + kSyncStatus, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
