@@ -36,17 +36,20 @@ __device__ __forceinline__ unsigned long long as_bits(double d) { return (unsign
 // needs no cache maintenance at all: the state written in the same stage stays in L2.
 
 // Poll *w (relaxed) until it reaches want; gives up when another block has aborted or the
-// launch's time limit passes (then it sets the abort word and status bit 1).
+// launch's time limit passes (then it sets the abort word and status bit 1).  The abort
+// word and the clock are read only every 32nd poll, so a poll costs one load round trip.
 __device__ __forceinline__ bool poll_until(unsigned* sync, unsigned long long timeout_ticks, unsigned* w,
                                            unsigned want) {
   const unsigned long long t0 = wall_clock64();
-  for (;;) {
+  for (unsigned it = 1;; ++it) {
     if (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want) return true;
-    if (__hip_atomic_load(sync + kSyncAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
-    if (wall_clock64() - t0 > timeout_ticks) {
-      __hip_atomic_store(sync + kSyncAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_or(sync + kSyncStatus, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return false;
+    if ((it & 31u) == 0u) {
+      if (__hip_atomic_load(sync + kSyncAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+      if (wall_clock64() - t0 > timeout_ticks) {
+        __hip_atomic_store(sync + kSyncAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_or(sync + kSyncStatus, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
     }
     __builtin_amdgcn_s_sleep(1);
   }
@@ -59,21 +62,23 @@ __device__ __forceinline__ bool wait_arrivals(unsigned* sync, unsigned long long
   int ok = 1;
   if (threadIdx.x < 64) {
     const unsigned long long t0 = wall_clock64();
-    for (;;) {
+    for (unsigned it = 1;; ++it) {
       unsigned lowest = 0xffffffffu;
       for (unsigned b = 1 + threadIdx.x; b < gridDim.x; b += 64)
         lowest = min(lowest, __hip_atomic_load(sync + kSyncArrive + b, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT));
       if (lowest >= want) break;
-      if (__hip_atomic_load(sync + kSyncAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        ok = 0;
-        break;
-      }
-      if (wall_clock64() - t0 > timeout_ticks) {
-        __hip_atomic_store(sync + kSyncAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_or(sync + kSyncStatus, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ok = 0;
-        break;
+      if ((it & 31u) == 0u) {
+        if (__hip_atomic_load(sync + kSyncAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          ok = 0;
+          break;
+        }
+        if (wall_clock64() - t0 > timeout_ticks) {
+          __hip_atomic_store(sync + kSyncAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_or(sync + kSyncStatus, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
       }
       __builtin_amdgcn_s_sleep(1);
     }
