@@ -122,6 +122,47 @@ def adjoint_timing(nb, workloads):
                 grad_times_param={k: float(v * xi) for k, v, xi in zip(nb.PARAM_NAMES, g, x)})
 
 
+def mixed_precision(nb, workloads, literal_steps: int):
+    """Mixed precision (FP32 state and, where the step resolves every beam, FP32 stage
+    arithmetic; FP64 moments and renormalisation) against FP64 on the 6M-beam 3-flavour
+    workload: the full resolved variant (600 -> 1090 km, 10000 steps, FP32 arithmetic from
+    the first step) and a prefix of the literal run (10 -> 500 km, unresolved throughout, so
+    the mixed mode keeps FP64 arithmetic there).  Times are HIP events around the stepping
+    calls; max |dP_ee| is against the FP64 GPU run, which is bitwise the oracle."""
+    import numpy as np
+    import torch
+
+    def one(d, precision, steps):
+        m = nb.Model(d, precision=precision)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        m.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        pee = m.pee().cpu().numpy()
+        k = m.mixed_fp32_step() if precision else None
+        del m
+        torch.cuda.empty_cache()
+        return e0.elapsed_time(e1) / 1e3, pee, k
+
+    out = {}
+    for label, d, steps in (("resolved_full", workloads.three_flavor_6m_resolved(), None),
+                            ("literal_prefix", workloads.three_flavor_6m(), literal_steps)):
+        steps = d["n_steps"] if steps is None else steps
+        t64, p64, _ = one(d, 0, steps)
+        t32, p32, k = one(d, 1, steps)
+        out[label] = dict(
+            workload=f"3-flavour, {d['n_energy']} E x {d['n_u']} u x 2 = "
+                     f"{2 * d['n_energy'] * d['n_u']} beams, {d['r_start_km']:g} -> "
+                     f"{d['r_end_km']:g} km, {steps} of {d['n_steps']} steps",
+            fp32_arithmetic_from_step=k, fp64_s=round(t64, 4), mixed_s=round(t32, 4),
+            speed_ratio=round(t64 / t32, 3), max_abs_dpee=float(np.abs(p64 - p32).max()),
+            mean_abs_dpee=float(np.abs(p64 - p32).mean()))
+    return out
+
+
 def cpu_baseline(d: dict, seconds: float):
     """The oracle as it stands, on this host's cores, over a bounded prefix of the same
     workload (whole steps of every beam until `seconds` of CPU time have passed)."""
@@ -149,7 +190,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the adjoint and mixed-precision measurements")
+    ap.add_argument("--mixed-literal-steps", type=int, default=2000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -213,6 +256,8 @@ def main():
         out["adjoint"] = adj
         out["adjoint_forward_ratio"] = adj["ratio"]
         torch.cuda.empty_cache()
+        log("mixed precision (6M beams) ...")
+        out["mixed_precision"] = mixed_precision(nb, workloads, args.mixed_literal_steps)
     if args.copy_probe:
         n = 1 << 27                      # 2^27 doubles = 1 GiB each way
         src = torch.ones(n, dtype=torch.float64, device="cuda")

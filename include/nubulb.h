@@ -106,6 +106,14 @@ int nb_read_pee(const nb_model *m, double *dev_out);
 int nb_get_state(const nb_model *m, double *dst, int on_device);
 int nb_set_state(nb_model *m, const double *src, int64_t step, int on_device);
 
+/* Mixed precision (3 flavours, precision = NB_FP32_STATE): the state is stored in FP32; the
+ * moment sums and the renormalisation of each updated state are FP64.  The per-beam stage
+ * arithmetic (generators, commutators, exponentials) is FP32 from the returned step on,
+ * where an a-priori bound shows every beam's per-step rotation angle below one radian, and
+ * FP64 before it (nearer the neutrinosphere FP32 cannot hold the per-step phase).  Returns
+ * that step (n_steps if FP32 arithmetic is never used), or -1 for other models. */
+int64_t nb_mixed_fp32_step(const nb_model *m);
+
 /* HIP graph of one stepping launch: nb_graph_capture records "advance n_steps from the
  * device step counter" (n_steps >= 1) on the bound stream (which must not be the NULL
  * stream) into a graph held by the model; nb_graph_launch replays it and checks the

@@ -22,6 +22,7 @@ EXPORTS = [
     "nb_step", "nb_run", "nb_step_index", "nb_read_pee", "nb_get_state", "nb_set_state",
     "nb_adjoint", "nb_host_tables", "nb_last_error", "nb_test_sincos", "nb_test_sqrt_div",
     "nb_test_exp3", "nb_test_rotate", "nb_graph_capture", "nb_graph_launch", "nb_autotune",
+    "nb_mixed_fp32_step",
 ]
 
 
@@ -72,6 +73,8 @@ def lib():
         L.nb_run.argtypes = [vp]
         L.nb_step_index.argtypes = [vp]
         L.nb_step_index.restype = i64
+        L.nb_mixed_fp32_step.argtypes = [vp]
+        L.nb_mixed_fp32_step.restype = i64
         L.nb_read_pee.argtypes = [vp, vp]
         L.nb_get_state.argtypes = [vp, vp, C.c_int]
         L.nb_set_state.argtypes = [vp, vp, i64, C.c_int]
@@ -145,6 +148,10 @@ class HostModel:
         self.nsc = int(lib().nb_state_comps(h))
         self.nf = int(d["n_flavor"])
         self.n_models = int(lib().nb_n_models(h))
+
+    def mixed_fp32_step(self) -> int:
+        """First step advanced with FP32 stage arithmetic (mixed precision), or -1."""
+        return int(lib().nb_mixed_fp32_step(self.h))
 
     def offsets(self):
         off = (C.c_int64 * (self.n_models + 1))()

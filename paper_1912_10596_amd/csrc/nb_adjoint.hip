@@ -129,7 +129,9 @@ __device__ bool grid_sum(const AdjArgs& a, unsigned epoch, double (&v)[NV], doub
   }
   if (blockIdx.x != 0) {
     if (!arrive_and_wait(a.sync, a.timeout_ticks, want)) return false;
-    if (tid < NV) res[tid] = as_double(__hip_atomic_load(gres + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (tid < NV)
+      res[tid] = as_double(__hip_atomic_load(gres + (size_t)(blockIdx.x % kFlagCopies) * 8 + tid, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT));
     __syncthreads();
     return true;
   }
@@ -156,7 +158,8 @@ __device__ bool grid_sum(const AdjArgs& a, unsigned epoch, double (&v)[NV], doub
     double tot = 0.0;
     for (int gg = 0; gg < G; ++gg) tot += sred[gg * NV + tid];
     res[tid] = tot;
-    __hip_atomic_store(gres + tid, as_bits(tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int c = 0; c < kFlagCopies; ++c)
+      __hip_atomic_store(gres + (size_t)c * 8 + tid, as_bits(tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   release_grid(a.sync, want);
   return true;

@@ -15,7 +15,7 @@
 #include "nb_internal.h"
 
 namespace nb {
-template <int NF, typename ST, bool TLDS>
+template <int NF, typename ST, bool TLDS, bool F32>
 __global__ void k_advance(StepArgs a);
 __global__ void k_batch2(BatchArgs a);
 template <int BPT>
@@ -23,6 +23,7 @@ __global__ void k_adjoint2(AdjArgs a);
 __global__ void k_zero_sync(unsigned int* sync, int keep_status);
 __global__ void k_zero_u64(unsigned long long* p, long long n);
 __global__ void k_set_step(long long* step_ctl, long long step);
+__global__ void k_set_target(long long* step_ctl, long long k, long long total);
 template <typename ST>
 __global__ void k_init(ST* X, long long nb, long long plane, int nsc);
 template <typename ST>
@@ -80,6 +81,8 @@ struct Sub {
   nb_params p{};
   long long NE = 0, NU = 0, beam0 = 0, row0 = 0, tab0 = 0;
   double h = 0, lam0 = 0, kappa0 = 0, s1 = 0, s0 = 0, p2e1 = 0, p2e0 = 0;
+  double vac_max = 0;                // max over energy bins of sum |H_vac entries|
+  long long fp32_from = 0;           // mixed precision: first step run with FP32 arithmetic
   int e1 = 0, e0 = 0, nf = 2;
   std::vector<double> E, tab;
   std::vector<double> dtab;          // 2f: [dG0/dL_e | dG1/dL_ebar | dG/dL_x | dbx/dth | dbz/dth] x NE
@@ -204,6 +207,17 @@ static void build_tables(Sub* m) {
         m->tab[(size_t)q * NE + k] = (U[ia[q]][1] * U[ib[q]][1]) * w2 + (U[ia[q]][2] * U[ib[q]][2]) * w3;
     }
   }
+  // largest sum of |entries| of the traceless vacuum Hamiltonian over the energy bins
+  m->vac_max = 0.0;
+  if (m->nf == 3) {
+    for (long long k = 0; k < NE; ++k) {
+      const double tr = (m->tab[k] + m->tab[NE + k] + m->tab[2 * NE + k]) / 3.0;
+      double sv = 0.0;
+      for (int q = 0; q < 3; ++q) sv += std::fabs(m->tab[(size_t)q * NE + k] - tr);
+      for (int q = 3; q < 6; ++q) sv += 2.0 * std::fabs(m->tab[(size_t)q * NE + k]);
+      m->vac_max = std::max(m->vac_max, sv);
+    }
+  }
   // fixed point: every beam contribution |g rho~| 2^e1 < 2^58, so a lane can add 32 of
   // them in a signed 64-bit integer; every angle term of J0, (energy sum / cos) 2^e0,
   // stays below 2^62 (cos is smallest at r_start, u_max)
@@ -223,6 +237,30 @@ static void build_tables(Sub* m) {
   m->p2e1 = std::ldexp(1.0, -m->e1);
   m->s0 = std::ldexp(1.0, m->e0);
   m->p2e0 = std::ldexp(1.0, -m->e0);
+  // Mixed precision (3f, FP32 state): the first step from which every beam's stage
+  // generator rotates by at most one radian, bounded a priori by
+  //   (h/c_min) (lambda + 8 mu G (1/c_min - c_min) + max_k sum |H_vac - tr/3|),
+  // G = sum_b |g_b|: each nu-nu component mu |sum_b g_b rho~_b (1/c_b - c)| is at most
+  // mu G (1/c_min - c_min) since |rho~| <= 1 and 0 <= 1/c_b - c <= 1/c_min - c_min.  Every
+  // term decreases with r.
+  m->fp32_from = p.n_steps;
+  if (m->nf == 3) {
+    double gsum = 0.0;
+    for (long long k = 0; k < NE; ++k) gsum += std::fabs(G0[k]) + std::fabs(G1[k]);
+    gsum *= (double)m->NU;
+    long long last_bad = -1;
+    for (long long n = 0; n < p.n_steps; ++n) {
+      const double r = p.r_start_km + (double)n * m->h;
+      const double q = p.r_nu_km / r;
+      double qp = 1.0;
+      for (int i = 0; i < p.ne_power; ++i) qp *= q;
+      const double lam = m->lam0 * qp, mu = 0.5 * q * q;
+      const double cmn = std::sqrt(1.0 - ulast * q * q);
+      const double bound = (m->h / cmn) * ((lam + 8.0 * mu * gsum * (1.0 / cmn - cmn)) + m->vac_max);
+      if (!(bound <= 1.0)) last_bad = n;
+    }
+    m->fp32_from = last_bad + 1;
+  }
 }
 
 static int make_sub(const nb_params* p, Sub* s) {
@@ -321,6 +359,10 @@ extern "C" int64_t nb_n_beams(const nb_model* m) { return m ? m->nb : 0; }
 extern "C" int32_t nb_n_models(const nb_model* m) { return m ? m->nmodels : 0; }
 extern "C" int32_t nb_state_comps(const nb_model* m) { return m ? m->nsc : 0; }
 extern "C" int64_t nb_step_index(const nb_model* m) { return m ? m->step : -1; }
+extern "C" int64_t nb_mixed_fp32_step(const nb_model* m) {
+  if (!m || m->batch || !state_fp32(m)) return -1;
+  return m->subs[0].fp32_from;
+}
 
 extern "C" int nb_pee_offsets(const nb_model* m, int64_t* off) {
   if (!m || !off) return fail(NB_EINVAL, "NULL argument");
@@ -355,7 +397,7 @@ static Layout layout_of(const nb_model* m) {
   L.tab = o;
   o = align256(o + sizeof(double) * m->tab.size());
   L.J = o;
-  o = align256(o + sizeof(double) * 4 * 2 * m->nc);
+  o = align256(o + sizeof(double) * kFlagCopies * 4 * 2 * m->nc);
   L.part = o;
   o = align256(o + 16 * (size_t)kMaxBlocks * 2 * m->nc);
   L.sync = o;
@@ -382,7 +424,7 @@ static Layout layout_of(const nb_model* m) {
     L.apart = o;
     o = align256(o + sizeof(double) * (size_t)kMaxBlocks * 8);
     L.aout = o;
-    o = align256(o + sizeof(double) * 16);
+    o = align256(o + sizeof(double) * (8 + kFlagCopies * 8));
   }
   L.need = o;
   return L;
@@ -400,9 +442,16 @@ static size_t advance_dyn_lds(const nb_model* m) { return tab_in_lds(m) ? tab_by
 static const void* advance_kernel(const nb_model* m) {
   if (m->batch) return (const void*)&k_batch2;
   const bool l = tab_in_lds(m);
-  if (m->nf == 2) return l ? (const void*)&k_advance<2, double, true> : (const void*)&k_advance<2, double, false>;
-  if (state_fp32(m)) return l ? (const void*)&k_advance<3, float, true> : (const void*)&k_advance<3, float, false>;
-  return l ? (const void*)&k_advance<3, double, true> : (const void*)&k_advance<3, double, false>;
+  if (m->nf == 2)
+    return l ? (const void*)&k_advance<2, double, true, false> : (const void*)&k_advance<2, double, false, false>;
+  if (state_fp32(m))
+    return l ? (const void*)&k_advance<3, float, true, false> : (const void*)&k_advance<3, float, false, false>;
+  return l ? (const void*)&k_advance<3, double, true, false> : (const void*)&k_advance<3, double, false, false>;
+}
+// The FP32-arithmetic stepping kernel of the mixed-precision mode (nullptr otherwise).
+static const void* advance_kernel_f32(const nb_model* m) {
+  if (m->batch || !state_fp32(m)) return nullptr;
+  return tab_in_lds(m) ? (const void*)&k_advance<3, float, true, true> : (const void*)&k_advance<3, float, false, true>;
 }
 
 static int launch_1d(const void* fn, long long n, void** args, hipStream_t s) {
@@ -423,6 +472,14 @@ static int set_device_step(nb_model* m, long long step) {
   long long* ctl = (long long*)(m->ws + m->off_ctl);
   void* args[] = {&ctl, &step};
   NB_HIP(hipLaunchKernel((const void*)&k_set_step, dim3(1), dim3(1), args, 0, m->stream));
+  return NB_OK;
+}
+
+// Clear the barrier words, optionally keeping the status word (a kernel: capturable).
+static int zero_sync(nb_model* m, int keep) {
+  unsigned int* sync = (unsigned int*)(m->ws + m->off_sync);
+  void* zargs[] = {&sync, &keep};
+  NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(256), dim3(256), zargs, 0, m->stream));
   return NB_OK;
 }
 
@@ -490,6 +547,12 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
   NB_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
   NB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nbpm, advance_kernel(m), kBlock,
                                                        advance_dyn_lds(m)));
+  if (advance_kernel_f32(m)) {
+    int nb32 = 0;
+    NB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb32, advance_kernel_f32(m), kBlock,
+                                                         advance_dyn_lds(m)));
+    nbpm = std::min(nbpm, nb32);
+  }
   if (nbpm < 1) return fail(NB_EHIP, "stepping kernel cannot be resident");
   int max_blocks = std::min(cus * nbpm, kMaxBlocks);
   if (m->p.max_blocks > 0) max_blocks = std::min(max_blocks, (int)m->p.max_blocks);
@@ -560,7 +623,7 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
   unsigned int* sync = (unsigned int*)(m->ws + m->off_sync);
   int keep = 0;
   void* zargs[] = {&sync, &keep};
-  NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(8), dim3(256), zargs, 0, m->stream));
+  NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(256), dim3(256), zargs, 0, m->stream));
   NB_HIP(hipStreamSynchronize(m->stream));
   return nb_reset(m);
 }
@@ -580,7 +643,7 @@ static int check_status(nb_model* m) {
   if (st) {
     int keep = 0;
     void* zargs[] = {&sync, &keep};
-    NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(8), dim3(256), zargs, 0, m->stream));
+    NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(256), dim3(256), zargs, 0, m->stream));
     NB_HIP(hipStreamSynchronize(m->stream));
     if (st & 2u) return fail(NB_ETIMEOUT, "grid barrier time limit exceeded");
     return fail(NB_ENUMERIC, "moment contribution out of fixed-point range (NaN or overflow)");
@@ -598,7 +661,7 @@ static int enqueue_advance(nb_model* m, long long k) {
   unsigned int* sync = (unsigned int*)(m->ws + m->off_sync);
   int keep = 1;
   void* zargs[] = {&sync, &keep};
-  NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(8), dim3(256), zargs, 0, m->stream));
+  NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(256), dim3(256), zargs, 0, m->stream));
   const unsigned long long timeout = m->ticks_per_s * 20ull;
   if (m->batch) {
     unsigned long long* acc = (unsigned long long*)(m->ws + m->off_acc);
@@ -660,15 +723,35 @@ static int enqueue_advance(nb_model* m, long long k) {
   a.p2e0 = s.p2e0;
   a.timeout_ticks = timeout;
   a.Jhist = m->jhist;
-  void* args[] = {&a};
-  const hipError_t e =
-      capturing(m->stream)
-          ? hipLaunchKernel(advance_kernel(m), dim3(m->nblocks), dim3(kBlock), args, advance_dyn_lds(m),
-                            m->stream)
-          : hipLaunchCooperativeKernel(advance_kernel(m), dim3(m->nblocks), dim3(kBlock), args,
-                                       (unsigned)advance_dyn_lds(m), m->stream);
-  if (e != hipSuccess) return fail(NB_EHIP, "stepping launch: %s", hipGetErrorString(e));
-  return NB_OK;
+  auto launch = [&](const void* fn) -> int {
+    void* args[] = {&a};
+    const hipError_t e =
+        capturing(m->stream)
+            ? hipLaunchKernel(fn, dim3(m->nblocks), dim3(kBlock), args, advance_dyn_lds(m), m->stream)
+            : hipLaunchCooperativeKernel(fn, dim3(m->nblocks), dim3(kBlock), args,
+                                         (unsigned)advance_dyn_lds(m), m->stream);
+    if (e != hipSuccess) return fail(NB_EHIP, "stepping launch: %s", hipGetErrorString(e));
+    return NB_OK;
+  };
+  if (!advance_kernel_f32(m)) return launch(advance_kernel(m));
+  // Mixed precision: FP64-arithmetic steps before fp32_from, FP32-arithmetic steps after,
+  // as two windowed launches sharing one target of k steps from the device counter.
+  {
+    long long* ctl = (long long*)(m->ws + m->off_ctl);
+    long long kk = k, total = m->p.n_steps;
+    void* targs[] = {&ctl, &kk, &total};
+    NB_HIP(hipLaunchKernel((const void*)&k_set_target, dim3(1), dim3(1), targs, 0, m->stream));
+  }
+  a.use_window = 1;
+  a.win_lo = 0;
+  a.win_hi = s.fp32_from;
+  int rc = launch(advance_kernel(m));
+  if (rc) return rc;
+  rc = zero_sync(m, 1);
+  if (rc) return rc;
+  a.win_lo = s.fp32_from;
+  a.win_hi = m->p.n_steps;
+  return launch(advance_kernel_f32(m));
 }
 
 static int advance(nb_model* m, long long n) {
@@ -900,7 +983,7 @@ extern "C" int nb_adjoint(nb_model* m, const double* dev_dl_dpee, double* grad_o
   unsigned int* sync = (unsigned int*)(m->ws + m->off_sync);
   int keep = 1;
   void* zargs[] = {&sync, &keep};
-  NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(8), dim3(256), zargs, 0, m->stream));
+  NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(256), dim3(256), zargs, 0, m->stream));
   const Sub& s = m->subs[0];
   AdjArgs a{};
   a.tab = (const double*)(m->ws + m->off_tab);

@@ -7,13 +7,17 @@ namespace nb {
 
 constexpr int kMaxBlocks = 8192;  // upper bound on blocks of one stepping launch
 
-// Offsets (in 32-bit words) of the synchronisation words; the singletons each on their
-// own 128-byte line, then one arrival word per block.
-constexpr int kSyncFlag = 32;     // epoch + 1 of the last barrier released by block 0
-constexpr int kSyncAbort = 64;    // set when any block gives up waiting
-constexpr int kSyncStatus = 96;   // bit 0: fixed-point range error, bit 1: barrier timeout
-constexpr int kSyncArrive = 128;  // [kMaxBlocks]: epoch + 1 of each block's last arrival
-constexpr int kSyncWords = kSyncArrive + kMaxBlocks;
+// Offsets (in 32-bit words) of the synchronisation words.  Every word that more than one
+// block writes or polls sits on a 128-byte line of its own: the abort and status words,
+// kFlagCopies copies of the release flag (block b polls copy b % kFlagCopies) and one
+// arrival word per block.
+constexpr int kLineWords = 32;
+constexpr int kFlagCopies = 8;
+constexpr int kSyncAbort = 1 * kLineWords;   // set when any block gives up waiting
+constexpr int kSyncStatus = 2 * kLineWords;  // bit 0: fixed-point range error, bit 1: barrier timeout
+constexpr int kSyncFlag = 4 * kLineWords;    // [kFlagCopies] lines: epoch + 1 of the last release
+constexpr int kSyncArrive = kSyncFlag + kFlagCopies * kLineWords;  // [kMaxBlocks] lines
+constexpr int kSyncWords = kSyncArrive + kMaxBlocks * kLineWords;
 
 constexpr int kBlock = 512;       // threads per block of the stepping kernels (8 waves)
 
@@ -21,10 +25,12 @@ constexpr int kBlock = 512;       // threads per block of the stepping kernels (
 struct StepArgs {
   void* X;                 // state planes [nsc][plane] (double, or float for FP32 state)
   const double* tab;       // tables: 2f [bx|bz|G0|G1] x NE; 3f [h_ee..h_mt (6)|G0|G1] x NE
-  double* J;               // stage moments [4][2*NC]: J0 then J1 per slot
+  double* J;               // stage moments [kFlagCopies][4][2*NC] (J0 then J1 per slot); block b
+                           // reads copy b % kFlagCopies
   unsigned long long* part;// block partials [gridDim][2*NC][2] (I128 halves)
   unsigned int* sync;      // kSyncWords words
-  long long* step_ctl;     // device step counter: read at launch start, advanced at the end
+  long long* step_ctl;     // [0] device step counter (read at launch start, advanced at the
+                           // end); [1] target of a group of windowed launches
   long long plane;         // plane stride (elements)
   int NE, NU;
   long long nsteps, total_steps;  // requested steps (clamped to total_steps - start)
@@ -33,6 +39,8 @@ struct StepArgs {
   double s1, s0, p2e1, p2e0;  // fixed-point scales 2^e1, 2^e0, 2^-e1, 2^-e0
   unsigned long long timeout_ticks;
   double* Jhist;           // nullptr, or [step][4][2*NC]: every stage's moments (adjoint tape)
+  int use_window;          // 0: advance min(nsteps, total - step) steps; 1: the window below
+  long long win_lo, win_hi;// windowed launch: only steps in [win_lo, win_hi), up to step_ctl[1]
 };
 
 // One two-flavour model of a batch.
@@ -78,7 +86,8 @@ struct AdjArgs {
   double cot_const;
   double* state_bar;       // nullptr, or [3][nb]: dL/d(state at the first step)
   double* part;            // [gridDim][8] block partials of the reductions
-  double* out;             // [8] final reduction: dL/d{L_e, L_ebar, L_x, theta_v, n0}
+  double* out;             // [8 + kFlagCopies * 8]: dL/d{L_e, L_ebar, L_x, theta_v, n0}, then the
+                           // copies of the current reduction
   unsigned int* sync;
   long long plane, nb;
   int NE, NU;

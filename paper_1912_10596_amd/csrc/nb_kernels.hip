@@ -15,6 +15,7 @@
 // Four barriers per step; the final pass writes rho_{n+1} and also produces the next
 // step's stage-1 moments.
 #include "nb_device.h"
+#include "nb_device32.h"
 #include "nb_internal.h"
 #include "nb_stage.h"
 
@@ -52,8 +53,9 @@ __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, double*
   if (blockIdx.x != 0) {
     if (!arrive_and_wait(a.sync, a.timeout_ticks, want)) return false;
     if (tid < NV)
-      sJ[tid] = as_double(__hip_atomic_load((unsigned long long*)gJ + tid, __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT));
+      sJ[tid] = as_double(__hip_atomic_load(
+          (unsigned long long*)gJ + (size_t)(blockIdx.x % kFlagCopies) * 4 * NV + tid, __ATOMIC_RELAXED,
+          __HIP_MEMORY_SCOPE_AGENT));
     __syncthreads();
     return true;
   }
@@ -86,8 +88,9 @@ __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, double*
     for (int gg = 0; gg < G; ++gg) tot = i128_add(tot, sred[gg * NV + tid]);
     const double val = i128_to_double(tot) * (tid < NV / 2 ? a.p2e0 : a.p2e1);
     sJ[tid] = val;
-    __hip_atomic_store((unsigned long long*)gJ + tid, as_bits(val), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+    for (int c = 0; c < kFlagCopies; ++c)
+      __hip_atomic_store((unsigned long long*)gJ + (size_t)c * 4 * NV + tid, as_bits(val), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
   }
   release_grid(a.sync, want);
   return true;
@@ -284,6 +287,129 @@ __device__ __forceinline__ Herm3 gen3(int s, const double* v, double lam, const 
 
 // Row-wise nn terms of the four stage slots live in LDS (one 32-double block per wave)
 // and are re-read per beam, so the compiler does not keep all of them in registers.
+// One (species, emission bin) row of the three-flavour stage, FP64 arithmetic.
+template <typename ST, int KIND>
+__device__ __forceinline__ void row3(const StepArgs& a, long long row, const Radial& g0, const Radial& gm,
+                                     const Radial& g1, const double (*sJ)[16], const double* tab,
+                                     double* snn, int lane, long long* fl, I128& T, int& err) {
+  const long long plane = a.plane;
+  const int NE = a.NE;
+  ST* X = (ST*)a.X;
+  const int s = (int)(row / a.NU);
+  const int j = (int)(row - (long long)s * a.NU);
+  const RowGeo rg = row_geo(u_of(j, a.NU), a.h, g0, gm, g1);
+  const double icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
+  {
+    double t[8];
+    if (KIND == 1 || KIND == 2 || KIND == 4) {
+      nunu<8>(sJ[0], g0.mu, rg.c0, t);
+      for (int i = 0; i < 8; ++i) snn[i] = t[i];
+    }
+    if (KIND == 2 || KIND == 4) {
+      nunu<8>(sJ[1], gm.mu, rg.cm, t);
+      for (int i = 0; i < 8; ++i) snn[8 + i] = t[i];
+    }
+    if (KIND >= 3) {
+      nunu<8>(sJ[2], gm.mu, rg.cm, t);
+      for (int i = 0; i < 8; ++i) snn[16 + i] = t[i];
+    }
+    if (KIND == 4) {
+      nunu<8>(sJ[3], g1.mu, rg.c1, t);
+      for (int i = 0; i < 8; ++i) snn[24 + i] = t[i];
+    }
+  }
+  const double* G = tab + (size_t)(6 + s) * NE;
+  const long long rb = row * NE;
+  I128 mine = i128_zero();
+  for (int k0 = lane; k0 - lane < NE; k0 += 64 * 32) {
+    const int kend = min(NE, k0 + 64 * 32);
+    long long acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    ST q[6];
+    if (k0 < kend) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) q[c] = X[rb + k0 + c * plane];
+    }
+    for (int k = k0; k < kend; k += 64) {
+      cplx ps[3] = {mk((double)q[0], (double)q[1]), mk((double)q[2], (double)q[3]),
+                    mk((double)q[4], (double)q[5])};
+      if (k + 64 < kend) {    // prefetch the lane's next beam
+#pragma unroll
+        for (int c = 0; c < 6; ++c) q[c] = X[rb + k + 64 + c * plane];
+      }
+      __asm__ volatile("" ::: "memory");   // re-read the row's nn terms from LDS per beam
+      if (KIND >= 1) {
+        double v[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] = tab[c * NE + k];
+        Herm3 K1;
+        if (KIND != 3) K1 = gen3(s, v, g0.lam, snn, rg.hc0);
+        if (KIND == 1) {
+          exp3_apply(hscale(0.5, K1), ps);
+        } else if (KIND == 2) {
+          const Herm3 K2 = gen3(s, v, gm.lam, snn + 8, rg.hcm);
+          const Herm3 C = icomm(K1, K2);
+          Herm3 O;
+          O.d0 = 0.5 * K2.d0 + 0.125 * C.d0;
+          O.d1 = 0.5 * K2.d1 + 0.125 * C.d1;
+          O.d2 = 0.5 * K2.d2 + 0.125 * C.d2;
+          O.o01 = mk(0.5 * K2.o01.re + 0.125 * C.o01.re, 0.5 * K2.o01.im + 0.125 * C.o01.im);
+          O.o02 = mk(0.5 * K2.o02.re + 0.125 * C.o02.re, 0.5 * K2.o02.im + 0.125 * C.o02.im);
+          O.o12 = mk(0.5 * K2.o12.re + 0.125 * C.o12.re, 0.5 * K2.o12.im + 0.125 * C.o12.im);
+          exp3_apply(O, ps);
+        } else if (KIND == 3) {
+          exp3_apply(gen3(s, v, gm.lam, snn + 16, rg.hcm), ps);
+        } else {
+          // Theta = (((K1 + 2 K2) + 2 K3) + K4)/6 + i[K1,K4]/12, accumulated in that order
+          Herm3 acc3 = K1;
+          haxpy(acc3, 2.0, gen3(s, v, gm.lam, snn + 8, rg.hcm));
+          haxpy(acc3, 2.0, gen3(s, v, gm.lam, snn + 16, rg.hcm));
+          const Herm3 K4 = gen3(s, v, g1.lam, snn + 24, rg.hc1);
+          hadd(acc3, K4);
+          const Herm3 C = icomm(K1, K4);
+          Herm3 Th;
+          Th.d0 = acc3.d0 * (1.0 / 6.0) + C.d0 * (1.0 / 12.0);
+          Th.d1 = acc3.d1 * (1.0 / 6.0) + C.d1 * (1.0 / 12.0);
+          Th.d2 = acc3.d2 * (1.0 / 6.0) + C.d2 * (1.0 / 12.0);
+          Th.o01 = mk(acc3.o01.re * (1.0 / 6.0) + C.o01.re * (1.0 / 12.0),
+                      acc3.o01.im * (1.0 / 6.0) + C.o01.im * (1.0 / 12.0));
+          Th.o02 = mk(acc3.o02.re * (1.0 / 6.0) + C.o02.re * (1.0 / 12.0),
+                      acc3.o02.im * (1.0 / 6.0) + C.o02.im * (1.0 / 12.0));
+          Th.o12 = mk(acc3.o12.re * (1.0 / 6.0) + C.o12.re * (1.0 / 12.0),
+                      acc3.o12.im * (1.0 / 6.0) + C.o12.im * (1.0 / 12.0));
+          exp3_apply(Th, ps);
+          if (a.renorm) {
+            const double nrm2 = (norm2(ps[0]) + norm2(ps[1])) + norm2(ps[2]);
+            const double inv = 1.0 / sqrt(nrm2);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ps[c] = mk(ps[c].re * inv, ps[c].im * inv);
+          }
+          // store, and take the next step's moments from exactly what was stored
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const ST re = (ST)ps[c].re, im = (ST)ps[c].im;
+            X[rb + k + (2 * c) * plane] = re;
+            X[rb + k + (2 * c + 1) * plane] = im;
+            ps[c] = mk((double)re, (double)im);
+          }
+        }
+      }
+      // rho~ components: rho_ee-rho_tt, rho_mm-rho_tt, Re/Im rho_em, rho_et, rho_mt;
+      // antineutrinos: -rho^* (real parts and diagonal negated)
+      const double n0 = norm2(ps[0]), nm = norm2(ps[1]), nt = norm2(ps[2]);
+      const cplx em = cmul_conjb(ps[0], ps[1]), et = cmul_conjb(ps[0], ps[2]), mt = cmul_conjb(ps[1], ps[2]);
+      double v8[8] = {n0 - nt, nm - nt, em.re, em.im, et.re, et.im, mt.re, mt.im};
+      if (s) {
+        v8[0] = -v8[0]; v8[1] = -v8[1]; v8[2] = -v8[2]; v8[4] = -v8[4]; v8[6] = -v8[6];
+      }
+      const double w = G[k];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc[i] += to_fix(w * v8[i], a.s1, kTwo58, err);
+    }
+    fold_segment<8>(acc, lane, fl, mine);
+  }
+  close_row<8>(Scales{a.s1, a.s0, a.p2e1, a.p2e0}, lane, mine, icmom, T, err);
+}
+
 template <typename ST, int KIND>
 __device__ __forceinline__ void stage3(const StepArgs& a, long long n, const double (*sJ)[16],
                                        const double* tab, double* snn, long long gw,
@@ -292,130 +418,173 @@ __device__ __forceinline__ void stage3(const StepArgs& a, long long n, const dou
   const double rm = r0 + 0.5 * a.h;
   const double r1 = a.rs + (double)(n + 1) * a.h;
   const Radial g0 = radial_at(a, r0), gm = radial_at(a, rm), g1 = radial_at(a, r1);
-  const long long nrow = 2LL * a.NU, plane = a.plane;
+  const long long nrow = 2LL * a.NU;
+  for (long long row = gw; row < nrow; row += nw)
+    row3<ST, KIND>(a, row, g0, gm, g1, sJ, tab, snn, lane, fl, T, err);
+}
+
+// ------------------------------------------------------- three flavours, mixed precision
+// NB_FP32_STATE: psi stored in FP32 and every per-beam stage operation (generators,
+// commutators, exponentials) in FP32; the moment contributions, their reduction and the
+// renormalisation of the updated state are FP64, and the next moments are taken from the
+// rounded stored state.
+__device__ __forceinline__ Herm3f gen3f(int s, const float* v, float lam, const float* nn, float hc) {
+  Herm3f H;
+  if (s == 0) {
+    H.d0 = (v[0] + lam) + nn[0];
+    H.d1 = v[1] + nn[1];
+    H.d2 = v[2];
+    H.o01 = mkf(v[3] + nn[2], nn[3]);
+    H.o02 = mkf(v[4] + nn[4], nn[5]);
+    H.o12 = mkf(v[5] + nn[6], nn[7]);
+  } else {
+    H.d0 = (v[0] - lam) - nn[0];
+    H.d1 = v[1] - nn[1];
+    H.d2 = v[2];
+    H.o01 = mkf(v[3] - nn[2], nn[3]);
+    H.o02 = mkf(v[4] - nn[4], nn[5]);
+    H.o12 = mkf(v[5] - nn[6], nn[7]);
+  }
+  return hscalef(hc, H);
+}
+
+// One row of the mixed-precision stage with FP32 per-beam arithmetic.
+template <int KIND>
+__device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Radial& g0, const Radial& gm,
+                                      const Radial& g1, const RowGeo& rg, const double (*sJ)[16],
+                                      const double* tab, float* snn, int lane, long long* fl, I128& T,
+                                      int& err) {
+  const float lam0f = (float)g0.lam, lammf = (float)gm.lam, lam1f = (float)g1.lam;
+  const long long plane = a.plane;
   const int NE = a.NE;
-  ST* X = (ST*)a.X;
+  float* X = (float*)a.X;
+  const int s = (int)(row / a.NU);
+  const double icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
+  const float hc0 = (float)rg.hc0, hcm = (float)rg.hcm, hc1 = (float)rg.hc1;
+  {
+    double t[8];
+    if (KIND == 1 || KIND == 2 || KIND == 4) {
+      nunu<8>(sJ[0], g0.mu, rg.c0, t);
+      for (int i = 0; i < 8; ++i) snn[i] = (float)t[i];
+    }
+    if (KIND == 2 || KIND == 4) {
+      nunu<8>(sJ[1], gm.mu, rg.cm, t);
+      for (int i = 0; i < 8; ++i) snn[8 + i] = (float)t[i];
+    }
+    if (KIND >= 3) {
+      nunu<8>(sJ[2], gm.mu, rg.cm, t);
+      for (int i = 0; i < 8; ++i) snn[16 + i] = (float)t[i];
+    }
+    if (KIND == 4) {
+      nunu<8>(sJ[3], g1.mu, rg.c1, t);
+      for (int i = 0; i < 8; ++i) snn[24 + i] = (float)t[i];
+    }
+  }
+  const double* G = tab + (size_t)(6 + s) * NE;
+  const long long rb = row * NE;
+  I128 mine = i128_zero();
+  for (int k0 = lane; k0 - lane < NE; k0 += 64 * 32) {
+    const int kend = min(NE, k0 + 64 * 32);
+    long long acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    float q[6];
+    if (k0 < kend) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) q[c] = X[rb + k0 + c * plane];
+    }
+    for (int k = k0; k < kend; k += 64) {
+      cplxf ps[3] = {mkf(q[0], q[1]), mkf(q[2], q[3]), mkf(q[4], q[5])};
+      if (k + 64 < kend) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) q[c] = X[rb + k + 64 + c * plane];
+      }
+      __asm__ volatile("" ::: "memory");
+      double pd[6];
+      if (KIND >= 1) {
+        float v[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] = (float)tab[c * NE + k];
+        Herm3f K1;
+        if (KIND != 3) K1 = gen3f(s, v, lam0f, snn, hc0);
+        if (KIND == 1) {
+          exp3_apply_f(hscalef(0.5f, K1), ps);
+        } else if (KIND == 2) {
+          const Herm3f K2 = gen3f(s, v, lammf, snn + 8, hcm);
+          const Herm3f C = icommf(K1, K2);
+          Herm3f O = hscalef(0.5f, K2);
+          haxpyf(O, 0.125f, C);
+          exp3_apply_f(O, ps);
+        } else if (KIND == 3) {
+          exp3_apply_f(gen3f(s, v, lammf, snn + 16, hcm), ps);
+        } else {
+          const Herm3f K4 = gen3f(s, v, lam1f, snn + 24, hc1);
+          const Herm3f C = icommf(K1, K4);
+          Herm3f acc3 = K1;
+          haxpyf(acc3, 2.0f, gen3f(s, v, lammf, snn + 8, hcm));
+          haxpyf(acc3, 2.0f, gen3f(s, v, lammf, snn + 16, hcm));
+          haxpyf(acc3, 1.0f, K4);
+          Herm3f Th = hscalef(1.0f / 6.0f, acc3);
+          haxpyf(Th, 1.0f / 12.0f, C);
+          exp3_apply_f(Th, ps);
+          // renormalise in FP64, store rounded to FP32, moments from the stored values
+          const double re0 = ps[0].re, im0 = ps[0].im, re1 = ps[1].re, im1 = ps[1].im;
+          const double re2 = ps[2].re, im2 = ps[2].im;
+          const double nrm2 = (fma(re0, re0, im0 * im0) + fma(re1, re1, im1 * im1)) + fma(re2, re2, im2 * im2);
+          const double inv = 1.0 / sqrt(nrm2);
+          const float o[6] = {(float)(re0 * inv), (float)(im0 * inv), (float)(re1 * inv),
+                              (float)(im1 * inv), (float)(re2 * inv), (float)(im2 * inv)};
+#pragma unroll
+          for (int c = 0; c < 6; ++c) X[rb + k + c * plane] = o[c];
+          ps[0] = mkf(o[0], o[1]);
+          ps[1] = mkf(o[2], o[3]);
+          ps[2] = mkf(o[4], o[5]);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        pd[2 * c] = (double)ps[c].re;
+        pd[2 * c + 1] = (double)ps[c].im;
+      }
+      const cplx p0 = mk(pd[0], pd[1]), p1 = mk(pd[2], pd[3]), p2 = mk(pd[4], pd[5]);
+      const double n0 = norm2(p0), nm = norm2(p1), nt = norm2(p2);
+      const cplx em = cmul_conjb(p0, p1), et = cmul_conjb(p0, p2), mt = cmul_conjb(p1, p2);
+      double v8[8] = {n0 - nt, nm - nt, em.re, em.im, et.re, et.im, mt.re, mt.im};
+      if (s) {
+        v8[0] = -v8[0]; v8[1] = -v8[1]; v8[2] = -v8[2]; v8[4] = -v8[4]; v8[6] = -v8[6];
+      }
+      const double w = G[k];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc[i] += to_fix(w * v8[i], a.s1, kTwo58, err);
+    }
+    fold_segment<8>(acc, lane, fl, mine);
+  }
+  close_row<8>(Scales{a.s1, a.s0, a.p2e1, a.p2e0}, lane, mine, icmom, T, err);
+}
+
+// Mixed-precision stage: every row with FP32 per-beam arithmetic.  The host runs these
+// launches only over steps whose stage generators rotate a beam by at most one radian per
+// step (a bound computed from the model's parameters); nearer the neutrinosphere FP32
+// cannot hold the per-step phase and the FP64-arithmetic launch on the FP32 state is used.
+template <int KIND>
+__device__ __forceinline__ void stage3m(const StepArgs& a, long long n, const double (*sJ)[16],
+                                        const double* tab, double* snn, long long gw, long long nw,
+                                        int lane, long long* fl, I128& T, int& err) {
+  const double r0 = a.rs + (double)n * a.h;
+  const double rm = r0 + 0.5 * a.h;
+  const double r1 = a.rs + (double)(n + 1) * a.h;
+  const Radial g0 = radial_at(a, r0), gm = radial_at(a, rm), g1 = radial_at(a, r1);
+  const long long nrow = 2LL * a.NU;
   for (long long row = gw; row < nrow; row += nw) {
     const int s = (int)(row / a.NU);
     const int j = (int)(row - (long long)s * a.NU);
     const RowGeo rg = row_geo(u_of(j, a.NU), a.h, g0, gm, g1);
-    const double icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
-    {
-      double t[8];
-      if (KIND == 1 || KIND == 2 || KIND == 4) {
-        nunu<8>(sJ[0], g0.mu, rg.c0, t);
-        for (int i = 0; i < 8; ++i) snn[i] = t[i];
-      }
-      if (KIND == 2 || KIND == 4) {
-        nunu<8>(sJ[1], gm.mu, rg.cm, t);
-        for (int i = 0; i < 8; ++i) snn[8 + i] = t[i];
-      }
-      if (KIND >= 3) {
-        nunu<8>(sJ[2], gm.mu, rg.cm, t);
-        for (int i = 0; i < 8; ++i) snn[16 + i] = t[i];
-      }
-      if (KIND == 4) {
-        nunu<8>(sJ[3], g1.mu, rg.c1, t);
-        for (int i = 0; i < 8; ++i) snn[24 + i] = t[i];
-      }
-    }
-    const double* G = tab + (size_t)(6 + s) * NE;
-    const long long rb = row * NE;
-    I128 mine = i128_zero();
-    for (int k0 = lane; k0 - lane < NE; k0 += 64 * 32) {
-      const int kend = min(NE, k0 + 64 * 32);
-      long long acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      ST q[6];
-      if (k0 < kend) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) q[c] = X[rb + k0 + c * plane];
-      }
-      for (int k = k0; k < kend; k += 64) {
-        cplx ps[3] = {mk((double)q[0], (double)q[1]), mk((double)q[2], (double)q[3]),
-                      mk((double)q[4], (double)q[5])};
-        if (k + 64 < kend) {    // prefetch the lane's next beam
-#pragma unroll
-          for (int c = 0; c < 6; ++c) q[c] = X[rb + k + 64 + c * plane];
-        }
-        __asm__ volatile("" ::: "memory");   // re-read the row's nn terms from LDS per beam
-        if (KIND >= 1) {
-          double v[6];
-#pragma unroll
-          for (int c = 0; c < 6; ++c) v[c] = tab[c * NE + k];
-          Herm3 K1;
-          if (KIND != 3) K1 = gen3(s, v, g0.lam, snn, rg.hc0);
-          if (KIND == 1) {
-            exp3_apply(hscale(0.5, K1), ps);
-          } else if (KIND == 2) {
-            const Herm3 K2 = gen3(s, v, gm.lam, snn + 8, rg.hcm);
-            const Herm3 C = icomm(K1, K2);
-            Herm3 O;
-            O.d0 = 0.5 * K2.d0 + 0.125 * C.d0;
-            O.d1 = 0.5 * K2.d1 + 0.125 * C.d1;
-            O.d2 = 0.5 * K2.d2 + 0.125 * C.d2;
-            O.o01 = mk(0.5 * K2.o01.re + 0.125 * C.o01.re, 0.5 * K2.o01.im + 0.125 * C.o01.im);
-            O.o02 = mk(0.5 * K2.o02.re + 0.125 * C.o02.re, 0.5 * K2.o02.im + 0.125 * C.o02.im);
-            O.o12 = mk(0.5 * K2.o12.re + 0.125 * C.o12.re, 0.5 * K2.o12.im + 0.125 * C.o12.im);
-            exp3_apply(O, ps);
-          } else if (KIND == 3) {
-            exp3_apply(gen3(s, v, gm.lam, snn + 16, rg.hcm), ps);
-          } else {
-            // Theta = (((K1 + 2 K2) + 2 K3) + K4)/6 + i[K1,K4]/12, accumulated in that order
-            Herm3 acc3 = K1;
-            haxpy(acc3, 2.0, gen3(s, v, gm.lam, snn + 8, rg.hcm));
-            haxpy(acc3, 2.0, gen3(s, v, gm.lam, snn + 16, rg.hcm));
-            const Herm3 K4 = gen3(s, v, g1.lam, snn + 24, rg.hc1);
-            hadd(acc3, K4);
-            const Herm3 C = icomm(K1, K4);
-            Herm3 Th;
-            Th.d0 = acc3.d0 * (1.0 / 6.0) + C.d0 * (1.0 / 12.0);
-            Th.d1 = acc3.d1 * (1.0 / 6.0) + C.d1 * (1.0 / 12.0);
-            Th.d2 = acc3.d2 * (1.0 / 6.0) + C.d2 * (1.0 / 12.0);
-            Th.o01 = mk(acc3.o01.re * (1.0 / 6.0) + C.o01.re * (1.0 / 12.0),
-                        acc3.o01.im * (1.0 / 6.0) + C.o01.im * (1.0 / 12.0));
-            Th.o02 = mk(acc3.o02.re * (1.0 / 6.0) + C.o02.re * (1.0 / 12.0),
-                        acc3.o02.im * (1.0 / 6.0) + C.o02.im * (1.0 / 12.0));
-            Th.o12 = mk(acc3.o12.re * (1.0 / 6.0) + C.o12.re * (1.0 / 12.0),
-                        acc3.o12.im * (1.0 / 6.0) + C.o12.im * (1.0 / 12.0));
-            exp3_apply(Th, ps);
-            if (a.renorm) {
-              const double nrm2 = (norm2(ps[0]) + norm2(ps[1])) + norm2(ps[2]);
-              const double inv = 1.0 / sqrt(nrm2);
-#pragma unroll
-              for (int c = 0; c < 3; ++c) ps[c] = mk(ps[c].re * inv, ps[c].im * inv);
-            }
-            // store, and take the next step's moments from exactly what was stored
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              const ST re = (ST)ps[c].re, im = (ST)ps[c].im;
-              X[rb + k + (2 * c) * plane] = re;
-              X[rb + k + (2 * c + 1) * plane] = im;
-              ps[c] = mk((double)re, (double)im);
-            }
-          }
-        }
-        // rho~ components: rho_ee-rho_tt, rho_mm-rho_tt, Re/Im rho_em, rho_et, rho_mt;
-        // antineutrinos: -rho^* (real parts and diagonal negated)
-        const double n0 = norm2(ps[0]), nm = norm2(ps[1]), nt = norm2(ps[2]);
-        const cplx em = cmul_conjb(ps[0], ps[1]), et = cmul_conjb(ps[0], ps[2]), mt = cmul_conjb(ps[1], ps[2]);
-        double v8[8] = {n0 - nt, nm - nt, em.re, em.im, et.re, et.im, mt.re, mt.im};
-        if (s) {
-          v8[0] = -v8[0]; v8[1] = -v8[1]; v8[2] = -v8[2]; v8[4] = -v8[4]; v8[6] = -v8[6];
-        }
-        const double w = G[k];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) acc[i] += to_fix(w * v8[i], a.s1, kTwo58, err);
-      }
-      fold_segment<8>(acc, lane, fl, mine);
-    }
-    close_row<8>(Scales{a.s1, a.s0, a.p2e1, a.p2e0}, lane, mine, icmom, T, err);
+    row3m<KIND>(a, row, g0, gm, g1, rg, sJ, tab, (float*)snn, lane, fl, T, err);
   }
 }
 
 // --------------------------------------------------------------- the stepper
 // The energy tables (vacuum terms and weights) are staged into LDS once per launch
 // when TLDS (they are read by every row).
-template <int NF, typename ST, bool TLDS>
+template <int NF, typename ST, bool TLDS, bool F32>
 __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   constexpr int NC = (NF == 2) ? 3 : 8;
   constexpr int NV = 2 * NC;
@@ -437,14 +606,22 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   }
   double* snn = snn_all[wid];
   long long* fl = sfold[wid];
-  const long long step0 = *a.step_ctl;
-  const long long nsteps = max(0LL, min(a.nsteps, a.total_steps - step0));
+  const long long step0 = a.step_ctl[0];
+  long long nsteps;
+  if (a.use_window) {
+    // steps [step0, min(target, win_hi)) if step0 lies in the window [win_lo, win_hi)
+    nsteps = (step0 < a.win_lo) ? 0LL : max(0LL, min(a.step_ctl[1], a.win_hi) - step0);
+  } else {
+    nsteps = max(0LL, min(a.nsteps, a.total_steps - step0));
+  }
+  if (a.use_window && nsteps == 0) return;   // uniform over the grid: nothing to do
   unsigned epoch = 0;
   int err = 0;
   bool ok = true;
   I128 T = i128_zero();
   if constexpr (NF == 2) stage2<0>(a, step0, sJ, tab, gw, nw, lane, fl, T, err);
-  else stage3<ST, 0>(a, step0, sJ, tab, snn, gw, nw, lane, fl, T, err);
+  else if constexpr (F32) stage3m<0>(a, step0, sJ, tab, snn, gw, nw, lane, fl, T, err);
+    else stage3<ST, 0>(a, step0, sJ, tab, snn, gw, nw, lane, fl, T, err);
   ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[0], a.J);
   // the adjoint's forward pass records every stage's moments: [step][slot][NV]
   auto record = [&](long long step, int slot) {
@@ -455,21 +632,25 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   for (long long n = step0; ok && n < step0 + nsteps; ++n) {
     T = i128_zero();
     if constexpr (NF == 2) stage2<1>(a, n, sJ, tab, gw, nw, lane, fl, T, err);
+    else if constexpr (F32) stage3m<1>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
     else stage3<ST, 1>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
     if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[1], a.J + NV))) break;
     record(n, 1);
     T = i128_zero();
     if constexpr (NF == 2) stage2<2>(a, n, sJ, tab, gw, nw, lane, fl, T, err);
+    else if constexpr (F32) stage3m<2>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
     else stage3<ST, 2>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
     if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[2], a.J + 2 * NV))) break;
     record(n, 2);
     T = i128_zero();
     if constexpr (NF == 2) stage2<3>(a, n, sJ, tab, gw, nw, lane, fl, T, err);
+    else if constexpr (F32) stage3m<3>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
     else stage3<ST, 3>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
     if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[3], a.J + 3 * NV))) break;
     record(n, 3);
     T = i128_zero();
     if constexpr (NF == 2) stage2<4>(a, n, sJ, tab, gw, nw, lane, fl, T, err);
+    else if constexpr (F32) stage3m<4>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
     else stage3<ST, 4>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
     ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[0], a.J);
     record(n + 1, 0);
@@ -479,12 +660,14 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   if (ok && blockIdx.x == 0 && threadIdx.x == 0) *a.step_ctl = step0 + nsteps;
 }
 
-template __global__ void k_advance<2, double, true>(StepArgs);
-template __global__ void k_advance<2, double, false>(StepArgs);
-template __global__ void k_advance<3, double, true>(StepArgs);
-template __global__ void k_advance<3, double, false>(StepArgs);
-template __global__ void k_advance<3, float, true>(StepArgs);
-template __global__ void k_advance<3, float, false>(StepArgs);
+template __global__ void k_advance<2, double, true, false>(StepArgs);
+template __global__ void k_advance<2, double, false, false>(StepArgs);
+template __global__ void k_advance<3, double, true, false>(StepArgs);
+template __global__ void k_advance<3, double, false, false>(StepArgs);
+template __global__ void k_advance<3, float, true, false>(StepArgs);
+template __global__ void k_advance<3, float, false, false>(StepArgs);
+template __global__ void k_advance<3, float, true, true>(StepArgs);
+template __global__ void k_advance<3, float, false, true>(StepArgs);
 
 // --------------------------------------------------------------- batched models
 // Many independent two-flavour models in one persistent launch (shared step grid).
@@ -629,6 +812,10 @@ __global__ void k_zero_u64(unsigned long long* p, long long n) {
     p[i] = 0ull;
 }
 __global__ void k_set_step(long long* step_ctl, long long step) { *step_ctl = step; }
+// Target of a group of windowed launches: k more steps from the device step counter.
+__global__ void k_set_target(long long* step_ctl, long long k, long long total) {
+  step_ctl[1] = min(step_ctl[0] + k, total);
+}
 
 __global__ void k_zero_sync(unsigned int* sync, int keep_status) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kSyncWords; i += gridDim.x * blockDim.x)

@@ -65,7 +65,7 @@ __device__ __forceinline__ bool wait_arrivals(unsigned* sync, unsigned long long
     for (unsigned it = 1;; ++it) {
       unsigned lowest = 0xffffffffu;
       for (unsigned b = 1 + threadIdx.x; b < gridDim.x; b += 64)
-        lowest = min(lowest, __hip_atomic_load(sync + kSyncArrive + b, __ATOMIC_RELAXED,
+        lowest = min(lowest, __hip_atomic_load(sync + kSyncArrive + b * kLineWords, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT));
       if (lowest >= want) break;
       if ((it & 31u) == 0u) {
@@ -92,8 +92,10 @@ __device__ __forceinline__ bool arrive_and_wait(unsigned* sync, unsigned long lo
   __shared__ int s_ok;
   __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_store(sync + kSyncArrive + blockIdx.x, want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s_ok = poll_until(sync, timeout_ticks, sync + kSyncFlag, want) ? 1 : 0;
+    __hip_atomic_store(sync + kSyncArrive + blockIdx.x * kLineWords, want, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    s_ok = poll_until(sync, timeout_ticks, sync + kSyncFlag + (blockIdx.x % kFlagCopies) * kLineWords, want)
+               ? 1 : 0;
   }
   __syncthreads();
   return s_ok != 0;
@@ -101,8 +103,9 @@ __device__ __forceinline__ bool arrive_and_wait(unsigned* sync, unsigned long lo
 // Block 0 releases the grid (all its threads call this, after their result stores).
 __device__ __forceinline__ void release_grid(unsigned* sync, unsigned want) {
   __syncthreads();
-  if (threadIdx.x == 0)
-    __hip_atomic_store(sync + kSyncFlag, want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x < kFlagCopies)
+    __hip_atomic_store(sync + kSyncFlag + threadIdx.x * kLineWords, want, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Geometry of one emission bin u at the three stage radii of a step.

@@ -82,3 +82,39 @@ def test_product_path_has_no_oracle_dependency():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "libnbo" not in txt and "nbo.h" not in txt, f
+
+
+def _herm(o):
+    """3x3 Hermitian matrix from (d0, d1, d2, Re/Im o01, o02, o12)."""
+    H = np.diag(o[:3]).astype(complex)
+    for i, (a, b) in enumerate(((0, 1), (0, 2), (1, 2))):
+        H[a, b] = o[3 + 2 * i] + 1j * o[4 + 2 * i]
+        H[b, a] = np.conj(H[a, b])
+    return H
+
+
+@pytest.mark.parametrize("r_start", [440.0, 460.0])
+def test_mixed_precision_switch_is_a_valid_angle_bound(oracle, r_start):
+    """The library's a-priori bound behind the mixed-precision FP32 switch, checked against
+    the oracle's Hamiltonians: from the switch step on, every beam's stage generator
+    (h/cos) H, traceless, has eigenvalues below one radian -- on the oracle's own state at
+    that step, at the step's three stage radii."""
+    import paper_1912_10596_amd as nb
+    d0 = workloads.three_flavor_6m()
+    h = (d0["r_end_km"] - d0["r_start_km"]) / d0["n_steps"]
+    d = workloads.small_params(n_flavor=3, n_energy=37, n_u=5, n_steps=1200, r_start_km=r_start,
+                               r_end_km=r_start + 1200 * h)
+    k = nb.HostModel(d, precision=1).mixed_fp32_step()
+    assert 0 < k < d["n_steps"]
+    o = oracle.Model(d)
+    o.step(k)
+    worst = 0.0
+    for r in (d["r_start_km"] + k * h, d["r_start_km"] + (k + 0.5) * h, d["r_start_km"] + (k + 1) * h):
+        j0, j1 = o.moments(r)
+        H = o.hamiltonian(r, j0, j1)
+        c = np.tile(np.repeat(o.cos_theta(r), d["n_energy"]), 2)
+        for b in range(0, o.nb, 7):
+            K = _herm(H[b]) * (h / c[b])
+            K -= np.trace(K) / 3.0 * np.eye(3)
+            worst = max(worst, np.abs(np.linalg.eigvalsh(K)).max())
+    assert worst < 1.0, worst

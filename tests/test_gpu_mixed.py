@@ -1,0 +1,123 @@
+"""Mixed precision (three flavours, precision = NB_FP32_STATE): FP32 state and FP32 stage
+arithmetic where the step resolves every beam, FP64 moments and renormalisation, checked
+against the FP64 GPU run (which is itself bit-for-bit the oracle).
+
+Tolerance: the mixed path has no bitwise contract.  Per step its stage arithmetic rounds at
+FP32 precision (6e-8 relative) on rotation angles below one radian, so after N steps the
+difference in P_ee stays near N x 6e-8 at worst; the target for the 10000-step workload is
+1e-5, which the tests below apply to shorter runs as well.
+"""
+import copy
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TARGET = 1e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def nb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device visible")
+    import paper_1912_10596_amd as nb
+    nb.lib()
+    return nb
+
+
+def _h6():
+    d = workloads.three_flavor_6m()
+    return (d["r_end_km"] - d["r_start_km"]) / d["n_steps"]
+
+
+def _small(r_start, n_steps, n_energy=37, n_u=5):
+    h = _h6()
+    return workloads.small_params(n_flavor=3, n_energy=n_energy, n_u=n_u, n_steps=n_steps,
+                                  r_start_km=r_start, r_end_km=r_start + n_steps * h)
+
+
+def _run(nb, d, precision, steps=None):
+    m = nb.Model(d, precision=precision)
+    if steps is None:
+        m.run()
+    else:
+        m.step(steps)
+    return m
+
+
+def test_mixed_resolved_small_against_fp64(nb):
+    d = _small(600.0, 800)
+    m32 = _run(nb, d, 1)
+    assert m32.mixed_fp32_step() == 0
+    p64 = _run(nb, d, 0).pee().cpu().numpy()
+    p32 = m32.pee().cpu().numpy()
+    dp = np.abs(p64 - p32).max()
+    _say(f"resolved 37x5x2, 800 steps: max |dP_ee| = {dp:.3e}")
+    assert dp < TARGET
+    assert np.abs(p64 - p32).max() > 0.0           # it really is a different arithmetic
+
+
+def test_mixed_state_is_normalised(nb):
+    d = _small(600.0, 50, n_energy=70, n_u=3)
+    st = _run(nb, d, 1).get_state().cpu().numpy()
+    nrm = (st ** 2).sum(axis=0)
+    assert np.abs(nrm - 1.0).max() < 4e-7           # FP32 rounding of a unit FP64 vector
+
+
+def test_mixed_window_split_and_graph_replay(nb):
+    """A run whose FP32 arithmetic starts mid-way: one call, split calls and graph replays
+    give the same bits (the switch is taken from the device step counter)."""
+    import torch
+    d = _small(440.0, 1200)
+    ref = nb.Model(d, precision=1)
+    k = ref.mixed_fp32_step()
+    _say(f"FP32 arithmetic from step {k} of {d['n_steps']}")
+    assert 0 < k < d["n_steps"]
+    ref.run()
+    split = nb.Model(d, precision=1)
+    for n in (k - 7, 13, 500, d["n_steps"]):
+        split.step(n)
+    np.testing.assert_array_equal(split.get_state().cpu().numpy(), ref.get_state().cpu().numpy())
+    g = nb.Model(d, precision=1, stream=torch.cuda.Stream())
+    with torch.cuda.stream(g.stream):
+        g.graph_capture(97)
+    while g.step_index() < d["n_steps"]:
+        g.graph_launch()
+    with torch.cuda.stream(g.stream):
+        st = g.get_state()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(st.cpu().numpy(), ref.get_state().cpu().numpy())
+
+
+def test_mixed_unresolved_part_is_fp64_arithmetic(nb):
+    """Before the FP32 step the mixed path runs FP64 arithmetic on the FP32-stored state:
+    over a prefix that ends before it, P_ee differs from FP64 only by the FP32 rounding of
+    the stored state (checked on a resolved-scale prefix, so the difference stays small)."""
+    d = _small(440.0, 1200)
+    k = nb.HostModel(d, precision=1).mixed_fp32_step()
+    n = min(k, 200)
+    p64 = _run(nb, d, 0, n).pee().cpu().numpy()
+    p32 = _run(nb, d, 1, n).pee().cpu().numpy()
+    assert np.abs(p64 - p32).max() < TARGET
+
+
+def test_mixed_6m_resolved_prefix(nb):
+    """The 6M-beam workload (1000 E x 3000 u x 2) in its resolved variant: 300 steps."""
+    d = workloads.three_flavor_6m_resolved()
+    p64 = _run(nb, d, 0, 300).pee().cpu().numpy()
+    m32 = _run(nb, d, 1, 300)
+    p32 = m32.pee().cpu().numpy()
+    dp = np.abs(p64 - p32).max()
+    _say(f"6M resolved, 300 steps: max |dP_ee| = {dp:.3e}")
+    assert m32.mixed_fp32_step() == 0
+    assert dp < TARGET

@@ -97,6 +97,18 @@ def adjoint_200k_resolved() -> dict:
     return resolved(adjoint_200k(), ADJOINT_RESOLVED_START_KM)
 
 
+# Start radius of the resolved mixed-precision variant of the 6M-beam workload: with its
+# step length (0.049 km) every beam's per-step rotation angle is below one radian from
+# here on, so the FP32 stage arithmetic applies to every step.
+MIXED_RESOLVED_START_KM = 600.0
+
+
+def three_flavor_6m_resolved() -> dict:
+    """The 6M-beam workload with its step length and step count kept and the start moved
+    out to MIXED_RESOLVED_START_KM (600 -> 1090 km)."""
+    return resolved(three_flavor_6m(), MIXED_RESOLVED_START_KM)
+
+
 def three_flavor_6m() -> dict:
     """3 flavours, 1000 E x 3000 u x 2 = 6M beams, 10 -> 500 km in 10000 steps."""
     return base_params(n_flavor=3, n_energy=1000, n_u=3000, r_end_km=500.0, n_steps=10000,
