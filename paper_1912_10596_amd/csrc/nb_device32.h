@@ -109,10 +109,17 @@ __device__ __forceinline__ void k0_minusf(const cplxf v[3], float d0, float d1, 
   o[2] = caddf(caddf(cmulf_conja(y, v[0]), cmulf_conja(z, v[1])), rmulf(d2, v[2]));
 }
 
-// psi <- exp(-i K) psi (up to a global phase) in FP32: the algorithm of the FP64 version
-// (largest eigenvalue by Newton on the characteristic cubic, its eigenvector from the
-// largest row cross product, the closed-form 2x2 propagator on the orthogonal plane).
-__device__ __forceinline__ void exp3_apply_f(const Herm3f& K, cplxf psi[3]) {
+// Eigen-split of exp(-i K) in FP32, the algorithm of the FP64 version (largest eigenvalue
+// by Newton on the characteristic cubic, its eigenvector from the largest row cross
+// product): psi = al v1 + pp with pp orthogonal to v1, kp = (K0 - hm) pp, and the phases
+// phi (of v1) and th (of the orthogonal plane), so that
+//   exp(-i K) psi = e^{-i phi} al v1 + cos(th) pp - i sin(th)/th kp   (global phase dropped).
+// Returns false if K is zero (exp(-iK) psi = psi up to a phase).
+struct Split3f {
+  cplxf v1[3], pp[3], kp[3], al;
+  float phi, th;
+};
+__device__ __forceinline__ bool split3_f(const Herm3f& K, const cplxf psi[3], Split3f& o) {
   const float tr = ((K.d0 + K.d1) + K.d2) * (1.0f / 3.0f);
   const float a0 = K.d0 - tr, a1 = K.d1 - tr, a2 = K.d2 - tr;
   const cplxf x = K.o01, y = K.o02, z = K.o12;
@@ -122,7 +129,7 @@ __device__ __forceinline__ void exp3_apply_f(const Herm3f& K, cplxf psi[3]) {
   const cplxf xz = cmulf(x, z);
   const float t = fmaf(xz.re, y.re, xz.im * y.im);
   const float q = fmaf(a0, fmaf(a1, a2, -nz), fmaf(-a1, ny, fmaf(-a2, nx, 2.0f * t)));
-  if (!(p > 0.0f)) return;
+  if (!(p > 0.0f)) return false;
   const float sg = (q < 0.0f) ? -1.0f : 1.0f;
   const float qa = sg * q;
   float lam = 2.0f * sqrtf(p * (1.0f / 3.0f));
@@ -163,46 +170,76 @@ __device__ __forceinline__ void exp3_apply_f(const Herm3f& K, cplxf psi[3]) {
       nb = n;
     }
   }
-  if (!(nb > 0.0f)) return;
+  if (!(nb > 0.0f)) return false;
   const float inb = rsqrtf(nb);
-  const cplxf v1[3] = {rmulf(inb, best[0]), rmulf(inb, best[1]), rmulf(inb, best[2])};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) o.v1[c] = rmulf(inb, best[c]);
   const float hm = -0.5f * l1;
   const float d0 = a0 - hm, d1 = a1 - hm, d2 = a2 - hm;
-  float th;
   {
-    const float nc0 = norm2f(v1[0]), nc1 = norm2f(v1[1]), nc2 = norm2f(v1[2]);
+    const float nc0 = norm2f(o.v1[0]), nc1 = norm2f(o.v1[1]), nc2 = norm2f(o.v1[2]);
     int m = 0;
     float ncm = nc0;
     if (nc1 < ncm) { m = 1; ncm = nc1; }
     if (nc2 < ncm) { m = 2; ncm = nc2; }
-    const cplxf vm = (m == 0) ? v1[0] : ((m == 1) ? v1[1] : v1[2]);
+    const cplxf vm = (m == 0) ? o.v1[0] : ((m == 1) ? o.v1[1] : o.v1[2]);
     cplxf w[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const cplxf tm = cmulf_conjb(v1[c], vm);
+      const cplxf tm = cmulf_conjb(o.v1[c], vm);
       w[c] = (c == m) ? mkf(1.0f - ncm, 0.0f) : mkf(-tm.re, -tm.im);
     }
     const float inw = rsqrtf(cnorm2vf(w));
     const cplxf u[3] = {rmulf(inw, w[0]), rmulf(inw, w[1]), rmulf(inw, w[2])};
     cplxf ku[3];
     k0_minusf(u, d0, d1, d2, x, y, z, ku);
-    th = sqrtf(cnorm2vf(ku));
+    o.th = sqrtf(cnorm2vf(ku));
   }
-  const cplxf al = caddf(caddf(cmulf_conja(v1[0], psi[0]), cmulf_conja(v1[1], psi[1])),
-                         cmulf_conja(v1[2], psi[2]));
-  cplxf pp[3], kp[3];
+  o.al = caddf(caddf(cmulf_conja(o.v1[0], psi[0]), cmulf_conja(o.v1[1], psi[1])),
+               cmulf_conja(o.v1[2], psi[2]));
 #pragma unroll
-  for (int c = 0; c < 3; ++c) pp[c] = csubf(psi[c], cmulf(al, v1[c]));
-  k0_minusf(pp, d0, d1, d2, x, y, z, kp);
-  const float phi = l1 - hm;
+  for (int c = 0; c < 3; ++c) o.pp[c] = csubf(psi[c], cmulf(o.al, o.v1[c]));
+  k0_minusf(o.pp, d0, d1, d2, x, y, z, o.kp);
+  o.phi = l1 - hm;
+  return true;
+}
+
+// psi <- exp(-i K) psi (up to a global phase) in FP32.
+__device__ __forceinline__ void exp3_apply_f(const Herm3f& K, cplxf psi[3]) {
+  Split3f e;
+  if (!split3_f(K, psi, e)) return;
   float sp, cp, st, ct;
-  sincos_f(phi, sp, cp);
-  sincos_f(th, st, ct);
-  const float sc = (th > 0.0f) ? st * rcp_f(th) : 1.0f;
-  const cplxf ap = cmulf(al, mkf(cp, -sp));
+  sincos_f(e.phi, sp, cp);
+  sincos_f(e.th, st, ct);
+  const float sc = (e.th > 0.0f) ? st * rcp_f(e.th) : 1.0f;
+  const cplxf ap = cmulf(e.al, mkf(cp, -sp));
 #pragma unroll
   for (int c = 0; c < 3; ++c)
-    psi[c] = caddf(cmulf(ap, v1[c]), mkf(fmaf(ct, pp[c].re, sc * kp[c].im), fmaf(ct, pp[c].im, -(sc * kp[c].re))));
+    psi[c] = caddf(cmulf(ap, e.v1[c]),
+                   mkf(fmaf(ct, e.pp[c].re, sc * e.kp[c].im), fmaf(ct, e.pp[c].im, -(sc * e.kp[c].re))));
+}
+
+// The increment d = exp(-i K) psi - psi in FP32 (global phase of exp dropped as above),
+// formed without cancellation: cos x - 1 = -2 sin^2(x/2), sin x = 2 sin(x/2) cos(x/2), so
+//   d = ((cos phi - 1) - i sin phi) al v1 + (cos th - 1) pp - i sin(th)/th kp
+// is accurate relative to its own size, and psi + d is formed by the caller in FP64.
+__device__ __forceinline__ void exp3_incr_f(const Herm3f& K, const cplxf psi[3], cplxf d[3]) {
+  Split3f e;
+  if (!split3_f(K, psi, e)) {
+    d[0] = d[1] = d[2] = mkf(0.0f, 0.0f);
+    return;
+  }
+  float sh, ch, tsh, tch;
+  sincos_f(0.5f * e.phi, sh, ch);
+  sincos_f(0.5f * e.th, tsh, tch);
+  const float cpm1 = -2.0f * (sh * sh), sp = 2.0f * (sh * ch);
+  const float ctm1 = -2.0f * (tsh * tsh);
+  const float sc = (e.th > 0.0f) ? (2.0f * (tsh * tch)) * rcp_f(e.th) : 1.0f;
+  const cplxf ap = cmulf(e.al, mkf(cpm1, -sp));
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    d[c] = caddf(cmulf(ap, e.v1[c]),
+                 mkf(fmaf(ctm1, e.pp[c].re, sc * e.kp[c].im), fmaf(ctm1, e.pp[c].im, -(sc * e.kp[c].re))));
 }
 
 }  // namespace nb

@@ -452,8 +452,8 @@ __device__ __forceinline__ Herm3f gen3f(int s, const float* v, float lam, const 
 template <int KIND>
 __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Radial& g0, const Radial& gm,
                                       const Radial& g1, const RowGeo& rg, const double (*sJ)[16],
-                                      const double* tab, float* snn, int lane, long long* fl, I128& T,
-                                      int& err) {
+                                      const double* tab, double* snd, float* snn, int lane, long long* fl,
+                                      I128& T, int& err) {
   const float lam0f = (float)g0.lam, lammf = (float)gm.lam, lam1f = (float)g1.lam;
   const long long plane = a.plane;
   const int NE = a.NE;
@@ -478,6 +478,15 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
     if (KIND == 4) {
       nunu<8>(sJ[3], g1.mu, rg.c1, t);
       for (int i = 0; i < 8; ++i) snn[24 + i] = (float)t[i];
+      // the final update builds Theta's generators in FP64 (below)
+      nunu<8>(sJ[0], g0.mu, rg.c0, t);
+      for (int i = 0; i < 8; ++i) snd[i] = t[i];
+      nunu<8>(sJ[1], gm.mu, rg.cm, t);
+      for (int i = 0; i < 8; ++i) snd[8 + i] = t[i];
+      nunu<8>(sJ[2], gm.mu, rg.cm, t);
+      for (int i = 0; i < 8; ++i) snd[16 + i] = t[i];
+      nunu<8>(sJ[3], g1.mu, rg.c1, t);
+      for (int i = 0; i < 8; ++i) snd[24 + i] = t[i];
     }
   }
   const double* G = tab + (size_t)(6 + s) * NE;
@@ -516,18 +525,33 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
         } else if (KIND == 3) {
           exp3_apply_f(gen3f(s, v, lammf, snn + 16, hcm), ps);
         } else {
-          const Herm3f K4 = gen3f(s, v, lam1f, snn + 24, hc1);
-          const Herm3f C = icommf(K1, K4);
-          Herm3f acc3 = K1;
-          haxpyf(acc3, 2.0f, gen3f(s, v, lammf, snn + 8, hcm));
-          haxpyf(acc3, 2.0f, gen3f(s, v, lammf, snn + 16, hcm));
-          haxpyf(acc3, 1.0f, K4);
-          Herm3f Th = hscalef(1.0f / 6.0f, acc3);
-          haxpyf(Th, 1.0f / 12.0f, C);
-          exp3_apply_f(Th, ps);
-          // renormalise in FP64, store rounded to FP32, moments from the stored values
-          const double re0 = ps[0].re, im0 = ps[0].im, re1 = ps[1].re, im1 = ps[1].im;
-          const double re2 = ps[2].re, im2 = ps[2].im;
+          // Theta = (K1 + 2 K2 + 2 K3 + K4)/6 + i[K1,K4]/12.  The generators are nearly
+          // constant from step to step (the vacuum term is), so rounding them to FP32 would
+          // repeat the same phase error every step; the weighted sum is formed in FP64 and
+          // rounded once.  The commutator, of order |K|^2 h/r, is FP32.
+          double vd[6];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) vd[c] = tab[c * NE + k];
+          Herm3 acc3 = gen3(s, vd, g0.lam, snd, rg.hc0);
+          haxpy(acc3, 2.0, gen3(s, vd, gm.lam, snd + 8, rg.hcm));
+          haxpy(acc3, 2.0, gen3(s, vd, gm.lam, snd + 16, rg.hcm));
+          hadd(acc3, gen3(s, vd, g1.lam, snd + 24, rg.hc1));
+          const Herm3f C = icommf(K1, gen3f(s, v, lam1f, snn + 24, hc1));
+          auto th_of = [](double sum, float cm) { return (float)(sum * (1.0 / 6.0) + (double)cm * (1.0 / 12.0)); };
+          Herm3f Th;
+          Th.d0 = th_of(acc3.d0, C.d0);
+          Th.d1 = th_of(acc3.d1, C.d1);
+          Th.d2 = th_of(acc3.d2, C.d2);
+          Th.o01 = mkf(th_of(acc3.o01.re, C.o01.re), th_of(acc3.o01.im, C.o01.im));
+          Th.o02 = mkf(th_of(acc3.o02.re, C.o02.re), th_of(acc3.o02.im, C.o02.im));
+          Th.o12 = mkf(th_of(acc3.o12.re, C.o12.re), th_of(acc3.o12.im, C.o12.im));
+          // psi + (exp(-i Theta) - 1) psi formed in FP64 from the FP32 increment, then
+          // renormalised in FP64, stored rounded to FP32; moments from the stored values
+          cplxf dl[3];
+          exp3_incr_f(Th, ps, dl);
+          const double re0 = (double)ps[0].re + (double)dl[0].re, im0 = (double)ps[0].im + (double)dl[0].im;
+          const double re1 = (double)ps[1].re + (double)dl[1].re, im1 = (double)ps[1].im + (double)dl[1].im;
+          const double re2 = (double)ps[2].re + (double)dl[2].re, im2 = (double)ps[2].im + (double)dl[2].im;
           const double nrm2 = (fma(re0, re0, im0 * im0) + fma(re1, re1, im1 * im1)) + fma(re2, re2, im2 * im2);
           const double inv = 1.0 / sqrt(nrm2);
           const float o[6] = {(float)(re0 * inv), (float)(im0 * inv), (float)(re1 * inv),
@@ -577,7 +601,7 @@ __device__ __forceinline__ void stage3m(const StepArgs& a, long long n, const do
     const int s = (int)(row / a.NU);
     const int j = (int)(row - (long long)s * a.NU);
     const RowGeo rg = row_geo(u_of(j, a.NU), a.h, g0, gm, g1);
-    row3m<KIND>(a, row, g0, gm, g1, rg, sJ, tab, (float*)snn, lane, fl, T, err);
+    row3m<KIND>(a, row, g0, gm, g1, rg, sJ, tab, snn, (float*)(snn + 32), lane, fl, T, err);
   }
 }
 
@@ -591,7 +615,7 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   __shared__ double sJ[4][NV];
   __shared__ I128 sw[kBlock / 64][NV];
   __shared__ I128 sred[kBlock];
-  __shared__ double snn_all[kBlock / 64][32];
+  __shared__ double snn_all[kBlock / 64][F32 ? 48 : 32];   // nn terms (mixed: then 32 floats)
   __shared__ long long sfold[kBlock / 64][(NC + 2) * 64];
   extern __shared__ double dyn_tab[];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
