@@ -38,6 +38,7 @@ PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X FP64 vector, published (256 CU x 2.4 GHz
 METRIC = "beam-steps/sec + HBM GB/s (3-flavor 800k beams); adjoint/forward time ratio"
 KERNEL_SOURCES = ["paper_1912_10596_amd/csrc/nb_kernels.hip",
                   "paper_1912_10596_amd/csrc/nb_device.h",
+                  "paper_1912_10596_amd/csrc/nb_device32.h",
                   "paper_1912_10596_amd/csrc/nb_stage.h",
                   "paper_1912_10596_amd/csrc/nb_internal.h"]
 
@@ -120,6 +121,43 @@ def adjoint_timing(nb, workloads):
                 ratio=round(ta / tf, 3), loss="sum of dE/N_u Pee over all beams",
                 grad={k: float(v) for k, v in zip(nb.PARAM_NAMES, g)},
                 grad_times_param={k: float(v * xi) for k, v, xi in zip(nb.PARAM_NAMES, g, x)})
+
+
+def batch_timing(nb, workloads, steps: int):
+    """The 256 uneven two-flavour models in one persistent launch: `steps` steps eager
+    (HIP events) and the same number as replays of a captured HIP graph."""
+    import torch
+    ds = workloads.batch_256()
+    s = torch.cuda.Stream()
+    m = nb.Model(ds, stream=s)
+    with torch.cuda.stream(s):
+        m.step(2)                      # warm-up launch
+        m.reset()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        m.step(steps)
+        e1.record(s)
+    torch.cuda.synchronize()
+    eager = e0.elapsed_time(e1) / 1e3
+    with torch.cuda.stream(s):
+        m.reset()
+        m.graph_capture(steps // 4)
+        torch.cuda.synchronize()
+        e0.record(s)
+        for _ in range(4):
+            m.graph_launch()
+        e1.record(s)
+    torch.cuda.synchronize()
+    graph = e0.elapsed_time(e1) / 1e3
+    beams = m.nb
+    del m
+    torch.cuda.empty_cache()
+    return dict(workload=f"256 two-flavour models, {beams} beams in one launch, 10 -> 300 km, "
+                         f"{steps} of 5000 steps", beam_steps_per_s_eager=beams * steps / eager,
+                ms_per_step_eager=round(eager * 1e3 / steps, 4),
+                ms_per_step_graph=round(graph * 1e3 / (4 * (steps // 4)), 4))
 
 
 def mixed_precision(nb, workloads, literal_steps: int):
@@ -256,6 +294,8 @@ def main():
         out["adjoint"] = adj
         out["adjoint_forward_ratio"] = adj["ratio"]
         torch.cuda.empty_cache()
+        log("batched models (256, 63M beams) ...")
+        out["batch"] = batch_timing(nb, workloads, 40)
         log("mixed precision (6M beams) ...")
         out["mixed_precision"] = mixed_precision(nb, workloads, args.mixed_literal_steps)
     if args.copy_probe:
