@@ -9,6 +9,10 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+// No bit-for-bit contract binds this arithmetic, so products and sums may fuse into fma
+// (the rest of the library is compiled without contraction).
+#pragma clang fp contract(fast)
+
 namespace nb {
 
 // sin and cos in FP32: x = k pi/2 + r (three-part split of pi/2 applied with fma),
@@ -243,3 +247,5 @@ __device__ __forceinline__ void exp3_incr_f(const Herm3f& K, const cplxf psi[3],
 }
 
 }  // namespace nb
+
+#pragma clang fp contract(off)

@@ -449,11 +449,16 @@ __device__ __forceinline__ Herm3f gen3f(int s, const float* v, float lam, const 
 }
 
 // One row of the mixed-precision stage with FP32 per-beam arithmetic.
+// The moment contributions of a lane's beams (k = lane mod 64 within a segment of 64 x 16
+// beams) are summed in FP64 and converted to fixed point once per segment, so the total
+// does not depend on the launch shape; 16 beams below 2^58 each stay below 2^62.
 template <int KIND>
 __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Radial& g0, const Radial& gm,
                                       const Radial& g1, const RowGeo& rg, const double (*sJ)[16],
                                       const double* tab, double* snd, float* snn, int lane, long long* fl,
                                       I128& T, int& err) {
+#pragma clang fp contract(fast)
+  constexpr int kSeg = 64 * 16;
   const float lam0f = (float)g0.lam, lammf = (float)gm.lam, lam1f = (float)g1.lam;
   const long long plane = a.plane;
   const int NE = a.NE;
@@ -467,34 +472,46 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
       nunu<8>(sJ[0], g0.mu, rg.c0, t);
       for (int i = 0; i < 8; ++i) snn[i] = (float)t[i];
     }
-    if (KIND == 2 || KIND == 4) {
+    if (KIND == 2) {
       nunu<8>(sJ[1], gm.mu, rg.cm, t);
       for (int i = 0; i < 8; ++i) snn[8 + i] = (float)t[i];
     }
-    if (KIND >= 3) {
+    if (KIND == 3) {
       nunu<8>(sJ[2], gm.mu, rg.cm, t);
       for (int i = 0; i < 8; ++i) snn[16 + i] = (float)t[i];
     }
     if (KIND == 4) {
       nunu<8>(sJ[3], g1.mu, rg.c1, t);
       for (int i = 0; i < 8; ++i) snn[24 + i] = (float)t[i];
-      // the final update builds Theta's generators in FP64 (below)
-      nunu<8>(sJ[0], g0.mu, rg.c0, t);
-      for (int i = 0; i < 8; ++i) snd[i] = t[i];
-      nunu<8>(sJ[1], gm.mu, rg.cm, t);
-      for (int i = 0; i < 8; ++i) snd[8 + i] = t[i];
-      nunu<8>(sJ[2], gm.mu, rg.cm, t);
-      for (int i = 0; i < 8; ++i) snd[16 + i] = t[i];
-      nunu<8>(sJ[3], g1.mu, rg.c1, t);
-      for (int i = 0; i < 8; ++i) snd[24 + i] = t[i];
+      // Theta's generator sum (K1 + 2 K2 + 2 K3 + K4)/6 is affine in the vacuum entries v
+      // of the beam: A v + c with the row constants A = (hc0 + 4 hcm + hc1)/6 and c from the
+      // matter and nn terms, formed here in FP64 (snd[0] = A, snd[1..8] = c)
+      const double w[4] = {rg.hc0, 2.0 * rg.hcm, 2.0 * rg.hcm, rg.hc1};
+      const double lam[4] = {g0.lam, gm.lam, gm.lam, g1.lam};
+      double cs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      double bl = 0.0;
+      for (int i = 0; i < 4; ++i) {
+        const Radial& gi = (i == 0) ? g0 : ((i == 3) ? g1 : gm);
+        const double ci = (i == 0) ? rg.c0 : ((i == 3) ? rg.c1 : rg.cm);
+        nunu<8>(sJ[i], gi.mu, ci, t);
+        for (int c = 0; c < 8; ++c) cs[c] += w[i] * t[c];
+        bl += w[i] * lam[i];
+      }
+      cs[0] += bl;
+      snd[0] = (((w[0] + w[1]) + w[2]) + w[3]) * (1.0 / 6.0);
+      for (int c = 0; c < 8; ++c) {
+        // antineutrinos: H_vac - lam E_ee - nn^*, i.e. real parts negated, imaginary kept
+        const bool keep = (s == 0) || (c == 3) || (c == 5) || (c == 7);
+        snd[1 + c] = (keep ? cs[c] : -cs[c]) * (1.0 / 6.0);
+      }
     }
   }
   const double* G = tab + (size_t)(6 + s) * NE;
   const long long rb = row * NE;
   I128 mine = i128_zero();
-  for (int k0 = lane; k0 - lane < NE; k0 += 64 * 32) {
-    const int kend = min(NE, k0 + 64 * 32);
-    long long acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int k0 = lane; k0 - lane < NE; k0 += kSeg) {
+    const int kend = min(NE, k0 + kSeg);
+    double dacc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     float q[6];
     if (k0 < kend) {
 #pragma unroll
@@ -510,8 +527,12 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
       double pd[6];
       if (KIND >= 1) {
         float v[6];
+        double vd[6];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) v[c] = (float)tab[c * NE + k];
+        for (int c = 0; c < 6; ++c) {
+          vd[c] = tab[c * NE + k];
+          v[c] = (float)vd[c];
+        }
         Herm3f K1;
         if (KIND != 3) K1 = gen3f(s, v, lam0f, snn, hc0);
         if (KIND == 1) {
@@ -527,24 +548,19 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
         } else {
           // Theta = (K1 + 2 K2 + 2 K3 + K4)/6 + i[K1,K4]/12.  The generators are nearly
           // constant from step to step (the vacuum term is), so rounding them to FP32 would
-          // repeat the same phase error every step; the weighted sum is formed in FP64 and
-          // rounded once.  The commutator, of order |K|^2 h/r, is FP32.
-          double vd[6];
-#pragma unroll
-          for (int c = 0; c < 6; ++c) vd[c] = tab[c * NE + k];
-          Herm3 acc3 = gen3(s, vd, g0.lam, snd, rg.hc0);
-          haxpy(acc3, 2.0, gen3(s, vd, gm.lam, snd + 8, rg.hcm));
-          haxpy(acc3, 2.0, gen3(s, vd, gm.lam, snd + 16, rg.hcm));
-          hadd(acc3, gen3(s, vd, g1.lam, snd + 24, rg.hc1));
+          // repeat the same phase error every step; their weighted sum is formed in FP64
+          // from the row constants and rounded once.  The commutator, of order |K|^2 h/r,
+          // is FP32.
           const Herm3f C = icommf(K1, gen3f(s, v, lam1f, snn + 24, hc1));
-          auto th_of = [](double sum, float cm) { return (float)(sum * (1.0 / 6.0) + (double)cm * (1.0 / 12.0)); };
+          const double A = snd[0];
+          auto th_of = [](double sum, float cm) { return (float)fma((double)cm, 1.0 / 12.0, sum); };
           Herm3f Th;
-          Th.d0 = th_of(acc3.d0, C.d0);
-          Th.d1 = th_of(acc3.d1, C.d1);
-          Th.d2 = th_of(acc3.d2, C.d2);
-          Th.o01 = mkf(th_of(acc3.o01.re, C.o01.re), th_of(acc3.o01.im, C.o01.im));
-          Th.o02 = mkf(th_of(acc3.o02.re, C.o02.re), th_of(acc3.o02.im, C.o02.im));
-          Th.o12 = mkf(th_of(acc3.o12.re, C.o12.re), th_of(acc3.o12.im, C.o12.im));
+          Th.d0 = th_of(fma(A, vd[0], snd[1]), C.d0);
+          Th.d1 = th_of(fma(A, vd[1], snd[2]), C.d1);
+          Th.d2 = th_of(A * vd[2], C.d2);
+          Th.o01 = mkf(th_of(fma(A, vd[3], snd[3]), C.o01.re), th_of(snd[4], C.o01.im));
+          Th.o02 = mkf(th_of(fma(A, vd[4], snd[5]), C.o02.re), th_of(snd[6], C.o02.im));
+          Th.o12 = mkf(th_of(fma(A, vd[5], snd[7]), C.o12.re), th_of(snd[8], C.o12.im));
           // psi + (exp(-i Theta) - 1) psi formed in FP64 from the FP32 increment, then
           // renormalised in FP64, stored rounded to FP32; moments from the stored values
           cplxf dl[3];
@@ -577,8 +593,11 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
       }
       const double w = G[k];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) acc[i] += to_fix(w * v8[i], a.s1, kTwo58, err);
+      for (int i = 0; i < 8; ++i) dacc[i] = fma(w, v8[i], dacc[i]);
     }
+    long long acc[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = to_fix(dacc[i], a.s1, kTwo62, err);
     fold_segment<8>(acc, lane, fl, mine);
   }
   close_row<8>(Scales{a.s1, a.s0, a.p2e1, a.p2e0}, lane, mine, icmom, T, err);
