@@ -105,7 +105,7 @@ struct nb_model {
   hipStream_t stream = nullptr;
   int device = 0, cus = 0, max_blocks = 0, nblocks = 0;
   unsigned long long ticks_per_s = 0;
-  size_t off_X = 0, off_tab = 0, off_J = 0, off_part = 0, off_sync = 0, off_ctl = 0;
+  size_t off_X = 0, off_tab = 0, off_sync = 0, off_ctl = 0;
   size_t off_models = 0, off_waves = 0, off_acc = 0, need = 0;
   size_t off_adj = 0, off_jhist = 0, off_dtab = 0, off_apart = 0, off_aout = 0;
   double* jhist = nullptr;           // set while the adjoint's forward pass records moments
@@ -376,7 +376,7 @@ static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 // Workspace: state planes | tables | stage moments | block partials | sync words | step
 // counter | (batches) model descriptors | wave row ranges | moment accumulators.
 struct Layout {
-  size_t X, tab, J, part, sync, ctl, models, waves, acc, adj, jhist, dtab, apart, aout, need;
+  size_t X, tab, sync, ctl, models, waves, acc, adj, jhist, dtab, apart, aout, need;
 };
 
 // The adjoint (single two-flavour model with adjoint_ckpt = K > 0) reserves state slots
@@ -396,10 +396,6 @@ static Layout layout_of(const nb_model* m) {
   o = align256(o + es * (size_t)m->plane * m->nsc);
   L.tab = o;
   o = align256(o + sizeof(double) * m->tab.size());
-  L.J = o;
-  o = align256(o + sizeof(double) * kFlagCopies * 4 * 2 * m->nc);
-  L.part = o;
-  o = align256(o + 16 * (size_t)kMaxBlocks * 2 * m->nc);
   L.sync = o;
   o = align256(o + sizeof(unsigned int) * kSyncWords);
   L.ctl = o;
@@ -562,8 +558,6 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
   drop_graph(m);
   m->off_X = L.X;
   m->off_tab = L.tab;
-  m->off_J = L.J;
-  m->off_part = L.part;
   m->off_sync = L.sync;
   m->off_ctl = L.ctl;
   m->off_models = L.models;
@@ -702,8 +696,6 @@ static int enqueue_advance(nb_model* m, long long k) {
   StepArgs a{};
   a.X = m->ws + m->off_X;
   a.tab = (const double*)(m->ws + m->off_tab);
-  a.J = (double*)(m->ws + m->off_J);
-  a.part = (unsigned long long*)(m->ws + m->off_part);
   a.sync = sync;
   a.step_ctl = (long long*)(m->ws + m->off_ctl);
   a.plane = m->plane;

@@ -17,7 +17,15 @@ constexpr int kSyncAbort = 1 * kLineWords;   // set when any block gives up wait
 constexpr int kSyncStatus = 2 * kLineWords;  // bit 0: fixed-point range error, bit 1: barrier timeout
 constexpr int kSyncFlag = 4 * kLineWords;    // [kFlagCopies] lines: epoch + 1 of the last release
 constexpr int kSyncArrive = kSyncFlag + kFlagCopies * kLineWords;  // [kMaxBlocks] lines
-constexpr int kSyncWords = kSyncArrive + kMaxBlocks * kLineWords;
+// Tagged 64-bit words of the single-model stepping kernels' moment reduction (every word
+// carries the barrier epoch it belongs to, so no separate arrival or release word is
+// needed): kFlagCopies copies of the reduced moments (block b reads copy b % kFlagCopies),
+// two lines each; one two-line slot of block partials per block.
+constexpr int kTagLines = 2;
+constexpr int kSyncJTag = kSyncArrive + kMaxBlocks * kLineWords;
+constexpr int kSyncPart = kSyncJTag + kFlagCopies * kTagLines * kLineWords;
+constexpr int kSyncWords = kSyncPart + kMaxBlocks * kTagLines * kLineWords;
+constexpr int kTagWords64 = kTagLines * kLineWords / 2;   // 64-bit words per copy or slot
 
 constexpr int kBlock = 512;       // threads per block of the stepping kernels (8 waves)
 
@@ -25,10 +33,7 @@ constexpr int kBlock = 512;       // threads per block of the stepping kernels (
 struct StepArgs {
   void* X;                 // state planes [nsc][plane] (double, or float for FP32 state)
   const double* tab;       // tables: 2f [bx|bz|G0|G1] x NE; 3f [h_ee..h_mt (6)|G0|G1] x NE
-  double* J;               // stage moments [kFlagCopies][4][2*NC] (J0 then J1 per slot); block b
-                           // reads copy b % kFlagCopies
-  unsigned long long* part;// block partials [gridDim][2*NC][2] (I128 halves)
-  unsigned int* sync;      // kSyncWords words
+  unsigned int* sync;      // kSyncWords words (barrier words and the tagged reduction words)
   long long* step_ctl;     // [0] device step counter (read at launch start, advanced at the
                            // end); [1] target of a group of windowed launches
   long long plane;         // plane stride (elements)

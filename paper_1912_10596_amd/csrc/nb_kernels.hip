@@ -25,88 +25,154 @@ __device__ __forceinline__ Radial radial_at(const StepArgs& a, double r) {
   return radial(a.R, a.ne_power, a.lam0, r);
 }
 
-template <int NV>
-__device__ __forceinline__ I128 select_comp(const I128 (&S)[NV], int c) {
-  I128 r = S[0];
-#pragma unroll
-  for (int i = 1; i < NV; ++i) {
-    if (c == i) r = S[i];
-  }
-  return r;
+// Grid-wide reduction of the stage moments with tagged words.  Every 64-bit word that
+// crosses blocks carries the epoch of the barrier it belongs to, so a reader knows from
+// the word itself whether it is current, and no arrival or release word (and no store
+// acknowledgement before one) lies on the critical path:
+//  * every block publishes its partial (NV 128-bit sums, each below 2^95 in magnitude) as
+//    2 NV words of a 16-bit tag and a 48-bit chunk: bits 0..47, then bits 48..95;
+//  * block 0 polls all partial words (each of its threads owns one chunk position of a
+//    set of blocks and re-polls only the words not yet current, all loads in flight),
+//    adds the chunks in 64-bit integers (below 2^61 for up to 8192 blocks), combines them
+//    to the exact 128-bit totals and publishes the moments as 2 NV words of a 32-bit tag
+//    and a 32-bit half, in kFlagCopies copies;
+//  * every other block polls the 2 NV words of its copy, one per lane of its first wave.
+// A word is written again only after every block has read it: block b publishes partial
+// e + 1 after reading moments e, which block 0 publishes after reading every partial e.
+// All words are zeroed before each launch and epochs start at 1, so a tag equal to the
+// wanted epoch is never stale (the 16-bit tags of the partials repeat only every 65536
+// barriers, and every partial word is rewritten at every barrier).
+// Returns false if the barrier was abandoned (time limit or abort).
+constexpr unsigned long long kMask48 = (1ull << 48) - 1ull;
+// 48-bit chunk k of a 128-bit value below 2^95 in magnitude: k = 0 the unsigned bits
+// 0..47, k = 1 the signed bits 48..95 (as a 48-bit field of the tagged word, and as its
+// integer value).
+__device__ __forceinline__ unsigned long long chunk_field(const I128& x, int k) {
+  return (k ? ((x.lo >> 48) | ((unsigned long long)x.hi << 16)) : x.lo) & kMask48;
+}
+__device__ __forceinline__ long long chunk_value(unsigned long long field, int k) {
+  return k ? ((long long)(field << 16) >> 16) : (long long)field;
 }
 
-// Grid-wide reduction of the stage moments without read-modify-write contention: every
-// block publishes its partial (threads tid < NV) and then an arrival word of its own;
-// block 0 waits for all arrival words, folds the partials exactly, stores the stage
-// moments (J0 | J1) and releases one flag that every other block polls.
-// Returns false if the barrier was abandoned (time limit or abort).
+// blk: the block's partial (threads tid < NV hold component tid); own: in block 0, thread
+// tid < 2 NV holds chunk tid % 2 of its component tid / 2.
 template <int NV>
-__device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, double* sJ,
-                            double* gJ, I128* sred) {
+__device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, long long own, double* sJ,
+                            long long* sacc) {
+  constexpr int W = 2 * NV;          // words per partial and per moment copy
+  constexpr int G = kBlock / W;      // block-0 thread groups, one chunk position per thread
+  static_assert(W <= kTagWords64, "tagged slot too small");
   const int tid = threadIdx.x;
   const unsigned want = epoch + 1u;
-  if (tid < NV) {
-    unsigned long long* p = a.part + ((size_t)blockIdx.x * NV + tid) * 2;
-    __hip_atomic_store(p, blk.lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(p + 1, (unsigned long long)blk.hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  unsigned long long* part = reinterpret_cast<unsigned long long*>(a.sync + kSyncPart);
+  unsigned long long* jw = reinterpret_cast<unsigned long long*>(a.sync + kSyncJTag);
+  const unsigned long long tag16 = (unsigned long long)(want & 0xffffu);
   if (blockIdx.x != 0) {
-    if (!arrive_and_wait(a.sync, a.timeout_ticks, want)) return false;
-    if (tid < NV)
-      sJ[tid] = as_double(__hip_atomic_load(
-          (unsigned long long*)gJ + (size_t)(blockIdx.x % kFlagCopies) * 4 * NV + tid, __ATOMIC_RELAXED,
-          __HIP_MEMORY_SCOPE_AGENT));
-    __syncthreads();
-    return true;
-  }
-  if (!wait_arrivals(a.sync, a.timeout_ticks, want)) return false;
-  // fold: thread (v, g) adds partial v of blocks g, g + G, ... (eight loads in flight)
-  constexpr int G = kBlock / NV;
-  const int v = tid % NV, g = tid / NV;
-  if (g < G) {
-    const unsigned long long* P = a.part + (size_t)v * 2;
-    auto ld = [&](unsigned b) {
-      const unsigned long long* q = P + (size_t)b * NV * 2;
-      return I128{__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                  (long long)__hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
-    };
-    I128 acc = i128_zero();
-    unsigned b = g;
-    for (; b + 7 * G < gridDim.x; b += 8 * G) {
-      I128 t[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) t[i] = ld(b + i * G);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) acc = i128_add(acc, t[i]);
+    if (tid < NV) {
+      unsigned long long* q = part + (size_t)blockIdx.x * kTagWords64 + 2 * tid;
+      __hip_atomic_store(q, (tag16 << 48) | chunk_field(blk, 0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(q + 1, (tag16 << 48) | chunk_field(blk, 1), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
     }
-    for (; b < gridDim.x; b += G) acc = i128_add(acc, ld(b));
-    sred[tid] = acc;
+    int ok = 1;
+    if (tid < W) {
+      const unsigned long long* w =
+          jw + (size_t)(blockIdx.x % kFlagCopies) * kTagWords64 + tid;
+      const unsigned long long t0 = wall_clock64();
+      unsigned long long x;
+      for (unsigned it = 1;; ++it) {
+        x = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((unsigned)(x >> 32) == want) break;
+        if ((it & 31u) == 0u && give_up(a.sync, t0, a.timeout_ticks)) {
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      // lane 2v holds the low half of moment v, lane 2v + 1 the high half
+      const unsigned hi = __shfl_down((unsigned)x, 1, 64);
+      if (ok && (tid & 1) == 0)
+        sJ[tid >> 1] = as_double(((unsigned long long)hi << 32) | (x & 0xffffffffull));
+    }
+    return !__syncthreads_or(!ok);
   }
-  __syncthreads();
+  // block 0: its own partial goes straight to the fold
+  int ok = 1;
+  const int pos = tid % W, g = tid / W;
+  long long acc = (g == 0) ? own : 0;
+  if (g < G) {
+    const unsigned long long t0 = wall_clock64();
+    for (unsigned b0 = 1 + g; b0 < gridDim.x && ok; b0 += 16 * G) {
+      unsigned pend = 0;
+      unsigned long long w[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (b0 + i * G < gridDim.x) pend |= 1u << i;
+      for (unsigned it = 1; pend; ++it) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          if (pend & (1u << i))
+            w[i] = __hip_atomic_load(part + (size_t)(b0 + i * G) * kTagWords64 + pos, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          if ((pend & (1u << i)) && (w[i] >> 48) == tag16) {
+            acc += chunk_value(w[i] & kMask48, pos & 1);
+            pend &= ~(1u << i);
+          }
+        }
+        if (!pend) break;
+        if ((it & 31u) == 0u && give_up(a.sync, t0, a.timeout_ticks)) {
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+  }
+  sacc[tid] = acc;
+  if (__syncthreads_or(!ok)) return false;
   if (tid < NV) {
-    I128 tot = i128_zero();
-    for (int gg = 0; gg < G; ++gg) tot = i128_add(tot, sred[gg * NV + tid]);
+    long long c0 = 0, c1 = 0;
+    for (int gg = 0; gg < G; ++gg) {
+      c0 += sacc[gg * W + 2 * tid];
+      c1 += sacc[gg * W + 2 * tid + 1];
+    }
+    // total = c0 + c1 2^48 (c0 >= 0, c1 signed)
+    const I128 tot = i128_add(I128{(unsigned long long)c0, 0ll},
+                              I128{(unsigned long long)c1 << 48, c1 >> 16});
     const double val = i128_to_double(tot) * (tid < NV / 2 ? a.p2e0 : a.p2e1);
     sJ[tid] = val;
-    for (int c = 0; c < kFlagCopies; ++c)
-      __hip_atomic_store((unsigned long long*)gJ + (size_t)c * 4 * NV + tid, as_bits(val), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long bits = as_bits(val);
+    const unsigned long long tg = (unsigned long long)want << 32;
+#pragma unroll
+    for (int c = 0; c < kFlagCopies; ++c) {
+      unsigned long long* q = jw + (size_t)c * kTagWords64 + 2 * tid;
+      __hip_atomic_store(q, tg | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(q + 1, tg | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
-  release_grid(a.sync, want);
+  __syncthreads();
   return true;
 }
 
 // Fold the waves' per-lane totals (lane v holds value v) and run the grid reduction.
 template <int NV>
 __device__ bool finish_stage(const StepArgs& a, unsigned epoch, I128 T, I128 (*sw)[NV],
-                             I128* sred, double* sJ, double* gJ) {
+                             long long* sacc, double* sJ) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane < NV) sw[wid][lane] = T;
   __syncthreads();
   I128 blk = i128_zero();
+  long long own = 0;
   if (threadIdx.x < NV)
     for (int w = 0; w < kBlock / 64; ++w) blk = i128_add(blk, sw[w][threadIdx.x]);
-  return grid_reduce<NV>(a, epoch, blk, sJ, gJ, sred);
+  if (blockIdx.x == 0 && threadIdx.x < 2 * NV) {
+    I128 c = i128_zero();
+    for (int w = 0; w < kBlock / 64; ++w) c = i128_add(c, sw[w][threadIdx.x >> 1]);
+    own = chunk_value(chunk_field(c, threadIdx.x & 1), threadIdx.x & 1);
+  }
+  return grid_reduce<NV>(a, epoch, blk, own, sJ, sacc);
 }
 
 // ------------------------------------------------------------- row helpers
@@ -633,7 +699,7 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   constexpr int NV = 2 * NC;
   __shared__ double sJ[4][NV];
   __shared__ I128 sw[kBlock / 64][NV];
-  __shared__ I128 sred[kBlock];
+  __shared__ long long sacc[kBlock];
   __shared__ double snn_all[kBlock / 64][F32 ? 48 : 32];   // nn terms (mixed: then 32 floats)
   __shared__ long long sfold[kBlock / 64][(NC + 2) * 64];
   extern __shared__ double dyn_tab[];
@@ -665,7 +731,7 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   if constexpr (NF == 2) stage2<0>(a, step0, sJ, tab, gw, nw, lane, fl, T, err);
   else if constexpr (F32) stage3m<0>(a, step0, sJ, tab, snn, gw, nw, lane, fl, T, err);
     else stage3<ST, 0>(a, step0, sJ, tab, snn, gw, nw, lane, fl, T, err);
-  ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[0], a.J);
+  ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[0]);
   // the adjoint's forward pass records every stage's moments: [step][slot][NV]
   auto record = [&](long long step, int slot) {
     if (a.Jhist && ok && blockIdx.x == 0 && threadIdx.x < NV)
@@ -677,25 +743,25 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
     if constexpr (NF == 2) stage2<1>(a, n, sJ, tab, gw, nw, lane, fl, T, err);
     else if constexpr (F32) stage3m<1>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
     else stage3<ST, 1>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
-    if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[1], a.J + NV))) break;
+    if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[1]))) break;
     record(n, 1);
     T = i128_zero();
     if constexpr (NF == 2) stage2<2>(a, n, sJ, tab, gw, nw, lane, fl, T, err);
     else if constexpr (F32) stage3m<2>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
     else stage3<ST, 2>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
-    if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[2], a.J + 2 * NV))) break;
+    if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[2]))) break;
     record(n, 2);
     T = i128_zero();
     if constexpr (NF == 2) stage2<3>(a, n, sJ, tab, gw, nw, lane, fl, T, err);
     else if constexpr (F32) stage3m<3>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
     else stage3<ST, 3>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
-    if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[3], a.J + 3 * NV))) break;
+    if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[3]))) break;
     record(n, 3);
     T = i128_zero();
     if constexpr (NF == 2) stage2<4>(a, n, sJ, tab, gw, nw, lane, fl, T, err);
     else if constexpr (F32) stage3m<4>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
     else stage3<ST, 4>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
-    ok = finish_stage<NV>(a, epoch++, T, sw, sred, sJ[0], a.J);
+    ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[0]);
     record(n + 1, 0);
   }
   if (err) __hip_atomic_fetch_or(a.sync + kSyncStatus, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

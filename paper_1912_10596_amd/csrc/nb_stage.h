@@ -35,6 +35,20 @@ __device__ __forceinline__ unsigned long long as_bits(double d) { return (unsign
 // published data only after it has read the word that announces them.  So the barrier
 // needs no cache maintenance at all: the state written in the same stage stays in L2.
 
+// Checked every 32nd poll of a wait: true if another block has aborted, or if this wait,
+// begun at t0, has passed the launch's time limit (then it sets the abort word and status
+// bit 1 so that every other waiter gives up too).
+__device__ __forceinline__ bool give_up(unsigned* sync, unsigned long long t0,
+                                        unsigned long long timeout_ticks) {
+  if (__hip_atomic_load(sync + kSyncAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return true;
+  if (wall_clock64() - t0 > timeout_ticks) {
+    __hip_atomic_store(sync + kSyncAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_or(sync + kSyncStatus, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+  }
+  return false;
+}
+
 // Poll *w (relaxed) until it reaches want; gives up when another block has aborted or the
 // launch's time limit passes (then it sets the abort word and status bit 1).  The abort
 // word and the clock are read only every 32nd poll, so a poll costs one load round trip.
@@ -43,14 +57,7 @@ __device__ __forceinline__ bool poll_until(unsigned* sync, unsigned long long ti
   const unsigned long long t0 = wall_clock64();
   for (unsigned it = 1;; ++it) {
     if (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want) return true;
-    if ((it & 31u) == 0u) {
-      if (__hip_atomic_load(sync + kSyncAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
-      if (wall_clock64() - t0 > timeout_ticks) {
-        __hip_atomic_store(sync + kSyncAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_or(sync + kSyncStatus, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return false;
-      }
-    }
+    if ((it & 31u) == 0u && give_up(sync, t0, timeout_ticks)) return false;
     __builtin_amdgcn_s_sleep(1);
   }
 }
@@ -68,17 +75,9 @@ __device__ __forceinline__ bool wait_arrivals(unsigned* sync, unsigned long long
         lowest = min(lowest, __hip_atomic_load(sync + kSyncArrive + b * kLineWords, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT));
       if (lowest >= want) break;
-      if ((it & 31u) == 0u) {
-        if (__hip_atomic_load(sync + kSyncAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          ok = 0;
-          break;
-        }
-        if (wall_clock64() - t0 > timeout_ticks) {
-          __hip_atomic_store(sync + kSyncAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_fetch_or(sync + kSyncStatus, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          ok = 0;
-          break;
-        }
+      if ((it & 31u) == 0u && give_up(sync, t0, timeout_ticks)) {
+        ok = 0;
+        break;
       }
       __builtin_amdgcn_s_sleep(1);
     }
