@@ -106,62 +106,120 @@ __device__ __forceinline__ double wave_sum_f64(double x) {
 }
 
 // Deterministic grid sum of NV per-thread values: wave butterflies, the block's waves in
-// order, then block 0 folds the block partials in a fixed order and releases the grid.
-// The result lands in res[0..NV) of every block.  Returns false if the barrier was
-// abandoned (time limit or abort).
+// order, then block 0 adds the block partials in ascending block order within each of its
+// thread groups and the group sums in order.  Partials and result travel as tagged words
+// (a 32-bit barrier epoch and a 32-bit half of the double), the protocol of the stepping
+// kernels' moment reduction: block b publishes its partial as 2 NV words, block 0 polls
+// every partial word with all loads in flight and publishes the sums in kFlagCopies copies,
+// the other blocks poll the 2 NV words of copy b % kFlagCopies.  The result lands in
+// res[0..NV) of every block.  Returns false if the barrier was abandoned (time limit or
+// abort).
 template <int NV>
 __device__ bool grid_sum(const AdjArgs& a, unsigned epoch, double (&v)[NV], double* res,
                          double (*sw)[8], double* sred) {
+  constexpr int W = 2 * NV;        // words per partial and per result copy
+  constexpr int G = kBlock / W;    // block-0 thread groups
+  static_assert(W <= kTagWords64, "tagged slot too small");
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const unsigned want = epoch + 1u;
-  unsigned long long* gres = reinterpret_cast<unsigned long long*>(a.out + 8);
+  const unsigned long long tg = (unsigned long long)want << 32;
+  unsigned long long* part = reinterpret_cast<unsigned long long*>(a.sync + kSyncPart);
+  unsigned long long* jw = reinterpret_cast<unsigned long long*>(a.sync + kSyncJTag);
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     const double t = wave_sum_f64(v[i]);
     if (lane == 0) sw[wid][i] = t;
   }
   __syncthreads();
-  if (tid < NV) {
+  // thread tid < W: half tid % 2 of block sum tid / 2
+  unsigned half = 0;
+  if (tid < W) {
     double blk = 0.0;
-    for (int w = 0; w < kBlock / 64; ++w) blk += sw[w][tid];
-    __hip_atomic_store(reinterpret_cast<unsigned long long*>(a.part) + (size_t)blockIdx.x * 8 + tid,
-                       as_bits(blk), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int w = 0; w < kBlock / 64; ++w) blk += sw[w][tid >> 1];
+    const unsigned long long bits = as_bits(blk);
+    half = (tid & 1) ? (unsigned)(bits >> 32) : (unsigned)bits;
+    if (blockIdx.x != 0)
+      __hip_atomic_store(part + (size_t)blockIdx.x * kTagWords64 + tid, tg | half, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
   }
   if (blockIdx.x != 0) {
-    if (!arrive_and_wait(a.sync, a.timeout_ticks, want)) return false;
-    if (tid < NV)
-      res[tid] = as_double(__hip_atomic_load(gres + (size_t)(blockIdx.x % kFlagCopies) * 8 + tid, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT));
-    __syncthreads();
-    return true;
-  }
-  if (!wait_arrivals(a.sync, a.timeout_ticks, want)) return false;
-  // fold in ascending block order (four loads in flight)
-  constexpr int G = kBlock / NV;
-  const int vi = tid % NV, g = tid / NV;
-  if (g < G) {
-    const unsigned long long* P = reinterpret_cast<const unsigned long long*>(a.part) + vi;
-    auto ld = [&](unsigned b) {
-      return as_double(__hip_atomic_load(P + (size_t)b * 8, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    };
-    double acc = 0.0;
-    unsigned b = g;
-    for (; b + 3 * G < gridDim.x; b += 4 * G) {
-      const double t0 = ld(b), t1 = ld(b + G), t2 = ld(b + 2 * G), t3 = ld(b + 3 * G);
-      acc = (((acc + t0) + t1) + t2) + t3;
+    int ok = 1;
+    unsigned long long x = 0;
+    if (tid < W) {
+      const unsigned long long* w = jw + (size_t)(blockIdx.x % kFlagCopies) * kTagWords64 + tid;
+      const unsigned long long t0 = wall_clock64();
+      for (unsigned it = 1;; ++it) {
+        x = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((unsigned)(x >> 32) == want) break;
+        if ((it & 31u) == 0u && give_up(a.sync, t0, a.timeout_ticks)) {
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
     }
-    for (; b < gridDim.x; b += G) acc += ld(b);
-    sred[tid] = acc;
+    if (tid < 64) {
+      const unsigned hi = __shfl_down((unsigned)x, 1, 64);
+      if (ok && tid < W && (tid & 1) == 0)
+        res[tid >> 1] = as_double(((unsigned long long)hi << 32) | (x & 0xffffffffull));
+    }
+    return !__syncthreads_or(!ok);
   }
-  __syncthreads();
+  // block 0: thread (g, pos) collects word pos of blocks g, g + G, ... (kFly loads in flight);
+  // the even thread of each pair then adds the doubles in ascending block order
+  // (few loads in flight: the reverse step keeps many per-beam values live across this call)
+  constexpr int kFly = 8;
+  int ok = 1;
+  const int pos = tid % W, g = tid / W;
+  double acc = 0.0;
+  const unsigned long long t0 = wall_clock64();
+  for (unsigned b0 = g; b0 < gridDim.x; b0 += kFly * G) {
+    unsigned long long w[kFly];
+    unsigned pend = 0;
+    if (g < G) {
+#pragma unroll
+      for (int i = 0; i < kFly; ++i) {
+        const unsigned b = b0 + i * G;
+        if (b == 0) w[i] = tg | half;          // block 0's own partial
+        else if (b < gridDim.x) pend |= 1u << i;
+      }
+    }
+    for (unsigned it = 1; pend && ok; ++it) {
+#pragma unroll
+      for (int i = 0; i < kFly; ++i)
+        if (pend & (1u << i))
+          w[i] = __hip_atomic_load(part + (size_t)(b0 + i * G) * kTagWords64 + pos, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+      for (int i = 0; i < kFly; ++i)
+        if ((pend & (1u << i)) && (unsigned)(w[i] >> 32) == want) pend &= ~(1u << i);
+      if (pend && (it & 31u) == 0u && give_up(a.sync, t0, a.timeout_ticks)) ok = 0;
+      if (pend && ok) __builtin_amdgcn_s_sleep(1);
+    }
+    // the two threads of a pair share g, so they run the same iterations of this loop
+#pragma unroll
+    for (int i = 0; i < kFly; ++i) {
+      const unsigned mine = (g < G && b0 + i * G < gridDim.x) ? (unsigned)w[i] : 0u;
+      const unsigned hi = __shfl_down(mine, 1, 64);
+      if (g < G && (pos & 1) == 0 && b0 + i * G < gridDim.x)
+        acc += as_double(((unsigned long long)hi << 32) | mine);
+    }
+  }
+  if (g < G && (pos & 1) == 0) sred[g * NV + (pos >> 1)] = acc;
+  if (__syncthreads_or(!ok)) return false;
   if (tid < NV) {
     double tot = 0.0;
     for (int gg = 0; gg < G; ++gg) tot += sred[gg * NV + tid];
     res[tid] = tot;
-    for (int c = 0; c < kFlagCopies; ++c)
-      __hip_atomic_store(gres + (size_t)c * 8 + tid, as_bits(tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long bits = as_bits(tot);
+#pragma unroll
+    for (int c = 0; c < kFlagCopies; ++c) {
+      unsigned long long* q = jw + (size_t)c * kTagWords64 + 2 * tid;
+      __hip_atomic_store(q, tg | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(q + 1, tg | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
-  release_grid(a.sync, want);
+  __syncthreads();
   return true;
 }
 

@@ -107,7 +107,7 @@ struct nb_model {
   unsigned long long ticks_per_s = 0;
   size_t off_X = 0, off_tab = 0, off_sync = 0, off_ctl = 0;
   size_t off_models = 0, off_waves = 0, off_acc = 0, need = 0;
-  size_t off_adj = 0, off_jhist = 0, off_dtab = 0, off_apart = 0, off_aout = 0;
+  size_t off_adj = 0, off_jhist = 0, off_dtab = 0, off_aout = 0;
   double* jhist = nullptr;           // set while the adjoint's forward pass records moments
   int adj_blocks = 0, adj_bpt = 0;
   long long* pinned = nullptr;       // [0] status, [1] step, [8..12] adjoint gradients
@@ -376,7 +376,7 @@ static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 // Workspace: state planes | tables | stage moments | block partials | sync words | step
 // counter | (batches) model descriptors | wave row ranges | moment accumulators.
 struct Layout {
-  size_t X, tab, sync, ctl, models, waves, acc, adj, jhist, dtab, apart, aout, need;
+  size_t X, tab, sync, ctl, models, waves, acc, adj, jhist, dtab, aout, need;
 };
 
 // The adjoint (single two-flavour model with adjoint_ckpt = K > 0) reserves state slots
@@ -410,17 +410,15 @@ static Layout layout_of(const nb_model* m) {
     L.acc = o;
     o = align256(o + sizeof(unsigned long long) * (size_t)kAccSets * m->nmodels * 6 * kAccLimbs);
   }
-  L.adj = L.jhist = L.dtab = L.apart = L.aout = o;
+  L.adj = L.jhist = L.dtab = L.aout = o;
   if (adjoint_enabled(m)) {
     o = align256(o + sizeof(double) * (size_t)adjoint_slots(m) * 3 * m->plane);
     L.jhist = o;
     o = align256(o + sizeof(double) * (size_t)(m->p.n_steps + 1) * 24);
     L.dtab = o;
     o = align256(o + sizeof(double) * m->subs[0].dtab.size());
-    L.apart = o;
-    o = align256(o + sizeof(double) * (size_t)kMaxBlocks * 8);
     L.aout = o;
-    o = align256(o + sizeof(double) * (8 + kFlagCopies * 8));
+    o = align256(o + sizeof(double) * 8);
   }
   L.need = o;
   return L;
@@ -566,7 +564,6 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
   m->off_adj = L.adj;
   m->off_jhist = L.jhist;
   m->off_dtab = L.dtab;
-  m->off_apart = L.apart;
   m->off_aout = L.aout;
   m->need = L.need;
   m->adj_bpt = 0;
@@ -986,7 +983,6 @@ extern "C" int nb_adjoint(nb_model* m, const double* dev_dl_dpee, double* grad_o
   a.cot = dev_dl_dpee;
   a.cot_const = ((s.p.e_max_mev - s.p.e_min_mev) / (double)s.NE) / (double)s.NU;
   a.state_bar = dev_state_bar;
-  a.part = (double*)(m->ws + m->off_apart);
   a.out = (double*)(m->ws + m->off_aout);
   a.sync = sync;
   a.plane = m->plane;

@@ -90,10 +90,8 @@ struct AdjArgs {
   const double* cot;       // dL/dPee per beam, or nullptr: cot_const for every beam
   double cot_const;
   double* state_bar;       // nullptr, or [3][nb]: dL/d(state at the first step)
-  double* part;            // [gridDim][8] block partials of the reductions
-  double* out;             // [8 + kFlagCopies * 8]: dL/d{L_e, L_ebar, L_x, theta_v, n0}, then the
-                           // copies of the current reduction
-  unsigned int* sync;
+  double* out;             // [8]: dL/d{L_e, L_ebar, L_x, theta_v, n0}
+  unsigned int* sync;      // kSyncWords words (barrier words and the tagged reduction words)
   long long plane, nb;
   int NE, NU;
   long long n0, nsteps, ckpt, nseg;  // first step, steps, checkpoint period, segments
