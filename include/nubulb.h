@@ -44,7 +44,8 @@ enum {
   NB_EWORKSPACE = -3,  /* workspace too small or misaligned (256 B) */
   NB_EHIP = -4,        /* a HIP runtime call failed (no device, launch failure, ...) */
   NB_ENUMERIC = -5,    /* a moment contribution left the fixed-point range (NaN/overflow) */
-  NB_ETIMEOUT = -6     /* a grid barrier did not complete within its time limit */
+  NB_ETIMEOUT = -6,    /* a grid barrier did not complete within its time limit */
+  NB_ESTEP = -7        /* adaptive step control failed (step length underflow or attempt limit) */
 };
 
 enum { NB_FP64 = 0, NB_FP32_STATE = 1 };
@@ -69,6 +70,8 @@ typedef struct {
   double theta[3];      /* 2f: [0] = theta_v.  3f: theta_12, theta_13, theta_23 */
   double delta_cp;      /* must be 0 (real mixing matrix) */
   double n0_cm3;        /* electron density scale */
+  int32_t adaptive;     /* 1: reserve workspace for nb_run_adaptive (single FP64 models) */
+  int32_t reserved;     /* must be 0 */
 } nb_params;
 
 typedef struct nb_model nb_model;
@@ -147,6 +150,30 @@ int nb_autotune(nb_model *m, int32_t trial_steps, double *best_ms);
  * order, so results repeat bit for bit.  Not capturable into a graph (it synchronises). */
 int nb_adjoint(nb_model *m, const double *dev_dl_dpee, double *grad_out, int32_t ckpt_every,
                double *dev_state_bar);
+
+/* Adaptive step-size control (the paper's solver adapts its radial step, Sec. 3.4).
+ * Integrates from r_start to r_end with RKMK4 steps whose length follows an embedded error
+ * estimate: E = max over beams of |Theta - F_2|^2, the squared distance between the order-4
+ * generator Theta and the generator F_2 of the exponential midpoint rule built from the
+ * same stages (3 flavours: traceless part, Frobenius norm), with the low 16 bits of its
+ * binary form cleared.  A step of length h is accepted if E <= tol^2; then h doubles (at
+ * most to h_max_km; <= 0: no cap) if E <= tol^2/64.  A rejected step is retried from the
+ * same state with h/2.  The last step ends exactly at r_end.  The first step length is
+ * (r_end - r_start)/n_steps.  Every decision is taken by every block from the same reduced
+ * E, so the run is deterministic and matches a serial implementation bit for bit.
+ *   Requires a single FP64 model created with adaptive = 1, at step 0 (after nb_bind or
+ *   nb_reset).  On success the state is at r_end and the step index is n_steps.
+ *   stats (host, may be NULL): accepted and rejected steps, attempts, and the step length
+ *   after the last decision.
+ *   NB_ESTEP if h falls below 2^-40 of the first step length or max_attempts is exceeded;
+ *   the model is then reset to its initial state.
+ * Not capturable into a graph (it synchronises to read the step statistics). */
+typedef struct {
+  int64_t accepted, rejected, attempts;
+  double h_last_km;
+} nb_adaptive_stats;
+int nb_run_adaptive(nb_model *m, double tol, double h_max_km, int64_t max_attempts,
+                    nb_adaptive_stats *stats);
 
 /* Host tables (no device work), layout as [E_k | weights[2][NE] | vacuum terms |
  * lam0, kappa0, h, 2^-e1, 2^-e0, e1, e0]; vacuum terms are (B_x, B_z) per k for 2f and

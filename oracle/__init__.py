@@ -66,6 +66,9 @@ def lib():
         L.nbo_fixed_sum.restype = C.c_double
         L.nbo_single_angle_run.argtypes = [C.POINTER(Params), dp]
         L.nbo_adjoint.argtypes = [vp, C.c_int32, vp, dp, dp, vp]
+        L.nbo_run_adaptive.argtypes = [vp, C.c_double, C.c_double, C.c_int64,
+                                       C.POINTER(C.c_int64), C.POINTER(C.c_int64), dp]
+        L.nbo_step_error.argtypes = [vp, C.c_double, dp]
         _lib = L
     return _lib
 
@@ -131,6 +134,20 @@ class Model:
 
     def step_index(self) -> int:
         return int(lib().nbo_step_index(self.h))
+
+    def step_error(self, h: float) -> float:
+        """Error estimate of one step of length h from the current state (no state change)."""
+        e = C.c_double()
+        _check(lib().nbo_step_error(self.h, float(h), C.byref(e)), "nbo_step_error")
+        return float(e.value)
+
+    def run_adaptive(self, tol: float, h_max: float = 0.0, max_attempts: int = 10**7) -> dict:
+        """Adaptive step-size control from step 0 to r_end (nbo_run_adaptive)."""
+        acc, rej, hl = C.c_int64(), C.c_int64(), C.c_double()
+        _check(lib().nbo_run_adaptive(self.h, float(tol), float(h_max), int(max_attempts),
+                                      C.byref(acc), C.byref(rej), C.byref(hl)),
+               "nbo_run_adaptive")
+        return dict(accepted=int(acc.value), rejected=int(rej.value), h_last=float(hl.value))
 
     def pee(self) -> np.ndarray:
         out = np.empty(self.nb, np.float64)

@@ -580,25 +580,30 @@ static herm3 h3_scale(double a, const herm3 *H) {
 }
 
 /* Scaled stage generator of beam b at radius g: 2f f = (h/c) B; 3f K = (h/c) H. */
-static void stage_f2(const nbo_model *m, int64_t b, const radial *g, const double *J0,
-                     const double *J1, double f[3]) {
+static void stage_f2h(const nbo_model *m, int64_t b, const radial *g, const double *J0,
+                      const double *J1, double h, double f[3]) {
   const int s = (int)(b / (m->NU * m->NE));
   const int64_t j = (b / m->NE) % m->NU, k = b % m->NE;
   const double c = c_of(g, u_of(m, j));
-  const double hc = m->h / c;
+  const double hc = h / c;
   double B[3];
   beam_B2(m, s, k, g, c, J0, J1, B);
   f[0] = hc * B[0]; f[1] = hc * B[1]; f[2] = hc * B[2];
 }
-static herm3 stage_K3(const nbo_model *m, int64_t b, const radial *g, const double *J0,
-                      const double *J1) {
+static herm3 stage_K3h(const nbo_model *m, int64_t b, const radial *g, const double *J0,
+                       const double *J1, double h) {
   const int s = (int)(b / (m->NU * m->NE));
   const int64_t j = (b / m->NE) % m->NU, k = b % m->NE;
   const double c = c_of(g, u_of(m, j));
-  const double hc = m->h / c;
+  const double hc = h / c;
   herm3 H;
   beam_H3(m, s, k, g, c, J0, J1, &H);
   return h3_scale(hc, &H);
+}
+/* the 2-flavour generator of the fixed step h = (r_end - r_start) / n_steps */
+static void stage_f2(const nbo_model *m, int64_t b, const radial *g, const double *J0,
+                     const double *J1, double f[3]) {
+  stage_f2h(m, b, g, J0, J1, m->h, f);
 }
 
 static void renorm2(double *P) {
@@ -625,29 +630,34 @@ static void apply3(const herm3 *K, const double *x, double *y) {
   for (int c = 0; c < 3; ++c) { y[2 * c] = o[c].re; y[2 * c + 1] = o[c].im; }
 }
 
-/* One RKMK4 step (see the file header). */
-static int step_rkmk4(nbo_model *m) {
-  const double rs = m->p.r_start_km, h = m->h;
-  const double r0 = rs + (double)m->step * h;
-  const double rm = r0 + 0.5 * h;
-  const double r1 = rs + (double)(m->step + 1) * h;
+/* One RKMK4 step (see the file header) from the state X at r0 over the step length h,
+ * with stage radii r0, rm = r0 + h/2 and r1 = r0 + h (r1 passed separately so that the
+ * fixed-step grid r_n = r_start + n h is reproduced exactly).  The new state goes to Xout
+ * (which may be X).  If emax is not NULL it receives the embedded error estimate of the
+ * step: the largest over beams of |Theta - F_2|^2, the squared distance between the
+ * order-4 generator and the generator of the exponential midpoint rule (order 2) built
+ * from the same stages (3 flavours: traceless part, Frobenius norm), with the low 16 bits
+ * of its binary representation cleared. */
+static int rkmk4_step(nbo_model *m, const double *X, double r0, double rm, double r1, double h,
+                      double *Xout, double *emax) {
   const radial g0 = radial_at(m, r0), gm = radial_at(m, rm), g1 = radial_at(m, r1);
   double J[4][2][8];
-  int st = moments(m, m->X, r0, J[0][0], J[0][1]);
+  int st = moments(m, X, r0, J[0][0], J[0][1]);
   const int64_t nb = m->nb;
   const int nsc = m->nsc;
+  double *eb = emax ? (double *)malloc(sizeof(double) * nb) : NULL;
   /* stage 2 */
 #pragma omp parallel for schedule(static)
   for (int64_t b = 0; b < nb; ++b) {
-    const double *x = m->X + b * nsc;
+    const double *x = X + b * nsc;
     double *y = m->Y + b * nsc;
     if (m->nf == 2) {
       double f1[3], o[3];
-      stage_f2(m, b, &g0, J[0][0], J[0][1], f1);
+      stage_f2h(m, b, &g0, J[0][0], J[0][1], h, f1);
       o[0] = 0.5 * f1[0]; o[1] = 0.5 * f1[1]; o[2] = 0.5 * f1[2];
       rotate2(o, x, y);
     } else {
-      herm3 K1 = stage_K3(m, b, &g0, J[0][0], J[0][1]);
+      herm3 K1 = stage_K3h(m, b, &g0, J[0][0], J[0][1], h);
       herm3 O = h3_scale(0.5, &K1);
       apply3(&O, x, y);
     }
@@ -656,18 +666,18 @@ static int step_rkmk4(nbo_model *m) {
   /* stage 3 */
 #pragma omp parallel for schedule(static)
   for (int64_t b = 0; b < nb; ++b) {
-    const double *x = m->X + b * nsc;
+    const double *x = X + b * nsc;
     double *y = m->Y + b * nsc;
     if (m->nf == 2) {
       double f1[3], f2[3], cr[3], o[3];
-      stage_f2(m, b, &g0, J[0][0], J[0][1], f1);
-      stage_f2(m, b, &gm, J[1][0], J[1][1], f2);
+      stage_f2h(m, b, &g0, J[0][0], J[0][1], h, f1);
+      stage_f2h(m, b, &gm, J[1][0], J[1][1], h, f2);
       cross3(f1, f2, cr);
       for (int c = 0; c < 3; ++c) o[c] = 0.5 * f2[c] - 0.125 * cr[c];
       rotate2(o, x, y);
     } else {
-      herm3 K1 = stage_K3(m, b, &g0, J[0][0], J[0][1]);
-      herm3 K2 = stage_K3(m, b, &gm, J[1][0], J[1][1]);
+      herm3 K1 = stage_K3h(m, b, &g0, J[0][0], J[0][1], h);
+      herm3 K2 = stage_K3h(m, b, &gm, J[1][0], J[1][1], h);
       herm3 C = h3_icomm(&K1, &K2), O;
       for (int i = 0; i < 3; ++i) O.d[i] = 0.5 * K2.d[i] + 0.125 * C.d[i];
       for (int i = 0; i < 3; ++i)
@@ -679,14 +689,14 @@ static int step_rkmk4(nbo_model *m) {
   /* stage 4 */
 #pragma omp parallel for schedule(static)
   for (int64_t b = 0; b < nb; ++b) {
-    const double *x = m->X + b * nsc;
+    const double *x = X + b * nsc;
     double *y = m->Y + b * nsc;
     if (m->nf == 2) {
       double f3[3];
-      stage_f2(m, b, &gm, J[2][0], J[2][1], f3);
+      stage_f2h(m, b, &gm, J[2][0], J[2][1], h, f3);
       rotate2(f3, x, y);
     } else {
-      herm3 K3 = stage_K3(m, b, &gm, J[2][0], J[2][1]);
+      herm3 K3 = stage_K3h(m, b, &gm, J[2][0], J[2][1], h);
       apply3(&K3, x, y);
     }
   }
@@ -694,24 +704,29 @@ static int step_rkmk4(nbo_model *m) {
   /* final update */
 #pragma omp parallel for schedule(static)
   for (int64_t b = 0; b < nb; ++b) {
-    double *x = m->X + b * nsc;
+    const double *x = X + b * nsc;
+    double *xo = Xout + b * nsc;
     if (m->nf == 2) {
       double f1[3], f2[3], f3[3], f4[3], cr[3], th[3], y[3];
-      stage_f2(m, b, &g0, J[0][0], J[0][1], f1);
-      stage_f2(m, b, &gm, J[1][0], J[1][1], f2);
-      stage_f2(m, b, &gm, J[2][0], J[2][1], f3);
-      stage_f2(m, b, &g1, J[3][0], J[3][1], f4);
+      stage_f2h(m, b, &g0, J[0][0], J[0][1], h, f1);
+      stage_f2h(m, b, &gm, J[1][0], J[1][1], h, f2);
+      stage_f2h(m, b, &gm, J[2][0], J[2][1], h, f3);
+      stage_f2h(m, b, &g1, J[3][0], J[3][1], h, f4);
       cross3(f1, f4, cr);
       for (int c = 0; c < 3; ++c)
         th[c] = (((f1[c] + 2.0 * f2[c]) + 2.0 * f3[c]) + f4[c]) * (1.0 / 6.0) - cr[c] * (1.0 / 12.0);
+      if (eb) {
+        const double d0 = th[0] - f2[0], d1 = th[1] - f2[1], d2 = th[2] - f2[2];
+        eb[b] = (d0 * d0 + d1 * d1) + d2 * d2;
+      }
       rotate2(th, x, y);
       if (m->p.renorm) renorm2(y);
-      x[0] = y[0]; x[1] = y[1]; x[2] = y[2];
+      xo[0] = y[0]; xo[1] = y[1]; xo[2] = y[2];
     } else {
-      herm3 K1 = stage_K3(m, b, &g0, J[0][0], J[0][1]);
-      herm3 K2 = stage_K3(m, b, &gm, J[1][0], J[1][1]);
-      herm3 K3 = stage_K3(m, b, &gm, J[2][0], J[2][1]);
-      herm3 K4 = stage_K3(m, b, &g1, J[3][0], J[3][1]);
+      herm3 K1 = stage_K3h(m, b, &g0, J[0][0], J[0][1], h);
+      herm3 K2 = stage_K3h(m, b, &gm, J[1][0], J[1][1], h);
+      herm3 K3 = stage_K3h(m, b, &gm, J[2][0], J[2][1], h);
+      herm3 K4 = stage_K3h(m, b, &g1, J[3][0], J[3][1], h);
       herm3 C = h3_icomm(&K1, &K4), T;
       for (int i = 0; i < 3; ++i)
         T.d[i] = (((K1.d[i] + 2.0 * K2.d[i]) + 2.0 * K3.d[i]) + K4.d[i]) * (1.0 / 6.0) + C.d[i] * (1.0 / 12.0);
@@ -720,13 +735,107 @@ static int step_rkmk4(nbo_model *m) {
         const double im = (((K1.o[i].im + 2.0 * K2.o[i].im) + 2.0 * K3.o[i].im) + K4.o[i].im) * (1.0 / 6.0) + C.o[i].im * (1.0 / 12.0);
         T.o[i] = cx_make(re, im);
       }
+      if (eb) {
+        double a[3], o2[3];
+        const double dd0 = T.d[0] - K2.d[0], dd1 = T.d[1] - K2.d[1], dd2 = T.d[2] - K2.d[2];
+        const double tr = ((dd0 + dd1) + dd2) * (1.0 / 3.0);
+        a[0] = dd0 - tr; a[1] = dd1 - tr; a[2] = dd2 - tr;
+        for (int i = 0; i < 3; ++i) {
+          const double re = T.o[i].re - K2.o[i].re, im = T.o[i].im - K2.o[i].im;
+          o2[i] = re * re + im * im;
+        }
+        eb[b] = ((a[0] * a[0] + a[1] * a[1]) + a[2] * a[2]) + 2.0 * ((o2[0] + o2[1]) + o2[2]);
+      }
       double y[6];
       apply3(&T, x, y);
       if (m->p.renorm) renorm3(y);
-      for (int c = 0; c < 6; ++c) x[c] = y[c];
+      for (int c = 0; c < 6; ++c) xo[c] = y[c];
     }
   }
+  if (eb) {
+    double e = 0.0;
+    for (int64_t b = 0; b < nb; ++b)
+      if (eb[b] > e) e = eb[b];
+    uint64_t bits;
+    memcpy(&bits, &e, 8);
+    bits &= ~(uint64_t)0xffff;
+    memcpy(emax, &bits, 8);
+    free(eb);
+  }
+  return st;
+}
+
+/* One step of the fixed grid r_n = r_start + n h, in place. */
+static int step_rkmk4(nbo_model *m) {
+  const double rs = m->p.r_start_km, h = m->h;
+  const double r0 = rs + (double)m->step * h;
+  const double rm = r0 + 0.5 * h;
+  const double r1 = rs + (double)(m->step + 1) * h;
+  const int st = rkmk4_step(m, m->X, r0, rm, r1, h, m->X, NULL);
   m->step += 1;
+  return st;
+}
+
+/* The error estimate of one step of length h from the current state and step, without
+ * advancing (for the estimator's pins). */
+int nbo_step_error(nbo_model *m, double h, double *E) {
+  if (!m || !(h > 0.0) || !E) return NBO_EINVAL;
+  const double r0 = m->p.r_start_km + (double)m->step * m->h;
+  double *Xs = (double *)malloc(sizeof(double) * (size_t)m->nb * (size_t)m->nsc);
+  const int st = rkmk4_step(m, m->X, r0, r0 + 0.5 * h, r0 + h, h, Xs, E);
+  free(Xs);
+  return st ? NBO_ENUMERIC : NBO_OK;
+}
+
+/* Adaptive step-size control on top of the RKMK4 step (the paper integrates with an
+ * adaptive step size, Sec. 3.4; the controller below is this library's own, with
+ * power-of-two step changes so that both implementations take identical decisions):
+ *   a step of length h from r is accepted if its error estimate E <= tol^2; the state
+ *   and r advance, and h doubles (up to h_max) if E <= tol^2 / 64, i.e. when the doubled
+ *   step's estimate, which grows as h^6, is expected to pass as well;
+ *   a rejected step is retried from the same state with h / 2.
+ * The last step is shortened to end exactly at r_end.  The first step length is the
+ * model's (r_end - r_start) / n_steps; the run fails if h falls below 2^-40 of it or the
+ * attempts exceed max_attempts.  The model must be at its start (step 0); it ends at
+ * r_end with its step index set to n_steps. */
+int nbo_run_adaptive(nbo_model *m, double tol, double h_max, int64_t max_attempts,
+                     int64_t *accepted, int64_t *rejected, double *h_last) {
+  if (!m || !(tol > 0.0) || max_attempts < 1 || m->step != 0 || m->p.integrator != 0)
+    return NBO_EINVAL;
+  const double r_end = m->p.r_end_km;
+  double r = m->p.r_start_km, h = m->h;
+  const double hmin = ldexp(m->h, -40);
+  const double hmax = (h_max > 0.0) ? h_max : (r_end - r);
+  const double tol2 = tol * tol, grow = tol2 * (1.0 / 64.0);
+  const size_t bytes = sizeof(double) * (size_t)m->nb * (size_t)m->nsc;
+  double *Xn = (double *)malloc(bytes);
+  int64_t acc = 0, rej = 0, att = 0;
+  int st = NBO_OK;
+  for (;;) {
+    const int last = (r + h >= r_end);
+    const double hs = last ? r_end - r : h;
+    const double r1 = last ? r_end : r + hs;
+    double E = 0.0;
+    if (rkmk4_step(m, m->X, r, r + 0.5 * hs, r1, hs, Xn, &E)) { st = NBO_ENUMERIC; break; }
+    ++att;
+    if (E <= tol2) {
+      double *t = m->X; m->X = Xn; Xn = t;
+      r = r1;
+      ++acc;
+      if (E <= grow && 2.0 * h <= hmax) h = 2.0 * h;
+      if (last) break;
+    } else {
+      ++rej;
+      h = 0.5 * h;
+      if (h < hmin) { st = NBO_ESTEP; break; }
+    }
+    if (att >= max_attempts) { st = NBO_ESTEP; break; }
+  }
+  free(Xn);
+  if (st == NBO_OK) m->step = m->p.n_steps;
+  if (accepted) *accepted = acc;
+  if (rejected) *rejected = rej;
+  if (h_last) *h_last = h;
   return st;
 }
 

@@ -23,7 +23,7 @@
 extern "C" {
 #endif
 
-enum { NBO_OK = 0, NBO_EINVAL = -1, NBO_ENUMERIC = -5 };
+enum { NBO_OK = 0, NBO_EINVAL = -1, NBO_ENUMERIC = -5, NBO_ESTEP = -7 };
 
 typedef struct {
   int32_t n_flavor;     /* 2 or 3 */
@@ -83,6 +83,16 @@ void nbo_exp3_apply(const double *k9, const double *psi6, double *out6);
 void nbo_rotate(const double *x3, const double *p3, double *out3);
 /* Exact fixed-point sum of n doubles scaled by 2^e, returned as a double (tests). */
 double nbo_fixed_sum(const double *v, int64_t n, int e);
+
+/* Adaptive step-size control (RKMK4 steps with an embedded order-2 error estimate; see
+ * nbo.c for the controller).  From step 0 to r_end; *accepted, *rejected and the step
+ * length after the last decision (*h_last) are reported.  h_max <= 0: no cap.
+ * Returns NBO_ESTEP if the step length underflows or max_attempts is exceeded. */
+int  nbo_run_adaptive(nbo_model *m, double tol, double h_max, int64_t max_attempts,
+                      int64_t *accepted, int64_t *rejected, double *h_last);
+
+/* Error estimate of one step of length h from the current state (no state change). */
+int  nbo_step_error(nbo_model *m, double h, double *E);
 
 /* Separately coded single-angle solver (2 flavours): one emission bin at u = 1/2. */
 int  nbo_single_angle_run(const nbo_params *p, double *pee_out /* [2][NE] */);

@@ -13,7 +13,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnubulb.so")
 
-NB_OK, NB_EINVAL, NB_EUNBOUND, NB_EWORKSPACE, NB_EHIP, NB_ENUMERIC, NB_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
+NB_OK, NB_EINVAL, NB_EUNBOUND, NB_EWORKSPACE, NB_EHIP, NB_ENUMERIC, NB_ETIMEOUT, NB_ESTEP = (
+    0, -1, -2, -3, -4, -5, -6, -7)
 NB_FP64, NB_FP32_STATE = 0, 1
 
 EXPORTS = [
@@ -22,7 +23,7 @@ EXPORTS = [
     "nb_step", "nb_run", "nb_step_index", "nb_read_pee", "nb_get_state", "nb_set_state",
     "nb_adjoint", "nb_host_tables", "nb_last_error", "nb_test_sincos", "nb_test_sqrt_div",
     "nb_test_exp3", "nb_test_rotate", "nb_graph_capture", "nb_graph_launch", "nb_autotune",
-    "nb_mixed_fp32_step",
+    "nb_mixed_fp32_step", "nb_run_adaptive",
 ]
 
 
@@ -35,8 +36,13 @@ class Params(C.Structure):
         ("r_start_km", C.c_double), ("r_end_km", C.c_double),
         ("lum_erg_s", C.c_double * 3), ("temp_mev", C.c_double * 3),
         ("dm2_ev2", C.c_double * 2), ("theta", C.c_double * 3), ("delta_cp", C.c_double),
-        ("n0_cm3", C.c_double),
+        ("n0_cm3", C.c_double), ("adaptive", C.c_int32), ("reserved", C.c_int32),
     ]
+
+
+class AdaptiveStats(C.Structure):
+    _fields_ = [("accepted", C.c_int64), ("rejected", C.c_int64), ("attempts", C.c_int64),
+                ("h_last_km", C.c_double)]
 
 
 class NubulbError(RuntimeError):
@@ -88,6 +94,7 @@ def lib():
         L.nb_graph_capture.argtypes = [vp, i64]
         L.nb_graph_launch.argtypes = [vp]
         L.nb_autotune.argtypes = [vp, C.c_int32, dp]
+        L.nb_run_adaptive.argtypes = [vp, C.c_double, C.c_double, i64, C.POINTER(AdaptiveStats)]
         _lib = L
     return _lib
 
@@ -98,9 +105,10 @@ def _check(rc: int, what: str):
 
 
 def make_params(d: dict, precision: int | None = None, adjoint_ckpt: int = 0,
-                max_blocks: int = 0) -> Params:
+                max_blocks: int = 0, adaptive: bool = False) -> Params:
     p = Params()
     p.max_blocks = int(d.get("max_blocks", max_blocks))
+    p.adaptive = int(bool(adaptive))
     for k in ("n_flavor", "n_energy", "n_u", "ne_power", "renorm", "n_steps"):
         setattr(p, k, int(d[k]))
     p.precision = int(d.get("precision", 0) if precision is None else precision)
@@ -130,7 +138,8 @@ class HostModel:
     """A model (or, given a list of parameter dicts, a batch of two-flavour models)
     created on the host only: parameter validation and tables, no device work."""
 
-    def __init__(self, d, precision: int | None = None, adjoint_ckpt: int = 0):
+    def __init__(self, d, precision: int | None = None, adjoint_ckpt: int = 0,
+                 adaptive: bool = False):
         h = C.c_void_p()
         if isinstance(d, (list, tuple)):
             self.ds = [dict(x) for x in d]
@@ -140,7 +149,7 @@ class HostModel:
             d = d[0]
         else:
             self.ds = [dict(d)]
-            self.params = make_params(d, precision, adjoint_ckpt)
+            self.params = make_params(d, precision, adjoint_ckpt, adaptive=adaptive)
             _check(lib().nb_model_create(C.byref(self.params), C.byref(h)), "nb_model_create")
         self.d = dict(d)
         self.h = h
@@ -187,8 +196,8 @@ class Model(HostModel):
     """A bulb model bound to device memory on the current torch device and stream."""
 
     def __init__(self, d: dict, precision: int | None = None, adjoint_ckpt: int = 0,
-                 device="cuda", stream=None):
-        super().__init__(d, precision, adjoint_ckpt)
+                 device="cuda", stream=None, adaptive: bool = False):
+        super().__init__(d, precision, adjoint_ckpt, adaptive)
         torch = _torch()
         nbytes = self.workspace_bytes()
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
@@ -209,6 +218,15 @@ class Model(HostModel):
 
     def step_index(self) -> int:
         return int(lib().nb_step_index(self.h))
+
+    def run_adaptive(self, tol: float, h_max: float = 0.0, max_attempts: int = 10**7) -> dict:
+        """Adaptive step-size control from step 0 to r_end (nb_run_adaptive); the model must
+        have been created with adaptive=True."""
+        st = AdaptiveStats()
+        _check(lib().nb_run_adaptive(self.h, float(tol), float(h_max), int(max_attempts),
+                                     C.byref(st)), "nb_run_adaptive")
+        return dict(accepted=int(st.accepted), rejected=int(st.rejected),
+                    attempts=int(st.attempts), h_last=float(st.h_last_km))
 
     def pee(self, out=None):
         torch = _torch()

@@ -20,6 +20,8 @@ __global__ void k_advance(StepArgs a);
 __global__ void k_batch2(BatchArgs a);
 template <int BPT>
 __global__ void k_adjoint2(AdjArgs a);
+template <int NF, bool TLDS>
+__global__ void k_adaptive(StepArgs a);
 __global__ void k_zero_sync(unsigned int* sync, int keep_status);
 __global__ void k_zero_u64(unsigned long long* p, long long n);
 __global__ void k_set_step(long long* step_ctl, long long step);
@@ -107,7 +109,7 @@ struct nb_model {
   unsigned long long ticks_per_s = 0;
   size_t off_X = 0, off_tab = 0, off_sync = 0, off_ctl = 0;
   size_t off_models = 0, off_waves = 0, off_acc = 0, need = 0;
-  size_t off_adj = 0, off_jhist = 0, off_dtab = 0, off_aout = 0;
+  size_t off_adj = 0, off_jhist = 0, off_dtab = 0, off_aout = 0, off_X2 = 0;
   double* jhist = nullptr;           // set while the adjoint's forward pass records moments
   int adj_blocks = 0, adj_bpt = 0;
   long long* pinned = nullptr;       // [0] status, [1] step, [8..12] adjoint gradients
@@ -142,6 +144,9 @@ static int validate(const nb_params* p) {
   if (p->adjoint_ckpt > 0 && (p->n_flavor != 2 || p->precision != NB_FP64))
     return fail(NB_EINVAL, "the adjoint is a two-flavour FP64 mode");
   if (p->max_blocks < 0) return fail(NB_EINVAL, "max_blocks must be >= 0");
+  if (p->adaptive != 0 && p->adaptive != 1) return fail(NB_EINVAL, "adaptive must be 0 or 1");
+  if (p->adaptive && p->precision != NB_FP64) return fail(NB_EINVAL, "adaptive stepping is an FP64 mode");
+  if (p->reserved != 0) return fail(NB_EINVAL, "reserved must be 0");
   return NB_OK;
 }
 
@@ -325,6 +330,7 @@ extern "C" int nb_batch_create(const nb_params* p, int32_t n_models, nb_model** 
     if (q.n_flavor != 2 || q.precision != NB_FP64)
       return fail(NB_EINVAL, "batched models are two-flavour FP64 (model %d)", i);
     if (q.adjoint_ckpt != 0) return fail(NB_EINVAL, "batched models have no adjoint (model %d)", i);
+    if (q.adaptive != 0) return fail(NB_EINVAL, "batched models step on a fixed grid (model %d)", i);
     if (q.n_steps != p[0].n_steps || q.r_start_km != p[0].r_start_km || q.r_end_km != p[0].r_end_km ||
         q.r_nu_km != p[0].r_nu_km || q.ne_power != p[0].ne_power || q.renorm != p[0].renorm)
       return fail(NB_EINVAL, "batched models must share the radial grid, R, ne_power and renorm (model %d)", i);
@@ -373,10 +379,11 @@ extern "C" int nb_pee_offsets(const nb_model* m, int64_t* off) {
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// Workspace: state planes | tables | stage moments | block partials | sync words | step
-// counter | (batches) model descriptors | wave row ranges | moment accumulators.
+// Workspace: state planes | tables | sync and tagged reduction words | step counter |
+// (batches) model descriptors | wave row ranges | moment accumulators | (adjoint) its
+// regions | (adaptive) the second state buffer.
 struct Layout {
-  size_t X, tab, sync, ctl, models, waves, acc, adj, jhist, dtab, aout, need;
+  size_t X, tab, sync, ctl, models, waves, acc, adj, jhist, dtab, aout, X2, need;
 };
 
 // The adjoint (single two-flavour model with adjoint_ckpt = K > 0) reserves state slots
@@ -420,6 +427,8 @@ static Layout layout_of(const nb_model* m) {
     L.aout = o;
     o = align256(o + sizeof(double) * 8);
   }
+  L.X2 = o;
+  if (!m->batch && m->p.adaptive) o = align256(o + es * (size_t)m->plane * m->nsc);
   L.need = o;
   return L;
 }
@@ -432,6 +441,14 @@ static constexpr size_t kTabLdsMax = 64 * 1024;
 static size_t tab_bytes(const nb_model* m) { return sizeof(double) * m->tab.size(); }
 static bool tab_in_lds(const nb_model* m) { return !m->batch && tab_bytes(m) <= kTabLdsMax; }
 static size_t advance_dyn_lds(const nb_model* m) { return tab_in_lds(m) ? tab_bytes(m) : 0; }
+
+// The adaptive-step kernel of a single FP64 model created with adaptive = 1 (else nullptr).
+static const void* adaptive_kernel(const nb_model* m) {
+  if (m->batch || !m->p.adaptive) return nullptr;
+  const bool l = tab_in_lds(m);
+  if (m->nf == 2) return l ? (const void*)&k_adaptive<2, true> : (const void*)&k_adaptive<2, false>;
+  return l ? (const void*)&k_adaptive<3, true> : (const void*)&k_adaptive<3, false>;
+}
 
 static const void* advance_kernel(const nb_model* m) {
   if (m->batch) return (const void*)&k_batch2;
@@ -547,6 +564,12 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
                                                          advance_dyn_lds(m)));
     nbpm = std::min(nbpm, nb32);
   }
+  if (adaptive_kernel(m)) {
+    int nba = 0;
+    NB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nba, adaptive_kernel(m), kBlock,
+                                                         advance_dyn_lds(m)));
+    nbpm = std::min(nbpm, nba);
+  }
   if (nbpm < 1) return fail(NB_EHIP, "stepping kernel cannot be resident");
   int max_blocks = std::min(cus * nbpm, kMaxBlocks);
   if (m->p.max_blocks > 0) max_blocks = std::min(max_blocks, (int)m->p.max_blocks);
@@ -565,6 +588,7 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
   m->off_jhist = L.jhist;
   m->off_dtab = L.dtab;
   m->off_aout = L.aout;
+  m->off_X2 = L.X2;
   m->need = L.need;
   m->adj_bpt = 0;
   m->adj_blocks = 0;
@@ -771,6 +795,79 @@ extern "C" int nb_step(nb_model* m, int64_t n) {
 extern "C" int nb_run(nb_model* m) {
   if (!m) return fail(NB_EINVAL, "model is NULL");
   return nb_step(m, m->p.n_steps - m->step);
+}
+
+// ----------------------------------------------------------------- adaptive steps
+extern "C" int nb_run_adaptive(nb_model* m, double tol, double h_max_km, int64_t max_attempts,
+                               nb_adaptive_stats* stats) {
+  if (!m) return fail(NB_EINVAL, "model is NULL");
+  if (!m->ws) return fail(NB_EUNBOUND, "no workspace bound");
+  if (!adaptive_kernel(m)) return fail(NB_EINVAL, "model was not created with adaptive = 1");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(NB_EINVAL, "tol must be > 0");
+  if (max_attempts < 1) return fail(NB_EINVAL, "max_attempts must be >= 1");
+  if (!std::isfinite(h_max_km)) return fail(NB_EINVAL, "h_max_km must be finite");
+  if (m->step != 0) return fail(NB_EINVAL, "adaptive runs start at step 0 (call nb_reset)");
+  if (capturing(m->stream)) return fail(NB_EINVAL, "adaptive runs cannot be captured");
+  drop_graph(m);
+  const Sub& s = m->subs[0];
+  const double span = m->p.r_end_km - m->p.r_start_km;
+  long long init[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double r0 = m->p.r_start_km, h0 = s.h;
+  std::memcpy(&init[kCtlR], &r0, sizeof(double));
+  std::memcpy(&init[kCtlH], &h0, sizeof(double));
+  long long* ctl = (long long*)(m->ws + m->off_ctl);
+  NB_HIP(hipMemcpyAsync(ctl, init, sizeof(init), hipMemcpyHostToDevice, m->stream));
+  int rc = zero_sync(m, 1);
+  if (rc) return rc;
+  StepArgs a{};
+  a.X = m->ws + m->off_X;
+  a.X2 = m->ws + m->off_X2;
+  a.tab = (const double*)(m->ws + m->off_tab);
+  a.sync = (unsigned int*)(m->ws + m->off_sync);
+  a.step_ctl = ctl;
+  a.plane = m->plane;
+  a.NE = (int)s.NE;
+  a.NU = (int)s.NU;
+  a.nsteps = m->p.n_steps;
+  a.total_steps = m->p.n_steps;
+  a.rs = m->p.r_start_km;
+  a.h = s.h;
+  a.R = m->p.r_nu_km;
+  a.lam0 = s.lam0;
+  a.ne_power = m->p.ne_power;
+  a.renorm = m->p.renorm;
+  a.s1 = s.s1;
+  a.s0 = s.s0;
+  a.p2e1 = s.p2e1;
+  a.p2e0 = s.p2e0;
+  a.timeout_ticks = m->ticks_per_s * 20ull;
+  a.tol2 = tol * tol;
+  a.hmax = (h_max_km > 0.0) ? h_max_km : span;
+  a.hmin = std::ldexp(s.h, -40);
+  a.r_end = m->p.r_end_km;
+  a.max_attempts = max_attempts;
+  void* args[] = {&a};
+  const hipError_t e = hipLaunchCooperativeKernel(adaptive_kernel(m), dim3(m->nblocks), dim3(kBlock), args,
+                                                  (unsigned)advance_dyn_lds(m), m->stream);
+  if (e != hipSuccess) return fail(NB_EHIP, "adaptive launch: %s", hipGetErrorString(e));
+  long long out[8];
+  NB_HIP(hipMemcpyAsync(out, ctl, sizeof(out), hipMemcpyDeviceToHost, m->stream));
+  rc = check_status(m);
+  if (rc) return rc;
+  if (stats) {
+    stats->accepted = out[kCtlAcc];
+    stats->rejected = out[kCtlRej];
+    stats->attempts = out[kCtlAtt];
+    std::memcpy(&stats->h_last_km, &out[kCtlH], sizeof(double));
+  }
+  if (out[kCtlFail]) {
+    // the partial state has no place on the fixed grid: back to the initial state
+    rc = nb_reset(m);
+    if (rc) return rc;
+    return fail(NB_ESTEP, "adaptive step control failed after %lld attempts (%lld accepted)",
+                (long long)out[kCtlAtt], (long long)out[kCtlAcc]);
+  }
+  return NB_OK;
 }
 
 // ----------------------------------------------------------------- HIP graphs

@@ -20,8 +20,8 @@ constexpr int kSyncArrive = kSyncFlag + kFlagCopies * kLineWords;  // [kMaxBlock
 // Tagged 64-bit words of the single-model stepping kernels' moment reduction (every word
 // carries the barrier epoch it belongs to, so no separate arrival or release word is
 // needed): kFlagCopies copies of the reduced moments (block b reads copy b % kFlagCopies),
-// two lines each; one two-line slot of block partials per block.
-constexpr int kTagLines = 2;
+// kTagLines lines each; one slot of kTagLines lines of block partials per block.
+constexpr int kTagLines = 3;
 constexpr int kSyncJTag = kSyncArrive + kMaxBlocks * kLineWords;
 constexpr int kSyncPart = kSyncJTag + kFlagCopies * kTagLines * kLineWords;
 constexpr int kSyncWords = kSyncPart + kMaxBlocks * kTagLines * kLineWords;
@@ -46,7 +46,14 @@ struct StepArgs {
   double* Jhist;           // nullptr, or [step][4][2*NC]: every stage's moments (adjoint tape)
   int use_window;          // 0: advance min(nsteps, total - step) steps; 1: the window below
   long long win_lo, win_hi;// windowed launch: only steps in [win_lo, win_hi), up to step_ctl[1]
+  // adaptive step control (k_adaptive): second state buffer, tolerance^2, step limits, end
+  void* X2;
+  double tol2, hmax, hmin, r_end;
+  long long max_attempts;
 };
+// step_ctl words of an adaptive run: [2] r, [3] h (double bits), [4] accepted, [5] rejected,
+// [6] attempts, [7] 1 if the step control failed
+constexpr int kCtlR = 2, kCtlH = 3, kCtlAcc = 4, kCtlRej = 5, kCtlAtt = 6, kCtlFail = 7;
 
 // One two-flavour model of a batch.
 struct BatchModel {

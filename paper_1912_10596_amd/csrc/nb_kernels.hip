@@ -18,6 +18,7 @@
 #include "nb_device32.h"
 #include "nb_internal.h"
 #include "nb_stage.h"
+#include <type_traits>
 
 namespace nb {
 
@@ -55,13 +56,18 @@ __device__ __forceinline__ long long chunk_value(unsigned long long field, int k
 }
 
 // blk: the block's partial (threads tid < NV hold component tid); own: in block 0, thread
-// tid < 2 NV holds chunk tid % 2 of its component tid / 2.
-template <int NV>
-__device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, long long own, double* sJ,
-                            long long* sacc) {
-  constexpr int W = 2 * NV;          // words per partial and per moment copy
+// tid < W holds chunk tid % 2 of its component tid / 2 (and, with MAXE, thread 2 NV the
+// block's error field).  MAXE adds one more word to every partial, efield (thread NV): the
+// block's largest error estimate as the top 48 bits of its binary form (a non-negative
+// double, so the integer order of the fields is the order of the values); block 0 takes
+// the largest field and publishes the value in two more words, which lands in *sE.
+template <int NV, bool MAXE>
+__device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, long long own,
+                            unsigned long long efield, double* sJ, long long* sacc, double* sE) {
+  constexpr int W = 2 * NV + (MAXE ? 1 : 0);   // words per partial
+  constexpr int JW = 2 * NV + (MAXE ? 2 : 0);  // words per moment copy
   constexpr int G = kBlock / W;      // block-0 thread groups, one chunk position per thread
-  static_assert(W <= kTagWords64, "tagged slot too small");
+  static_assert(JW <= kTagWords64, "tagged slot too small");
   const int tid = threadIdx.x;
   const unsigned want = epoch + 1u;
   unsigned long long* part = reinterpret_cast<unsigned long long*>(a.sync + kSyncPart);
@@ -74,8 +80,11 @@ __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, long lo
       __hip_atomic_store(q + 1, (tag16 << 48) | chunk_field(blk, 1), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
     }
+    if (MAXE && tid == NV)
+      __hip_atomic_store(part + (size_t)blockIdx.x * kTagWords64 + 2 * NV, (tag16 << 48) | efield,
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
-    if (tid < W) {
+    if (tid < JW) {
       const unsigned long long* w =
           jw + (size_t)(blockIdx.x % kFlagCopies) * kTagWords64 + tid;
       const unsigned long long t0 = wall_clock64();
@@ -89,10 +98,14 @@ __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, long lo
         }
         __builtin_amdgcn_s_sleep(1);
       }
-      // lane 2v holds the low half of moment v, lane 2v + 1 the high half
+      // lane 2v holds the low half of moment v, lane 2v + 1 the high half (lanes 2 NV and
+      // 2 NV + 1: the error estimate)
       const unsigned hi = __shfl_down((unsigned)x, 1, 64);
-      if (ok && (tid & 1) == 0)
-        sJ[tid >> 1] = as_double(((unsigned long long)hi << 32) | (x & 0xffffffffull));
+      if (ok && (tid & 1) == 0) {
+        const double val = as_double(((unsigned long long)hi << 32) | (x & 0xffffffffull));
+        if (tid < 2 * NV) sJ[tid >> 1] = val;
+        else *sE = val;
+      }
     }
     return !__syncthreads_or(!ok);
   }
@@ -117,7 +130,8 @@ __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, long lo
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           if ((pend & (1u << i)) && (w[i] >> 48) == tag16) {
-            acc += chunk_value(w[i] & kMask48, pos & 1);
+            if (MAXE && pos == 2 * NV) acc = max(acc, (long long)(w[i] & kMask48));
+            else acc += chunk_value(w[i] & kMask48, pos & 1);
             pend &= ~(1u << i);
           }
         }
@@ -151,20 +165,44 @@ __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, long lo
       __hip_atomic_store(q, tg | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(q + 1, tg | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+  } else if (MAXE && tid == NV) {
+    long long f = 0;
+    for (int gg = 0; gg < G; ++gg) f = max(f, sacc[gg * W + 2 * NV]);
+    const unsigned long long bits = (unsigned long long)f << 16;
+    *sE = as_double(bits);
+    const unsigned long long tg = (unsigned long long)want << 32;
+#pragma unroll
+    for (int c = 0; c < kFlagCopies; ++c) {
+      unsigned long long* q = jw + (size_t)c * kTagWords64 + 2 * NV;
+      __hip_atomic_store(q, tg | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(q + 1, tg | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
   __syncthreads();
   return true;
 }
 
 // Fold the waves' per-lane totals (lane v holds value v) and run the grid reduction.
-template <int NV>
+// MAXE: also the largest of the lanes' error estimates emax (then swm holds one double per
+// wave and the grid's largest estimate lands in *sE).
+template <int NV, bool MAXE = false>
 __device__ bool finish_stage(const StepArgs& a, unsigned epoch, I128 T, I128 (*sw)[NV],
-                             long long* sacc, double* sJ) {
+                             long long* sacc, double* sJ, double emax = 0.0, double* swm = nullptr,
+                             double* sE = nullptr) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane < NV) sw[wid][lane] = T;
+  if constexpr (MAXE) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(emax, off, 64);
+      emax = (o > emax) ? o : emax;
+    }
+    if (lane == 0) swm[wid] = emax;
+  }
   __syncthreads();
   I128 blk = i128_zero();
   long long own = 0;
+  unsigned long long efield = 0;
   if (threadIdx.x < NV)
     for (int w = 0; w < kBlock / 64; ++w) blk = i128_add(blk, sw[w][threadIdx.x]);
   if (blockIdx.x == 0 && threadIdx.x < 2 * NV) {
@@ -172,7 +210,29 @@ __device__ bool finish_stage(const StepArgs& a, unsigned epoch, I128 T, I128 (*s
     for (int w = 0; w < kBlock / 64; ++w) c = i128_add(c, sw[w][threadIdx.x >> 1]);
     own = chunk_value(chunk_field(c, threadIdx.x & 1), threadIdx.x & 1);
   }
-  return grid_reduce<NV>(a, epoch, blk, own, sJ, sacc);
+  if constexpr (MAXE) {
+    if (threadIdx.x == NV || (blockIdx.x == 0 && threadIdx.x == 2 * NV)) {
+      double m = 0.0;
+      for (int w = 0; w < kBlock / 64; ++w) m = (swm[w] > m) ? swm[w] : m;
+      efield = as_bits(m) >> 16;
+      if (threadIdx.x == 2 * NV) own = (long long)efield;
+    }
+  }
+  return grid_reduce<NV, MAXE>(a, epoch, blk, own, efield, sJ, sacc, sE);
+}
+
+// Radii and length of one step: stage radii r0, rm = r0 + h/2 and r1.  On the fixed grid
+// r1 = r_start + (n + 1) h (not r0 + h), as in the serial definition.
+struct StepGeo {
+  double r0, rm, r1, h;
+};
+__device__ __forceinline__ StepGeo geo_fixed(const StepArgs& a, long long n) {
+  StepGeo g;
+  g.r0 = a.rs + (double)n * a.h;
+  g.rm = g.r0 + 0.5 * a.h;
+  g.r1 = a.rs + (double)(n + 1) * a.h;
+  g.h = a.h;
+  return g;
 }
 
 // ------------------------------------------------------------- row helpers
@@ -230,12 +290,14 @@ __device__ __forceinline__ void close_row(const Scales& sc, int lane, const I128
 // J[i]: stage moments J^(i+1) (J0 | J1, 6 doubles).  A lane adds the fixed-point
 // contributions of up to 32 of its beams in 64-bit integers (each below 2^58) before they
 // are folded into exact 128-bit wave sums.
-template <int KIND>
-__device__ __forceinline__ void row2(double* X, long long plane, long long rb, int NE, int s,
-                                     double u, double h, const double* tab, const Radial& g0,
+// ADAPT (final update only): the new state goes to Xo instead of X, and emax keeps the
+// largest embedded error estimate |Theta - f2|^2 of the lane's beams.
+template <int KIND, bool ADAPT = false>
+__device__ __forceinline__ void row2(const double* X, double* Xo, long long plane, long long rb, int NE,
+                                     int s, double u, double h, const double* tab, const Radial& g0,
                                      const Radial& gm, const Radial& g1, const double* const* J,
                                      const Scales& sc, int renorm, int lane, long long* fl, I128& T,
-                                     int& err) {
+                                     int& err, double& emax) {
   const RowGeo rg = row_geo(u, h, g0, gm, g1);
   const double icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
   double n1[3], n2[3], n3[3], n4[3];
@@ -283,6 +345,11 @@ __device__ __forceinline__ void row2(double* X, long long plane, long long rb, i
           const double t0 = (((f1[0] + 2.0 * f2[0]) + 2.0 * f3[0]) + f4[0]) * (1.0 / 6.0) - cr0 * (1.0 / 12.0);
           const double t1 = (((f1[1] + 2.0 * f2[1]) + 2.0 * f3[1]) + f4[1]) * (1.0 / 6.0) - cr1 * (1.0 / 12.0);
           const double t2 = (((f1[2] + 2.0 * f2[2]) + 2.0 * f3[2]) + f4[2]) * (1.0 / 6.0) - cr2 * (1.0 / 12.0);
+          if (ADAPT) {
+            const double d0 = t0 - f2[0], d1 = t1 - f2[1], d2 = t2 - f2[2];
+            const double e = (d0 * d0 + d1 * d1) + d2 * d2;
+            emax = (e > emax) ? e : emax;
+          }
           rotate2(t0, t1, t2, P0, P1, P2);
           if (renorm) {
             const double nrm2 = (P0 * P0 + P1 * P1) + P2 * P2;
@@ -291,9 +358,9 @@ __device__ __forceinline__ void row2(double* X, long long plane, long long rb, i
             P1 = P1 * inv;
             P2 = P2 * inv;
           }
-          X[rb + k] = P0;
-          X[rb + k + plane] = P1;
-          X[rb + k + 2 * plane] = P2;
+          Xo[rb + k] = P0;
+          Xo[rb + k + plane] = P1;
+          Xo[rb + k + 2 * plane] = P2;
         }
       }
       // rho~: rho for neutrinos, -rho^* (Bloch (-x, y, -z)) for antineutrinos
@@ -308,22 +375,20 @@ __device__ __forceinline__ void row2(double* X, long long plane, long long rb, i
   close_row<3>(sc, lane, mine, icmom, T, err);
 }
 
-template <int KIND>
-__device__ __forceinline__ void stage2(const StepArgs& a, long long n, const double (*sJ)[6],
-                                       const double* tab, long long gw, long long nw, int lane,
-                                       long long* fl, I128& T, int& err) {
-  const double r0 = a.rs + (double)n * a.h;
-  const double rm = r0 + 0.5 * a.h;
-  const double r1 = a.rs + (double)(n + 1) * a.h;
-  const Radial g0 = radial_at(a, r0), gm = radial_at(a, rm), g1 = radial_at(a, r1);
+template <int KIND, bool ADAPT = false>
+__device__ __forceinline__ void stage2(const StepArgs& a, const StepGeo& G, const double* X, double* Xo,
+                                       const double (*sJ)[6], const double* tab, long long gw,
+                                       long long nw, int lane, long long* fl, I128& T, int& err,
+                                       double& emax) {
+  const Radial g0 = radial_at(a, G.r0), gm = radial_at(a, G.rm), g1 = radial_at(a, G.r1);
   const Scales sc{a.s1, a.s0, a.p2e1, a.p2e0};
   const double* J[4] = {sJ[0], sJ[1], sJ[2], sJ[3]};
   const long long nrow = 2LL * a.NU;
   for (long long row = gw; row < nrow; row += nw) {
     const int s = (int)(row / a.NU);
     const int j = (int)(row - (long long)s * a.NU);
-    row2<KIND>((double*)a.X, a.plane, row * a.NE, a.NE, s, u_of(j, a.NU), a.h, tab, g0, gm, g1,
-               J, sc, a.renorm, lane, fl, T, err);
+    row2<KIND, ADAPT>(X, Xo, a.plane, row * a.NE, a.NE, s, u_of(j, a.NU), G.h, tab, g0, gm, g1, J, sc,
+                      a.renorm, lane, fl, T, err, emax);
   }
 }
 
@@ -354,16 +419,18 @@ __device__ __forceinline__ Herm3 gen3(int s, const double* v, double lam, const 
 // Row-wise nn terms of the four stage slots live in LDS (one 32-double block per wave)
 // and are re-read per beam, so the compiler does not keep all of them in registers.
 // One (species, emission bin) row of the three-flavour stage, FP64 arithmetic.
-template <typename ST, int KIND>
-__device__ __forceinline__ void row3(const StepArgs& a, long long row, const Radial& g0, const Radial& gm,
-                                     const Radial& g1, const double (*sJ)[16], const double* tab,
-                                     double* snn, int lane, long long* fl, I128& T, int& err) {
+// ADAPT (final update only): the new state goes to Xo instead of X, and emax keeps the
+// largest embedded error estimate |Theta - K2|^2 (traceless part, Frobenius norm).
+template <typename ST, int KIND, bool ADAPT = false>
+__device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, long long row, double h,
+                                     const Radial& g0, const Radial& gm, const Radial& g1,
+                                     const double (*sJ)[16], const double* tab, double* snn, int lane,
+                                     long long* fl, I128& T, int& err, double& emax) {
   const long long plane = a.plane;
   const int NE = a.NE;
-  ST* X = (ST*)a.X;
   const int s = (int)(row / a.NU);
   const int j = (int)(row - (long long)s * a.NU);
-  const RowGeo rg = row_geo(u_of(j, a.NU), a.h, g0, gm, g1);
+  const RowGeo rg = row_geo(u_of(j, a.NU), h, g0, gm, g1);
   const double icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
   {
     double t[8];
@@ -427,7 +494,8 @@ __device__ __forceinline__ void row3(const StepArgs& a, long long row, const Rad
         } else {
           // Theta = (((K1 + 2 K2) + 2 K3) + K4)/6 + i[K1,K4]/12, accumulated in that order
           Herm3 acc3 = K1;
-          haxpy(acc3, 2.0, gen3(s, v, gm.lam, snn + 8, rg.hcm));
+          const Herm3 K2 = gen3(s, v, gm.lam, snn + 8, rg.hcm);
+          haxpy(acc3, 2.0, K2);
           haxpy(acc3, 2.0, gen3(s, v, gm.lam, snn + 16, rg.hcm));
           const Herm3 K4 = gen3(s, v, g1.lam, snn + 24, rg.hc1);
           hadd(acc3, K4);
@@ -442,6 +510,17 @@ __device__ __forceinline__ void row3(const StepArgs& a, long long row, const Rad
                       acc3.o02.im * (1.0 / 6.0) + C.o02.im * (1.0 / 12.0));
           Th.o12 = mk(acc3.o12.re * (1.0 / 6.0) + C.o12.re * (1.0 / 12.0),
                       acc3.o12.im * (1.0 / 6.0) + C.o12.im * (1.0 / 12.0));
+          if (ADAPT) {
+            const double dd0 = Th.d0 - K2.d0, dd1 = Th.d1 - K2.d1, dd2 = Th.d2 - K2.d2;
+            const double tr = ((dd0 + dd1) + dd2) * (1.0 / 3.0);
+            const double a0 = dd0 - tr, a1 = dd1 - tr, a2 = dd2 - tr;
+            const double x0 = Th.o01.re - K2.o01.re, y0 = Th.o01.im - K2.o01.im;
+            const double x1 = Th.o02.re - K2.o02.re, y1 = Th.o02.im - K2.o02.im;
+            const double x2 = Th.o12.re - K2.o12.re, y2 = Th.o12.im - K2.o12.im;
+            const double o0 = x0 * x0 + y0 * y0, o1 = x1 * x1 + y1 * y1, o2 = x2 * x2 + y2 * y2;
+            const double e = ((a0 * a0 + a1 * a1) + a2 * a2) + 2.0 * ((o0 + o1) + o2);
+            emax = (e > emax) ? e : emax;
+          }
           exp3_apply(Th, ps);
           if (a.renorm) {
             const double nrm2 = (norm2(ps[0]) + norm2(ps[1])) + norm2(ps[2]);
@@ -453,8 +532,8 @@ __device__ __forceinline__ void row3(const StepArgs& a, long long row, const Rad
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             const ST re = (ST)ps[c].re, im = (ST)ps[c].im;
-            X[rb + k + (2 * c) * plane] = re;
-            X[rb + k + (2 * c + 1) * plane] = im;
+            Xo[rb + k + (2 * c) * plane] = re;
+            Xo[rb + k + (2 * c + 1) * plane] = im;
             ps[c] = mk((double)re, (double)im);
           }
         }
@@ -476,17 +555,15 @@ __device__ __forceinline__ void row3(const StepArgs& a, long long row, const Rad
   close_row<8>(Scales{a.s1, a.s0, a.p2e1, a.p2e0}, lane, mine, icmom, T, err);
 }
 
-template <typename ST, int KIND>
-__device__ __forceinline__ void stage3(const StepArgs& a, long long n, const double (*sJ)[16],
-                                       const double* tab, double* snn, long long gw,
-                                       long long nw, int lane, long long* fl, I128& T, int& err) {
-  const double r0 = a.rs + (double)n * a.h;
-  const double rm = r0 + 0.5 * a.h;
-  const double r1 = a.rs + (double)(n + 1) * a.h;
-  const Radial g0 = radial_at(a, r0), gm = radial_at(a, rm), g1 = radial_at(a, r1);
+template <typename ST, int KIND, bool ADAPT = false>
+__device__ __forceinline__ void stage3(const StepArgs& a, const StepGeo& G, const ST* X, ST* Xo,
+                                       const double (*sJ)[16], const double* tab, double* snn,
+                                       long long gw, long long nw, int lane, long long* fl, I128& T,
+                                       int& err, double& emax) {
+  const Radial g0 = radial_at(a, G.r0), gm = radial_at(a, G.rm), g1 = radial_at(a, G.r1);
   const long long nrow = 2LL * a.NU;
   for (long long row = gw; row < nrow; row += nw)
-    row3<ST, KIND>(a, row, g0, gm, g1, sJ, tab, snn, lane, fl, T, err);
+    row3<ST, KIND, ADAPT>(a, X, Xo, row, G.h, g0, gm, g1, sJ, tab, snn, lane, fl, T, err, emax);
 }
 
 // ------------------------------------------------------- three flavours, mixed precision
@@ -674,18 +751,15 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
 // step (a bound computed from the model's parameters); nearer the neutrinosphere FP32
 // cannot hold the per-step phase and the FP64-arithmetic launch on the FP32 state is used.
 template <int KIND>
-__device__ __forceinline__ void stage3m(const StepArgs& a, long long n, const double (*sJ)[16],
+__device__ __forceinline__ void stage3m(const StepArgs& a, const StepGeo& G, const double (*sJ)[16],
                                         const double* tab, double* snn, long long gw, long long nw,
                                         int lane, long long* fl, I128& T, int& err) {
-  const double r0 = a.rs + (double)n * a.h;
-  const double rm = r0 + 0.5 * a.h;
-  const double r1 = a.rs + (double)(n + 1) * a.h;
-  const Radial g0 = radial_at(a, r0), gm = radial_at(a, rm), g1 = radial_at(a, r1);
+  const Radial g0 = radial_at(a, G.r0), gm = radial_at(a, G.rm), g1 = radial_at(a, G.r1);
   const long long nrow = 2LL * a.NU;
   for (long long row = gw; row < nrow; row += nw) {
     const int s = (int)(row / a.NU);
     const int j = (int)(row - (long long)s * a.NU);
-    const RowGeo rg = row_geo(u_of(j, a.NU), a.h, g0, gm, g1);
+    const RowGeo rg = row_geo(u_of(j, a.NU), G.h, g0, gm, g1);
     row3m<KIND>(a, row, g0, gm, g1, rg, sJ, tab, snn, (float*)(snn + 32), lane, fl, T, err);
   }
 }
@@ -727,10 +801,11 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   unsigned epoch = 0;
   int err = 0;
   bool ok = true;
+  double enone = 0.0;   // error estimate (adaptive runs only)
   I128 T = i128_zero();
-  if constexpr (NF == 2) stage2<0>(a, step0, sJ, tab, gw, nw, lane, fl, T, err);
-  else if constexpr (F32) stage3m<0>(a, step0, sJ, tab, snn, gw, nw, lane, fl, T, err);
-    else stage3<ST, 0>(a, step0, sJ, tab, snn, gw, nw, lane, fl, T, err);
+  if constexpr (NF == 2) stage2<0>(a, geo_fixed(a, step0), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
+  else if constexpr (F32) stage3m<0>(a, geo_fixed(a, step0), sJ, tab, snn, gw, nw, lane, fl, T, err);
+    else stage3<ST, 0>(a, geo_fixed(a, step0), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone);
   ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[0]);
   // the adjoint's forward pass records every stage's moments: [step][slot][NV]
   auto record = [&](long long step, int slot) {
@@ -740,27 +815,27 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   record(step0, 0);
   for (long long n = step0; ok && n < step0 + nsteps; ++n) {
     T = i128_zero();
-    if constexpr (NF == 2) stage2<1>(a, n, sJ, tab, gw, nw, lane, fl, T, err);
-    else if constexpr (F32) stage3m<1>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
-    else stage3<ST, 1>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
+    if constexpr (NF == 2) stage2<1>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
+    else if constexpr (F32) stage3m<1>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err);
+    else stage3<ST, 1>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone);
     if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[1]))) break;
     record(n, 1);
     T = i128_zero();
-    if constexpr (NF == 2) stage2<2>(a, n, sJ, tab, gw, nw, lane, fl, T, err);
-    else if constexpr (F32) stage3m<2>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
-    else stage3<ST, 2>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
+    if constexpr (NF == 2) stage2<2>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
+    else if constexpr (F32) stage3m<2>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err);
+    else stage3<ST, 2>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone);
     if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[2]))) break;
     record(n, 2);
     T = i128_zero();
-    if constexpr (NF == 2) stage2<3>(a, n, sJ, tab, gw, nw, lane, fl, T, err);
-    else if constexpr (F32) stage3m<3>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
-    else stage3<ST, 3>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
+    if constexpr (NF == 2) stage2<3>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
+    else if constexpr (F32) stage3m<3>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err);
+    else stage3<ST, 3>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone);
     if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[3]))) break;
     record(n, 3);
     T = i128_zero();
-    if constexpr (NF == 2) stage2<4>(a, n, sJ, tab, gw, nw, lane, fl, T, err);
-    else if constexpr (F32) stage3m<4>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
-    else stage3<ST, 4>(a, n, sJ, tab, snn, gw, nw, lane, fl, T, err);
+    if constexpr (NF == 2) stage2<4>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
+    else if constexpr (F32) stage3m<4>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err);
+    else stage3<ST, 4>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone);
     ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[0]);
     record(n + 1, 0);
   }
@@ -777,6 +852,131 @@ template __global__ void k_advance<3, float, true, false>(StepArgs);
 template __global__ void k_advance<3, float, false, false>(StepArgs);
 template __global__ void k_advance<3, float, true, true>(StepArgs);
 template __global__ void k_advance<3, float, false, true>(StepArgs);
+
+// --------------------------------------------------------------- adaptive step control
+// One persistent launch integrates from r (step_ctl[kCtlR]) with the step length
+// step_ctl[kCtlH] to r_end.  Each attempt is a full RKMK4 step from the current state X
+// into the other buffer Xn; the final update's barrier also reduces the largest error
+// estimate E, from which every block takes the same decision: accept (swap buffers,
+// advance r, double h if E <= tol^2/64 and 2h <= h_max) or reject (keep X and the saved
+// moments of X, halve h).  The last step is shortened to end at r_end.  At the end each
+// wavefront copies its rows back to X if the result sits in the second buffer.
+template <int NF, bool TLDS>
+__global__ void __launch_bounds__(kBlock) k_adaptive(StepArgs a) {
+  constexpr int NC = (NF == 2) ? 3 : 8;
+  constexpr int NV = 2 * NC;
+  __shared__ double sJ[4][NV];
+  __shared__ double sJsave[NV];
+  __shared__ double sE[1];
+  __shared__ double swm[kBlock / 64];
+  __shared__ I128 sw[kBlock / 64][NV];
+  __shared__ long long sacc[kBlock];
+  __shared__ double snn_all[kBlock / 64][32];
+  __shared__ long long sfold[kBlock / 64][(NC + 2) * 64];
+  extern __shared__ double dyn_tab[];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const long long gw = (long long)blockIdx.x * (kBlock / 64) + wid;
+  const long long nw = (long long)gridDim.x * (kBlock / 64);
+  const double* tab = a.tab;
+  if constexpr (TLDS) {
+    const int ntab = ((NF == 2) ? 4 : 8) * a.NE;
+    for (int i = threadIdx.x; i < ntab; i += kBlock) dyn_tab[i] = a.tab[i];
+    __syncthreads();
+    tab = dyn_tab;
+  }
+  double* snn = snn_all[wid];
+  long long* fl = sfold[wid];
+  long long* ctl = a.step_ctl;
+  double r = as_double((unsigned long long)ctl[kCtlR]);
+  double h = as_double((unsigned long long)ctl[kCtlH]);
+  double* X = (double*)a.X;
+  double* Xn = (double*)a.X2;
+  unsigned epoch = 0;
+  int err = 0, fail = 0;
+  long long nacc = 0, nrej = 0, natt = 0;
+  double emax = 0.0;
+  I128 T = i128_zero();
+  auto stage = [&](auto kind, const StepGeo& G) {
+    constexpr int K = decltype(kind)::value;
+    if constexpr (NF == 2) stage2<K, K == 4>(a, G, X, Xn, sJ, tab, gw, nw, lane, fl, T, err, emax);
+    else stage3<double, K, K == 4>(a, G, X, Xn, sJ, tab, snn, gw, nw, lane, fl, T, err, emax);
+  };
+  using K0 = std::integral_constant<int, 0>;
+  using K1 = std::integral_constant<int, 1>;
+  using K2 = std::integral_constant<int, 2>;
+  using K3 = std::integral_constant<int, 3>;
+  using K4 = std::integral_constant<int, 4>;
+  stage(K0{}, StepGeo{r, r, r, 0.0});
+  bool ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[0]);
+  if (threadIdx.x < NV) sJsave[threadIdx.x] = sJ[0][threadIdx.x];
+  while (ok) {
+    const bool last = (r + h >= a.r_end);
+    const double hs = last ? a.r_end - r : h;
+    const StepGeo G{r, r + 0.5 * hs, last ? a.r_end : r + hs, hs};
+    T = i128_zero();
+    stage(K1{}, G);
+    if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[1]))) break;
+    T = i128_zero();
+    stage(K2{}, G);
+    if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[2]))) break;
+    T = i128_zero();
+    stage(K3{}, G);
+    if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[3]))) break;
+    T = i128_zero();
+    emax = 0.0;
+    stage(K4{}, G);
+    if (!(ok = finish_stage<NV, true>(a, epoch++, T, sw, sacc, sJ[0], emax, swm, sE))) break;
+    ++natt;
+    const double E = *sE;
+    if (E <= a.tol2) {
+      ++nacc;
+      r = G.r1;
+      double* t = X;
+      X = Xn;
+      Xn = t;
+      if (E <= a.tol2 * (1.0 / 64.0) && 2.0 * h <= a.hmax) h = 2.0 * h;
+      if (threadIdx.x < NV) sJsave[threadIdx.x] = sJ[0][threadIdx.x];
+      if (last) break;
+    } else {
+      ++nrej;
+      h = 0.5 * h;
+      if (threadIdx.x < NV) sJ[0][threadIdx.x] = sJsave[threadIdx.x];
+      if (h < a.hmin) {
+        fail = 1;
+        break;
+      }
+    }
+    if (natt >= a.max_attempts) {
+      fail = 1;
+      break;
+    }
+    __syncthreads();
+  }
+  if (ok && X != (double*)a.X) {
+    // the accepted state sits in the second buffer: copy this wavefront's rows back
+    constexpr int nsc = (NF == 2) ? 3 : 6;
+    double* D = (double*)a.X;
+    for (long long row = gw; row < 2LL * a.NU; row += nw)
+      for (int k = lane; k < a.NE; k += 64)
+#pragma unroll
+        for (int c = 0; c < nsc; ++c) D[row * a.NE + k + c * a.plane] = X[row * a.NE + k + c * a.plane];
+  }
+  if (err) __hip_atomic_fetch_or(a.sync + kSyncStatus, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (ok && blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl[kCtlR] = (long long)as_bits(r);
+    ctl[kCtlH] = (long long)as_bits(h);
+    ctl[kCtlAcc] = nacc;
+    ctl[kCtlRej] = nrej;
+    ctl[kCtlAtt] = natt;
+    ctl[kCtlFail] = fail;
+    if (!fail) ctl[0] = a.total_steps;
+  }
+}
+
+template __global__ void k_adaptive<2, true>(StepArgs);
+template __global__ void k_adaptive<2, false>(StepArgs);
+template __global__ void k_adaptive<3, true>(StepArgs);
+template __global__ void k_adaptive<3, false>(StepArgs);
 
 // --------------------------------------------------------------- batched models
 // Many independent two-flavour models in one persistent launch (shared step grid).
@@ -874,8 +1074,9 @@ __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, lon
     const long long lr = row - mrow0;
     const int s = (int)(lr / mNU);
     const int j = (int)(lr - (long long)s * mNU);
-    row2<KIND>(a.X, a.plane, mbeam0 + lr * mNE, mNE, s, u_of(j, mNU), a.h, a.tab + mtab0,
-               g0, gm, g1, J, sc, a.renorm, lane, fl, T, err);
+    double enone = 0.0;
+    row2<KIND>(a.X, a.X, a.plane, mbeam0 + lr * mNE, mNE, s, u_of(j, mNU), a.h, a.tab + mtab0,
+               g0, gm, g1, J, sc, a.renorm, lane, fl, T, err, enone);
   }
   if (m >= 0 && lane < 6) acc_add(acc_slot(a, epoch, m) + lane * kAccLimbs, T);
   // clear the set the next epoch will collect into
