@@ -201,6 +201,48 @@ def mixed_precision(nb, workloads, literal_steps: int):
     return out
 
 
+def adaptive_timing(nb, workloads):
+    """Adaptive step-size control (nb_run_adaptive).  (a) The 800k-beam 3-flavour shape over
+    a resolved span (600 -> 700 km): attempts, time per attempt against the fixed-step
+    kernel on the same span, and max |dP_ee| against a fine fixed-step run (8000 steps).
+    (b) A prefix of the literal 1024-beam two-flavour run (10 -> 10.1 km), where the
+    controller shrinks the step to a few microns of km."""
+    import numpy as np
+    import torch
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    d = dict(workloads.three_flavor_800k(), r_start_km=600.0, r_end_km=700.0, n_steps=500)
+    m = nb.Model(dict(d, n_steps=8000))
+    _, t_fix = timed(m.run)
+    p_ref = m.pee().cpu().numpy()
+    del m
+    torch.cuda.empty_cache()
+    out = {"fixed_8000_steps": dict(s=round(t_fix, 4), ms_per_step=round(t_fix / 8000 * 1e3, 4))}
+    for tol in (1e-6, 1e-7):
+        m = nb.Model(d, adaptive=True)
+        st, t = timed(lambda: m.run_adaptive(tol))
+        out[f"tol_{tol:g}"] = dict(
+            st, s=round(t, 4), ms_per_attempt=round(t / st["attempts"] * 1e3, 4),
+            max_abs_dpee_vs_fixed_8000=float(np.abs(m.pee().cpu().numpy() - p_ref).max()))
+        del m
+        torch.cuda.empty_cache()
+    out["workload"] = ("3-flavour, 400 E x 1000 u x 2 = 800000 beams, 600 -> 700 km, first step "
+                       "0.2 km")
+    lit = dict(workloads.two_flavor_small(), r_end_km=10.1, n_steps=20)
+    m = nb.Model(lit, adaptive=True)
+    st, t = timed(lambda: m.run_adaptive(1e-3, max_attempts=10**7))
+    out["literal_1024_prefix"] = dict(
+        st, s=round(t, 3), us_per_attempt=round(t / st["attempts"] * 1e6, 2),
+        workload="2-flavour, 32 E x 16 u x 2 = 1024 beams, 10 -> 10.1 km, tol 1e-3")
+    return out
+
+
 def cpu_baseline(d: dict, seconds: float):
     """The oracle as it stands, on this host's cores, over a bounded prefix of the same
     workload (whole steps of every beam until `seconds` of CPU time have passed)."""
@@ -298,6 +340,9 @@ def main():
         out["batch"] = batch_timing(nb, workloads, 40)
         log("mixed precision (6M beams) ...")
         out["mixed_precision"] = mixed_precision(nb, workloads, args.mixed_literal_steps)
+        torch.cuda.empty_cache()
+        log("adaptive step control (800k beams, 1024-beam literal prefix) ...")
+        out["adaptive"] = adaptive_timing(nb, workloads)
     if args.copy_probe:
         n = 1 << 27                      # 2^27 doubles = 1 GiB each way
         src = torch.ones(n, dtype=torch.float64, device="cuda")

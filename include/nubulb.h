@@ -157,7 +157,7 @@ int nb_adjoint(nb_model *m, const double *dev_dl_dpee, double *grad_out, int32_t
  * generator Theta and the generator F_2 of the exponential midpoint rule built from the
  * same stages (3 flavours: traceless part, Frobenius norm), with the low 16 bits of its
  * binary form cleared.  A step of length h is accepted if E <= tol^2; then h doubles (at
- * most to h_max_km; <= 0: no cap) if E <= tol^2/64.  A rejected step is retried from the
+ * most to h_max_km; <= 0: no cap) if E <= tol^2/128.  A rejected step is retried from the
  * same state with h/2.  The last step ends exactly at r_end.  The first step length is
  * (r_end - r_start)/n_steps.  Every decision is taken by every block from the same reduced
  * E, so the run is deterministic and matches a serial implementation bit for bit.

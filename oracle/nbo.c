@@ -791,8 +791,9 @@ int nbo_step_error(nbo_model *m, double h, double *E) {
  * adaptive step size, Sec. 3.4; the controller below is this library's own, with
  * power-of-two step changes so that both implementations take identical decisions):
  *   a step of length h from r is accepted if its error estimate E <= tol^2; the state
- *   and r advance, and h doubles (up to h_max) if E <= tol^2 / 64, i.e. when the doubled
- *   step's estimate, which grows as h^6, is expected to pass as well;
+ *   and r advance, and h doubles (up to h_max) if E <= tol^2 / 128, i.e. when the doubled
+ *   step's estimate, which grows as h^6 (a factor 64), is expected to pass with a margin
+ *   of 2;
  *   a rejected step is retried from the same state with h / 2.
  * The last step is shortened to end exactly at r_end.  The first step length is the
  * model's (r_end - r_start) / n_steps; the run fails if h falls below 2^-40 of it or the
@@ -806,7 +807,7 @@ int nbo_run_adaptive(nbo_model *m, double tol, double h_max, int64_t max_attempt
   double r = m->p.r_start_km, h = m->h;
   const double hmin = ldexp(m->h, -40);
   const double hmax = (h_max > 0.0) ? h_max : (r_end - r);
-  const double tol2 = tol * tol, grow = tol2 * (1.0 / 64.0);
+  const double tol2 = tol * tol, grow = tol2 * (1.0 / 128.0);
   const size_t bytes = sizeof(double) * (size_t)m->nb * (size_t)m->nsc;
   double *Xn = (double *)malloc(bytes);
   int64_t acc = 0, rej = 0, att = 0;

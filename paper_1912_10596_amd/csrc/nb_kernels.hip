@@ -858,7 +858,7 @@ template __global__ void k_advance<3, float, false, true>(StepArgs);
 // step_ctl[kCtlH] to r_end.  Each attempt is a full RKMK4 step from the current state X
 // into the other buffer Xn; the final update's barrier also reduces the largest error
 // estimate E, from which every block takes the same decision: accept (swap buffers,
-// advance r, double h if E <= tol^2/64 and 2h <= h_max) or reject (keep X and the saved
+// advance r, double h if E <= tol^2/128 and 2h <= h_max) or reject (keep X and the saved
 // moments of X, halve h).  The last step is shortened to end at r_end.  At the end each
 // wavefront copies its rows back to X if the result sits in the second buffer.
 template <int NF, bool TLDS>
@@ -934,7 +934,7 @@ __global__ void __launch_bounds__(kBlock) k_adaptive(StepArgs a) {
       double* t = X;
       X = Xn;
       Xn = t;
-      if (E <= a.tol2 * (1.0 / 64.0) && 2.0 * h <= a.hmax) h = 2.0 * h;
+      if (E <= a.tol2 * (1.0 / 128.0) && 2.0 * h <= a.hmax) h = 2.0 * h;
       if (threadIdx.x < NV) sJsave[threadIdx.x] = sJ[0][threadIdx.x];
       if (last) break;
     } else {
