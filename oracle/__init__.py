@@ -19,7 +19,7 @@ class Params(C.Structure):
     _fields_ = [
         ("n_flavor", C.c_int32), ("n_energy", C.c_int32), ("n_u", C.c_int32),
         ("ne_power", C.c_int32), ("renorm", C.c_int32), ("integrator", C.c_int32),
-        ("species4", C.c_int32), ("pad", C.c_int32), ("n_steps", C.c_int64),
+        ("species4", C.c_int32), ("n_phi", C.c_int32), ("n_steps", C.c_int64),
         ("e_min_mev", C.c_double), ("e_max_mev", C.c_double), ("r_nu_km", C.c_double),
         ("r_start_km", C.c_double), ("r_end_km", C.c_double),
         ("lum_erg_s", C.c_double * 3), ("temp_mev", C.c_double * 3),
@@ -69,6 +69,9 @@ def lib():
         L.nbo_run_adaptive.argtypes = [vp, C.c_double, C.c_double, C.c_int64,
                                        C.POINTER(C.c_int64), C.POINTER(C.c_int64), dp]
         L.nbo_step_error.argtypes = [vp, C.c_double, dp]
+        L.nbo_moments4.argtypes = [vp, C.c_double, dp]
+        L.nbo_hamiltonian4.argtypes = [vp, C.c_double, dp, dp]
+        L.nbo_phi_table.argtypes = [vp, dp]
         _lib = L
     return _lib
 
@@ -91,6 +94,7 @@ def make_params(d: dict, integrator: int = 0, species4: int = 0) -> Params:
     p.theta[:] = [float(x) for x in d["theta"]]
     p.integrator = integrator
     p.species4 = species4
+    p.n_phi = int(d.get("n_phi", 0))
     return p
 
 
@@ -150,9 +154,12 @@ class Model:
         return dict(accepted=int(acc.value), rejected=int(rej.value), h_last=float(hl.value))
 
     def pee(self) -> np.ndarray:
+        """P_ee as [species][n_u][n_energy] (bulb) or [species][n_u][n_phi][n_energy]."""
         out = np.empty(self.nb, np.float64)
         _check(lib().nbo_read_pee(self.h, _dp(out)), "nbo_read_pee")
-        return out.reshape(self.ns, int(self.d["n_u"]), int(self.d["n_energy"]))
+        nphi = int(self.d.get("n_phi", 0))
+        shape = (self.ns, int(self.d["n_u"])) + ((nphi,) if nphi else ()) + (int(self.d["n_energy"]),)
+        return out.reshape(shape)
 
     def get_state(self) -> np.ndarray:
         out = np.empty(self.nb * self.nsc, np.float64)
@@ -191,6 +198,25 @@ class Model:
         _check(lib().nbo_hamiltonian(self.h, float(r), _dp(a0), _dp(a1), _dp(out)),
                "nbo_hamiltonian")
         return out.reshape(self.nb, per)
+
+    def moments4(self, r: float) -> np.ndarray:
+        """[4][ncomp]: J0, J1 and (extended model) J_sc, J_ss."""
+        out = np.zeros(4 * self.ncomp, np.float64)
+        _check(lib().nbo_moments4(self.h, float(r), _dp(out)), "nbo_moments4")
+        return out.reshape(4, self.ncomp)
+
+    def hamiltonian4(self, r: float, jm) -> np.ndarray:
+        a = np.ascontiguousarray(np.asarray(jm, np.float64).reshape(4 * self.ncomp))
+        per = 3 if self.nf == 2 else 9
+        out = np.empty(self.nb * per, np.float64)
+        _check(lib().nbo_hamiltonian4(self.h, float(r), _dp(a), _dp(out)), "nbo_hamiltonian4")
+        return out.reshape(self.nb, per)
+
+    def phi_table(self) -> np.ndarray:
+        n = int(self.d["n_phi"])
+        out = np.empty(2 * n, np.float64)
+        _check(lib().nbo_phi_table(self.h, _dp(out)), "nbo_phi_table")
+        return out.reshape(2, n)
 
     def cos_theta(self, r: float) -> np.ndarray:
         out = np.empty(int(self.d["n_u"]), np.float64)

@@ -310,7 +310,9 @@ struct nbo_model {
   int nf, ncomp, nsc;       /* flavours, moment components, state components */
   int ns;                   /* species rows */
   int anti[6], init_flav[6];
-  int64_t NE, NU, nb;
+  int64_t NE, NU, NP, nb;   /* energy, emission and azimuthal bins (NP = 1: bulb) */
+  int ext;                  /* extended bulb model (n_phi >= 1) */
+  double *cphi, *sphi;      /* cos and sin of the azimuth of every azimuthal bin */
   double dE, du, h, R, lam0, kappa0;
   double *E, *w;            /* E[k]; w[s*NE + k] (includes kappa0 du dE) */
   double *bv;               /* 2f: bx,bz per k; 3f: 6 per k (d0,d1,d2,o01,o02,o12) */
@@ -336,6 +338,29 @@ static radial radial_at(const nbo_model *m, double r) {
 }
 static inline double u_of(const nbo_model *m, int64_t j) { return ((double)j + 0.5) / (double)m->NU; }
 static inline double c_of(const radial *g, double u) { return sqrt(1.0 - u * g->q2); }
+/* sin(theta) at radius r of emission bin u: sin(theta) r = sin(theta_R) R */
+static inline double s_of(const radial *g, double u) { return sqrt(u * g->q2); }
+
+/* Beam b = ((s n_u + j) n_phi + p) n_energy + k -> its species, emission, azimuthal and
+ * energy bins. */
+static inline void beam_of(const nbo_model *m, int64_t b, int *s, int64_t *j, int64_t *p, int64_t *k) {
+  *k = b % m->NE;
+  const int64_t row = b / m->NE;
+  *p = row % m->NP;
+  *j = (row / m->NP) % m->NU;
+  *s = (int)(row / (m->NP * m->NU));
+}
+/* Geometry of a beam at one radius: cos(theta), sin(theta), cos(phi), sin(phi). */
+typedef struct { double c, sn, cp, sp; } bgeo;
+static bgeo geo_of(const nbo_model *m, const radial *g, int64_t j, int64_t p) {
+  bgeo o;
+  const double u = u_of(m, j);
+  o.c = c_of(g, u);
+  o.sn = m->ext ? s_of(g, u) : 0.0;
+  o.cp = m->ext ? m->cphi[p] : 0.0;
+  o.sp = m->ext ? m->sphi[p] : 0.0;
+  return o;
+}
 
 static double fermi_dirac(double E, double T) {
   return (E * E) / ((F2_0 * ((T * T) * T)) * (exp(E / T) + 1.0));
@@ -361,7 +386,8 @@ int nbo_create(const nbo_params *p, nbo_model **out) {
   if (!p || (p->n_flavor != 2 && p->n_flavor != 3) || p->n_energy < 1 || p->n_u < 1 ||
       p->n_steps < 1 || !(p->r_start_km >= p->r_nu_km) || !(p->r_end_km > p->r_start_km) ||
       !(p->e_max_mev > p->e_min_mev) || !(p->e_min_mev > 0.0) || p->delta_cp != 0.0 ||
-      p->ne_power < 0 || p->ne_power > 8 || !(p->r_nu_km > 0.0))
+      p->ne_power < 0 || p->ne_power > 8 || !(p->r_nu_km > 0.0) || p->n_phi < 0 ||
+      p->n_phi > 4096)
     return NBO_EINVAL;
   for (int i = 0; i < 3; ++i)
     if (!(p->temp_mev[i] > 0.0) || !(p->lum_erg_s[i] >= 0.0)) return NBO_EINVAL;
@@ -381,7 +407,24 @@ int nbo_create(const nbo_params *p, nbo_model **out) {
     m->ns = 2 * m->nf;
     for (int s = 0; s < m->ns; ++s) { m->anti[s] = s / m->nf; m->init_flav[s] = s % m->nf; }
   }
-  m->nb = (int64_t)m->ns * m->NU * m->NE;
+  m->ext = p->n_phi >= 1;
+  m->NP = m->ext ? p->n_phi : 1;
+  m->nb = (int64_t)m->ns * m->NU * m->NP * m->NE;
+  m->cphi = (double *)malloc(sizeof(double) * m->NP);
+  m->sphi = (double *)malloc(sizeof(double) * m->NP);
+  /* azimuthal bin midpoints phi_p = 2 pi (p + 1/2) / n_phi; for even n_phi the second half
+   * is the first half turned by pi with the signs flipped exactly, so that the azimuthal
+   * sums of an axially symmetric state vanish exactly */
+  for (int64_t q = 0; q < m->NP; ++q) {
+    if (m->NP % 2 == 0 && q >= m->NP / 2) {
+      m->cphi[q] = -m->cphi[q - m->NP / 2];
+      m->sphi[q] = -m->sphi[q - m->NP / 2];
+    } else {
+      const double ph = (2.0 * PI_D) * (((double)q + 0.5) / (double)m->NP);
+      m->cphi[q] = cos(ph);
+      m->sphi[q] = sin(ph);
+    }
+  }
   m->dE = (p->e_max_mev - p->e_min_mev) / (double)m->NE;
   m->du = 1.0 / (double)m->NU;
   m->h = (p->r_end_km - p->r_start_km) / (double)p->n_steps;
@@ -398,7 +441,9 @@ int nbo_create(const nbo_params *p, nbo_model **out) {
   /* number luminosities N = L / <E>, <E> = T F3/F2 (Fermi-Dirac, zero chemical potential) */
   double N[3];
   for (int a = 0; a < 3; ++a) N[a] = p->lum_erg_s[a] * ERG_MEV / ((p->temp_mev[a] * F3_0) / F2_0);
-  const double pref = (m->kappa0 * m->du) * m->dE;
+  /* extended model: the azimuthal average (1/2pi) int dphi' becomes the mean over bins */
+  const double pref = m->ext ? ((m->kappa0 * m->du) * m->dE) * (1.0 / (double)m->NP)
+                             : (m->kappa0 * m->du) * m->dE;
   for (int64_t k = 0; k < m->NE; ++k) {
     const double E = p->e_min_mev + ((double)k + 0.5) * m->dE;
     m->E[k] = E;
@@ -461,7 +506,7 @@ int nbo_create(const nbo_params *p, nbo_model **out) {
 
 void nbo_destroy(nbo_model *m) {
   if (!m) return;
-  free(m->E); free(m->w); free(m->bv); free(m->X); free(m->Y);
+  free(m->E); free(m->w); free(m->bv); free(m->X); free(m->Y); free(m->cphi); free(m->sphi);
   free(m);
 }
 
@@ -472,7 +517,7 @@ int64_t nbo_step_index(const nbo_model *m) { return m->step; }
 
 int nbo_reset(nbo_model *m) {
   for (int64_t b = 0; b < m->nb; ++b) {
-    const int s = (int)(b / (m->NU * m->NE));
+    const int s = (int)(b / (m->NU * m->NP * m->NE));
     double *x = m->X + b * m->nsc;
     const int fl = m->init_flav[s];
     if (m->nf == 2) { x[0] = 0.0; x[1] = 0.0; x[2] = fl == 0 ? 1.0 : -1.0; }
@@ -504,19 +549,23 @@ static void rho_tilde(const nbo_model *m, int s, const double *x, double *out) {
 }
 
 /* J0 = sum_b g_b rho~_b / c_b(r), J1 = sum_b g_b rho~_b: the energy sum of each
- * (species, angle) row is taken first, exactly in fixed point, then the angle sum. */
-static int moments(const nbo_model *m, const double *X, double r, double *J0, double *J1) {
+ * (species, angle[, azimuth]) row is taken first, exactly in fixed point, then the angle
+ * sum.  Extended model (Eq. F with the azimuthal moments): also
+ * J_sc = sum_b g_b rho~_b sin(theta_b) cos(phi_b) / c_b and J_ss (sin(phi_b)), per row from
+ * the row's energy sum like J0.  Jm[0..1] (bulb) or Jm[0..3] receive the moments. */
+static int moments(const nbo_model *m, const double *X, double r, double (*Jm)[8]) {
   const radial g = radial_at(m, r);
   const int nc = m->ncomp;
-  const int64_t nrow = (int64_t)m->ns * m->NU;
-  i128 *T0 = (i128 *)calloc((size_t)nrow * nc, sizeof(i128));
-  i128 *T1 = (i128 *)calloc((size_t)nrow * nc, sizeof(i128));
+  const int nm = m->ext ? 4 : 2;
+  const int64_t nrow = (int64_t)m->ns * m->NU * m->NP;
+  i128 *T = (i128 *)calloc((size_t)nrow * nm * nc, sizeof(i128));
   int err = 0;
 #pragma omp parallel for schedule(static) reduction(| : err)
   for (int64_t row = 0; row < nrow; ++row) {
-    const int s = (int)(row / m->NU);
-    const int64_t j = row % m->NU;
-    const double ic = 1.0 / c_of(&g, u_of(m, j));
+    const int s = (int)(row / (m->NU * m->NP));
+    const int64_t j = (row / m->NP) % m->NU, q = row % m->NP;
+    const bgeo bg = geo_of(m, &g, j, q);
+    const double ic = 1.0 / bg.c;
     i128 S[8] = {0};
     for (int64_t k = 0; k < m->NE; ++k) {
       const int64_t b = row * m->NE + k;
@@ -524,37 +573,53 @@ static int moments(const nbo_model *m, const double *X, double r, double *J0, do
       rho_tilde(m, s, X + b * m->nsc, v);
       for (int c = 0; c < nc; ++c) S[c] += to_fix(m->w[s * m->NE + k] * v[c], m->s1, TWO58, &err);
     }
+    i128 *t = T + row * nm * nc;
     for (int c = 0; c < nc; ++c) {
-      T1[row * nc + c] = S[c];
-      T0[row * nc + c] = to_fix(ic * (i128_to_double(S[c]) * m->p2e1), m->s0, TWO62, &err);
+      const double e = i128_to_double(S[c]) * m->p2e1;
+      t[c] = to_fix(ic * e, m->s0, TWO62, &err);
+      t[nc + c] = S[c];
+      if (m->ext) {
+        const double a = bg.sn * ic;
+        t[2 * nc + c] = to_fix((a * bg.cp) * e, m->s0, TWO62, &err);
+        t[3 * nc + c] = to_fix((a * bg.sp) * e, m->s0, TWO62, &err);
+      }
     }
   }
-  for (int c = 0; c < nc; ++c) {
-    i128 a0 = 0, a1 = 0;
-    for (int64_t row = 0; row < nrow; ++row) { a0 += T0[row * nc + c]; a1 += T1[row * nc + c]; }
-    J0[c] = i128_to_double(a0) * m->p2e0;
-    J1[c] = i128_to_double(a1) * m->p2e1;
-  }
-  free(T0); free(T1);
+  for (int i = 0; i < nm; ++i)
+    for (int c = 0; c < nc; ++c) {
+      i128 acc = 0;
+      for (int64_t row = 0; row < nrow; ++row) acc += T[(row * nm + i) * nc + c];
+      Jm[i][c] = i128_to_double(acc) * (i == 1 ? m->p2e1 : m->p2e0);
+    }
+  free(T);
   return err ? NBO_ENUMERIC : NBO_OK;
 }
 
-/* Hamiltonian of beam (s, k) in angle bin with cos(theta) = c (Eq. eom):
- * nu:   H_vac + lam E_ee + mu (J0 - c J1)
- * nubar: H_vac - lam E_ee - mu (J0 - c J1)^*                                          */
-static void beam_B2(const nbo_model *m, int s, int64_t k, const radial *g, double c,
-                    const double *J0, const double *J1, double B[3]) {
-  const double nx = g->mu * (J0[0] - c * J1[0]);
-  const double ny = g->mu * (J0[1] - c * J1[1]);
-  const double nz = g->mu * (J0[2] - c * J1[2]);
+/* The neutrino-neutrino term of a beam: mu (J0 - c J1) in the bulb model (Eq. Hnu with
+ * 1 - v.v' = 1 - c c'); the extended model adds - mu sin(theta) (cos(phi) J_sc +
+ * sin(phi) J_ss) from the azimuthal part of 1 - v.v'. */
+static inline double nunu_of(const nbo_model *m, const radial *g, const bgeo *bg,
+                             const double (*Jm)[8], int i) {
+  if (!m->ext) return g->mu * (Jm[0][i] - bg->c * Jm[1][i]);
+  return g->mu * ((Jm[0][i] - bg->c * Jm[1][i]) - bg->sn * (bg->cp * Jm[2][i] + bg->sp * Jm[3][i]));
+}
+
+/* Hamiltonian of beam (s, k) with geometry bg (Eq. eom):
+ * nu:   H_vac + lam E_ee + nn
+ * nubar: H_vac - lam E_ee - nn^*                                                      */
+static void beam_B2(const nbo_model *m, int s, int64_t k, const radial *g, const bgeo *bg,
+                    const double (*Jm)[8], double B[3]) {
+  const double nx = nunu_of(m, g, bg, Jm, 0);
+  const double ny = nunu_of(m, g, bg, Jm, 1);
+  const double nz = nunu_of(m, g, bg, Jm, 2);
   const double bx = m->bv[2 * k], bz = m->bv[2 * k + 1];
   if (!m->anti[s]) { B[0] = bx + nx; B[1] = ny; B[2] = (bz + g->lam) + nz; }
   else { B[0] = bx - nx; B[1] = ny; B[2] = (bz - g->lam) - nz; }
 }
-static void beam_H3(const nbo_model *m, int s, int64_t k, const radial *g, double c,
-                    const double *J0, const double *J1, herm3 *H) {
+static void beam_H3(const nbo_model *m, int s, int64_t k, const radial *g, const bgeo *bg,
+                    const double (*Jm)[8], herm3 *H) {
   double nn[8];
-  for (int i = 0; i < 8; ++i) nn[i] = g->mu * (J0[i] - c * J1[i]);
+  for (int i = 0; i < 8; ++i) nn[i] = nunu_of(m, g, bg, Jm, i);
   const double *v = m->bv + 6 * k;
   if (!m->anti[s]) {
     H->d[0] = (v[0] + g->lam) + nn[0];
@@ -580,30 +645,32 @@ static herm3 h3_scale(double a, const herm3 *H) {
 }
 
 /* Scaled stage generator of beam b at radius g: 2f f = (h/c) B; 3f K = (h/c) H. */
-static void stage_f2h(const nbo_model *m, int64_t b, const radial *g, const double *J0,
-                      const double *J1, double h, double f[3]) {
-  const int s = (int)(b / (m->NU * m->NE));
-  const int64_t j = (b / m->NE) % m->NU, k = b % m->NE;
-  const double c = c_of(g, u_of(m, j));
-  const double hc = h / c;
+static void stage_f2h(const nbo_model *m, int64_t b, const radial *g, const double (*Jm)[8],
+                      double h, double f[3]) {
+  int s;
+  int64_t j, q, k;
+  beam_of(m, b, &s, &j, &q, &k);
+  const bgeo bg = geo_of(m, g, j, q);
+  const double hc = h / bg.c;
   double B[3];
-  beam_B2(m, s, k, g, c, J0, J1, B);
+  beam_B2(m, s, k, g, &bg, Jm, B);
   f[0] = hc * B[0]; f[1] = hc * B[1]; f[2] = hc * B[2];
 }
-static herm3 stage_K3h(const nbo_model *m, int64_t b, const radial *g, const double *J0,
-                       const double *J1, double h) {
-  const int s = (int)(b / (m->NU * m->NE));
-  const int64_t j = (b / m->NE) % m->NU, k = b % m->NE;
-  const double c = c_of(g, u_of(m, j));
-  const double hc = h / c;
+static herm3 stage_K3h(const nbo_model *m, int64_t b, const radial *g, const double (*Jm)[8],
+                       double h) {
+  int s;
+  int64_t j, q, k;
+  beam_of(m, b, &s, &j, &q, &k);
+  const bgeo bg = geo_of(m, g, j, q);
+  const double hc = h / bg.c;
   herm3 H;
-  beam_H3(m, s, k, g, c, J0, J1, &H);
+  beam_H3(m, s, k, g, &bg, Jm, &H);
   return h3_scale(hc, &H);
 }
 /* the 2-flavour generator of the fixed step h = (r_end - r_start) / n_steps */
-static void stage_f2(const nbo_model *m, int64_t b, const radial *g, const double *J0,
-                     const double *J1, double f[3]) {
-  stage_f2h(m, b, g, J0, J1, m->h, f);
+static void stage_f2(const nbo_model *m, int64_t b, const radial *g, const double (*Jm)[8],
+                     double f[3]) {
+  stage_f2h(m, b, g, Jm, m->h, f);
 }
 
 static void renorm2(double *P) {
@@ -641,8 +708,8 @@ static void apply3(const herm3 *K, const double *x, double *y) {
 static int rkmk4_step(nbo_model *m, const double *X, double r0, double rm, double r1, double h,
                       double *Xout, double *emax) {
   const radial g0 = radial_at(m, r0), gm = radial_at(m, rm), g1 = radial_at(m, r1);
-  double J[4][2][8];
-  int st = moments(m, X, r0, J[0][0], J[0][1]);
+  double J[4][4][8];
+  int st = moments(m, X, r0, J[0]);
   const int64_t nb = m->nb;
   const int nsc = m->nsc;
   double *eb = emax ? (double *)malloc(sizeof(double) * nb) : NULL;
@@ -653,16 +720,16 @@ static int rkmk4_step(nbo_model *m, const double *X, double r0, double rm, doubl
     double *y = m->Y + b * nsc;
     if (m->nf == 2) {
       double f1[3], o[3];
-      stage_f2h(m, b, &g0, J[0][0], J[0][1], h, f1);
+      stage_f2h(m, b, &g0, J[0], h, f1);
       o[0] = 0.5 * f1[0]; o[1] = 0.5 * f1[1]; o[2] = 0.5 * f1[2];
       rotate2(o, x, y);
     } else {
-      herm3 K1 = stage_K3h(m, b, &g0, J[0][0], J[0][1], h);
+      herm3 K1 = stage_K3h(m, b, &g0, J[0], h);
       herm3 O = h3_scale(0.5, &K1);
       apply3(&O, x, y);
     }
   }
-  st |= moments(m, m->Y, rm, J[1][0], J[1][1]);
+  st |= moments(m, m->Y, rm, J[1]);
   /* stage 3 */
 #pragma omp parallel for schedule(static)
   for (int64_t b = 0; b < nb; ++b) {
@@ -670,14 +737,14 @@ static int rkmk4_step(nbo_model *m, const double *X, double r0, double rm, doubl
     double *y = m->Y + b * nsc;
     if (m->nf == 2) {
       double f1[3], f2[3], cr[3], o[3];
-      stage_f2h(m, b, &g0, J[0][0], J[0][1], h, f1);
-      stage_f2h(m, b, &gm, J[1][0], J[1][1], h, f2);
+      stage_f2h(m, b, &g0, J[0], h, f1);
+      stage_f2h(m, b, &gm, J[1], h, f2);
       cross3(f1, f2, cr);
       for (int c = 0; c < 3; ++c) o[c] = 0.5 * f2[c] - 0.125 * cr[c];
       rotate2(o, x, y);
     } else {
-      herm3 K1 = stage_K3h(m, b, &g0, J[0][0], J[0][1], h);
-      herm3 K2 = stage_K3h(m, b, &gm, J[1][0], J[1][1], h);
+      herm3 K1 = stage_K3h(m, b, &g0, J[0], h);
+      herm3 K2 = stage_K3h(m, b, &gm, J[1], h);
       herm3 C = h3_icomm(&K1, &K2), O;
       for (int i = 0; i < 3; ++i) O.d[i] = 0.5 * K2.d[i] + 0.125 * C.d[i];
       for (int i = 0; i < 3; ++i)
@@ -685,7 +752,7 @@ static int rkmk4_step(nbo_model *m, const double *X, double r0, double rm, doubl
       apply3(&O, x, y);
     }
   }
-  st |= moments(m, m->Y, rm, J[2][0], J[2][1]);
+  st |= moments(m, m->Y, rm, J[2]);
   /* stage 4 */
 #pragma omp parallel for schedule(static)
   for (int64_t b = 0; b < nb; ++b) {
@@ -693,14 +760,14 @@ static int rkmk4_step(nbo_model *m, const double *X, double r0, double rm, doubl
     double *y = m->Y + b * nsc;
     if (m->nf == 2) {
       double f3[3];
-      stage_f2h(m, b, &gm, J[2][0], J[2][1], h, f3);
+      stage_f2h(m, b, &gm, J[2], h, f3);
       rotate2(f3, x, y);
     } else {
-      herm3 K3 = stage_K3h(m, b, &gm, J[2][0], J[2][1], h);
+      herm3 K3 = stage_K3h(m, b, &gm, J[2], h);
       apply3(&K3, x, y);
     }
   }
-  st |= moments(m, m->Y, r1, J[3][0], J[3][1]);
+  st |= moments(m, m->Y, r1, J[3]);
   /* final update */
 #pragma omp parallel for schedule(static)
   for (int64_t b = 0; b < nb; ++b) {
@@ -708,10 +775,10 @@ static int rkmk4_step(nbo_model *m, const double *X, double r0, double rm, doubl
     double *xo = Xout + b * nsc;
     if (m->nf == 2) {
       double f1[3], f2[3], f3[3], f4[3], cr[3], th[3], y[3];
-      stage_f2h(m, b, &g0, J[0][0], J[0][1], h, f1);
-      stage_f2h(m, b, &gm, J[1][0], J[1][1], h, f2);
-      stage_f2h(m, b, &gm, J[2][0], J[2][1], h, f3);
-      stage_f2h(m, b, &g1, J[3][0], J[3][1], h, f4);
+      stage_f2h(m, b, &g0, J[0], h, f1);
+      stage_f2h(m, b, &gm, J[1], h, f2);
+      stage_f2h(m, b, &gm, J[2], h, f3);
+      stage_f2h(m, b, &g1, J[3], h, f4);
       cross3(f1, f4, cr);
       for (int c = 0; c < 3; ++c)
         th[c] = (((f1[c] + 2.0 * f2[c]) + 2.0 * f3[c]) + f4[c]) * (1.0 / 6.0) - cr[c] * (1.0 / 12.0);
@@ -723,10 +790,10 @@ static int rkmk4_step(nbo_model *m, const double *X, double r0, double rm, doubl
       if (m->p.renorm) renorm2(y);
       xo[0] = y[0]; xo[1] = y[1]; xo[2] = y[2];
     } else {
-      herm3 K1 = stage_K3h(m, b, &g0, J[0][0], J[0][1], h);
-      herm3 K2 = stage_K3h(m, b, &gm, J[1][0], J[1][1], h);
-      herm3 K3 = stage_K3h(m, b, &gm, J[2][0], J[2][1], h);
-      herm3 K4 = stage_K3h(m, b, &g1, J[3][0], J[3][1], h);
+      herm3 K1 = stage_K3h(m, b, &g0, J[0], h);
+      herm3 K2 = stage_K3h(m, b, &gm, J[1], h);
+      herm3 K3 = stage_K3h(m, b, &gm, J[2], h);
+      herm3 K4 = stage_K3h(m, b, &g1, J[3], h);
       herm3 C = h3_icomm(&K1, &K4), T;
       for (int i = 0; i < 3; ++i)
         T.d[i] = (((K1.d[i] + 2.0 * K2.d[i]) + 2.0 * K3.d[i]) + K4.d[i]) * (1.0 / 6.0) + C.d[i] * (1.0 / 12.0);
@@ -842,25 +909,26 @@ int nbo_run_adaptive(nbo_model *m, double tol, double h_max, int64_t max_attempt
 
 /* Right-hand side for plain RK4: 2f dP/dr = (1/c) B x P; 3f dpsi/dr = -(i/c) H psi. */
 static int rhs(const nbo_model *m, const double *X, double r, double *D) {
-  double J0[8], J1[8];
-  int st = moments(m, X, r, J0, J1);
+  double Jm[4][8];
+  int st = moments(m, X, r, Jm);
   const radial g = radial_at(m, r);
 #pragma omp parallel for schedule(static)
   for (int64_t b = 0; b < m->nb; ++b) {
-    const int s = (int)(b / (m->NU * m->NE));
-    const int64_t j = (b / m->NE) % m->NU, k = b % m->NE;
-    const double c = c_of(&g, u_of(m, j));
-    const double ic = 1.0 / c;
+    int s;
+    int64_t j, q, k;
+    beam_of(m, b, &s, &j, &q, &k);
+    const bgeo bg = geo_of(m, &g, j, q);
+    const double ic = 1.0 / bg.c;
     const double *x = X + b * m->nsc;
     double *d = D + b * m->nsc;
     if (m->nf == 2) {
       double B[3], cr[3];
-      beam_B2(m, s, k, &g, c, J0, J1, B);
+      beam_B2(m, s, k, &g, &bg, (const double (*)[8])Jm, B);
       cross3(B, x, cr);
       d[0] = ic * cr[0]; d[1] = ic * cr[1]; d[2] = ic * cr[2];
     } else {
       herm3 H;
-      beam_H3(m, s, k, &g, c, J0, J1, &H);
+      beam_H3(m, s, k, &g, &bg, (const double (*)[8])Jm, &H);
       const cx ps[3] = {cx_make(x[0], x[1]), cx_make(x[2], x[3]), cx_make(x[4], x[5])};
       for (int a = 0; a < 3; ++a) {
         const cx hp = cx_add(cx_add(cx_mul(h3_at(&H, a, 0), ps[0]), cx_mul(h3_at(&H, a, 1), ps[1])),
@@ -942,25 +1010,51 @@ int nbo_tables(const nbo_model *m, double *out, int64_t cap) {
 }
 
 int nbo_moments(const nbo_model *m, double r, double *j0, double *j1) {
-  return moments(m, m->X, r, j0, j1);
+  double Jm[4][8];
+  const int st = moments(m, m->X, r, Jm);
+  for (int c = 0; c < m->ncomp; ++c) { j0[c] = Jm[0][c]; j1[c] = Jm[1][c]; }
+  return st;
+}
+int nbo_moments4(const nbo_model *m, double r, double *jm) {
+  double Jm[4][8] = {{0}};
+  const int st = moments(m, m->X, r, Jm);
+  for (int i = 0; i < 4; ++i)
+    for (int c = 0; c < m->ncomp; ++c) jm[i * m->ncomp + c] = Jm[i][c];
+  return st;
 }
 
-int nbo_hamiltonian(const nbo_model *m, double r, const double *j0, const double *j1,
-                    double *out) {
+int nbo_hamiltonian4(const nbo_model *m, double r, const double *jm, double *out) {
+  double Jm[4][8] = {{0}};
+  for (int i = 0; i < 4; ++i)
+    for (int c = 0; c < m->ncomp; ++c) Jm[i][c] = jm[i * m->ncomp + c];
   const radial g = radial_at(m, r);
   for (int64_t b = 0; b < m->nb; ++b) {
-    const int s = (int)(b / (m->NU * m->NE));
-    const int64_t j = (b / m->NE) % m->NU, k = b % m->NE;
-    const double c = c_of(&g, u_of(m, j));
-    if (m->nf == 2) beam_B2(m, s, k, &g, c, j0, j1, out + 3 * b);
+    int s;
+    int64_t j, q, k;
+    beam_of(m, b, &s, &j, &q, &k);
+    const bgeo bg = geo_of(m, &g, j, q);
+    if (m->nf == 2) beam_B2(m, s, k, &g, &bg, (const double (*)[8])Jm, out + 3 * b);
     else {
       herm3 H;
-      beam_H3(m, s, k, &g, c, j0, j1, &H);
+      beam_H3(m, s, k, &g, &bg, (const double (*)[8])Jm, &H);
       double *o = out + 9 * b;
       o[0] = H.d[0]; o[1] = H.d[1]; o[2] = H.d[2];
       for (int i = 0; i < 3; ++i) { o[3 + 2 * i] = H.o[i].re; o[4 + 2 * i] = H.o[i].im; }
     }
   }
+  return NBO_OK;
+}
+
+int nbo_hamiltonian(const nbo_model *m, double r, const double *j0, const double *j1,
+                    double *out) {
+  double jm[4 * 8] = {0};
+  for (int c = 0; c < m->ncomp; ++c) { jm[c] = j0[c]; jm[m->ncomp + c] = j1[c]; }
+  return nbo_hamiltonian4(m, r, jm, out);
+}
+
+int nbo_phi_table(const nbo_model *m, double *out) {
+  if (!m->ext) return NBO_EINVAL;
+  for (int64_t q = 0; q < m->NP; ++q) { out[q] = m->cphi[q]; out[m->NP + q] = m->sphi[q]; }
   return NBO_OK;
 }
 
@@ -1099,29 +1193,29 @@ static int step_moments(nbo_model *m, const double *X, int64_t n, double J[4][2]
   const double rs = m->p.r_start_km, h = m->h;
   const double r0 = rs + (double)n * h, rm = r0 + 0.5 * h, r1 = rs + (double)(n + 1) * h;
   const radial g0 = radial_at(m, r0), gm = radial_at(m, rm);
-  int st = moments(m, X, r0, J[0][0], J[0][1]);
+  int st = moments(m, X, r0, J[0]);
   for (int64_t b = 0; b < m->nb; ++b) {
     double f1[3], o[3];
-    stage_f2(m, b, &g0, J[0][0], J[0][1], f1);
+    stage_f2(m, b, &g0, (const double (*)[8])J[0], f1);
     for (int c = 0; c < 3; ++c) o[c] = 0.5 * f1[c];
     rotate2(o, X + 3 * b, m->Y + 3 * b);
   }
-  st |= moments(m, m->Y, rm, J[1][0], J[1][1]);
+  st |= moments(m, m->Y, rm, J[1]);
   for (int64_t b = 0; b < m->nb; ++b) {
     double f1[3], f2[3], cr[3], o[3];
-    stage_f2(m, b, &g0, J[0][0], J[0][1], f1);
-    stage_f2(m, b, &gm, J[1][0], J[1][1], f2);
+    stage_f2(m, b, &g0, (const double (*)[8])J[0], f1);
+    stage_f2(m, b, &gm, (const double (*)[8])J[1], f2);
     cross3(f1, f2, cr);
     for (int c = 0; c < 3; ++c) o[c] = 0.5 * f2[c] - 0.125 * cr[c];
     rotate2(o, X + 3 * b, m->Y + 3 * b);
   }
-  st |= moments(m, m->Y, rm, J[2][0], J[2][1]);
+  st |= moments(m, m->Y, rm, J[2]);
   for (int64_t b = 0; b < m->nb; ++b) {
     double f3[3];
-    stage_f2(m, b, &gm, J[2][0], J[2][1], f3);
+    stage_f2(m, b, &gm, (const double (*)[8])J[2], f3);
     rotate2(f3, X + 3 * b, m->Y + 3 * b);
   }
-  st |= moments(m, m->Y, r1, J[3][0], J[3][1]);
+  st |= moments(m, m->Y, r1, J[3]);
   return st;
 }
 
@@ -1181,10 +1275,10 @@ static void reverse_step(nbo_model *m, const adj_tables *t, const double *X, int
     const int64_t j = (b / m->NE) % m->NU, k = b % m->NE;
     const double u = u_of(m, j);
     double f1[3], f2[3], f3[3], f4[3], cr[3], th[3], Pp[3];
-    stage_f2(m, b, &g0, J[0][0], J[0][1], f1);
-    stage_f2(m, b, &gm, J[1][0], J[1][1], f2);
-    stage_f2(m, b, &gm, J[2][0], J[2][1], f3);
-    stage_f2(m, b, &g1, J[3][0], J[3][1], f4);
+    stage_f2(m, b, &g0, (const double (*)[8])J[0], f1);
+    stage_f2(m, b, &gm, (const double (*)[8])J[1], f2);
+    stage_f2(m, b, &gm, (const double (*)[8])J[2], f3);
+    stage_f2(m, b, &g1, (const double (*)[8])J[3], f4);
     cross3(f1, f4, cr);
     for (int c = 0; c < 3; ++c)
       th[c] = (((f1[c] + 2.0 * f2[c]) + 2.0 * f3[c]) + f4[c]) * (1.0 / 6.0) - cr[c] * (1.0 / 12.0);
@@ -1220,7 +1314,7 @@ static void reverse_step(nbo_model *m, const adj_tables *t, const double *X, int
     const int64_t j = (b / m->NE) % m->NU, k = b % m->NE;
     const double u = u_of(m, j);
     double f3[3], Y[3], Yb[3] = {0, 0, 0}, om[3], f3b[3];
-    stage_f2(m, b, &gm, J[2][0], J[2][1], f3);
+    stage_f2(m, b, &gm, (const double (*)[8])J[2], f3);
     rotate2(f3, X + 3 * b, Y);
     m_adjoint(m, s, k, c_of(&g1, u), Jb[3][0], Jb[3][1], Y, Yb, &wbar[b]);
     add_rot_adjoint(f3, 1.0, Yb, Pb + 3 * b);
@@ -1237,8 +1331,8 @@ static void reverse_step(nbo_model *m, const adj_tables *t, const double *X, int
     const int64_t j = (b / m->NE) % m->NU, k = b % m->NE;
     const double u = u_of(m, j);
     double f1[3], f2[3], cr[3], o[3], Y[3], Yb[3] = {0, 0, 0}, om[3], ob[3];
-    stage_f2(m, b, &g0, J[0][0], J[0][1], f1);
-    stage_f2(m, b, &gm, J[1][0], J[1][1], f2);
+    stage_f2(m, b, &g0, (const double (*)[8])J[0], f1);
+    stage_f2(m, b, &gm, (const double (*)[8])J[1], f2);
     cross3(f1, f2, cr);
     for (int c = 0; c < 3; ++c) o[c] = 0.5 * f2[c] - 0.125 * cr[c];
     rotate2(o, X + 3 * b, Y);
@@ -1263,7 +1357,7 @@ static void reverse_step(nbo_model *m, const adj_tables *t, const double *X, int
     const int64_t j = (b / m->NE) % m->NU, k = b % m->NE;
     const double u = u_of(m, j);
     double f1[3], o[3], Y[3], Yb[3] = {0, 0, 0}, om[3], ob[3];
-    stage_f2(m, b, &g0, J[0][0], J[0][1], f1);
+    stage_f2(m, b, &g0, (const double (*)[8])J[0], f1);
     for (int c = 0; c < 3; ++c) o[c] = 0.5 * f1[c];
     rotate2(o, X + 3 * b, Y);
     m_adjoint(m, s, k, c_of(&gm, u), Jb[1][0], Jb[1][1], Y, Yb, &wbar[b]);
@@ -1285,7 +1379,7 @@ static void reverse_step(nbo_model *m, const adj_tables *t, const double *X, int
 
 int nbo_adjoint(nbo_model *m, int32_t ckpt, const double *dl_dpee, double *grad, double *loss,
                 double *state_bar) {
-  if (!m || m->nf != 2 || m->p.species4 || m->p.integrator || ckpt < 1) return NBO_EINVAL;
+  if (!m || m->nf != 2 || m->p.species4 || m->p.integrator || m->ext || ckpt < 1) return NBO_EINVAL;
   const int64_t n0 = m->step, N = m->p.n_steps;
   const int64_t nseg = (N - n0 + ckpt - 1) / ckpt;
   const int64_t ns = m->nb * 3;

@@ -34,7 +34,8 @@ typedef struct {
   int32_t integrator;   /* 0: RKMK4 (exact exponentials); 1: plain RK4 on the ODE */
   int32_t species4;     /* 0: track nu_e- and anti-nu_e-born beams only;
                            1: track every initially populated flavour explicitly */
-  int32_t pad;
+  int32_t n_phi;        /* 0: the bulb model (axial symmetry); >= 1: the extended bulb
+                           model with n_phi azimuthal bins of equal width over [0, 2pi) */
   int64_t n_steps;
   double e_min_mev, e_max_mev, r_nu_km, r_start_km, r_end_km;
   double lum_erg_s[3];  /* nu_e, anti-nu_e, nu_x (= every heavy flavour and antiflavour) */
@@ -57,7 +58,8 @@ int  nbo_state_comps(const nbo_model *m);         /* 3 (2f Bloch vector) or 6 (3
 int  nbo_reset(nbo_model *m);
 int  nbo_step(nbo_model *m, int64_t n);
 int64_t nbo_step_index(const nbo_model *m);
-/* Re rho_ee of every beam, layout [species][n_u][n_energy]. */
+/* Re rho_ee of every beam, layout [species][n_u][n_phi][n_energy] (n_phi = 1 for the
+ * bulb model). */
 int  nbo_read_pee(const nbo_model *m, double *out);
 /* State exchange: [comp][beam] planes, beam = (s*n_u + j)*n_energy + k. */
 int  nbo_get_state(const nbo_model *m, double *out);
@@ -68,6 +70,12 @@ int  nbo_set_state(nbo_model *m, const double *in, int64_t step);
 int  nbo_tables(const nbo_model *m, double *out, int64_t cap);
 /* Moments J0 (ncomp) and J1 (ncomp) of the current state at radius r (Eq. F). */
 int  nbo_moments(const nbo_model *m, double r, double *j0, double *j1);
+/* All moments as [4][ncomp]: J0, J1, and for the extended model J_sc, J_ss (else 0). */
+int  nbo_moments4(const nbo_model *m, double r, double *jm);
+/* Per-beam Hamiltonian for the four moments jm [4][ncomp] (layout as nbo_hamiltonian). */
+int  nbo_hamiltonian4(const nbo_model *m, double r, const double *jm, double *out);
+/* cos and sin of the azimuth of every azimuthal bin ([2][n_phi]); extended model only. */
+int  nbo_phi_table(const nbo_model *m, double *out);
 /* Per-beam Hamiltonian at radius r for given moments (2f: B vector, 3 per beam;
  * 3f: Hermitian matrix d0,d1,d2,Re/Im o01,o02,o12 = 9 per beam).  Not scaled by h/c. */
 int  nbo_hamiltonian(const nbo_model *m, double r, const double *j0, const double *j1,

@@ -123,3 +123,45 @@ def bvec(H):
 
 def expm_apply(H, L, psi):
     return linalg.expm(-1j * H * L) @ psi
+
+
+def brute_h_nunu_ext(d, r, rho_e, rho_ebar):
+    """H_nunu of the extended bulb model by the direct pair sum of Eq. Hnu with the
+    azimuthal replacements of Eq. int-v: 1 - v.v' = 1 - [c c' + s s' cos(phi - phi')] and
+    the average (1/2 pi) int dphi' taken over n_phi equal bins.
+
+    rho_e, rho_ebar: [NU, NP, NE, n, n].  Returns [2, NU, NP, NE, n, n] as brute_h_nunu.
+    """
+    n = rho_e.shape[-1]
+    E, dE, u, du = bins(d)
+    NP = d["n_phi"]
+    phi = 2.0 * np.pi * (np.arange(NP) + 0.5) / NP
+    R = d["r_nu_km"]
+    L = d["lum_erg_s"]; T = d["temp_mev"]
+    Nnum = [L[a] * ERG_MEV / mean_energy(T[a]) for a in range(3)]
+    fe, fb, fx = spectrum(E, T[0]), spectrum(E, T[1]), spectrum(E, T[2])
+    I = np.eye(n)
+    cth = np.sqrt(1.0 - u * (R / r) ** 2)
+    sth = np.sqrt(u) * (R / r)
+    pref = sqrt2gf_km_cm3() / (2.0 * np.pi * (R * 1e5) ** 2 * C_CM_S)
+    F = np.zeros((len(u), NP, n, n), complex)          # energy-integrated source per bin
+    for jp in range(len(u)):
+        for pp in range(NP):
+            for kp in range(len(E)):
+                Fe = Nnum[0] * fe[kp] * rho_e[jp, pp, kp]
+                Fx = Nnum[2] * fx[kp] * (I - rho_e[jp, pp, kp])
+                Fb = Nnum[1] * fb[kp] * rho_ebar[jp, pp, kp]
+                Fbx = Nnum[2] * fx[kp] * (I - rho_ebar[jp, pp, kp])
+                F[jp, pp] += dE * (Fe + Fx - np.conj(Fb + Fbx))
+    Hnn = np.zeros((2, len(u), NP, len(E), n, n), complex)
+    for j in range(len(u)):
+        for p in range(NP):
+            acc = np.zeros((n, n), complex)
+            for jp in range(len(u)):
+                for pp in range(NP):
+                    vv = cth[j] * cth[jp] + sth[j] * sth[jp] * np.cos(phi[p] - phi[pp])
+                    geo = (1.0 - vv) * (R * R / (2 * r * r)) * du / cth[jp] / NP
+                    acc += geo * F[jp, pp]
+            Hnn[0, j, p] = pref * acc
+    Hnn[1] = -np.conj(Hnn[0])
+    return Hnn
