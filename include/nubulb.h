@@ -8,7 +8,9 @@
  * dl = dr/cos(theta) (Eq. U), and whose Hamiltonian
  *     H = H_vac(E) + H_mat(r) + H_nunu(theta; r)                       (Eq. eom)
  * is rebuilt at every stage from two moments of all beams, J0 = sum g rho~/cos(theta')
- * and J1 = sum g rho~ (Eqs. Hnu and F), summed exactly in fixed point.  Antineutrinos
+ * and J1 = sum g rho~ (Eqs. Hnu and F), summed exactly in fixed point (the extended model
+ * adds J_sc and J_ss, the sin(theta) cos(phi) and sin(theta) sin(phi) moments of Eq. F, and
+ * H_nunu gains - sin(theta) (cos(phi) J_sc + sin(phi) J_ss)).  Antineutrinos
  * evolve with H_vac - H_mat - H_nunu^* (Eq. eom).  Every beam starts in its flavour
  * eigenstate at r_start (Sec. 3.4).
  *
@@ -23,8 +25,9 @@
  *   - streams: all device work is enqueued on the stream given to nb_bind.  Calls return
  *     after checking the kernels' status word, i.e. after the stream has drained, unless
  *     the stream is being captured into a HIP graph (then they return at once).
- *   - beam index b = (s * n_u + j) * n_energy + k, with species s (0 = nu_e-born,
- *     1 = anti-nu_e-born), emission bin j and energy bin k; energy is innermost.
+ *   - beam index b = ((s * n_u + j) * n_phi + p) * n_energy + k, with species s
+ *     (0 = nu_e-born, 1 = anti-nu_e-born), emission bin j, azimuthal bin p (n_phi = 1 and
+ *     p = 0 for the bulb model) and energy bin k; energy is innermost.
  *   - layouts of device buffers are plain arrays of double in that beam order.
  *   - errors are checked before any device work is enqueued.
  */
@@ -71,7 +74,9 @@ typedef struct {
   double delta_cp;      /* must be 0 (real mixing matrix) */
   double n0_cm3;        /* electron density scale */
   int32_t adaptive;     /* 1: reserve workspace for nb_run_adaptive (single FP64 models) */
-  int32_t reserved;     /* must be 0 */
+  int32_t n_phi;        /* 0: the bulb model.  >= 1: the extended bulb model (Sec. 2, the
+                           replacements of Eq. int-v) with n_phi azimuthal bins of equal
+                           width over [0, 2 pi); single FP64 models, fixed steps */
 } nb_params;
 
 typedef struct nb_model nb_model;

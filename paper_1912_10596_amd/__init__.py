@@ -36,7 +36,7 @@ class Params(C.Structure):
         ("r_start_km", C.c_double), ("r_end_km", C.c_double),
         ("lum_erg_s", C.c_double * 3), ("temp_mev", C.c_double * 3),
         ("dm2_ev2", C.c_double * 2), ("theta", C.c_double * 3), ("delta_cp", C.c_double),
-        ("n0_cm3", C.c_double), ("adaptive", C.c_int32), ("reserved", C.c_int32),
+        ("n0_cm3", C.c_double), ("adaptive", C.c_int32), ("n_phi", C.c_int32),
     ]
 
 
@@ -109,6 +109,7 @@ def make_params(d: dict, precision: int | None = None, adjoint_ckpt: int = 0,
     p = Params()
     p.max_blocks = int(d.get("max_blocks", max_blocks))
     p.adaptive = int(bool(adaptive))
+    p.n_phi = int(d.get("n_phi", 0))
     for k in ("n_flavor", "n_energy", "n_u", "ne_power", "renorm", "n_steps"):
         setattr(p, k, int(d[k]))
     p.precision = int(d.get("precision", 0) if precision is None else precision)

@@ -15,7 +15,7 @@
 #include "nb_internal.h"
 
 namespace nb {
-template <int NF, typename ST, bool TLDS, bool F32>
+template <int NF, typename ST, bool TLDS, bool F32, bool EXT>
 __global__ void k_advance(StepArgs a);
 __global__ void k_batch2(BatchArgs a);
 template <int BPT>
@@ -81,7 +81,7 @@ static double fd_spectrum(double E, double T) {  // normalised Fermi-Dirac, zero
 // One model (or, for a batch, one member): parameters and host tables.
 struct Sub {
   nb_params p{};
-  long long NE = 0, NU = 0, beam0 = 0, row0 = 0, tab0 = 0;
+  long long NE = 0, NU = 0, NP = 1, beam0 = 0, row0 = 0, tab0 = 0;  // NP: azimuthal bins
   double h = 0, lam0 = 0, kappa0 = 0, s1 = 0, s0 = 0, p2e1 = 0, p2e0 = 0;
   double vac_max = 0;                // max over energy bins of sum |H_vac entries|
   long long fp32_from = 0;           // mixed precision: first step run with FP32 arithmetic
@@ -146,7 +146,11 @@ static int validate(const nb_params* p) {
   if (p->max_blocks < 0) return fail(NB_EINVAL, "max_blocks must be >= 0");
   if (p->adaptive != 0 && p->adaptive != 1) return fail(NB_EINVAL, "adaptive must be 0 or 1");
   if (p->adaptive && p->precision != NB_FP64) return fail(NB_EINVAL, "adaptive stepping is an FP64 mode");
-  if (p->reserved != 0) return fail(NB_EINVAL, "reserved must be 0");
+  if (p->n_phi < 0 || p->n_phi > 4096) return fail(NB_EINVAL, "n_phi must be in 0..4096");
+  if (p->n_phi > 0 && (p->precision != NB_FP64 || p->adjoint_ckpt != 0 || p->adaptive != 0))
+    return fail(NB_EINVAL, "the extended bulb model is an FP64 fixed-step mode without adjoint");
+  if ((long long)p->n_energy * p->n_u * (p->n_phi > 0 ? p->n_phi : 1) > (1LL << 34))
+    return fail(NB_EINVAL, "too many beams");
   return NB_OK;
 }
 
@@ -166,10 +170,31 @@ static void build_tables(Sub* m) {
   m->kappa0 = s2gf / (((2.0 * kPi) * (rcm * rcm)) * kClight);
   double N[3];
   for (int a = 0; a < 3; ++a) N[a] = p.lum_erg_s[a] * kErgMeV / ((p.temp_mev[a] * kFD3) / kFD2);
-  const double pref = (m->kappa0 * du) * dE;
+  // extended model: the azimuthal average (1/2pi) int dphi' becomes the mean over the bins
+  const bool ext = p.n_phi > 0;
+  const double pref = ext ? ((m->kappa0 * du) * dE) * (1.0 / (double)m->NP) : (m->kappa0 * du) * dE;
   const int nv = (m->nf == 2) ? 2 : 6;
   m->E.assign(NE, 0.0);
-  m->tab.assign((size_t)(nv + 2) * NE, 0.0);
+  // tables: [vacuum terms (nv) | G0 | G1] x NE, then (extended) cos and sin of the azimuth
+  // of every azimuthal bin
+  m->tab.assign((size_t)(nv + 2) * NE + (ext ? (size_t)2 * m->NP : 0), 0.0);
+  if (ext) {
+    // bin midpoints phi_p = 2 pi (p + 1/2) / n_phi; for even n_phi the second half is the
+    // first turned by pi with exactly flipped signs (azimuthal sums of an axially
+    // symmetric state then vanish exactly)
+    double* cp = m->tab.data() + (size_t)(nv + 2) * NE;
+    double* sp = cp + m->NP;
+    for (long long q = 0; q < m->NP; ++q) {
+      if (m->NP % 2 == 0 && q >= m->NP / 2) {
+        cp[q] = -cp[q - m->NP / 2];
+        sp[q] = -sp[q - m->NP / 2];
+      } else {
+        const double ph = (2.0 * kPi) * (((double)q + 0.5) / (double)m->NP);
+        cp[q] = std::cos(ph);
+        sp[q] = std::sin(ph);
+      }
+    }
+  }
   m->dtab.assign(m->nf == 2 ? (size_t)5 * NE : 0, 0.0);
   double* G0 = m->tab.data() + (size_t)nv * NE;
   double* G1 = G0 + NE;
@@ -274,6 +299,7 @@ static int make_sub(const nb_params* p, Sub* s) {
   s->p = *p;
   s->NE = p->n_energy;
   s->NU = p->n_u;
+  s->NP = (p->n_phi > 0) ? p->n_phi : 1;
   build_tables(s);
   return NB_OK;
 }
@@ -295,8 +321,8 @@ static void finish_layout_host(nb_model* m) {
     s.beam0 = beam;
     s.row0 = row;
     s.tab0 = t;
-    beam += 2LL * s.NE * s.NU;
-    row += 2LL * s.NU;
+    beam += 2LL * s.NE * s.NU * s.NP;
+    row += 2LL * s.NU * s.NP;
     t += (long long)s.tab.size();
     m->tab.insert(m->tab.end(), s.tab.begin(), s.tab.end());
   }
@@ -331,6 +357,7 @@ extern "C" int nb_batch_create(const nb_params* p, int32_t n_models, nb_model** 
       return fail(NB_EINVAL, "batched models are two-flavour FP64 (model %d)", i);
     if (q.adjoint_ckpt != 0) return fail(NB_EINVAL, "batched models have no adjoint (model %d)", i);
     if (q.adaptive != 0) return fail(NB_EINVAL, "batched models step on a fixed grid (model %d)", i);
+    if (q.n_phi != 0) return fail(NB_EINVAL, "batched models are bulb models (model %d)", i);
     if (q.n_steps != p[0].n_steps || q.r_start_km != p[0].r_start_km || q.r_end_km != p[0].r_end_km ||
         q.r_nu_km != p[0].r_nu_km || q.ne_power != p[0].ne_power || q.renorm != p[0].renorm)
       return fail(NB_EINVAL, "batched models must share the radial grid, R, ne_power and renorm (model %d)", i);
@@ -454,15 +481,19 @@ static const void* advance_kernel(const nb_model* m) {
   if (m->batch) return (const void*)&k_batch2;
   const bool l = tab_in_lds(m);
   if (m->nf == 2)
-    return l ? (const void*)&k_advance<2, double, true, false> : (const void*)&k_advance<2, double, false, false>;
+    return m->p.n_phi > 0
+               ? (l ? (const void*)&k_advance<2, double, true, false, true> : (const void*)&k_advance<2, double, false, false, true>)
+               : (l ? (const void*)&k_advance<2, double, true, false, false> : (const void*)&k_advance<2, double, false, false, false>);
   if (state_fp32(m))
-    return l ? (const void*)&k_advance<3, float, true, false> : (const void*)&k_advance<3, float, false, false>;
-  return l ? (const void*)&k_advance<3, double, true, false> : (const void*)&k_advance<3, double, false, false>;
+    return l ? (const void*)&k_advance<3, float, true, false, false> : (const void*)&k_advance<3, float, false, false, false>;
+  if (m->p.n_phi > 0)
+    return l ? (const void*)&k_advance<3, double, true, false, true> : (const void*)&k_advance<3, double, false, false, true>;
+  return l ? (const void*)&k_advance<3, double, true, false, false> : (const void*)&k_advance<3, double, false, false, false>;
 }
 // The FP32-arithmetic stepping kernel of the mixed-precision mode (nullptr otherwise).
 static const void* advance_kernel_f32(const nb_model* m) {
   if (m->batch || !state_fp32(m)) return nullptr;
-  return tab_in_lds(m) ? (const void*)&k_advance<3, float, true, true> : (const void*)&k_advance<3, float, false, true>;
+  return tab_in_lds(m) ? (const void*)&k_advance<3, float, true, true, false> : (const void*)&k_advance<3, float, false, true, false>;
 }
 
 static int launch_1d(const void* fn, long long n, void** args, hipStream_t s) {
@@ -722,6 +753,7 @@ static int enqueue_advance(nb_model* m, long long k) {
   a.plane = m->plane;
   a.NE = (int)s.NE;
   a.NU = (int)s.NU;
+  a.NP = (int)s.NP;
   a.nsteps = k;
   a.total_steps = m->p.n_steps;
   a.rs = m->p.r_start_km;
@@ -828,6 +860,7 @@ extern "C" int nb_run_adaptive(nb_model* m, double tol, double h_max_km, int64_t
   a.plane = m->plane;
   a.NE = (int)s.NE;
   a.NU = (int)s.NU;
+  a.NP = 1;
   a.nsteps = m->p.n_steps;
   a.total_steps = m->p.n_steps;
   a.rs = m->p.r_start_km;

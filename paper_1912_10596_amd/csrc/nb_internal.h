@@ -21,7 +21,7 @@ constexpr int kSyncArrive = kSyncFlag + kFlagCopies * kLineWords;  // [kMaxBlock
 // carries the barrier epoch it belongs to, so no separate arrival or release word is
 // needed): kFlagCopies copies of the reduced moments (block b reads copy b % kFlagCopies),
 // kTagLines lines each; one slot of kTagLines lines of block partials per block.
-constexpr int kTagLines = 3;
+constexpr int kTagLines = 4;
 constexpr int kSyncJTag = kSyncArrive + kMaxBlocks * kLineWords;
 constexpr int kSyncPart = kSyncJTag + kFlagCopies * kTagLines * kLineWords;
 constexpr int kSyncWords = kSyncPart + kMaxBlocks * kTagLines * kLineWords;
@@ -32,12 +32,14 @@ constexpr int kBlock = 512;       // threads per block of the stepping kernels (
 // Arguments of the single-model stepping kernel (passed by value).
 struct StepArgs {
   void* X;                 // state planes [nsc][plane] (double, or float for FP32 state)
-  const double* tab;       // tables: 2f [bx|bz|G0|G1] x NE; 3f [h_ee..h_mt (6)|G0|G1] x NE
+  const double* tab;       // tables: 2f [bx|bz|G0|G1] x NE; 3f [h_ee..h_mt (6)|G0|G1] x NE;
+                           // extended model: then cos, sin of every azimuthal bin
   unsigned int* sync;      // kSyncWords words (barrier words and the tagged reduction words)
   long long* step_ctl;     // [0] device step counter (read at launch start, advanced at the
                            // end); [1] target of a group of windowed launches
   long long plane;         // plane stride (elements)
   int NE, NU;
+  int NP;                  // azimuthal bins (extended bulb model; 1 for the bulb model)
   long long nsteps, total_steps;  // requested steps (clamped to total_steps - start)
   double rs, h, R, lam0;
   int ne_power, renorm;

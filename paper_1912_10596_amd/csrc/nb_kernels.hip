@@ -61,7 +61,9 @@ __device__ __forceinline__ long long chunk_value(unsigned long long field, int k
 // block's largest error estimate as the top 48 bits of its binary form (a non-negative
 // double, so the integer order of the fields is the order of the values); block 0 takes
 // the largest field and publishes the value in two more words, which lands in *sE.
-template <int NV, bool MAXE>
+// NM moment groups of NV / NM components: J0 | J1 (| J_sc | J_ss); J1 is at scale 2^e1,
+// the others at 2^e0.
+template <int NV, bool MAXE, int NM = 2>
 __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, long long own,
                             unsigned long long efield, double* sJ, long long* sacc, double* sE) {
   constexpr int W = 2 * NV + (MAXE ? 1 : 0);   // words per partial
@@ -155,7 +157,7 @@ __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, long lo
     // total = c0 + c1 2^48 (c0 >= 0, c1 signed)
     const I128 tot = i128_add(I128{(unsigned long long)c0, 0ll},
                               I128{(unsigned long long)c1 << 48, c1 >> 16});
-    const double val = i128_to_double(tot) * (tid < NV / 2 ? a.p2e0 : a.p2e1);
+    const double val = i128_to_double(tot) * ((tid / (NV / NM)) == 1 ? a.p2e1 : a.p2e0);
     sJ[tid] = val;
     const unsigned long long bits = as_bits(val);
     const unsigned long long tg = (unsigned long long)want << 32;
@@ -185,7 +187,7 @@ __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, long lo
 // Fold the waves' per-lane totals (lane v holds value v) and run the grid reduction.
 // MAXE: also the largest of the lanes' error estimates emax (then swm holds one double per
 // wave and the grid's largest estimate lands in *sE).
-template <int NV, bool MAXE = false>
+template <int NV, bool MAXE = false, int NM = 2>
 __device__ bool finish_stage(const StepArgs& a, unsigned epoch, I128 T, I128 (*sw)[NV],
                              long long* sacc, double* sJ, double emax = 0.0, double* swm = nullptr,
                              double* sE = nullptr) {
@@ -218,7 +220,7 @@ __device__ bool finish_stage(const StepArgs& a, unsigned epoch, I128 T, I128 (*s
       if (threadIdx.x == 2 * NV) own = (long long)efield;
     }
   }
-  return grid_reduce<NV, MAXE>(a, epoch, blk, own, efield, sJ, sacc, sE);
+  return grid_reduce<NV, MAXE, NM>(a, epoch, blk, own, efield, sJ, sacc, sE);
 }
 
 // Radii and length of one step: stage radii r0, rm = r0 + h/2 and r1.  On the fixed grid
@@ -245,7 +247,7 @@ struct Scales {
 // ((NC + 2) x 64 words): every lane stores its NC sums; lane (g, c) of G = 64/NC groups adds
 // component c of L = ceil(64/G) lanes as a 128-bit integer; lanes v < 2 NC add the G group
 // sums of component v % NC.  Integer sums, so the order does not matter.
-template <int NC>
+template <int NC, int NM = 2>
 __device__ __forceinline__ void fold_segment(const long long* acc, int lane, long long* fl, I128& mine) {
   constexpr int G = 64 / NC, L = (64 + G - 1) / G;
 #pragma unroll
@@ -263,7 +265,7 @@ __device__ __forceinline__ void fold_segment(const long long* acc, int lane, lon
     gs[g * NC + c] = part;
   }
   __asm__ volatile("" ::: "memory");
-  if (lane < 2 * NC) {
+  if (lane < NM * NC) {
     const int cc = lane % NC;
     I128 t = i128_zero();
 #pragma unroll
@@ -273,14 +275,21 @@ __device__ __forceinline__ void fold_segment(const long long* acc, int lane, lon
   __asm__ volatile("" ::: "memory");
 }
 // End of a row: lanes v < NC add the J0 angle term (energy sum / cos), lanes
-// NC <= v < 2 NC the J1 energy sum, to their running totals.
-template <int NC>
+// NC <= v < 2 NC the J1 energy sum, to their running totals; with NM = 4 (extended model)
+// lanes 2 NC <= v < 3 NC add the J_sc term (energy sum sin(theta) cos(phi) / cos: asc =
+// (sin(theta) / cos) cos(phi)) and 3 NC <= v < 4 NC the J_ss term (ass, sin(phi)).
+template <int NC, int NM = 2>
 __device__ __forceinline__ void close_row(const Scales& sc, int lane, const I128& mine,
-                                          double icmom, I128& T, int& err) {
-  if (lane < NC)
+                                          double icmom, I128& T, int& err, double asc = 0.0,
+                                          double ass = 0.0) {
+  if (lane < NC) {
     T = i128_add(T, i128_from(to_fix(icmom * (i128_to_double(mine) * sc.p2e1), sc.s0, kTwo62, err)));
-  else if (lane < 2 * NC)
+  } else if (lane < 2 * NC) {
     T = i128_add(T, mine);
+  } else if (NM == 4 && lane < 4 * NC) {
+    const double f = (lane < 3 * NC) ? asc : ass;
+    T = i128_add(T, i128_from(to_fix(f * (i128_to_double(mine) * sc.p2e1), sc.s0, kTwo62, err)));
+  }
 }
 
 // ----------------------------------------------------------------- two flavours
@@ -292,19 +301,24 @@ __device__ __forceinline__ void close_row(const Scales& sc, int lane, const I128
 // are folded into exact 128-bit wave sums.
 // ADAPT (final update only): the new state goes to Xo instead of X, and emax keeps the
 // largest embedded error estimate |Theta - f2|^2 of the lane's beams.
-template <int KIND, bool ADAPT = false>
+// EXT: extended bulb model, azimuth (cp, sp) = (cos, sin) of the row's azimuthal bin.
+template <int KIND, bool ADAPT = false, bool EXT = false>
 __device__ __forceinline__ void row2(const double* X, double* Xo, long long plane, long long rb, int NE,
                                      int s, double u, double h, const double* tab, const Radial& g0,
                                      const Radial& gm, const Radial& g1, const double* const* J,
                                      const Scales& sc, int renorm, int lane, long long* fl, I128& T,
-                                     int& err, double& emax) {
+                                     int& err, double& emax, double cp = 0.0, double sp = 0.0) {
+  constexpr int NM = EXT ? 4 : 2;
   const RowGeo rg = row_geo(u, h, g0, gm, g1);
   const double icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
+  // sin(theta) at the three stage radii (sin(theta) r = sin(theta_R) R)
+  const double sn0 = EXT ? sqrt(u * g0.q2) : 0.0, snm = EXT ? sqrt(u * gm.q2) : 0.0;
+  const double sn1 = EXT ? sqrt(u * g1.q2) : 0.0;
   double n1[3], n2[3], n3[3], n4[3];
-  if (KIND == 1 || KIND == 2 || KIND == 4) nunu<3>(J[0], g0.mu, rg.c0, n1);
-  if (KIND == 2 || KIND == 4) nunu<3>(J[1], gm.mu, rg.cm, n2);
-  if (KIND >= 3) nunu<3>(J[2], gm.mu, rg.cm, n3);
-  if (KIND == 4) nunu<3>(J[3], g1.mu, rg.c1, n4);
+  if (KIND == 1 || KIND == 2 || KIND == 4) nunu_row<3, EXT>(J[0], g0.mu, rg.c0, sn0, cp, sp, n1);
+  if (KIND == 2 || KIND == 4) nunu_row<3, EXT>(J[1], gm.mu, rg.cm, snm, cp, sp, n2);
+  if (KIND >= 3) nunu_row<3, EXT>(J[2], gm.mu, rg.cm, snm, cp, sp, n3);
+  if (KIND == 4) nunu_row<3, EXT>(J[3], g1.mu, rg.c1, sn1, cp, sp, n4);
   const double* G = tab + (size_t)(2 + s) * NE;
   I128 mine = i128_zero();
   for (int k0 = lane; k0 - lane < NE; k0 += 64 * 32) {
@@ -370,25 +384,40 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
       acc[1] += to_fix(w * P1, sc.s1, kTwo58, err);
       acc[2] += to_fix(w * v2, sc.s1, kTwo58, err);
     }
-    fold_segment<3>(acc, lane, fl, mine);
+    fold_segment<3, NM>(acc, lane, fl, mine);
   }
-  close_row<3>(sc, lane, mine, icmom, T, err);
+  const double snmom = (KIND == 0) ? sn0 : ((KIND <= 2) ? snm : sn1);
+  close_row<3, NM>(sc, lane, mine, icmom, T, err, (snmom * icmom) * cp, (snmom * icmom) * sp);
 }
 
-template <int KIND, bool ADAPT = false>
+template <int KIND, bool ADAPT = false, bool EXT = false>
 __device__ __forceinline__ void stage2(const StepArgs& a, const StepGeo& G, const double* X, double* Xo,
-                                       const double (*sJ)[6], const double* tab, long long gw,
+                                       const double (*sJ)[EXT ? 12 : 6], const double* tab, long long gw,
                                        long long nw, int lane, long long* fl, I128& T, int& err,
                                        double& emax) {
   const Radial g0 = radial_at(a, G.r0), gm = radial_at(a, G.rm), g1 = radial_at(a, G.r1);
   const Scales sc{a.s1, a.s0, a.p2e1, a.p2e0};
   const double* J[4] = {sJ[0], sJ[1], sJ[2], sJ[3]};
-  const long long nrow = 2LL * a.NU;
-  for (long long row = gw; row < nrow; row += nw) {
-    const int s = (int)(row / a.NU);
-    const int j = (int)(row - (long long)s * a.NU);
-    row2<KIND, ADAPT>(X, Xo, a.plane, row * a.NE, a.NE, s, u_of(j, a.NU), G.h, tab, g0, gm, g1, J, sc,
-                      a.renorm, lane, fl, T, err, emax);
+  if constexpr (EXT) {
+    // rows (s, j, p): species, emission bin, azimuthal bin
+    const double* phi = a.tab + (size_t)4 * a.NE;
+    const long long nrow = 2LL * a.NU * a.NP;
+    for (long long row = gw; row < nrow; row += nw) {
+      const long long sj = row / a.NP;
+      const int p = (int)(row - sj * a.NP);
+      const int s = (int)(sj / a.NU);
+      const int j = (int)(sj - (long long)s * a.NU);
+      row2<KIND, ADAPT, true>(X, Xo, a.plane, row * a.NE, a.NE, s, u_of(j, a.NU), G.h, tab, g0, gm, g1,
+                              J, sc, a.renorm, lane, fl, T, err, emax, phi[p], phi[a.NP + p]);
+    }
+  } else {
+    const long long nrow = 2LL * a.NU;
+    for (long long row = gw; row < nrow; row += nw) {
+      const int s = (int)(row / a.NU);
+      const int j = (int)(row - (long long)s * a.NU);
+      row2<KIND, ADAPT>(X, Xo, a.plane, row * a.NE, a.NE, s, u_of(j, a.NU), G.h, tab, g0, gm, g1, J, sc,
+                        a.renorm, lane, fl, T, err, emax);
+    }
   }
 }
 
@@ -421,33 +450,50 @@ __device__ __forceinline__ Herm3 gen3(int s, const double* v, double lam, const 
 // One (species, emission bin) row of the three-flavour stage, FP64 arithmetic.
 // ADAPT (final update only): the new state goes to Xo instead of X, and emax keeps the
 // largest embedded error estimate |Theta - K2|^2 (traceless part, Frobenius norm).
-template <typename ST, int KIND, bool ADAPT = false>
+// EXT: extended bulb model; rows are (s, j, p) with the azimuth table of the tables.
+template <typename ST, int KIND, bool ADAPT = false, bool EXT = false>
 __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, long long row, double h,
                                      const Radial& g0, const Radial& gm, const Radial& g1,
-                                     const double (*sJ)[16], const double* tab, double* snn, int lane,
-                                     long long* fl, I128& T, int& err, double& emax) {
+                                     const double (*sJ)[EXT ? 32 : 16], const double* tab, double* snn,
+                                     int lane, long long* fl, I128& T, int& err, double& emax) {
+  constexpr int NM = EXT ? 4 : 2;
   const long long plane = a.plane;
   const int NE = a.NE;
-  const int s = (int)(row / a.NU);
-  const int j = (int)(row - (long long)s * a.NU);
-  const RowGeo rg = row_geo(u_of(j, a.NU), h, g0, gm, g1);
+  int s, j;
+  double cp = 0.0, sp = 0.0;
+  if constexpr (EXT) {
+    const long long sj = row / a.NP;
+    const int p = (int)(row - sj * a.NP);
+    s = (int)(sj / a.NU);
+    j = (int)(sj - (long long)s * a.NU);
+    const double* phi = a.tab + (size_t)8 * a.NE;
+    cp = phi[p];
+    sp = phi[a.NP + p];
+  } else {
+    s = (int)(row / a.NU);
+    j = (int)(row - (long long)s * a.NU);
+  }
+  const double u = u_of(j, a.NU);
+  const RowGeo rg = row_geo(u, h, g0, gm, g1);
   const double icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
+  const double sn0 = EXT ? sqrt(u * g0.q2) : 0.0, snm = EXT ? sqrt(u * gm.q2) : 0.0;
+  const double sn1 = EXT ? sqrt(u * g1.q2) : 0.0;
   {
     double t[8];
     if (KIND == 1 || KIND == 2 || KIND == 4) {
-      nunu<8>(sJ[0], g0.mu, rg.c0, t);
+      nunu_row<8, EXT>(sJ[0], g0.mu, rg.c0, sn0, cp, sp, t);
       for (int i = 0; i < 8; ++i) snn[i] = t[i];
     }
     if (KIND == 2 || KIND == 4) {
-      nunu<8>(sJ[1], gm.mu, rg.cm, t);
+      nunu_row<8, EXT>(sJ[1], gm.mu, rg.cm, snm, cp, sp, t);
       for (int i = 0; i < 8; ++i) snn[8 + i] = t[i];
     }
     if (KIND >= 3) {
-      nunu<8>(sJ[2], gm.mu, rg.cm, t);
+      nunu_row<8, EXT>(sJ[2], gm.mu, rg.cm, snm, cp, sp, t);
       for (int i = 0; i < 8; ++i) snn[16 + i] = t[i];
     }
     if (KIND == 4) {
-      nunu<8>(sJ[3], g1.mu, rg.c1, t);
+      nunu_row<8, EXT>(sJ[3], g1.mu, rg.c1, sn1, cp, sp, t);
       for (int i = 0; i < 8; ++i) snn[24 + i] = t[i];
     }
   }
@@ -550,20 +596,22 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
 #pragma unroll
       for (int i = 0; i < 8; ++i) acc[i] += to_fix(w * v8[i], a.s1, kTwo58, err);
     }
-    fold_segment<8>(acc, lane, fl, mine);
+    fold_segment<8, NM>(acc, lane, fl, mine);
   }
-  close_row<8>(Scales{a.s1, a.s0, a.p2e1, a.p2e0}, lane, mine, icmom, T, err);
+  const double snmom = (KIND == 0) ? sn0 : ((KIND <= 2) ? snm : sn1);
+  close_row<8, NM>(Scales{a.s1, a.s0, a.p2e1, a.p2e0}, lane, mine, icmom, T, err, (snmom * icmom) * cp,
+                   (snmom * icmom) * sp);
 }
 
-template <typename ST, int KIND, bool ADAPT = false>
+template <typename ST, int KIND, bool ADAPT = false, bool EXT = false>
 __device__ __forceinline__ void stage3(const StepArgs& a, const StepGeo& G, const ST* X, ST* Xo,
-                                       const double (*sJ)[16], const double* tab, double* snn,
+                                       const double (*sJ)[EXT ? 32 : 16], const double* tab, double* snn,
                                        long long gw, long long nw, int lane, long long* fl, I128& T,
                                        int& err, double& emax) {
   const Radial g0 = radial_at(a, G.r0), gm = radial_at(a, G.rm), g1 = radial_at(a, G.r1);
-  const long long nrow = 2LL * a.NU;
+  const long long nrow = 2LL * a.NU * (EXT ? a.NP : 1);
   for (long long row = gw; row < nrow; row += nw)
-    row3<ST, KIND, ADAPT>(a, X, Xo, row, G.h, g0, gm, g1, sJ, tab, snn, lane, fl, T, err, emax);
+    row3<ST, KIND, ADAPT, EXT>(a, X, Xo, row, G.h, g0, gm, g1, sJ, tab, snn, lane, fl, T, err, emax);
 }
 
 // ------------------------------------------------------- three flavours, mixed precision
@@ -767,10 +815,12 @@ __device__ __forceinline__ void stage3m(const StepArgs& a, const StepGeo& G, con
 // --------------------------------------------------------------- the stepper
 // The energy tables (vacuum terms and weights) are staged into LDS once per launch
 // when TLDS (they are read by every row).
-template <int NF, typename ST, bool TLDS, bool F32>
+// EXT: the extended bulb model (azimuthal bins, four moments); FP64 only.
+template <int NF, typename ST, bool TLDS, bool F32, bool EXT>
 __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   constexpr int NC = (NF == 2) ? 3 : 8;
-  constexpr int NV = 2 * NC;
+  constexpr int NM = EXT ? 4 : 2;
+  constexpr int NV = NM * NC;
   __shared__ double sJ[4][NV];
   __shared__ I128 sw[kBlock / 64][NV];
   __shared__ long long sacc[kBlock];
@@ -803,10 +853,10 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   bool ok = true;
   double enone = 0.0;   // error estimate (adaptive runs only)
   I128 T = i128_zero();
-  if constexpr (NF == 2) stage2<0>(a, geo_fixed(a, step0), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
+  if constexpr (NF == 2) stage2<0, false, EXT>(a, geo_fixed(a, step0), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
   else if constexpr (F32) stage3m<0>(a, geo_fixed(a, step0), sJ, tab, snn, gw, nw, lane, fl, T, err);
-    else stage3<ST, 0>(a, geo_fixed(a, step0), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone);
-  ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[0]);
+    else stage3<ST, 0, false, EXT>(a, geo_fixed(a, step0), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone);
+  ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[0]);
   // the adjoint's forward pass records every stage's moments: [step][slot][NV]
   auto record = [&](long long step, int slot) {
     if (a.Jhist && ok && blockIdx.x == 0 && threadIdx.x < NV)
@@ -815,28 +865,28 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   record(step0, 0);
   for (long long n = step0; ok && n < step0 + nsteps; ++n) {
     T = i128_zero();
-    if constexpr (NF == 2) stage2<1>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
+    if constexpr (NF == 2) stage2<1, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
     else if constexpr (F32) stage3m<1>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err);
-    else stage3<ST, 1>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone);
-    if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[1]))) break;
+    else stage3<ST, 1, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone);
+    if (!(ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[1]))) break;
     record(n, 1);
     T = i128_zero();
-    if constexpr (NF == 2) stage2<2>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
+    if constexpr (NF == 2) stage2<2, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
     else if constexpr (F32) stage3m<2>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err);
-    else stage3<ST, 2>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone);
-    if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[2]))) break;
+    else stage3<ST, 2, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone);
+    if (!(ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[2]))) break;
     record(n, 2);
     T = i128_zero();
-    if constexpr (NF == 2) stage2<3>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
+    if constexpr (NF == 2) stage2<3, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
     else if constexpr (F32) stage3m<3>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err);
-    else stage3<ST, 3>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone);
-    if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[3]))) break;
+    else stage3<ST, 3, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone);
+    if (!(ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[3]))) break;
     record(n, 3);
     T = i128_zero();
-    if constexpr (NF == 2) stage2<4>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
+    if constexpr (NF == 2) stage2<4, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
     else if constexpr (F32) stage3m<4>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err);
-    else stage3<ST, 4>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone);
-    ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[0]);
+    else stage3<ST, 4, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone);
+    ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[0]);
     record(n + 1, 0);
   }
   if (err) __hip_atomic_fetch_or(a.sync + kSyncStatus, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -844,14 +894,18 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   if (ok && blockIdx.x == 0 && threadIdx.x == 0) *a.step_ctl = step0 + nsteps;
 }
 
-template __global__ void k_advance<2, double, true, false>(StepArgs);
-template __global__ void k_advance<2, double, false, false>(StepArgs);
-template __global__ void k_advance<3, double, true, false>(StepArgs);
-template __global__ void k_advance<3, double, false, false>(StepArgs);
-template __global__ void k_advance<3, float, true, false>(StepArgs);
-template __global__ void k_advance<3, float, false, false>(StepArgs);
-template __global__ void k_advance<3, float, true, true>(StepArgs);
-template __global__ void k_advance<3, float, false, true>(StepArgs);
+template __global__ void k_advance<2, double, true, false, false>(StepArgs);
+template __global__ void k_advance<2, double, false, false, false>(StepArgs);
+template __global__ void k_advance<3, double, true, false, false>(StepArgs);
+template __global__ void k_advance<3, double, false, false, false>(StepArgs);
+template __global__ void k_advance<3, float, true, false, false>(StepArgs);
+template __global__ void k_advance<3, float, false, false, false>(StepArgs);
+template __global__ void k_advance<3, float, true, true, false>(StepArgs);
+template __global__ void k_advance<3, float, false, true, false>(StepArgs);
+template __global__ void k_advance<2, double, true, false, true>(StepArgs);
+template __global__ void k_advance<2, double, false, false, true>(StepArgs);
+template __global__ void k_advance<3, double, true, false, true>(StepArgs);
+template __global__ void k_advance<3, double, false, false, true>(StepArgs);
 
 // --------------------------------------------------------------- adaptive step control
 // One persistent launch integrates from r (step_ctl[kCtlR]) with the step length

@@ -129,6 +129,22 @@ __device__ __forceinline__ void nunu(const double* J, double mu, double c, doubl
 #pragma unroll
   for (int i = 0; i < NC; ++i) nn[i] = mu * (J[i] - c * J[NC + i]);
 }
+// Extended bulb model: the azimuthal part of 1 - v.v' adds - sin(theta) (cos(phi) J_sc +
+// sin(phi) J_ss); J = [J0 | J1 | J_sc | J_ss].  The same for every energy bin of the row.
+template <int NC>
+__device__ __forceinline__ void nunu_ext(const double* J, double mu, double c, double sn, double cp,
+                                         double sp, double* nn) {
+#pragma unroll
+  for (int i = 0; i < NC; ++i)
+    nn[i] = mu * ((J[i] - c * J[NC + i]) - sn * (cp * J[2 * NC + i] + sp * J[3 * NC + i]));
+}
+// Row nn terms of either model (EXT: the extended bulb model).
+template <int NC, bool EXT>
+__device__ __forceinline__ void nunu_row(const double* J, double mu, double c, double sn, double cp,
+                                         double sp, double* nn) {
+  if constexpr (EXT) nunu_ext<NC>(J, mu, c, sn, cp, sp, nn);
+  else nunu<NC>(J, mu, c, nn);
+}
 // ----------------------------------------------------------------- two flavours
 // Stage generator f = (h/c) B of beam (s, k) with B = B_vac + lam e_z + nn for
 // neutrinos and B_vac - lam e_z - nn^* (nn^* = (x, -y, z)) for antineutrinos.

@@ -30,10 +30,15 @@ def test_every_declared_symbol_is_exported(nb):
     assert declared == set(nb.EXPORTS)
 
 
-@pytest.mark.parametrize("case", ["2f_small", "3f_small", "2f_batchlike", "3f_800k_shape"])
+@pytest.mark.parametrize("case", ["2f_small", "3f_small", "2f_batchlike", "3f_800k_shape",
+                                  "2f_extended", "3f_extended"])
 def test_host_tables_equal_oracle(nb, oracle, case):
     if case == "2f_small":
         d = workloads.two_flavor_small()
+    elif case == "2f_extended":
+        d = dict(workloads.two_flavor_small(), n_phi=5)
+    elif case == "3f_extended":
+        d = workloads.small_params(n_flavor=3, n_energy=37, n_u=5, n_phi=6)
     elif case == "3f_small":
         d = workloads.small_params(n_flavor=3, n_energy=37, n_u=5)
     elif case == "2f_batchlike":
@@ -53,6 +58,7 @@ def test_host_tables_equal_oracle(nb, oracle, case):
     dict(n_flavor=4), dict(n_energy=0), dict(n_u=0), dict(n_steps=0), dict(r_start_km=5.0),
     dict(r_end_km=10.0), dict(delta_cp=0.1), dict(ne_power=9), dict(e_min_mev=0.0),
     dict(precision=1), dict(temp_mev=[0.0, 1.0, 1.0]), dict(lum_erg_s=[-1.0, 1.0, 1.0]),
+    dict(n_phi=-1), dict(n_phi=5000),
 ])
 def test_invalid_parameters_rejected(nb, bad):
     d = workloads.two_flavor_small()
@@ -60,6 +66,24 @@ def test_invalid_parameters_rejected(nb, bad):
     with pytest.raises(nb.NubulbError) as e:
         nb.HostModel(d)
     assert e.value.code == nb.NB_EINVAL
+
+
+def test_extended_model_mode_checks(nb):
+    """The extended bulb model is a single-model FP64 fixed-step mode."""
+    d = dict(workloads.two_flavor_small(), n_phi=4)
+    nb.HostModel(d)
+    for kw in (dict(adjoint_ckpt=64), dict(adaptive=True)):
+        with pytest.raises(nb.NubulbError) as e:
+            nb.HostModel(d, **kw)
+        assert e.value.code == nb.NB_EINVAL
+    d3 = workloads.small_params(n_flavor=3, n_phi=4)
+    with pytest.raises(nb.NubulbError) as e:
+        nb.HostModel(d3, precision=nb.NB_FP32_STATE)
+    assert e.value.code == nb.NB_EINVAL
+    with pytest.raises(nb.NubulbError) as e:
+        nb.HostModel([d, d])
+    assert e.value.code == nb.NB_EINVAL
+    assert nb.HostModel(d).nb == 2 * 32 * 16 * 4
 
 
 def test_unbound_calls_fail_cleanly(nb):
