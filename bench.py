@@ -243,6 +243,34 @@ def adaptive_timing(nb, workloads):
     return out
 
 
+def extended_timing(nb, workloads):
+    """The extended bulb model (azimuthal bins, four moments) in the shape of the paper's
+    multi-node benchmark: 10 azimuthal x 100 energy x 10k and 30k polar bins x 2 species
+    (20M and 60M two-flavour beams), a prefix of the 10 -> 200 km run timed with HIP
+    events after a short warm-up."""
+    import torch
+    out = {}
+    for n_u, K in ((10000, 20), (30000, 10)):
+        d = workloads.extended_paper(n_u)
+        m = nb.Model(d)
+        m.step(2)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        m.step(K)
+        e1.record()
+        torch.cuda.synchronize()
+        s = e0.elapsed_time(e1) / 1e3
+        out[f"n_u_{n_u}"] = dict(
+            workload=f"2-flavour extended bulb model, 10 phi x 100 E x {n_u} u x 2 = {m.nb} beams",
+            steps=K, ms_per_step=round(s / K * 1e3, 4), beam_steps_per_s=m.nb * K / s,
+            hbm_gbs_algorithmic=round(m.nb * K * bytes_per_beam_step(2, False) / s / 1e9, 1))
+        del m
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(d: dict, seconds: float):
     """The oracle as it stands, on this host's cores, over a bounded prefix of the same
     workload (whole steps of every beam until `seconds` of CPU time have passed)."""
@@ -343,6 +371,9 @@ def main():
         torch.cuda.empty_cache()
         log("adaptive step control (800k beams, 1024-beam literal prefix) ...")
         out["adaptive"] = adaptive_timing(nb, workloads)
+        torch.cuda.empty_cache()
+        log("extended bulb model (20M and 60M beams) ...")
+        out["extended"] = extended_timing(nb, workloads)
     if args.copy_probe:
         n = 1 << 27                      # 2^27 doubles = 1 GiB each way
         src = torch.ones(n, dtype=torch.float64, device="cuda")

@@ -115,6 +115,13 @@ def three_flavor_6m() -> dict:
                        n0_cm3=draw_n0(), **copy.deepcopy(THREE_FLAVOR_MIX))
 
 
+def extended_paper(n_u: int = 10000) -> dict:
+    """The extended bulb model in the shape of the paper's multi-node benchmark: 10
+    azimuthal x 100 energy bins x n_u polar bins (10k-30k there) x 2 species, two flavours;
+    radial grid and physics of the 1024-beam model (10 -> 200 km, 2000 steps)."""
+    return base_params(n_flavor=2, n_energy=100, n_u=n_u, n_phi=10, n0_cm3=draw_n0())
+
+
 def batch_256(n_models: int = 256) -> list[dict]:
     """256 independent 2-flavour models of uneven size, 10 -> 300 km in 5000 steps.
 
