@@ -24,7 +24,7 @@ class Params(C.Structure):
         ("r_start_km", C.c_double), ("r_end_km", C.c_double),
         ("lum_erg_s", C.c_double * 3), ("temp_mev", C.c_double * 3),
         ("dm2_ev2", C.c_double * 2), ("theta", C.c_double * 3), ("delta_cp", C.c_double),
-        ("n0_cm3", C.c_double),
+        ("n0_cm3", C.c_double), ("lum_xbar_erg_s", C.c_double), ("temp_xbar_mev", C.c_double),
     ]
 
 
@@ -95,6 +95,8 @@ def make_params(d: dict, integrator: int = 0, species4: int = 0) -> Params:
     p.integrator = integrator
     p.species4 = species4
     p.n_phi = int(d.get("n_phi", 0))
+    p.lum_xbar_erg_s = float(d.get("lum_xbar_erg_s", 0.0))
+    p.temp_xbar_mev = float(d.get("temp_xbar_mev", 0.0))
     return p
 
 

@@ -391,6 +391,8 @@ int nbo_create(const nbo_params *p, nbo_model **out) {
     return NBO_EINVAL;
   for (int i = 0; i < 3; ++i)
     if (!(p->temp_mev[i] > 0.0) || !(p->lum_erg_s[i] >= 0.0)) return NBO_EINVAL;
+  if (p->temp_xbar_mev != 0.0 && (!(p->temp_xbar_mev > 0.0) || !(p->lum_xbar_erg_s >= 0.0)))
+    return NBO_EINVAL;
   nbo_model *m = (nbo_model *)calloc(1, sizeof(nbo_model));
   m->p = *p;
   m->nf = p->n_flavor;
@@ -439,8 +441,13 @@ int nbo_create(const nbo_params *p, nbo_model **out) {
   m->X = (double *)malloc(sizeof(double) * m->nb * m->nsc);
   m->Y = (double *)malloc(sizeof(double) * m->nb * m->nsc);
   /* number luminosities N = L / <E>, <E> = T F3/F2 (Fermi-Dirac, zero chemical potential) */
-  double N[3];
-  for (int a = 0; a < 3; ++a) N[a] = p->lum_erg_s[a] * ERG_MEV / ((p->temp_mev[a] * F3_0) / F2_0);
+  /* [3]: anti-nu_x, its own spectrum or that of nu_x */
+  double N[4], T[4];
+  for (int a = 0; a < 3; ++a) T[a] = p->temp_mev[a];
+  T[3] = (p->temp_xbar_mev != 0.0) ? p->temp_xbar_mev : p->temp_mev[2];
+  const double Lxb = (p->temp_xbar_mev != 0.0) ? p->lum_xbar_erg_s : p->lum_erg_s[2];
+  for (int a = 0; a < 3; ++a) N[a] = p->lum_erg_s[a] * ERG_MEV / ((T[a] * F3_0) / F2_0);
+  N[3] = Lxb * ERG_MEV / ((T[3] * F3_0) / F2_0);
   /* extended model: the azimuthal average (1/2pi) int dphi' becomes the mean over bins */
   const double pref = m->ext ? ((m->kappa0 * m->du) * m->dE) * (1.0 / (double)m->NP)
                              : (m->kappa0 * m->du) * m->dE;
@@ -450,16 +457,18 @@ int nbo_create(const nbo_params *p, nbo_model **out) {
     const double fe = fermi_dirac(E, p->temp_mev[0]);
     const double fb = fermi_dirac(E, p->temp_mev[1]);
     const double fx = fermi_dirac(E, p->temp_mev[2]);
+    const double fxb = fermi_dirac(E, T[3]);
     if (!p->species4) {
-      /* nu_x-born states are I - rho_e (unitarity), so they enter with -N_x f_x */
+      /* heavy-flavour-born states are I - rho_e (unitarity), so they enter with -N_x f_x
+       * (antineutrinos: -N_xbar f_xbar) */
       m->w[0 * m->NE + k] = pref * (N[0] * fe - N[2] * fx);
-      m->w[1 * m->NE + k] = pref * (N[1] * fb - N[2] * fx);
+      m->w[1 * m->NE + k] = pref * (N[1] * fb - N[3] * fxb);
     } else {
       for (int s = 0; s < m->ns; ++s) {
         const int a = m->anti[s], fl = m->init_flav[s];
         double Nf;
         if (fl == 0) Nf = a ? N[1] * fb : N[0] * fe;
-        else Nf = N[2] * fx;
+        else Nf = a ? N[3] * fxb : N[2] * fx;
         m->w[s * m->NE + k] = pref * Nf;
       }
     }
@@ -1379,7 +1388,9 @@ static void reverse_step(nbo_model *m, const adj_tables *t, const double *X, int
 
 int nbo_adjoint(nbo_model *m, int32_t ckpt, const double *dl_dpee, double *grad, double *loss,
                 double *state_bar) {
-  if (!m || m->nf != 2 || m->p.species4 || m->p.integrator || m->ext || ckpt < 1) return NBO_EINVAL;
+  if (!m || m->nf != 2 || m->p.species4 || m->p.integrator || m->ext || m->p.temp_xbar_mev != 0.0 ||
+      ckpt < 1)
+    return NBO_EINVAL;
   const int64_t n0 = m->step, N = m->p.n_steps;
   const int64_t nseg = (N - n0 + ckpt - 1) / ckpt;
   const int64_t ns = m->nb * 3;

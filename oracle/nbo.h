@@ -44,6 +44,8 @@ typedef struct {
   double theta[3];      /* 2f: [0] = theta_v;  3f: theta_12, theta_13, theta_23 */
   double delta_cp;      /* must be 0 */
   double n0_cm3;
+  double lum_xbar_erg_s, temp_xbar_mev;  /* anti-nu_x (= each heavy antiflavour); temp 0:
+                                            the nu_x values of lum_erg_s[2], temp_mev[2] */
 } nbo_params;
 
 typedef struct nbo_model nbo_model;

@@ -78,6 +78,14 @@ def bins(d):
     return E, dE, u, 1.0 / NU
 
 
+def _n_f_xbar(d, E):
+    """Number luminosity and spectrum of anti-nu_x: its own (lum_xbar_erg_s, temp_xbar_mev)
+    when temp_xbar_mev is set, else those of nu_x."""
+    T = d.get("temp_xbar_mev", 0.0) or d["temp_mev"][2]
+    L = d["lum_xbar_erg_s"] if d.get("temp_xbar_mev", 0.0) else d["lum_erg_s"][2]
+    return L * ERG_MEV / mean_energy(T), spectrum(E, T)
+
+
 def brute_h_nunu(d, r, rho_e, rho_ebar):
     """H_nunu for every (species, angle, energy) beam by the direct pair sum of Eq. Hnu.
 
@@ -94,6 +102,7 @@ def brute_h_nunu(d, r, rho_e, rho_ebar):
     L = d["lum_erg_s"]; T = d["temp_mev"]
     Nnum = [L[a] * ERG_MEV / mean_energy(T[a]) for a in range(3)]
     fe, fb, fx = spectrum(E, T[0]), spectrum(E, T[1]), spectrum(E, T[2])
+    Nxb, fxb = _n_f_xbar(d, E)
     I = np.eye(n)
     cth = np.sqrt(1.0 - u * (R / r) ** 2)
     # number density of the emitted flux per d cos(theta'): L_N/(2 pi R^2 c) at the
@@ -109,7 +118,7 @@ def brute_h_nunu(d, r, rho_e, rho_ebar):
                 Fe = Nnum[0] * fe[kp] * rho_e[jp, kp]
                 Fx = Nnum[2] * fx[kp] * (I - rho_e[jp, kp])          # nu_mu + nu_tau (or nu_x)
                 Fb = Nnum[1] * fb[kp] * rho_ebar[jp, kp]
-                Fbx = Nnum[2] * fx[kp] * (I - rho_ebar[jp, kp])
+                Fbx = Nxb * fxb[kp] * (I - rho_ebar[jp, kp])       # anti-nu_mu + anti-nu_tau
                 F += w * (Fe + Fx - np.conj(Fb + Fbx))
             Hnn[0, j] += pref * geo * F
     Hnn[1] = -np.conj(Hnn[0])

@@ -211,12 +211,14 @@ def test_msw_constant_density_closed_form(oracle, nf):
 
 # -------------------------------------------------- H_nunu (Eqs. Hnu and F)
 @pytest.mark.parametrize("nf", [2, 3])
-def test_factored_hamiltonian_equals_brute_pair_sum(oracle, nf):
+@pytest.mark.parametrize("xbar", [False, True])
+def test_factored_hamiltonian_equals_brute_pair_sum(oracle, nf, xbar):
     """J0/J1 factorisation = direct O(N^2) beam-pair sum of Eq. Hnu with every initial
     flavour explicit; also pins weights, the d cos(theta') Jacobian and the antineutrino
-    conjugation."""
+    conjugation (xbar: anti-nu_x with its own luminosity and temperature)."""
+    kw = dict(lum_xbar_erg_s=2.3e51, temp_xbar_mev=5.1) if xbar else {}
     d = workloads.small_params(n_flavor=nf, n_energy=3, n_u=4, n_steps=10,
-                               r_start_km=10.0, r_end_km=20.0)
+                               r_start_km=10.0, r_end_km=20.0, **kw)
     m = oracle.Model(d)
     rng = np.random.default_rng(21)
     NE, NU, nb = 3, 4, 2 * 3 * 4
@@ -303,13 +305,26 @@ def test_single_angle_equals_one_angle_bin(oracle):
 
 
 @pytest.mark.parametrize("nf", [2, 3])
-def test_two_tracked_species_equal_explicit_species(oracle, nf):
-    d = workloads.small_params(n_flavor=nf, n_energy=5, n_u=3, n_steps=40)
+@pytest.mark.parametrize("xbar", [False, True])
+def test_two_tracked_species_equal_explicit_species(oracle, nf, xbar):
+    """Tracking every initially populated flavour explicitly (the paper's four particles;
+    six for three flavours) gives the electron-born results of the two tracked species, and
+    each heavy-flavour-born state is the complement fixed by unitarity (sum over the flavours
+    of the same particle type = I).  With xbar the anti-nu_x spectrum differs from nu_x."""
+    kw = dict(lum_xbar_erg_s=2.3e51, temp_xbar_mev=5.1) if xbar else {}
+    d = workloads.small_params(n_flavor=nf, n_energy=5, n_u=3, n_steps=40, **kw)
     a = oracle.Model(d); a.run()
     b = oracle.Model(d, species4=1); b.run()
     pa, pb = a.pee(), b.pee()
     np.testing.assert_allclose(pa[0], pb[0], atol=1e-11)        # nu_e-born
     np.testing.assert_allclose(pa[1], pb[nf], atol=1e-11)       # anti-nu_e-born
+    # P_ee summed over the born flavours of one particle type is 1 (columns of a unitary)
+    np.testing.assert_allclose(pb[:nf].sum(axis=0), 1.0, atol=1e-11)
+    np.testing.assert_allclose(pb[nf:].sum(axis=0), 1.0, atol=1e-11)
+    if xbar:
+        c = oracle.Model(workloads.small_params(n_flavor=nf, n_energy=5, n_u=3, n_steps=40))
+        c.run()
+        assert np.abs(c.pee() - pa).max() > 1e-8                # the anti-nu_x spectrum matters
 
 
 # ------------------------------------------------------------------ integrator
