@@ -271,6 +271,31 @@ def extended_timing(nb, workloads):
     return out
 
 
+def track_all_timing(nb, workloads):
+    """Every initially populated flavour tracked explicitly (six species rows for three
+    flavours) with anti-nu_x on its own spectrum, on the 800k-beam 3-flavour shape
+    (400 E x 1000 u x 6 = 2.4M beams): the same per-beam cost as two tracked species is the
+    expectation."""
+    import torch
+    d = dict(workloads.three_flavor_800k(), track_all=1, lum_xbar_erg_s=1e51, temp_xbar_mev=5.5)
+    m = nb.Model(d)
+    m.step(5)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    K = 200
+    e0.record()
+    m.step(K)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3
+    out = dict(workload=f"3-flavour, 400 E x 1000 u x 6 species (every flavour tracked) = {m.nb} beams",
+               steps=K, ms_per_step=round(s / K * 1e3, 4), beam_steps_per_s=m.nb * K / s)
+    del m
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(d: dict, seconds: float):
     """The oracle as it stands, on this host's cores, over a bounded prefix of the same
     workload (whole steps of every beam until `seconds` of CPU time have passed)."""
@@ -374,6 +399,8 @@ def main():
         torch.cuda.empty_cache()
         log("extended bulb model (20M and 60M beams) ...")
         out["extended"] = extended_timing(nb, workloads)
+        log("every flavour tracked (2.4M beams) ...")
+        out["track_all"] = track_all_timing(nb, workloads)
     if args.copy_probe:
         n = 1 << 27                      # 2^27 doubles = 1 GiB each way
         src = torch.ones(n, dtype=torch.float64, device="cuda")

@@ -26,8 +26,9 @@
  *     after checking the kernels' status word, i.e. after the stream has drained, unless
  *     the stream is being captured into a HIP graph (then they return at once).
  *   - beam index b = ((s * n_u + j) * n_phi + p) * n_energy + k, with species s
- *     (0 = nu_e-born, 1 = anti-nu_e-born), emission bin j, azimuthal bin p (n_phi = 1 and
- *     p = 0 for the bulb model) and energy bin k; energy is innermost.
+ *     (0 = nu_e-born, 1 = anti-nu_e-born; with track_all s = anti * n_flavor + flavour of
+ *     birth), emission bin j, azimuthal bin p (n_phi = 1 and p = 0 for the bulb model) and
+ *     energy bin k; energy is innermost.
  *   - layouts of device buffers are plain arrays of double in that beam order.
  *   - errors are checked before any device work is enqueued.
  */
@@ -77,6 +78,13 @@ typedef struct {
   int32_t n_phi;        /* 0: the bulb model.  >= 1: the extended bulb model (Sec. 2, the
                            replacements of Eq. int-v) with n_phi azimuthal bins of equal
                            width over [0, 2 pi); single FP64 models, fixed steps */
+  int32_t track_all;    /* 0: track the nu_e- and anti-nu_e-born beams (heavy-flavour-born
+                           states follow from unitarity); 1: track every initially populated
+                           flavour explicitly (the paper's four particles, six for three
+                           flavours); single models without adjoint */
+  int32_t reserved;     /* must be 0 */
+  double lum_xbar_erg_s;/* anti-nu_x (each heavy antiflavour) luminosity and temperature; */
+  double temp_xbar_mev; /* temp_xbar_mev = 0: the nu_x values lum_erg_s[2], temp_mev[2] */
 } nb_params;
 
 typedef struct nb_model nb_model;
@@ -180,7 +188,7 @@ typedef struct {
 int nb_run_adaptive(nb_model *m, double tol, double h_max_km, int64_t max_attempts,
                     nb_adaptive_stats *stats);
 
-/* Host tables (no device work), layout as [E_k | weights[2][NE] | vacuum terms |
+/* Host tables (no device work), layout as [E_k | weights[n_species][NE] | vacuum terms |
  * lam0, kappa0, h, 2^-e1, 2^-e0, e1, e0]; vacuum terms are (B_x, B_z) per k for 2f and
  * 6 entries per k (H_ee, H_mm, H_tt, H_em, H_et, H_mt) for 3f.  Single models only. */
 int nb_host_tables(const nb_model *m, double *out, int64_t cap);

@@ -37,6 +37,8 @@ class Params(C.Structure):
         ("lum_erg_s", C.c_double * 3), ("temp_mev", C.c_double * 3),
         ("dm2_ev2", C.c_double * 2), ("theta", C.c_double * 3), ("delta_cp", C.c_double),
         ("n0_cm3", C.c_double), ("adaptive", C.c_int32), ("n_phi", C.c_int32),
+        ("track_all", C.c_int32), ("reserved", C.c_int32), ("lum_xbar_erg_s", C.c_double),
+        ("temp_xbar_mev", C.c_double),
     ]
 
 
@@ -110,6 +112,9 @@ def make_params(d: dict, precision: int | None = None, adjoint_ckpt: int = 0,
     p.max_blocks = int(d.get("max_blocks", max_blocks))
     p.adaptive = int(bool(adaptive))
     p.n_phi = int(d.get("n_phi", 0))
+    p.track_all = int(d.get("track_all", 0))
+    p.lum_xbar_erg_s = float(d.get("lum_xbar_erg_s", 0.0))
+    p.temp_xbar_mev = float(d.get("temp_xbar_mev", 0.0))
     for k in ("n_flavor", "n_energy", "n_u", "ne_power", "renorm", "n_steps"):
         setattr(p, k, int(d[k]))
     p.precision = int(d.get("precision", 0) if precision is None else precision)
@@ -180,13 +185,14 @@ class HostModel:
         import numpy as np
         ne = int(self.d["n_energy"])
         nv = 2 if self.nf == 2 else 6
-        n = ne + 2 * ne + nv * ne + 7
+        ns = 2 * self.nf if self.d.get("track_all", 0) else 2
+        n = ne + ns * ne + nv * ne + 7
         out = np.empty(n, np.float64)
         _check(lib().nb_host_tables(self.h, out.ctypes.data_as(C.POINTER(C.c_double)), n),
                "nb_host_tables")
         o = 0
         E = out[o:o + ne]; o += ne
-        w = out[o:o + 2 * ne].reshape(2, ne); o += 2 * ne
+        w = out[o:o + ns * ne].reshape(ns, ne); o += ns * ne
         bv = out[o:o + nv * ne].reshape(ne, nv); o += nv * ne
         lam0, kappa0, h, p2e1, p2e0, e1, e0 = out[o:o + 7]
         return dict(E=E, w=w, bv=bv, lam0=lam0, kappa0=kappa0, h=h, p2e1=p2e1, p2e0=p2e0,

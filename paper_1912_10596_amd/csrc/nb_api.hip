@@ -27,7 +27,7 @@ __global__ void k_zero_u64(unsigned long long* p, long long n);
 __global__ void k_set_step(long long* step_ctl, long long step);
 __global__ void k_set_target(long long* step_ctl, long long k, long long total);
 template <typename ST>
-__global__ void k_init(ST* X, long long nb, long long plane, int nsc);
+__global__ void k_init(ST* X, long long nb, long long plane, int nsc, long long per_species, int nfl);
 template <typename ST>
 __global__ void k_read_pee(const ST* X, long long nb, long long plane, int nsc, double* out);
 template <typename ST>
@@ -82,6 +82,7 @@ static double fd_spectrum(double E, double T) {  // normalised Fermi-Dirac, zero
 struct Sub {
   nb_params p{};
   long long NE = 0, NU = 0, NP = 1, beam0 = 0, row0 = 0, tab0 = 0;  // NP: azimuthal bins
+  int NS = 2;                        // species rows: 2, or 2 n_flavor when every flavour is tracked
   double h = 0, lam0 = 0, kappa0 = 0, s1 = 0, s0 = 0, p2e1 = 0, p2e0 = 0;
   double vac_max = 0;                // max over energy bins of sum |H_vac entries|
   long long fp32_from = 0;           // mixed precision: first step run with FP32 arithmetic
@@ -147,9 +148,16 @@ static int validate(const nb_params* p) {
   if (p->adaptive != 0 && p->adaptive != 1) return fail(NB_EINVAL, "adaptive must be 0 or 1");
   if (p->adaptive && p->precision != NB_FP64) return fail(NB_EINVAL, "adaptive stepping is an FP64 mode");
   if (p->n_phi < 0 || p->n_phi > 4096) return fail(NB_EINVAL, "n_phi must be in 0..4096");
+  if (p->track_all != 0 && p->track_all != 1) return fail(NB_EINVAL, "track_all must be 0 or 1");
+  if (p->reserved != 0) return fail(NB_EINVAL, "reserved must be 0");
+  if (p->temp_xbar_mev != 0.0 && (!(p->temp_xbar_mev > 0.0) || !(p->lum_xbar_erg_s >= 0.0)))
+    return fail(NB_EINVAL, "anti-nu_x temperature must be > 0 (or 0) and luminosity >= 0");
+  if (p->adjoint_ckpt > 0 && (p->track_all || p->temp_xbar_mev != 0.0))
+    return fail(NB_EINVAL, "the adjoint takes anti-nu_x = nu_x and two tracked species");
   if (p->n_phi > 0 && (p->precision != NB_FP64 || p->adjoint_ckpt != 0 || p->adaptive != 0))
     return fail(NB_EINVAL, "the extended bulb model is an FP64 fixed-step mode without adjoint");
-  if ((long long)p->n_energy * p->n_u * (p->n_phi > 0 ? p->n_phi : 1) > (1LL << 34))
+  if ((long long)p->n_energy * p->n_u * (p->n_phi > 0 ? p->n_phi : 1) *
+          (p->track_all ? p->n_flavor : 1) > (1LL << 34))
     return fail(NB_EINVAL, "too many beams");
   return NB_OK;
 }
@@ -168,21 +176,27 @@ static void build_tables(Sub* m) {
   m->lam0 = s2gf * p.n0_cm3;
   const double rcm = p.r_nu_km * 1.0e5;
   m->kappa0 = s2gf / (((2.0 * kPi) * (rcm * rcm)) * kClight);
-  double N[3];
-  for (int a = 0; a < 3; ++a) N[a] = p.lum_erg_s[a] * kErgMeV / ((p.temp_mev[a] * kFD3) / kFD2);
+  // [3]: anti-nu_x, with its own spectrum or that of nu_x
+  double N[4], T[4];
+  for (int a = 0; a < 3; ++a) T[a] = p.temp_mev[a];
+  T[3] = (p.temp_xbar_mev != 0.0) ? p.temp_xbar_mev : p.temp_mev[2];
+  const double Lxb = (p.temp_xbar_mev != 0.0) ? p.lum_xbar_erg_s : p.lum_erg_s[2];
+  for (int a = 0; a < 3; ++a) N[a] = p.lum_erg_s[a] * kErgMeV / ((T[a] * kFD3) / kFD2);
+  N[3] = Lxb * kErgMeV / ((T[3] * kFD3) / kFD2);
   // extended model: the azimuthal average (1/2pi) int dphi' becomes the mean over the bins
   const bool ext = p.n_phi > 0;
   const double pref = ext ? ((m->kappa0 * du) * dE) * (1.0 / (double)m->NP) : (m->kappa0 * du) * dE;
   const int nv = (m->nf == 2) ? 2 : 6;
   m->E.assign(NE, 0.0);
-  // tables: [vacuum terms (nv) | G0 | G1] x NE, then (extended) cos and sin of the azimuth
-  // of every azimuthal bin
-  m->tab.assign((size_t)(nv + 2) * NE + (ext ? (size_t)2 * m->NP : 0), 0.0);
+  // tables: [vacuum terms (nv) | weights G_s of the NS species rows] x NE, then (extended)
+  // cos and sin of the azimuth of every azimuthal bin
+  const int NS = m->NS;
+  m->tab.assign((size_t)(nv + NS) * NE + (ext ? (size_t)2 * m->NP : 0), 0.0);
   if (ext) {
     // bin midpoints phi_p = 2 pi (p + 1/2) / n_phi; for even n_phi the second half is the
     // first turned by pi with exactly flipped signs (azimuthal sums of an axially
     // symmetric state then vanish exactly)
-    double* cp = m->tab.data() + (size_t)(nv + 2) * NE;
+    double* cp = m->tab.data() + (size_t)(nv + NS) * NE;
     double* sp = cp + m->NP;
     for (long long q = 0; q < m->NP; ++q) {
       if (m->NP % 2 == 0 && q >= m->NP / 2) {
@@ -214,9 +228,20 @@ static void build_tables(Sub* m) {
     const double fe = fd_spectrum(e, p.temp_mev[0]);
     const double fb = fd_spectrum(e, p.temp_mev[1]);
     const double fx = fd_spectrum(e, p.temp_mev[2]);
-    // heavy-flavour-born states are I - rho_e (unitarity): they enter with -N_x f_x
-    G0[k] = pref * (N[0] * fe - N[2] * fx);
-    G1[k] = pref * (N[1] * fb - N[2] * fx);
+    const double fxb = fd_spectrum(e, T[3]);
+    if (NS == 2) {
+      // heavy-flavour-born states are I - rho_e (unitarity): they enter with -N_x f_x
+      // (antineutrinos: -N_xbar f_xbar)
+      G0[k] = pref * (N[0] * fe - N[2] * fx);
+      G1[k] = pref * (N[1] * fb - N[3] * fxb);
+    } else {
+      // every flavour tracked: species row s = anti * nf + flavour of birth
+      for (int sp = 0; sp < NS; ++sp) {
+        const int anti = sp / m->nf, fl = sp % m->nf;
+        const double Nf = (fl == 0) ? (anti ? N[1] * fb : N[0] * fe) : (anti ? N[3] * fxb : N[2] * fx);
+        G0[(size_t)sp * NE + k] = pref * Nf;
+      }
+    }
     if (m->nf == 2) {
       const double om = (kVac * p.dm2_ev2[0]) / e;
       const double s2 = std::sin(2.0 * p.theta[0]), c2 = std::cos(2.0 * p.theta[0]);
@@ -252,7 +277,7 @@ static void build_tables(Sub* m) {
   // them in a signed 64-bit integer; every angle term of J0, (energy sum / cos) 2^e0,
   // stays below 2^62 (cos is smallest at r_start, u_max)
   double wmax = 0.0;
-  for (long long k = 0; k < NE; ++k) wmax = std::max(wmax, std::max(std::fabs(G0[k]), std::fabs(G1[k])));
+  for (long long i = 0; i < (long long)NS * NE; ++i) wmax = std::max(wmax, std::fabs(G0[i]));
   if (!(wmax > 0.0)) wmax = 1.0;
   int ex = 0;
   std::frexp(wmax, &ex);
@@ -276,7 +301,7 @@ static void build_tables(Sub* m) {
   m->fp32_from = p.n_steps;
   if (m->nf == 3) {
     double gsum = 0.0;
-    for (long long k = 0; k < NE; ++k) gsum += std::fabs(G0[k]) + std::fabs(G1[k]);
+    for (long long i = 0; i < (long long)NS * NE; ++i) gsum += std::fabs(G0[i]);
     gsum *= (double)m->NU;
     long long last_bad = -1;
     for (long long n = 0; n < p.n_steps; ++n) {
@@ -300,6 +325,7 @@ static int make_sub(const nb_params* p, Sub* s) {
   s->NE = p->n_energy;
   s->NU = p->n_u;
   s->NP = (p->n_phi > 0) ? p->n_phi : 1;
+  s->NS = p->track_all ? 2 * p->n_flavor : 2;
   build_tables(s);
   return NB_OK;
 }
@@ -321,8 +347,8 @@ static void finish_layout_host(nb_model* m) {
     s.beam0 = beam;
     s.row0 = row;
     s.tab0 = t;
-    beam += 2LL * s.NE * s.NU * s.NP;
-    row += 2LL * s.NU * s.NP;
+    beam += (long long)s.NS * s.NE * s.NU * s.NP;
+    row += (long long)s.NS * s.NU * s.NP;
     t += (long long)s.tab.size();
     m->tab.insert(m->tab.end(), s.tab.begin(), s.tab.end());
   }
@@ -358,6 +384,7 @@ extern "C" int nb_batch_create(const nb_params* p, int32_t n_models, nb_model** 
     if (q.adjoint_ckpt != 0) return fail(NB_EINVAL, "batched models have no adjoint (model %d)", i);
     if (q.adaptive != 0) return fail(NB_EINVAL, "batched models step on a fixed grid (model %d)", i);
     if (q.n_phi != 0) return fail(NB_EINVAL, "batched models are bulb models (model %d)", i);
+    if (q.track_all != 0) return fail(NB_EINVAL, "batched models track two species (model %d)", i);
     if (q.n_steps != p[0].n_steps || q.r_start_km != p[0].r_start_km || q.r_end_km != p[0].r_end_km ||
         q.r_nu_km != p[0].r_nu_km || q.ne_power != p[0].ne_power || q.renorm != p[0].renorm)
       return fail(NB_EINVAL, "batched models must share the radial grid, R, ne_power and renorm (model %d)", i);
@@ -531,7 +558,12 @@ extern "C" int nb_reset(nb_model* m) {
   void* X = m->ws + m->off_X;
   long long nb_ = m->nb, plane = m->plane;
   int nsc = m->nsc;
-  void* args[] = {&X, &nb_, &plane, &nsc};
+  // flavour of birth: species row s of a single model = anti * (NS/2) + flavour; batches and
+  // two tracked species are all electron-born
+  const Sub& s0 = m->subs[0];
+  long long per_species = m->batch ? m->nb : s0.NE * s0.NU * s0.NP;
+  int nfl = m->batch ? 1 : s0.NS / 2;
+  void* args[] = {&X, &nb_, &plane, &nsc, &per_species, &nfl};
   int rc = launch_1d(state_fp32(m) ? (const void*)&k_init<float> : (const void*)&k_init<double>,
                      m->nb, args, m->stream);
   if (rc) return rc;
@@ -754,6 +786,7 @@ static int enqueue_advance(nb_model* m, long long k) {
   a.NE = (int)s.NE;
   a.NU = (int)s.NU;
   a.NP = (int)s.NP;
+  a.NS = s.NS;
   a.nsteps = k;
   a.total_steps = m->p.n_steps;
   a.rs = m->p.r_start_km;
@@ -861,6 +894,7 @@ extern "C" int nb_run_adaptive(nb_model* m, double tol, double h_max_km, int64_t
   a.NE = (int)s.NE;
   a.NU = (int)s.NU;
   a.NP = 1;
+  a.NS = s.NS;
   a.nsteps = m->p.n_steps;
   a.total_steps = m->p.n_steps;
   a.rs = m->p.r_start_km;
@@ -1157,11 +1191,11 @@ extern "C" int nb_host_tables(const nb_model* m, double* out, int64_t cap) {
   const Sub& s = m->subs[0];
   const int nv = (m->nf == 2) ? 2 : 6;
   const long long NE = s.NE;
-  const long long need = NE + 2 * NE + nv * NE + 7;
+  const long long need = NE + (long long)s.NS * NE + nv * NE + 7;
   if (cap < need) return fail(NB_EINVAL, "output too small (%lld needed)", need);
   long long o = 0;
   for (long long k = 0; k < NE; ++k) out[o++] = s.E[k];
-  for (int sp = 0; sp < 2; ++sp)
+  for (int sp = 0; sp < s.NS; ++sp)
     for (long long k = 0; k < NE; ++k) out[o++] = s.tab[(size_t)(nv + sp) * NE + k];
   for (long long k = 0; k < NE; ++k)
     for (int q = 0; q < nv; ++q) out[o++] = s.tab[(size_t)q * NE + k];

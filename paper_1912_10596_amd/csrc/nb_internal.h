@@ -32,7 +32,7 @@ constexpr int kBlock = 512;       // threads per block of the stepping kernels (
 // Arguments of the single-model stepping kernel (passed by value).
 struct StepArgs {
   void* X;                 // state planes [nsc][plane] (double, or float for FP32 state)
-  const double* tab;       // tables: 2f [bx|bz|G0|G1] x NE; 3f [h_ee..h_mt (6)|G0|G1] x NE;
+  const double* tab;       // tables: 2f [bx|bz|G_0..G_{NS-1}] x NE; 3f [h_ee..h_mt (6)|G_s] x NE;
                            // extended model: then cos, sin of every azimuthal bin
   unsigned int* sync;      // kSyncWords words (barrier words and the tagged reduction words)
   long long* step_ctl;     // [0] device step counter (read at launch start, advanced at the
@@ -40,6 +40,8 @@ struct StepArgs {
   long long plane;         // plane stride (elements)
   int NE, NU;
   int NP;                  // azimuthal bins (extended bulb model; 1 for the bulb model)
+  int NS;                  // species rows: 2 (nu_e-, anti-nu_e-born) or 2 n_flavor (every
+                           // flavour tracked; row s = anti * n_flavor + flavour of birth)
   long long nsteps, total_steps;  // requested steps (clamped to total_steps - start)
   double rs, h, R, lam0;
   int ne_power, renorm;

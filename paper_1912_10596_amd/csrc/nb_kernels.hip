@@ -307,8 +307,11 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
                                      int s, double u, double h, const double* tab, const Radial& g0,
                                      const Radial& gm, const Radial& g1, const double* const* J,
                                      const Scales& sc, int renorm, int lane, long long* fl, I128& T,
-                                     int& err, double& emax, double cp = 0.0, double sp = 0.0) {
+                                     int& err, double& emax, double cp = 0.0, double sp = 0.0,
+                                     int an = -1) {
   constexpr int NM = EXT ? 4 : 2;
+  // species row s, antiparticle flag an (default: s itself, two tracked species)
+  if (an < 0) an = s;
   const RowGeo rg = row_geo(u, h, g0, gm, g1);
   const double icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
   // sin(theta) at the three stage radii (sin(theta) r = sin(theta_R) R)
@@ -336,23 +339,23 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
       if (KIND >= 1) {
         const double bx = tab[k], bz = tab[NE + k];
         double f1[3], f2[3], f3[3], f4[3];
-        if (KIND != 3) gen2(s, bx, bz, g0.lam, n1, rg.hc0, f1);
+        if (KIND != 3) gen2(an, bx, bz, g0.lam, n1, rg.hc0, f1);
         if (KIND == 1) {
           rotate2(0.5 * f1[0], 0.5 * f1[1], 0.5 * f1[2], P0, P1, P2);
         } else if (KIND == 2) {
-          gen2(s, bx, bz, gm.lam, n2, rg.hcm, f2);
+          gen2(an, bx, bz, gm.lam, n2, rg.hcm, f2);
           const double cr0 = f1[1] * f2[2] - f1[2] * f2[1];
           const double cr1 = f1[2] * f2[0] - f1[0] * f2[2];
           const double cr2 = f1[0] * f2[1] - f1[1] * f2[0];
           rotate2(0.5 * f2[0] - 0.125 * cr0, 0.5 * f2[1] - 0.125 * cr1, 0.5 * f2[2] - 0.125 * cr2,
                   P0, P1, P2);
         } else if (KIND == 3) {
-          gen2(s, bx, bz, gm.lam, n3, rg.hcm, f3);
+          gen2(an, bx, bz, gm.lam, n3, rg.hcm, f3);
           rotate2(f3[0], f3[1], f3[2], P0, P1, P2);
         } else {
-          gen2(s, bx, bz, gm.lam, n2, rg.hcm, f2);
-          gen2(s, bx, bz, gm.lam, n3, rg.hcm, f3);
-          gen2(s, bx, bz, g1.lam, n4, rg.hc1, f4);
+          gen2(an, bx, bz, gm.lam, n2, rg.hcm, f2);
+          gen2(an, bx, bz, gm.lam, n3, rg.hcm, f3);
+          gen2(an, bx, bz, g1.lam, n4, rg.hc1, f4);
           const double cr0 = f1[1] * f4[2] - f1[2] * f4[1];
           const double cr1 = f1[2] * f4[0] - f1[0] * f4[2];
           const double cr2 = f1[0] * f4[1] - f1[1] * f4[0];
@@ -379,7 +382,7 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
       }
       // rho~: rho for neutrinos, -rho^* (Bloch (-x, y, -z)) for antineutrinos
       const double w = G[k];
-      const double v0 = s ? -P0 : P0, v2 = s ? -P2 : P2;
+      const double v0 = an ? -P0 : P0, v2 = an ? -P2 : P2;
       acc[0] += to_fix(w * v0, sc.s1, kTwo58, err);
       acc[1] += to_fix(w * P1, sc.s1, kTwo58, err);
       acc[2] += to_fix(w * v2, sc.s1, kTwo58, err);
@@ -400,23 +403,24 @@ __device__ __forceinline__ void stage2(const StepArgs& a, const StepGeo& G, cons
   const double* J[4] = {sJ[0], sJ[1], sJ[2], sJ[3]};
   if constexpr (EXT) {
     // rows (s, j, p): species, emission bin, azimuthal bin
-    const double* phi = a.tab + (size_t)4 * a.NE;
-    const long long nrow = 2LL * a.NU * a.NP;
+    const double* phi = a.tab + (size_t)(2 + a.NS) * a.NE;
+    const long long nrow = (long long)a.NS * a.NU * a.NP;
     for (long long row = gw; row < nrow; row += nw) {
       const long long sj = row / a.NP;
       const int p = (int)(row - sj * a.NP);
       const int s = (int)(sj / a.NU);
       const int j = (int)(sj - (long long)s * a.NU);
       row2<KIND, ADAPT, true>(X, Xo, a.plane, row * a.NE, a.NE, s, u_of(j, a.NU), G.h, tab, g0, gm, g1,
-                              J, sc, a.renorm, lane, fl, T, err, emax, phi[p], phi[a.NP + p]);
+                              J, sc, a.renorm, lane, fl, T, err, emax, phi[p], phi[a.NP + p],
+                              s >= (a.NS >> 1));
     }
   } else {
-    const long long nrow = 2LL * a.NU;
+    const long long nrow = (long long)a.NS * a.NU;
     for (long long row = gw; row < nrow; row += nw) {
       const int s = (int)(row / a.NU);
       const int j = (int)(row - (long long)s * a.NU);
       row2<KIND, ADAPT>(X, Xo, a.plane, row * a.NE, a.NE, s, u_of(j, a.NU), G.h, tab, g0, gm, g1, J, sc,
-                        a.renorm, lane, fl, T, err, emax);
+                        a.renorm, lane, fl, T, err, emax, 0.0, 0.0, s >= (a.NS >> 1));
     }
   }
 }
@@ -466,13 +470,14 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
     const int p = (int)(row - sj * a.NP);
     s = (int)(sj / a.NU);
     j = (int)(sj - (long long)s * a.NU);
-    const double* phi = a.tab + (size_t)8 * a.NE;
+    const double* phi = a.tab + (size_t)(6 + a.NS) * a.NE;
     cp = phi[p];
     sp = phi[a.NP + p];
   } else {
     s = (int)(row / a.NU);
     j = (int)(row - (long long)s * a.NU);
   }
+  const int an = (s >= (a.NS >> 1)) ? 1 : 0;   // antiparticle row
   const double u = u_of(j, a.NU);
   const RowGeo rg = row_geo(u, h, g0, gm, g1);
   const double icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
@@ -521,11 +526,11 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
 #pragma unroll
         for (int c = 0; c < 6; ++c) v[c] = tab[c * NE + k];
         Herm3 K1;
-        if (KIND != 3) K1 = gen3(s, v, g0.lam, snn, rg.hc0);
+        if (KIND != 3) K1 = gen3(an, v, g0.lam, snn, rg.hc0);
         if (KIND == 1) {
           exp3_apply(hscale(0.5, K1), ps);
         } else if (KIND == 2) {
-          const Herm3 K2 = gen3(s, v, gm.lam, snn + 8, rg.hcm);
+          const Herm3 K2 = gen3(an, v, gm.lam, snn + 8, rg.hcm);
           const Herm3 C = icomm(K1, K2);
           Herm3 O;
           O.d0 = 0.5 * K2.d0 + 0.125 * C.d0;
@@ -536,14 +541,14 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
           O.o12 = mk(0.5 * K2.o12.re + 0.125 * C.o12.re, 0.5 * K2.o12.im + 0.125 * C.o12.im);
           exp3_apply(O, ps);
         } else if (KIND == 3) {
-          exp3_apply(gen3(s, v, gm.lam, snn + 16, rg.hcm), ps);
+          exp3_apply(gen3(an, v, gm.lam, snn + 16, rg.hcm), ps);
         } else {
           // Theta = (((K1 + 2 K2) + 2 K3) + K4)/6 + i[K1,K4]/12, accumulated in that order
           Herm3 acc3 = K1;
-          const Herm3 K2 = gen3(s, v, gm.lam, snn + 8, rg.hcm);
+          const Herm3 K2 = gen3(an, v, gm.lam, snn + 8, rg.hcm);
           haxpy(acc3, 2.0, K2);
-          haxpy(acc3, 2.0, gen3(s, v, gm.lam, snn + 16, rg.hcm));
-          const Herm3 K4 = gen3(s, v, g1.lam, snn + 24, rg.hc1);
+          haxpy(acc3, 2.0, gen3(an, v, gm.lam, snn + 16, rg.hcm));
+          const Herm3 K4 = gen3(an, v, g1.lam, snn + 24, rg.hc1);
           hadd(acc3, K4);
           const Herm3 C = icomm(K1, K4);
           Herm3 Th;
@@ -589,7 +594,7 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
       const double n0 = norm2(ps[0]), nm = norm2(ps[1]), nt = norm2(ps[2]);
       const cplx em = cmul_conjb(ps[0], ps[1]), et = cmul_conjb(ps[0], ps[2]), mt = cmul_conjb(ps[1], ps[2]);
       double v8[8] = {n0 - nt, nm - nt, em.re, em.im, et.re, et.im, mt.re, mt.im};
-      if (s) {
+      if (an) {
         v8[0] = -v8[0]; v8[1] = -v8[1]; v8[2] = -v8[2]; v8[4] = -v8[4]; v8[6] = -v8[6];
       }
       const double w = G[k];
@@ -609,7 +614,7 @@ __device__ __forceinline__ void stage3(const StepArgs& a, const StepGeo& G, cons
                                        long long gw, long long nw, int lane, long long* fl, I128& T,
                                        int& err, double& emax) {
   const Radial g0 = radial_at(a, G.r0), gm = radial_at(a, G.rm), g1 = radial_at(a, G.r1);
-  const long long nrow = 2LL * a.NU * (EXT ? a.NP : 1);
+  const long long nrow = (long long)a.NS * a.NU * (EXT ? a.NP : 1);
   for (long long row = gw; row < nrow; row += nw)
     row3<ST, KIND, ADAPT, EXT>(a, X, Xo, row, G.h, g0, gm, g1, sJ, tab, snn, lane, fl, T, err, emax);
 }
@@ -655,6 +660,7 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
   const int NE = a.NE;
   float* X = (float*)a.X;
   const int s = (int)(row / a.NU);
+  const int an = (s >= (a.NS >> 1)) ? 1 : 0;   // antiparticle row
   const double icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
   const float hc0 = (float)rg.hc0, hcm = (float)rg.hcm, hc1 = (float)rg.hc1;
   {
@@ -692,7 +698,7 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
       snd[0] = (((w[0] + w[1]) + w[2]) + w[3]) * (1.0 / 6.0);
       for (int c = 0; c < 8; ++c) {
         // antineutrinos: H_vac - lam E_ee - nn^*, i.e. real parts negated, imaginary kept
-        const bool keep = (s == 0) || (c == 3) || (c == 5) || (c == 7);
+        const bool keep = (an == 0) || (c == 3) || (c == 5) || (c == 7);
         snd[1 + c] = (keep ? cs[c] : -cs[c]) * (1.0 / 6.0);
       }
     }
@@ -725,24 +731,24 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
           v[c] = (float)vd[c];
         }
         Herm3f K1;
-        if (KIND != 3) K1 = gen3f(s, v, lam0f, snn, hc0);
+        if (KIND != 3) K1 = gen3f(an, v, lam0f, snn, hc0);
         if (KIND == 1) {
           exp3_apply_f(hscalef(0.5f, K1), ps);
         } else if (KIND == 2) {
-          const Herm3f K2 = gen3f(s, v, lammf, snn + 8, hcm);
+          const Herm3f K2 = gen3f(an, v, lammf, snn + 8, hcm);
           const Herm3f C = icommf(K1, K2);
           Herm3f O = hscalef(0.5f, K2);
           haxpyf(O, 0.125f, C);
           exp3_apply_f(O, ps);
         } else if (KIND == 3) {
-          exp3_apply_f(gen3f(s, v, lammf, snn + 16, hcm), ps);
+          exp3_apply_f(gen3f(an, v, lammf, snn + 16, hcm), ps);
         } else {
           // Theta = (K1 + 2 K2 + 2 K3 + K4)/6 + i[K1,K4]/12.  The generators are nearly
           // constant from step to step (the vacuum term is), so rounding them to FP32 would
           // repeat the same phase error every step; their weighted sum is formed in FP64
           // from the row constants and rounded once.  The commutator, of order |K|^2 h/r,
           // is FP32.
-          const Herm3f C = icommf(K1, gen3f(s, v, lam1f, snn + 24, hc1));
+          const Herm3f C = icommf(K1, gen3f(an, v, lam1f, snn + 24, hc1));
           const double A = snd[0];
           auto th_of = [](double sum, float cm) { return (float)fma((double)cm, 1.0 / 12.0, sum); };
           Herm3f Th;
@@ -779,7 +785,7 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
       const double n0 = norm2(p0), nm = norm2(p1), nt = norm2(p2);
       const cplx em = cmul_conjb(p0, p1), et = cmul_conjb(p0, p2), mt = cmul_conjb(p1, p2);
       double v8[8] = {n0 - nt, nm - nt, em.re, em.im, et.re, et.im, mt.re, mt.im};
-      if (s) {
+      if (an) {
         v8[0] = -v8[0]; v8[1] = -v8[1]; v8[2] = -v8[2]; v8[4] = -v8[4]; v8[6] = -v8[6];
       }
       const double w = G[k];
@@ -803,7 +809,7 @@ __device__ __forceinline__ void stage3m(const StepArgs& a, const StepGeo& G, con
                                         const double* tab, double* snn, long long gw, long long nw,
                                         int lane, long long* fl, I128& T, int& err) {
   const Radial g0 = radial_at(a, G.r0), gm = radial_at(a, G.rm), g1 = radial_at(a, G.r1);
-  const long long nrow = 2LL * a.NU;
+  const long long nrow = (long long)a.NS * a.NU;
   for (long long row = gw; row < nrow; row += nw) {
     const int s = (int)(row / a.NU);
     const int j = (int)(row - (long long)s * a.NU);
@@ -832,7 +838,7 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   const long long nw = (long long)gridDim.x * (kBlock / 64);
   const double* tab = a.tab;
   if constexpr (TLDS) {
-    const int ntab = ((NF == 2) ? 4 : 8) * a.NE;
+    const int ntab = ((NF == 2) ? 2 : 6) * a.NE + a.NS * a.NE;
     for (int i = threadIdx.x; i < ntab; i += kBlock) dyn_tab[i] = a.tab[i];
     __syncthreads();
     tab = dyn_tab;
@@ -933,7 +939,7 @@ __global__ void __launch_bounds__(kBlock) k_adaptive(StepArgs a) {
   const long long nw = (long long)gridDim.x * (kBlock / 64);
   const double* tab = a.tab;
   if constexpr (TLDS) {
-    const int ntab = ((NF == 2) ? 4 : 8) * a.NE;
+    const int ntab = ((NF == 2) ? 2 : 6) * a.NE + a.NS * a.NE;
     for (int i = threadIdx.x; i < ntab; i += kBlock) dyn_tab[i] = a.tab[i];
     __syncthreads();
     tab = dyn_tab;
@@ -1010,7 +1016,7 @@ __global__ void __launch_bounds__(kBlock) k_adaptive(StepArgs a) {
     // the accepted state sits in the second buffer: copy this wavefront's rows back
     constexpr int nsc = (NF == 2) ? 3 : 6;
     double* D = (double*)a.X;
-    for (long long row = gw; row < 2LL * a.NU; row += nw)
+    for (long long row = gw; row < (long long)a.NS * a.NU; row += nw)
       for (int k = lane; k < a.NE; k += 64)
 #pragma unroll
         for (int c = 0; c < nsc; ++c) D[row * a.NE + k + c * a.plane] = X[row * a.NE + k + c * a.plane];
@@ -1186,18 +1192,23 @@ __global__ void k_zero_sync(unsigned int* sync, int keep_status) {
     if (!(keep_status && i == kSyncStatus)) sync[i] = 0u;
 }
 
-// Initial flavour eigenstates (Sec. 3.4): 2f P = (0,0,1); 3f psi = (1,0,0).
+// Initial flavour eigenstates (Sec. 3.4): species row s = b / per_species is born in
+// flavour s % nfl (nfl = 1 when only electron-born beams are tracked); 2f: P = (0, 0, +-1),
+// 3f: psi = the unit vector of that flavour.
 template <typename ST>
-__global__ void k_init(ST* X, long long nb, long long plane, int nsc) {
+__global__ void k_init(ST* X, long long nb, long long plane, int nsc, long long per_species, int nfl) {
   const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
+  const int fl = (int)((b / per_species) % nfl);
   for (int c = 0; c < nsc; ++c) {
-    const bool one = (nsc == 3) ? (c == 2) : (c == 0);
-    X[b + c * plane] = one ? (ST)1 : (ST)0;
+    ST v = (ST)0;
+    if (nsc == 3) v = (c == 2) ? (ST)(fl == 0 ? 1 : -1) : (ST)0;
+    else v = (c == 2 * fl) ? (ST)1 : (ST)0;
+    X[b + c * plane] = v;
   }
 }
-template __global__ void k_init<double>(double*, long long, long long, int);
-template __global__ void k_init<float>(float*, long long, long long, int);
+template __global__ void k_init<double>(double*, long long, long long, int, long long, int);
+template __global__ void k_init<float>(float*, long long, long long, int, long long, int);
 
 template <typename ST>
 __global__ void k_read_pee(const ST* X, long long nb, long long plane, int nsc, double* out) {

@@ -30,11 +30,24 @@ def test_every_declared_symbol_is_exported(nb):
     assert declared == set(nb.EXPORTS)
 
 
+XBAR = dict(lum_xbar_erg_s=2.3e51, temp_xbar_mev=5.1)
+
+
 @pytest.mark.parametrize("case", ["2f_small", "3f_small", "2f_batchlike", "3f_800k_shape",
-                                  "2f_extended", "3f_extended"])
+                                  "2f_extended", "3f_extended", "2f_xbar", "2f_track_all",
+                                  "3f_track_all_xbar"])
 def test_host_tables_equal_oracle(nb, oracle, case):
+    species4 = 0
     if case == "2f_small":
         d = workloads.two_flavor_small()
+    elif case == "2f_xbar":
+        d = dict(workloads.two_flavor_small(), **XBAR)
+    elif case == "2f_track_all":
+        d = dict(workloads.two_flavor_small(), track_all=1)
+        species4 = 1
+    elif case == "3f_track_all_xbar":
+        d = workloads.small_params(n_flavor=3, n_energy=37, n_u=5, track_all=1, **XBAR)
+        species4 = 1
     elif case == "2f_extended":
         d = dict(workloads.two_flavor_small(), n_phi=5)
     elif case == "3f_extended":
@@ -47,7 +60,7 @@ def test_host_tables_equal_oracle(nb, oracle, case):
         d = workloads.three_flavor_800k()
         d["n_u"] = 7
     g = nb.HostModel(d).tables()
-    o = oracle.Model(d).tables()
+    o = oracle.Model(d, species4=species4).tables()
     for k in ("E", "w", "bv"):
         np.testing.assert_array_equal(g[k], o[k], err_msg=k)
     for k in ("lam0", "kappa0", "h", "p2e1", "p2e0", "e1", "e0"):
@@ -58,7 +71,8 @@ def test_host_tables_equal_oracle(nb, oracle, case):
     dict(n_flavor=4), dict(n_energy=0), dict(n_u=0), dict(n_steps=0), dict(r_start_km=5.0),
     dict(r_end_km=10.0), dict(delta_cp=0.1), dict(ne_power=9), dict(e_min_mev=0.0),
     dict(precision=1), dict(temp_mev=[0.0, 1.0, 1.0]), dict(lum_erg_s=[-1.0, 1.0, 1.0]),
-    dict(n_phi=-1), dict(n_phi=5000),
+    dict(n_phi=-1), dict(n_phi=5000), dict(track_all=2), dict(temp_xbar_mev=-1.0),
+    dict(temp_xbar_mev=3.0, lum_xbar_erg_s=-1.0),
 ])
 def test_invalid_parameters_rejected(nb, bad):
     d = workloads.two_flavor_small()
@@ -84,6 +98,22 @@ def test_extended_model_mode_checks(nb):
         nb.HostModel([d, d])
     assert e.value.code == nb.NB_EINVAL
     assert nb.HostModel(d).nb == 2 * 32 * 16 * 4
+
+
+def test_species_mode_checks(nb):
+    """Explicit tracking multiplies the beams by the flavour count; the adjoint keeps two
+    tracked species and anti-nu_x = nu_x; batches track two species."""
+    d = workloads.two_flavor_small()
+    assert nb.HostModel(dict(d, track_all=1)).nb == 2 * nb.HostModel(d).nb
+    d3 = workloads.small_params(n_flavor=3, track_all=1)
+    assert nb.HostModel(d3).nb == 6 * 37 * 5
+    for bad in (dict(track_all=1), XBAR):
+        with pytest.raises(nb.NubulbError) as e:
+            nb.HostModel(dict(d, **bad), adjoint_ckpt=64)
+        assert e.value.code == nb.NB_EINVAL
+    with pytest.raises(nb.NubulbError) as e:
+        nb.HostModel([dict(d, track_all=1)] * 2)
+    assert e.value.code == nb.NB_EINVAL
 
 
 def test_unbound_calls_fail_cleanly(nb):
