@@ -459,7 +459,8 @@ template <typename ST, int KIND, bool ADAPT = false, bool EXT = false>
 __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, long long row, double h,
                                      const Radial& g0, const Radial& gm, const Radial& g1,
                                      const double (*sJ)[EXT ? 32 : 16], const double* tab, double* snn,
-                                     int lane, long long* fl, I128& T, int& err, double& emax) {
+                                     int lane, long long* fl, I128& T, int& err, double& emax,
+                                     const ST* pre = nullptr) {
   constexpr int NM = EXT ? 4 : 2;
   const long long plane = a.plane;
   const int NE = a.NE;
@@ -510,8 +511,13 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
     long long acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     ST q[6];
     if (k0 < kend) {
+      if (pre && k0 == lane) {   // the lane's first beam, loaded before the last barrier
 #pragma unroll
-      for (int c = 0; c < 6; ++c) q[c] = X[rb + k0 + c * plane];
+        for (int c = 0; c < 6; ++c) q[c] = pre[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) q[c] = X[rb + k0 + c * plane];
+      }
     }
     for (int k = k0; k < kend; k += 64) {
       cplx ps[3] = {mk((double)q[0], (double)q[1]), mk((double)q[2], (double)q[3]),
@@ -612,11 +618,23 @@ template <typename ST, int KIND, bool ADAPT = false, bool EXT = false>
 __device__ __forceinline__ void stage3(const StepArgs& a, const StepGeo& G, const ST* X, ST* Xo,
                                        const double (*sJ)[EXT ? 32 : 16], const double* tab, double* snn,
                                        long long gw, long long nw, int lane, long long* fl, I128& T,
-                                       int& err, double& emax) {
+                                       int& err, double& emax, const ST* pre = nullptr) {
   const Radial g0 = radial_at(a, G.r0), gm = radial_at(a, G.rm), g1 = radial_at(a, G.r1);
   const long long nrow = (long long)a.NS * a.NU * (EXT ? a.NP : 1);
   for (long long row = gw; row < nrow; row += nw)
-    row3<ST, KIND, ADAPT, EXT>(a, X, Xo, row, G.h, g0, gm, g1, sJ, tab, snn, lane, fl, T, err, emax);
+    row3<ST, KIND, ADAPT, EXT>(a, X, Xo, row, G.h, g0, gm, g1, sJ, tab, snn, lane, fl, T, err, emax,
+                               row == gw ? pre : nullptr);
+}
+// Load the lane's first beam of the wavefront's first row (the next stage starts there),
+// so that the load completes while the wavefront waits at the grid barrier.
+template <typename ST>
+__device__ __forceinline__ void prefetch_first(const StepArgs& a, long long gw, long long nrow, int lane,
+                                               ST* pre) {
+  if (gw < nrow && lane < a.NE) {
+    const ST* X = (const ST*)a.X;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) pre[c] = X[gw * a.NE + lane + c * a.plane];
+  }
 }
 
 // ------------------------------------------------------- three flavours, mixed precision
@@ -859,9 +877,12 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   bool ok = true;
   double enone = 0.0;   // error estimate (adaptive runs only)
   I128 T = i128_zero();
+  // 3f FP64 arithmetic: each stage's first beam is loaded before the preceding barrier
+  ST pre[6] = {};
+  const long long nrow3 = (long long)a.NS * a.NU * (EXT ? a.NP : 1);
   if constexpr (NF == 2) stage2<0, false, EXT>(a, geo_fixed(a, step0), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
   else if constexpr (F32) stage3m<0>(a, geo_fixed(a, step0), sJ, tab, snn, gw, nw, lane, fl, T, err);
-    else stage3<ST, 0, false, EXT>(a, geo_fixed(a, step0), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone);
+    else { stage3<ST, 0, false, EXT>(a, geo_fixed(a, step0), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
   ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[0]);
   // the adjoint's forward pass records every stage's moments: [step][slot][NV]
   auto record = [&](long long step, int slot) {
@@ -873,25 +894,25 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
     T = i128_zero();
     if constexpr (NF == 2) stage2<1, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
     else if constexpr (F32) stage3m<1>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err);
-    else stage3<ST, 1, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone);
+    else { stage3<ST, 1, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     if (!(ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[1]))) break;
     record(n, 1);
     T = i128_zero();
     if constexpr (NF == 2) stage2<2, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
     else if constexpr (F32) stage3m<2>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err);
-    else stage3<ST, 2, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone);
+    else { stage3<ST, 2, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     if (!(ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[2]))) break;
     record(n, 2);
     T = i128_zero();
     if constexpr (NF == 2) stage2<3, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
     else if constexpr (F32) stage3m<3>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err);
-    else stage3<ST, 3, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone);
+    else { stage3<ST, 3, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     if (!(ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[3]))) break;
     record(n, 3);
     T = i128_zero();
     if constexpr (NF == 2) stage2<4, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
     else if constexpr (F32) stage3m<4>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err);
-    else stage3<ST, 4, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone);
+    else { stage3<ST, 4, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[0]);
     record(n + 1, 0);
   }
