@@ -157,14 +157,22 @@ static inline cx h3_at(const herm3 *h, int a, int b) {
   return cx_conj(h->o[a + b - 1]);
 }
 
+/* a0 b0 + a1 b1 + a2 b2 (complex), the six real products accumulated with fma from the
+ * last one up: the fused form of every three-term complex dot product below. */
+static inline cx dot3_mul(cx a0, cx b0, cx a1, cx b1, cx a2, cx b2) {
+  return cx_make(fma(a0.re, b0.re, fma(-a0.im, b0.im, fma(a1.re, b1.re, fma(-a1.im, b1.im,
+                     fma(a2.re, b2.re, -(a2.im * b2.im)))))),
+                 fma(a0.re, b0.im, fma(a0.im, b0.re, fma(a1.re, b1.im, fma(a1.im, b1.re,
+                     fma(a2.re, b2.im, a2.im * b2.re))))));
+}
+
 /* C(A,B) = i [A,B] (Hermitian for Hermitian A, B). */
 static herm3 h3_icomm(const herm3 *A, const herm3 *B) {
   cx X[3][3];
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b)
-      X[a][b] = cx_add(cx_add(cx_mul(h3_at(A, a, 0), h3_at(B, 0, b)),
-                              cx_mul(h3_at(A, a, 1), h3_at(B, 1, b))),
-                       cx_mul(h3_at(A, a, 2), h3_at(B, 2, b)));
+      X[a][b] = dot3_mul(h3_at(A, a, 0), h3_at(B, 0, b), h3_at(A, a, 1), h3_at(B, 1, b),
+                         h3_at(A, a, 2), h3_at(B, 2, b));
   herm3 C;
   for (int a = 0; a < 3; ++a) C.d[a] = -2.0 * X[a][a].im;
   const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
@@ -176,12 +184,22 @@ static herm3 h3_icomm(const herm3 *A, const herm3 *B) {
   return C;
 }
 
+/* Component comp of the cross product u x v: p q - r s with p = u_a, q = v_b, r = u_b,
+ * s = v_a (a, b the other two indices in cyclic order), fused as in dot3_mul. */
 static inline cx cross_c(const cx u[3], const cx v[3], int comp) {
   const int a = (comp + 1) % 3, b = (comp + 2) % 3;
-  return cx_sub(cx_mul(u[a], v[b]), cx_mul(u[b], v[a]));
+  const cx p = u[a], q = v[b], r = u[b], w = v[a];
+  return cx_make(fma(p.re, q.re, fma(-p.im, q.im, fma(-r.re, w.re, r.im * w.im))),
+                 fma(p.re, q.im, fma(p.im, q.re, fma(-r.re, w.im, -(r.im * w.re)))));
 }
-static inline cx inner3(const cx u[3], const cx v[3]) { /* u^+ v */
-  return cx_add(cx_add(cx_cjmul(u[0], v[0]), cx_cjmul(u[1], v[1])), cx_cjmul(u[2], v[2]));
+/* u^+ v */
+static inline cx inner3(const cx u[3], const cx v[3]) {
+  return dot3_mul(cx_conj(u[0]), v[0], cx_conj(u[1]), v[1], cx_conj(u[2]), v[2]);
+}
+/* |v0|^2 + |v1|^2 + |v2|^2 */
+static inline double norm3(const cx v[3]) {
+  return fma(v[0].re, v[0].re, fma(v[0].im, v[0].im, fma(v[1].re, v[1].re, fma(v[1].im, v[1].im,
+             fma(v[2].re, v[2].re, v[2].im * v[2].im)))));
 }
 
 /* psi' = exp(-i K) psi up to a global phase, for Hermitian K.
@@ -225,9 +243,9 @@ static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
     c02[c] = cross_c(r0, r2, c);
     c12[c] = cross_c(r1, r2, c);
   }
-  const double n01 = (cx_norm2(c01[0]) + cx_norm2(c01[1])) + cx_norm2(c01[2]);
-  const double n02 = (cx_norm2(c02[0]) + cx_norm2(c02[1])) + cx_norm2(c02[2]);
-  const double n12 = (cx_norm2(c12[0]) + cx_norm2(c12[1])) + cx_norm2(c12[2]);
+  const double n01 = norm3(c01);
+  const double n02 = norm3(c02);
+  const double n12 = norm3(c12);
   const cx *best = c01;
   double nb = n01;
   if (n02 > nb) { best = c02; nb = n02; }
@@ -250,25 +268,38 @@ static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
       w[c] = cx_make(-tm.re, -tm.im);
     }
   }
-  const double nw = (cx_norm2(w[0]) + cx_norm2(w[1])) + cx_norm2(w[2]);
+  const double nw = norm3(w);
   const double inw = 1.0 / sqrt(nw);
   cx u[3];
   for (int c = 0; c < 3; ++c) u[c] = cx_rmul(inw, w[c]);
   const double hm = -0.5 * l1;
   const double d0 = a0 - hm, d1 = a1 - hm, d2 = a2 - hm;
-  /* (K0 - hm) v for a vector v */
-#define NB_KMV(v, o)                                                                    \
-  do {                                                                                \
-    (o)[0] = cx_add(cx_add(cx_rmul(d0, (v)[0]), cx_mul(x, (v)[1])), cx_mul(y, (v)[2])); \
-    (o)[1] = cx_add(cx_add(cx_cjmul(x, (v)[0]), cx_rmul(d1, (v)[1])), cx_mul(z, (v)[2])); \
-    (o)[2] = cx_add(cx_add(cx_cjmul(y, (v)[0]), cx_cjmul(z, (v)[1])), cx_rmul(d2, (v)[2])); \
+  /* (K0 - hm) v for a vector v: rows (d0, x, y), (x^*, d1, z), (y^*, z^*, d2), each a
+   * complex dot product with the real diagonal entry, fused from the last product up */
+#define NB_KMV(v, o)                                                                          \
+  do {                                                                                      \
+    (o)[0] = cx_make(fma(d0, (v)[0].re, fma(x.re, (v)[1].re, fma(-x.im, (v)[1].im,          \
+                         fma(y.re, (v)[2].re, -(y.im * (v)[2].im))))),                      \
+                     fma(d0, (v)[0].im, fma(x.re, (v)[1].im, fma(x.im, (v)[1].re,           \
+                         fma(y.re, (v)[2].im, y.im * (v)[2].re)))));                        \
+    (o)[1] = cx_make(fma(x.re, (v)[0].re, fma(x.im, (v)[0].im, fma(d1, (v)[1].re,           \
+                         fma(z.re, (v)[2].re, -(z.im * (v)[2].im))))),                      \
+                     fma(x.re, (v)[0].im, fma(-x.im, (v)[0].re, fma(d1, (v)[1].im,          \
+                         fma(z.re, (v)[2].im, z.im * (v)[2].re)))));                        \
+    (o)[2] = cx_make(fma(y.re, (v)[0].re, fma(y.im, (v)[0].im, fma(z.re, (v)[1].re,         \
+                         fma(z.im, (v)[1].im, d2 * (v)[2].re)))),                           \
+                     fma(y.re, (v)[0].im, fma(-y.im, (v)[0].re, fma(z.re, (v)[1].im,        \
+                         fma(-z.im, (v)[1].re, d2 * (v)[2].im)))));                         \
   } while (0)
   cx ku[3];
   NB_KMV(u, ku);
-  const double th = sqrt((cx_norm2(ku[0]) + cx_norm2(ku[1])) + cx_norm2(ku[2]));
+  const double th = sqrt(norm3(ku));
   const cx al = inner3(v1, psi);
   cx pp[3], kp[3];
-  for (int c = 0; c < 3; ++c) pp[c] = cx_sub(psi[c], cx_mul(al, v1[c]));
+  /* P psi = psi - al v1 */
+  for (int c = 0; c < 3; ++c)
+    pp[c] = cx_make(fma(-al.re, v1[c].re, fma(al.im, v1[c].im, psi[c].re)),
+                    fma(-al.re, v1[c].im, fma(-al.im, v1[c].re, psi[c].im)));
   NB_KMV(pp, kp);
 #undef NB_KMV
   const double phi = l1 - hm;
@@ -277,9 +308,10 @@ static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
   sincos_spec(th, &st, &ct);
   const double sc = (th > 0.0) ? st / th : 1.0;
   const cx ap = cx_mul(al, cx_make(cp, -sp));
+  /* ap v1 + cos(th) P psi - i sin(th)/th (K0 - hm) P psi */
   for (int c = 0; c < 3; ++c)
-    out[c] = cx_add(cx_mul(ap, v1[c]),
-                    cx_make(ct * pp[c].re + sc * kp[c].im, ct * pp[c].im - sc * kp[c].re));
+    out[c] = cx_make(fma(ap.re, v1[c].re, fma(-ap.im, v1[c].im, fma(ct, pp[c].re, sc * kp[c].im))),
+                     fma(ap.re, v1[c].im, fma(ap.im, v1[c].re, fma(ct, pp[c].im, -(sc * kp[c].re)))));
 }
 
 /* Rotation of the Bloch vector P about x by the angle |x| (2x2 form of Eq. U as a

@@ -155,6 +155,15 @@ __device__ __forceinline__ void hadd(Herm3& acc, const Herm3& K) {
   acc.o12 = mk(acc.o12.re + K.o12.re, acc.o12.im + K.o12.im);
 }
 
+// a0 b0 + a1 b1 + a2 b2 (complex): the six real products accumulated with fma from the
+// last one up (the specification's fused three-term complex dot product).
+__device__ __forceinline__ cplx dot3_mul(cplx a0, cplx b0, cplx a1, cplx b1, cplx a2, cplx b2) {
+  return mk(fma(a0.re, b0.re, fma(-a0.im, b0.im, fma(a1.re, b1.re, fma(-a1.im, b1.im,
+                fma(a2.re, b2.re, -(a2.im * b2.im)))))),
+            fma(a0.re, b0.im, fma(a0.im, b0.re, fma(a1.re, b1.im, fma(a1.im, b1.re,
+                fma(a2.re, b2.im, a2.im * b2.re))))));
+}
+
 // C(A,B) = i [A,B]: with X = A B, C_aa = -2 Im X_aa, C_ab = i (X_ab - conj(X_ba)).
 __device__ __forceinline__ Herm3 icomm(const Herm3& A, const Herm3& B) {
   cplx X[3][3];
@@ -162,8 +171,8 @@ __device__ __forceinline__ Herm3 icomm(const Herm3& A, const Herm3& B) {
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b)
-      X[a][b] = cadd(cadd(cmul(hat(A, a, 0), hat(B, 0, b)), cmul(hat(A, a, 1), hat(B, 1, b))),
-                     cmul(hat(A, a, 2), hat(B, 2, b)));
+      X[a][b] = dot3_mul(hat(A, a, 0), hat(B, 0, b), hat(A, a, 1), hat(B, 1, b), hat(A, a, 2),
+                         hat(B, 2, b));
   Herm3 C;
   C.d0 = -2.0 * X[0][0].im;
   C.d1 = -2.0 * X[1][1].im;
@@ -183,16 +192,23 @@ __device__ __forceinline__ Herm3 icomm(const Herm3& A, const Herm3& B) {
   return C;
 }
 
+// p q - r s (complex), fused as dot3_mul
+__device__ __forceinline__ cplx cross_term(cplx p, cplx q, cplx r, cplx w) {
+  return mk(fma(p.re, q.re, fma(-p.im, q.im, fma(-r.re, w.re, r.im * w.im))),
+            fma(p.re, q.im, fma(p.im, q.re, fma(-r.re, w.im, -(r.im * w.re)))));
+}
 __device__ __forceinline__ void cross3c(const cplx u[3], const cplx v[3], cplx o[3]) {
-  o[0] = csub(cmul(u[1], v[2]), cmul(u[2], v[1]));
-  o[1] = csub(cmul(u[2], v[0]), cmul(u[0], v[2]));
-  o[2] = csub(cmul(u[0], v[1]), cmul(u[1], v[0]));
+  o[0] = cross_term(u[1], v[2], u[2], v[1]);
+  o[1] = cross_term(u[2], v[0], u[0], v[2]);
+  o[2] = cross_term(u[0], v[1], u[1], v[0]);
 }
 __device__ __forceinline__ cplx dotc(const cplx u[3], const cplx v[3]) {  // u^+ v
-  return cadd(cadd(cmul_conja(u[0], v[0]), cmul_conja(u[1], v[1])), cmul_conja(u[2], v[2]));
+  return dot3_mul(conjg(u[0]), v[0], conjg(u[1]), v[1], conjg(u[2]), v[2]);
 }
+// |v0|^2 + |v1|^2 + |v2|^2, fused from the last square up
 __device__ __forceinline__ double cnorm2v(const cplx v[3]) {
-  return (norm2(v[0]) + norm2(v[1])) + norm2(v[2]);
+  return fma(v[0].re, v[0].re, fma(v[0].im, v[0].im, fma(v[1].re, v[1].re, fma(v[1].im, v[1].im,
+             fma(v[2].re, v[2].re, v[2].im * v[2].im)))));
 }
 
 // psi <- exp(-i K) psi up to a global phase (three flavours).  K0 = traceless part of K,
@@ -202,11 +218,16 @@ __device__ __forceinline__ double cnorm2v(const cplx v[3]) {
 // th^2, so the plane is propagated by the closed-form 2x2 exponential of Eq. U:
 //   psi' = e^{-i (l1 - hm)} (v1^+ psi) v1 + cos(th) P psi - i sin(th)/th (K0 - hm) P psi,
 // P = I - v1 v1^+, th = |(K0 - hm) u| for a unit u in the plane.
+// (K0 - hm) v: rows (d0, x, y), (x^*, d1, z), (y^*, z^*, d2), each a complex dot product
+// with the real diagonal entry, fused from the last product up
 __device__ __forceinline__ void k0_minus(const cplx v[3], double d0, double d1, double d2,
                                          cplx x, cplx y, cplx z, cplx o[3]) {
-  o[0] = cadd(cadd(rmul(d0, v[0]), cmul(x, v[1])), cmul(y, v[2]));
-  o[1] = cadd(cadd(cmul_conja(x, v[0]), rmul(d1, v[1])), cmul(z, v[2]));
-  o[2] = cadd(cadd(cmul_conja(y, v[0]), cmul_conja(z, v[1])), rmul(d2, v[2]));
+  o[0] = mk(fma(d0, v[0].re, fma(x.re, v[1].re, fma(-x.im, v[1].im, fma(y.re, v[2].re, -(y.im * v[2].im))))),
+            fma(d0, v[0].im, fma(x.re, v[1].im, fma(x.im, v[1].re, fma(y.re, v[2].im, y.im * v[2].re)))));
+  o[1] = mk(fma(x.re, v[0].re, fma(x.im, v[0].im, fma(d1, v[1].re, fma(z.re, v[2].re, -(z.im * v[2].im))))),
+            fma(x.re, v[0].im, fma(-x.im, v[0].re, fma(d1, v[1].im, fma(z.re, v[2].im, z.im * v[2].re)))));
+  o[2] = mk(fma(y.re, v[0].re, fma(y.im, v[0].im, fma(z.re, v[1].re, fma(z.im, v[1].im, d2 * v[2].re)))),
+            fma(y.re, v[0].im, fma(-y.im, v[0].re, fma(z.re, v[1].im, fma(-z.im, v[1].re, d2 * v[2].im)))));
 }
 
 __device__ __forceinline__ void exp3_apply(const Herm3& K, cplx psi[3]) {
@@ -290,7 +311,9 @@ __device__ __forceinline__ void exp3_apply(const Herm3& K, cplx psi[3]) {
   const cplx al = dotc(v1, psi);
   cplx pp[3], kp[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) pp[c] = csub(psi[c], cmul(al, v1[c]));
+  for (int c = 0; c < 3; ++c)   // P psi = psi - al v1
+    pp[c] = mk(fma(-al.re, v1[c].re, fma(al.im, v1[c].im, psi[c].re)),
+               fma(-al.re, v1[c].im, fma(-al.im, v1[c].re, psi[c].im)));
   k0_minus(pp, d0, d1, d2, x, y, z, kp);
   const double phi = l1 - hm;
   double sp, cp, st, ct;
@@ -299,8 +322,9 @@ __device__ __forceinline__ void exp3_apply(const Herm3& K, cplx psi[3]) {
   const double sc = (th > 0.0) ? st / th : 1.0;
   const cplx ap = cmul(al, mk(cp, -sp));
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
-    psi[c] = cadd(cmul(ap, v1[c]), mk(ct * pp[c].re + sc * kp[c].im, ct * pp[c].im - sc * kp[c].re));
+  for (int c = 0; c < 3; ++c)   // ap v1 + cos(th) P psi - i sin(th)/th (K0 - hm) P psi
+    psi[c] = mk(fma(ap.re, v1[c].re, fma(-ap.im, v1[c].im, fma(ct, pp[c].re, sc * kp[c].im))),
+                fma(ap.re, v1[c].im, fma(ap.im, v1[c].re, fma(ct, pp[c].im, -(sc * kp[c].re)))));
 }
 
 // Bloch-vector rotation about x by |x| (two flavours): unit quaternion
