@@ -68,7 +68,7 @@ static double sqrt2gf_km_cm3(void) {
 #define PI_D 3.141592653589793
 #define F2_0 1.8030853547393914  /* int x^2/(e^x+1) = 3 zeta(3)/2 */
 #define F3_0 5.682196976983475   /* int x^3/(e^x+1) = 7 pi^4/120 */
-#define TWO58 288230376151711744.0
+#define TWO51 2251799813685248.0
 #define TWO62 4611686018427387904.0
 #define TWO64 18446744073709551616.0
 
@@ -114,12 +114,23 @@ static void sincos_spec(double x, double *sn, double *cs) {
 }
 
 /* ------------------------------------------------------------- fixed point */
-/* One contribution v becomes the integer trunc(v 2^e); |v 2^e| < limit is required
- * (2^58 for beam contributions, 2^62 for the per-angle terms of J0). */
+/* One per-angle term v of J0 becomes the integer trunc(v 2^e); |v 2^e| < limit = 2^62 is
+ * required. */
 static inline int64_t to_fix(double v, double scale, double limit, int *err) {
   const double x = v * scale;
   if (!(fabs(x) < limit)) { *err = 1; return 0; }
   return (int64_t)x;
+}
+/* A beam's moment contribution v 2^e1 (|.| < 2^50 by the choice of e1) rounded to the
+ * nearest integer (ties to even): adding 1.5 2^52 leaves the integer in the low mantissa
+ * bits, exactly for |x| < 2^51.  Out of range (NaN included) sets *err. */
+static inline int64_t to_fix_beam(double v, double scale, int *err) {
+  const double x = v * scale;
+  if (!(fabs(x) < TWO51)) { *err = 1; return 0; }
+  const double t = x + 0x1.8p52;
+  int64_t b;
+  memcpy(&b, &t, sizeof b);
+  return b - (int64_t)0x4338000000000000LL;
 }
 /* Integer -> double in sign-magnitude form: |x| = hi 2^64 + lo, each half converted
  * (round to nearest) and added; the sign is applied last. */
@@ -222,11 +233,13 @@ static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
   const double t = fma(xz.re, y.re, xz.im * y.im);             /* Re(x z conj(y)) */
   const double q = fma(a0, fma(a1, a2, -nz), fma(-a1, ny, fma(-a2, nx, 2.0 * t))); /* det */
   if (!(p > 0.0)) { out[0] = psi[0]; out[1] = psi[1]; out[2] = psi[2]; return; }
-  /* largest-magnitude root of l^3 - p l - q: Newton from 2 sqrt(p/3) on the |q| problem */
+  /* largest-magnitude root of l^3 - p l - q: 5 Newton steps from 2 sqrt(p/3) on the |q|
+   * problem (the start is within 16 % of the root, so 5 quadratic steps reach full FP64
+   * accuracy) */
   const double sg = (q < 0.0) ? -1.0 : 1.0;
   const double qa = sg * q;
   double lam = 2.0 * sqrt(p * (1.0 / 3.0));
-  for (int it = 0; it < 6; ++it) {
+  for (int it = 0; it < 5; ++it) {
     const double l2 = lam * lam;
     const double fv = fma(lam, l2 - p, -qa);
     const double dv = fma(3.0, l2, -p);
@@ -524,15 +537,16 @@ int nbo_create(const nbo_params *p, nbo_model **out) {
         m->bv[6 * k + e] = (U[ia[e]][1] * U[ib[e]][1]) * w2 + (U[ia[e]][2] * U[ib[e]][2]) * w3;
     }
   }
-  /* fixed-point scales: every beam contribution |w rho~| 2^e1 < 2^58 (so that 32 of them
-   * add up inside a signed 64-bit integer) and every angle term of J0 times 2^e0 < 2^62 */
+  /* fixed-point scales: every beam contribution |w rho~| 2^e1 < 2^50 (converted by rounding,
+   * and 32 of them add up far inside a signed 64-bit integer) and every angle term of J0
+   * times 2^e0 < 2^62 */
   double wmax = 0.0;
   for (int64_t i = 0; i < m->NE * m->ns; ++i)
     if (fabs(m->w[i]) > wmax) wmax = fabs(m->w[i]);
   if (!(wmax > 0.0)) wmax = 1.0;
   int ex;
   frexp(wmax, &ex);
-  m->e1 = 57 - ex;
+  m->e1 = 50 - ex;
   const double qs = m->R / p->r_start_km;
   const double cmin = sqrt(1.0 - u_of(m, m->NU - 1) * (qs * qs));
   const double b0 = (wmax * (double)m->NE) * (1.0 / cmin);
@@ -612,7 +626,7 @@ static int moments(const nbo_model *m, const double *X, double r, double (*Jm)[8
       const int64_t b = row * m->NE + k;
       double v[8];
       rho_tilde(m, s, X + b * m->nsc, v);
-      for (int c = 0; c < nc; ++c) S[c] += to_fix(m->w[s * m->NE + k] * v[c], m->s1, TWO58, &err);
+      for (int c = 0; c < nc; ++c) S[c] += to_fix_beam(m->w[s * m->NE + k] * v[c], m->s1, &err);
     }
     i128 *t = T + row * nm * nc;
     for (int c = 0; c < nc; ++c) {
@@ -1156,7 +1170,7 @@ int nbo_single_angle_run(const nbo_params *pin, double *pee_out) {
         const int s = (int)(i / NE);
         const double *x = src + 3 * i;
         const double v[3] = {s ? -x[0] : x[0], x[1], s ? -x[2] : x[2]};
-        for (int c = 0; c < 3; ++c) S[c] += to_fix(m->w[i] * v[c], m->s1, TWO58, &err);
+        for (int c = 0; c < 3; ++c) S[c] += to_fix_beam(m->w[i] * v[c], m->s1, &err);
       }
       for (int c = 0; c < 3; ++c) Jn[st_i][c] = i128_to_double(S[c]) * m->p2e1;
       const radial g = radial_at(m, rr[st_i]);
@@ -1202,7 +1216,7 @@ int nbo_single_angle_run(const nbo_params *pin, double *pee_out) {
 
 /* ------------------------------------------------------------------- adjoint */
 /* Reverse mode of the two-flavour RKMK4 integration.  The moment sums are treated as the
- * exact sums they represent (the fixed-point truncation is below 2^-58 of the largest
+ * exact sums they represent (the fixed-point quantisation is below 2^-50 of the largest
  * term).  Notation of the forward step (file header): f_i = (h/c_i) B(r_i, J^(i)),
  * Y2 = R(f1/2)P, Y3 = R(Om3)P with Om3 = f2/2 - f1 x f2/8, Y4 = R(f3)P,
  * Theta = (f1 + 2f2 + 2f3 + f4)/6 - f1 x f4/12, P' = R(Theta)P, P_{n+1} = P'/|P'|.

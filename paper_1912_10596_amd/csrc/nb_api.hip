@@ -273,15 +273,16 @@ static void build_tables(Sub* m) {
       m->vac_max = std::max(m->vac_max, sv);
     }
   }
-  // fixed point: every beam contribution |g rho~| 2^e1 < 2^58, so a lane can add 32 of
-  // them in a signed 64-bit integer; every angle term of J0, (energy sum / cos) 2^e0,
-  // stays below 2^62 (cos is smallest at r_start, u_max)
+  // fixed point: every beam contribution |g rho~| 2^e1 < 2^50 (rounded to an integer by
+  // the 1.5 2^52 addition, exact below 2^51; a lane adds up to 32 of them in a signed
+  // 64-bit integer); every angle term of J0, (energy sum / cos) 2^e0, stays below 2^62
+  // (cos is smallest at r_start, u_max)
   double wmax = 0.0;
   for (long long i = 0; i < (long long)NS * NE; ++i) wmax = std::max(wmax, std::fabs(G0[i]));
   if (!(wmax > 0.0)) wmax = 1.0;
   int ex = 0;
   std::frexp(wmax, &ex);
-  m->e1 = 57 - ex;
+  m->e1 = 50 - ex;
   const double qs = p.r_nu_km / p.r_start_km;
   const double ulast = ((double)(m->NU - 1) + 0.5) / (double)m->NU;
   const double cmin = std::sqrt(1.0 - ulast * (qs * qs));

@@ -297,7 +297,7 @@ __device__ __forceinline__ void close_row(const Scales& sc, int lane, const I128
 // KIND: 0 moments of rho_n at r_n; 1 stage Y2 (moments at r_n + h/2); 2 stage Y3
 // (r_n + h/2); 3 stage Y4 (r_{n+1}); 4 final update, store and moments at r_{n+1}.
 // J[i]: stage moments J^(i+1) (J0 | J1, 6 doubles).  A lane adds the fixed-point
-// contributions of up to 32 of its beams in 64-bit integers (each below 2^58) before they
+// contributions of up to 32 of its beams in 64-bit integers (each below 2^50) before they
 // are folded into exact 128-bit wave sums.
 // ADAPT (final update only): the new state goes to Xo instead of X, and emax keeps the
 // largest embedded error estimate |Theta - f2|^2 of the lane's beams.
@@ -383,9 +383,9 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
       // rho~: rho for neutrinos, -rho^* (Bloch (-x, y, -z)) for antineutrinos
       const double w = G[k];
       const double v0 = an ? -P0 : P0, v2 = an ? -P2 : P2;
-      acc[0] += to_fix(w * v0, sc.s1, kTwo58, err);
-      acc[1] += to_fix(w * P1, sc.s1, kTwo58, err);
-      acc[2] += to_fix(w * v2, sc.s1, kTwo58, err);
+      acc[0] += to_fix_beam(w * v0, sc.s1, err);
+      acc[1] += to_fix_beam(w * P1, sc.s1, err);
+      acc[2] += to_fix_beam(w * v2, sc.s1, err);
     }
     fold_segment<3, NM>(acc, lane, fl, mine);
   }
@@ -605,7 +605,7 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
       }
       const double w = G[k];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) acc[i] += to_fix(w * v8[i], a.s1, kTwo58, err);
+      for (int i = 0; i < 8; ++i) acc[i] += to_fix_beam(w * v8[i], a.s1, err);
     }
     fold_segment<8, NM>(acc, lane, fl, mine);
   }
@@ -665,7 +665,7 @@ __device__ __forceinline__ Herm3f gen3f(int s, const float* v, float lam, const 
 // One row of the mixed-precision stage with FP32 per-beam arithmetic.
 // The moment contributions of a lane's beams (k = lane mod 64 within a segment of 64 x 16
 // beams) are summed in FP64 and converted to fixed point once per segment, so the total
-// does not depend on the launch shape; 16 beams below 2^58 each stay below 2^62.
+// does not depend on the launch shape; 16 beams below 2^50 each stay far below 2^62.
 template <int KIND>
 __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Radial& g0, const Radial& gm,
                                       const Radial& g1, const RowGeo& rg, const double (*sJ)[16],
