@@ -68,7 +68,6 @@ static double sqrt2gf_km_cm3(void) {
 #define PI_D 3.141592653589793
 #define F2_0 1.8030853547393914  /* int x^2/(e^x+1) = 3 zeta(3)/2 */
 #define F3_0 5.682196976983475   /* int x^3/(e^x+1) = 7 pi^4/120 */
-#define TWO51 2251799813685248.0
 #define TWO62 4611686018427387904.0
 #define TWO64 18446744073709551616.0
 
@@ -121,13 +120,14 @@ static inline int64_t to_fix(double v, double scale, double limit, int *err) {
   if (!(fabs(x) < limit)) { *err = 1; return 0; }
   return (int64_t)x;
 }
-/* A beam's moment contribution v 2^e1 (|.| < 2^50 by the choice of e1) rounded to the
- * nearest integer (ties to even): adding 1.5 2^52 leaves the integer in the low mantissa
- * bits, exactly for |x| < 2^51.  Out of range (NaN included) sets *err. */
-static inline int64_t to_fix_beam(double v, double scale, int *err) {
-  const double x = v * scale;
-  if (!(fabs(x) < TWO51)) { *err = 1; return 0; }
-  const double t = x + 0x1.8p52;
+/* A beam's moment contribution: the exact product v ws (ws = w 2^e1, the weight in units
+ * of the fixed-point step) rounded once to the nearest integer, ties to even.  fma adds
+ * 1.5 2^52 to the exact product and rounds in a binade of unit spacing, so the integer
+ * sits in the low mantissa bits; this is exact for |v ws| <= 2^51, which the state check
+ * of the caller (squared norm below 2, so |v| < 2, and |ws| < 2^50 by the choice of e1)
+ * guarantees. */
+static inline int64_t fix_round(double v, double ws) {
+  const double t = fma(v, ws, 0x1.8p52);
   int64_t b;
   memcpy(&b, &t, sizeof b);
   return b - (int64_t)0x4338000000000000LL;
@@ -584,23 +584,27 @@ int nbo_reset(nbo_model *m) {
 
 /* rho~ of one beam: rho for neutrinos, -rho^* for antineutrinos (Eq. F), as the moment
  * components (2f: Bloch vector; 3f: rho_ee-rho_tt, rho_mm-rho_tt, Re/Im rho_em, rho_et, rho_mt). */
-static void rho_tilde(const nbo_model *m, int s, const double *x, double *out) {
+static double rho_tilde(const nbo_model *m, int s, const double *x, double *out) {
   const int a = m->anti[s];
   if (m->nf == 2) {
     out[0] = a ? -x[0] : x[0];
     out[1] = x[1];
     out[2] = a ? -x[2] : x[2];
-    return;
+    return fma(x[0], x[0], fma(x[1], x[1], x[2] * x[2]));
   }
   const cx p0 = cx_make(x[0], x[1]), p1 = cx_make(x[2], x[3]), p2 = cx_make(x[4], x[5]);
   const double n0 = cx_norm2(p0), n1 = cx_norm2(p1), n2 = cx_norm2(p2);
   const cx em = cx_mulc(p0, p1), et = cx_mulc(p0, p2), mt = cx_mulc(p1, p2);
   const double v[8] = {n0 - n2, n1 - n2, em.re, em.im, et.re, et.im, mt.re, mt.im};
-  if (!a) { for (int c = 0; c < 8; ++c) out[c] = v[c]; return; }
-  out[0] = -v[0]; out[1] = -v[1];
-  out[2] = -v[2]; out[3] = v[3];
-  out[4] = -v[4]; out[5] = v[5];
-  out[6] = -v[6]; out[7] = v[7];
+  if (!a) {
+    for (int c = 0; c < 8; ++c) out[c] = v[c];
+  } else {
+    out[0] = -v[0]; out[1] = -v[1];
+    out[2] = -v[2]; out[3] = v[3];
+    out[4] = -v[4]; out[5] = v[5];
+    out[6] = -v[6]; out[7] = v[7];
+  }
+  return (n0 + n1) + n2;
 }
 
 /* J0 = sum_b g_b rho~_b / c_b(r), J1 = sum_b g_b rho~_b: the energy sum of each
@@ -625,8 +629,10 @@ static int moments(const nbo_model *m, const double *X, double r, double (*Jm)[8
     for (int64_t k = 0; k < m->NE; ++k) {
       const int64_t b = row * m->NE + k;
       double v[8];
-      rho_tilde(m, s, X + b * m->nsc, v);
-      for (int c = 0; c < nc; ++c) S[c] += to_fix_beam(m->w[s * m->NE + k] * v[c], m->s1, &err);
+      /* a state of squared norm 2 or more (NaN included) is a numerical failure */
+      if (!(rho_tilde(m, s, X + b * m->nsc, v) < 2.0)) err = 1;
+      const double ws = m->w[s * m->NE + k] * m->s1;
+      for (int c = 0; c < nc; ++c) S[c] += fix_round(v[c], ws);
     }
     i128 *t = T + row * nm * nc;
     for (int c = 0; c < nc; ++c) {
@@ -1170,7 +1176,9 @@ int nbo_single_angle_run(const nbo_params *pin, double *pee_out) {
         const int s = (int)(i / NE);
         const double *x = src + 3 * i;
         const double v[3] = {s ? -x[0] : x[0], x[1], s ? -x[2] : x[2]};
-        for (int c = 0; c < 3; ++c) S[c] += to_fix_beam(m->w[i] * v[c], m->s1, &err);
+        if (!(fma(x[0], x[0], fma(x[1], x[1], x[2] * x[2])) < 2.0)) err = 1;
+        const double ws = m->w[i] * m->s1;
+        for (int c = 0; c < 3; ++c) S[c] += fix_round(v[c], ws);
       }
       for (int c = 0; c < 3; ++c) Jn[st_i][c] = i128_to_double(S[c]) * m->p2e1;
       const radial g = radial_at(m, rr[st_i]);

@@ -273,9 +273,10 @@ static void build_tables(Sub* m) {
       m->vac_max = std::max(m->vac_max, sv);
     }
   }
-  // fixed point: every beam contribution |g rho~| 2^e1 < 2^50 (rounded to an integer by
-  // the 1.5 2^52 addition, exact below 2^51; a lane adds up to 32 of them in a signed
-  // 64-bit integer); every angle term of J0, (energy sum / cos) 2^e0, stays below 2^62
+  // fixed point: |g| 2^e1 < 2^50, so a beam contribution g rho~ 2^e1 of a state with
+  // squared norm below 2 (checked per beam) stays below 2^51, where the fma with 1.5 2^52
+  // rounds it exactly to an integer; a lane adds up to 32 of them in a 64-bit integer;
+  // every angle term of J0, (energy sum / cos) 2^e0, stays below 2^62
   // (cos is smallest at r_start, u_max)
   double wmax = 0.0;
   for (long long i = 0; i < (long long)NS * NE; ++i) wmax = std::max(wmax, std::fabs(G0[i]));

@@ -13,7 +13,6 @@
 
 namespace nb {
 
-constexpr double kTwo51 = 2251799813685248.0;
 constexpr double kTwo62 = 4611686018427387904.0;
 constexpr double kTwo64 = 18446744073709551616.0;
 
@@ -90,16 +89,15 @@ __device__ __forceinline__ long long to_fix(double v, double scale, double limit
   }
   return (long long)x;
 }
-// A beam's moment contribution v * scale (below 2^50 in magnitude by the choice of the
-// scale) rounded to the nearest integer, ties to even: adding 1.5 2^52 leaves the integer
-// in the low mantissa bits, exact for |x| < 2^51 (checked; NaN included).
-__device__ __forceinline__ long long to_fix_beam(double v, double scale, int& err) {
-  const double x = v * scale;
-  if (!(fabs(x) < kTwo51)) {
-    err = 1;
-    return 0;
-  }
-  return __double_as_longlong(x + 0x1.8p52) - 0x4338000000000000LL;
+// A beam's moment contribution: the exact product v * ws (ws = weight * 2^e1) rounded
+// once to the nearest integer, ties to even.  The fma adds 1.5 2^52 and rounds in a binade
+// of unit spacing, so the integer sits in the low mantissa bits: the result's bit pattern
+// is kFixMagic + that integer (exact for |v ws| <= 2^51, which the caller's per-beam state
+// check guarantees).  Callers add bit patterns and take kFixMagic off once per count of
+// contributions; all of it is modulo 2^64, so the true sum comes out exactly.
+constexpr unsigned long long kFixMagic = 0x4338000000000000ull;
+__device__ __forceinline__ unsigned long long fix_bits(double v, double ws) {
+  return (unsigned long long)__double_as_longlong(fma(v, ws, 0x1.8p52));
 }
 // Butterfly sum over the 64 lanes of a wavefront; every lane gets the total.
 __device__ __forceinline__ I128 wave_sum(I128 a) {

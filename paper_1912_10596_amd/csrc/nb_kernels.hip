@@ -242,6 +242,13 @@ __device__ __forceinline__ StepGeo geo_fixed(const StepArgs& a, long long n) {
 struct Scales {
   double s1, s0, p2e1, p2e0;
 };
+// Start value of a lane's 64-bit sums over the segment k0, k0 + 64, ... < kend: minus
+// kFixMagic once per contribution (modulo 2^64), so that adding the contributions' bit
+// patterns leaves the sum of their integers.
+__device__ __forceinline__ unsigned long long fix_base(int k0, int kend) {
+  const unsigned long long n = (kend > k0) ? (unsigned long long)((kend - k0 + 63) >> 6) : 0ull;
+  return 0ull - n * kFixMagic;
+}
 // End of a row segment: the lanes' 64-bit sums -> exact per-component wave sums, added to
 // `mine` of lanes v < 2 NC (component v % NC).  Through this wave's LDS scratch fl
 // ((NC + 2) x 64 words): every lane stores its NC sums; lane (g, c) of G = 64/NC groups adds
@@ -297,8 +304,9 @@ __device__ __forceinline__ void close_row(const Scales& sc, int lane, const I128
 // KIND: 0 moments of rho_n at r_n; 1 stage Y2 (moments at r_n + h/2); 2 stage Y3
 // (r_n + h/2); 3 stage Y4 (r_{n+1}); 4 final update, store and moments at r_{n+1}.
 // J[i]: stage moments J^(i+1) (J0 | J1, 6 doubles).  A lane adds the fixed-point
-// contributions of up to 32 of its beams in 64-bit integers (each below 2^50) before they
-// are folded into exact 128-bit wave sums.
+// contributions of up to 32 of its beams in 64-bit integers (each below 2^51) before they
+// are folded into exact 128-bit wave sums; a beam whose state has squared norm 2 or more
+// (NaN included) sets err.
 // ADAPT (final update only): the new state goes to Xo instead of X, and emax keeps the
 // largest embedded error estimate |Theta - f2|^2 of the lane's beams.
 // EXT: extended bulb model, azimuth (cp, sp) = (cos, sin) of the row's azimuthal bin.
@@ -326,7 +334,8 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
   I128 mine = i128_zero();
   for (int k0 = lane; k0 - lane < NE; k0 += 64 * 32) {
     const int kend = min(NE, k0 + 64 * 32);
-    long long acc[3] = {0, 0, 0};
+    const unsigned long long base = fix_base(k0, kend);
+    unsigned long long acc[3] = {base, base, base};
     double q0 = 0.0, q1 = 0.0, q2 = 0.0;
     if (k0 < kend) {
       q0 = X[rb + k0]; q1 = X[rb + k0 + plane]; q2 = X[rb + k0 + 2 * plane];
@@ -381,13 +390,14 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
         }
       }
       // rho~: rho for neutrinos, -rho^* (Bloch (-x, y, -z)) for antineutrinos
-      const double w = G[k];
-      const double v0 = an ? -P0 : P0, v2 = an ? -P2 : P2;
-      acc[0] += to_fix_beam(w * v0, sc.s1, err);
-      acc[1] += to_fix_beam(w * P1, sc.s1, err);
-      acc[2] += to_fix_beam(w * v2, sc.s1, err);
+      if (!(fma(P0, P0, fma(P1, P1, P2 * P2)) < 2.0)) err = 1;
+      const double ws = G[k] * sc.s1;
+      const double wa = an ? -ws : ws;
+      acc[0] += fix_bits(P0, wa);
+      acc[1] += fix_bits(P1, ws);
+      acc[2] += fix_bits(P2, wa);
     }
-    fold_segment<3, NM>(acc, lane, fl, mine);
+    fold_segment<3, NM>(reinterpret_cast<const long long*>(acc), lane, fl, mine);
   }
   const double snmom = (KIND == 0) ? sn0 : ((KIND <= 2) ? snm : sn1);
   close_row<3, NM>(sc, lane, mine, icmom, T, err, (snmom * icmom) * cp, (snmom * icmom) * sp);
@@ -508,7 +518,8 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
   I128 mine = i128_zero();
   for (int k0 = lane; k0 - lane < NE; k0 += 64 * 32) {
     const int kend = min(NE, k0 + 64 * 32);
-    long long acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const unsigned long long base = fix_base(k0, kend);
+    unsigned long long acc[8] = {base, base, base, base, base, base, base, base};
     ST q[6];
     if (k0 < kend) {
       if (pre && k0 == lane) {   // the lane's first beam, loaded before the last barrier
@@ -599,15 +610,14 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
       // antineutrinos: -rho^* (real parts and diagonal negated)
       const double n0 = norm2(ps[0]), nm = norm2(ps[1]), nt = norm2(ps[2]);
       const cplx em = cmul_conjb(ps[0], ps[1]), et = cmul_conjb(ps[0], ps[2]), mt = cmul_conjb(ps[1], ps[2]);
-      double v8[8] = {n0 - nt, nm - nt, em.re, em.im, et.re, et.im, mt.re, mt.im};
-      if (an) {
-        v8[0] = -v8[0]; v8[1] = -v8[1]; v8[2] = -v8[2]; v8[4] = -v8[4]; v8[6] = -v8[6];
-      }
-      const double w = G[k];
+      const double v8[8] = {n0 - nt, nm - nt, em.re, em.im, et.re, et.im, mt.re, mt.im};
+      if (!((n0 + nm) + nt < 2.0)) err = 1;
+      const double ws = G[k] * a.s1;
+      const double wa = an ? -ws : ws;    // the negated components of -rho^*
 #pragma unroll
-      for (int i = 0; i < 8; ++i) acc[i] += to_fix_beam(w * v8[i], a.s1, err);
+      for (int i = 0; i < 8; ++i) acc[i] += fix_bits(v8[i], (i < 3 || i == 4 || i == 6) ? wa : ws);
     }
-    fold_segment<8, NM>(acc, lane, fl, mine);
+    fold_segment<8, NM>(reinterpret_cast<const long long*>(acc), lane, fl, mine);
   }
   const double snmom = (KIND == 0) ? sn0 : ((KIND <= 2) ? snm : sn1);
   close_row<8, NM>(Scales{a.s1, a.s0, a.p2e1, a.p2e0}, lane, mine, icmom, T, err, (snmom * icmom) * cp,
