@@ -220,8 +220,11 @@ static inline double norm3(const cx v[3]) {
  * eigenvalues) squares to th^2 times the identity, so
  *   exp(-i K0) psi = e^{-i l1} (v1^+ psi) v1
  *                  + e^{-i hm} [cos(th) P psi - i sin(th)/th (K0 - hm) P psi],
- * the 2x2 propagator of Eq. U on the plane.  th = |(K0 - hm) u| for a unit u in the
- * plane.  The traces (of K, and e^{-i hm}) only contribute global phases. */
+ * the 2x2 propagator of Eq. U on the plane.  th = |(K0 - hm) w| / |w| for any w in the
+ * plane.  The traces (of K, and e^{-i hm}) only contribute global phases.  v1 and w are
+ * kept unnormalised (v1 = c / |c| with c a cross product, w = |c|^2 times the Gram-Schmidt
+ * vector), so the intermediate magnitudes grow like |K0|^10: the form holds for
+ * 2^-100 < |K0| < 1e30, and |K0|^2 / 2 <= 2^-200 is taken as K0 = 0 (error below 1e-30). */
 static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
   const double tr = ((K->d[0] + K->d[1]) + K->d[2]) * (1.0 / 3.0);
   const double a0 = K->d[0] - tr, a1 = K->d[1] - tr, a2 = K->d[2] - tr;
@@ -232,18 +235,20 @@ static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
   const cx xz = cx_mul(x, z);
   const double t = fma(xz.re, y.re, xz.im * y.im);             /* Re(x z conj(y)) */
   const double q = fma(a0, fma(a1, a2, -nz), fma(-a1, ny, fma(-a2, nx, 2.0 * t))); /* det */
-  if (!(p > 0.0)) { out[0] = psi[0]; out[1] = psi[1]; out[2] = psi[2]; return; }
-  /* largest-magnitude root of l^3 - p l - q: 5 Newton steps from 2 sqrt(p/3) on the |q|
-   * problem (the start is within 16 % of the root, so 5 quadratic steps reach full FP64
-   * accuracy) */
+  if (!(p > 0x1p-200)) { out[0] = psi[0]; out[1] = psi[1]; out[2] = psi[2]; return; }
+  /* largest-magnitude root of l^3 - p l - q: 3 Halley steps l - f f' / (f'^2 - f f''/2)
+   * (f'' = 6 l) from 2 sqrt(p/3) on the |q| problem (the root's magnitude lies in
+   * [sqrt(p), 2 sqrt(p/3)], so the start is within 16 % and three cubic steps reach full
+   * FP64 accuracy) */
   const double sg = (q < 0.0) ? -1.0 : 1.0;
   const double qa = sg * q;
   double lam = 2.0 * sqrt(p * (1.0 / 3.0));
-  for (int it = 0; it < 5; ++it) {
+  for (int it = 0; it < 3; ++it) {
     const double l2 = lam * lam;
     const double fv = fma(lam, l2 - p, -qa);
     const double dv = fma(3.0, l2, -p);
-    lam = lam - fv / dv;
+    const double den = fma(dv, dv, -((3.0 * lam) * fv));
+    lam = lam - (fv * dv) / den;
   }
   const double l1 = sg * lam;
   /* eigenvector: largest cross product of two rows of K0 - l1 I (first wins ties) */
@@ -264,27 +269,21 @@ static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
   if (n02 > nb) { best = c02; nb = n02; }
   if (n12 > nb) { best = c12; nb = n12; }
   if (!(nb > 0.0)) { out[0] = psi[0]; out[1] = psi[1]; out[2] = psi[2]; return; }
-  const double inb = 1.0 / sqrt(nb);
-  cx v1[3];
-  for (int c = 0; c < 3; ++c) v1[c] = cx_rmul(inb, best[c]);
-  /* unit vector of the plane: Gram-Schmidt of the axis where v1 is smallest */
+  /* vector of the plane: nb e_m - c conj(c_m), nb times the Gram-Schmidt of the axis m
+   * where c is smallest against c / |c| (its m-th entry nb - |c_m|^2 >= 2 nb / 3) */
   double nc[3];
-  for (int c = 0; c < 3; ++c) nc[c] = cx_norm2(v1[c]);
+  for (int c = 0; c < 3; ++c) nc[c] = cx_norm2(best[c]);
   int m = 0;
   if (nc[1] < nc[m]) m = 1;
   if (nc[2] < nc[m]) m = 2;
   cx w[3];
   for (int c = 0; c < 3; ++c) {
-    if (c == m) w[c] = cx_make(1.0 - nc[m], 0.0);
+    if (c == m) w[c] = cx_make(nb - nc[m], 0.0);
     else {
-      const cx tm = cx_mulc(v1[c], v1[m]);
+      const cx tm = cx_mulc(best[c], best[m]);
       w[c] = cx_make(-tm.re, -tm.im);
     }
   }
-  const double nw = norm3(w);
-  const double inw = 1.0 / sqrt(nw);
-  cx u[3];
-  for (int c = 0; c < 3; ++c) u[c] = cx_rmul(inw, w[c]);
   const double hm = -0.5 * l1;
   const double d0 = a0 - hm, d1 = a1 - hm, d2 = a2 - hm;
   /* (K0 - hm) v for a vector v: rows (d0, x, y), (x^*, d1, z), (y^*, z^*, d2), each a
@@ -304,15 +303,16 @@ static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
                      fma(y.re, (v)[0].im, fma(-y.im, (v)[0].re, fma(z.re, (v)[1].im,        \
                          fma(-z.im, (v)[1].re, d2 * (v)[2].im)))));                         \
   } while (0)
-  cx ku[3];
-  NB_KMV(u, ku);
-  const double th = sqrt(norm3(ku));
-  const cx al = inner3(v1, psi);
+  cx kw[3];
+  NB_KMV(w, kw);
+  const double th = sqrt(norm3(kw) / norm3(w));
+  /* al = (c^+ psi) / |c|^2, so that (v1^+ psi) v1 = al c */
+  const cx al = cx_rmul(1.0 / nb, inner3(best, psi));
   cx pp[3], kp[3];
-  /* P psi = psi - al v1 */
+  /* P psi = psi - al c */
   for (int c = 0; c < 3; ++c)
-    pp[c] = cx_make(fma(-al.re, v1[c].re, fma(al.im, v1[c].im, psi[c].re)),
-                    fma(-al.re, v1[c].im, fma(-al.im, v1[c].re, psi[c].im)));
+    pp[c] = cx_make(fma(-al.re, best[c].re, fma(al.im, best[c].im, psi[c].re)),
+                    fma(-al.re, best[c].im, fma(-al.im, best[c].re, psi[c].im)));
   NB_KMV(pp, kp);
 #undef NB_KMV
   const double phi = l1 - hm;
@@ -321,10 +321,10 @@ static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
   sincos_spec(th, &st, &ct);
   const double sc = (th > 0.0) ? st / th : 1.0;
   const cx ap = cx_mul(al, cx_make(cp, -sp));
-  /* ap v1 + cos(th) P psi - i sin(th)/th (K0 - hm) P psi */
+  /* ap c + cos(th) P psi - i sin(th)/th (K0 - hm) P psi */
   for (int c = 0; c < 3; ++c)
-    out[c] = cx_make(fma(ap.re, v1[c].re, fma(-ap.im, v1[c].im, fma(ct, pp[c].re, sc * kp[c].im))),
-                     fma(ap.re, v1[c].im, fma(ap.im, v1[c].re, fma(ct, pp[c].im, -(sc * kp[c].re)))));
+    out[c] = cx_make(fma(ap.re, best[c].re, fma(-ap.im, best[c].im, fma(ct, pp[c].re, sc * kp[c].im))),
+                     fma(ap.re, best[c].im, fma(ap.im, best[c].re, fma(ct, pp[c].im, -(sc * kp[c].re)))));
 }
 
 /* Rotation of the Bloch vector P about x by the angle |x| (2x2 form of Eq. U as a

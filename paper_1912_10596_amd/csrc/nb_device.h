@@ -220,12 +220,16 @@ __device__ __forceinline__ double cnorm2v(const cplx v[3]) {
 }
 
 // psi <- exp(-i K) psi up to a global phase (three flavours).  K0 = traceless part of K,
-// l1 its eigenvalue of largest magnitude (5 Newton steps on the characteristic cubic
-// l^3 - p l - q from 2 sqrt(p/3), which is within 16 % of it: full FP64 accuracy), v1 its eigenvector (the largest cross product of two
-// rows of K0 - l1).  On the plane orthogonal to v1, K0 - hm with hm = -l1/2 squares to
-// th^2, so the plane is propagated by the closed-form 2x2 exponential of Eq. U:
+// l1 its eigenvalue of largest magnitude (3 Halley steps on the characteristic cubic
+// l^3 - p l - q from 2 sqrt(p/3), which is within 16 % of it: full FP64 accuracy), c the
+// largest cross product of two rows of K0 - l1 (its eigenvector, v1 = c / |c|).  On the
+// plane orthogonal to v1, K0 - hm with hm = -l1/2 squares to th^2, so the plane is
+// propagated by the closed-form 2x2 exponential of Eq. U:
 //   psi' = e^{-i (l1 - hm)} (v1^+ psi) v1 + cos(th) P psi - i sin(th)/th (K0 - hm) P psi,
-// P = I - v1 v1^+, th = |(K0 - hm) u| for a unit u in the plane.
+// P = I - v1 v1^+, th = |(K0 - hm) w| / |w| for any w in the plane.  Nothing is normalised:
+// (v1^+ psi) v1 = al c with al = (c^+ psi) / |c|^2, and w = |c|^2 e_m - c conj(c_m) (m the
+// smallest entry of c).  The magnitudes then grow like |K0|^10, which holds for
+// 2^-100 < |K0| < 1e30; |K0|^2 / 2 <= 2^-200 is taken as K0 = 0 (error below 1e-30).
 // (K0 - hm) v: rows (d0, x, y), (x^*, d1, z), (y^*, z^*, d2), each a complex dot product
 // with the real diagonal entry, fused from the last product up
 __device__ __forceinline__ void k0_minus(const cplx v[3], double d0, double d1, double d2,
@@ -248,16 +252,17 @@ __device__ __forceinline__ void exp3_apply(const Herm3& K, cplx psi[3]) {
   const cplx xz = cmul(x, z);
   const double t = fma(xz.re, y.re, xz.im * y.im);
   const double q = fma(a0, fma(a1, a2, -nz), fma(-a1, ny, fma(-a2, nx, 2.0 * t)));
-  if (!(p > 0.0)) return;
+  if (!(p > 0x1p-200)) return;
   const double sg = (q < 0.0) ? -1.0 : 1.0;
   const double qa = sg * q;
   double lam = 2.0 * sqrt(p * (1.0 / 3.0));
 #pragma unroll
-  for (int it = 0; it < 5; ++it) {
+  for (int it = 0; it < 3; ++it) {   // Halley: l - f f' / (f'^2 - f f''/2), f'' = 6 l
     const double l2 = lam * lam;
     const double fv = fma(lam, l2 - p, -qa);
     const double dv = fma(3.0, l2, -p);
-    lam = lam - fv / dv;
+    const double den = fma(dv, dv, -((3.0 * lam) * fv));
+    lam = lam - (fv * dv) / den;
   }
   const double l1 = sg * lam;
   const cplx r0[3] = {mk(a0 - l1, 0.0), x, y};
@@ -291,37 +296,33 @@ __device__ __forceinline__ void exp3_apply(const Herm3& K, cplx psi[3]) {
     }
   }
   if (!(nb > 0.0)) return;
-  const double inb = 1.0 / sqrt(nb);
-  const cplx v1[3] = {rmul(inb, best[0]), rmul(inb, best[1]), rmul(inb, best[2])};
   const double hm = -0.5 * l1;
   const double d0 = a0 - hm, d1 = a1 - hm, d2 = a2 - hm;
   double th;
   {
-    // unit vector of the plane: Gram-Schmidt of the axis where v1 is smallest
-    const double nc0 = norm2(v1[0]), nc1 = norm2(v1[1]), nc2 = norm2(v1[2]);
+    // vector of the plane: nb e_m - c conj(c_m), m the smallest entry of c
+    const double nc0 = norm2(best[0]), nc1 = norm2(best[1]), nc2 = norm2(best[2]);
     int m = 0;
     double ncm = nc0;
     if (nc1 < ncm) { m = 1; ncm = nc1; }
     if (nc2 < ncm) { m = 2; ncm = nc2; }
-    const cplx vm = (m == 0) ? v1[0] : ((m == 1) ? v1[1] : v1[2]);
+    const cplx cm = (m == 0) ? best[0] : ((m == 1) ? best[1] : best[2]);
     cplx w[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const cplx tm = cmul_conjb(v1[c], vm);
-      w[c] = (c == m) ? mk(1.0 - ncm, 0.0) : mk(-tm.re, -tm.im);
+      const cplx tm = cmul_conjb(best[c], cm);
+      w[c] = (c == m) ? mk(nb - ncm, 0.0) : mk(-tm.re, -tm.im);
     }
-    const double inw = 1.0 / sqrt(cnorm2v(w));
-    const cplx u[3] = {rmul(inw, w[0]), rmul(inw, w[1]), rmul(inw, w[2])};
-    cplx ku[3];
-    k0_minus(u, d0, d1, d2, x, y, z, ku);
-    th = sqrt(cnorm2v(ku));
+    cplx kw[3];
+    k0_minus(w, d0, d1, d2, x, y, z, kw);
+    th = sqrt(cnorm2v(kw) / cnorm2v(w));
   }
-  const cplx al = dotc(v1, psi);
+  const cplx al = rmul(1.0 / nb, dotc(best, psi));   // (v1^+ psi) v1 = al c
   cplx pp[3], kp[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c)   // P psi = psi - al v1
-    pp[c] = mk(fma(-al.re, v1[c].re, fma(al.im, v1[c].im, psi[c].re)),
-               fma(-al.re, v1[c].im, fma(-al.im, v1[c].re, psi[c].im)));
+  for (int c = 0; c < 3; ++c)   // P psi = psi - al c
+    pp[c] = mk(fma(-al.re, best[c].re, fma(al.im, best[c].im, psi[c].re)),
+               fma(-al.re, best[c].im, fma(-al.im, best[c].re, psi[c].im)));
   k0_minus(pp, d0, d1, d2, x, y, z, kp);
   const double phi = l1 - hm;
   double sp, cp, st, ct;
@@ -330,9 +331,9 @@ __device__ __forceinline__ void exp3_apply(const Herm3& K, cplx psi[3]) {
   const double sc = (th > 0.0) ? st / th : 1.0;
   const cplx ap = cmul(al, mk(cp, -sp));
 #pragma unroll
-  for (int c = 0; c < 3; ++c)   // ap v1 + cos(th) P psi - i sin(th)/th (K0 - hm) P psi
-    psi[c] = mk(fma(ap.re, v1[c].re, fma(-ap.im, v1[c].im, fma(ct, pp[c].re, sc * kp[c].im))),
-                fma(ap.re, v1[c].im, fma(ap.im, v1[c].re, fma(ct, pp[c].im, -(sc * kp[c].re)))));
+  for (int c = 0; c < 3; ++c)   // ap c + cos(th) P psi - i sin(th)/th (K0 - hm) P psi
+    psi[c] = mk(fma(ap.re, best[c].re, fma(-ap.im, best[c].im, fma(ct, pp[c].re, sc * kp[c].im))),
+                fma(ap.re, best[c].im, fma(ap.im, best[c].re, fma(ct, pp[c].im, -(sc * kp[c].re)))));
 }
 
 // Bloch-vector rotation about x by |x| (two flavours): unit quaternion

@@ -139,6 +139,34 @@ def test_exp3_against_expm(oracle, kind):
     np.testing.assert_array_equal(oracle.exp3_apply(np.zeros(9), psi), psi)
 
 
+def test_exp3_magnitude_range(oracle):
+    """The unnormalised form's range: |K0| from just above its lower end (1e-29: every
+    intermediate about |K0|^10 stays normal) to 1e9, first-order exact at the small end
+    (psi' = psi - i K psi) and against expm above; below the end (1e-31) K0 counts as zero."""
+    rng = np.random.default_rng(12)
+    for scale in (1e-29, 1e-20, 1e9):
+        for _ in range(10):
+            k9 = rng.normal(size=9) * scale
+            psi = rng.normal(size=6); psi /= np.linalg.norm(psi)
+            got = oracle.exp3_apply(k9, psi)
+            assert np.isfinite(got).all()
+            pv = psi[0::2] + 1j * psi[1::2]
+            U = linalg.expm(-1j * _herm(k9))
+            want = np.outer(U @ pv, (U @ pv).conj())
+            np.testing.assert_allclose(_rho(got), want, atol=3e-15 * max(1.0, scale * 3) + 1e-14)
+            if scale < 1e-19:
+                # global phase fixed by the first entry: psi' = (1 - i K0) psi to O(K^2)
+                H = _herm(k9)
+                H0 = H - np.trace(H) / 3 * np.eye(3)
+                lin = pv - 1j * (H0 @ pv)
+                g = got[0::2] + 1j * got[1::2]
+                ph = (g @ lin.conj()) / abs(g @ lin.conj())
+                np.testing.assert_allclose(g / ph, lin, rtol=0, atol=1e-15)
+    k9 = rng.normal(size=9) * 1e-31
+    psi = rng.normal(size=6); psi /= np.linalg.norm(psi)
+    np.testing.assert_array_equal(oracle.exp3_apply(k9, psi), psi)
+
+
 def test_fixed_point_sum_exact_and_order_free(oracle):
     rng = np.random.default_rng(5)
     v = rng.normal(size=2000) * 10.0 ** rng.uniform(-8, 3, size=2000)
