@@ -195,14 +195,6 @@ static herm3 h3_icomm(const herm3 *A, const herm3 *B) {
   return C;
 }
 
-/* Component comp of the cross product u x v: p q - r s with p = u_a, q = v_b, r = u_b,
- * s = v_a (a, b the other two indices in cyclic order), fused as in dot3_mul. */
-static inline cx cross_c(const cx u[3], const cx v[3], int comp) {
-  const int a = (comp + 1) % 3, b = (comp + 2) % 3;
-  const cx p = u[a], q = v[b], r = u[b], w = v[a];
-  return cx_make(fma(p.re, q.re, fma(-p.im, q.im, fma(-r.re, w.re, r.im * w.im))),
-                 fma(p.re, q.im, fma(p.im, q.re, fma(-r.re, w.im, -(r.im * w.re)))));
-}
 /* u^+ v */
 static inline cx inner3(const cx u[3], const cx v[3]) {
   return dot3_mul(cx_conj(u[0]), v[0], cx_conj(u[1]), v[1], cx_conj(u[2]), v[2]);
@@ -222,8 +214,8 @@ static inline double norm3(const cx v[3]) {
  *                  + e^{-i hm} [cos(th) P psi - i sin(th)/th (K0 - hm) P psi],
  * the 2x2 propagator of Eq. U on the plane.  th = |(K0 - hm) w| / |w| for any w in the
  * plane.  The traces (of K, and e^{-i hm}) only contribute global phases.  v1 and w are
- * kept unnormalised (v1 = c / |c| with c a cross product, w = |c|^2 times the Gram-Schmidt
- * vector), so the intermediate magnitudes grow like |K0|^10: the form holds for
+ * kept unnormalised (v1 = c / |c| with c a column of adj(K0 - l1), w = |c|^2 times the
+ * Gram-Schmidt vector), so the intermediate magnitudes grow like |K0|^10: the form holds for
  * 2^-100 < |K0| < 1e30, and |K0|^2 / 2 <= 2^-200 is taken as K0 = 0 (error below 1e-30). */
 static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
   const double tr = ((K->d[0] + K->d[1]) + K->d[2]) * (1.0 / 3.0);
@@ -251,23 +243,29 @@ static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
     lam = lam - (fv * dv) / den;
   }
   const double l1 = sg * lam;
-  /* eigenvector: largest cross product of two rows of K0 - l1 I (first wins ties) */
-  const cx r0[3] = {cx_make(a0 - l1, 0.0), x, y};
-  const cx r1[3] = {cx_conj(x), cx_make(a1 - l1, 0.0), z};
-  const cx r2[3] = {cx_conj(y), cx_conj(z), cx_make(a2 - l1, 0.0)};
-  cx c01[3], c02[3], c12[3];
-  for (int c = 0; c < 3; ++c) {
-    c01[c] = cross_c(r0, r1, c);
-    c02[c] = cross_c(r0, r2, c);
-    c12[c] = cross_c(r1, r2, c);
-  }
-  const double n01 = norm3(c01);
-  const double n02 = norm3(c02);
-  const double n12 = norm3(c12);
-  const cx *best = c01;
-  double nb = n01;
-  if (n02 > nb) { best = c02; nb = n02; }
-  if (n12 > nb) { best = c12; nb = n12; }
+  /* eigenvector: a column of adj(K0 - l1 I), which has rank one (mu v1 v1^+ with
+   * mu = (l2 - l1)(l3 - l1) > 0), the one with the largest diagonal entry (first wins
+   * ties; the largest |v1_j|, so the best-conditioned column).  With p_i = a_i - l1 the
+   * cofactors are c00 = p1 p2 - |z|^2, c11 = p0 p2 - |y|^2, c22 = p0 p1 - |x|^2 and the
+   * entries above the diagonal u = y z^* - p2 x, v = x z - p1 y, t = x^* y - p0 z, so the
+   * columns are (c00, u^*, v^*), (u, c11, t^*) and (v, t, c22). */
+  const double p0 = a0 - l1, p1 = a1 - l1, p2 = a2 - l1;
+  const double c00 = fma(p1, p2, -nz), c11 = fma(p0, p2, -ny), c22 = fma(p0, p1, -nx);
+  const cx u = cx_make(fma(y.re, z.re, fma(y.im, z.im, -(p2 * x.re))),
+                       fma(y.im, z.re, fma(-y.re, z.im, -(p2 * x.im))));
+  const cx v = cx_make(fma(x.re, z.re, fma(-x.im, z.im, -(p1 * y.re))),
+                       fma(x.re, z.im, fma(x.im, z.re, -(p1 * y.im))));
+  const cx tt = cx_make(fma(x.re, y.re, fma(x.im, y.im, -(p0 * z.re))),
+                        fma(x.re, y.im, fma(-x.im, y.re, -(p0 * z.im))));
+  int jc = 0;
+  double cjj = c00;
+  if (c11 > cjj) { jc = 1; cjj = c11; }
+  if (c22 > cjj) { jc = 2; cjj = c22; }
+  cx best[3];
+  if (jc == 0) { best[0] = cx_make(c00, 0.0); best[1] = cx_conj(u); best[2] = cx_conj(v); }
+  else if (jc == 1) { best[0] = u; best[1] = cx_make(c11, 0.0); best[2] = cx_conj(tt); }
+  else { best[0] = v; best[1] = tt; best[2] = cx_make(c22, 0.0); }
+  const double nb = norm3(best);
   if (!(nb > 0.0)) { out[0] = psi[0]; out[1] = psi[1]; out[2] = psi[2]; return; }
   /* vector of the plane: nb e_m - c conj(c_m), nb times the Gram-Schmidt of the axis m
    * where c is smallest against c / |c| (its m-th entry nb - |c_m|^2 >= 2 nb / 3) */

@@ -200,16 +200,6 @@ __device__ __forceinline__ Herm3 icomm(const Herm3& A, const Herm3& B) {
   return C;
 }
 
-// p q - r s (complex), fused as dot3_mul
-__device__ __forceinline__ cplx cross_term(cplx p, cplx q, cplx r, cplx w) {
-  return mk(fma(p.re, q.re, fma(-p.im, q.im, fma(-r.re, w.re, r.im * w.im))),
-            fma(p.re, q.im, fma(p.im, q.re, fma(-r.re, w.im, -(r.im * w.re)))));
-}
-__device__ __forceinline__ void cross3c(const cplx u[3], const cplx v[3], cplx o[3]) {
-  o[0] = cross_term(u[1], v[2], u[2], v[1]);
-  o[1] = cross_term(u[2], v[0], u[0], v[2]);
-  o[2] = cross_term(u[0], v[1], u[1], v[0]);
-}
 __device__ __forceinline__ cplx dotc(const cplx u[3], const cplx v[3]) {  // u^+ v
   return dot3_mul(conjg(u[0]), v[0], conjg(u[1]), v[1], conjg(u[2]), v[2]);
 }
@@ -221,10 +211,10 @@ __device__ __forceinline__ double cnorm2v(const cplx v[3]) {
 
 // psi <- exp(-i K) psi up to a global phase (three flavours).  K0 = traceless part of K,
 // l1 its eigenvalue of largest magnitude (3 Halley steps on the characteristic cubic
-// l^3 - p l - q from 2 sqrt(p/3), which is within 16 % of it: full FP64 accuracy), c the
-// largest cross product of two rows of K0 - l1 (its eigenvector, v1 = c / |c|).  On the
-// plane orthogonal to v1, K0 - hm with hm = -l1/2 squares to th^2, so the plane is
-// propagated by the closed-form 2x2 exponential of Eq. U:
+// l^3 - p l - q from 2 sqrt(p/3), which is within 16 % of it: full FP64 accuracy), c a
+// column of adj(K0 - l1) (its eigenvector, v1 = c / |c|).  On the plane orthogonal to v1,
+// K0 - hm with hm = -l1/2 squares to th^2, so the plane is propagated by the closed-form
+// 2x2 exponential of Eq. U:
 //   psi' = e^{-i (l1 - hm)} (v1^+ psi) v1 + cos(th) P psi - i sin(th)/th (K0 - hm) P psi,
 // P = I - v1 v1^+, th = |(K0 - hm) w| / |w| for any w in the plane.  Nothing is normalised:
 // (v1^+ psi) v1 = al c with al = (c^+ psi) / |c|^2, and w = |c|^2 e_m - c conj(c_m) (m the
@@ -265,36 +255,27 @@ __device__ __forceinline__ void exp3_apply(const Herm3& K, cplx psi[3]) {
     lam = lam - (fv * dv) / den;
   }
   const double l1 = sg * lam;
-  const cplx r0[3] = {mk(a0 - l1, 0.0), x, y};
-  const cplx r1[3] = {conjg(x), mk(a1 - l1, 0.0), z};
-  const cplx r2[3] = {conjg(y), conjg(z), mk(a2 - l1, 0.0)};
-  // eigenvector: the largest of the three row cross products (first one wins ties)
+  // eigenvector c: the column of adj(K0 - l1) = mu v1 v1^+ (mu > 0) with the largest
+  // diagonal entry (first wins ties).  p_i = a_i - l1; diagonal cofactors p1 p2 - |z|^2,
+  // p0 p2 - |y|^2, p0 p1 - |x|^2; above the diagonal u = y z^* - p2 x, v = x z - p1 y,
+  // t = x^* y - p0 z; columns (c00, u^*, v^*), (u, c11, t^*), (v, t, c22).
+  const double p0 = a0 - l1, p1 = a1 - l1, p2 = a2 - l1;
+  const double c00 = fma(p1, p2, -nz), c11 = fma(p0, p2, -ny), c22 = fma(p0, p1, -nx);
+  const cplx u = mk(fma(y.re, z.re, fma(y.im, z.im, -(p2 * x.re))),
+                    fma(y.im, z.re, fma(-y.re, z.im, -(p2 * x.im))));
+  const cplx v = mk(fma(x.re, z.re, fma(-x.im, z.im, -(p1 * y.re))),
+                    fma(x.re, z.im, fma(x.im, z.re, -(p1 * y.im))));
+  const cplx tt = mk(fma(x.re, y.re, fma(x.im, y.im, -(p0 * z.re))),
+                     fma(x.re, y.im, fma(-x.im, y.re, -(p0 * z.im))));
+  int jc = 0;
+  double cjj = c00;
+  if (c11 > cjj) { jc = 1; cjj = c11; }
+  if (c22 > cjj) { jc = 2; cjj = c22; }
   cplx best[3];
-  double nb;
-  {
-    cplx c[3];
-    cross3c(r0, r1, c);
-    nb = cnorm2v(c);
-    best[0] = c[0]; best[1] = c[1]; best[2] = c[2];
-  }
-  {
-    cplx c[3];
-    cross3c(r0, r2, c);
-    const double n = cnorm2v(c);
-    if (n > nb) {
-      best[0] = c[0]; best[1] = c[1]; best[2] = c[2];
-      nb = n;
-    }
-  }
-  {
-    cplx c[3];
-    cross3c(r1, r2, c);
-    const double n = cnorm2v(c);
-    if (n > nb) {
-      best[0] = c[0]; best[1] = c[1]; best[2] = c[2];
-      nb = n;
-    }
-  }
+  best[0] = (jc == 0) ? mk(c00, 0.0) : ((jc == 1) ? u : v);
+  best[1] = (jc == 0) ? conjg(u) : ((jc == 1) ? mk(c11, 0.0) : tt);
+  best[2] = (jc == 0) ? conjg(v) : ((jc == 1) ? conjg(tt) : mk(c22, 0.0));
+  const double nb = cnorm2v(best);
   if (!(nb > 0.0)) return;
   const double hm = -0.5 * l1;
   const double d0 = a0 - hm, d1 = a1 - hm, d2 = a2 - hm;
