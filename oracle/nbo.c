@@ -212,11 +212,11 @@ static inline double norm3(const cx v[3]) {
  * eigenvalues) squares to th^2 times the identity, so
  *   exp(-i K0) psi = e^{-i l1} (v1^+ psi) v1
  *                  + e^{-i hm} [cos(th) P psi - i sin(th)/th (K0 - hm) P psi],
- * the 2x2 propagator of Eq. U on the plane.  th = |(K0 - hm) w| / |w| for any w in the
- * plane.  The traces (of K, and e^{-i hm}) only contribute global phases.  v1 and w are
- * kept unnormalised (v1 = c / |c| with c a column of adj(K0 - l1), w = |c|^2 times the
- * Gram-Schmidt vector), so the intermediate magnitudes grow like |K0|^10: the form holds for
- * 2^-100 < |K0| < 1e30, and |K0|^2 / 2 <= 2^-200 is taken as K0 = 0 (error below 1e-30). */
+ * the 2x2 propagator of Eq. U on the plane, th = |(K0 - hm) w| / |w| for any w in the
+ * plane (here w = P psi).  The traces (of K, and e^{-i hm}) only contribute global phases.
+ * v1 is kept unnormalised (v1 = c / |c| with c a column of adj(K0 - l1)), so intermediate
+ * magnitudes grow like |K0|^5: the form holds for 2^-100 < |K0| < 1e60, and
+ * |K0|^2 / 2 <= 2^-200 is taken as K0 = 0 (error below 1e-30). */
 static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
   const double tr = ((K->d[0] + K->d[1]) + K->d[2]) * (1.0 / 3.0);
   const double a0 = K->d[0] - tr, a1 = K->d[1] - tr, a2 = K->d[2] - tr;
@@ -267,21 +267,6 @@ static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
   else { best[0] = v; best[1] = tt; best[2] = cx_make(c22, 0.0); }
   const double nb = norm3(best);
   if (!(nb > 0.0)) { out[0] = psi[0]; out[1] = psi[1]; out[2] = psi[2]; return; }
-  /* vector of the plane: nb e_m - c conj(c_m), nb times the Gram-Schmidt of the axis m
-   * where c is smallest against c / |c| (its m-th entry nb - |c_m|^2 >= 2 nb / 3) */
-  double nc[3];
-  for (int c = 0; c < 3; ++c) nc[c] = cx_norm2(best[c]);
-  int m = 0;
-  if (nc[1] < nc[m]) m = 1;
-  if (nc[2] < nc[m]) m = 2;
-  cx w[3];
-  for (int c = 0; c < 3; ++c) {
-    if (c == m) w[c] = cx_make(nb - nc[m], 0.0);
-    else {
-      const cx tm = cx_mulc(best[c], best[m]);
-      w[c] = cx_make(-tm.re, -tm.im);
-    }
-  }
   const double hm = -0.5 * l1;
   const double d0 = a0 - hm, d1 = a1 - hm, d2 = a2 - hm;
   /* (K0 - hm) v for a vector v: rows (d0, x, y), (x^*, d1, z), (y^*, z^*, d2), each a
@@ -301,9 +286,6 @@ static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
                      fma(y.re, (v)[0].im, fma(-y.im, (v)[0].re, fma(z.re, (v)[1].im,        \
                          fma(-z.im, (v)[1].re, d2 * (v)[2].im)))));                         \
   } while (0)
-  cx kw[3];
-  NB_KMV(w, kw);
-  const double th = sqrt(norm3(kw) / norm3(w));
   /* al = (c^+ psi) / |c|^2, so that (v1^+ psi) v1 = al c */
   const cx al = cx_rmul(1.0 / nb, inner3(best, psi));
   cx pp[3], kp[3];
@@ -313,6 +295,11 @@ static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
                     fma(-al.re, best[c].im, fma(-al.im, best[c].re, psi[c].im)));
   NB_KMV(pp, kp);
 #undef NB_KMV
+  /* (K0 - hm)^2 = th^2 on the plane: th = |(K0 - hm) P psi| / |P psi|, 0 for P psi = 0 (a
+   * rounding-level component of P psi along v1 perturbs th only where P psi itself is of
+   * that order, so the result stays within rounding of the exact one) */
+  const double npp = norm3(pp);
+  const double th = (npp > 0.0) ? sqrt(norm3(kp) / npp) : 0.0;
   const double phi = l1 - hm;
   double sp, cp, st, ct;
   sincos_spec(phi, &sp, &cp);

@@ -216,10 +216,10 @@ __device__ __forceinline__ double cnorm2v(const cplx v[3]) {
 // K0 - hm with hm = -l1/2 squares to th^2, so the plane is propagated by the closed-form
 // 2x2 exponential of Eq. U:
 //   psi' = e^{-i (l1 - hm)} (v1^+ psi) v1 + cos(th) P psi - i sin(th)/th (K0 - hm) P psi,
-// P = I - v1 v1^+, th = |(K0 - hm) w| / |w| for any w in the plane.  Nothing is normalised:
-// (v1^+ psi) v1 = al c with al = (c^+ psi) / |c|^2, and w = |c|^2 e_m - c conj(c_m) (m the
-// smallest entry of c).  The magnitudes then grow like |K0|^10, which holds for
-// 2^-100 < |K0| < 1e30; |K0|^2 / 2 <= 2^-200 is taken as K0 = 0 (error below 1e-30).
+// P = I - v1 v1^+, th = |(K0 - hm) w| / |w| for any w in the plane, here w = P psi.
+// Nothing is normalised: (v1^+ psi) v1 = al c with al = (c^+ psi) / |c|^2.  The magnitudes
+// then grow like |K0|^5, which holds for 2^-100 < |K0| < 1e60; |K0|^2 / 2 <= 2^-200 is
+// taken as K0 = 0 (error below 1e-30).
 // (K0 - hm) v: rows (d0, x, y), (x^*, d1, z), (y^*, z^*, d2), each a complex dot product
 // with the real diagonal entry, fused from the last product up
 __device__ __forceinline__ void k0_minus(const cplx v[3], double d0, double d1, double d2,
@@ -279,25 +279,6 @@ __device__ __forceinline__ void exp3_apply(const Herm3& K, cplx psi[3]) {
   if (!(nb > 0.0)) return;
   const double hm = -0.5 * l1;
   const double d0 = a0 - hm, d1 = a1 - hm, d2 = a2 - hm;
-  double th;
-  {
-    // vector of the plane: nb e_m - c conj(c_m), m the smallest entry of c
-    const double nc0 = norm2(best[0]), nc1 = norm2(best[1]), nc2 = norm2(best[2]);
-    int m = 0;
-    double ncm = nc0;
-    if (nc1 < ncm) { m = 1; ncm = nc1; }
-    if (nc2 < ncm) { m = 2; ncm = nc2; }
-    const cplx cm = (m == 0) ? best[0] : ((m == 1) ? best[1] : best[2]);
-    cplx w[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const cplx tm = cmul_conjb(best[c], cm);
-      w[c] = (c == m) ? mk(nb - ncm, 0.0) : mk(-tm.re, -tm.im);
-    }
-    cplx kw[3];
-    k0_minus(w, d0, d1, d2, x, y, z, kw);
-    th = sqrt(cnorm2v(kw) / cnorm2v(w));
-  }
   const cplx al = rmul(1.0 / nb, dotc(best, psi));   // (v1^+ psi) v1 = al c
   cplx pp[3], kp[3];
 #pragma unroll
@@ -305,6 +286,9 @@ __device__ __forceinline__ void exp3_apply(const Herm3& K, cplx psi[3]) {
     pp[c] = mk(fma(-al.re, best[c].re, fma(al.im, best[c].im, psi[c].re)),
                fma(-al.re, best[c].im, fma(-al.im, best[c].re, psi[c].im)));
   k0_minus(pp, d0, d1, d2, x, y, z, kp);
+  // (K0 - hm)^2 = th^2 on the plane: th = |(K0 - hm) P psi| / |P psi| (0 for P psi = 0)
+  const double npp = cnorm2v(pp);
+  const double th = (npp > 0.0) ? sqrt(cnorm2v(kp) / npp) : 0.0;
   const double phi = l1 - hm;
   double sp, cp, st, ct;
   sincos_nb(phi, sp, cp);

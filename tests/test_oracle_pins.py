@@ -139,6 +139,36 @@ def test_exp3_against_expm(oracle, kind):
     np.testing.assert_array_equal(oracle.exp3_apply(np.zeros(9), psi), psi)
 
 
+def test_exp3_state_along_isolated_eigenvector(oracle):
+    """psi (almost) along the eigenvector of the largest-magnitude eigenvalue, where the plane
+    component P psi is tiny: against expm for |P psi| from 1e-2 down to 1e-17 and 0 (a
+    diagonal K with a flavour eigenstate), so the plane angle taken from P psi stays harmless."""
+    rng = np.random.default_rng(13)
+    for scale in (0.3, 50.0, 3e4):
+        for _ in range(6):
+            k9 = rng.normal(size=9) * scale
+            H = _herm(k9)
+            ev, V = np.linalg.eigh(H - np.trace(H) / 3 * np.eye(3))
+            i1 = int(np.argmax(np.abs(ev)))
+            v1 = V[:, i1]
+            pl = V[:, [i for i in range(3) if i != i1]] @ (rng.normal(size=2) + 1j * rng.normal(size=2))
+            pl /= np.linalg.norm(pl)
+            for dlt in (1e-2, 1e-6, 1e-10, 1e-14, 1e-17):
+                pv = v1 + dlt * pl
+                pv /= np.linalg.norm(pv)
+                psi = np.empty(6); psi[0::2] = pv.real; psi[1::2] = pv.imag
+                got = oracle.exp3_apply(k9, psi)
+                U = linalg.expm(-1j * H)
+                want = np.outer(U @ pv, (U @ pv).conj())
+                np.testing.assert_allclose(_rho(got), want, atol=3e-15 * max(1.0, scale * 3) + 1e-14)
+    k9 = np.zeros(9); k9[:3] = [3.0, -1.0, 0.5]
+    for e in range(3):
+        psi = np.zeros(6); psi[2 * e] = 1.0
+        got = oracle.exp3_apply(k9, psi)
+        assert np.isfinite(got).all()
+        np.testing.assert_allclose(_rho(got), _rho(psi), atol=1e-15)
+
+
 def test_exp3_magnitude_range(oracle):
     """The unnormalised form's range: |K0| from just above its lower end (1e-29: every
     intermediate about |K0|^10 stays normal) to 1e9, first-order exact at the small end
