@@ -346,6 +346,8 @@ struct nbo_model {
   double dE, du, h, R, lam0, kappa0;
   double *E, *w;            /* E[k]; w[s*NE + k] (includes kappa0 du dE) */
   double *bv;               /* 2f: bx,bz per k; 3f: 6 per k (d0,d1,d2,o01,o02,o12) */
+  double v0[6];             /* 3f: the vacuum Hamiltonian times E (bv of bin k = v0 / E_k) */
+  double *ek;               /* 3f: e_k = 1 / E_k */
   double s1, s0, p2e1, p2e0;/* fixed-point scales 2^e1, 2^e0 and their inverses */
   int e1, e0;
   double *X;                /* state [nb][nsc] */
@@ -468,6 +470,7 @@ int nbo_create(const nbo_params *p, nbo_model **out) {
   m->E = (double *)malloc(sizeof(double) * m->NE);
   m->w = (double *)malloc(sizeof(double) * m->NE * m->ns);
   m->bv = (double *)malloc(sizeof(double) * m->NE * (m->nf == 2 ? 2 : 6));
+  m->ek = (double *)malloc(sizeof(double) * m->NE);
   m->X = (double *)malloc(sizeof(double) * m->nb * m->nsc);
   m->Y = (double *)malloc(sizeof(double) * m->nb * m->nsc);
   /* number luminosities N = L / <E>, <E> = T F3/F2 (Fermi-Dirac, zero chemical potential) */
@@ -518,8 +521,12 @@ int nbo_create(const nbo_params *p, nbo_model **out) {
       const double w2 = ((2.0 * VAC_K) * p->dm2_ev2[0]) / E; /* dm21 / 2E */
       const double w3 = ((2.0 * VAC_K) * p->dm2_ev2[1]) / E; /* dm31 / 2E */
       const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
-      for (int e = 0; e < 6; ++e)
+      for (int e = 0; e < 6; ++e) {
         m->bv[6 * k + e] = (U[ia[e]][1] * U[ib[e]][1]) * w2 + (U[ia[e]][2] * U[ib[e]][2]) * w3;
+        m->v0[e] = (U[ia[e]][1] * U[ib[e]][1]) * ((2.0 * VAC_K) * p->dm2_ev2[0]) +
+                   (U[ia[e]][2] * U[ib[e]][2]) * ((2.0 * VAC_K) * p->dm2_ev2[1]);
+      }
+      m->ek[k] = 1.0 / E;
     }
   }
   /* fixed-point scales: every beam contribution |w rho~| 2^e1 < 2^50 (converted by rounding,
@@ -546,7 +553,7 @@ int nbo_create(const nbo_params *p, nbo_model **out) {
 
 void nbo_destroy(nbo_model *m) {
   if (!m) return;
-  free(m->E); free(m->w); free(m->bv); free(m->X); free(m->Y); free(m->cphi); free(m->sphi);
+  free(m->E); free(m->w); free(m->bv); free(m->ek); free(m->X); free(m->Y); free(m->cphi); free(m->sphi);
   free(m);
 }
 
@@ -683,14 +690,8 @@ static void beam_H3(const nbo_model *m, int s, int64_t k, const radial *g, const
     H->o[2] = cx_make(v[5] - nn[6], nn[7]);
   }
 }
-static herm3 h3_scale(double a, const herm3 *H) {
-  herm3 K;
-  for (int i = 0; i < 3; ++i) K.d[i] = a * H->d[i];
-  for (int i = 0; i < 3; ++i) K.o[i] = cx_make(a * H->o[i].re, a * H->o[i].im);
-  return K;
-}
 
-/* Scaled stage generator of beam b at radius g: 2f f = (h/c) B; 3f K = (h/c) H. */
+/* Scaled stage generator of beam b at radius g: 2f f = (h/c) B (3f: row_gen3 below). */
 static void stage_f2h(const nbo_model *m, int64_t b, const radial *g, const double (*Jm)[8],
                       double h, double f[3]) {
   int s;
@@ -701,17 +702,6 @@ static void stage_f2h(const nbo_model *m, int64_t b, const radial *g, const doub
   double B[3];
   beam_B2(m, s, k, g, &bg, Jm, B);
   f[0] = hc * B[0]; f[1] = hc * B[1]; f[2] = hc * B[2];
-}
-static herm3 stage_K3h(const nbo_model *m, int64_t b, const radial *g, const double (*Jm)[8],
-                       double h) {
-  int s;
-  int64_t j, q, k;
-  beam_of(m, b, &s, &j, &q, &k);
-  const bgeo bg = geo_of(m, g, j, q);
-  const double hc = h / bg.c;
-  herm3 H;
-  beam_H3(m, s, k, g, &bg, Jm, &H);
-  return h3_scale(hc, &H);
 }
 /* the 2-flavour generator of the fixed step h = (r_end - r_start) / n_steps */
 static void stage_f2(const nbo_model *m, int64_t b, const radial *g, const double (*Jm)[8],
@@ -743,6 +733,115 @@ static void apply3(const herm3 *K, const double *x, double *y) {
   for (int c = 0; c < 3; ++c) { y[2 * c] = o[c].re; y[2 * c + 1] = o[c].im; }
 }
 
+/* Three-flavour stage generators by linearity.  Stage i's generator of a beam of energy
+ * bin k is K_i = a_i (V_k + M_i): a_i = h / c_i with c_i = cos(theta) at the stage radius,
+ * V_k = e_k V0 the vacuum Hamiltonian of the bin (e_k = 1 / E_k), M_i the matter and nu-nu
+ * part, which is the same for every energy of a (species, angle) row.  Every generator the
+ * step exponentiates is affine in V_k: with
+ *   i[K_1, K_i] = a_1 a_i i[V_k + M_1, M_i - M_1] = a_1 a_i (e_k i[V0, D] + i[M_1, D]),
+ * D = M_i - M_1, each is G = alpha V_k + e_k P + Q with alpha, P, Q fixed per row:
+ *   K1/2                alpha = a1/2, P = 0, Q = (a1/2) M1
+ *   K3                  alpha = am,   P = 0, Q = am M3
+ *   K2/2 + i[K1,K2]/8   alpha = am/2, P = c i[V0, D], Q = (am/2) M2 + c i[M1, D],
+ *                       c = a1 am / 8, D = M2 - M1
+ *   Theta               alpha = (a1 + 2 am + 2 am + a4)/6, P = c i[V0, D], Q = S/6 + c i[M1, D],
+ *                       c = a1 a4 / 12, D = M4 - M1, S = a1 M1 + 2 am M2 + 2 am M3 + a4 M4
+ * (am: stages 2 and 3 share the radius r + h/2).  The step's error estimate takes
+ * Theta - K2 = (alpha - am) V_k + e_k P + (Q - am M2).  Hermitian 3x3 matrices are
+ * handled here as 9 reals: d0 d1 d2, then re and im of the (0,1), (0,2), (1,2) entries. */
+static void h3_to9(const herm3 *h, double o[9]) {
+  o[0] = h->d[0]; o[1] = h->d[1]; o[2] = h->d[2];
+  for (int i = 0; i < 3; ++i) { o[3 + 2 * i] = h->o[i].re; o[4 + 2 * i] = h->o[i].im; }
+}
+static herm3 h3_from9(const double o[9]) {
+  herm3 h;
+  h.d[0] = o[0]; h.d[1] = o[1]; h.d[2] = o[2];
+  for (int i = 0; i < 3; ++i) h.o[i] = cx_make(o[3 + 2 * i], o[4 + 2 * i]);
+  return h;
+}
+/* M of species s at stage radius g: lam E_ee + nn (nu), -(lam E_ee + nn^*) (nubar) */
+static void matter_M3(const nbo_model *m, int s, const radial *g, const bgeo *bg,
+                      const double (*Jm)[8], double M[9]) {
+  double nn[8];
+  for (int i = 0; i < 8; ++i) nn[i] = nunu_of(m, g, bg, Jm, i);
+  const double sg = m->anti[s] ? -1.0 : 1.0;
+  M[0] = sg * (g->lam + nn[0]);
+  M[1] = sg * nn[1];
+  M[2] = 0.0;
+  for (int i = 0; i < 3; ++i) { M[3 + 2 * i] = sg * nn[2 + 2 * i]; M[4 + 2 * i] = nn[3 + 2 * i]; }
+}
+typedef struct { double alpha, alphaE; double P[9], Q[9], QE[9]; } lingen3;
+/* alpha V_k (+ e_k P) + Q for the six vacuum entries of bin k (v) */
+static herm3 lin3(double alpha, const double *P, const double *Q, const double *v, double ek) {
+  double o[9];
+  for (int i = 0; i < 3; ++i) o[i] = fma(alpha, v[i], P ? fma(ek, P[i], Q[i]) : Q[i]);
+  for (int i = 0; i < 3; ++i) {
+    const int r = 3 + 2 * i, im = 4 + 2 * i;
+    o[r] = fma(alpha, v[3 + i], P ? fma(ek, P[r], Q[r]) : Q[r]);
+    o[im] = P ? fma(ek, P[im], Q[im]) : Q[im];
+  }
+  return h3_from9(o);
+}
+/* The row constants of generator `kind` (1: K1/2, 2: K2/2 + i[K1,K2]/8, 3: K3, 4: Theta)
+ * for the row of beam b; J[i] are the stage moments. */
+static void row_gen3(const nbo_model *m, int64_t b, int kind, const radial *g0, const radial *gm,
+                     const radial *g1, const double (*J)[4][8], double h, lingen3 *L) {
+  int s;
+  int64_t j, q, k;
+  beam_of(m, b, &s, &j, &q, &k);
+  const bgeo b0 = geo_of(m, g0, j, q), bm = geo_of(m, gm, j, q), b1 = geo_of(m, g1, j, q);
+  const double a1 = h / b0.c, am = h / bm.c, a4 = h / b1.c;
+  double M1[9], M2[9], M3[9], M4[9];
+  if (kind != 3) matter_M3(m, s, g0, &b0, J[0], M1);
+  if (kind == 2 || kind == 4) matter_M3(m, s, gm, &bm, J[1], M2);
+  if (kind >= 3) matter_M3(m, s, gm, &bm, J[2], M3);
+  if (kind == 4) matter_M3(m, s, g1, &b1, J[3], M4);
+  if (kind == 1 || kind == 3) {
+    L->alpha = (kind == 1) ? 0.5 * a1 : am;
+    for (int i = 0; i < 9; ++i) L->Q[i] = L->alpha * ((kind == 1) ? M1[i] : M3[i]);
+    return;
+  }
+  const double *Mi = (kind == 2) ? M2 : M4;
+  double D[9];
+  for (int i = 0; i < 9; ++i) D[i] = Mi[i] - M1[i];
+  herm3 V0, Dh = h3_from9(D), M1h = h3_from9(M1);
+  V0.d[0] = m->v0[0]; V0.d[1] = m->v0[1]; V0.d[2] = m->v0[2];
+  for (int i = 0; i < 3; ++i) V0.o[i] = cx_make(m->v0[3 + i], 0.0);
+  const herm3 R1h = h3_icomm(&V0, &Dh), R2h = h3_icomm(&M1h, &Dh);
+  double R1[9], R2[9];
+  h3_to9(&R1h, R1);
+  h3_to9(&R2h, R2);
+  if (kind == 2) {
+    const double c = (a1 * am) * 0.125;
+    L->alpha = 0.5 * am;
+    for (int i = 0; i < 9; ++i) {
+      L->P[i] = c * R1[i];
+      L->Q[i] = fma(L->alpha, M2[i], c * R2[i]);
+    }
+    return;
+  }
+  const double c = (a1 * a4) * (1.0 / 12.0), a2 = 2.0 * am;
+  L->alpha = (((a1 + a2) + a2) + a4) * (1.0 / 6.0);
+  L->alphaE = L->alpha - am;
+  for (int i = 0; i < 9; ++i) {
+    const double S = fma(a4, M4[i], fma(a2, M3[i], fma(a2, M2[i], a1 * M1[i])));
+    L->P[i] = c * R1[i];
+    L->Q[i] = fma(S, 1.0 / 6.0, c * R2[i]);
+    L->QE[i] = fma(-am, M2[i], L->Q[i]);
+  }
+}
+/* generator `kind` of beam b (its row constants, then the bin's vacuum entries) */
+static herm3 gen3_lin(const nbo_model *m, int64_t b, int kind, const radial *g0, const radial *gm,
+                      const radial *g1, const double (*J)[4][8], double h, herm3 *Ediff) {
+  lingen3 L;
+  row_gen3(m, b, kind, g0, gm, g1, J, h, &L);
+  const int64_t k = b % m->NE;
+  const double *v = m->bv + 6 * k;
+  const int wp = (kind == 2 || kind == 4);
+  if (Ediff) *Ediff = lin3(L.alphaE, L.P, L.QE, v, m->ek[k]);
+  return lin3(L.alpha, wp ? L.P : NULL, L.Q, v, m->ek[k]);
+}
+
 /* One RKMK4 step (see the file header) from the state X at r0 over the step length h,
  * with stage radii r0, rm = r0 + h/2 and r1 = r0 + h (r1 passed separately so that the
  * fixed-step grid r_n = r_start + n h is reproduced exactly).  The new state goes to Xout
@@ -755,6 +854,7 @@ static int rkmk4_step(nbo_model *m, const double *X, double r0, double rm, doubl
                       double *Xout, double *emax) {
   const radial g0 = radial_at(m, r0), gm = radial_at(m, rm), g1 = radial_at(m, r1);
   double J[4][4][8];
+  const double (*CJ)[4][8] = (const double (*)[4][8])J;
   int st = moments(m, X, r0, J[0]);
   const int64_t nb = m->nb;
   const int nsc = m->nsc;
@@ -770,8 +870,7 @@ static int rkmk4_step(nbo_model *m, const double *X, double r0, double rm, doubl
       o[0] = 0.5 * f1[0]; o[1] = 0.5 * f1[1]; o[2] = 0.5 * f1[2];
       rotate2(o, x, y);
     } else {
-      herm3 K1 = stage_K3h(m, b, &g0, J[0], h);
-      herm3 O = h3_scale(0.5, &K1);
+      const herm3 O = gen3_lin(m, b, 1, &g0, &gm, &g1, CJ, h, NULL);   /* K1/2 */
       apply3(&O, x, y);
     }
   }
@@ -789,12 +888,7 @@ static int rkmk4_step(nbo_model *m, const double *X, double r0, double rm, doubl
       for (int c = 0; c < 3; ++c) o[c] = 0.5 * f2[c] - 0.125 * cr[c];
       rotate2(o, x, y);
     } else {
-      herm3 K1 = stage_K3h(m, b, &g0, J[0], h);
-      herm3 K2 = stage_K3h(m, b, &gm, J[1], h);
-      herm3 C = h3_icomm(&K1, &K2), O;
-      for (int i = 0; i < 3; ++i) O.d[i] = 0.5 * K2.d[i] + 0.125 * C.d[i];
-      for (int i = 0; i < 3; ++i)
-        O.o[i] = cx_make(0.5 * K2.o[i].re + 0.125 * C.o[i].re, 0.5 * K2.o[i].im + 0.125 * C.o[i].im);
+      const herm3 O = gen3_lin(m, b, 2, &g0, &gm, &g1, CJ, h, NULL);   /* K2/2 + i[K1,K2]/8 */
       apply3(&O, x, y);
     }
   }
@@ -809,7 +903,7 @@ static int rkmk4_step(nbo_model *m, const double *X, double r0, double rm, doubl
       stage_f2h(m, b, &gm, J[2], h, f3);
       rotate2(f3, x, y);
     } else {
-      herm3 K3 = stage_K3h(m, b, &gm, J[2], h);
+      const herm3 K3 = gen3_lin(m, b, 3, &g0, &gm, &g1, CJ, h, NULL);
       apply3(&K3, x, y);
     }
   }
@@ -836,27 +930,14 @@ static int rkmk4_step(nbo_model *m, const double *X, double r0, double rm, doubl
       if (m->p.renorm) renorm2(y);
       xo[0] = y[0]; xo[1] = y[1]; xo[2] = y[2];
     } else {
-      herm3 K1 = stage_K3h(m, b, &g0, J[0], h);
-      herm3 K2 = stage_K3h(m, b, &gm, J[1], h);
-      herm3 K3 = stage_K3h(m, b, &gm, J[2], h);
-      herm3 K4 = stage_K3h(m, b, &g1, J[3], h);
-      herm3 C = h3_icomm(&K1, &K4), T;
-      for (int i = 0; i < 3; ++i)
-        T.d[i] = (((K1.d[i] + 2.0 * K2.d[i]) + 2.0 * K3.d[i]) + K4.d[i]) * (1.0 / 6.0) + C.d[i] * (1.0 / 12.0);
-      for (int i = 0; i < 3; ++i) {
-        const double re = (((K1.o[i].re + 2.0 * K2.o[i].re) + 2.0 * K3.o[i].re) + K4.o[i].re) * (1.0 / 6.0) + C.o[i].re * (1.0 / 12.0);
-        const double im = (((K1.o[i].im + 2.0 * K2.o[i].im) + 2.0 * K3.o[i].im) + K4.o[i].im) * (1.0 / 6.0) + C.o[i].im * (1.0 / 12.0);
-        T.o[i] = cx_make(re, im);
-      }
+      herm3 Ed;
+      const herm3 T = gen3_lin(m, b, 4, &g0, &gm, &g1, CJ, h, eb ? &Ed : NULL);   /* Theta */
       if (eb) {
+        /* |Theta - K2|^2: traceless part, Frobenius norm */
         double a[3], o2[3];
-        const double dd0 = T.d[0] - K2.d[0], dd1 = T.d[1] - K2.d[1], dd2 = T.d[2] - K2.d[2];
-        const double tr = ((dd0 + dd1) + dd2) * (1.0 / 3.0);
-        a[0] = dd0 - tr; a[1] = dd1 - tr; a[2] = dd2 - tr;
-        for (int i = 0; i < 3; ++i) {
-          const double re = T.o[i].re - K2.o[i].re, im = T.o[i].im - K2.o[i].im;
-          o2[i] = re * re + im * im;
-        }
+        const double tr = ((Ed.d[0] + Ed.d[1]) + Ed.d[2]) * (1.0 / 3.0);
+        for (int i = 0; i < 3; ++i) a[i] = Ed.d[i] - tr;
+        for (int i = 0; i < 3; ++i) o2[i] = Ed.o[i].re * Ed.o[i].re + Ed.o[i].im * Ed.o[i].im;
         eb[b] = ((a[0] * a[0] + a[1] * a[1]) + a[2] * a[2]) + 2.0 * ((o2[0] + o2[1]) + o2[2]);
       }
       double y[6];

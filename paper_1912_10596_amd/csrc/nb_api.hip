@@ -85,6 +85,7 @@ struct Sub {
   int NS = 2;                        // species rows: 2, or 2 n_flavor when every flavour is tracked
   double h = 0, lam0 = 0, kappa0 = 0, s1 = 0, s0 = 0, p2e1 = 0, p2e0 = 0;
   double vac_max = 0;                // max over energy bins of sum |H_vac entries|
+  double v0[6] = {0, 0, 0, 0, 0, 0};  // 3f: vacuum Hamiltonian times E (bin k: v0 / E_k)
   long long fp32_from = 0;           // mixed precision: first step run with FP32 arithmetic
   int e1 = 0, e0 = 0, nf = 2;
   std::vector<double> E, tab;
@@ -186,10 +187,10 @@ static void build_tables(Sub* m) {
   // extended model: the azimuthal average (1/2pi) int dphi' becomes the mean over the bins
   const bool ext = p.n_phi > 0;
   const double pref = ext ? ((m->kappa0 * du) * dE) * (1.0 / (double)m->NP) : (m->kappa0 * du) * dE;
-  const int nv = (m->nf == 2) ? 2 : 6;
+  const int nv = (m->nf == 2) ? 2 : kVacRows3;
   m->E.assign(NE, 0.0);
-  // tables: [vacuum terms (nv) | weights G_s of the NS species rows] x NE, then (extended)
-  // cos and sin of the azimuth of every azimuthal bin
+  // tables: [vacuum terms (2f: bx, bz; 3f: 6 entries and e_k = 1/E_k) | weights G_s of the
+  // NS species rows] x NE, then (extended) cos and sin of the azimuth of every azimuthal bin
   const int NS = m->NS;
   m->tab.assign((size_t)(nv + NS) * NE + (ext ? (size_t)2 * m->NP : 0), 0.0);
   if (ext) {
@@ -258,8 +259,12 @@ static void build_tables(Sub* m) {
       const double w2 = ((2.0 * kVac) * p.dm2_ev2[0]) / e;  // dm^2_21 / 2E
       const double w3 = ((2.0 * kVac) * p.dm2_ev2[1]) / e;  // dm^2_31 / 2E
       static const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
-      for (int q = 0; q < 6; ++q)
+      for (int q = 0; q < 6; ++q) {
         m->tab[(size_t)q * NE + k] = (U[ia[q]][1] * U[ib[q]][1]) * w2 + (U[ia[q]][2] * U[ib[q]][2]) * w3;
+        m->v0[q] = (U[ia[q]][1] * U[ib[q]][1]) * ((2.0 * kVac) * p.dm2_ev2[0]) +
+                   (U[ia[q]][2] * U[ib[q]][2]) * ((2.0 * kVac) * p.dm2_ev2[1]);
+      }
+      m->tab[(size_t)6 * NE + k] = 1.0 / e;
     }
   }
   // largest sum of |entries| of the traceless vacuum Hamiltonian over the energy bins
@@ -491,8 +496,9 @@ static Layout layout_of(const nb_model* m) {
 
 extern "C" size_t nb_workspace_bytes(const nb_model* m) { return m ? layout_of(m).need : 0; }
 
-// Energy tables are staged in LDS when they fit in this many bytes per block.
-static constexpr size_t kTabLdsMax = 64 * 1024;
+// Energy tables are staged in LDS when they fit in this many bytes per block (the
+// stepping kernels' static LDS is about 50 KB; a CU holds 160 KB and runs one block).
+static constexpr size_t kTabLdsMax = 96 * 1024;
 
 static size_t tab_bytes(const nb_model* m) { return sizeof(double) * m->tab.size(); }
 static bool tab_in_lds(const nb_model* m) { return !m->batch && tab_bytes(m) <= kTabLdsMax; }
@@ -801,6 +807,7 @@ static int enqueue_advance(nb_model* m, long long k) {
   a.s0 = s.s0;
   a.p2e1 = s.p2e1;
   a.p2e0 = s.p2e0;
+  for (int q = 0; q < 6; ++q) a.v0[q] = s.v0[q];
   a.timeout_ticks = timeout;
   a.Jhist = m->jhist;
   auto launch = [&](const void* fn) -> int {
@@ -909,6 +916,7 @@ extern "C" int nb_run_adaptive(nb_model* m, double tol, double h_max_km, int64_t
   a.s0 = s.s0;
   a.p2e1 = s.p2e1;
   a.p2e0 = s.p2e0;
+  for (int q = 0; q < 6; ++q) a.v0[q] = s.v0[q];
   a.timeout_ticks = m->ticks_per_s * 20ull;
   a.tol2 = tol * tol;
   a.hmax = (h_max_km > 0.0) ? h_max_km : span;
@@ -1192,13 +1200,14 @@ extern "C" int nb_host_tables(const nb_model* m, double* out, int64_t cap) {
   if (m->batch) return fail(NB_EINVAL, "host tables are reported for single models");
   const Sub& s = m->subs[0];
   const int nv = (m->nf == 2) ? 2 : 6;
+  const int rows = (m->nf == 2) ? 2 : kVacRows3;   // table rows before the weights
   const long long NE = s.NE;
   const long long need = NE + (long long)s.NS * NE + nv * NE + 7;
   if (cap < need) return fail(NB_EINVAL, "output too small (%lld needed)", need);
   long long o = 0;
   for (long long k = 0; k < NE; ++k) out[o++] = s.E[k];
   for (int sp = 0; sp < s.NS; ++sp)
-    for (long long k = 0; k < NE; ++k) out[o++] = s.tab[(size_t)(nv + sp) * NE + k];
+    for (long long k = 0; k < NE; ++k) out[o++] = s.tab[(size_t)(rows + sp) * NE + k];
   for (long long k = 0; k < NE; ++k)
     for (int q = 0; q < nv; ++q) out[o++] = s.tab[(size_t)q * NE + k];
   out[o++] = s.lam0;

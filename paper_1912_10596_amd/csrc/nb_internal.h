@@ -27,13 +27,15 @@ constexpr int kSyncPart = kSyncJTag + kFlagCopies * kTagLines * kLineWords;
 constexpr int kSyncWords = kSyncPart + kMaxBlocks * kTagLines * kLineWords;
 constexpr int kTagWords64 = kTagLines * kLineWords / 2;   // 64-bit words per copy or slot
 
+constexpr int kVacRows3 = 7;    // 3f table rows before the weights: 6 vacuum entries and e_k
 constexpr int kBlock = 512;       // threads per block of the stepping kernels (8 waves)
 
 // Arguments of the single-model stepping kernel (passed by value).
 struct StepArgs {
   void* X;                 // state planes [nsc][plane] (double, or float for FP32 state)
-  const double* tab;       // tables: 2f [bx|bz|G_0..G_{NS-1}] x NE; 3f [h_ee..h_mt (6)|G_s] x NE;
-                           // extended model: then cos, sin of every azimuthal bin
+  const double* tab;       // tables: 2f [bx|bz|G_0..G_{NS-1}] x NE; 3f [h_ee..h_mt (6)|e_k|G_s]
+                           // x NE with e_k = 1/E_k; extended model: then cos, sin of every
+                           // azimuthal bin
   unsigned int* sync;      // kSyncWords words (barrier words and the tagged reduction words)
   long long* step_ctl;     // [0] device step counter (read at launch start, advanced at the
                            // end); [1] target of a group of windowed launches
@@ -46,6 +48,7 @@ struct StepArgs {
   double rs, h, R, lam0;
   int ne_power, renorm;
   double s1, s0, p2e1, p2e0;  // fixed-point scales 2^e1, 2^e0, 2^-e1, 2^-e0
+  double v0[6];            // 3f: the vacuum Hamiltonian times E (entries of bin k = e_k v0)
   unsigned long long timeout_ticks;
   double* Jhist;           // nullptr, or [step][4][2*NC]: every stage's moments (adjoint tape)
   int use_window;          // 0: advance min(nsteps, total - step) steps; 1: the window below

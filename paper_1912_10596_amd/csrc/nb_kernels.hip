@@ -436,31 +436,57 @@ __device__ __forceinline__ void stage2(const StepArgs& a, const StepGeo& G, cons
 }
 
 // --------------------------------------------------------------- three flavours
-// K = (h/c) H of beam (s, k): H = H_vac + lam E_ee + nn (neutrinos) or
-// H_vac - lam E_ee - nn^* (antineutrinos); v: the six vacuum entries of energy bin k.
-__device__ __forceinline__ Herm3 gen3(int s, const double* v, double lam, const double* nn,
-                                      double hc) {
-  Herm3 H;
-  if (s == 0) {
-    H.d0 = (v[0] + lam) + nn[0];
-    H.d1 = v[1] + nn[1];
-    H.d2 = v[2];
-    H.o01 = mk(v[3] + nn[2], nn[3]);
-    H.o02 = mk(v[4] + nn[4], nn[5]);
-    H.o12 = mk(v[5] + nn[6], nn[7]);
-  } else {
-    H.d0 = (v[0] - lam) - nn[0];
-    H.d1 = v[1] - nn[1];
-    H.d2 = v[2];
-    H.o01 = mk(v[3] - nn[2], nn[3]);
-    H.o02 = mk(v[4] - nn[4], nn[5]);
-    H.o12 = mk(v[5] - nn[6], nn[7]);
+// Stage generators by linearity.  Stage i's generator of a beam of energy bin k is
+// K_i = a_i (V_k + M_i): a_i = h / cos(theta) at the stage radius, V_k = e_k V0 the vacuum
+// Hamiltonian of the bin (e_k = 1 / E_k), M_i the matter and nu-nu part, the same for
+// every energy of a (species, angle) row.  Every generator the step exponentiates is
+// affine in V_k; with i[K_1, K_i] = a_1 a_i (e_k i[V0, D] + i[M_1, D]), D = M_i - M_1, each
+// is G = alpha V_k + e_k P + Q with alpha, P, Q fixed per row:
+//   K1/2               alpha = a1/2, P = 0, Q = (a1/2) M1
+//   K3                 alpha = am,   P = 0, Q = am M3
+//   K2/2 + i[K1,K2]/8  alpha = am/2, P = c i[V0, D], Q = (am/2) M2 + c i[M1, D], c = a1 am/8
+//   Theta              alpha = (a1 + 2 am + 2 am + a4)/6, P = c i[V0, D],
+//                      Q = S/6 + c i[M1, D], c = a1 a4/12, S = a1 M1 + 2 am M2 + 2 am M3 + a4 M4
+// and the error estimate Theta - K2 = (alpha - am) V_k + e_k P + (Q - am M2).  Per beam that
+// is 6 (no P) or 15 fma.  Hermitian matrices as 9 reals: d0 d1 d2, re/im of (0,1), (0,2),
+// (1,2).
+__device__ __forceinline__ Herm3 h9(const double* o) {
+  return Herm3{o[0], o[1], o[2], mk(o[3], o[4]), mk(o[5], o[6]), mk(o[7], o[8])};
+}
+__device__ __forceinline__ void to9(const Herm3& h, double* o) {
+  o[0] = h.d0; o[1] = h.d1; o[2] = h.d2;
+  o[3] = h.o01.re; o[4] = h.o01.im; o[5] = h.o02.re; o[6] = h.o02.im; o[7] = h.o12.re; o[8] = h.o12.im;
+}
+// M of a stage: lam E_ee + nn (neutrinos), -(lam E_ee + nn^*) (antineutrinos)
+__device__ __forceinline__ void matter_m3(int an, double lam, const double* nn, double* M) {
+  const double sg = an ? -1.0 : 1.0;
+  M[0] = sg * (lam + nn[0]);
+  M[1] = sg * nn[1];
+  M[2] = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    M[3 + 2 * i] = sg * nn[2 + 2 * i];
+    M[4 + 2 * i] = nn[3 + 2 * i];
   }
-  return hscale(hc, H);
+}
+// alpha V_k + Q
+__device__ __forceinline__ Herm3 lin3q(double alpha, const double* Q, const double* v) {
+  return Herm3{fma(alpha, v[0], Q[0]), fma(alpha, v[1], Q[1]), fma(alpha, v[2], Q[2]),
+               mk(fma(alpha, v[3], Q[3]), Q[4]), mk(fma(alpha, v[4], Q[5]), Q[6]),
+               mk(fma(alpha, v[5], Q[7]), Q[8])};
+}
+// alpha V_k + e_k P + Q
+__device__ __forceinline__ Herm3 lin3p(double alpha, const double* P, const double* Q, const double* v,
+                                       double ek) {
+  return Herm3{fma(alpha, v[0], fma(ek, P[0], Q[0])), fma(alpha, v[1], fma(ek, P[1], Q[1])),
+               fma(alpha, v[2], fma(ek, P[2], Q[2])),
+               mk(fma(alpha, v[3], fma(ek, P[3], Q[3])), fma(ek, P[4], Q[4])),
+               mk(fma(alpha, v[4], fma(ek, P[5], Q[5])), fma(ek, P[6], Q[6])),
+               mk(fma(alpha, v[5], fma(ek, P[7], Q[7])), fma(ek, P[8], Q[8]))};
 }
 
-// Row-wise nn terms of the four stage slots live in LDS (one 32-double block per wave)
-// and are re-read per beam, so the compiler does not keep all of them in registers.
+// The row constants Q, P (and the error estimate's Q) live in LDS (one 32-double block per
+// wave) and are re-read per beam, so the compiler does not keep all of them in registers.
 // One (species, emission bin) row of the three-flavour stage, FP64 arithmetic.
 // ADAPT (final update only): the new state goes to Xo instead of X, and emax keeps the
 // largest embedded error estimate |Theta - K2|^2 (traceless part, Frobenius norm).
@@ -481,7 +507,7 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
     const int p = (int)(row - sj * a.NP);
     s = (int)(sj / a.NU);
     j = (int)(sj - (long long)s * a.NU);
-    const double* phi = a.tab + (size_t)(6 + a.NS) * a.NE;
+    const double* phi = a.tab + (size_t)(kVacRows3 + a.NS) * a.NE;
     cp = phi[p];
     sp = phi[a.NP + p];
   } else {
@@ -494,26 +520,63 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
   const double icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
   const double sn0 = EXT ? sqrt(u * g0.q2) : 0.0, snm = EXT ? sqrt(u * gm.q2) : 0.0;
   const double sn1 = EXT ? sqrt(u * g1.q2) : 0.0;
-  {
-    double t[8];
-    if (KIND == 1 || KIND == 2 || KIND == 4) {
-      nunu_row<8, EXT>(sJ[0], g0.mu, rg.c0, sn0, cp, sp, t);
-      for (int i = 0; i < 8; ++i) snn[i] = t[i];
+  double alpha = 0.0, alphaE = 0.0;
+  if constexpr (KIND >= 1) {
+    // row constants: snn[0..8] Q, [9..17] P, [18..26] Q of Theta - K2
+    double nn[8], M1[9], M2[9], M3[9], M4[9];
+    if (KIND != 3) {
+      nunu_row<8, EXT>(sJ[0], g0.mu, rg.c0, sn0, cp, sp, nn);
+      matter_m3(an, g0.lam, nn, M1);
     }
     if (KIND == 2 || KIND == 4) {
-      nunu_row<8, EXT>(sJ[1], gm.mu, rg.cm, snm, cp, sp, t);
-      for (int i = 0; i < 8; ++i) snn[8 + i] = t[i];
+      nunu_row<8, EXT>(sJ[1], gm.mu, rg.cm, snm, cp, sp, nn);
+      matter_m3(an, gm.lam, nn, M2);
     }
     if (KIND >= 3) {
-      nunu_row<8, EXT>(sJ[2], gm.mu, rg.cm, snm, cp, sp, t);
-      for (int i = 0; i < 8; ++i) snn[16 + i] = t[i];
+      nunu_row<8, EXT>(sJ[2], gm.mu, rg.cm, snm, cp, sp, nn);
+      matter_m3(an, gm.lam, nn, M3);
     }
     if (KIND == 4) {
-      nunu_row<8, EXT>(sJ[3], g1.mu, rg.c1, sn1, cp, sp, t);
-      for (int i = 0; i < 8; ++i) snn[24 + i] = t[i];
+      nunu_row<8, EXT>(sJ[3], g1.mu, rg.c1, sn1, cp, sp, nn);
+      matter_m3(an, g1.lam, nn, M4);
+    }
+    if (KIND == 1 || KIND == 3) {
+      alpha = (KIND == 1) ? 0.5 * rg.hc0 : rg.hcm;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) snn[i] = alpha * ((KIND == 1) ? M1[i] : M3[i]);
+    } else {
+      const double* Mi = (KIND == 2) ? M2 : M4;
+      double D[9], R1[9], R2[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) D[i] = Mi[i] - M1[i];
+      const Herm3 Dh = h9(D);
+      const Herm3 V0{a.v0[0], a.v0[1], a.v0[2], mk(a.v0[3], 0.0), mk(a.v0[4], 0.0), mk(a.v0[5], 0.0)};
+      to9(icomm(V0, Dh), R1);
+      to9(icomm(h9(M1), Dh), R2);
+      if (KIND == 2) {
+        const double c = (rg.hc0 * rg.hcm) * 0.125;
+        alpha = 0.5 * rg.hcm;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          snn[9 + i] = c * R1[i];
+          snn[i] = fma(alpha, M2[i], c * R2[i]);
+        }
+      } else {
+        const double c = (rg.hc0 * rg.hc1) * (1.0 / 12.0), a2 = 2.0 * rg.hcm;
+        alpha = (((rg.hc0 + a2) + a2) + rg.hc1) * (1.0 / 6.0);
+        alphaE = alpha - rg.hcm;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          const double S = fma(rg.hc1, M4[i], fma(a2, M3[i], fma(a2, M2[i], rg.hc0 * M1[i])));
+          const double Qi = fma(S, 1.0 / 6.0, c * R2[i]);
+          snn[9 + i] = c * R1[i];
+          snn[i] = Qi;
+          if (ADAPT) snn[18 + i] = fma(-rg.hcm, M2[i], Qi);
+        }
+      }
     }
   }
-  const double* G = tab + (size_t)(6 + s) * NE;
+  const double* G = tab + (size_t)(kVacRows3 + s) * NE;
   const long long rb = row * NE;
   I128 mine = i128_zero();
   for (int k0 = lane; k0 - lane < NE; k0 += 64 * 32) {
@@ -542,50 +605,21 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
         double v[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) v[c] = tab[c * NE + k];
-        Herm3 K1;
-        if (KIND != 3) K1 = gen3(an, v, g0.lam, snn, rg.hc0);
-        if (KIND == 1) {
-          exp3_apply(hscale(0.5, K1), ps);
+        if (KIND == 1 || KIND == 3) {
+          exp3_apply(lin3q(alpha, snn, v), ps);
         } else if (KIND == 2) {
-          const Herm3 K2 = gen3(an, v, gm.lam, snn + 8, rg.hcm);
-          const Herm3 C = icomm(K1, K2);
-          Herm3 O;
-          O.d0 = 0.5 * K2.d0 + 0.125 * C.d0;
-          O.d1 = 0.5 * K2.d1 + 0.125 * C.d1;
-          O.d2 = 0.5 * K2.d2 + 0.125 * C.d2;
-          O.o01 = mk(0.5 * K2.o01.re + 0.125 * C.o01.re, 0.5 * K2.o01.im + 0.125 * C.o01.im);
-          O.o02 = mk(0.5 * K2.o02.re + 0.125 * C.o02.re, 0.5 * K2.o02.im + 0.125 * C.o02.im);
-          O.o12 = mk(0.5 * K2.o12.re + 0.125 * C.o12.re, 0.5 * K2.o12.im + 0.125 * C.o12.im);
-          exp3_apply(O, ps);
-        } else if (KIND == 3) {
-          exp3_apply(gen3(an, v, gm.lam, snn + 16, rg.hcm), ps);
+          exp3_apply(lin3p(alpha, snn + 9, snn, v, tab[6 * NE + k]), ps);
         } else {
-          // Theta = (((K1 + 2 K2) + 2 K3) + K4)/6 + i[K1,K4]/12, accumulated in that order
-          Herm3 acc3 = K1;
-          const Herm3 K2 = gen3(an, v, gm.lam, snn + 8, rg.hcm);
-          haxpy(acc3, 2.0, K2);
-          haxpy(acc3, 2.0, gen3(an, v, gm.lam, snn + 16, rg.hcm));
-          const Herm3 K4 = gen3(an, v, g1.lam, snn + 24, rg.hc1);
-          hadd(acc3, K4);
-          const Herm3 C = icomm(K1, K4);
-          Herm3 Th;
-          Th.d0 = acc3.d0 * (1.0 / 6.0) + C.d0 * (1.0 / 12.0);
-          Th.d1 = acc3.d1 * (1.0 / 6.0) + C.d1 * (1.0 / 12.0);
-          Th.d2 = acc3.d2 * (1.0 / 6.0) + C.d2 * (1.0 / 12.0);
-          Th.o01 = mk(acc3.o01.re * (1.0 / 6.0) + C.o01.re * (1.0 / 12.0),
-                      acc3.o01.im * (1.0 / 6.0) + C.o01.im * (1.0 / 12.0));
-          Th.o02 = mk(acc3.o02.re * (1.0 / 6.0) + C.o02.re * (1.0 / 12.0),
-                      acc3.o02.im * (1.0 / 6.0) + C.o02.im * (1.0 / 12.0));
-          Th.o12 = mk(acc3.o12.re * (1.0 / 6.0) + C.o12.re * (1.0 / 12.0),
-                      acc3.o12.im * (1.0 / 6.0) + C.o12.im * (1.0 / 12.0));
+          const double ek = tab[6 * NE + k];
+          const Herm3 Th = lin3p(alpha, snn + 9, snn, v, ek);
           if (ADAPT) {
-            const double dd0 = Th.d0 - K2.d0, dd1 = Th.d1 - K2.d1, dd2 = Th.d2 - K2.d2;
-            const double tr = ((dd0 + dd1) + dd2) * (1.0 / 3.0);
-            const double a0 = dd0 - tr, a1 = dd1 - tr, a2 = dd2 - tr;
-            const double x0 = Th.o01.re - K2.o01.re, y0 = Th.o01.im - K2.o01.im;
-            const double x1 = Th.o02.re - K2.o02.re, y1 = Th.o02.im - K2.o02.im;
-            const double x2 = Th.o12.re - K2.o12.re, y2 = Th.o12.im - K2.o12.im;
-            const double o0 = x0 * x0 + y0 * y0, o1 = x1 * x1 + y1 * y1, o2 = x2 * x2 + y2 * y2;
+            // |Theta - K2|^2: traceless part, Frobenius norm
+            const Herm3 Ed = lin3p(alphaE, snn + 9, snn + 18, v, ek);
+            const double tr = ((Ed.d0 + Ed.d1) + Ed.d2) * (1.0 / 3.0);
+            const double a0 = Ed.d0 - tr, a1 = Ed.d1 - tr, a2 = Ed.d2 - tr;
+            const double o0 = Ed.o01.re * Ed.o01.re + Ed.o01.im * Ed.o01.im;
+            const double o1 = Ed.o02.re * Ed.o02.re + Ed.o02.im * Ed.o02.im;
+            const double o2 = Ed.o12.re * Ed.o12.re + Ed.o12.im * Ed.o12.im;
             const double e = ((a0 * a0 + a1 * a1) + a2 * a2) + 2.0 * ((o0 + o1) + o2);
             emax = (e > emax) ? e : emax;
           }
@@ -731,7 +765,7 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
       }
     }
   }
-  const double* G = tab + (size_t)(6 + s) * NE;
+  const double* G = tab + (size_t)(kVacRows3 + s) * NE;
   const long long rb = row * NE;
   I128 mine = i128_zero();
   for (int k0 = lane; k0 - lane < NE; k0 += kSeg) {
@@ -866,7 +900,7 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   const long long nw = (long long)gridDim.x * (kBlock / 64);
   const double* tab = a.tab;
   if constexpr (TLDS) {
-    const int ntab = ((NF == 2) ? 2 : 6) * a.NE + a.NS * a.NE;
+    const int ntab = ((NF == 2) ? 2 : kVacRows3) * a.NE + a.NS * a.NE;
     for (int i = threadIdx.x; i < ntab; i += kBlock) dyn_tab[i] = a.tab[i];
     __syncthreads();
     tab = dyn_tab;
@@ -970,7 +1004,7 @@ __global__ void __launch_bounds__(kBlock) k_adaptive(StepArgs a) {
   const long long nw = (long long)gridDim.x * (kBlock / 64);
   const double* tab = a.tab;
   if constexpr (TLDS) {
-    const int ntab = ((NF == 2) ? 2 : 6) * a.NE + a.NS * a.NE;
+    const int ntab = ((NF == 2) ? 2 : kVacRows3) * a.NE + a.NS * a.NE;
     for (int i = threadIdx.x; i < ntab; i += kBlock) dyn_tab[i] = a.tab[i];
     __syncthreads();
     tab = dyn_tab;
