@@ -1,10 +1,10 @@
 // nb_device32.h -- single-precision per-beam arithmetic of the mixed-precision stepper.
 //
-// The same operations as the FP64 primitives of nb_device.h (stage generator, the exact
-// 3x3 exponential exp(-iK) psi, the commutator i[A,B]) carried out in FP32 for the
-// NB_FP32_STATE mode.  There is no bit-for-bit contract here: divisions use the hardware
-// reciprocal, sin/cos a short polynomial after a three-part reduction, and the moment sums
-// and the renormalisation stay in FP64 in the caller.  Accuracy is that of FP32 per step;
+// The exact 3x3 exponential exp(-iK) psi of nb_device.h carried out in FP32 for the
+// NB_FP32_STATE mode (the generators come from FP64 row constants in the caller).  There
+// is no bit-for-bit contract here: divisions use the hardware reciprocal, sin/cos a short
+// polynomial after a three-part reduction, and the moment sums and the renormalisation
+// stay in FP64 in the caller.  Accuracy is that of FP32 per step;
 // rotation angles must stay well below 2^15 (pi/2 multiples) for the reduction to hold.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -39,6 +39,28 @@ __device__ __forceinline__ void sincos_f(float x, float& sn, float& cs) {
   cs = (q == 0) ? c : ((q == 1) ? -s : ((q == 2) ? -c : s));
 }
 __device__ __forceinline__ float rcp_f(float x) { return __builtin_amdgcn_rcpf(x); }
+// cos x - 1 and sin(x)/x from x2 = x^2 for x^2 <= 4, without range reduction: Taylor series
+// to x^16 / 16! and x^14 / 15! (remainders below 4e-9 at |x| = 2); cos x - 1 is accurate
+// relative to its own size.
+__device__ __forceinline__ void cosm1_sinc_f(float x2, float& cm1, float& snc) {
+  float pc = 1.0f / 20922789888000.0f;
+  pc = fmaf(pc, x2, -1.0f / 87178291200.0f);
+  pc = fmaf(pc, x2, 1.0f / 479001600.0f);
+  pc = fmaf(pc, x2, -1.0f / 3628800.0f);
+  pc = fmaf(pc, x2, 1.0f / 40320.0f);
+  pc = fmaf(pc, x2, -1.0f / 720.0f);
+  pc = fmaf(pc, x2, 1.0f / 24.0f);
+  pc = fmaf(pc, x2, -0.5f);
+  cm1 = x2 * pc;
+  float ps = -1.0f / 1307674368000.0f;
+  ps = fmaf(ps, x2, 1.0f / 6227020800.0f);
+  ps = fmaf(ps, x2, -1.0f / 39916800.0f);
+  ps = fmaf(ps, x2, 1.0f / 362880.0f);
+  ps = fmaf(ps, x2, -1.0f / 5040.0f);
+  ps = fmaf(ps, x2, 1.0f / 120.0f);
+  ps = fmaf(ps, x2, -1.0f / 6.0f);
+  snc = fmaf(ps, x2, 1.0f);
+}
 
 struct cplxf {
   float re, im;
@@ -63,46 +85,6 @@ struct Herm3f {
   float d0, d1, d2;
   cplxf o01, o02, o12;
 };
-__device__ __forceinline__ cplxf hatf(const Herm3f& h, int a, int b) {
-  if (a == b) return mkf(a == 0 ? h.d0 : (a == 1 ? h.d1 : h.d2), 0.0f);
-  const cplxf o = (a + b == 1) ? h.o01 : ((a + b == 2) ? h.o02 : h.o12);
-  return a < b ? o : conjf_(o);
-}
-__device__ __forceinline__ Herm3f hscalef(float s, const Herm3f& h) {
-  return Herm3f{s * h.d0, s * h.d1, s * h.d2, rmulf(s, h.o01), rmulf(s, h.o02), rmulf(s, h.o12)};
-}
-__device__ __forceinline__ void haxpyf(Herm3f& acc, float a, const Herm3f& K) {
-  acc.d0 = fmaf(a, K.d0, acc.d0);
-  acc.d1 = fmaf(a, K.d1, acc.d1);
-  acc.d2 = fmaf(a, K.d2, acc.d2);
-  acc.o01 = mkf(fmaf(a, K.o01.re, acc.o01.re), fmaf(a, K.o01.im, acc.o01.im));
-  acc.o02 = mkf(fmaf(a, K.o02.re, acc.o02.re), fmaf(a, K.o02.im, acc.o02.im));
-  acc.o12 = mkf(fmaf(a, K.o12.re, acc.o12.re), fmaf(a, K.o12.im, acc.o12.im));
-}
-// C(A,B) = i [A,B]
-__device__ __forceinline__ Herm3f icommf(const Herm3f& A, const Herm3f& B) {
-  cplxf X[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-      X[a][b] = caddf(caddf(cmulf(hatf(A, a, 0), hatf(B, 0, b)), cmulf(hatf(A, a, 1), hatf(B, 1, b))),
-                      cmulf(hatf(A, a, 2), hatf(B, 2, b)));
-  Herm3f C;
-  C.d0 = -2.0f * X[0][0].im;
-  C.d1 = -2.0f * X[1][1].im;
-  C.d2 = -2.0f * X[2][2].im;
-  C.o01 = mkf(-(X[0][1].im + X[1][0].im), X[0][1].re - X[1][0].re);
-  C.o02 = mkf(-(X[0][2].im + X[2][0].im), X[0][2].re - X[2][0].re);
-  C.o12 = mkf(-(X[1][2].im + X[2][1].im), X[1][2].re - X[2][1].re);
-  return C;
-}
-
-__device__ __forceinline__ void cross3cf(const cplxf u[3], const cplxf v[3], cplxf o[3]) {
-  o[0] = csubf(cmulf(u[1], v[2]), cmulf(u[2], v[1]));
-  o[1] = csubf(cmulf(u[2], v[0]), cmulf(u[0], v[2]));
-  o[2] = csubf(cmulf(u[0], v[1]), cmulf(u[1], v[0]));
-}
 __device__ __forceinline__ float cnorm2vf(const cplxf v[3]) {
   return (norm2f(v[0]) + norm2f(v[1])) + norm2f(v[2]);
 }
@@ -114,14 +96,18 @@ __device__ __forceinline__ void k0_minusf(const cplxf v[3], float d0, float d1, 
 }
 
 // Eigen-split of exp(-i K) in FP32, the algorithm of the FP64 version (largest eigenvalue
-// by Newton on the characteristic cubic, its eigenvector from the largest row cross
-// product): psi = al v1 + pp with pp orthogonal to v1, kp = (K0 - hm) pp, and the phases
-// phi (of v1) and th (of the orthogonal plane), so that
+// by Halley steps on the characteristic cubic, its eigenvector from the column of
+// adj(K0 - l1) with the largest diagonal entry, the plane angle from P psi), except that
+// v1 is normalised with the hardware rsqrt (FP32 cannot hold |K0|^5): psi = al v1 + pp with
+// pp orthogonal to v1, kp = (K0 - hm) pp, and the phases phi (of v1) and th (of the
+// orthogonal plane), so that
 //   exp(-i K) psi = e^{-i phi} al v1 + cos(th) pp - i sin(th)/th kp   (global phase dropped).
-// Returns false if K is zero (exp(-iK) psi = psi up to a phase).
+// Returns false if K is zero (exp(-iK) psi = psi up to a phase).  The caller evaluates the
+// phases without range reduction when |phi| and th are at most 2 (the resolved steps this
+// mode runs, where every generator's eigenvalues stay near or below one).
 struct Split3f {
   cplxf v1[3], pp[3], kp[3], al;
-  float phi, th;
+  float phi, th2;   // th2 = th^2
 };
 __device__ __forceinline__ bool split3_f(const Herm3f& K, const cplxf psi[3], Split3f& o) {
   const float tr = ((K.d0 + K.d1) + K.d2) * (1.0f / 3.0f);
@@ -138,84 +124,71 @@ __device__ __forceinline__ bool split3_f(const Herm3f& K, const cplxf psi[3], Sp
   const float qa = sg * q;
   float lam = 2.0f * sqrtf(p * (1.0f / 3.0f));
 #pragma unroll
-  for (int it = 0; it < 5; ++it) {
+  for (int it = 0; it < 3; ++it) {
     const float l2 = lam * lam;
     const float fv = fmaf(lam, l2 - p, -qa);
     const float dv = fmaf(3.0f, l2, -p);
-    lam = lam - fv * rcp_f(dv);
+    const float den = fmaf(dv, dv, -((3.0f * lam) * fv));
+    lam = lam - (fv * dv) * rcp_f(den);
   }
   const float l1 = sg * lam;
-  const cplxf r0[3] = {mkf(a0 - l1, 0.0f), x, y};
-  const cplxf r1[3] = {conjf_(x), mkf(a1 - l1, 0.0f), z};
-  const cplxf r2[3] = {conjf_(y), conjf_(z), mkf(a2 - l1, 0.0f)};
+  const float p0 = a0 - l1, p1 = a1 - l1, p2 = a2 - l1;
+  const float c00 = fmaf(p1, p2, -nz), c11 = fmaf(p0, p2, -ny), c22 = fmaf(p0, p1, -nx);
+  const cplxf u = mkf(fmaf(y.re, z.re, fmaf(y.im, z.im, -(p2 * x.re))), fmaf(y.im, z.re, fmaf(-y.re, z.im, -(p2 * x.im))));
+  const cplxf v = mkf(fmaf(x.re, z.re, fmaf(-x.im, z.im, -(p1 * y.re))), fmaf(x.re, z.im, fmaf(x.im, z.re, -(p1 * y.im))));
+  const cplxf tt = mkf(fmaf(x.re, y.re, fmaf(x.im, y.im, -(p0 * z.re))), fmaf(x.re, y.im, fmaf(-x.im, y.re, -(p0 * z.im))));
+  int jc = 0;
+  float cjj = c00;
+  if (c11 > cjj) { jc = 1; cjj = c11; }
+  if (c22 > cjj) { jc = 2; cjj = c22; }
   cplxf best[3];
-  float nb;
-  {
-    cplxf c[3];
-    cross3cf(r0, r1, c);
-    nb = cnorm2vf(c);
-    best[0] = c[0]; best[1] = c[1]; best[2] = c[2];
-  }
-  {
-    cplxf c[3];
-    cross3cf(r0, r2, c);
-    const float n = cnorm2vf(c);
-    if (n > nb) {
-      best[0] = c[0]; best[1] = c[1]; best[2] = c[2];
-      nb = n;
-    }
-  }
-  {
-    cplxf c[3];
-    cross3cf(r1, r2, c);
-    const float n = cnorm2vf(c);
-    if (n > nb) {
-      best[0] = c[0]; best[1] = c[1]; best[2] = c[2];
-      nb = n;
-    }
-  }
+  best[0] = (jc == 0) ? mkf(c00, 0.0f) : ((jc == 1) ? u : v);
+  best[1] = (jc == 0) ? conjf_(u) : ((jc == 1) ? mkf(c11, 0.0f) : tt);
+  best[2] = (jc == 0) ? conjf_(v) : ((jc == 1) ? conjf_(tt) : mkf(c22, 0.0f));
+  const float nb = cnorm2vf(best);
   if (!(nb > 0.0f)) return false;
   const float inb = rsqrtf(nb);
 #pragma unroll
   for (int c = 0; c < 3; ++c) o.v1[c] = rmulf(inb, best[c]);
   const float hm = -0.5f * l1;
   const float d0 = a0 - hm, d1 = a1 - hm, d2 = a2 - hm;
-  {
-    const float nc0 = norm2f(o.v1[0]), nc1 = norm2f(o.v1[1]), nc2 = norm2f(o.v1[2]);
-    int m = 0;
-    float ncm = nc0;
-    if (nc1 < ncm) { m = 1; ncm = nc1; }
-    if (nc2 < ncm) { m = 2; ncm = nc2; }
-    const cplxf vm = (m == 0) ? o.v1[0] : ((m == 1) ? o.v1[1] : o.v1[2]);
-    cplxf w[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const cplxf tm = cmulf_conjb(o.v1[c], vm);
-      w[c] = (c == m) ? mkf(1.0f - ncm, 0.0f) : mkf(-tm.re, -tm.im);
-    }
-    const float inw = rsqrtf(cnorm2vf(w));
-    const cplxf u[3] = {rmulf(inw, w[0]), rmulf(inw, w[1]), rmulf(inw, w[2])};
-    cplxf ku[3];
-    k0_minusf(u, d0, d1, d2, x, y, z, ku);
-    o.th = sqrtf(cnorm2vf(ku));
-  }
   o.al = caddf(caddf(cmulf_conja(o.v1[0], psi[0]), cmulf_conja(o.v1[1], psi[1])),
                cmulf_conja(o.v1[2], psi[2]));
 #pragma unroll
   for (int c = 0; c < 3; ++c) o.pp[c] = csubf(psi[c], cmulf(o.al, o.v1[c]));
   k0_minusf(o.pp, d0, d1, d2, x, y, z, o.kp);
+  // (K0 - hm)^2 = th^2 on the plane: th^2 = |kp|^2 / |pp|^2 (0 for pp = 0)
+  const float npp = cnorm2vf(o.pp);
+  o.th2 = (npp > 0.0f) ? cnorm2vf(o.kp) * rcp_f(npp) : 0.0f;
   o.phi = l1 - hm;
   return true;
 }
 
+// cos and sin of phi, cos th and sin(th)/th: Taylor series in phi^2 and th^2 when both
+// are at most 4, else range reduction.
+__device__ __forceinline__ void phases_f(const Split3f& e, float& cp, float& sp, float& ct, float& sc) {
+  const float p2 = e.phi * e.phi;
+  if (p2 <= 4.0f && e.th2 <= 4.0f) {
+    float cm1, snc;
+    cosm1_sinc_f(p2, cm1, snc);
+    cp = 1.0f + cm1;
+    sp = e.phi * snc;
+    cosm1_sinc_f(e.th2, cm1, sc);
+    ct = 1.0f + cm1;
+  } else {
+    const float th = sqrtf(e.th2);
+    float st;
+    sincos_f(e.phi, sp, cp);
+    sincos_f(th, st, ct);
+    sc = (th > 0.0f) ? st * rcp_f(th) : 1.0f;
+  }
+}
 // psi <- exp(-i K) psi (up to a global phase) in FP32.
 __device__ __forceinline__ void exp3_apply_f(const Herm3f& K, cplxf psi[3]) {
   Split3f e;
   if (!split3_f(K, psi, e)) return;
-  float sp, cp, st, ct;
-  sincos_f(e.phi, sp, cp);
-  sincos_f(e.th, st, ct);
-  const float sc = (e.th > 0.0f) ? st * rcp_f(e.th) : 1.0f;
+  float sp, cp, ct, sc;
+  phases_f(e, cp, sp, ct, sc);
   const cplxf ap = cmulf(e.al, mkf(cp, -sp));
 #pragma unroll
   for (int c = 0; c < 3; ++c)
@@ -233,12 +206,23 @@ __device__ __forceinline__ void exp3_incr_f(const Herm3f& K, const cplxf psi[3],
     d[0] = d[1] = d[2] = mkf(0.0f, 0.0f);
     return;
   }
-  float sh, ch, tsh, tch;
-  sincos_f(0.5f * e.phi, sh, ch);
-  sincos_f(0.5f * e.th, tsh, tch);
-  const float cpm1 = -2.0f * (sh * sh), sp = 2.0f * (sh * ch);
-  const float ctm1 = -2.0f * (tsh * tsh);
-  const float sc = (e.th > 0.0f) ? (2.0f * (tsh * tch)) * rcp_f(e.th) : 1.0f;
+  float cpm1, sp, ctm1, sc;
+  const float p2 = e.phi * e.phi;
+  if (p2 <= 4.0f && e.th2 <= 4.0f) {
+    float snc;
+    cosm1_sinc_f(p2, cpm1, snc);
+    sp = e.phi * snc;
+    cosm1_sinc_f(e.th2, ctm1, sc);
+  } else {
+    const float th = sqrtf(e.th2);
+    float sh, ch, tsh, tch;
+    sincos_f(0.5f * e.phi, sh, ch);
+    sincos_f(0.5f * th, tsh, tch);
+    cpm1 = -2.0f * (sh * sh);
+    sp = 2.0f * (sh * ch);
+    ctm1 = -2.0f * (tsh * tsh);
+    sc = (th > 0.0f) ? (2.0f * (tsh * tch)) * rcp_f(th) : 1.0f;
+  }
   const cplxf ap = cmulf(e.al, mkf(cpm1, -sp));
 #pragma unroll
   for (int c = 0; c < 3; ++c)
