@@ -13,6 +13,7 @@
 
 namespace nb {
 
+constexpr double kTwo56 = 72057594037927936.0;
 constexpr double kTwo62 = 4611686018427387904.0;
 constexpr double kTwo64 = 18446744073709551616.0;
 

@@ -256,28 +256,31 @@ __device__ __forceinline__ unsigned long long fix_base(int k0, int kend) {
 // sums of component v % NC.  Integer sums, so the order does not matter.
 template <int NC, int NM = 2>
 __device__ __forceinline__ void fold_segment(const long long* acc, int lane, long long* fl, I128& mine) {
+  // Every lane sum is below 2^56 in magnitude (at most 32 contributions below 2^51, or a
+  // mixed-precision lane sum converted below 2^56), so one component's 64 lane sums add up
+  // below 2^62: plain 64-bit integer sums, widened to 128 bits once per segment.
   constexpr int G = 64 / NC, L = (64 + G - 1) / G;
 #pragma unroll
   for (int i = 0; i < NC; ++i) fl[i * 64 + lane] = acc[i];
   __asm__ volatile("" ::: "memory");   // the wave's LDS operations complete in program order
-  I128* gs = reinterpret_cast<I128*>(fl + NC * 64);
+  long long* gs = fl + NC * 64;
   const int c = lane % NC, g = lane / NC;
   if (g < G) {
-    I128 part = i128_zero();
+    long long part = 0;
 #pragma unroll
     for (int i = 0; i < L; ++i) {
       const int src = g * L + i;
-      if (src < 64) part = i128_add(part, i128_from(fl[c * 64 + src]));
+      if (src < 64) part += fl[c * 64 + src];
     }
     gs[g * NC + c] = part;
   }
   __asm__ volatile("" ::: "memory");
   if (lane < NM * NC) {
     const int cc = lane % NC;
-    I128 t = i128_zero();
+    long long t = 0;
 #pragma unroll
-    for (int gg = 0; gg < G; ++gg) t = i128_add(t, gs[gg * NC + cc]);
-    mine = i128_add(mine, t);
+    for (int gg = 0; gg < G; ++gg) t += gs[gg * NC + cc];
+    mine = i128_add(mine, i128_from(t));
   }
   __asm__ volatile("" ::: "memory");
 }
@@ -705,7 +708,8 @@ __device__ __forceinline__ void prefetch_first(const StepArgs& a, long long gw, 
 // One row of the mixed-precision stage with FP32 per-beam arithmetic.
 // The moment contributions of a lane's beams (k = lane mod 64 within a segment of 64 x 16
 // beams) are summed in FP64 and converted to fixed point once per segment, so the total
-// does not depend on the launch shape; 16 beams below 2^50 each stay far below 2^62.
+// does not depend on the launch shape; 16 contributions below 2^51 each stay below the
+// 2^56 that the fold's 64-bit lane sums allow.
 template <int KIND>
 __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Radial& g0, const Radial& gm,
                                       const Radial& g1, const RowGeo& rg, const double (*sJ)[16],
@@ -808,17 +812,15 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
       const cplx p0 = mk(pd[0], pd[1]), p1 = mk(pd[2], pd[3]), p2 = mk(pd[4], pd[5]);
       const double n0 = norm2(p0), nm = norm2(p1), nt = norm2(p2);
       const cplx em = cmul_conjb(p0, p1), et = cmul_conjb(p0, p2), mt = cmul_conjb(p1, p2);
-      double v8[8] = {n0 - nt, nm - nt, em.re, em.im, et.re, et.im, mt.re, mt.im};
-      if (an) {
-        v8[0] = -v8[0]; v8[1] = -v8[1]; v8[2] = -v8[2]; v8[4] = -v8[4]; v8[6] = -v8[6];
-      }
+      const double v8[8] = {n0 - nt, nm - nt, em.re, em.im, et.re, et.im, mt.re, mt.im};
       const double w = G[k];
+      const double wa = an ? -w : w;   // the negated components of -rho^*
 #pragma unroll
-      for (int i = 0; i < 8; ++i) dacc[i] = fma(w, v8[i], dacc[i]);
+      for (int i = 0; i < 8; ++i) dacc[i] = fma((i < 3 || i == 4 || i == 6) ? wa : w, v8[i], dacc[i]);
     }
     long long acc[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) acc[i] = to_fix(dacc[i], a.s1, kTwo62, err);
+    for (int i = 0; i < 8; ++i) acc[i] = to_fix(dacc[i], a.s1, kTwo56, err);
     fold_segment<8>(acc, lane, fl, mine);
   }
   close_row<8>(Scales{a.s1, a.s0, a.p2e1, a.p2e0}, lane, mine, icmom, T, err);
