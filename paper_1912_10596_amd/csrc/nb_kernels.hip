@@ -302,6 +302,36 @@ __device__ __forceinline__ void close_row(const Scales& sc, int lane, const I128
   }
 }
 
+// Row geometry of a stage: cos(theta) and h / cos(theta) at the three stage radii, 1/cos at
+// the radius of the stage's moments, and (extended model) sin(theta) at the three radii.
+// The wavefront's first row keeps it in LDS (gc, 11 doubles: c0 cm c1 hc0 hcm hc1, 1/cm,
+// 1/c1, sin(theta)) from stage 1 of a step for stages 2-4, which use the same radii.
+template <int KIND, bool EXT>
+__device__ __forceinline__ void stage_geo(double u, double h, const Radial& g0, const Radial& gm,
+                                          const Radial& g1, double* gc, RowGeo& rg, double& icmom,
+                                          double& sn0, double& snm, double& sn1) {
+  if (KIND >= 2 && gc) {
+    rg.c0 = gc[0]; rg.cm = gc[1]; rg.c1 = gc[2];
+    rg.hc0 = gc[3]; rg.hcm = gc[4]; rg.hc1 = gc[5];
+    icmom = (KIND == 2) ? gc[6] : gc[7];
+    sn0 = gc[8]; snm = gc[9]; sn1 = gc[10];
+    return;
+  }
+  rg = row_geo(u, h, g0, gm, g1);
+  icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
+  // sin(theta) at the three stage radii (sin(theta) r = sin(theta_R) R)
+  sn0 = EXT ? sqrt(u * g0.q2) : 0.0;
+  snm = EXT ? sqrt(u * gm.q2) : 0.0;
+  sn1 = EXT ? sqrt(u * g1.q2) : 0.0;
+  if (KIND == 1 && gc) {
+    gc[0] = rg.c0; gc[1] = rg.cm; gc[2] = rg.c1;
+    gc[3] = rg.hc0; gc[4] = rg.hcm; gc[5] = rg.hc1;
+    gc[6] = icmom;
+    gc[7] = 1.0 / rg.c1;
+    gc[8] = sn0; gc[9] = snm; gc[10] = sn1;
+  }
+}
+
 // ----------------------------------------------------------------- two flavours
 // Stage stencil for one (species s, emission bin u) row of NE beams starting at beam rb.
 // KIND: 0 moments of rho_n at r_n; 1 stage Y2 (moments at r_n + h/2); 2 stage Y3
@@ -319,15 +349,13 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
                                      const Radial& gm, const Radial& g1, const double* const* J,
                                      const Scales& sc, int renorm, int lane, long long* fl, I128& T,
                                      int& err, double& emax, double cp = 0.0, double sp = 0.0,
-                                     int an = -1) {
+                                     int an = -1, double* gc = nullptr) {
   constexpr int NM = EXT ? 4 : 2;
   // species row s, antiparticle flag an (default: s itself, two tracked species)
   if (an < 0) an = s;
-  const RowGeo rg = row_geo(u, h, g0, gm, g1);
-  const double icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
-  // sin(theta) at the three stage radii (sin(theta) r = sin(theta_R) R)
-  const double sn0 = EXT ? sqrt(u * g0.q2) : 0.0, snm = EXT ? sqrt(u * gm.q2) : 0.0;
-  const double sn1 = EXT ? sqrt(u * g1.q2) : 0.0;
+  RowGeo rg;
+  double icmom, sn0, snm, sn1;
+  stage_geo<KIND, EXT>(u, h, g0, gm, g1, gc, rg, icmom, sn0, snm, sn1);
   double n1[3], n2[3], n3[3], n4[3];
   if (KIND == 1 || KIND == 2 || KIND == 4) nunu_row<3, EXT>(J[0], g0.mu, rg.c0, sn0, cp, sp, n1);
   if (KIND == 2 || KIND == 4) nunu_row<3, EXT>(J[1], gm.mu, rg.cm, snm, cp, sp, n2);
@@ -410,7 +438,7 @@ template <int KIND, bool ADAPT = false, bool EXT = false>
 __device__ __forceinline__ void stage2(const StepArgs& a, const StepGeo& G, const double* X, double* Xo,
                                        const double (*sJ)[EXT ? 12 : 6], const double* tab, long long gw,
                                        long long nw, int lane, long long* fl, I128& T, int& err,
-                                       double& emax) {
+                                       double& emax, double* gc = nullptr) {
   const Radial g0 = radial_at(a, G.r0), gm = radial_at(a, G.rm), g1 = radial_at(a, G.r1);
   const Scales sc{a.s1, a.s0, a.p2e1, a.p2e0};
   const double* J[4] = {sJ[0], sJ[1], sJ[2], sJ[3]};
@@ -425,7 +453,7 @@ __device__ __forceinline__ void stage2(const StepArgs& a, const StepGeo& G, cons
       const int j = (int)(sj - (long long)s * a.NU);
       row2<KIND, ADAPT, true>(X, Xo, a.plane, row * a.NE, a.NE, s, u_of(j, a.NU), G.h, tab, g0, gm, g1,
                               J, sc, a.renorm, lane, fl, T, err, emax, phi[p], phi[a.NP + p],
-                              s >= (a.NS >> 1));
+                              s >= (a.NS >> 1), row == gw ? gc : nullptr);
     }
   } else {
     const long long nrow = (long long)a.NS * a.NU;
@@ -433,7 +461,8 @@ __device__ __forceinline__ void stage2(const StepArgs& a, const StepGeo& G, cons
       const int s = (int)(row / a.NU);
       const int j = (int)(row - (long long)s * a.NU);
       row2<KIND, ADAPT>(X, Xo, a.plane, row * a.NE, a.NE, s, u_of(j, a.NU), G.h, tab, g0, gm, g1, J, sc,
-                        a.renorm, lane, fl, T, err, emax, 0.0, 0.0, s >= (a.NS >> 1));
+                        a.renorm, lane, fl, T, err, emax, 0.0, 0.0, s >= (a.NS >> 1),
+                        row == gw ? gc : nullptr);
     }
   }
 }
@@ -565,7 +594,7 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
                                      const Radial& g0, const Radial& gm, const Radial& g1,
                                      const double (*sJ)[EXT ? 32 : 16], const double* tab, double* snn,
                                      int lane, long long* fl, I128& T, int& err, double& emax,
-                                     const ST* pre = nullptr) {
+                                     const ST* pre = nullptr, double* gc = nullptr) {
   constexpr int NM = EXT ? 4 : 2;
   const long long plane = a.plane;
   const int NE = a.NE;
@@ -585,10 +614,9 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
   }
   const int an = (s >= (a.NS >> 1)) ? 1 : 0;   // antiparticle row
   const double u = u_of(j, a.NU);
-  const RowGeo rg = row_geo(u, h, g0, gm, g1);
-  const double icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
-  const double sn0 = EXT ? sqrt(u * g0.q2) : 0.0, snm = EXT ? sqrt(u * gm.q2) : 0.0;
-  const double sn1 = EXT ? sqrt(u * g1.q2) : 0.0;
+  RowGeo rg;
+  double icmom, sn0, snm, sn1;
+  stage_geo<KIND, EXT>(u, h, g0, gm, g1, gc, rg, icmom, sn0, snm, sn1);
   double alpha = 0.0, alphaE = 0.0;
   if constexpr (KIND >= 1)
     alpha = row_lin3<KIND, ADAPT, EXT>(a, an, rg, g0, gm, g1, sJ[0], sJ[1], sJ[2], sJ[3], sn0, snm, sn1,
@@ -679,12 +707,13 @@ template <typename ST, int KIND, bool ADAPT = false, bool EXT = false>
 __device__ __forceinline__ void stage3(const StepArgs& a, const StepGeo& G, const ST* X, ST* Xo,
                                        const double (*sJ)[EXT ? 32 : 16], const double* tab, double* snn,
                                        long long gw, long long nw, int lane, long long* fl, I128& T,
-                                       int& err, double& emax, const ST* pre = nullptr) {
+                                       int& err, double& emax, const ST* pre = nullptr,
+                                       double* gc = nullptr) {
   const Radial g0 = radial_at(a, G.r0), gm = radial_at(a, G.rm), g1 = radial_at(a, G.r1);
   const long long nrow = (long long)a.NS * a.NU * (EXT ? a.NP : 1);
   for (long long row = gw; row < nrow; row += nw)
     row3<ST, KIND, ADAPT, EXT>(a, X, Xo, row, G.h, g0, gm, g1, sJ, tab, snn, lane, fl, T, err, emax,
-                               row == gw ? pre : nullptr);
+                               row == gw ? pre : nullptr, row == gw ? gc : nullptr);
 }
 // Load the lane's first beam of the wavefront's first row (the next stage starts there),
 // so that the load completes while the wavefront waits at the grid barrier.
@@ -712,7 +741,7 @@ __device__ __forceinline__ void prefetch_first(const StepArgs& a, long long gw, 
 // 2^56 that the fold's 64-bit lane sums allow.
 template <int KIND>
 __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Radial& g0, const Radial& gm,
-                                      const Radial& g1, const RowGeo& rg, const double (*sJ)[16],
+                                      const Radial& g1, const RowGeo& rg, double icmom, const double (*sJ)[16],
                                       const double* tab, double* snd, float* snn, int lane, long long* fl,
                                       I128& T, int& err) {
 #pragma clang fp contract(fast)
@@ -722,7 +751,6 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
   float* X = (float*)a.X;
   const int s = (int)(row / a.NU);
   const int an = (s >= (a.NS >> 1)) ? 1 : 0;   // antiparticle row
-  const double icmom = 1.0 / ((KIND == 0) ? rg.c0 : ((KIND <= 2) ? rg.cm : rg.c1));
   // generator row constants (FP64, as in the FP64 stepper): snd[0..8] Q, snd[9..17] P;
   // stages 1-3 use FP32 copies in snn, the final update's Theta is summed in FP64
   double alphaE = 0.0;
@@ -833,14 +861,16 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
 template <int KIND>
 __device__ __forceinline__ void stage3m(const StepArgs& a, const StepGeo& G, const double (*sJ)[16],
                                         const double* tab, double* snn, long long gw, long long nw,
-                                        int lane, long long* fl, I128& T, int& err) {
+                                        int lane, long long* fl, I128& T, int& err, double* gc = nullptr) {
   const Radial g0 = radial_at(a, G.r0), gm = radial_at(a, G.rm), g1 = radial_at(a, G.r1);
   const long long nrow = (long long)a.NS * a.NU;
   for (long long row = gw; row < nrow; row += nw) {
     const int s = (int)(row / a.NU);
     const int j = (int)(row - (long long)s * a.NU);
-    const RowGeo rg = row_geo(u_of(j, a.NU), G.h, g0, gm, g1);
-    row3m<KIND>(a, row, g0, gm, g1, rg, sJ, tab, snn, (float*)(snn + 32), lane, fl, T, err);
+    RowGeo rg;
+    double icmom, sn0, snm, sn1;
+    stage_geo<KIND, false>(u_of(j, a.NU), G.h, g0, gm, g1, row == gw ? gc : nullptr, rg, icmom, sn0, snm, sn1);
+    row3m<KIND>(a, row, g0, gm, g1, rg, icmom, sJ, tab, snn, (float*)(snn + 32), lane, fl, T, err);
   }
 }
 
@@ -856,7 +886,8 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   __shared__ double sJ[4][NV];
   __shared__ I128 sw[kBlock / 64][NV];
   __shared__ long long sacc[kBlock];
-  __shared__ double snn_all[kBlock / 64][F32 ? 48 : 32];   // nn terms (mixed: then 32 floats)
+  // per wavefront: row constants (mixed: then 32 floats); 2f: the first row's geometry
+  __shared__ double snn_all[kBlock / 64][F32 ? 48 : (NF == 2 ? 48 : 32)];
   __shared__ long long sfold[kBlock / 64][(NC + 2) * 64];
   extern __shared__ double dyn_tab[];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -870,6 +901,9 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
     tab = dyn_tab;
   }
   double* snn = snn_all[wid];
+  // the first row's geometry cache pays for two flavours; in the three-flavour kernels the
+  // extra live values cost more in spills than the recomputation
+  double* gc = (NF == 2) ? snn + 32 : nullptr;
   long long* fl = sfold[wid];
   const long long step0 = a.step_ctl[0];
   long long nsteps;
@@ -900,27 +934,27 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   record(step0, 0);
   for (long long n = step0; ok && n < step0 + nsteps; ++n) {
     T = i128_zero();
-    if constexpr (NF == 2) stage2<1, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
-    else if constexpr (F32) stage3m<1>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err);
-    else { stage3<ST, 1, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
+    if constexpr (NF == 2) stage2<1, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, gc);
+    else if constexpr (F32) stage3m<1>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err, gc);
+    else { stage3<ST, 1, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     if (!(ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[1]))) break;
     record(n, 1);
     T = i128_zero();
-    if constexpr (NF == 2) stage2<2, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
-    else if constexpr (F32) stage3m<2>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err);
-    else { stage3<ST, 2, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
+    if constexpr (NF == 2) stage2<2, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, gc);
+    else if constexpr (F32) stage3m<2>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err, gc);
+    else { stage3<ST, 2, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     if (!(ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[2]))) break;
     record(n, 2);
     T = i128_zero();
-    if constexpr (NF == 2) stage2<3, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
-    else if constexpr (F32) stage3m<3>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err);
-    else { stage3<ST, 3, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
+    if constexpr (NF == 2) stage2<3, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, gc);
+    else if constexpr (F32) stage3m<3>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err, gc);
+    else { stage3<ST, 3, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     if (!(ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[3]))) break;
     record(n, 3);
     T = i128_zero();
-    if constexpr (NF == 2) stage2<4, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
-    else if constexpr (F32) stage3m<4>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err);
-    else { stage3<ST, 4, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
+    if constexpr (NF == 2) stage2<4, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, gc);
+    else if constexpr (F32) stage3m<4>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err, gc);
+    else { stage3<ST, 4, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[0]);
     record(n + 1, 0);
   }
@@ -960,7 +994,7 @@ __global__ void __launch_bounds__(kBlock) k_adaptive(StepArgs a) {
   __shared__ double swm[kBlock / 64];
   __shared__ I128 sw[kBlock / 64][NV];
   __shared__ long long sacc[kBlock];
-  __shared__ double snn_all[kBlock / 64][32];
+  __shared__ double snn_all[kBlock / 64][48];   // row constants, then the first row's geometry
   __shared__ long long sfold[kBlock / 64][(NC + 2) * 64];
   extern __shared__ double dyn_tab[];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -974,6 +1008,7 @@ __global__ void __launch_bounds__(kBlock) k_adaptive(StepArgs a) {
     tab = dyn_tab;
   }
   double* snn = snn_all[wid];
+  double* gc = (NF == 2) ? snn + 32 : nullptr;   // as in k_advance
   long long* fl = sfold[wid];
   long long* ctl = a.step_ctl;
   double r = as_double((unsigned long long)ctl[kCtlR]);
@@ -987,8 +1022,8 @@ __global__ void __launch_bounds__(kBlock) k_adaptive(StepArgs a) {
   I128 T = i128_zero();
   auto stage = [&](auto kind, const StepGeo& G) {
     constexpr int K = decltype(kind)::value;
-    if constexpr (NF == 2) stage2<K, K == 4>(a, G, X, Xn, sJ, tab, gw, nw, lane, fl, T, err, emax);
-    else stage3<double, K, K == 4>(a, G, X, Xn, sJ, tab, snn, gw, nw, lane, fl, T, err, emax);
+    if constexpr (NF == 2) stage2<K, K == 4>(a, G, X, Xn, sJ, tab, gw, nw, lane, fl, T, err, emax, gc);
+    else stage3<double, K, K == 4>(a, G, X, Xn, sJ, tab, snn, gw, nw, lane, fl, T, err, emax, nullptr, gc);
   };
   using K0 = std::integral_constant<int, 0>;
   using K1 = std::integral_constant<int, 1>;
