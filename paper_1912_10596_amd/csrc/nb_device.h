@@ -212,7 +212,7 @@ __device__ __forceinline__ double cnorm2v(const cplx v[3]) {
 
 // psi <- exp(-i K) psi up to a global phase (three flavours).  K0 = traceless part of K,
 // l1 its eigenvalue of largest magnitude (3 Halley steps on the characteristic cubic
-// l^3 - p l - q from 2 sqrt(p/3), which is within 16 % of it: full FP64 accuracy), c a
+// l^3 - p l - q from a start within 23 % above it: full FP64 accuracy), c a
 // column of adj(K0 - l1) (its eigenvector, v1 = c / |c|).  On the plane orthogonal to v1,
 // K0 - hm with hm = -l1/2 squares to th^2, so the plane is propagated by the closed-form
 // 2x2 exponential of Eq. U:
@@ -246,7 +246,11 @@ __device__ __forceinline__ void exp3_apply(const Herm3& K, cplx psi[3]) {
   if (!(p > 0x1p-200)) return;
   const double sg = (q < 0.0) ? -1.0 : 1.0;
   const double qa = sg * q;
-  double lam = 2.0 * sqrt(p * (1.0 / 3.0));
+  // start: 2 sqrt(p/3) by halving the exponent in the bit pattern of p/3 (at most 6.1 %
+  // above the square root, never below: above the root and within 23 % of it)
+  double lam = 2.0 * __longlong_as_double(
+                         (long long)(((unsigned long long)__double_as_longlong(p * (1.0 / 3.0)) >> 1) +
+                                     0x1FF8000000000000ull));
 #pragma unroll
   for (int it = 0; it < 3; ++it) {   // Halley: l - f f' / (f'^2 - f f''/2), f'' = 6 l
     const double l2 = lam * lam;

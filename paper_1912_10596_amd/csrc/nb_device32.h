@@ -122,7 +122,9 @@ __device__ __forceinline__ bool split3_f(const Herm3f& K, const cplxf psi[3], Sp
   if (!(p > 0.0f)) return false;
   const float sg = (q < 0.0f) ? -1.0f : 1.0f;
   const float qa = sg * q;
-  float lam = 2.0f * sqrtf(p * (1.0f / 3.0f));
+  // start: 2 sqrt(p/3) by halving the exponent in the bit pattern (above the root, within
+  // 23 % of it)
+  float lam = 2.0f * __int_as_float((int)(((unsigned)__float_as_int(p * (1.0f / 3.0f)) >> 1) + 0x1FC00000u));
 #pragma unroll
   for (int it = 0; it < 3; ++it) {
     const float l2 = lam * lam;
