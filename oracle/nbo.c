@@ -73,14 +73,17 @@ static double sqrt2gf_km_cm3(void) {
 
 /* --------------------------------------------------------------- sin / cos */
 /* Cody-Waite reduction by pi/2 (three-part split, fma), Taylor polynomials of
- * degree 17 (sin) and 18 (cos) on |r| <= pi/4. */
+ * degree 17 (sin) and 18 (cos) on |r| <= pi/4.  The multiple k is the exact product
+ * x 2/pi rounded once to the nearest integer: fma adds 1.5 2^52 and rounds in a binade of
+ * unit spacing, so t - 1.5 2^52 = k and the low bits of t are k mod 4 (|x| < 2^50). */
 static const double TWO_OVER_PI = 0x1.45f306dc9c883p-1;
 static const double PIO2_HI = 0x1.921fb54442d18p+0;
 static const double PIO2_MID = 0x1.1a62633145c07p-54;
 static const double PIO2_LO = -0x1.f1976b7ed8fbcp-110;
 
 static void sincos_spec(double x, double *sn, double *cs) {
-  const double k = rint(x * TWO_OVER_PI);
+  const double t = fma(x, TWO_OVER_PI, 0x1.8p52);
+  const double k = t - 0x1.8p52;
   double r = fma(-k, PIO2_HI, x);
   r = fma(-k, PIO2_MID, r);
   r = fma(-k, PIO2_LO, r);
@@ -104,7 +107,9 @@ static void sincos_spec(double x, double *sn, double *cs) {
   pc = fma(pc, r2, 1.0 / 24.0);
   pc = fma(pc, r2, -0.5);
   const double c = fma(r2, pc, 1.0);
-  switch ((int)((long long)k & 3)) {
+  uint64_t tb;
+  memcpy(&tb, &t, sizeof tb);
+  switch ((int)(tb & 3)) {
     case 0: *sn = s; *cs = c; break;
     case 1: *sn = c; *cs = -s; break;
     case 2: *sn = -s; *cs = -c; break;

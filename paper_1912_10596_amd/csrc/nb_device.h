@@ -18,11 +18,15 @@ constexpr double kTwo62 = 4611686018427387904.0;
 constexpr double kTwo64 = 18446744073709551616.0;
 
 // ------------------------------------------------------------------ sin / cos
-// sin and cos of one argument.  Reduction x = k pi/2 + r with k = rint(2x/pi) and a
+// sin and cos of one argument.  Reduction x = k pi/2 + r with k the nearest integer to 2x/pi and a
 // three-part split of pi/2 (each part applied with one fma); then Taylor series of sin
 // (to r^17) and cos (to r^18) by Horner in r^2; the quadrant k mod 4 picks signs.
 __device__ __forceinline__ void sincos_nb(double x, double& sn, double& cs) {
-  const double k = rint(x * 0x1.45f306dc9c883p-1);
+  // k = the exact product x 2/pi rounded once to the nearest integer: the fma adds
+  // 1.5 2^52 and rounds in a binade of unit spacing, so t - 1.5 2^52 = k and the low bits
+  // of t are k mod 4 (|x| < 2^50)
+  const double t = fma(x, 0x1.45f306dc9c883p-1, 0x1.8p52);
+  const double k = t - 0x1.8p52;
   double r = fma(-k, 0x1.921fb54442d18p+0, x);
   r = fma(-k, 0x1.1a62633145c07p-54, r);
   r = fma(-k, -0x1.f1976b7ed8fbcp-110, r);
@@ -46,7 +50,7 @@ __device__ __forceinline__ void sincos_nb(double x, double& sn, double& cs) {
   pc = fma(pc, r2, 1.0 / 24.0);
   pc = fma(pc, r2, -0.5);
   const double c = fma(r2, pc, 1.0);
-  const int quad = (int)((long long)k & 3);
+  const int quad = (int)(__double_as_longlong(t) & 3);
   const double a = (quad & 1) ? c : s;    // |sin| candidate
   const double b = (quad & 1) ? s : c;    // |cos| candidate
   sn = (quad & 2) ? -a : a;

@@ -18,7 +18,10 @@ namespace nb {
 // sin and cos in FP32: x = k pi/2 + r (three-part split of pi/2 applied with fma),
 // Taylor polynomials of degree 9 (sin) and 10 (cos) on |r| <= pi/4.
 __device__ __forceinline__ void sincos_f(float x, float& sn, float& cs) {
-  const float k = rintf(x * 0x1.45f306p-1f);
+  // k = x 2/pi rounded to the nearest integer by adding 1.5 2^23 (|x| < 2^21); the low bits
+  // of t are k mod 4
+  const float t = fmaf(x, 0x1.45f306p-1f, 0x1.8p23f);
+  const float k = t - 0x1.8p23f;
   float r = fmaf(-k, 0x1.92p+0f, x);
   r = fmaf(-k, 0x1.fb6p-12f, r);
   r = fmaf(-k, -0x1.777a5cp-25f, r);
@@ -34,7 +37,7 @@ __device__ __forceinline__ void sincos_f(float x, float& sn, float& cs) {
   pc = fmaf(pc, r2, 1.0f / 24.0f);
   pc = fmaf(pc, r2, -0.5f);
   const float c = fmaf(r2, pc, 1.0f);
-  const int q = ((int)k) & 3;
+  const int q = __float_as_int(t) & 3;
   sn = (q == 0) ? s : ((q == 1) ? c : ((q == 2) ? -s : -c));
   cs = (q == 0) ? c : ((q == 1) ? -s : ((q == 2) ? -c : s));
 }
