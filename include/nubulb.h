@@ -61,7 +61,9 @@ typedef struct {
   int32_t n_u;          /* N_u bins of equal width in u = sin^2(theta_R) over [0,1], midpoints */
   int32_t ne_power;     /* n_e(r) = n0_cm3 (R/r)^ne_power; 3 for the bulb, 0..8 allowed */
   int32_t precision;    /* NB_FP64, or NB_FP32_STATE (3 flavours: state stored in FP32) */
-  int32_t renorm;       /* 1: renormalise every beam after every step (0: tests only) */
+  int32_t renorm;       /* 1: renormalise every beam after every step (0: tests only); the
+                           factor is 1.5 - n^2/2, exact to rounding for the near-unit norms a
+                           step leaves (initial states must have unit norm) */
   int32_t adjoint_ckpt; /* >0: reserve workspace for nb_adjoint with this checkpoint period */
   int32_t max_blocks;   /* 0: as many blocks as fit on the device; else an upper bound */
   int64_t n_steps;      /* radial steps from r_start_km to r_end_km */

@@ -724,15 +724,19 @@ static void stage_f2(const nbo_model *m, int64_t b, const radial *g, const doubl
   stage_f2h(m, b, g, Jm, m->h, f);
 }
 
+/* Renormalisation after a step: a unitary step leaves the squared norm at 1 + d with d at
+ * rounding level, so one Newton step for 1/sqrt(n2) from 1, 1.5 - n2/2, equals 1/sqrt(n2)
+ * to within 3 d^2 / 8 (a state set far from unit norm converges to it quadratically over
+ * the following steps; one with n2 >= 2 fails the moments' state check). */
 static void renorm2(double *P) {
   const double n2 = (P[0] * P[0] + P[1] * P[1]) + P[2] * P[2];
-  const double inv = 1.0 / sqrt(n2);
+  const double inv = fma(-0.5, n2, 1.5);
   P[0] = P[0] * inv; P[1] = P[1] * inv; P[2] = P[2] * inv;
 }
 static void renorm3(double *x) {
   const double n2 = (cx_norm2(cx_make(x[0], x[1])) + cx_norm2(cx_make(x[2], x[3]))) +
                     cx_norm2(cx_make(x[4], x[5]));
-  const double inv = 1.0 / sqrt(n2);
+  const double inv = fma(-0.5, n2, 1.5);
   for (int c = 0; c < 6; ++c) x[c] = x[c] * inv;
 }
 
@@ -1429,10 +1433,10 @@ static void reverse_step(nbo_model *m, const adj_tables *t, const double *X, int
     rotate2(th, X + 3 * b, Pp);
     double Ppb[3] = {Pb[3 * b], Pb[3 * b + 1], Pb[3 * b + 2]};
     if (m->p.renorm) {
-      const double nr = sqrt((Pp[0] * Pp[0] + Pp[1] * Pp[1]) + Pp[2] * Pp[2]);
-      const double Pn[3] = {Pp[0] / nr, Pp[1] / nr, Pp[2] / nr};
-      const double d = Pn[0] * Ppb[0] + Pn[1] * Ppb[1] + Pn[2] * Ppb[2];
-      for (int c = 0; c < 3; ++c) Ppb[c] = (Ppb[c] - Pn[c] * d) / nr;
+      /* y = P (1.5 - |P|^2 / 2): P-bar = (1.5 - |P|^2 / 2) y-bar - P (P . y-bar) */
+      const double sf = 1.5 - 0.5 * ((Pp[0] * Pp[0] + Pp[1] * Pp[1]) + Pp[2] * Pp[2]);
+      const double d = Pp[0] * Ppb[0] + Pp[1] * Ppb[1] + Pp[2] * Ppb[2];
+      for (int c = 0; c < 3; ++c) Ppb[c] = sf * Ppb[c] - Pp[c] * d;
     }
     double pbn[3] = {0, 0, 0}, om[3], thb[3];
     add_rot_adjoint(th, 1.0, Ppb, pbn);

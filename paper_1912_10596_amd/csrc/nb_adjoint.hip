@@ -354,9 +354,9 @@ __global__ void __launch_bounds__(kBlock) k_adjoint2(AdjArgs a) {
         const double t1 = (((f1[1] + 2.0 * f2[1]) + 2.0 * f3[1]) + f4[1]) * (1.0 / 6.0) - cr1 * (1.0 / 12.0);
         const double t2 = (((f1[2] + 2.0 * f2[2]) + 2.0 * f3[2]) + f4[2]) * (1.0 / 6.0) - cr2 * (1.0 / 12.0);
         rotate2(t0, t1, t2, P0, P1, P2);
-        if (a.renorm) {
+        if (a.renorm) {   // as the forward stepper: one Newton step for 1/sqrt from 1
           const double nrm2 = (P0 * P0 + P1 * P1) + P2 * P2;
-          const double inv = 1.0 / sqrt(nrm2);
+          const double inv = fma(-0.5, nrm2, 1.5);
           P0 = P0 * inv;
           P1 = P1 * inv;
           P2 = P2 * inv;
@@ -405,12 +405,12 @@ __global__ void __launch_bounds__(kBlock) k_adjoint2(AdjArgs a) {
         rot_fwd(R, B.P[0], B.P[1], B.P[2], Pp[0], Pp[1], Pp[2]);
         double Ppb[3] = {B.Pb[0], B.Pb[1], B.Pb[2]};
         if (a.renorm) {
-          const double nr = sqrt((Pp[0] * Pp[0] + Pp[1] * Pp[1]) + Pp[2] * Pp[2]);
-          const double e0 = Pp[0] / nr, e1 = Pp[1] / nr, e2 = Pp[2] / nr;
-          const double d = (e0 * Ppb[0] + e1 * Ppb[1]) + e2 * Ppb[2];
-          Ppb[0] = (Ppb[0] - e0 * d) / nr;
-          Ppb[1] = (Ppb[1] - e1 * d) / nr;
-          Ppb[2] = (Ppb[2] - e2 * d) / nr;
+          // y = P (1.5 - |P|^2 / 2): P-bar = (1.5 - |P|^2 / 2) y-bar - P (P . y-bar)
+          const double sf = fma(-0.5, (Pp[0] * Pp[0] + Pp[1] * Pp[1]) + Pp[2] * Pp[2], 1.5);
+          const double d = (Pp[0] * Ppb[0] + Pp[1] * Ppb[1]) + Pp[2] * Ppb[2];
+          Ppb[0] = sf * Ppb[0] - Pp[0] * d;
+          Ppb[1] = sf * Ppb[1] - Pp[1] * d;
+          Ppb[2] = sf * Ppb[2] - Pp[2] * d;
         }
         B.Pb[0] = B.Pb[1] = B.Pb[2] = 0.0;
         rot_inv_add(R, Ppb[0], Ppb[1], Ppb[2], B.Pb);

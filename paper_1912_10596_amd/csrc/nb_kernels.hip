@@ -410,7 +410,7 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
           rotate2(t0, t1, t2, P0, P1, P2);
           if (renorm) {
             const double nrm2 = (P0 * P0 + P1 * P1) + P2 * P2;
-            const double inv = 1.0 / sqrt(nrm2);
+            const double inv = fma(-0.5, nrm2, 1.5);   // one Newton step for 1/sqrt from 1
             P0 = P0 * inv;
             P1 = P1 * inv;
             P2 = P2 * inv;
@@ -671,7 +671,7 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
           exp3_apply(Th, ps);
           if (a.renorm) {
             const double nrm2 = (norm2(ps[0]) + norm2(ps[1])) + norm2(ps[2]);
-            const double inv = 1.0 / sqrt(nrm2);
+            const double inv = fma(-0.5, nrm2, 1.5);   // one Newton step for 1/sqrt from 1
 #pragma unroll
             for (int c = 0; c < 3; ++c) ps[c] = mk(ps[c].re * inv, ps[c].im * inv);
           }
