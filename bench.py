@@ -10,11 +10,11 @@ is resident in HBM before timing starts.  Prints ONE JSON line on stdout.
 Algorithmic cost per beam-step (counted from the kernel's arithmetic, fma = 2 flops,
 div/sqrt = 1; terms that are the same for a whole (species, angle) row are counted once
 per row and omitted here):
-  3 flavours: 4 exponentials exp(-iK) psi (405 flops each: characteristic cubic by three
+  3 flavours: 4 exponentials exp(-iK) psi (406 flops each: characteristic cubic by three
   Halley steps, eigenvector as an adjugate column, the 2x2 propagator on the eigen-plane,
   two sin/cos), 4 generators alpha V_k + e_k P + Q from the per-row constants (84 in all),
   renormalisation (19), 4 moment contributions with the state check (48 each)
-  ->  1915 flops.
+  ->  1919 flops.
   2 flavours: 4 quaternion rotations (85), 8 B-vector builds (7), 2 cross products,
   combinations, renormalisation, 4 moment contributions with the state check (12 each)
   ->  508 flops.
@@ -34,7 +34,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FLOPS_PER_BEAM_STEP = {2: 508.0, 3: 1915.0}
+FLOPS_PER_BEAM_STEP = {2: 508.0, 3: 1919.0}
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
 PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X FP64 vector, published (256 CU x 2.4 GHz x 128)
 METRIC = "beam-steps/sec + HBM GB/s (3-flavor 800k beams); adjoint/forward time ratio"
