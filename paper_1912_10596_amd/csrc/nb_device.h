@@ -141,32 +141,6 @@ struct Herm3 {
   double d0, d1, d2;
   cplx o01, o02, o12;
 };
-__device__ __forceinline__ cplx hat(const Herm3& h, int a, int b) {
-  // compile-time indices after unrolling
-  if (a == b) return mk(a == 0 ? h.d0 : (a == 1 ? h.d1 : h.d2), 0.0);
-  const cplx o = (a + b == 1) ? h.o01 : ((a + b == 2) ? h.o02 : h.o12);
-  return a < b ? o : conjg(o);
-}
-__device__ __forceinline__ Herm3 hscale(double s, const Herm3& h) {
-  return Herm3{s * h.d0, s * h.d1, s * h.d2, rmul(s, h.o01), rmul(s, h.o02), rmul(s, h.o12)};
-}
-// acc <- acc + a * K, entry by entry (one multiply and one add per real entry).
-__device__ __forceinline__ void haxpy(Herm3& acc, double a, const Herm3& K) {
-  acc.d0 = acc.d0 + a * K.d0;
-  acc.d1 = acc.d1 + a * K.d1;
-  acc.d2 = acc.d2 + a * K.d2;
-  acc.o01 = mk(acc.o01.re + a * K.o01.re, acc.o01.im + a * K.o01.im);
-  acc.o02 = mk(acc.o02.re + a * K.o02.re, acc.o02.im + a * K.o02.im);
-  acc.o12 = mk(acc.o12.re + a * K.o12.re, acc.o12.im + a * K.o12.im);
-}
-__device__ __forceinline__ void hadd(Herm3& acc, const Herm3& K) {
-  acc.d0 = acc.d0 + K.d0;
-  acc.d1 = acc.d1 + K.d1;
-  acc.d2 = acc.d2 + K.d2;
-  acc.o01 = mk(acc.o01.re + K.o01.re, acc.o01.im + K.o01.im);
-  acc.o02 = mk(acc.o02.re + K.o02.re, acc.o02.im + K.o02.im);
-  acc.o12 = mk(acc.o12.re + K.o12.re, acc.o12.im + K.o12.im);
-}
 
 // a0 b0 + a1 b1 + a2 b2 (complex): the six real products accumulated with fma from the
 // last one up (the specification's fused three-term complex dot product).
@@ -175,34 +149,6 @@ __device__ __forceinline__ cplx dot3_mul(cplx a0, cplx b0, cplx a1, cplx b1, cpl
                 fma(a2.re, b2.re, -(a2.im * b2.im)))))),
             fma(a0.re, b0.im, fma(a0.im, b0.re, fma(a1.re, b1.im, fma(a1.im, b1.re,
                 fma(a2.re, b2.im, a2.im * b2.re))))));
-}
-
-// C(A,B) = i [A,B]: with X = A B, C_aa = -2 Im X_aa, C_ab = i (X_ab - conj(X_ba)).
-__device__ __forceinline__ Herm3 icomm(const Herm3& A, const Herm3& B) {
-  cplx X[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-      X[a][b] = dot3_mul(hat(A, a, 0), hat(B, 0, b), hat(A, a, 1), hat(B, 1, b), hat(A, a, 2),
-                         hat(B, 2, b));
-  Herm3 C;
-  C.d0 = -2.0 * X[0][0].im;
-  C.d1 = -2.0 * X[1][1].im;
-  C.d2 = -2.0 * X[2][2].im;
-  {
-    const double dre = X[0][1].re - X[1][0].re, dim = X[0][1].im + X[1][0].im;
-    C.o01 = mk(-dim, dre);
-  }
-  {
-    const double dre = X[0][2].re - X[2][0].re, dim = X[0][2].im + X[2][0].im;
-    C.o02 = mk(-dim, dre);
-  }
-  {
-    const double dre = X[1][2].re - X[2][1].re, dim = X[1][2].im + X[2][1].im;
-    C.o12 = mk(-dim, dre);
-  }
-  return C;
 }
 
 __device__ __forceinline__ cplx dotc(const cplx u[3], const cplx v[3]) {  // u^+ v

@@ -482,25 +482,6 @@ __device__ __forceinline__ void stage2(const StepArgs& a, const StepGeo& G, cons
 // and the error estimate Theta - K2 = (alpha - am) V_k + e_k P + (Q - am M2).  Per beam that
 // is 6 (no P) or 15 fma.  Hermitian matrices as 9 reals: d0 d1 d2, re/im of (0,1), (0,2),
 // (1,2).
-__device__ __forceinline__ Herm3 h9(const double* o) {
-  return Herm3{o[0], o[1], o[2], mk(o[3], o[4]), mk(o[5], o[6]), mk(o[7], o[8])};
-}
-__device__ __forceinline__ void to9(const Herm3& h, double* o) {
-  o[0] = h.d0; o[1] = h.d1; o[2] = h.d2;
-  o[3] = h.o01.re; o[4] = h.o01.im; o[5] = h.o02.re; o[6] = h.o02.im; o[7] = h.o12.re; o[8] = h.o12.im;
-}
-// M of a stage: lam E_ee + nn (neutrinos), -(lam E_ee + nn^*) (antineutrinos)
-__device__ __forceinline__ void matter_m3(int an, double lam, const double* nn, double* M) {
-  const double sg = an ? -1.0 : 1.0;
-  M[0] = sg * (lam + nn[0]);
-  M[1] = sg * nn[1];
-  M[2] = 0.0;
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    M[3 + 2 * i] = sg * nn[2 + 2 * i];
-    M[4 + 2 * i] = nn[3 + 2 * i];
-  }
-}
 // alpha V_k + Q
 __device__ __forceinline__ Herm3 lin3q(double alpha, const double* Q, const double* v) {
   return Herm3{fma(alpha, v[0], Q[0]), fma(alpha, v[1], Q[1]), fma(alpha, v[2], Q[2]),
@@ -519,67 +500,118 @@ __device__ __forceinline__ Herm3 lin3p(double alpha, const double* P, const doub
 
 // Row constants of stage KIND's generator (KIND >= 1): Q to snn[0..8], P to snn[9..17]
 // and, with ADAPT (KIND 4), the error estimate's Q to snn[18..26]; returns alpha (and the
-// error estimate's alpha in alphaE).  J0..J3: the stage moments.
+// error estimate's alpha in alphaE).  J0..J3: the stage moments.  Lane i < 9 computes
+// component i of every 9-real matrix (the same operations as a matrix-at-a-time
+// evaluation, component by component); the commutators read their operands as full
+// complex 3x3 matrices from the wavefront's scratch fl (free before the beam loop), where
+// each lane writes its component and its mirror.
+// Component i of the 9-real form: 0..2 the diagonal, 3 + 2t / 4 + 2t re / im of entry t of
+// (0,1), (0,2), (1,2).  nn component of M's component i (the matter part sits on i = 0):
+__device__ __forceinline__ int nn_index(int i) { return (i <= 1) ? i : i - 1; }
+// nu-nu component j of a row (as nunu_row)
+template <int NC, bool EXT>
+__device__ __forceinline__ double nunu_comp(const double* J, double mu, double c, double sn, double cp,
+                                            double sp, int j) {
+  if constexpr (EXT) return mu * ((J[j] - c * J[NC + j]) - sn * (cp * J[2 * NC + j] + sp * J[3 * NC + j]));
+  else return mu * (J[j] - c * J[NC + j]);
+}
+// component i of M = lam E_ee + nn (neutrinos) or -(lam E_ee + nn^*) (antineutrinos)
+__device__ __forceinline__ double matter_comp(int an, double lam, double nnv, int i) {
+  const double sg = an ? -1.0 : 1.0;
+  if (i == 0) return sg * (lam + nnv);
+  if (i == 2) return 0.0;
+  return (i >= 4 && (i & 1) == 0) ? nnv : sg * nnv;
+}
+// Write component i of a 9-real Hermitian matrix (value v) into the full complex 3x3
+// matrix F (row-major, re/im pairs), with its conjugate mirror.
+__device__ __forceinline__ void put_full(double* F, int i, double v) {
+  if (i < 3) {
+    F[(i * 3 + i) * 2] = v;
+    F[(i * 3 + i) * 2 + 1] = 0.0;
+  } else {
+    const int t = (i - 3) >> 1, a = (t == 2) ? 1 : 0, b = (t == 0) ? 1 : 2;
+    if ((i & 1) == 1) {   // real part
+      F[(a * 3 + b) * 2] = v;
+      F[(b * 3 + a) * 2] = v;
+    } else {              // imaginary part
+      F[(a * 3 + b) * 2 + 1] = v;
+      F[(b * 3 + a) * 2 + 1] = -v;
+    }
+  }
+}
+// Component i of i[A, B] from the full matrices (X = A B; C_aa = -2 Im X_aa, C_ab =
+// (-(Im X_ab + Im X_ba), Re X_ab - Re X_ba)), as icomm.
+__device__ __forceinline__ double icomm_comp(const double* A, const double* B, int i) {
+  int a, b;
+  if (i < 3) {
+    a = i;
+    b = i;
+  } else {
+    const int t = (i - 3) >> 1;
+    a = (t == 2) ? 1 : 0;
+    b = (t == 0) ? 1 : 2;
+  }
+  auto at = [](const double* F, int r, int c) { return mk(F[(r * 3 + c) * 2], F[(r * 3 + c) * 2 + 1]); };
+  const cplx xab = dot3_mul(at(A, a, 0), at(B, 0, b), at(A, a, 1), at(B, 1, b), at(A, a, 2), at(B, 2, b));
+  if (i < 3) return -2.0 * xab.im;
+  const cplx xba = dot3_mul(at(A, b, 0), at(B, 0, a), at(A, b, 1), at(B, 1, a), at(A, b, 2), at(B, 2, a));
+  if ((i & 1) == 1) return -(xab.im + xba.im);
+  return xab.re - xba.re;
+}
 template <int KIND, bool ADAPT, bool EXT>
 __device__ __forceinline__ double row_lin3(const StepArgs& a, int an, const RowGeo& rg, const Radial& g0,
                                            const Radial& gm, const Radial& g1, const double* J0,
                                            const double* J1, const double* J2, const double* J3,
                                            double sn0, double snm, double sn1, double cp, double sp,
-                                           double* snn, double& alphaE) {
-  double alpha = 0.0;
-  // row constants: snn[0..8] Q, [9..17] P, [18..26] Q of Theta - K2
-  double nn[8], M1[9], M2[9], M3[9], M4[9];
-  if (KIND != 3) {
-    nunu_row<8, EXT>(J0, g0.mu, rg.c0, sn0, cp, sp, nn);
-    matter_m3(an, g0.lam, nn, M1);
-  }
-  if (KIND == 2 || KIND == 4) {
-    nunu_row<8, EXT>(J1, gm.mu, rg.cm, snm, cp, sp, nn);
-    matter_m3(an, gm.lam, nn, M2);
-  }
-  if (KIND >= 3) {
-    nunu_row<8, EXT>(J2, gm.mu, rg.cm, snm, cp, sp, nn);
-    matter_m3(an, gm.lam, nn, M3);
-  }
-  if (KIND == 4) {
-    nunu_row<8, EXT>(J3, g1.mu, rg.c1, sn1, cp, sp, nn);
-    matter_m3(an, g1.lam, nn, M4);
-  }
+                                           double* snn, double& alphaE, int lane, double* scr) {
+  constexpr int NC = 8;
+  const int i = (lane < 9) ? lane : 8;   // lanes 9..63 repeat component 8 and write nothing
+  const int jn = nn_index(i);
+  double M1 = 0.0, M2 = 0.0, M3 = 0.0, M4 = 0.0;
+  if (KIND != 3) M1 = matter_comp(an, g0.lam, nunu_comp<NC, EXT>(J0, g0.mu, rg.c0, sn0, cp, sp, jn), i);
+  if (KIND == 2 || KIND == 4) M2 = matter_comp(an, gm.lam, nunu_comp<NC, EXT>(J1, gm.mu, rg.cm, snm, cp, sp, jn), i);
+  if (KIND >= 3) M3 = matter_comp(an, gm.lam, nunu_comp<NC, EXT>(J2, gm.mu, rg.cm, snm, cp, sp, jn), i);
+  if (KIND == 4) M4 = matter_comp(an, g1.lam, nunu_comp<NC, EXT>(J3, g1.mu, rg.c1, sn1, cp, sp, jn), i);
+  double alpha;
   if (KIND == 1 || KIND == 3) {
     alpha = (KIND == 1) ? 0.5 * rg.hc0 : rg.hcm;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) snn[i] = alpha * ((KIND == 1) ? M1[i] : M3[i]);
+    if (lane < 9) snn[i] = alpha * ((KIND == 1) ? M1 : M3);
   } else {
-    const double* Mi = (KIND == 2) ? M2 : M4;
-    double D[9], R1[9], R2[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) D[i] = Mi[i] - M1[i];
-    const Herm3 Dh = h9(D);
-    const Herm3 V0{a.v0[0], a.v0[1], a.v0[2], mk(a.v0[3], 0.0), mk(a.v0[4], 0.0), mk(a.v0[5], 0.0)};
-    to9(icomm(V0, Dh), R1);
-    to9(icomm(h9(M1), Dh), R2);
+    const double D = ((KIND == 2) ? M2 : M4) - M1;
+    // full matrices: V0 at scr[0..17], M1 at scr[18..35], D at scr[36..53]
+    double* FV = scr;
+    double* FM = scr + 18;
+    double* FD = scr + 36;
+    if (lane < 9) {
+      const double v0 = (i < 3) ? a.v0[i] : (((i & 1) == 1) ? a.v0[3 + ((i - 3) >> 1)] : 0.0);
+      put_full(FV, i, v0);
+      put_full(FM, i, M1);
+      put_full(FD, i, D);
+    }
+    __asm__ volatile("" ::: "memory");   // the wave's LDS operations complete in program order
+    const double R1 = icomm_comp(FV, FD, i), R2 = icomm_comp(FM, FD, i);
+    __asm__ volatile("" ::: "memory");
     if (KIND == 2) {
       const double c = (rg.hc0 * rg.hcm) * 0.125;
       alpha = 0.5 * rg.hcm;
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        snn[9 + i] = c * R1[i];
-        snn[i] = fma(alpha, M2[i], c * R2[i]);
+      if (lane < 9) {
+        snn[9 + i] = c * R1;
+        snn[i] = fma(alpha, M2, c * R2);
       }
     } else {
       const double c = (rg.hc0 * rg.hc1) * (1.0 / 12.0), a2 = 2.0 * rg.hcm;
       alpha = (((rg.hc0 + a2) + a2) + rg.hc1) * (1.0 / 6.0);
       alphaE = alpha - rg.hcm;
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        const double S = fma(rg.hc1, M4[i], fma(a2, M3[i], fma(a2, M2[i], rg.hc0 * M1[i])));
-        const double Qi = fma(S, 1.0 / 6.0, c * R2[i]);
-        snn[9 + i] = c * R1[i];
+      const double S = fma(rg.hc1, M4, fma(a2, M3, fma(a2, M2, rg.hc0 * M1)));
+      const double Qi = fma(S, 1.0 / 6.0, c * R2);
+      if (lane < 9) {
+        snn[9 + i] = c * R1;
         snn[i] = Qi;
-        if (ADAPT) snn[18 + i] = fma(-rg.hcm, M2[i], Qi);
+        if (ADAPT) snn[18 + i] = fma(-rg.hcm, M2, Qi);
       }
     }
   }
+  __asm__ volatile("" ::: "memory");
   return alpha;
 }
 
@@ -620,7 +652,7 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
   double alpha = 0.0, alphaE = 0.0;
   if constexpr (KIND >= 1)
     alpha = row_lin3<KIND, ADAPT, EXT>(a, an, rg, g0, gm, g1, sJ[0], sJ[1], sJ[2], sJ[3], sn0, snm, sn1,
-                                       cp, sp, snn, alphaE);
+                                       cp, sp, snn, alphaE, lane, reinterpret_cast<double*>(fl));
   const double* G = tab + (size_t)(kVacRows3 + s) * NE;
   const long long rb = row * NE;
   I128 mine = i128_zero();
@@ -756,7 +788,8 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
   double alphaE = 0.0;
   const double alpha = (KIND >= 1)
       ? row_lin3<(KIND >= 1 ? KIND : 1), false, false>(a, an, rg, g0, gm, g1, sJ[0], sJ[1], sJ[2], sJ[3],
-                                                        0.0, 0.0, 0.0, 0.0, 0.0, snd, alphaE)
+                                                        0.0, 0.0, 0.0, 0.0, 0.0, snd, alphaE, lane,
+                                                        reinterpret_cast<double*>(fl))
       : 0.0;
   const float alphaf = (float)alpha;
   if (KIND >= 1 && KIND <= 3) {
