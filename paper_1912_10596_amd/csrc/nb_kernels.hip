@@ -919,8 +919,8 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   __shared__ double sJ[4][NV];
   __shared__ I128 sw[kBlock / 64][NV];
   __shared__ long long sacc[kBlock];
-  // per wavefront: row constants (mixed: then 32 floats); 2f: the first row's geometry
-  __shared__ double snn_all[kBlock / 64][F32 ? 48 : (NF == 2 ? 48 : 32)];
+  // per wavefront: row constants (mixed: then 32 floats), then the first row's geometry
+  __shared__ double snn_all[kBlock / 64][F32 ? 64 : 48];
   __shared__ long long sfold[kBlock / 64][(NC + 2) * 64];
   extern __shared__ double dyn_tab[];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -934,9 +934,7 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
     tab = dyn_tab;
   }
   double* snn = snn_all[wid];
-  // the first row's geometry cache pays for two flavours; in the three-flavour kernels the
-  // extra live values cost more in spills than the recomputation
-  double* gc = (NF == 2) ? snn + 32 : nullptr;
+  double* gc = snn + (F32 ? 48 : 32);   // the first row's stage geometry
   long long* fl = sfold[wid];
   const long long step0 = a.step_ctl[0];
   long long nsteps;
@@ -1041,7 +1039,7 @@ __global__ void __launch_bounds__(kBlock) k_adaptive(StepArgs a) {
     tab = dyn_tab;
   }
   double* snn = snn_all[wid];
-  double* gc = (NF == 2) ? snn + 32 : nullptr;   // as in k_advance
+  double* gc = snn + 32;   // the first row's stage geometry
   long long* fl = sfold[wid];
   long long* ctl = a.step_ctl;
   double r = as_double((unsigned long long)ctl[kCtlR]);
