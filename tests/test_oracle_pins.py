@@ -433,3 +433,74 @@ def test_thread_count_and_restart_are_bitwise(oracle):
     x = m.get_state()
     m2 = oracle.Model(d); m2.set_state(x, 5); m2.step(7)
     np.testing.assert_array_equal(m2.get_state(), outs[0])
+
+
+@pytest.mark.parametrize("nf", [2, 3])
+def test_one_step_equals_definition(oracle, nf):
+    """One oracle RKMK4 step from a random state against the method written out with dense
+    matrices and SciPy's expm: stage generators K_i = (h / cos theta(r_i)) H(r_i, Y_i) with
+    H = H_vac + lam E_ee + H_nunu (antineutrinos: H_vac - lam E_ee - H_nunu^*, H_nunu by the
+    brute-force pair sum over the stage state Y_i), Y2 = e^{-i K1/2} psi,
+    Y3 = e^{-i (K2/2 + i[K1,K2]/8)} psi, Y4 = e^{-i K3} psi and
+    psi' = e^{-i Theta} psi with Theta = (K1 + 2 K2 + 2 K3 + K4)/6 + i[K1,K4]/12.  This pins
+    the oracle's restated arithmetic (generators from per-row constants, commutators by
+    bilinearity, the eigen-split exponential, fixed-point moments) against the definitions."""
+    NE, NU = 3, 4
+    d = workloads.small_params(n_flavor=nf, n_energy=NE, n_u=NU, n_steps=100, r_start_km=100.0,
+                               r_end_km=101.0, n0_cm3=1e32)
+    m = oracle.Model(d)
+    rng = np.random.default_rng(29)
+    nb = 2 * NU * NE
+    if nf == 2:
+        P = rng.normal(size=(3, nb)); P /= np.linalg.norm(P, axis=0)
+        m.set_state(P, 0)
+        sig = [np.array([[0, 1], [1, 0]]), np.array([[0, -1j], [1j, 0]]), np.array([[1, 0], [0, -1]])]
+        rho0 = 0.5 * (np.eye(2)[None] + sum(P[i][:, None, None] * sig[i] for i in range(3)))
+    else:
+        psi = rng.normal(size=(6, nb)); psi /= np.linalg.norm(psi, axis=0)
+        m.set_state(psi, 0)
+        pv = (psi[0::2] + 1j * psi[1::2]).T
+        rho0 = np.einsum("bi,bj->bij", pv, pv.conj())
+    rho0 = rho0.reshape(2, NU, NE, nf, nf)
+    E, dE, u, du = ref.bins(d)
+    R, h = d["r_nu_km"], (d["r_end_km"] - d["r_start_km"]) / d["n_steps"]
+    r0, rm, r1 = d["r_start_km"], d["r_start_km"] + 0.5 * h, d["r_start_km"] + h
+    hvac = ref.hvac2 if nf == 2 else ref.hvac3
+    e_ee = np.zeros((nf, nf)); e_ee[0, 0] = 1.0
+
+    def gens(r, rho):
+        lam = ref.sqrt2gf_km_cm3() * d["n0_cm3"] * (R / r) ** 3
+        Hnn = ref.brute_h_nunu(d, r, rho[0], rho[1])
+        K = np.zeros((2, NU, NE, nf, nf), complex)
+        for s in range(2):
+            sg = 1 if s == 0 else -1
+            for j in range(NU):
+                c = np.sqrt(1.0 - u[j] * (R / r) ** 2)
+                for k in range(NE):
+                    K[s, j, k] = (h / c) * (hvac(d, E[k]) + sg * lam * e_ee + Hnn[s, j, k])
+        return K
+
+    def evolve(G, rho):
+        U = np.array([[[linalg.expm(-1j * G[s, j, k]) for k in range(NE)] for j in range(NU)]
+                      for s in range(2)])
+        return U @ rho @ np.conj(np.swapaxes(U, -1, -2))
+
+    def icomm(A, B):
+        return 1j * (A @ B - B @ A)
+
+    K1 = gens(r0, rho0)
+    K2 = gens(rm, evolve(0.5 * K1, rho0))
+    K3 = gens(rm, evolve(0.5 * K2 + icomm(K1, K2) / 8.0, rho0))
+    K4 = gens(r1, evolve(K3, rho0))
+    want = evolve((K1 + 2.0 * K2 + 2.0 * K3 + K4) / 6.0 + icomm(K1, K4) / 12.0, rho0)
+    m.step(1)
+    x = m.get_state()
+    if nf == 2:
+        got = 0.5 * (np.eye(2)[None] + sum(x[i][:, None, None] * sig[i] for i in range(3)))
+    else:
+        gv = (x[0::2] + 1j * x[1::2]).T
+        got = np.einsum("bi,bj->bij", gv, gv.conj())
+    got = got.reshape(2, NU, NE, nf, nf)
+    kmax = max(np.abs(K1).max(), np.abs(K4).max())
+    assert kmax > 1e-3                      # the step actually rotates the states
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
