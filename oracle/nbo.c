@@ -220,8 +220,9 @@ static inline double norm3(const cx v[3]) {
  * the 2x2 propagator of Eq. U on the plane, th = |(K0 - hm) w| / |w| for any w in the
  * plane (here w = P psi).  The traces (of K, and e^{-i hm}) only contribute global phases.
  * v1 is kept unnormalised (v1 = c / |c| with c a column of adj(K0 - l1)), so intermediate
- * magnitudes grow like |K0|^5: the form holds for 2^-100 < |K0| < 1e60, and
- * |K0|^2 / 2 <= 2^-200 is taken as K0 = 0 (error below 1e-30). */
+ * magnitudes grow like |K0|^5; with the sin/cos reduction (phases below 2^50) the form
+ * holds for 2^-100 < |K0| < 1e15, and |K0|^2 / 2 <= 2^-200 is taken as K0 = 0 (error below
+ * 1e-30). */
 static void exp3_apply(const herm3 *K, const cx psi[3], cx out[3]) {
   const double tr = ((K->d[0] + K->d[1]) + K->d[2]) * (1.0 / 3.0);
   const double a0 = K->d[0] - tr, a1 = K->d[1] - tr, a2 = K->d[2] - tr;

@@ -169,8 +169,8 @@ __device__ __forceinline__ double cnorm2v(const cplx v[3]) {
 //   psi' = e^{-i (l1 - hm)} (v1^+ psi) v1 + cos(th) P psi - i sin(th)/th (K0 - hm) P psi,
 // P = I - v1 v1^+, th = |(K0 - hm) w| / |w| for any w in the plane, here w = P psi.
 // Nothing is normalised: (v1^+ psi) v1 = al c with al = (c^+ psi) / |c|^2.  The magnitudes
-// then grow like |K0|^5, which holds for 2^-100 < |K0| < 1e60; |K0|^2 / 2 <= 2^-200 is
-// taken as K0 = 0 (error below 1e-30).
+// then grow like |K0|^5; with the sin/cos reduction (phases below 2^50) the form holds for
+// 2^-100 < |K0| < 1e15; |K0|^2 / 2 <= 2^-200 is taken as K0 = 0 (error below 1e-30).
 // (K0 - hm) v: rows (d0, x, y), (x^*, d1, z), (y^*, z^*, d2), each a complex dot product
 // with the real diagonal entry, fused from the last product up
 __device__ __forceinline__ void k0_minus(const cplx v[3], double d0, double d1, double d2,

@@ -84,6 +84,37 @@ def test_exp3_bitwise(nb, oracle):
                 ks.append(k9)
                 p = rng.normal(size=6)
                 ps.append(p / np.linalg.norm(p))
+    # the form's range and its special cases: |K| at and around the 2^-100 floor, huge |K|,
+    # psi along the isolated eigenvector (P psi from 1e-2 down to 0), flavour eigenstates of
+    # a diagonal K, an exactly degenerate pair of eigenvalues
+    for scale in (1e-31, 3e-30, 1e-29, 1e-20, 1e9, 1e14):
+        for _ in range(50):
+            ks.append(rng.normal(size=9) * scale)
+            p = rng.normal(size=6)
+            ps.append(p / np.linalg.norm(p))
+    for scale in (0.3, 50.0):
+        for _ in range(20):
+            k9 = rng.normal(size=9) * scale
+            H = np.diag(k9[:3]).astype(complex)
+            for t, (a, b) in enumerate([(0, 1), (0, 2), (1, 2)]):
+                H[a, b] = k9[3 + 2 * t] + 1j * k9[4 + 2 * t]
+                H[b, a] = np.conj(H[a, b])
+            ev, V = np.linalg.eigh(H - np.trace(H) / 3 * np.eye(3))
+            i1 = int(np.argmax(np.abs(ev)))
+            pl = V[:, [i for i in range(3) if i != i1]] @ (rng.normal(size=2) + 1j * rng.normal(size=2))
+            for dlt in (1e-2, 1e-10, 1e-17, 0.0):
+                pv = V[:, i1] + dlt * pl / np.linalg.norm(pl)
+                pv /= np.linalg.norm(pv)
+                ks.append(k9)
+                ps.append(np.stack([pv.real, pv.imag], axis=1).ravel())
+    for e in range(3):
+        k9 = np.zeros(9); k9[:3] = [3.0, -1.0, 0.5]
+        p = np.zeros(6); p[2 * e] = 1.0
+        ks.append(k9); ps.append(p)
+    k9 = np.zeros(9); k9[:3] = [2.0, -1.0, -1.0]          # eigenvalues (2, -1, -1) exactly
+    for _ in range(10):
+        p = rng.normal(size=6)
+        ks.append(k9); ps.append(p / np.linalg.norm(p))
     ks, ps = np.array(ks), np.array(ps)
     got = nb.test_exp3(_dev(ks), _dev(ps)).cpu().numpy()
     want = np.stack([oracle.exp3_apply(ks[i], ps[i]) for i in range(len(ks))])
