@@ -71,7 +71,8 @@ def test_spectrum_weights_against_quadrature(oracle):
 def test_sincos_against_libm(oracle):
     rng = np.random.default_rng(7)
     x = np.concatenate([np.linspace(-8, 8, 20001), rng.uniform(-1e3, 1e3, 20000),
-                        rng.uniform(-4e6, 4e6, 20000), [0.0, -0.0, np.pi / 4, 1e-300]])
+                        rng.uniform(-4e6, 4e6, 20000), rng.uniform(-1e15, 1e15, 20000),
+                        [0.0, -0.0, np.pi / 4, 1e-300, 2.0 ** 50 * 0.999]])
     s, c = oracle.sincos(x)
     assert np.max(np.abs(s - np.sin(x))) <= 2.3e-16
     assert np.max(np.abs(c - np.cos(x))) <= 2.3e-16
