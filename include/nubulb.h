@@ -60,7 +60,8 @@ typedef struct {
   int32_t n_energy;     /* N_E bins of equal width over [e_min_mev, e_max_mev], midpoints */
   int32_t n_u;          /* N_u bins of equal width in u = sin^2(theta_R) over [0,1], midpoints */
   int32_t ne_power;     /* n_e(r) = n0_cm3 (R/r)^ne_power; 3 for the bulb, 0..8 allowed */
-  int32_t precision;    /* NB_FP64, or NB_FP32_STATE (3 flavours: state stored in FP32) */
+  int32_t precision;    /* NB_FP64, or NB_FP32_STATE (3 flavours: state stored in FP32;
+                           at most 2^30 - 64 beams, NB_EINVAL beyond) */
   int32_t renorm;       /* 1: renormalise every beam after every step (0: tests only); the
                            factor is 1.5 - n^2/2, exact to rounding for the near-unit norms a
                            step leaves (initial states must have unit norm) */

@@ -138,6 +138,10 @@ static int validate(const nb_params* p) {
     return fail(NB_EINVAL, "unknown precision");
   if (p->precision == NB_FP32_STATE && p->n_flavor != 3)
     return fail(NB_EINVAL, "FP32 state is a three-flavour mode");
+  // the FP32 stepping kernel addresses a state plane with 32-bit byte offsets
+  if (p->precision == NB_FP32_STATE &&
+      (long long)p->n_energy * p->n_u * (p->track_all ? 2 * p->n_flavor : 2) > (1LL << 30) - 64)
+    return fail(NB_EINVAL, "FP32 state planes must stay below 4 GiB (at most 2^30 - 64 beams)");
   for (int i = 0; i < 3; ++i)
     if (!(p->temp_mev[i] > 0.0) || !(p->lum_erg_s[i] >= 0.0))
       return fail(NB_EINVAL, "temperatures must be > 0 and luminosities >= 0");
@@ -503,6 +507,15 @@ static constexpr size_t kTabLdsMax = 96 * 1024;
 static size_t tab_bytes(const nb_model* m) { return sizeof(double) * m->tab.size(); }
 static bool tab_in_lds(const nb_model* m) { return !m->batch && tab_bytes(m) <= kTabLdsMax; }
 static size_t advance_dyn_lds(const nb_model* m) { return tab_in_lds(m) ? tab_bytes(m) : 0; }
+// The FP32-arithmetic kernel stages the table and, from the next 16-byte boundary, an FP32
+// copy of the vacuum rows and e_k (eight floats per energy) when both fit in this many
+// bytes (with its static LDS, below the 160 KB of a CU).
+static constexpr size_t kTabLdsMaxF32 = 104 * 1024;
+static size_t f32_lds_bytes(const nb_model* m) {
+  return sizeof(double) * ((m->tab.size() + 1) & ~(size_t)1) + sizeof(float) * 8 * (size_t)m->p.n_energy;
+}
+static bool f32_tab_in_lds(const nb_model* m) { return !m->batch && f32_lds_bytes(m) <= kTabLdsMaxF32; }
+static size_t f32_dyn_lds(const nb_model* m) { return f32_tab_in_lds(m) ? f32_lds_bytes(m) : 0; }
 
 // The adaptive-step kernel of a single FP64 model created with adaptive = 1 (else nullptr).
 static const void* adaptive_kernel(const nb_model* m) {
@@ -528,7 +541,8 @@ static const void* advance_kernel(const nb_model* m) {
 // The FP32-arithmetic stepping kernel of the mixed-precision mode (nullptr otherwise).
 static const void* advance_kernel_f32(const nb_model* m) {
   if (m->batch || !state_fp32(m)) return nullptr;
-  return tab_in_lds(m) ? (const void*)&k_advance<3, float, true, true, false> : (const void*)&k_advance<3, float, false, true, false>;
+  return f32_tab_in_lds(m) ? (const void*)&k_advance<3, float, true, true, false>
+                           : (const void*)&k_advance<3, float, false, true, false>;
 }
 
 static int launch_1d(const void* fn, long long n, void** args, hipStream_t s) {
@@ -632,7 +646,7 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
   if (advance_kernel_f32(m)) {
     int nb32 = 0;
     NB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb32, advance_kernel_f32(m), kBlock,
-                                                         advance_dyn_lds(m)));
+                                                         f32_dyn_lds(m)));
     nbpm = std::min(nbpm, nb32);
   }
   if (adaptive_kernel(m)) {
@@ -810,17 +824,16 @@ static int enqueue_advance(nb_model* m, long long k) {
   for (int q = 0; q < 6; ++q) a.v0[q] = s.v0[q];
   a.timeout_ticks = timeout;
   a.Jhist = m->jhist;
-  auto launch = [&](const void* fn) -> int {
+  auto launch = [&](const void* fn, size_t lds) -> int {
     void* args[] = {&a};
     const hipError_t e =
         capturing(m->stream)
-            ? hipLaunchKernel(fn, dim3(m->nblocks), dim3(kBlock), args, advance_dyn_lds(m), m->stream)
-            : hipLaunchCooperativeKernel(fn, dim3(m->nblocks), dim3(kBlock), args,
-                                         (unsigned)advance_dyn_lds(m), m->stream);
+            ? hipLaunchKernel(fn, dim3(m->nblocks), dim3(kBlock), args, lds, m->stream)
+            : hipLaunchCooperativeKernel(fn, dim3(m->nblocks), dim3(kBlock), args, (unsigned)lds, m->stream);
     if (e != hipSuccess) return fail(NB_EHIP, "stepping launch: %s", hipGetErrorString(e));
     return NB_OK;
   };
-  if (!advance_kernel_f32(m)) return launch(advance_kernel(m));
+  if (!advance_kernel_f32(m)) return launch(advance_kernel(m), advance_dyn_lds(m));
   // Mixed precision: FP64-arithmetic steps before fp32_from, FP32-arithmetic steps after,
   // as two windowed launches sharing one target of k steps from the device counter.
   {
@@ -832,13 +845,13 @@ static int enqueue_advance(nb_model* m, long long k) {
   a.use_window = 1;
   a.win_lo = 0;
   a.win_hi = s.fp32_from;
-  int rc = launch(advance_kernel(m));
+  int rc = launch(advance_kernel(m), advance_dyn_lds(m));
   if (rc) return rc;
   rc = zero_sync(m, 1);
   if (rc) return rc;
   a.win_lo = s.fp32_from;
   a.win_hi = m->p.n_steps;
-  return launch(advance_kernel_f32(m));
+  return launch(advance_kernel_f32(m), f32_dyn_lds(m));
 }
 
 static int advance(nb_model* m, long long n) {

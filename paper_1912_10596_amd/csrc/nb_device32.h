@@ -72,15 +72,7 @@ __device__ __forceinline__ cplxf mkf(float re, float im) { return cplxf{re, im};
 __device__ __forceinline__ cplxf cmulf(cplxf a, cplxf b) {
   return mkf(fmaf(a.re, b.re, -(a.im * b.im)), fmaf(a.re, b.im, a.im * b.re));
 }
-__device__ __forceinline__ cplxf cmulf_conja(cplxf a, cplxf b) {  // conj(a) * b
-  return mkf(fmaf(a.re, b.re, a.im * b.im), fmaf(a.re, b.im, -(a.im * b.re)));
-}
-__device__ __forceinline__ cplxf cmulf_conjb(cplxf a, cplxf b) {  // a * conj(b)
-  return mkf(fmaf(a.re, b.re, a.im * b.im), fmaf(a.im, b.re, -(a.re * b.im)));
-}
 __device__ __forceinline__ cplxf rmulf(float a, cplxf b) { return mkf(a * b.re, a * b.im); }
-__device__ __forceinline__ cplxf caddf(cplxf a, cplxf b) { return mkf(a.re + b.re, a.im + b.im); }
-__device__ __forceinline__ cplxf csubf(cplxf a, cplxf b) { return mkf(a.re - b.re, a.im - b.im); }
 __device__ __forceinline__ cplxf conjf_(cplxf a) { return mkf(a.re, -a.im); }
 __device__ __forceinline__ float norm2f(cplxf a) { return fmaf(a.re, a.re, a.im * a.im); }
 
@@ -88,14 +80,28 @@ struct Herm3f {
   float d0, d1, d2;
   cplxf o01, o02, o12;
 };
+// The sums below are written as single fma chains (one product rounded on its own, the
+// rest fused), which halves the instruction count against separate products and adds.
 __device__ __forceinline__ float cnorm2vf(const cplxf v[3]) {
-  return (norm2f(v[0]) + norm2f(v[1])) + norm2f(v[2]);
+  return fmaf(v[0].re, v[0].re, fmaf(v[0].im, v[0].im, fmaf(v[1].re, v[1].re, fmaf(v[1].im, v[1].im,
+              fmaf(v[2].re, v[2].re, v[2].im * v[2].im)))));
 }
+// u^+ v
+__device__ __forceinline__ cplxf dotcf(const cplxf u[3], const cplxf v[3]) {
+  return mkf(fmaf(u[0].re, v[0].re, fmaf(u[0].im, v[0].im, fmaf(u[1].re, v[1].re, fmaf(u[1].im, v[1].im,
+                 fmaf(u[2].re, v[2].re, u[2].im * v[2].im))))),
+             fmaf(u[0].re, v[0].im, fmaf(-u[0].im, v[0].re, fmaf(u[1].re, v[1].im, fmaf(-u[1].im, v[1].re,
+                 fmaf(u[2].re, v[2].im, -(u[2].im * v[2].re)))))));
+}
+// (K0 - hm) v: rows (d0, x, y), (x^*, d1, z), (y^*, z^*, d2)
 __device__ __forceinline__ void k0_minusf(const cplxf v[3], float d0, float d1, float d2, cplxf x,
                                           cplxf y, cplxf z, cplxf o[3]) {
-  o[0] = caddf(caddf(rmulf(d0, v[0]), cmulf(x, v[1])), cmulf(y, v[2]));
-  o[1] = caddf(caddf(cmulf_conja(x, v[0]), rmulf(d1, v[1])), cmulf(z, v[2]));
-  o[2] = caddf(caddf(cmulf_conja(y, v[0]), cmulf_conja(z, v[1])), rmulf(d2, v[2]));
+  o[0] = mkf(fmaf(d0, v[0].re, fmaf(x.re, v[1].re, fmaf(-x.im, v[1].im, fmaf(y.re, v[2].re, -(y.im * v[2].im))))),
+             fmaf(d0, v[0].im, fmaf(x.re, v[1].im, fmaf(x.im, v[1].re, fmaf(y.re, v[2].im, y.im * v[2].re)))));
+  o[1] = mkf(fmaf(x.re, v[0].re, fmaf(x.im, v[0].im, fmaf(d1, v[1].re, fmaf(z.re, v[2].re, -(z.im * v[2].im))))),
+             fmaf(x.re, v[0].im, fmaf(-x.im, v[0].re, fmaf(d1, v[1].im, fmaf(z.re, v[2].im, z.im * v[2].re)))));
+  o[2] = mkf(fmaf(y.re, v[0].re, fmaf(y.im, v[0].im, fmaf(z.re, v[1].re, fmaf(z.im, v[1].im, d2 * v[2].re)))),
+             fmaf(y.re, v[0].im, fmaf(-y.im, v[0].re, fmaf(z.re, v[1].im, fmaf(-z.im, v[1].re, d2 * v[2].im)))));
 }
 
 // Eigen-split of exp(-i K) in FP32, the algorithm of the FP64 version (largest eigenvalue
@@ -125,11 +131,13 @@ __device__ __forceinline__ bool split3_f(const Herm3f& K, const cplxf psi[3], Sp
   if (!(p > 0.0f)) return false;
   const float sg = (q < 0.0f) ? -1.0f : 1.0f;
   const float qa = sg * q;
-  // start: 2 sqrt(p/3) by halving the exponent in the bit pattern (above the root, within
-  // 23 % of it)
-  float lam = 2.0f * __int_as_float((int)(((unsigned)__float_as_int(p * (1.0f / 3.0f)) >> 1) + 0x1FC00000u));
+  // start: 0.9 times 2 sqrt(p/3), the square root by halving the exponent in the bit
+  // pattern (at most 6.1 % above it).  The root lies between sqrt(p) and 2 sqrt(p/3), so the
+  // start is within 10 % of it on either side, from where two Halley steps leave a relative
+  // error below 1e-8 (worst case over the cubic's shapes and the estimate's range).
+  float lam = 1.8f * __int_as_float((int)(((unsigned)__float_as_int(p * (1.0f / 3.0f)) >> 1) + 0x1FC00000u));
 #pragma unroll
-  for (int it = 0; it < 3; ++it) {
+  for (int it = 0; it < 2; ++it) {
     const float l2 = lam * lam;
     const float fv = fmaf(lam, l2 - p, -qa);
     const float dv = fmaf(3.0f, l2, -p);
@@ -157,10 +165,11 @@ __device__ __forceinline__ bool split3_f(const Herm3f& K, const cplxf psi[3], Sp
   for (int c = 0; c < 3; ++c) o.v1[c] = rmulf(inb, best[c]);
   const float hm = -0.5f * l1;
   const float d0 = a0 - hm, d1 = a1 - hm, d2 = a2 - hm;
-  o.al = caddf(caddf(cmulf_conja(o.v1[0], psi[0]), cmulf_conja(o.v1[1], psi[1])),
-               cmulf_conja(o.v1[2], psi[2]));
+  o.al = dotcf(o.v1, psi);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) o.pp[c] = csubf(psi[c], cmulf(o.al, o.v1[c]));
+  for (int c = 0; c < 3; ++c)   // psi - al v1
+    o.pp[c] = mkf(fmaf(-o.al.re, o.v1[c].re, fmaf(o.al.im, o.v1[c].im, psi[c].re)),
+                  fmaf(-o.al.re, o.v1[c].im, fmaf(-o.al.im, o.v1[c].re, psi[c].im)));
   k0_minusf(o.pp, d0, d1, d2, x, y, z, o.kp);
   // (K0 - hm)^2 = th^2 on the plane: th^2 = |kp|^2 / |pp|^2 (0 for pp = 0)
   const float npp = cnorm2vf(o.pp);
@@ -196,9 +205,9 @@ __device__ __forceinline__ void exp3_apply_f(const Herm3f& K, cplxf psi[3]) {
   phases_f(e, cp, sp, ct, sc);
   const cplxf ap = cmulf(e.al, mkf(cp, -sp));
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
-    psi[c] = caddf(cmulf(ap, e.v1[c]),
-                   mkf(fmaf(ct, e.pp[c].re, sc * e.kp[c].im), fmaf(ct, e.pp[c].im, -(sc * e.kp[c].re))));
+  for (int c = 0; c < 3; ++c)   // ap v1 + cos(th) pp - i sin(th)/th kp
+    psi[c] = mkf(fmaf(ap.re, e.v1[c].re, fmaf(-ap.im, e.v1[c].im, fmaf(ct, e.pp[c].re, sc * e.kp[c].im))),
+                 fmaf(ap.re, e.v1[c].im, fmaf(ap.im, e.v1[c].re, fmaf(ct, e.pp[c].im, -(sc * e.kp[c].re)))));
 }
 
 // The increment d = exp(-i K) psi - psi in FP32 (global phase of exp dropped as above),
@@ -231,8 +240,8 @@ __device__ __forceinline__ void exp3_incr_f(const Herm3f& K, const cplxf psi[3],
   const cplxf ap = cmulf(e.al, mkf(cpm1, -sp));
 #pragma unroll
   for (int c = 0; c < 3; ++c)
-    d[c] = caddf(cmulf(ap, e.v1[c]),
-                 mkf(fmaf(ctm1, e.pp[c].re, sc * e.kp[c].im), fmaf(ctm1, e.pp[c].im, -(sc * e.kp[c].re))));
+    d[c] = mkf(fmaf(ap.re, e.v1[c].re, fmaf(-ap.im, e.v1[c].im, fmaf(ctm1, e.pp[c].re, sc * e.kp[c].im))),
+               fmaf(ap.re, e.v1[c].im, fmaf(ap.im, e.v1[c].re, fmaf(ctm1, e.pp[c].im, -(sc * e.kp[c].re)))));
 }
 
 }  // namespace nb

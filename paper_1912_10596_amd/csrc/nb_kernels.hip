@@ -771,16 +771,22 @@ __device__ __forceinline__ void prefetch_first(const StepArgs& a, long long gw, 
 // beams) are summed in FP64 and converted to fixed point once per segment, so the total
 // does not depend on the launch shape; 16 contributions below 2^51 each stay below the
 // 2^56 that the fold's 64-bit lane sums allow.
-template <int KIND>
+// FT: ftab (LDS) holds the vacuum rows and e_k as FP32, eight floats per energy
+// (H_ee, H_mumu, H_tautau, H_emu, H_etau, H_mutau, e_k, 0), read by stages 1-3.
+template <int KIND, bool FT>
 __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Radial& g0, const Radial& gm,
                                       const Radial& g1, const RowGeo& rg, double icmom, const double (*sJ)[16],
-                                      const double* tab, double* snd, float* snn, int lane, long long* fl,
-                                      I128& T, int& err) {
+                                      const double* tab, const float* ftab, double* snd, float* snn, int lane,
+                                      long long* fl, I128& T, int& err) {
 #pragma clang fp contract(fast)
   constexpr int kSeg = 64 * 16;
   const long long plane = a.plane;
   const int NE = a.NE;
-  float* X = (float*)a.X;
+  // per-plane bases (uniform) and one 32-bit byte offset per lane: the FP32 planes are
+  // below 2^32 bytes (checked at model creation)
+  char* Xp[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) Xp[c] = (char*)((float*)a.X + c * plane);
   const int s = (int)(row / a.NU);
   const int an = (s >= (a.NS >> 1)) ? 1 : 0;   // antiparticle row
   // generator row constants (FP64, as in the FP64 stepper): snd[0..8] Q, snd[9..17] P;
@@ -805,23 +811,31 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
     float q[6];
     if (k0 < kend) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) q[c] = X[rb + k0 + c * plane];
+      for (int c = 0; c < 6; ++c) q[c] = *(const float*)(Xp[c] + (unsigned)(rb + k0) * 4u);
     }
     for (int k = k0; k < kend; k += 64) {
       cplxf ps[3] = {mkf(q[0], q[1]), mkf(q[2], q[3]), mkf(q[4], q[5])};
       if (k + 64 < kend) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) q[c] = X[rb + k + 64 + c * plane];
+        for (int c = 0; c < 6; ++c) q[c] = *(const float*)(Xp[c] + (unsigned)(rb + k + 64) * 4u);
       }
       __asm__ volatile("" ::: "memory");
       double pd[6];
       if (KIND >= 1) {
-        float v[6];
+        float v[6], ekf = 0.0f;
         double vd[6];
+        if constexpr (KIND <= 3 && FT) {
+          const float4 f0 = *reinterpret_cast<const float4*>(ftab + 8 * k);
+          const float4 f1 = *reinterpret_cast<const float4*>(ftab + 8 * k + 4);
+          v[0] = f0.x; v[1] = f0.y; v[2] = f0.z; v[3] = f0.w; v[4] = f1.x; v[5] = f1.y;
+          ekf = f1.z;
+        } else {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
-          vd[c] = tab[c * NE + k];
-          v[c] = (float)vd[c];
+          for (int c = 0; c < 6; ++c) {
+            vd[c] = tab[c * NE + k];
+            v[c] = (float)vd[c];
+          }
+          if (KIND == 2) ekf = (float)tab[6 * NE + k];
         }
         if (KIND == 1 || KIND == 3) {
           exp3_apply_f(Herm3f{fmaf(alphaf, v[0], snn[0]), fmaf(alphaf, v[1], snn[1]), fmaf(alphaf, v[2], snn[2]),
@@ -829,7 +843,7 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
                               mkf(fmaf(alphaf, v[5], snn[7]), snn[8])},
                        ps);
         } else if (KIND == 2) {
-          const float ek = (float)tab[6 * NE + k];
+          const float ek = ekf;
           const float* P = snn + 9;
           exp3_apply_f(Herm3f{fmaf(alphaf, v[0], fmaf(ek, P[0], snn[0])), fmaf(alphaf, v[1], fmaf(ek, P[1], snn[1])),
                               fmaf(alphaf, v[2], fmaf(ek, P[2], snn[2])),
@@ -859,7 +873,7 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
           const float o[6] = {(float)(re0 * inv), (float)(im0 * inv), (float)(re1 * inv),
                               (float)(im1 * inv), (float)(re2 * inv), (float)(im2 * inv)};
 #pragma unroll
-          for (int c = 0; c < 6; ++c) X[rb + k + c * plane] = o[c];
+          for (int c = 0; c < 6; ++c) *(float*)(Xp[c] + (unsigned)(rb + k) * 4u) = o[c];
           ps[0] = mkf(o[0], o[1]);
           ps[1] = mkf(o[2], o[3]);
           ps[2] = mkf(o[4], o[5]);
@@ -891,10 +905,11 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
 // launches only over steps whose stage generators rotate a beam by at most one radian per
 // step (a bound computed from the model's parameters); nearer the neutrinosphere FP32
 // cannot hold the per-step phase and the FP64-arithmetic launch on the FP32 state is used.
-template <int KIND>
+template <int KIND, bool FT>
 __device__ __forceinline__ void stage3m(const StepArgs& a, const StepGeo& G, const double (*sJ)[16],
-                                        const double* tab, double* snn, long long gw, long long nw,
-                                        int lane, long long* fl, I128& T, int& err, double* gc = nullptr) {
+                                        const double* tab, const float* ftab, double* snn, long long gw,
+                                        long long nw, int lane, long long* fl, I128& T, int& err,
+                                        double* gc = nullptr) {
   const Radial g0 = radial_at(a, G.r0), gm = radial_at(a, G.rm), g1 = radial_at(a, G.r1);
   const long long nrow = (long long)a.NS * a.NU;
   for (long long row = gw; row < nrow; row += nw) {
@@ -903,7 +918,7 @@ __device__ __forceinline__ void stage3m(const StepArgs& a, const StepGeo& G, con
     RowGeo rg;
     double icmom, sn0, snm, sn1;
     stage_geo<KIND, false>(u_of(j, a.NU), G.h, g0, gm, g1, row == gw ? gc : nullptr, rg, icmom, sn0, snm, sn1);
-    row3m<KIND>(a, row, g0, gm, g1, rg, icmom, sJ, tab, snn, (float*)(snn + 32), lane, fl, T, err);
+    row3m<KIND, FT>(a, row, g0, gm, g1, rg, icmom, sJ, tab, ftab, snn, (float*)(snn + 32), lane, fl, T, err);
   }
 }
 
@@ -922,14 +937,25 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   // per wavefront: row constants (mixed: then 32 floats), then the first row's geometry
   __shared__ double snn_all[kBlock / 64][F32 ? 64 : 48];
   __shared__ long long sfold[kBlock / 64][(NC + 2) * 64];
-  extern __shared__ double dyn_tab[];
+  extern __shared__ __align__(16) double dyn_tab[];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const long long gw = (long long)blockIdx.x * (kBlock / 64) + wid;
   const long long nw = (long long)gridDim.x * (kBlock / 64);
   const double* tab = a.tab;
+  const float* ftab = nullptr;
   if constexpr (TLDS) {
     const int ntab = ((NF == 2) ? 2 : kVacRows3) * a.NE + a.NS * a.NE;
     for (int i = threadIdx.x; i < ntab; i += kBlock) dyn_tab[i] = a.tab[i];
+    if constexpr (F32) {
+      // the FP32 copy of the vacuum rows and e_k, eight floats per energy, after the table
+      // (at a 16-byte boundary)
+      float* ft = reinterpret_cast<float*>(dyn_tab + ((ntab + 1) & ~1));
+      for (int i = threadIdx.x; i < 8 * a.NE; i += kBlock) {
+        const int k = i >> 3, c = i & 7;
+        ft[i] = (c < 7) ? (float)a.tab[c * a.NE + k] : 0.0f;
+      }
+      ftab = ft;
+    }
     __syncthreads();
     tab = dyn_tab;
   }
@@ -954,7 +980,7 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   ST pre[6] = {};
   const long long nrow3 = (long long)a.NS * a.NU * (EXT ? a.NP : 1);
   if constexpr (NF == 2) stage2<0, false, EXT>(a, geo_fixed(a, step0), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
-  else if constexpr (F32) stage3m<0>(a, geo_fixed(a, step0), sJ, tab, snn, gw, nw, lane, fl, T, err);
+  else if constexpr (F32) stage3m<0, TLDS>(a, geo_fixed(a, step0), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err);
     else { stage3<ST, 0, false, EXT>(a, geo_fixed(a, step0), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
   ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[0]);
   // the adjoint's forward pass records every stage's moments: [step][slot][NV]
@@ -966,25 +992,25 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   for (long long n = step0; ok && n < step0 + nsteps; ++n) {
     T = i128_zero();
     if constexpr (NF == 2) stage2<1, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, gc);
-    else if constexpr (F32) stage3m<1>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err, gc);
+    else if constexpr (F32) stage3m<1, TLDS>(a, geo_fixed(a, n), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err, gc);
     else { stage3<ST, 1, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     if (!(ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[1]))) break;
     record(n, 1);
     T = i128_zero();
     if constexpr (NF == 2) stage2<2, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, gc);
-    else if constexpr (F32) stage3m<2>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err, gc);
+    else if constexpr (F32) stage3m<2, TLDS>(a, geo_fixed(a, n), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err, gc);
     else { stage3<ST, 2, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     if (!(ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[2]))) break;
     record(n, 2);
     T = i128_zero();
     if constexpr (NF == 2) stage2<3, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, gc);
-    else if constexpr (F32) stage3m<3>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err, gc);
+    else if constexpr (F32) stage3m<3, TLDS>(a, geo_fixed(a, n), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err, gc);
     else { stage3<ST, 3, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     if (!(ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[3]))) break;
     record(n, 3);
     T = i128_zero();
     if constexpr (NF == 2) stage2<4, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, gc);
-    else if constexpr (F32) stage3m<4>(a, geo_fixed(a, n), sJ, tab, snn, gw, nw, lane, fl, T, err, gc);
+    else if constexpr (F32) stage3m<4, TLDS>(a, geo_fixed(a, n), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err, gc);
     else { stage3<ST, 4, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[0]);
     record(n + 1, 0);
@@ -1027,7 +1053,7 @@ __global__ void __launch_bounds__(kBlock) k_adaptive(StepArgs a) {
   __shared__ long long sacc[kBlock];
   __shared__ double snn_all[kBlock / 64][48];   // row constants, then the first row's geometry
   __shared__ long long sfold[kBlock / 64][(NC + 2) * 64];
-  extern __shared__ double dyn_tab[];
+  extern __shared__ __align__(16) double dyn_tab[];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const long long gw = (long long)blockIdx.x * (kBlock / 64) + wid;
   const long long nw = (long long)gridDim.x * (kBlock / 64);

@@ -172,3 +172,15 @@ def test_mixed_precision_switch_is_a_valid_angle_bound(oracle, r_start):
             K -= np.trace(K) / 3.0 * np.eye(3)
             worst = max(worst, np.abs(np.linalg.eigvalsh(K)).max())
     assert worst < 1.0, worst
+
+
+def test_fp32_state_beam_limit(nb):
+    """The FP32-arithmetic kernel addresses a state plane with 32-bit byte offsets, so FP32
+    state is limited to 2^30 - 64 beams; FP64 state of the same size is accepted."""
+    d = workloads.small_params(n_flavor=3, n_energy=1024, n_u=1 << 19)
+    with pytest.raises(nb.NubulbError) as e:
+        nb.HostModel(d, precision=nb.NB_FP32_STATE)
+    assert e.value.code == nb.NB_EINVAL
+    assert nb.HostModel(d).nb == 1 << 30
+    ok = workloads.small_params(n_flavor=3, n_energy=1023, n_u=1 << 19)
+    assert nb.HostModel(ok, precision=nb.NB_FP32_STATE).nb == 1023 * 2 ** 20
