@@ -67,6 +67,22 @@ def test_mixed_resolved_small_against_fp64(nb):
     assert np.abs(p64 - p32).max() > 0.0           # it really is a different arithmetic
 
 
+@pytest.mark.parametrize("n_energy", [1000, 1100])
+def test_mixed_fp32_table_in_and_out_of_lds(nb, n_energy):
+    """The FP32-arithmetic kernel reads an FP32 copy of the vacuum rows from LDS when the
+    table and the copy fit in 104 KB (1000 energies: 72 KB + 32 KB) and converts the FP64
+    rows from global memory otherwise (1100 energies: 79.2 KB + 35.2 KB); both give the same
+    FP32 values, so both stay within the target of the FP64 run."""
+    d = _small(600.0, 300, n_energy=n_energy, n_u=3)
+    m32 = _run(nb, d, 1)
+    assert m32.mixed_fp32_step() == 0
+    p64 = _run(nb, d, 0).pee().cpu().numpy()
+    p32 = m32.pee().cpu().numpy()
+    dp = np.abs(p64 - p32).max()
+    _say(f"resolved {n_energy}x3x2, 300 steps: max |dP_ee| = {dp:.3e}")
+    assert 0.0 < dp < TARGET
+
+
 def test_mixed_state_is_normalised(nb):
     d = _small(600.0, 50, n_energy=70, n_u=3)
     st = _run(nb, d, 1).get_state().cpu().numpy()
