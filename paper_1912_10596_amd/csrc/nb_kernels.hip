@@ -351,6 +351,12 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
                                      int& err, double& emax, double cp = 0.0, double sp = 0.0,
                                      int an = -1, double* gc = nullptr) {
   constexpr int NM = EXT ? 4 : 2;
+  // the lane's first beam of the row, loaded before the row set-up so that the set-up
+  // arithmetic overlaps the load
+  double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+  if (lane < NE) {
+    q0 = X[rb + lane]; q1 = X[rb + lane + plane]; q2 = X[rb + lane + 2 * plane];
+  }
   // species row s, antiparticle flag an (default: s itself, two tracked species)
   if (an < 0) an = s;
   RowGeo rg;
@@ -367,8 +373,7 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
     const int kend = min(NE, k0 + 64 * 32);
     const unsigned long long base = fix_base(k0, kend);
     unsigned long long acc[3] = {base, base, base};
-    double q0 = 0.0, q1 = 0.0, q2 = 0.0;
-    if (k0 < kend) {
+    if (k0 != lane && k0 < kend) {   // a later segment's first beam
       q0 = X[rb + k0]; q1 = X[rb + k0 + plane]; q2 = X[rb + k0 + 2 * plane];
     }
     for (int k = k0; k < kend; k += 64) {
