@@ -132,6 +132,8 @@ CASES = [
     (3, 70, 3, 10, 10.0, 10.5, 0),       # literal bulb start, 2 chunks, ragged tail
     (3, 64, 1, 6, 10.0, 10.3, 1),        # one block
     (3, 129, 4, 4, 40.0, 40.4, 2),
+    (2, 2200, 1, 4, 30.0, 30.4, 0),      # rows of two 2048-energy segments
+    (3, 2100, 1, 3, 40.0, 40.3, 0),      # two segments; tables (151 KB) read from HBM, not LDS
 ]
 
 
