@@ -64,6 +64,8 @@ def lib():
         L.nbo_rotate.restype = None
         L.nbo_fixed_sum.argtypes = [dp, C.c_int64, C.c_int]
         L.nbo_fixed_sum.restype = C.c_double
+        L.nbo_fix_round.argtypes = [dp, dp, C.c_int64, C.POINTER(C.c_int64)]
+        L.nbo_fix_round.restype = None
         L.nbo_single_angle_run.argtypes = [C.POINTER(Params), dp]
         L.nbo_adjoint.argtypes = [vp, C.c_int32, vp, dp, dp, vp]
         L.nbo_run_adaptive.argtypes = [vp, C.c_double, C.c_double, C.c_int64,
@@ -72,6 +74,22 @@ def lib():
         L.nbo_moments4.argtypes = [vp, C.c_double, dp]
         L.nbo_hamiltonian4.argtypes = [vp, C.c_double, dp, dp]
         L.nbo_phi_table.argtypes = [vp, dp]
+        L.nbp_create.argtypes = [C.POINTER(Params), C.POINTER(vp)]
+        L.nbp_destroy.argtypes = [vp]
+        L.nbp_destroy.restype = None
+        L.nbp_n_beams.argtypes = [vp]
+        L.nbp_n_beams.restype = C.c_int64
+        L.nbp_step_index.argtypes = [vp]
+        L.nbp_step_index.restype = C.c_int64
+        L.nbp_reset.argtypes = [vp]
+        L.nbp_step.argtypes = [vp, C.c_int64]
+        L.nbp_read_pee.argtypes = [vp, dp]
+        L.nbp_get_rho.argtypes = [vp, dp]
+        L.nbp_set_rho.argtypes = [vp, dp, C.c_int64]
+        L.nbp_moments.argtypes = [vp, C.c_double, dp]
+        L.nbp_hamiltonian.argtypes = [vp, C.c_double, dp]
+        L.nbp_expm.argtypes = [C.c_int, dp, dp]
+        L.nbp_expm.restype = None
         _lib = L
     return _lib
 
@@ -243,6 +261,96 @@ class Model:
         return float(loss.value), g
 
 
+def rho_from_planes(x: np.ndarray, nf: int) -> np.ndarray:
+    """Density matrices [nb][n][n] of state planes (2f: Bloch vectors [3][nb], rho =
+    (1 + P.sigma)/2; 3f: wavefunctions [6][nb] as Re/Im pairs, rho = psi psi^+)."""
+    x = np.asarray(x, np.float64)
+    if nf == 2:
+        P = x.reshape(3, -1)
+        rho = np.empty((P.shape[1], 2, 2), complex)
+        rho[:, 0, 0] = 0.5 * (1 + P[2]); rho[:, 1, 1] = 0.5 * (1 - P[2])
+        rho[:, 0, 1] = 0.5 * (P[0] - 1j * P[1]); rho[:, 1, 0] = 0.5 * (P[0] + 1j * P[1])
+        return rho
+    pv = (x.reshape(6, -1)[0::2] + 1j * x.reshape(6, -1)[1::2]).T
+    return np.einsum("bi,bj->bij", pv, pv.conj())
+
+
+class PlainModel:
+    """The oracle's plain mode (oracle/plain.c): density matrices, dense per-beam
+    generators, Jacobi exponentials, plain FP64 sums.  Same parameters and beam order as
+    Model; fixed-step RKMK4 only."""
+
+    def __init__(self, d: dict, species4: int = 0):
+        self.d = dict(d)
+        self.params = make_params(d, 0, species4)
+        h = C.c_void_p()
+        _check(lib().nbp_create(C.byref(self.params), C.byref(h)), "nbp_create")
+        self.h = h
+        self.nb = int(lib().nbp_n_beams(h))
+        self.nf = int(d["n_flavor"])
+        self.ns = 2 * self.nf if species4 else 2
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.nbp_destroy(self.h)
+            self.h = None
+
+    def reset(self):
+        _check(lib().nbp_reset(self.h), "nbp_reset")
+
+    def step(self, n: int):
+        _check(lib().nbp_step(self.h, int(n)), "nbp_step")
+
+    def run(self):
+        self.step(int(self.d["n_steps"]) - self.step_index())
+
+    def step_index(self) -> int:
+        return int(lib().nbp_step_index(self.h))
+
+    def pee(self) -> np.ndarray:
+        out = np.empty(self.nb, np.float64)
+        _check(lib().nbp_read_pee(self.h, _dp(out)), "nbp_read_pee")
+        nphi = int(self.d.get("n_phi", 0))
+        shape = (self.ns, int(self.d["n_u"])) + ((nphi,) if nphi else ()) + (int(self.d["n_energy"]),)
+        return out.reshape(shape)
+
+    def get_rho(self) -> np.ndarray:
+        n = self.nf
+        out = np.empty(self.nb * n * n * 2, np.float64)
+        _check(lib().nbp_get_rho(self.h, _dp(out)), "nbp_get_rho")
+        return out.view(np.complex128).reshape(self.nb, n, n)
+
+    def set_rho(self, rho: np.ndarray, step: int):
+        a = np.ascontiguousarray(np.asarray(rho, np.complex128).reshape(self.nb, self.nf, self.nf))
+        _check(lib().nbp_set_rho(self.h, _dp(a.view(np.float64).reshape(-1)), int(step)),
+               "nbp_set_rho")
+
+    def set_state(self, x: np.ndarray, step: int):
+        """From state planes as Model.set_state takes them."""
+        self.set_rho(rho_from_planes(x, self.nf), step)
+
+    def moments(self, r: float) -> np.ndarray:
+        n = self.nf
+        out = np.empty(4 * n * n * 2, np.float64)
+        _check(lib().nbp_moments(self.h, float(r), _dp(out)), "nbp_moments")
+        return out.view(np.complex128).reshape(4, n, n)
+
+    def hamiltonian(self, r: float) -> np.ndarray:
+        n = self.nf
+        out = np.empty(self.nb * n * n * 2, np.float64)
+        _check(lib().nbp_hamiltonian(self.h, float(r), _dp(out)), "nbp_hamiltonian")
+        return out.view(np.complex128).reshape(self.nb, n, n)
+
+
+def plain_expm(K: np.ndarray) -> np.ndarray:
+    """exp(-i K) of a Hermitian 2x2 or 3x3 K by the plain mode's Jacobi exponential."""
+    K = np.ascontiguousarray(np.asarray(K, np.complex128))
+    n = K.shape[0]
+    out = np.empty((n, n), np.complex128)
+    lib().nbp_expm(n, _dp(K.view(np.float64).reshape(-1)), _dp(out.view(np.float64).reshape(-1)))
+    return out
+
+
 def set_threads(n: int):
     lib().nbo_set_threads(int(n))
 
@@ -275,6 +383,15 @@ def rotate(x3, p3) -> np.ndarray:
 def fixed_sum(v, e: int) -> float:
     v = np.ascontiguousarray(v, np.float64)
     return float(lib().nbo_fixed_sum(_dp(v), v.size, int(e)))
+
+
+def fix_round(v, ws) -> np.ndarray:
+    """The fixed-point integers of beam contributions v * ws (round to nearest, ties even)."""
+    v = np.ascontiguousarray(v, np.float64); ws = np.ascontiguousarray(ws, np.float64)
+    assert v.shape == ws.shape
+    out = np.empty(v.size, np.int64)
+    lib().nbo_fix_round(_dp(v), _dp(ws), v.size, out.ctypes.data_as(C.POINTER(C.c_int64)))
+    return out
 
 
 def single_angle_run(d: dict) -> np.ndarray:

@@ -1230,6 +1230,11 @@ double nbo_fixed_sum(const double *v, int64_t n, int e) {
   return i128_to_double(a) * ldexp(1.0, -e);
 }
 
+/* The integer of every beam contribution fix_round(v[i], ws[i]) (tests). */
+void nbo_fix_round(const double *v, const double *ws, int64_t n, int64_t *out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = fix_round(v[i], ws[i]);
+}
+
 /* ------------------------------------------------------- single-angle solver */
 /* All beams at one emission bin u = 1/2.  Then J0 = J1/c and the neutrino-neutrino
  * Hamiltonian reduces to mu (1/c - c) J1 for every beam: a direct E-only system. */

@@ -93,6 +93,9 @@ void nbo_exp3_apply(const double *k9, const double *psi6, double *out6);
 void nbo_rotate(const double *x3, const double *p3, double *out3);
 /* Exact fixed-point sum of n doubles scaled by 2^e, returned as a double (tests). */
 double nbo_fixed_sum(const double *v, int64_t n, int e);
+/* The fixed-point integer of each beam contribution: v ws rounded to the nearest integer,
+ * ties to even (|v ws| <= 2^51). */
+void nbo_fix_round(const double *v, const double *ws, int64_t n, int64_t *out);
 
 /* Adaptive step-size control (RKMK4 steps with an embedded order-2 error estimate; see
  * nbo.c for the controller).  From step 0 to r_end; *accepted, *rejected and the step
@@ -115,6 +118,31 @@ int  nbo_single_angle_run(const nbo_params *p, double *pee_out /* [2][NE] */);
  * state_bar (NULL or [nb][3]) = dL/d(initial Bloch vectors).  The model ends at n_steps. */
 int  nbo_adjoint(nbo_model *m, int32_t ckpt, const double *dl_dpee, double *grad, double *loss,
                  double *state_bar);
+
+
+/* ---- plain mode (plain.c): the step evaluated straight from its definitions ----
+ * Density matrices as full complex matrices, dense per-beam generators and commutators,
+ * exponentials by Jacobi eigen-decomposition, plain FP64 sums, exact renormalisation;
+ * it shares no arithmetic with the functions above.  Fixed-step RKMK4 only (integrator
+ * must be 0).  Complex arrays are interleaved (re, im). */
+typedef struct plain_model plain_model;
+int  nbp_create(const nbo_params *p, plain_model **out);
+void nbp_destroy(plain_model *m);
+int64_t nbp_n_beams(const plain_model *m);
+int64_t nbp_step_index(const plain_model *m);
+int  nbp_reset(plain_model *m);
+int  nbp_step(plain_model *m, int64_t n);
+/* Re rho_ee of every beam, beam order as nbo_read_pee */
+int  nbp_read_pee(const plain_model *m, double *out);
+/* rho of every beam, [nb][n][n] complex */
+int  nbp_get_rho(const plain_model *m, double *out);
+int  nbp_set_rho(plain_model *m, const double *in, int64_t step);
+/* moments of the current state at radius r, [4][n][n] complex: J0, J1, Jsc, Jss */
+int  nbp_moments(const plain_model *m, double r, double *out);
+/* Hamiltonian of every beam at radius r for the current state's moments, [nb][n][n] */
+int  nbp_hamiltonian(const plain_model *m, double r, double *out);
+/* exp(-i K) for a Hermitian n x n K (n = 2, 3), [n][n] complex in and out */
+void nbp_expm(int n, const double *k, double *out);
 
 #ifdef __cplusplus
 }

@@ -94,6 +94,29 @@ def test_adaptive_converges_to_fine_fixed_steps(oracle, nf):
     assert errs[2] < 3e-6, errs
 
 
+@pytest.mark.parametrize("ratio,doubles", [(110.0, False), (150.0, True)])
+def test_growth_threshold_is_tol2_over_128(oracle, ratio, doubles):
+    """The step doubles after an accepted step only if its estimate E <= tol^2/128.  With
+    four steps of h and the first estimate E1 = tol^2/ratio (the estimate changes by a few
+    per cent from step to step here): at ratio 110 the step never doubles (four accepted
+    steps; a threshold of tol^2/64 would double it, giving h, 2h, h); at ratio 150 it
+    doubles after the first step (three accepted steps; tol^2/256 would not)."""
+    d = _resolved(2)
+    d.update(r_start_km=200.0, r_end_km=200.08, n_steps=4)      # h = 0.02 km
+    m = oracle.Model(d)
+    e1 = m.step_error(0.02)
+    es = []
+    for k in range(4):
+        es.append(m.step_error(0.02))
+        m.step(1)
+    assert max(es) / min(es) < 1.05                              # E nearly constant
+    assert e1 * 64 * 1.05 < e1 * ratio                          # the doubled step passes
+    tol = float(np.sqrt(e1 * ratio))
+    st = oracle.Model(d).run_adaptive(tol)
+    assert st["rejected"] == 0
+    assert st["accepted"] == (3 if doubles else 4), (st, es)
+
+
 def test_rejected_steps_are_retried_with_half_the_step(oracle):
     """A first step far too long for the tolerance is rejected and retried with h/2 until
     it passes; the tally adds up, and the step never grows above h_max."""
