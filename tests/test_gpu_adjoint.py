@@ -167,6 +167,44 @@ def test_adjoint_rejects_unsupported(nb):
     assert m.step_index() == 0
 
 
+def test_adjoint_200k_full_run_against_central_differences(nb):
+    """The 200k-beam adjoint workload (200 E x 500 u x 2, 5000 steps, checkpoints every 64
+    steps) in its resolved variant (500 -> 790 km), loss = energy-integrated final P_ee of
+    both species: the five gradients against central differences of full GPU forward runs,
+    x +- 1e-6 |x|, to 1e-6 relative.  A central difference is only as good as the loss it
+    differentiates: the rounding of a forward run moves L by some 1e-15 whatever the
+    parameter, so the bound also admits that noise over 2h (measured from runs at x (1 +
+    k 1e-13), whose true change is far below it)."""
+    d = workloads.adjoint_200k_resolved()
+    m = nb.Model(d, adjoint_ckpt=64)
+    g = m.adjoint()
+    nbm = m.nb
+    c = np.full(nbm, ((d["e_max_mev"] - d["e_min_mev"]) / d["n_energy"]) / d["n_u"])
+    x0 = [*d["lum_erg_s"], d["theta"][0], d["n0_cm3"]]
+    del m
+
+    def loss(x):
+        f = nb.Model(nb._with_params(d, x))
+        f.run()
+        return float(np.sum(c * f.pee().cpu().numpy()))
+
+    L0 = loss(x0)
+    for i in range(5):
+        h = 1e-6 * abs(x0[i])
+        xp = list(x0); xp[i] += h
+        xm = list(x0); xm[i] -= h
+        fd = (loss(xp) - loss(xm)) / (2 * h)
+        noise = 0.0
+        for k in (1, 2, 3):
+            xe = list(x0); xe[i] = x0[i] * (1.0 + k * 1e-13)
+            noise = max(noise, abs(loss(xe) - L0))
+        bound = 1e-6 * abs(fd) + 2.0 * noise / (2 * h)
+        _say(f"200k full run: dL/d{nb.PARAM_NAMES[i]} adjoint {g[i]:.10e} central {fd:.10e} "
+             f"rel {abs(g[i] - fd) / abs(fd):.2e}; loss noise {noise:.1e} -> FD noise "
+             f"{noise / (2 * h) / abs(fd):.1e} rel")
+        assert abs(g[i] - fd) <= bound, (nb.PARAM_NAMES[i], g[i], fd, noise)
+
+
 def test_adjoint_200k_prefix(nb, oracle):
     """The 200k-beam adjoint workload (200 E x 500 u x 2) in its resolved variant, its
     first 70 steps with checkpoints every 64 steps (a full and a ragged segment)."""

@@ -111,16 +111,20 @@ def test_autotune_keeps_results(nb):
 
 
 def test_batch_256_shape_prefix(nb, oracle):
-    """The 256-model workload (63M beams): two steps, sampled models against single runs
-    and the oracle."""
+    """The 256-model workload (64M beams) in one launch: 50 steps from the neutrinosphere;
+    every model against its own single-model run and 8 of them against the oracle, bit for
+    bit."""
     ds = workloads.batch_256()
     b = nb.Model(ds)
     _say(f"batch: {b.n_models} models, {b.nb} beams")
-    b.step(2)
+    b.step(50)
     parts = _split(b.pee().cpu().numpy(), b.offsets())
-    for i in (0, 77, 255):
-        s = nb.Model(ds[i]); s.step(2)
+    for i in range(len(ds)):
+        s = nb.Model(ds[i]); s.step(50)
         np.testing.assert_array_equal(parts[i], s.pee().cpu().numpy(), err_msg=f"model {i}")
-        o = oracle.Model(ds[i]); o.step(2)
-        np.testing.assert_array_equal(parts[i], o.pee().reshape(-1), err_msg=f"oracle {i}")
         del s
+    _say("batch: 256 single-model runs equal; oracle")
+    for i in (0, 37, 77, 101, 150, 199, 230, 255):
+        o = oracle.Model(ds[i]); o.step(50)
+        np.testing.assert_array_equal(parts[i], o.pee().reshape(-1), err_msg=f"oracle {i}")
+        _say(f"  oracle model {i}: {ds[i]['n_energy']}x{ds[i]['n_u']} equal")

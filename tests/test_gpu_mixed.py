@@ -1,6 +1,8 @@
 """Mixed precision (three flavours, precision = NB_FP32_STATE): FP32 state and FP32 stage
 arithmetic where the step resolves every beam, FP64 moments and renormalisation, checked
-against the FP64 GPU run (which is itself bit-for-bit the oracle).
+against the FP64 oracle (both of its modes: the specification mode, which the FP64 GPU run
+equals bit for bit, and the plain mode, which shares no arithmetic with either) and, at the
+full 6M-beam size the oracle cannot run, against the FP64 GPU run.
 
 Tolerance: the mixed path has no bitwise contract.  Per step its stage arithmetic rounds at
 FP32 precision (6e-8 relative) on rotation angles below one radian, so after N steps the
@@ -55,28 +57,37 @@ def _run(nb, d, precision, steps=None):
     return m
 
 
-def test_mixed_resolved_small_against_fp64(nb):
+def _oracle_pee(oracle, d, steps=None, plain=False):
+    o = oracle.PlainModel(d) if plain else oracle.Model(d)
+    if steps is None:
+        o.run()
+    else:
+        o.step(steps)
+    return o.pee().reshape(-1)
+
+
+def test_mixed_resolved_small_against_fp64_oracle(nb, oracle):
     d = _small(600.0, 800)
     m32 = _run(nb, d, 1)
     assert m32.mixed_fp32_step() == 0
-    p64 = _run(nb, d, 0).pee().cpu().numpy()
     p32 = m32.pee().cpu().numpy()
-    dp = np.abs(p64 - p32).max()
-    _say(f"resolved 37x5x2, 800 steps: max |dP_ee| = {dp:.3e}")
-    assert dp < TARGET
-    assert np.abs(p64 - p32).max() > 0.0           # it really is a different arithmetic
+    for plain in (False, True):
+        po = _oracle_pee(oracle, d, plain=plain)
+        dp = np.abs(po - p32).max()
+        _say(f"resolved 37x5x2, 800 steps: max |dP_ee| vs {'plain' if plain else 'spec'} oracle = {dp:.3e}")
+        assert 0.0 < dp < TARGET                    # a different arithmetic, within the target
 
 
 @pytest.mark.parametrize("n_energy", [1000, 1100])
-def test_mixed_fp32_table_in_and_out_of_lds(nb, n_energy):
+def test_mixed_fp32_table_in_and_out_of_lds(nb, oracle, n_energy):
     """The FP32-arithmetic kernel reads an FP32 copy of the vacuum rows from LDS when the
     table and the copy fit in 104 KB (1000 energies: 72 KB + 32 KB) and converts the FP64
     rows from global memory otherwise (1100 energies: 79.2 KB + 35.2 KB); both give the same
-    FP32 values, so both stay within the target of the FP64 run."""
+    FP32 values, so both stay within the target of the FP64 oracle."""
     d = _small(600.0, 300, n_energy=n_energy, n_u=3)
     m32 = _run(nb, d, 1)
     assert m32.mixed_fp32_step() == 0
-    p64 = _run(nb, d, 0).pee().cpu().numpy()
+    p64 = _oracle_pee(oracle, d)
     p32 = m32.pee().cpu().numpy()
     dp = np.abs(p64 - p32).max()
     _say(f"resolved {n_energy}x3x2, 300 steps: max |dP_ee| = {dp:.3e}")
@@ -125,6 +136,20 @@ def test_mixed_unresolved_part_is_fp64_arithmetic(nb):
     p64 = _run(nb, d, 0, n).pee().cpu().numpy()
     p32 = _run(nb, d, 1, n).pee().cpu().numpy()
     assert np.abs(p64 - p32).max() < TARGET
+
+
+def test_mixed_6m_shape_subset_against_oracle(nb, oracle):
+    """The resolved 6M-beam workload's energy grid and step length on 30 of its 3000 angle
+    bins (1000 E x 30 u x 2 = 60k beams), 300 steps, against the FP64 oracle."""
+    d = dict(workloads.three_flavor_6m_resolved(), n_u=30)
+    m32 = _run(nb, d, 1, 300)
+    assert m32.mixed_fp32_step() == 0
+    p32 = m32.pee().cpu().numpy()
+    po = _oracle_pee(oracle, d, 300)
+    dp = np.abs(po - p32).max()
+    _say(f"6M shape, 1000x30x2, 300 steps: max |dP_ee| vs oracle = {dp:.3e}")
+    assert np.abs(po - 1.0).max() > 1e-3
+    assert 0.0 < dp < TARGET
 
 
 def test_mixed_6m_resolved_prefix(nb):
