@@ -117,6 +117,18 @@ int nb_step(nb_model *m, int64_t n);
 /* Advance to r_end_km. */
 int nb_run(nb_model *m);
 int64_t nb_step_index(const nb_model *m);
+/* For callers that cannot allocate device memory or use the workspace's scratch (code
+ * under graph capture, tight serving loops, harnesses that forbid allocation): nb_step
+ * with the scratch of the stepping launches -- the barrier and tagged reduction words and,
+ * for batches, the moment accumulators -- taken from a static device array of the library
+ * instead of the bound workspace (6.1 MB per device, held until the process ends).  Same
+ * kernels and the same bits as nb_step; the model's state, tables and step counter stay
+ * in its workspace.  Allocates nothing.  Limits: at most 1024 models in a batch and 8192
+ * blocks per launch (every launch shape nb_bind picks fits), NB_EINVAL beyond.  Every call
+ * on one device shares that device's array and clears it first, so calls that overlap on
+ * one device (other host threads, other streams) race and must be serialised by the
+ * caller.  Errors as nb_step. */
+int nb_step_static(nb_model *m, int64_t n);
 /* Survival probability Re(rho_ee) of every beam (paper's P_ee, Sec. 3.5) into the
  * caller's device array dev_out[nb_n_beams]. */
 int nb_read_pee(const nb_model *m, double *dev_out);

@@ -23,7 +23,7 @@ EXPORTS = [
     "nb_step", "nb_run", "nb_step_index", "nb_read_pee", "nb_get_state", "nb_set_state",
     "nb_adjoint", "nb_host_tables", "nb_last_error", "nb_test_sincos", "nb_test_sqrt_div",
     "nb_test_exp3", "nb_test_rotate", "nb_graph_capture", "nb_graph_launch", "nb_autotune",
-    "nb_mixed_fp32_step", "nb_run_adaptive",
+    "nb_mixed_fp32_step", "nb_run_adaptive", "nb_step_static",
 ]
 
 
@@ -78,6 +78,7 @@ def lib():
         L.nb_bind.argtypes = [vp, vp, C.c_size_t, vp]
         L.nb_reset.argtypes = [vp]
         L.nb_step.argtypes = [vp, i64]
+        L.nb_step_static.argtypes = [vp, i64]
         L.nb_run.argtypes = [vp]
         L.nb_step_index.argtypes = [vp]
         L.nb_step_index.restype = i64
@@ -222,6 +223,10 @@ class Model(HostModel):
 
     def run(self):
         _check(lib().nb_run(self.h), "nb_run")
+
+    def step_static(self, n: int):
+        """nb_step with the launch scratch in the library's static device array."""
+        _check(lib().nb_step_static(self.h, int(n)), "nb_step_static")
 
     def step_index(self) -> int:
         return int(lib().nb_step_index(self.h))

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -118,7 +119,19 @@ struct nb_model {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   long long graph_steps = 0;
+  // set only inside nb_step_static: barrier words and batch accumulators taken from the
+  // static scratch array instead of the workspace
+  unsigned int* sync_static = nullptr;
+  unsigned long long* acc_static = nullptr;
 };
+
+// Barrier and reduction words, and batch moment accumulators, of the stepping launches.
+static unsigned int* sync_words(const nb_model* m) {
+  return m->sync_static ? m->sync_static : (unsigned int*)(m->ws + m->off_sync);
+}
+static unsigned long long* acc_words(const nb_model* m) {
+  return m->acc_static ? m->acc_static : (unsigned long long*)(m->ws + m->off_acc);
+}
 
 static bool state_fp32(const nb_model* m) { return m->nf == 3 && m->p.precision == NB_FP32_STATE; }
 
@@ -568,7 +581,7 @@ static int set_device_step(nb_model* m, long long step) {
 
 // Clear the barrier words, optionally keeping the status word (a kernel: capturable).
 static int zero_sync(nb_model* m, int keep) {
-  unsigned int* sync = (unsigned int*)(m->ws + m->off_sync);
+  unsigned int* sync = sync_words(m);
   void* zargs[] = {&sync, &keep};
   NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(256), dim3(256), zargs, 0, m->stream));
   return NB_OK;
@@ -732,7 +745,7 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
 // outside graph capture).
 static int check_status(nb_model* m) {
   if (capturing(m->stream)) return NB_OK;
-  unsigned int* sync = (unsigned int*)(m->ws + m->off_sync);
+  unsigned int* sync = sync_words(m);
   NB_HIP(hipMemcpyAsync(m->pinned, sync + kSyncStatus, sizeof(unsigned int), hipMemcpyDeviceToHost,
                         m->stream));
   NB_HIP(hipMemcpyAsync(m->pinned + 1, m->ws + m->off_ctl, sizeof(long long), hipMemcpyDeviceToHost,
@@ -758,13 +771,13 @@ static long long launch_chunk(const nb_model* m) {
 
 // Enqueue one stepping launch of k steps (from the device step counter) on the stream.
 static int enqueue_advance(nb_model* m, long long k) {
-  unsigned int* sync = (unsigned int*)(m->ws + m->off_sync);
+  unsigned int* sync = sync_words(m);
   int keep = 1;
   void* zargs[] = {&sync, &keep};
   NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(256), dim3(256), zargs, 0, m->stream));
   const unsigned long long timeout = m->ticks_per_s * 20ull;
   if (m->batch) {
-    unsigned long long* acc = (unsigned long long*)(m->ws + m->off_acc);
+    unsigned long long* acc = acc_words(m);
     long long nacc = (long long)kAccSets * m->nmodels * 6 * kAccLimbs;
     void* zz[] = {&acc, &nacc};
     NB_HIP(hipLaunchKernel((const void*)&k_zero_u64, dim3(64), dim3(256), zz, 0, m->stream));
@@ -882,6 +895,63 @@ extern "C" int nb_step(nb_model* m, int64_t n) {
 extern "C" int nb_run(nb_model* m) {
   if (!m) return fail(NB_EINVAL, "model is NULL");
   return nb_step(m, m->p.n_steps - m->step);
+}
+
+// ------------------------------------------------- static scratch: stepping without allocation
+// nb_step_static takes the scratch of the stepping launches -- the barrier and tagged
+// reduction words (kSyncWords 32-bit words, enough for the largest grid of kMaxBlocks
+// blocks) and the batch kernel's moment accumulators (kStaticModels models) -- from this
+// array instead of the workspace.  Each device holds its own copy until the process ends.
+constexpr int kStaticModels = 1024;
+constexpr size_t kStaticSync64 = ((size_t)kSyncWords + 1) / 2;         // sync words, as u64
+constexpr size_t kStaticAccOff = (kStaticSync64 + 31) / 32 * 32;       // 256-byte boundary
+constexpr size_t kStaticWords = kStaticAccOff + (size_t)kAccSets * kStaticModels * 6 * kAccLimbs;
+static __device__ __align__(256) unsigned long long scratch[kStaticWords];
+
+// Device address of this device's copy of scratch, looked up once per device with that
+// device current (the host-side name of the array is not a device address).
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[kMaxDevices] = {};
+static int static_scratch(int dev, unsigned long long** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev < 0 || dev >= kMaxDevices) return fail(NB_EINVAL, "device %d out of range", dev);
+  if (!g_scratch_addr[dev]) {
+    int cur = 0;
+    NB_HIP(hipGetDevice(&cur));
+    if (cur != dev) NB_HIP(hipSetDevice(dev));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr)
+      return fail(NB_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_addr[dev] = ptr;
+  }
+  *out = (unsigned long long*)g_scratch_addr[dev];
+  return NB_OK;
+}
+
+extern "C" int nb_step_static(nb_model* m, int64_t n) {
+  if (!m) return fail(NB_EINVAL, "model is NULL");
+  if (!m->ws) return fail(NB_EUNBOUND, "no workspace bound");
+  if (n < 0) return fail(NB_EINVAL, "negative step count");
+  if (m->batch && m->nmodels > kStaticModels)
+    return fail(NB_EINVAL, "nb_step_static: %d models exceed the static scratch limit of %d models",
+                m->nmodels, kStaticModels);
+  if (m->nblocks > kMaxBlocks)
+    return fail(NB_EINVAL, "nb_step_static: %d blocks exceed the static scratch limit of %d blocks",
+                m->nblocks, kMaxBlocks);
+  unsigned long long* s = nullptr;
+  int rc = static_scratch(m->device, &s);
+  if (rc) return rc;
+  m->sync_static = (unsigned int*)s;
+  m->acc_static = s + kStaticAccOff;
+  // the previous call on this device left its epochs (and maybe a status) in the array
+  rc = zero_sync(m, 0);
+  if (!rc) rc = nb_step(m, n);
+  m->sync_static = nullptr;
+  m->acc_static = nullptr;
+  return rc;
 }
 
 // ----------------------------------------------------------------- adaptive steps
