@@ -20,11 +20,15 @@ per row and omitted here):
   ->  508 flops.
 Algorithmic HBM bytes per beam-step: the state is read at stages 2, 3, 4 and the final
 pass and written once: 5 x (state reals) x (bytes per real): 3f FP64 psi 240 B, 3f FP32
-psi 120 B, 2f Bloch vector 120 B.
+psi 120 B, 2f Bloch vector 120 B.  The same five passes over a full density matrix (n^2
+reals per beam) would move 360 B for 3f FP64; the line reports that accounting beside
+the one of the stored state.  A device-to-device copy of 1 GiB, timed the same way, gives
+the bandwidth a streaming kernel can reach on the box: the second ceiling.
 """
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -91,6 +95,30 @@ def traffic_from_profile(name: str, launch_steps: int, nb: int):
         return None
     per_beam_step = t["hbm_bytes_per_beam_step"]
     return per_beam_step * launch_steps * nb
+
+
+def copy_probe_gbs(reps: int = 5) -> float:
+    """Bandwidth of a 1 GiB device-to-device copy (read + write bytes over the median
+    HIP-event time of `reps` copies): the streaming ceiling measured on this device."""
+    import torch
+    n = 1 << 27                          # 2^27 doubles = 1 GiB each way
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    del src, dst
+    torch.cuda.empty_cache()
+    ts.sort()
+    return 2.0 * 8.0 * n / ts[len(ts) // 2] / 1e9
 
 
 def adjoint_timing(nb, workloads):
@@ -328,8 +356,6 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint and mixed-precision measurements")
     ap.add_argument("--mixed-literal-steps", type=int, default=2000)
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also run one 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this stepper runs on one GPU only (no multi-GPU path is built); "
@@ -371,6 +397,15 @@ def main():
                                peak=PEAK_FP64_VALU_TFLOPS, unit="TFLOP/s", frac=round(f_alu, 4)))
     roof["kernel"] = "nb::k_advance<3, double>"
     roof["launch_ms"] = round(ev * 1e3, 3)
+    roof["bytes_per_beam_step"] = bytes_per_beam_step(3, False)
+    # the same passes over full density matrices (9 reals per beam): 360 B per beam-step
+    rho_gbs = 5.0 * 9 * 8.0 * beam_steps / ev / 1e9
+    roof["rho_accounting"] = dict(bytes_per_beam_step=360.0, achieved=round(rho_gbs, 1),
+                                  frac=round(rho_gbs / PEAK_HBM_GBS, 4))
+    if traffic:
+        meas = traffic / ev / 1e9
+        roof["measured_hbm"] = dict(achieved=round(meas, 1), frac=round(meas / PEAK_HBM_GBS, 4),
+                                    bytes_per_beam_step=round(traffic / beam_steps, 1))
     out = {
         "metric": METRIC, "value": value, "unit": "beam-steps/s", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -384,7 +419,12 @@ def main():
         "roofline": roof,
     }
     del m
+    gc.collect()
     torch.cuda.empty_cache()
+    log("copy probe (1 GiB device copy) ...")
+    cp = copy_probe_gbs()
+    roof["copy_probe"] = dict(achieved_gbs=round(cp, 1), frac_of_peak=round(cp / PEAK_HBM_GBS, 4),
+                              kernel_frac_of_copy=round(gbs / cp, 4))
     if not args.no_extras:
         log("adjoint timing (200k beams) ...")
         adj = adjoint_timing(nb, workloads)
@@ -403,18 +443,15 @@ def main():
         out["extended"] = extended_timing(nb, workloads)
         log("every flavour tracked (2.4M beams) ...")
         out["track_all"] = track_all_timing(nb, workloads)
-    if args.copy_probe:
-        n = 1 << 27                      # 2^27 doubles = 1 GiB each way
-        src = torch.ones(n, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copy probe: 1 GiB read + 1 GiB written")
-        del src, dst
-        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds)
+    # release every model (its pinned host word, graphs, workspace) and torch's cached
+    # device memory while the runtime and any attached profiler are still up, rather than
+    # from finalisers during interpreter shutdown
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 
