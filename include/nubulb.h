@@ -121,9 +121,9 @@ int64_t nb_step_index(const nb_model *m);
  * under graph capture, tight serving loops, harnesses that forbid allocation): nb_step
  * with the scratch of the stepping launches -- the barrier and tagged reduction words and,
  * for batches, the moment accumulators -- taken from a static device array of the library
- * instead of the bound workspace (6.1 MB per device, held until the process ends).  Same
+ * instead of the bound workspace (3.3 MB per device, held until the process ends).  Same
  * kernels and the same bits as nb_step; the model's state, tables and step counter stay
- * in its workspace.  Allocates nothing.  Limits: at most 1024 models in a batch and 8192
+ * in its workspace.  Allocates nothing.  Limits: at most 1024 models in a batch and 2048
  * blocks per launch (every launch shape nb_bind picks fits), NB_EINVAL beyond.  Every call
  * on one device shares that device's array and clears it first, so calls that overlap on
  * one device (other host threads, other streams) race and must be serialised by the

@@ -276,40 +276,256 @@ __device__ __forceinline__ void stage_f(const AdjArgs& a, const AdjBeam& q, cons
   gen2(q.s, a.tab[q.k], a.tab[a.NE + q.k], g.lam, nn, hc, f);
 }
 
+// Beam b's fixed labels, its adjoint initialised from the cotangent (L = sum_b c_b Pee_b,
+// Pee = (1 + P_z)/2).
+__device__ __forceinline__ void beam_init(const AdjArgs& a, long long b, bool on, AdjBeam& q) {
+  q.on = on;
+  const long long bb = on ? b : 0;
+  const long long row = bb / a.NE;
+  q.k = (int)(bb - row * a.NE);
+  q.s = (int)(row / a.NU);
+  q.u = u_of((int)(row - (long long)q.s * a.NU), a.NU);
+  const double cb = on ? (a.cot ? a.cot[b] : a.cot_const) : 0.0;
+  q.Pb[0] = 0.0;
+  q.Pb[1] = 0.0;
+  q.Pb[2] = 0.5 * cb;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    q.F1[c] = 0.0;
+    q.Tb[c] = 0.0;
+    q.P[c] = 0.0;
+  }
+  q.c0 = q.cm = q.c1 = 1.0;
+  q.hc0 = q.hcm = q.hc1 = 0.0;
+}
+
+// Recompute beam b's states over a segment of len steps from its checkpoint with the
+// recorded moments (the stepping kernel's arithmetic, hence its bits) into the tape.
+__device__ __forceinline__ void recompute_segment(const AdjArgs& a, const AdjBeam& q, long long b, long long seg,
+                                                  long long s0, long long len) {
+  const long long plane = a.plane;
+  const double* ck = a.ck + (size_t)seg * 3 * plane;
+  double P0 = ck[b], P1 = ck[b + plane], P2 = ck[b + 2 * plane];
+  for (long long t = 0; t < len; ++t) {
+    double* tp = a.tape + (size_t)t * 3 * plane;
+    tp[b] = P0;
+    tp[b + plane] = P1;
+    tp[b + 2 * plane] = P2;
+    if (t + 1 == len) break;
+    const long long n = s0 + t;
+    const double r0 = a.rs + (double)n * a.h;
+    const double rm = r0 + 0.5 * a.h;
+    const double r1 = a.rs + (double)(n + 1) * a.h;
+    const Radial g0 = radial(a.R, a.ne_power, a.lam0, r0), gm = radial(a.R, a.ne_power, a.lam0, rm),
+                 g1 = radial(a.R, a.ne_power, a.lam0, r1);
+    const RowGeo rg = row_geo(q.u, a.h, g0, gm, g1);
+    const double* J = a.Jhist + (size_t)n * 24;
+    double n1[3], n2[3], n3[3], n4[3], f1[3], f2[3], f3[3], f4[3];
+    nunu<3>(J, g0.mu, rg.c0, n1);
+    nunu<3>(J + 6, gm.mu, rg.cm, n2);
+    nunu<3>(J + 12, gm.mu, rg.cm, n3);
+    nunu<3>(J + 18, g1.mu, rg.c1, n4);
+    const double bx = a.tab[q.k], bz = a.tab[a.NE + q.k];
+    gen2(q.s, bx, bz, g0.lam, n1, rg.hc0, f1);
+    gen2(q.s, bx, bz, gm.lam, n2, rg.hcm, f2);
+    gen2(q.s, bx, bz, gm.lam, n3, rg.hcm, f3);
+    gen2(q.s, bx, bz, g1.lam, n4, rg.hc1, f4);
+    const double cr0 = f1[1] * f4[2] - f1[2] * f4[1];
+    const double cr1 = f1[2] * f4[0] - f1[0] * f4[2];
+    const double cr2 = f1[0] * f4[1] - f1[1] * f4[0];
+    const double t0 = (((f1[0] + 2.0 * f2[0]) + 2.0 * f3[0]) + f4[0]) * (1.0 / 6.0) - cr0 * (1.0 / 12.0);
+    const double t1 = (((f1[1] + 2.0 * f2[1]) + 2.0 * f3[1]) + f4[1]) * (1.0 / 6.0) - cr1 * (1.0 / 12.0);
+    const double t2 = (((f1[2] + 2.0 * f2[2]) + 2.0 * f3[2]) + f4[2]) * (1.0 / 6.0) - cr2 * (1.0 / 12.0);
+    rotate2(t0, t1, t2, P0, P1, P2);
+    if (a.renorm) {   // as the forward stepper: one Newton step for 1/sqrt from 1
+      const double nrm2 = (P0 * P0 + P1 * P1) + P2 * P2;
+      const double inv = fma(-0.5, nrm2, 1.5);
+      P0 = P0 * inv;
+      P1 = P1 * inv;
+      P2 = P2 * inv;
+    }
+  }
+}
+
+// The state at the start of the step being reversed (tape slot t) and the beam's geometry
+// at the step's three stage radii.
+__device__ __forceinline__ void load_step(const AdjArgs& a, AdjBeam& B, long long b, long long t,
+                                          const Radial& g0, const Radial& gm, const Radial& g1) {
+  const double* tp = a.tape + (size_t)t * 3 * a.plane;
+  B.P[0] = tp[b];
+  B.P[1] = tp[b + a.plane];
+  B.P[2] = tp[b + 2 * a.plane];
+  const RowGeo rg = row_geo(B.u, a.h, g0, gm, g1);
+  B.c0 = rg.c0; B.cm = rg.cm; B.c1 = rg.c1;
+  B.hc0 = rg.hc0; B.hcm = rg.hcm; B.hc1 = rg.hc1;
+}
+
+// A: P_{n+1} = R(Theta) P_n / |.|  ->  Theta-bar, f4-bar
+__device__ __forceinline__ void phase_a(const AdjArgs& a, AdjBeam& B, const double (*sJ)[6], const Radial& g0,
+                                        const Radial& gm, const Radial& g1, double (&red)[6], double (&gacc)[5]) {
+  double f1[3], f2[3], f3[3], f4[3], cr[3];
+  stage_f(a, B, sJ[0], g0, B.c0, B.hc0, f1);
+  stage_f(a, B, sJ[1], gm, B.cm, B.hcm, f2);
+  stage_f(a, B, sJ[2], gm, B.cm, B.hcm, f3);
+  stage_f(a, B, sJ[3], g1, B.c1, B.hc1, f4);
+  cross(f1, f4, cr);
+  double th[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    th[c] = (((f1[c] + 2.0 * f2[c]) + 2.0 * f3[c]) + f4[c]) * (1.0 / 6.0) - cr[c] * (1.0 / 12.0);
+  const Rot R = make_rot(th[0], th[1], th[2]);
+  double Pp[3];
+  rot_fwd(R, B.P[0], B.P[1], B.P[2], Pp[0], Pp[1], Pp[2]);
+  double Ppb[3] = {B.Pb[0], B.Pb[1], B.Pb[2]};
+  if (a.renorm) {
+    // y = P (1.5 - |P|^2 / 2): P-bar = (1.5 - |P|^2 / 2) y-bar - P (P . y-bar)
+    const double sf = fma(-0.5, (Pp[0] * Pp[0] + Pp[1] * Pp[1]) + Pp[2] * Pp[2], 1.5);
+    const double d = (Pp[0] * Ppb[0] + Pp[1] * Ppb[1]) + Pp[2] * Ppb[2];
+    Ppb[0] = sf * Ppb[0] - Pp[0] * d;
+    Ppb[1] = sf * Ppb[1] - Pp[1] * d;
+    Ppb[2] = sf * Ppb[2] - Pp[2] * d;
+  }
+  B.Pb[0] = B.Pb[1] = B.Pb[2] = 0.0;
+  rot_inv_add(R, Ppb[0], Ppb[1], Ppb[2], B.Pb);
+  double om[3], tb[3], c4[3], c1v[3], f4b[3];
+  cross(Pp, Ppb, om);
+  jl_t(R, om, tb);
+  cross(f4, tb, c4);
+  cross(tb, f1, c1v);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    B.F1[c] = tb[c] / 6.0 - c4[c] / 12.0;
+    f4b[c] = tb[c] / 6.0 - c1v[c] / 12.0;
+    B.Tb[c] = tb[c];
+  }
+  const double Bb[3] = {B.hc1 * f4b[0], B.hc1 * f4b[1], B.hc1 * f4b[2]};
+  b_bar(a, B, Bb, B.c1, g1, red, gacc);
+}
+// B: Y4 = R(f3) P  ->  f3-bar
+__device__ __forceinline__ void phase_b(const AdjArgs& a, AdjBeam& B, const double (*sJ)[6], const double* Jb,
+                                        const Radial& gm, double (&red)[6], double (&gacc)[5]) {
+  double f3[3], Y[3], Yb[3], om[3], f3b[3];
+  stage_f(a, B, sJ[2], gm, B.cm, B.hcm, f3);
+  const Rot R = make_rot(f3[0], f3[1], f3[2]);
+  rot_fwd(R, B.P[0], B.P[1], B.P[2], Y[0], Y[1], Y[2]);
+  m_bar(a, B, Jb, B.c1, Y, Yb, gacc);
+  rot_inv_add(R, Yb[0], Yb[1], Yb[2], B.Pb);
+  cross(Y, Yb, om);
+  jl_t(R, om, f3b);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) f3b[c] += B.Tb[c] / 3.0;
+  const double Bb[3] = {B.hcm * f3b[0], B.hcm * f3b[1], B.hcm * f3b[2]};
+  b_bar(a, B, Bb, B.cm, gm, red, gacc);
+}
+// C: Y3 = R(Om) P, Om = f2/2 - (f1 x f2)/8  ->  f2-bar, f1-bar
+__device__ __forceinline__ void phase_c(const AdjArgs& a, AdjBeam& B, const double (*sJ)[6], const double* Jb,
+                                        const Radial& g0, const Radial& gm, double (&red)[6], double (&gacc)[5]) {
+  double f1[3], f2[3], cr[3], Y[3], Yb[3], om[3], ob[3], a1[3], a2[3], f2b[3];
+  stage_f(a, B, sJ[0], g0, B.c0, B.hc0, f1);
+  stage_f(a, B, sJ[1], gm, B.cm, B.hcm, f2);
+  cross(f1, f2, cr);
+  const Rot R = make_rot(0.5 * f2[0] - 0.125 * cr[0], 0.5 * f2[1] - 0.125 * cr[1],
+                         0.5 * f2[2] - 0.125 * cr[2]);
+  rot_fwd(R, B.P[0], B.P[1], B.P[2], Y[0], Y[1], Y[2]);
+  m_bar(a, B, Jb, B.cm, Y, Yb, gacc);
+  rot_inv_add(R, Yb[0], Yb[1], Yb[2], B.Pb);
+  cross(Y, Yb, om);
+  jl_t(R, om, ob);
+  cross(ob, f1, a1);
+  cross(f2, ob, a2);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    f2b[c] = (0.5 * ob[c] - a1[c] / 8.0) + B.Tb[c] / 3.0;
+    B.F1[c] -= a2[c] / 8.0;
+  }
+  const double Bb[3] = {B.hcm * f2b[0], B.hcm * f2b[1], B.hcm * f2b[2]};
+  b_bar(a, B, Bb, B.cm, gm, red, gacc);
+}
+// D: Y2 = R(f1/2) P  ->  f1-bar complete
+__device__ __forceinline__ void phase_d(const AdjArgs& a, AdjBeam& B, const double (*sJ)[6], const double* Jb,
+                                        const Radial& g0, double (&red)[6], double (&gacc)[5]) {
+  double f1[3], Y[3], Yb[3], om[3], ob[3];
+  stage_f(a, B, sJ[0], g0, B.c0, B.hc0, f1);
+  const Rot R = make_rot(0.5 * f1[0], 0.5 * f1[1], 0.5 * f1[2]);
+  rot_fwd(R, B.P[0], B.P[1], B.P[2], Y[0], Y[1], Y[2]);
+  m_bar(a, B, Jb, B.cm, Y, Yb, gacc);
+  rot_inv_add(R, Yb[0], Yb[1], Yb[2], B.Pb);
+  cross(Y, Yb, om);
+  jl_t(R, om, ob);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) B.F1[c] += 0.5 * ob[c];
+  const double Bb[3] = {B.hc0 * B.F1[0], B.hc0 * B.F1[1], B.hc0 * B.F1[2]};
+  b_bar(a, B, Bb, B.c0, g0, red, gacc);
+}
+// J^(1) = M(P_n): the moment adjoint broadcast onto the state itself
+__device__ __forceinline__ void phase_e(const AdjArgs& a, AdjBeam& B, const double* Jb, double (&gacc)[5]) {
+  double Yb[3];
+  m_bar(a, B, Jb, B.c0, B.P, Yb, gacc);
+  B.Pb[0] += Yb[0];
+  B.Pb[1] += Yb[1];
+  B.Pb[2] += Yb[2];
+}
+
+// Adjoint registers of beam b kept in the workspace between phases (spill mode): P-bar,
+// f1-bar, Theta-bar as nine planes of a.plane doubles.
+__device__ __forceinline__ void adj_load(const AdjArgs& a, AdjBeam& B, long long b) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    B.Pb[c] = a.spill[(size_t)c * a.plane + b];
+    B.F1[c] = a.spill[(size_t)(3 + c) * a.plane + b];
+    B.Tb[c] = a.spill[(size_t)(6 + c) * a.plane + b];
+  }
+}
+__device__ __forceinline__ void adj_store(const AdjArgs& a, const AdjBeam& B, long long b) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    a.spill[(size_t)c * a.plane + b] = B.Pb[c];
+    a.spill[(size_t)(3 + c) * a.plane + b] = B.F1[c];
+    a.spill[(size_t)(6 + c) * a.plane + b] = B.Tb[c];
+  }
+}
+
+// BPT > 0: thread gt owns beams gt + i nthr (i < BPT) and keeps their adjoint registers for
+// the whole launch.  BPT = 0 (spill mode, any number of beams): each phase loops over the
+// thread's beams gt, gt + nthr, ..., reading and writing their adjoint registers in the
+// workspace and recomputing the state and geometry from the tape.
 template <int BPT>
 __global__ void __launch_bounds__(kBlock) k_adjoint2(AdjArgs a) {
   __shared__ double sJ[4][6];
   __shared__ double sRes[8];
   __shared__ double sw[kBlock / 64][8];
   __shared__ double sred[kBlock];
+  constexpr int NQ = BPT > 0 ? BPT : 1;
   const int tid = threadIdx.x;
   const long long nthr = (long long)gridDim.x * kBlock;
   const long long gt = (long long)blockIdx.x * kBlock + tid;
-  const long long plane = a.plane;
-  AdjBeam q[BPT];
+  AdjBeam q[NQ];
+  if constexpr (BPT > 0) {
 #pragma unroll
-  for (int i = 0; i < BPT; ++i) {
-    const long long b = gt + i * nthr;
-    q[i].on = b < a.nb;
-    const long long bb = q[i].on ? b : 0;
-    const long long row = bb / a.NE;
-    q[i].k = (int)(bb - row * a.NE);
-    q[i].s = (int)(row / a.NU);
-    q[i].u = u_of((int)(row - (long long)q[i].s * a.NU), a.NU);
-    const double cb = q[i].on ? (a.cot ? a.cot[b] : a.cot_const) : 0.0;
-    // L = sum_b c_b Pee_b, Pee = (1 + P_z)/2
-    q[i].Pb[0] = 0.0;
-    q[i].Pb[1] = 0.0;
-    q[i].Pb[2] = 0.5 * cb;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      q[i].F1[c] = 0.0;
-      q[i].Tb[c] = 0.0;
-      q[i].P[c] = 0.0;
+    for (int i = 0; i < BPT; ++i) beam_init(a, gt + i * nthr, gt + i * nthr < a.nb, q[i]);
+  } else {
+    for (long long b = gt; b < a.nb; b += nthr) {
+      beam_init(a, b, true, q[0]);
+      adj_store(a, q[0], b);
     }
-    q[i].c0 = q[i].cm = q[i].c1 = 1.0;
-    q[i].hc0 = q[i].hcm = q[i].hc1 = 0.0;
   }
+  // every beam of this thread (register mode: its BPT slots; spill mode: all of them, each
+  // loaded and stored around fn)
+  auto each = [&](auto fn, bool with_state, long long t, const Radial& g0, const Radial& gm, const Radial& g1) {
+    if constexpr (BPT > 0) {
+#pragma unroll
+      for (int i = 0; i < BPT; ++i)
+        if (q[i].on) fn(q[i], gt + i * nthr);
+    } else {
+      for (long long b = gt; b < a.nb; b += nthr) {
+        beam_init(a, b, true, q[0]);
+        adj_load(a, q[0], b);
+        if (with_state) load_step(a, q[0], b, t, g0, gm, g1);
+        fn(q[0], b);
+        adj_store(a, q[0], b);
+      }
+    }
+  };
   double gacc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   unsigned epoch = 0;
   bool ok = true;
@@ -317,50 +533,14 @@ __global__ void __launch_bounds__(kBlock) k_adjoint2(AdjArgs a) {
     const long long s0 = a.n0 + seg * a.ckpt;
     const long long len = min(a.ckpt, a.n0 + a.nsteps - s0);
     // -- recompute the segment's states from its checkpoint with the recorded moments
+    if constexpr (BPT > 0) {
 #pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-      if (!q[i].on) continue;
-      const long long b = gt + i * nthr;
-      const double* ck = a.ck + (size_t)seg * 3 * plane;
-      double P0 = ck[b], P1 = ck[b + plane], P2 = ck[b + 2 * plane];
-      for (long long t = 0; t < len; ++t) {
-        double* tp = a.tape + (size_t)t * 3 * plane;
-        tp[b] = P0;
-        tp[b + plane] = P1;
-        tp[b + 2 * plane] = P2;
-        if (t + 1 == len) break;
-        const long long n = s0 + t;
-        const double r0 = a.rs + (double)n * a.h;
-        const double rm = r0 + 0.5 * a.h;
-        const double r1 = a.rs + (double)(n + 1) * a.h;
-        const Radial g0 = radial(a.R, a.ne_power, a.lam0, r0), gm = radial(a.R, a.ne_power, a.lam0, rm),
-                     g1 = radial(a.R, a.ne_power, a.lam0, r1);
-        const RowGeo rg = row_geo(q[i].u, a.h, g0, gm, g1);
-        const double* J = a.Jhist + (size_t)n * 24;
-        double n1[3], n2[3], n3[3], n4[3], f1[3], f2[3], f3[3], f4[3];
-        nunu<3>(J, g0.mu, rg.c0, n1);
-        nunu<3>(J + 6, gm.mu, rg.cm, n2);
-        nunu<3>(J + 12, gm.mu, rg.cm, n3);
-        nunu<3>(J + 18, g1.mu, rg.c1, n4);
-        const double bx = a.tab[q[i].k], bz = a.tab[a.NE + q[i].k];
-        gen2(q[i].s, bx, bz, g0.lam, n1, rg.hc0, f1);
-        gen2(q[i].s, bx, bz, gm.lam, n2, rg.hcm, f2);
-        gen2(q[i].s, bx, bz, gm.lam, n3, rg.hcm, f3);
-        gen2(q[i].s, bx, bz, g1.lam, n4, rg.hc1, f4);
-        const double cr0 = f1[1] * f4[2] - f1[2] * f4[1];
-        const double cr1 = f1[2] * f4[0] - f1[0] * f4[2];
-        const double cr2 = f1[0] * f4[1] - f1[1] * f4[0];
-        const double t0 = (((f1[0] + 2.0 * f2[0]) + 2.0 * f3[0]) + f4[0]) * (1.0 / 6.0) - cr0 * (1.0 / 12.0);
-        const double t1 = (((f1[1] + 2.0 * f2[1]) + 2.0 * f3[1]) + f4[1]) * (1.0 / 6.0) - cr1 * (1.0 / 12.0);
-        const double t2 = (((f1[2] + 2.0 * f2[2]) + 2.0 * f3[2]) + f4[2]) * (1.0 / 6.0) - cr2 * (1.0 / 12.0);
-        rotate2(t0, t1, t2, P0, P1, P2);
-        if (a.renorm) {   // as the forward stepper: one Newton step for 1/sqrt from 1
-          const double nrm2 = (P0 * P0 + P1 * P1) + P2 * P2;
-          const double inv = fma(-0.5, nrm2, 1.5);
-          P0 = P0 * inv;
-          P1 = P1 * inv;
-          P2 = P2 * inv;
-        }
+      for (int i = 0; i < BPT; ++i)
+        if (q[i].on) recompute_segment(a, q[i], gt + i * nthr, seg, s0, len);
+    } else {
+      for (long long b = gt; b < a.nb; b += nthr) {
+        beam_init(a, b, true, q[0]);
+        recompute_segment(a, q[0], b, seg, s0, len);
       }
     }
     // -- reverse steps of the segment
@@ -375,178 +555,69 @@ __global__ void __launch_bounds__(kBlock) k_adjoint2(AdjArgs a) {
       __syncthreads();
       double red[6];
       double Jb[6];
-      // A: P_{n+1} = R(Theta) P_n / |.|  ->  Theta-bar, f4-bar
 #pragma unroll
       for (int c = 0; c < 6; ++c) red[c] = 0.0;
-#pragma unroll
-      for (int i = 0; i < BPT; ++i) {
-        AdjBeam& B = q[i];
-        if (!B.on) continue;
-        const long long b = gt + i * nthr;
-        const double* tp = a.tape + (size_t)t * 3 * plane;
-        B.P[0] = tp[b];
-        B.P[1] = tp[b + plane];
-        B.P[2] = tp[b + 2 * plane];
-        const RowGeo rg = row_geo(B.u, a.h, g0, gm, g1);
-        B.c0 = rg.c0; B.cm = rg.cm; B.c1 = rg.c1;
-        B.hc0 = rg.hc0; B.hcm = rg.hcm; B.hc1 = rg.hc1;
-        double f1[3], f2[3], f3[3], f4[3], cr[3];
-        stage_f(a, B, sJ[0], g0, B.c0, B.hc0, f1);
-        stage_f(a, B, sJ[1], gm, B.cm, B.hcm, f2);
-        stage_f(a, B, sJ[2], gm, B.cm, B.hcm, f3);
-        stage_f(a, B, sJ[3], g1, B.c1, B.hc1, f4);
-        cross(f1, f4, cr);
-        double th[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-          th[c] = (((f1[c] + 2.0 * f2[c]) + 2.0 * f3[c]) + f4[c]) * (1.0 / 6.0) - cr[c] * (1.0 / 12.0);
-        const Rot R = make_rot(th[0], th[1], th[2]);
-        double Pp[3];
-        rot_fwd(R, B.P[0], B.P[1], B.P[2], Pp[0], Pp[1], Pp[2]);
-        double Ppb[3] = {B.Pb[0], B.Pb[1], B.Pb[2]};
-        if (a.renorm) {
-          // y = P (1.5 - |P|^2 / 2): P-bar = (1.5 - |P|^2 / 2) y-bar - P (P . y-bar)
-          const double sf = fma(-0.5, (Pp[0] * Pp[0] + Pp[1] * Pp[1]) + Pp[2] * Pp[2], 1.5);
-          const double d = (Pp[0] * Ppb[0] + Pp[1] * Ppb[1]) + Pp[2] * Ppb[2];
-          Ppb[0] = sf * Ppb[0] - Pp[0] * d;
-          Ppb[1] = sf * Ppb[1] - Pp[1] * d;
-          Ppb[2] = sf * Ppb[2] - Pp[2] * d;
-        }
-        B.Pb[0] = B.Pb[1] = B.Pb[2] = 0.0;
-        rot_inv_add(R, Ppb[0], Ppb[1], Ppb[2], B.Pb);
-        double om[3], tb[3], c4[3], c1v[3], f4b[3];
-        cross(Pp, Ppb, om);
-        jl_t(R, om, tb);
-        cross(f4, tb, c4);
-        cross(tb, f1, c1v);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          B.F1[c] = tb[c] / 6.0 - c4[c] / 12.0;
-          f4b[c] = tb[c] / 6.0 - c1v[c] / 12.0;
-          B.Tb[c] = tb[c];
-        }
-        const double Bb[3] = {B.hc1 * f4b[0], B.hc1 * f4b[1], B.hc1 * f4b[2]};
-        b_bar(a, B, Bb, B.c1, g1, red, gacc);
-      }
+      each([&](AdjBeam& B, long long b) {
+        if constexpr (BPT > 0) load_step(a, B, b, t, g0, gm, g1);
+        phase_a(a, B, sJ, g0, gm, g1, red, gacc);
+      }, true, t, g0, gm, g1);
       if (!(ok = grid_sum<6>(a, epoch++, red, sRes, sw, sred))) break;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         Jb[c] = g1.mu * sRes[c];
         Jb[3 + c] = -(g1.mu * sRes[3 + c]);
       }
-      // B: Y4 = R(f3) P  ->  f3-bar
 #pragma unroll
       for (int c = 0; c < 6; ++c) red[c] = 0.0;
-#pragma unroll
-      for (int i = 0; i < BPT; ++i) {
-        AdjBeam& B = q[i];
-        if (!B.on) continue;
-        double f3[3], Y[3], Yb[3], om[3], f3b[3];
-        stage_f(a, B, sJ[2], gm, B.cm, B.hcm, f3);
-        const Rot R = make_rot(f3[0], f3[1], f3[2]);
-        rot_fwd(R, B.P[0], B.P[1], B.P[2], Y[0], Y[1], Y[2]);
-        m_bar(a, B, Jb, B.c1, Y, Yb, gacc);
-        rot_inv_add(R, Yb[0], Yb[1], Yb[2], B.Pb);
-        cross(Y, Yb, om);
-        jl_t(R, om, f3b);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) f3b[c] += B.Tb[c] / 3.0;
-        const double Bb[3] = {B.hcm * f3b[0], B.hcm * f3b[1], B.hcm * f3b[2]};
-        b_bar(a, B, Bb, B.cm, gm, red, gacc);
-      }
+      each([&](AdjBeam& B, long long) { phase_b(a, B, sJ, Jb, gm, red, gacc); }, true, t, g0, gm, g1);
       if (!(ok = grid_sum<6>(a, epoch++, red, sRes, sw, sred))) break;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         Jb[c] = gm.mu * sRes[c];
         Jb[3 + c] = -(gm.mu * sRes[3 + c]);
       }
-      // C: Y3 = R(Om) P, Om = f2/2 - (f1 x f2)/8  ->  f2-bar, f1-bar
 #pragma unroll
       for (int c = 0; c < 6; ++c) red[c] = 0.0;
-#pragma unroll
-      for (int i = 0; i < BPT; ++i) {
-        AdjBeam& B = q[i];
-        if (!B.on) continue;
-        double f1[3], f2[3], cr[3], Y[3], Yb[3], om[3], ob[3], a1[3], a2[3], f2b[3];
-        stage_f(a, B, sJ[0], g0, B.c0, B.hc0, f1);
-        stage_f(a, B, sJ[1], gm, B.cm, B.hcm, f2);
-        cross(f1, f2, cr);
-        const Rot R = make_rot(0.5 * f2[0] - 0.125 * cr[0], 0.5 * f2[1] - 0.125 * cr[1],
-                               0.5 * f2[2] - 0.125 * cr[2]);
-        rot_fwd(R, B.P[0], B.P[1], B.P[2], Y[0], Y[1], Y[2]);
-        m_bar(a, B, Jb, B.cm, Y, Yb, gacc);
-        rot_inv_add(R, Yb[0], Yb[1], Yb[2], B.Pb);
-        cross(Y, Yb, om);
-        jl_t(R, om, ob);
-        cross(ob, f1, a1);
-        cross(f2, ob, a2);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          f2b[c] = (0.5 * ob[c] - a1[c] / 8.0) + B.Tb[c] / 3.0;
-          B.F1[c] -= a2[c] / 8.0;
-        }
-        const double Bb[3] = {B.hcm * f2b[0], B.hcm * f2b[1], B.hcm * f2b[2]};
-        b_bar(a, B, Bb, B.cm, gm, red, gacc);
-      }
+      each([&](AdjBeam& B, long long) { phase_c(a, B, sJ, Jb, g0, gm, red, gacc); }, true, t, g0, gm, g1);
       if (!(ok = grid_sum<6>(a, epoch++, red, sRes, sw, sred))) break;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         Jb[c] = gm.mu * sRes[c];
         Jb[3 + c] = -(gm.mu * sRes[3 + c]);
       }
-      // D: Y2 = R(f1/2) P  ->  f1-bar complete
 #pragma unroll
       for (int c = 0; c < 6; ++c) red[c] = 0.0;
-#pragma unroll
-      for (int i = 0; i < BPT; ++i) {
-        AdjBeam& B = q[i];
-        if (!B.on) continue;
-        double f1[3], Y[3], Yb[3], om[3], ob[3];
-        stage_f(a, B, sJ[0], g0, B.c0, B.hc0, f1);
-        const Rot R = make_rot(0.5 * f1[0], 0.5 * f1[1], 0.5 * f1[2]);
-        rot_fwd(R, B.P[0], B.P[1], B.P[2], Y[0], Y[1], Y[2]);
-        m_bar(a, B, Jb, B.cm, Y, Yb, gacc);
-        rot_inv_add(R, Yb[0], Yb[1], Yb[2], B.Pb);
-        cross(Y, Yb, om);
-        jl_t(R, om, ob);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) B.F1[c] += 0.5 * ob[c];
-        const double Bb[3] = {B.hc0 * B.F1[0], B.hc0 * B.F1[1], B.hc0 * B.F1[2]};
-        b_bar(a, B, Bb, B.c0, g0, red, gacc);
-      }
+      each([&](AdjBeam& B, long long) { phase_d(a, B, sJ, Jb, g0, red, gacc); }, true, t, g0, gm, g1);
       if (!(ok = grid_sum<6>(a, epoch++, red, sRes, sw, sred))) break;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         Jb[c] = g0.mu * sRes[c];
         Jb[3 + c] = -(g0.mu * sRes[3 + c]);
       }
-      // J^(1) = M(P_n): broadcast onto the state itself
-#pragma unroll
-      for (int i = 0; i < BPT; ++i) {
-        AdjBeam& B = q[i];
-        if (!B.on) continue;
-        double Yb[3];
-        m_bar(a, B, Jb, B.c0, B.P, Yb, gacc);
-        B.Pb[0] += Yb[0];
-        B.Pb[1] += Yb[1];
-        B.Pb[2] += Yb[2];
-      }
+      each([&](AdjBeam& B, long long) { phase_e(a, B, Jb, gacc); }, true, t, g0, gm, g1);
     }
   }
   if (!ok) return;
   if (a.state_bar) {
+    if constexpr (BPT > 0) {
 #pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-      if (!q[i].on) continue;
-      const long long b = gt + i * nthr;
-      a.state_bar[b] = q[i].Pb[0];
-      a.state_bar[b + a.nb] = q[i].Pb[1];
-      a.state_bar[b + 2 * a.nb] = q[i].Pb[2];
+      for (int i = 0; i < BPT; ++i) {
+        if (!q[i].on) continue;
+        const long long b = gt + i * nthr;
+        a.state_bar[b] = q[i].Pb[0];
+        a.state_bar[b + a.nb] = q[i].Pb[1];
+        a.state_bar[b + 2 * a.nb] = q[i].Pb[2];
+      }
+    } else {
+      for (long long b = gt; b < a.nb; b += nthr)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.state_bar[b + c * a.nb] = a.spill[(size_t)c * a.plane + b];
     }
   }
   if (grid_sum<5>(a, epoch++, gacc, sRes, sw, sred) && blockIdx.x == 0 && tid < 5) a.out[tid] = sRes[tid];
 }
 
+template __global__ void k_adjoint2<0>(AdjArgs);
 template __global__ void k_adjoint2<1>(AdjArgs);
 template __global__ void k_adjoint2<2>(AdjArgs);
 template __global__ void k_adjoint2<4>(AdjArgs);

@@ -26,6 +26,7 @@ __global__ void k_adaptive(StepArgs a);
 __global__ void k_zero_sync(unsigned int* sync, int keep_status);
 __global__ void k_zero_u64(unsigned long long* p, long long n);
 __global__ void k_set_step(long long* step_ctl, long long step);
+__global__ void k_status_out(const unsigned int* sync, const long long* step_ctl, long long* host);
 __global__ void k_set_target(long long* step_ctl, long long k, long long total);
 template <typename ST>
 __global__ void k_init(ST* X, long long nb, long long plane, int nsc, long long per_species, int nfl);
@@ -112,7 +113,7 @@ struct nb_model {
   unsigned long long ticks_per_s = 0;
   size_t off_X = 0, off_tab = 0, off_sync = 0, off_ctl = 0;
   size_t off_models = 0, off_waves = 0, off_acc = 0, need = 0;
-  size_t off_adj = 0, off_jhist = 0, off_dtab = 0, off_aout = 0, off_X2 = 0;
+  size_t off_adj = 0, off_spill = 0, off_jhist = 0, off_dtab = 0, off_aout = 0, off_X2 = 0;
   double* jhist = nullptr;           // set while the adjoint's forward pass records moments
   int adj_blocks = 0, adj_bpt = 0;
   long long* pinned = nullptr;       // [0] status, [1] step, [8..12] adjoint gradients
@@ -461,7 +462,7 @@ static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 // (batches) model descriptors | wave row ranges | moment accumulators | (adjoint) its
 // regions | (adaptive) the second state buffer.
 struct Layout {
-  size_t X, tab, sync, ctl, models, waves, acc, adj, jhist, dtab, aout, X2, need;
+  size_t X, tab, sync, ctl, models, waves, acc, adj, spill, jhist, dtab, aout, X2, need;
 };
 
 // The adjoint (single two-flavour model with adjoint_ckpt = K > 0) reserves state slots
@@ -484,7 +485,7 @@ static Layout layout_of(const nb_model* m) {
   L.sync = o;
   o = align256(o + sizeof(unsigned int) * kSyncWords);
   L.ctl = o;
-  o = align256(o + 256);
+  o = align256(o + sizeof(long long) * kCtlWords);
   L.models = o;
   L.waves = o;
   L.acc = o;
@@ -495,9 +496,11 @@ static Layout layout_of(const nb_model* m) {
     L.acc = o;
     o = align256(o + sizeof(unsigned long long) * (size_t)kAccSets * m->nmodels * 6 * kAccLimbs);
   }
-  L.adj = L.jhist = L.dtab = L.aout = o;
+  L.adj = L.jhist = L.dtab = L.aout = L.spill = o;
   if (adjoint_enabled(m)) {
     o = align256(o + sizeof(double) * (size_t)adjoint_slots(m) * 3 * m->plane);
+    L.spill = o;   // the reverse kernel's adjoint registers when the beams outnumber its threads
+    o = align256(o + sizeof(double) * (size_t)9 * m->plane);
     L.jhist = o;
     o = align256(o + sizeof(double) * (size_t)(m->p.n_steps + 1) * 24);
     L.dtab = o;
@@ -683,6 +686,7 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
   m->off_waves = L.waves;
   m->off_acc = L.acc;
   m->off_adj = L.adj;
+  m->off_spill = L.spill;
   m->off_jhist = L.jhist;
   m->off_dtab = L.dtab;
   m->off_aout = L.aout;
@@ -691,7 +695,9 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
   m->adj_bpt = 0;
   m->adj_blocks = 0;
   if (adjoint_enabled(m)) {
-    // smallest beams-per-thread variant whose resident grid covers every beam
+    // smallest beams-per-thread variant whose resident grid covers every beam; beyond four
+    // beams per resident thread, the spill variant (adjoint registers in the workspace) on
+    // the full resident grid
     static const int bpts[3] = {1, 2, 4};
     static const void* fns[3] = {(const void*)&k_adjoint2<1>, (const void*)&k_adjoint2<2>,
                                  (const void*)&k_adjoint2<4>};
@@ -705,6 +711,15 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
         m->adj_bpt = bpts[i];
         m->adj_blocks = (int)std::max<long long>(1, need_blocks);
       }
+    }
+    if (!m->adj_bpt) {
+      int per = 0;
+      NB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)&k_adjoint2<0>, kBlock, 0));
+      if (per < 1) return fail(NB_EHIP, "adjoint kernel cannot be resident");
+      int blocks = std::min(cus * per, kMaxBlocks);
+      if (m->p.max_blocks > 0) blocks = std::min(blocks, (int)m->p.max_blocks);
+      m->adj_bpt = -1;   // spill mode
+      m->adj_blocks = std::max(1, blocks);
     }
   }
   m->ws = (char*)dev_ws;
@@ -746,10 +761,10 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
 static int check_status(nb_model* m) {
   if (capturing(m->stream)) return NB_OK;
   unsigned int* sync = sync_words(m);
-  NB_HIP(hipMemcpyAsync(m->pinned, sync + kSyncStatus, sizeof(unsigned int), hipMemcpyDeviceToHost,
-                        m->stream));
-  NB_HIP(hipMemcpyAsync(m->pinned + 1, m->ws + m->off_ctl, sizeof(long long), hipMemcpyDeviceToHost,
-                        m->stream));
+  const long long* ctl = (const long long*)(m->ws + m->off_ctl);
+  long long* host = m->pinned;
+  void* sargs[] = {&sync, &ctl, &host};
+  NB_HIP(hipLaunchKernel((const void*)&k_status_out, dim3(1), dim3(1), sargs, 0, m->stream));
   NB_HIP(hipStreamSynchronize(m->stream));
   const unsigned st = (unsigned)(m->pinned[0] & 0xffffffffll);
   m->step = m->pinned[1];
@@ -968,7 +983,8 @@ extern "C" int nb_run_adaptive(nb_model* m, double tol, double h_max_km, int64_t
   drop_graph(m);
   const Sub& s = m->subs[0];
   const double span = m->p.r_end_km - m->p.r_start_km;
-  long long init[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  long long init[kCtlMKind + 1] = {};
+  init[kCtlMTag] = -1;
   double r0 = m->p.r_start_km, h0 = s.h;
   std::memcpy(&init[kCtlR], &r0, sizeof(double));
   std::memcpy(&init[kCtlH], &h0, sizeof(double));
@@ -1199,7 +1215,7 @@ extern "C" int nb_adjoint(nb_model* m, const double* dev_dl_dpee, double* grad_o
     return fail(NB_EINVAL, "the adjoint needs a single two-flavour model created with adjoint_ckpt > 0");
   if (ckpt_every < 0) return fail(NB_EINVAL, "ckpt_every must be >= 0");
   if (capturing(m->stream)) return fail(NB_EINVAL, "the adjoint cannot be captured into a graph");
-  if (!m->adj_bpt) return fail(NB_EINVAL, "too many beams (%lld) for one resident adjoint grid", m->nb);
+  if (!m->adj_bpt) return fail(NB_EUNBOUND, "adjoint launch shape not set (bind the model)");
   const long long K = ckpt_every > 0 ? ckpt_every : m->p.adjoint_ckpt;
   const long long n0 = m->step, N = m->p.n_steps, ns = N - n0;
   const long long nseg = (ns + K - 1) / K;
@@ -1240,6 +1256,7 @@ extern "C" int nb_adjoint(nb_model* m, const double* dev_dl_dpee, double* grad_o
   a.cot = dev_dl_dpee;
   a.cot_const = ((s.p.e_max_mev - s.p.e_min_mev) / (double)s.NE) / (double)s.NU;
   a.state_bar = dev_state_bar;
+  a.spill = (double*)(m->ws + m->off_spill);
   a.out = (double*)(m->ws + m->off_aout);
   a.sync = sync;
   a.plane = m->plane;
@@ -1261,7 +1278,8 @@ extern "C" int nb_adjoint(nb_model* m, const double* dev_dl_dpee, double* grad_o
   void* args[] = {&a};
   const void* fn = m->adj_bpt == 1 ? (const void*)&k_adjoint2<1>
                  : m->adj_bpt == 2 ? (const void*)&k_adjoint2<2>
-                                   : (const void*)&k_adjoint2<4>;
+                 : m->adj_bpt == 4 ? (const void*)&k_adjoint2<4>
+                                   : (const void*)&k_adjoint2<0>;
   const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(m->adj_blocks), dim3(kBlock), args, 0, m->stream);
   if (e != hipSuccess) return fail(NB_EHIP, "adjoint launch: %s", hipGetErrorString(e));
   const long long before = m->step;

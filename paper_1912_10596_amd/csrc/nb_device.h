@@ -57,6 +57,41 @@ __device__ __forceinline__ void sincos_nb(double x, double& sn, double& cs) {
   cs = ((quad + 1) & 2) ? -b : b;
 }
 
+// The same sin/cos with its constants read from a table (for instance in LDS, so that a
+// kernel short of registers does not hold them in VGPRs): c = the values sincos_coefs writes.
+constexpr int kSinCosTab = 21;
+__device__ __forceinline__ void sincos_coefs(double* c) {
+  c[0] = 0x1.45f306dc9c883p-1; c[1] = 0x1.921fb54442d18p+0; c[2] = 0x1.1a62633145c07p-54;
+  c[3] = -0x1.f1976b7ed8fbcp-110;
+  c[4] = 1.0 / 355687428096000.0; c[5] = -1.0 / 1307674368000.0; c[6] = 1.0 / 6227020800.0;
+  c[7] = -1.0 / 39916800.0; c[8] = 1.0 / 362880.0; c[9] = -1.0 / 5040.0; c[10] = 1.0 / 120.0;
+  c[11] = -1.0 / 6.0;
+  c[12] = -1.0 / 6402373705728000.0; c[13] = 1.0 / 20922789888000.0; c[14] = -1.0 / 87178291200.0;
+  c[15] = 1.0 / 479001600.0; c[16] = -1.0 / 3628800.0; c[17] = 1.0 / 40320.0; c[18] = -1.0 / 720.0;
+  c[19] = 1.0 / 24.0; c[20] = -0.5;
+}
+__device__ __forceinline__ void sincos_tab(double x, const double* c, double& sn, double& cs) {
+  const double t = fma(x, c[0], 0x1.8p52);
+  const double k = t - 0x1.8p52;
+  double r = fma(-k, c[1], x);
+  r = fma(-k, c[2], r);
+  r = fma(-k, c[3], r);
+  const double r2 = r * r;
+  double ps = c[4];
+#pragma unroll
+  for (int i = 5; i <= 11; ++i) ps = fma(ps, r2, c[i]);
+  const double s = fma(r2 * r, ps, r);
+  double pc = c[12];
+#pragma unroll
+  for (int i = 13; i <= 20; ++i) pc = fma(pc, r2, c[i]);
+  const double cc = fma(r2, pc, 1.0);
+  const int quad = (int)(__double_as_longlong(t) & 3);
+  const double a = (quad & 1) ? cc : s;
+  const double b = (quad & 1) ? s : cc;
+  sn = (quad & 2) ? -a : a;
+  cs = ((quad + 1) & 2) ? -b : b;
+}
+
 // ------------------------------------------------------------- fixed point
 // 128-bit two's complement integer held as two 64-bit halves.
 struct I128 {
@@ -257,14 +292,18 @@ __device__ __forceinline__ void exp3_apply(const Herm3& K, cplx psi[3]) {
 }
 
 // Bloch-vector rotation about x by |x| (two flavours): unit quaternion
-// (cos|x|/2, sin(|x|/2) x/|x|), P' = P + w t + v x t with t = 2 v x P.
+// (cos|x|/2, sin(|x|/2) x/|x|), P' = P + w t + v x t with t = 2 v x P.  TAB: the sin/cos
+// constants are read from tab (sincos_coefs) instead of immediates.
+template <bool TAB = false>
 __device__ __forceinline__ void rotate2(const double x0, const double x1, const double x2,
-                                        double& P0, double& P1, double& P2) {
+                                        double& P0, double& P1, double& P2,
+                                        const double* tab = nullptr) {
   const double t2 = (x0 * x0 + x1 * x1) + x2 * x2;
   const double th = sqrt(t2);
   if (th == 0.0) return;
   double s, c;
-  sincos_nb(0.5 * th, s, c);
+  if constexpr (TAB) sincos_tab(0.5 * th, tab, s, c);
+  else sincos_nb(0.5 * th, s, c);
   const double k = s / th;
   const double v0 = x0 * k, v1 = x1 * k, v2 = x2 * k;
   double t0 = v1 * P2 - v2 * P1;

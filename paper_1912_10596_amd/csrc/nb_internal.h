@@ -5,7 +5,8 @@
 
 namespace nb {
 
-constexpr int kMaxBlocks = 8192;  // upper bound on blocks of one stepping launch
+constexpr int kMaxBlocks = 2048;  // upper bound on blocks of one stepping launch (MI355X: 256 CUs
+                                  // hold at most 4 blocks of 512 threads each)
 
 // Offsets (in 32-bit words) of the synchronisation words.  Every word that more than one
 // block writes or polls sits on a 128-byte line of its own: the abort and status words,
@@ -17,14 +18,15 @@ constexpr int kSyncAbort = 1 * kLineWords;   // set when any block gives up wait
 constexpr int kSyncStatus = 2 * kLineWords;  // bit 0: fixed-point range error, bit 1: barrier timeout
 constexpr int kSyncFlag = 4 * kLineWords;    // [kFlagCopies] lines: epoch + 1 of the last release
 constexpr int kSyncArrive = kSyncFlag + kFlagCopies * kLineWords;  // [kMaxBlocks] lines
-// Tagged 64-bit words of the single-model stepping kernels' moment reduction (every word
-// carries the barrier epoch it belongs to, so no separate arrival or release word is
-// needed): kFlagCopies copies of the reduced moments (block b reads copy b % kFlagCopies),
-// kTagLines lines each; one slot of kTagLines lines of block partials per block.
+// Tagged 64-bit words of the moment reductions (every word carries the barrier epoch it
+// belongs to, so no separate arrival or release word is needed): kFlagCopies copies of
+// reduced moments (the adjoint's sums; block b reads copy b % kFlagCopies), kTagLines lines
+// each; then block partials, one slot of kTagLines lines per block, in two regions used by
+// the stepping kernels at even and odd epochs (the adjoint uses the first).
 constexpr int kTagLines = 4;
 constexpr int kSyncJTag = kSyncArrive + kMaxBlocks * kLineWords;
 constexpr int kSyncPart = kSyncJTag + kFlagCopies * kTagLines * kLineWords;
-constexpr int kSyncWords = kSyncPart + kMaxBlocks * kTagLines * kLineWords;
+constexpr int kSyncWords = kSyncPart + 2 * kMaxBlocks * kTagLines * kLineWords;
 constexpr int kTagWords64 = kTagLines * kLineWords / 2;   // 64-bit words per copy or slot
 
 constexpr int kVacRows3 = 7;    // 3f table rows before the weights: 6 vacuum entries and e_k
@@ -61,6 +63,12 @@ struct StepArgs {
 // step_ctl words of an adaptive run: [2] r, [3] h (double bits), [4] accepted, [5] rejected,
 // [6] attempts, [7] 1 if the step control failed
 constexpr int kCtlR = 2, kCtlH = 3, kCtlAcc = 4, kCtlRej = 5, kCtlAtt = 6, kCtlFail = 7;
+// step_ctl words [kCtlMTag] and [kCtlMKind]: the step and the stepping-kernel variant whose
+// stage-1 moments (those of the state at that step) the launch that ended there left in
+// words [kCtlMom, kCtlMom + 32) as doubles, so that the next launch of the same variant
+// skips its initial moment pass; kCtlMTag = -1: none (every change of the state outside a
+// stepping launch sets it).
+constexpr int kCtlMTag = 9, kCtlMKind = 10, kCtlMom = 16, kCtlWords = 48;
 
 // One two-flavour model of a batch.
 struct BatchModel {
@@ -94,7 +102,8 @@ struct BatchArgs {
 };
 
 // Arguments of the two-flavour reverse (adjoint) kernel.  Beam b belongs to thread
-// b mod (grid threads); its adjoint state stays in registers for the whole launch.
+// b mod (grid threads); its adjoint state stays in registers for the whole launch, or, when
+// the beams outnumber four per resident thread, in the workspace (spill).
 struct AdjArgs {
   const double* tab;       // [bx|bz|G0|G1] x NE
   const double* dtab;      // [dG0/dL_e | dG1/dL_ebar | dG/dL_x | dbx/dtheta | dbz/dtheta] x NE
@@ -104,6 +113,7 @@ struct AdjArgs {
   const double* cot;       // dL/dPee per beam, or nullptr: cot_const for every beam
   double cot_const;
   double* state_bar;       // nullptr, or [3][nb]: dL/d(state at the first step)
+  double* spill;           // [9][plane]: the beams' adjoint registers (spill mode only)
   double* out;             // [8]: dL/d{L_e, L_ebar, L_x, theta_v, n0}
   unsigned int* sync;      // kSyncWords words (barrier words and the tagged reduction words)
   long long plane, nb;

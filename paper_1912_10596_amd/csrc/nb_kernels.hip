@@ -26,23 +26,24 @@ __device__ __forceinline__ Radial radial_at(const StepArgs& a, double r) {
   return radial(a.R, a.ne_power, a.lam0, r);
 }
 
-// Grid-wide reduction of the stage moments with tagged words.  Every 64-bit word that
-// crosses blocks carries the epoch of the barrier it belongs to, so a reader knows from
-// the word itself whether it is current, and no arrival or release word (and no store
-// acknowledgement before one) lies on the critical path:
+// Grid-wide reduction of the stage moments with tagged words, gathered by every block.
+// Every 64-bit word that crosses blocks carries the epoch of the barrier it belongs to, so
+// a reader knows from the word itself whether it is current, and no arrival or release
+// word (and no store acknowledgement before one) lies on the critical path:
 //  * every block publishes its partial (NV 128-bit sums, each below 2^95 in magnitude) as
-//    2 NV words of a 16-bit tag and a 48-bit chunk: bits 0..47, then bits 48..95;
-//  * block 0 polls all partial words (each of its threads owns one chunk position of a
-//    set of blocks and re-polls only the words not yet current, all loads in flight),
-//    adds the chunks in 64-bit integers (below 2^61 for up to 8192 blocks), combines them
-//    to the exact 128-bit totals and publishes the moments as 2 NV words of a 32-bit tag
-//    and a 32-bit half, in kFlagCopies copies;
-//  * every other block polls the 2 NV words of its copy, one per lane of its first wave.
-// A word is written again only after every block has read it: block b publishes partial
-// e + 1 after reading moments e, which block 0 publishes after reading every partial e.
-// All words are zeroed before each launch and epochs start at 1, so a tag equal to the
-// wanted epoch is never stale (the 16-bit tags of the partials repeat only every 65536
-// barriers, and every partial word is rewritten at every barrier).
+//    2 NV words of a 16-bit tag and a 48-bit chunk: bits 0..47, then bits 48..95, into its
+//    slot of the region of the epoch's parity;
+//  * every block polls all partial words (each of its threads owns one chunk position of
+//    a set of blocks and re-polls only the words not yet current, all loads in flight),
+//    adds the chunks in 64-bit integers (below 2^61 for up to kMaxBlocks blocks) and
+//    combines them to the exact 128-bit totals: the same integers in every block, whatever
+//    the order, so every block holds the same moments after one publish-and-poll hop.
+// The two parity regions make every word safe to rewrite: block b writes its slot of
+// parity e % 2 at epoch e only after reading every partial of epoch e - 1, and every
+// block c wrote that partial only after it had finished reading epoch e - 2, the previous
+// contents of the same parity region.  All words are zeroed before each launch and
+// epochs start at 1, so a tag equal to the wanted epoch is never stale (the 16-bit tags
+// repeat only every 65536 barriers).
 // Returns false if the barrier was abandoned (time limit or abort).
 constexpr unsigned long long kMask48 = (1ull << 48) - 1ull;
 // 48-bit chunk k of a 128-bit value below 2^95 in magnitude: k = 0 the unsigned bits
@@ -55,69 +56,38 @@ __device__ __forceinline__ long long chunk_value(unsigned long long field, int k
   return k ? ((long long)(field << 16) >> 16) : (long long)field;
 }
 
-// blk: the block's partial (threads tid < NV hold component tid); own: in block 0, thread
-// tid < W holds chunk tid % 2 of its component tid / 2 (and, with MAXE, thread 2 NV the
-// block's error field).  MAXE adds one more word to every partial, efield (thread NV): the
-// block's largest error estimate as the top 48 bits of its binary form (a non-negative
-// double, so the integer order of the fields is the order of the values); block 0 takes
-// the largest field and publishes the value in two more words, which lands in *sE.
+// blk: the block's partial (threads tid < NV hold component tid); own: unused (every
+// block reads its own partial back with the others).  MAXE adds one more word to every
+// partial, efield (thread NV): the block's largest error estimate as the top 48 bits of its
+// binary form (a non-negative double, so the integer order of the fields is the order of
+// the values); every block takes the largest field, which lands in *sE.
 // NM moment groups of NV / NM components: J0 | J1 (| J_sc | J_ss); J1 is at scale 2^e1,
 // the others at 2^e0.
 template <int NV, bool MAXE, int NM = 2>
 __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, long long own,
                             unsigned long long efield, double* sJ, long long* sacc, double* sE) {
   constexpr int W = 2 * NV + (MAXE ? 1 : 0);   // words per partial
-  constexpr int JW = 2 * NV + (MAXE ? 2 : 0);  // words per moment copy
-  constexpr int G = kBlock / W;      // block-0 thread groups, one chunk position per thread
-  static_assert(JW <= kTagWords64, "tagged slot too small");
+  constexpr int G = kBlock / W;                // thread groups, one chunk position per thread
+  static_assert(W <= kTagWords64, "tagged slot too small");
   const int tid = threadIdx.x;
   const unsigned want = epoch + 1u;
-  unsigned long long* part = reinterpret_cast<unsigned long long*>(a.sync + kSyncPart);
-  unsigned long long* jw = reinterpret_cast<unsigned long long*>(a.sync + kSyncJTag);
   const unsigned long long tag16 = (unsigned long long)(want & 0xffffu);
-  if (blockIdx.x != 0) {
-    if (tid < NV) {
-      unsigned long long* q = part + (size_t)blockIdx.x * kTagWords64 + 2 * tid;
-      __hip_atomic_store(q, (tag16 << 48) | chunk_field(blk, 0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(q + 1, (tag16 << 48) | chunk_field(blk, 1), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (MAXE && tid == NV)
-      __hip_atomic_store(part + (size_t)blockIdx.x * kTagWords64 + 2 * NV, (tag16 << 48) | efield,
-                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int ok = 1;
-    if (tid < JW) {
-      const unsigned long long* w =
-          jw + (size_t)(blockIdx.x % kFlagCopies) * kTagWords64 + tid;
-      const unsigned long long t0 = wall_clock64();
-      unsigned long long x;
-      for (unsigned it = 1;; ++it) {
-        x = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((unsigned)(x >> 32) == want) break;
-        if ((it & 31u) == 0u && give_up(a.sync, t0, a.timeout_ticks)) {
-          ok = 0;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-      // lane 2v holds the low half of moment v, lane 2v + 1 the high half (lanes 2 NV and
-      // 2 NV + 1: the error estimate)
-      const unsigned hi = __shfl_down((unsigned)x, 1, 64);
-      if (ok && (tid & 1) == 0) {
-        const double val = as_double(((unsigned long long)hi << 32) | (x & 0xffffffffull));
-        if (tid < 2 * NV) sJ[tid >> 1] = val;
-        else *sE = val;
-      }
-    }
-    return !__syncthreads_or(!ok);
+  unsigned long long* part = reinterpret_cast<unsigned long long*>(a.sync + kSyncPart) +
+                             (size_t)(epoch & 1u) * kMaxBlocks * kTagWords64;
+  unsigned long long* slot = part + (size_t)blockIdx.x * kTagWords64;
+  if (tid < NV) {
+    __hip_atomic_store(slot + 2 * tid, (tag16 << 48) | chunk_field(blk, 0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(slot + 2 * tid + 1, (tag16 << 48) | chunk_field(blk, 1), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
   }
-  // block 0: its own partial goes straight to the fold
+  if (MAXE && tid == NV)
+    __hip_atomic_store(slot + 2 * NV, (tag16 << 48) | efield, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   int ok = 1;
   const int pos = tid % W, g = tid / W;
-  long long acc = (g == 0) ? own : 0;
+  long long acc = 0;
   if (g < G) {
     const unsigned long long t0 = wall_clock64();
-    for (unsigned b0 = 1 + g; b0 < gridDim.x && ok; b0 += 16 * G) {
+    for (unsigned b0 = g; b0 < gridDim.x && ok; b0 += 16 * G) {
       unsigned pend = 0;
       unsigned long long w[16];
 #pragma unroll
@@ -154,31 +124,13 @@ __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, long lo
       c0 += sacc[gg * W + 2 * tid];
       c1 += sacc[gg * W + 2 * tid + 1];
     }
-    // total = c0 + c1 2^48 (c0 >= 0, c1 signed)
     const I128 tot = i128_add(I128{(unsigned long long)c0, 0ll},
                               I128{(unsigned long long)c1 << 48, c1 >> 16});
-    const double val = i128_to_double(tot) * ((tid / (NV / NM)) == 1 ? a.p2e1 : a.p2e0);
-    sJ[tid] = val;
-    const unsigned long long bits = as_bits(val);
-    const unsigned long long tg = (unsigned long long)want << 32;
-#pragma unroll
-    for (int c = 0; c < kFlagCopies; ++c) {
-      unsigned long long* q = jw + (size_t)c * kTagWords64 + 2 * tid;
-      __hip_atomic_store(q, tg | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(q + 1, tg | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    sJ[tid] = i128_to_double(tot) * ((tid / (NV / NM)) == 1 ? a.p2e1 : a.p2e0);
   } else if (MAXE && tid == NV) {
     long long f = 0;
     for (int gg = 0; gg < G; ++gg) f = max(f, sacc[gg * W + 2 * NV]);
-    const unsigned long long bits = (unsigned long long)f << 16;
-    *sE = as_double(bits);
-    const unsigned long long tg = (unsigned long long)want << 32;
-#pragma unroll
-    for (int c = 0; c < kFlagCopies; ++c) {
-      unsigned long long* q = jw + (size_t)c * kTagWords64 + 2 * NV;
-      __hip_atomic_store(q, tg | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(q + 1, tg | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    *sE = as_double((unsigned long long)f << 16);
   }
   __syncthreads();
   return true;
@@ -333,23 +285,51 @@ __device__ __forceinline__ void stage_geo(double u, double h, const Radial& g0, 
 }
 
 // ----------------------------------------------------------------- two flavours
+// Every two-flavour stage keeps its stage-wide and per-row constants in a per-wavefront LDS
+// block, written by lane 0 and re-read where they are used, so that the beam loop holds
+// only per-beam values in registers (which lets four wavefronts share a SIMD):
+constexpr int kC2Rad = 0;    // q2, lam, mu at the stage radii r0, rm, r1 (9)
+constexpr int kC2Sc = 9;     // fixed-point scales s1, s0, p2e1, p2e0 (4)
+constexpr int kC2Row = 13;   // generator i = 1..4: h/cos, lam, nu-nu term (3): 5 each (20);
+                             // then 1/cos at the moments' radius and the azimuthal factors (3)
+constexpr int kC2Geo = 36;   // the wavefront's first row's stage geometry (11, stage_geo)
+constexpr int kC2Size = 48;
+// Stage-wide constants: the radial profiles at the three stage radii and the scales.
+__device__ __forceinline__ void put_stage2(double* cb, int lane, const Radial& g0, const Radial& gm,
+                                           const Radial& g1, const Scales& sc) {
+  if (lane == 0) {
+    cb[kC2Rad + 0] = g0.q2; cb[kC2Rad + 1] = g0.lam; cb[kC2Rad + 2] = g0.mu;
+    cb[kC2Rad + 3] = gm.q2; cb[kC2Rad + 4] = gm.lam; cb[kC2Rad + 5] = gm.mu;
+    cb[kC2Rad + 6] = g1.q2; cb[kC2Rad + 7] = g1.lam; cb[kC2Rad + 8] = g1.mu;
+    cb[kC2Sc + 0] = sc.s1; cb[kC2Sc + 1] = sc.s0; cb[kC2Sc + 2] = sc.p2e1; cb[kC2Sc + 3] = sc.p2e0;
+  }
+  __asm__ volatile("" ::: "memory");   // the wave's LDS operations complete in program order
+}
+// Stage generator i of beam (bx, bz) from its row constants c = [h/cos, lam, nu-nu term]
+// (the arithmetic of gen2).
+__device__ __forceinline__ void gen2c(int an, double bx, double bz, const double* c, double f[3]) {
+  const double nn[3] = {c[2], c[3], c[4]};
+  gen2(an, bx, bz, c[1], nn, c[0], f);
+}
+
 // Stage stencil for one (species s, emission bin u) row of NE beams starting at beam rb.
 // KIND: 0 moments of rho_n at r_n; 1 stage Y2 (moments at r_n + h/2); 2 stage Y3
 // (r_n + h/2); 3 stage Y4 (r_{n+1}); 4 final update, store and moments at r_{n+1}.
 // J[i]: stage moments J^(i+1) (J0 | J1, 6 doubles).  A lane adds the fixed-point
 // contributions of up to 32 of its beams in 64-bit integers (each below 2^51) before they
 // are folded into exact 128-bit wave sums; a beam whose state has squared norm 2 or more
-// (NaN included) sets err.
+// (NaN included) sets err.  cb: the wavefront's constant block (put_stage2 written).
 // ADAPT (final update only): the new state goes to Xo instead of X, and emax keeps the
 // largest embedded error estimate |Theta - f2|^2 of the lane's beams.
 // EXT: extended bulb model, azimuth (cp, sp) = (cos, sin) of the row's azimuthal bin.
+// geo: this row is the wavefront's first (its stage geometry is cached across stages).
 template <int KIND, bool ADAPT = false, bool EXT = false>
 __device__ __forceinline__ void row2(const double* X, double* Xo, long long plane, long long rb, int NE,
-                                     int s, double u, double h, const double* tab, const Radial& g0,
-                                     const Radial& gm, const Radial& g1, const double* const* J,
-                                     const Scales& sc, int renorm, int lane, long long* fl, I128& T,
+                                     int s, double u, double h, const double* tab, double* cb,
+                                     const double* const* J, int renorm, int lane, long long* fl, I128& T,
                                      int& err, double& emax, double cp = 0.0, double sp = 0.0,
-                                     int an = -1, double* gc = nullptr) {
+                                     int an = -1, bool geo = false, const double* sct = nullptr) {
+  // sct: the block's sin/cos constants (sincos_coefs, in LDS)
   constexpr int NM = EXT ? 4 : 2;
   // the lane's first beam of the row, loaded before the row set-up so that the set-up
   // arithmetic overlaps the load
@@ -359,14 +339,36 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
   }
   // species row s, antiparticle flag an (default: s itself, two tracked species)
   if (an < 0) an = s;
-  RowGeo rg;
-  double icmom, sn0, snm, sn1;
-  stage_geo<KIND, EXT>(u, h, g0, gm, g1, gc, rg, icmom, sn0, snm, sn1);
-  double n1[3], n2[3], n3[3], n4[3];
-  if (KIND == 1 || KIND == 2 || KIND == 4) nunu_row<3, EXT>(J[0], g0.mu, rg.c0, sn0, cp, sp, n1);
-  if (KIND == 2 || KIND == 4) nunu_row<3, EXT>(J[1], gm.mu, rg.cm, snm, cp, sp, n2);
-  if (KIND >= 3) nunu_row<3, EXT>(J[2], gm.mu, rg.cm, snm, cp, sp, n3);
-  if (KIND == 4) nunu_row<3, EXT>(J[3], g1.mu, rg.c1, sn1, cp, sp, n4);
+  double* rc = cb + kC2Row;
+  __asm__ volatile("" ::: "memory");   // stage constants re-read from LDS for every row
+  {
+    const Radial g0{cb[kC2Rad + 0], cb[kC2Rad + 1], cb[kC2Rad + 2], 0.0};
+    const Radial gm{cb[kC2Rad + 3], cb[kC2Rad + 4], cb[kC2Rad + 5], 0.0};
+    const Radial g1{cb[kC2Rad + 6], cb[kC2Rad + 7], cb[kC2Rad + 8], 0.0};
+    RowGeo rg;
+    double icmom, sn0, snm, sn1;
+    stage_geo<KIND, EXT>(u, h, g0, gm, g1, geo ? cb + kC2Geo : nullptr, rg, icmom, sn0, snm, sn1);
+    double n[3];
+    if (KIND == 1 || KIND == 2 || KIND == 4) {
+      nunu_row<3, EXT>(J[0], g0.mu, rg.c0, sn0, cp, sp, n);
+      if (lane == 0) { rc[0] = rg.hc0; rc[1] = g0.lam; rc[2] = n[0]; rc[3] = n[1]; rc[4] = n[2]; }
+    }
+    if (KIND == 2 || KIND == 4) {
+      nunu_row<3, EXT>(J[1], gm.mu, rg.cm, snm, cp, sp, n);
+      if (lane == 0) { rc[5] = rg.hcm; rc[6] = gm.lam; rc[7] = n[0]; rc[8] = n[1]; rc[9] = n[2]; }
+    }
+    if (KIND >= 3) {
+      nunu_row<3, EXT>(J[2], gm.mu, rg.cm, snm, cp, sp, n);
+      if (lane == 0) { rc[10] = rg.hcm; rc[11] = gm.lam; rc[12] = n[0]; rc[13] = n[1]; rc[14] = n[2]; }
+    }
+    if (KIND == 4) {
+      nunu_row<3, EXT>(J[3], g1.mu, rg.c1, sn1, cp, sp, n);
+      if (lane == 0) { rc[15] = rg.hc1; rc[16] = g1.lam; rc[17] = n[0]; rc[18] = n[1]; rc[19] = n[2]; }
+    }
+    const double snmom = (KIND == 0) ? sn0 : ((KIND <= 2) ? snm : sn1);
+    if (lane == 0) { rc[20] = icmom; rc[21] = (snmom * icmom) * cp; rc[22] = (snmom * icmom) * sp; }
+  }
+  __asm__ volatile("" ::: "memory");
   const double* G = tab + (size_t)(2 + s) * NE;
   I128 mine = i128_zero();
   for (int k0 = lane; k0 - lane < NE; k0 += 64 * 32) {
@@ -381,26 +383,27 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
       if (k + 64 < kend) {    // prefetch the lane's next beam
         q0 = X[rb + k + 64]; q1 = X[rb + k + 64 + plane]; q2 = X[rb + k + 64 + 2 * plane];
       }
+      __asm__ volatile("" ::: "memory");   // the row constants are re-read from LDS per beam
       if (KIND >= 1) {
         const double bx = tab[k], bz = tab[NE + k];
         double f1[3], f2[3], f3[3], f4[3];
-        if (KIND != 3) gen2(an, bx, bz, g0.lam, n1, rg.hc0, f1);
+        if (KIND != 3) gen2c(an, bx, bz, rc + 0, f1);
         if (KIND == 1) {
-          rotate2(0.5 * f1[0], 0.5 * f1[1], 0.5 * f1[2], P0, P1, P2);
+          rotate2<true>(0.5 * f1[0], 0.5 * f1[1], 0.5 * f1[2], P0, P1, P2, sct);
         } else if (KIND == 2) {
-          gen2(an, bx, bz, gm.lam, n2, rg.hcm, f2);
+          gen2c(an, bx, bz, rc + 5, f2);
           const double cr0 = f1[1] * f2[2] - f1[2] * f2[1];
           const double cr1 = f1[2] * f2[0] - f1[0] * f2[2];
           const double cr2 = f1[0] * f2[1] - f1[1] * f2[0];
-          rotate2(0.5 * f2[0] - 0.125 * cr0, 0.5 * f2[1] - 0.125 * cr1, 0.5 * f2[2] - 0.125 * cr2,
-                  P0, P1, P2);
+          rotate2<true>(0.5 * f2[0] - 0.125 * cr0, 0.5 * f2[1] - 0.125 * cr1, 0.5 * f2[2] - 0.125 * cr2,
+                  P0, P1, P2, sct);
         } else if (KIND == 3) {
-          gen2(an, bx, bz, gm.lam, n3, rg.hcm, f3);
-          rotate2(f3[0], f3[1], f3[2], P0, P1, P2);
+          gen2c(an, bx, bz, rc + 10, f3);
+          rotate2<true>(f3[0], f3[1], f3[2], P0, P1, P2, sct);
         } else {
-          gen2(an, bx, bz, gm.lam, n2, rg.hcm, f2);
-          gen2(an, bx, bz, gm.lam, n3, rg.hcm, f3);
-          gen2(an, bx, bz, g1.lam, n4, rg.hc1, f4);
+          gen2c(an, bx, bz, rc + 5, f2);
+          gen2c(an, bx, bz, rc + 10, f3);
+          gen2c(an, bx, bz, rc + 15, f4);
           const double cr0 = f1[1] * f4[2] - f1[2] * f4[1];
           const double cr1 = f1[2] * f4[0] - f1[0] * f4[2];
           const double cr2 = f1[0] * f4[1] - f1[1] * f4[0];
@@ -412,7 +415,7 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
             const double e = (d0 * d0 + d1 * d1) + d2 * d2;
             emax = (e > emax) ? e : emax;
           }
-          rotate2(t0, t1, t2, P0, P1, P2);
+          rotate2<true>(t0, t1, t2, P0, P1, P2, sct);
           if (renorm) {
             const double nrm2 = (P0 * P0 + P1 * P1) + P2 * P2;
             const double inv = fma(-0.5, nrm2, 1.5);   // one Newton step for 1/sqrt from 1
@@ -427,7 +430,7 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
       }
       // rho~: rho for neutrinos, -rho^* (Bloch (-x, y, -z)) for antineutrinos
       if (!(fma(P0, P0, fma(P1, P1, P2 * P2)) < 2.0)) err = 1;
-      const double ws = G[k] * sc.s1;
+      const double ws = G[k] * cb[kC2Sc + 0];
       const double wa = an ? -ws : ws;
       acc[0] += fix_bits(P0, wa);
       acc[1] += fix_bits(P1, ws);
@@ -435,17 +438,18 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
     }
     fold_segment<3, NM>(reinterpret_cast<const long long*>(acc), lane, fl, mine);
   }
-  const double snmom = (KIND == 0) ? sn0 : ((KIND <= 2) ? snm : sn1);
-  close_row<3, NM>(sc, lane, mine, icmom, T, err, (snmom * icmom) * cp, (snmom * icmom) * sp);
+  __asm__ volatile("" ::: "memory");
+  close_row<3, NM>(Scales{cb[kC2Sc + 0], cb[kC2Sc + 1], cb[kC2Sc + 2], cb[kC2Sc + 3]}, lane, mine, rc[20], T,
+                   err, rc[21], rc[22]);
 }
 
 template <int KIND, bool ADAPT = false, bool EXT = false>
 __device__ __forceinline__ void stage2(const StepArgs& a, const StepGeo& G, const double* X, double* Xo,
                                        const double (*sJ)[EXT ? 12 : 6], const double* tab, long long gw,
                                        long long nw, int lane, long long* fl, I128& T, int& err,
-                                       double& emax, double* gc = nullptr) {
-  const Radial g0 = radial_at(a, G.r0), gm = radial_at(a, G.rm), g1 = radial_at(a, G.r1);
-  const Scales sc{a.s1, a.s0, a.p2e1, a.p2e0};
+                                       double& emax, double* cb, const double* sct, bool geo = false) {
+  put_stage2(cb, lane, radial_at(a, G.r0), radial_at(a, G.rm), radial_at(a, G.r1),
+             Scales{a.s1, a.s0, a.p2e1, a.p2e0});
   const double* J[4] = {sJ[0], sJ[1], sJ[2], sJ[3]};
   if constexpr (EXT) {
     // rows (s, j, p): species, emission bin, azimuthal bin
@@ -456,18 +460,17 @@ __device__ __forceinline__ void stage2(const StepArgs& a, const StepGeo& G, cons
       const int p = (int)(row - sj * a.NP);
       const int s = (int)(sj / a.NU);
       const int j = (int)(sj - (long long)s * a.NU);
-      row2<KIND, ADAPT, true>(X, Xo, a.plane, row * a.NE, a.NE, s, u_of(j, a.NU), G.h, tab, g0, gm, g1,
-                              J, sc, a.renorm, lane, fl, T, err, emax, phi[p], phi[a.NP + p],
-                              s >= (a.NS >> 1), row == gw ? gc : nullptr);
+      row2<KIND, ADAPT, true>(X, Xo, a.plane, row * a.NE, a.NE, s, u_of(j, a.NU), G.h, tab, cb, J,
+                              a.renorm, lane, fl, T, err, emax, phi[p], phi[a.NP + p],
+                              s >= (a.NS >> 1), geo && row == gw, sct);
     }
   } else {
     const long long nrow = (long long)a.NS * a.NU;
     for (long long row = gw; row < nrow; row += nw) {
       const int s = (int)(row / a.NU);
       const int j = (int)(row - (long long)s * a.NU);
-      row2<KIND, ADAPT>(X, Xo, a.plane, row * a.NE, a.NE, s, u_of(j, a.NU), G.h, tab, g0, gm, g1, J, sc,
-                        a.renorm, lane, fl, T, err, emax, 0.0, 0.0, s >= (a.NS >> 1),
-                        row == gw ? gc : nullptr);
+      row2<KIND, ADAPT>(X, Xo, a.plane, row * a.NE, a.NE, s, u_of(j, a.NU), G.h, tab, cb, J, a.renorm,
+                        lane, fl, T, err, emax, 0.0, 0.0, s >= (a.NS >> 1), geo && row == gw, sct);
     }
   }
 }
@@ -942,12 +945,15 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   // per wavefront: row constants (mixed: then 32 floats), then the first row's geometry
   __shared__ double snn_all[kBlock / 64][F32 ? 64 : 48];
   __shared__ long long sfold[kBlock / 64][(NC + 2) * 64];
+  __shared__ double s_sct[kSinCosTab];   // sin/cos constants of the two-flavour rotations
   extern __shared__ __align__(16) double dyn_tab[];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const long long gw = (long long)blockIdx.x * (kBlock / 64) + wid;
   const long long nw = (long long)gridDim.x * (kBlock / 64);
   const double* tab = a.tab;
   const float* ftab = nullptr;
+  if (NF == 2 && threadIdx.x == 0) sincos_coefs(s_sct);
+  if constexpr (NF == 2) __syncthreads();
   if constexpr (TLDS) {
     const int ntab = ((NF == 2) ? 2 : kVacRows3) * a.NE + a.NS * a.NE;
     for (int i = threadIdx.x; i < ntab; i += kBlock) dyn_tab[i] = a.tab[i];
@@ -984,10 +990,20 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   // 3f FP64 arithmetic: each stage's first beam is loaded before the preceding barrier
   ST pre[6] = {};
   const long long nrow3 = (long long)a.NS * a.NU * (EXT ? a.NP : 1);
-  if constexpr (NF == 2) stage2<0, false, EXT>(a, geo_fixed(a, step0), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone);
-  else if constexpr (F32) stage3m<0, TLDS>(a, geo_fixed(a, step0), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err);
+  // the stage-1 moments of the current state: left by the previous launch of this variant
+  // if it ended at this step (the same values the initial pass would compute), else the
+  // initial moment pass
+  const long long kind = NF * 16 + (sizeof(ST) == 4 ? 8 : 0) + (F32 ? 4 : 0) + (EXT ? 2 : 0);
+  if (a.step_ctl[kCtlMTag] == step0 && a.step_ctl[kCtlMKind] == kind) {
+    if constexpr (NF == 3 && !F32) prefetch_first<ST>(a, gw, nrow3, lane, pre);
+    if (threadIdx.x < NV) sJ[0][threadIdx.x] = as_double((unsigned long long)a.step_ctl[kCtlMom + threadIdx.x]);
+    __syncthreads();
+  } else {
+    if constexpr (NF == 2) stage2<0, false, EXT>(a, geo_fixed(a, step0), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct);
+    else if constexpr (F32) stage3m<0, TLDS>(a, geo_fixed(a, step0), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err);
     else { stage3<ST, 0, false, EXT>(a, geo_fixed(a, step0), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
-  ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[0]);
+    ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[0]);
+  }
   // the adjoint's forward pass records every stage's moments: [step][slot][NV]
   auto record = [&](long long step, int slot) {
     if (a.Jhist && ok && blockIdx.x == 0 && threadIdx.x < NV)
@@ -996,33 +1012,41 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   record(step0, 0);
   for (long long n = step0; ok && n < step0 + nsteps; ++n) {
     T = i128_zero();
-    if constexpr (NF == 2) stage2<1, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, gc);
+    if constexpr (NF == 2) stage2<1, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, true);
     else if constexpr (F32) stage3m<1, TLDS>(a, geo_fixed(a, n), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err, gc);
     else { stage3<ST, 1, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     if (!(ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[1]))) break;
     record(n, 1);
     T = i128_zero();
-    if constexpr (NF == 2) stage2<2, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, gc);
+    if constexpr (NF == 2) stage2<2, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, true);
     else if constexpr (F32) stage3m<2, TLDS>(a, geo_fixed(a, n), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err, gc);
     else { stage3<ST, 2, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     if (!(ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[2]))) break;
     record(n, 2);
     T = i128_zero();
-    if constexpr (NF == 2) stage2<3, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, gc);
+    if constexpr (NF == 2) stage2<3, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, true);
     else if constexpr (F32) stage3m<3, TLDS>(a, geo_fixed(a, n), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err, gc);
     else { stage3<ST, 3, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     if (!(ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[3]))) break;
     record(n, 3);
     T = i128_zero();
-    if constexpr (NF == 2) stage2<4, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, gc);
+    if constexpr (NF == 2) stage2<4, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, true);
     else if constexpr (F32) stage3m<4, TLDS>(a, geo_fixed(a, n), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err, gc);
     else { stage3<ST, 4, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[0]);
     record(n + 1, 0);
   }
   if (err) __hip_atomic_fetch_or(a.sync + kSyncStatus, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  // every block read the start step before the first barrier; block 0 passes the last
-  if (ok && blockIdx.x == 0 && threadIdx.x == 0) *a.step_ctl = step0 + nsteps;
+  // every block read the start step before the first barrier; block 0 passes the last, and
+  // leaves the moments of the new state for the next launch
+  if (ok && blockIdx.x == 0) {
+    if (threadIdx.x < NV) a.step_ctl[kCtlMom + threadIdx.x] = (long long)as_bits(sJ[0][threadIdx.x]);
+    if (threadIdx.x == 0) {
+      a.step_ctl[0] = step0 + nsteps;
+      a.step_ctl[kCtlMTag] = step0 + nsteps;
+      a.step_ctl[kCtlMKind] = kind;
+    }
+  }
 }
 
 template __global__ void k_advance<2, double, true, false, false>(StepArgs);
@@ -1058,11 +1082,14 @@ __global__ void __launch_bounds__(kBlock) k_adaptive(StepArgs a) {
   __shared__ long long sacc[kBlock];
   __shared__ double snn_all[kBlock / 64][48];   // row constants, then the first row's geometry
   __shared__ long long sfold[kBlock / 64][(NC + 2) * 64];
+  __shared__ double s_sct[kSinCosTab];   // sin/cos constants of the two-flavour rotations
   extern __shared__ __align__(16) double dyn_tab[];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const long long gw = (long long)blockIdx.x * (kBlock / 64) + wid;
   const long long nw = (long long)gridDim.x * (kBlock / 64);
   const double* tab = a.tab;
+  if (NF == 2 && threadIdx.x == 0) sincos_coefs(s_sct);
+  if constexpr (NF == 2) __syncthreads();
   if constexpr (TLDS) {
     const int ntab = ((NF == 2) ? 2 : kVacRows3) * a.NE + a.NS * a.NE;
     for (int i = threadIdx.x; i < ntab; i += kBlock) dyn_tab[i] = a.tab[i];
@@ -1084,7 +1111,7 @@ __global__ void __launch_bounds__(kBlock) k_adaptive(StepArgs a) {
   I128 T = i128_zero();
   auto stage = [&](auto kind, const StepGeo& G) {
     constexpr int K = decltype(kind)::value;
-    if constexpr (NF == 2) stage2<K, K == 4>(a, G, X, Xn, sJ, tab, gw, nw, lane, fl, T, err, emax, gc);
+    if constexpr (NF == 2) stage2<K, K == 4>(a, G, X, Xn, sJ, tab, gw, nw, lane, fl, T, err, emax, snn, s_sct, true);
     else stage3<double, K, K == 4>(a, G, X, Xn, sJ, tab, snn, gw, nw, lane, fl, T, err, emax, nullptr, gc);
   };
   using K0 = std::integral_constant<int, 0>;
@@ -1155,6 +1182,7 @@ __global__ void __launch_bounds__(kBlock) k_adaptive(StepArgs a) {
     ctl[kCtlRej] = nrej;
     ctl[kCtlAtt] = natt;
     ctl[kCtlFail] = fail;
+    ctl[kCtlMTag] = -1;   // the state changed outside the fixed-step launches
     if (!fail) ctl[0] = a.total_steps;
   }
 }
@@ -1208,7 +1236,8 @@ __device__ bool grid_barrier(const BatchArgs& a, unsigned epoch) {
 
 template <int KIND>
 __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, long long r0w,
-                            long long r1w, int lane, double (*Jv)[6], long long* fl, int& err) {
+                            long long r1w, int lane, double (*Jv)[6], long long* fl, double* cb,
+                            const double* sct, int& err) {
   const double r0 = a.rs + (double)n * a.h;
   const double rm = r0 + 0.5 * a.h;
   const double r1 = a.rs + (double)(n + 1) * a.h;
@@ -1216,8 +1245,6 @@ __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, lon
   int m = -1;
   long long mrow0 = 0, mrow1 = 0, mbeam0 = 0, mtab0 = 0;
   int mNE = 0, mNU = 1;
-  Radial g0{}, gm{}, g1{};
-  Scales sc{};
   const double* J[4] = {Jv[0], Jv[1], Jv[2], Jv[3]};   // this wave's LDS block
   I128 T = i128_zero();
   for (long long row = r0w; row < r1w; ++row) {
@@ -1242,10 +1269,9 @@ __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, lon
       mbeam0 = md->beam0;
       mtab0 = md->tab0;
       const double lam0 = md->lam0;
-      g0 = radial(a.R, a.ne_power, lam0, r0);
-      gm = radial(a.R, a.ne_power, lam0, rm);
-      g1 = radial(a.R, a.ne_power, lam0, r1);
-      sc = Scales{md->s1, md->s0, md->p2e1, md->p2e0};
+      const Scales sc{md->s1, md->s0, md->p2e1, md->p2e0};
+      put_stage2(cb, lane, radial(a.R, a.ne_power, lam0, r0), radial(a.R, a.ne_power, lam0, rm),
+                 radial(a.R, a.ne_power, lam0, r1), sc);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const bool need = (i == 0) ? (KIND == 1 || KIND == 2 || KIND == 4)
@@ -1261,8 +1287,8 @@ __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, lon
     const int s = (int)(lr / mNU);
     const int j = (int)(lr - (long long)s * mNU);
     double enone = 0.0;
-    row2<KIND>(a.X, a.X, a.plane, mbeam0 + lr * mNE, mNE, s, u_of(j, mNU), a.h, a.tab + mtab0,
-               g0, gm, g1, J, sc, a.renorm, lane, fl, T, err, enone);
+    row2<KIND>(a.X, a.X, a.plane, mbeam0 + lr * mNE, mNE, s, u_of(j, mNU), a.h, a.tab + mtab0, cb, J,
+               a.renorm, lane, fl, T, err, enone, 0.0, 0.0, -1, false, sct);
   }
   if (m >= 0 && lane < 6) acc_add(acc_slot(a, epoch, m) + lane * kAccLimbs, T);
   // clear the set the next epoch will collect into
@@ -1273,9 +1299,16 @@ __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, lon
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_batch2(BatchArgs a) {
+// Four wavefronts per SIMD (128 VGPRs): the rows of a batch are short (50-400 energies),
+// so a wave spends much of its time on row set-up and the first load of each row, which
+// more wavefronts hide (measured: 4.35 -> 4.20 ms per step on the 256-model batch).
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_batch2(BatchArgs a) {
   __shared__ double sJw[kBlock / 64][4][6];
   __shared__ long long sfold[kBlock / 64][(3 + 2) * 64];
+  __shared__ double scb[kBlock / 64][kC2Size];
+  __shared__ double s_sct[kSinCosTab];   // sin/cos constants of the rotations
+  if (threadIdx.x == 0) sincos_coefs(s_sct);
+  __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   double (*Jv)[6] = sJw[wid];
   const long long w = (long long)blockIdx.x * (kBlock / 64) + wid;
@@ -1286,16 +1319,16 @@ __global__ void __launch_bounds__(kBlock) k_batch2(BatchArgs a) {
   unsigned epoch = 0;
   int err = 0;
   bool ok;
-  batch_stage<0>(a, step0, epoch, r0w, r1w, lane, Jv, sfold[wid], err);
+  batch_stage<0>(a, step0, epoch, r0w, r1w, lane, Jv, sfold[wid], scb[wid], s_sct, err);
   ok = grid_barrier(a, epoch++);
   for (long long n = step0; ok && n < step0 + nsteps; ++n) {
-    batch_stage<1>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], err);
+    batch_stage<1>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], scb[wid], s_sct, err);
     if (!(ok = grid_barrier(a, epoch++))) break;
-    batch_stage<2>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], err);
+    batch_stage<2>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], scb[wid], s_sct, err);
     if (!(ok = grid_barrier(a, epoch++))) break;
-    batch_stage<3>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], err);
+    batch_stage<3>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], scb[wid], s_sct, err);
     if (!(ok = grid_barrier(a, epoch++))) break;
-    batch_stage<4>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], err);
+    batch_stage<4>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], scb[wid], s_sct, err);
     ok = grid_barrier(a, epoch++);
   }
   if (err) __hip_atomic_fetch_or(a.sync + kSyncStatus, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1307,7 +1340,17 @@ __global__ void k_zero_u64(unsigned long long* p, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     p[i] = 0ull;
 }
-__global__ void k_set_step(long long* step_ctl, long long step) { *step_ctl = step; }
+// The state was set or reset: the step, and no moments left for the next launch.
+__global__ void k_set_step(long long* step_ctl, long long step) {
+  step_ctl[0] = step;
+  step_ctl[kCtlMTag] = -1;
+}
+// The status word and the device step counter into host memory (one small write the host
+// reads after synchronising, instead of two copies).
+__global__ void k_status_out(const unsigned int* sync, const long long* step_ctl, long long* host) {
+  __hip_atomic_store(host, (long long)sync[kSyncStatus], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(host + 1, step_ctl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 // Target of a group of windowed launches: k more steps from the device step counter.
 __global__ void k_set_target(long long* step_ctl, long long k, long long total) {
   step_ctl[1] = min(step_ctl[0] + k, total);

@@ -176,10 +176,14 @@ def test_adjoint_200k_full_run_against_central_differences(nb):
     At x +- 1e-6 |x| every gradient must agree to 1e-6 except where the difference quotient
     itself is limited by the rounding of the forward runs: the loss (about 50) carries a
     rounding of a few 1e-15 whatever the parameter (measured: 4e-15), against a change
-    2h dL/dx of 8e-11 for L_x (x dL/dx = -4e-5), a floor of 5e-5 relative; there the bar at
-    h = 1e-6 is 1e-4.  At x +- 1e-4 |x| that floor drops a hundredfold while the truncation
-    error of the central difference (h^2/6 of the third derivative, about 1e-9 relative)
-    stays far below 1e-6: there every gradient must agree to 1e-6."""
+    2h dL/dx of 8e-11 for L_x (x dL/dx = -4e-5), a floor of 5e-5 relative.  Where that floor
+    exceeds 5e-7 the quotient at h = 1e-6 must stay within twice it, and the gradient must
+    agree to 1e-6 with the quotient at x +- 1e-4 |x|, where the floor is a hundred times
+    lower and the truncation error (h^2/6 of the third derivative) of a luminosity, on
+    which the loss depends smoothly this far out, stays near 1e-9 relative.  (theta_v is not
+    such a parameter: the loss oscillates in it, and at 1e-4 the truncation error is 8e-5;
+    at 1e-6 its quotient agrees to 2e-9.)
+    """
     import math
     d = workloads.adjoint_200k_resolved()
     m = nb.Model(d, adjoint_ckpt=64)
@@ -205,8 +209,34 @@ def test_adjoint_200k_full_run_against_central_differences(nb):
         _say(f"200k full run: dL/d{nb.PARAM_NAMES[i]} adjoint {g[i]:.10e} central(1e-6) {f6:.10e} "
              f"rel {r6:.2e}; central(1e-4) {f4:.10e} rel {r4:.2e}")
         floor = 4e-15 / (2e-6 * abs(x0[i] * g[i]))     # loss rounding over 2h dL/dx
-        assert r6 <= max(1e-6, 2.0 * floor), (nb.PARAM_NAMES[i], g[i], f6, floor)
-        assert r4 <= 1e-6, (nb.PARAM_NAMES[i], g[i], f4)
+        if floor <= 5e-7:
+            assert r6 <= 1e-6, (nb.PARAM_NAMES[i], g[i], f6, floor)
+        else:
+            assert r6 <= 2.0 * floor, (nb.PARAM_NAMES[i], g[i], f6, floor)
+            assert r4 <= 1e-6, (nb.PARAM_NAMES[i], g[i], f4)
+
+
+def test_adjoint_beyond_four_beams_per_thread(nb, oracle):
+    """1.1M beams (500 E x 1100 u x 2), more than four per resident thread of the reverse
+    kernel: its spill variant keeps the beams' adjoint registers in the workspace between
+    phases.  Against the oracle adjoint, 6 steps with checkpoints every 4 (a full and a
+    short segment), the 200k workload's step length from 500 km, random cotangent."""
+    import torch
+    d = workloads.adjoint_200k_resolved()
+    h = (d["r_end_km"] - d["r_start_km"]) / d["n_steps"]
+    d = dict(d, n_energy=500, n_u=1100, n_steps=6, r_end_km=d["r_start_km"] + 6 * h)
+    _say("adjoint 1.1M beams: oracle")
+    o = oracle.Model(d)
+    c = _cot(o.nb, 17)
+    _, go, sbo = o.adjoint(4, c, want_state_bar=True)
+    _say("adjoint 1.1M beams: gpu")
+    m = nb.Model(d, adjoint_ckpt=4)
+    g, sb = m.adjoint(torch.as_tensor(c, device="cuda"), want_state_bar=True)
+    _say(f"grad gpu {g} oracle {go}")
+    np.testing.assert_allclose(g, go, rtol=RTOL, atol=0)
+    sb = sb.cpu().numpy()
+    np.testing.assert_allclose(sb, sbo, rtol=RTOL, atol=RTOL * np.abs(sbo).max())
+    np.testing.assert_array_equal(m.pee().cpu().numpy(), o.pee().reshape(-1))
 
 
 def test_adjoint_200k_prefix(nb, oracle):
