@@ -356,6 +356,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint and mixed-precision measurements")
     ap.add_argument("--mixed-literal-steps", type=int, default=2000)
+    ap.add_argument("--section", choices=["batch", "extended", "adjoint", "track_all"],
+                    help="run only this measurement and print its result (for profiling "
+                         "runs; no benchmark line)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this stepper runs on one GPU only (no multi-GPU path is built); "
@@ -368,6 +371,17 @@ def main():
 
     assert torch.cuda.is_available(), "no HIP device"
     torch.cuda.set_device(0)
+    if args.section:
+        fn = {"batch": lambda: batch_timing(nb, workloads, 40),
+              "extended": lambda: extended_timing(nb, workloads),
+              "adjoint": lambda: adjoint_timing(nb, workloads),
+              "track_all": lambda: track_all_timing(nb, workloads)}[args.section]
+        res = fn()
+        gc.collect()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        print(json.dumps({args.section: res}), flush=True)
+        return
     d = workloads.three_flavor_800k()
     K, W = args.steps, args.warmup
     if K + W > d["n_steps"]:
