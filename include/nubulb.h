@@ -47,9 +47,13 @@ enum {
   NB_EUNBOUND = -2,    /* no workspace bound yet */
   NB_EWORKSPACE = -3,  /* workspace too small or misaligned (256 B) */
   NB_EHIP = -4,        /* a HIP runtime call failed (no device, launch failure, ...) */
-  NB_ENUMERIC = -5,    /* a moment contribution left the fixed-point range (NaN/overflow) */
-  NB_ETIMEOUT = -6,    /* a grid barrier did not complete within its time limit */
-  NB_ESTEP = -7        /* adaptive step control failed (step length underflow or attempt limit) */
+  NB_ENUMERIC = -5,    /* a moment contribution left the fixed-point range (NaN/overflow), or
+                          a renormalised state had |psi|^2 (|P|^2) off 1 by more than 1e-8
+                          (FP32 states: 1e-5) before the renormalisation */
+  NB_ETIMEOUT = -6,    /* a grid barrier did not complete within its time limit (20 s), or the
+                          host cancelled the model's launches (nb_cancel) */
+  NB_ESTEP = -7,       /* adaptive step control failed (step length underflow or attempt limit) */
+  NB_EIO = -8          /* the autotuner's cache file could not be read, parsed or written */
 };
 
 enum { NB_FP64 = 0, NB_FP32_STATE = 1 };
@@ -107,14 +111,28 @@ int32_t nb_state_comps(const nb_model *m);  /* 3 (2f Bloch vector) or 6 (3f wave
 int nb_pee_offsets(const nb_model *m, int64_t *off);
 /* Bytes of device workspace the model needs (256-byte aligned start required). */
 size_t nb_workspace_bytes(const nb_model *m);
-/* Bind caller-owned device memory and a HIP stream (hipStream_t, may be NULL), upload
- * the tables on that stream and reset the state (as nb_reset). */
+/* Bind caller-owned device memory and a HIP stream (hipStream_t, may be NULL) on the
+ * current device: measure the resident capacity of the stepping kernels there, upload the
+ * tables of Sec. 3.2 (energy bins, emission weights of Eqs. Hnu and F, vacuum
+ * Hamiltonians of Sec. 2) on that stream and reset the state (as nb_reset).  A model may be
+ * bound again (another workspace or stream); that drops its graph.  NB_EWORKSPACE if
+ * bytes < nb_workspace_bytes or dev_ws is not 256-byte aligned. */
 int nb_bind(nb_model *m, void *dev_ws, size_t bytes, void *hip_stream);
 /* Every beam back to its initial flavour eigenstate at r_start (Sec. 3.4); step = 0. */
 int nb_reset(nb_model *m);
-/* Advance n radial steps (bounded by n_steps - current step). */
+/* Advance n radial steps of the fixed grid r_k = r_start + k (r_end - r_start)/n_steps
+ * (bounded by n_steps - current step): each step is the RKMK4 step of Eq. U with the
+ * Hamiltonian of Eq. eom rebuilt at every stage from the moments of Eqs. Hnu and F (see
+ * the preamble).  One persistent cooperative launch per chunk of steps (so that the barrier
+ * epochs of a launch stay within 32 bits); returns after the stream has drained and the
+ * kernels' status word was checked.  NB_ENUMERIC: a moment contribution left its
+ * fixed-point range (NaN or overflow), or a state's norm was off 1 by more than a unitary
+ * step's rounding explains (renorm = 1); NB_ETIMEOUT: a grid
+ * barrier timed out or the model was cancelled -- in both cases the state is undefined
+ * until nb_reset or nb_set_state, except after a cancel that took effect before the launch
+ * started, which leaves state and step as they were. */
 int nb_step(nb_model *m, int64_t n);
-/* Advance to r_end_km. */
+/* Advance to r_end_km (nb_step of the remaining steps). */
 int nb_run(nb_model *m);
 int64_t nb_step_index(const nb_model *m);
 /* For callers that cannot allocate device memory or use the workspace's scratch (code
@@ -133,7 +151,9 @@ int nb_step_static(nb_model *m, int64_t n);
  * caller's device array dev_out[nb_n_beams]. */
 int nb_read_pee(const nb_model *m, double *dev_out);
 /* State exchange as FP64 planes [comp][beam] (2f: P_x, P_y, P_z; 3f: Re/Im psi_e,
- * psi_mu, psi_tau).  on_device: 1 if dst/src is device memory, 0 if host memory. */
+ * psi_mu, psi_tau).  on_device: 1 if dst/src is device memory, 0 if host memory (pageable
+ * or pinned; FP32 states are converted on the host).  Allocates no device memory.
+ * nb_set_state also sets the step index (0 <= step <= n_steps). */
 int nb_get_state(const nb_model *m, double *dst, int on_device);
 int nb_set_state(nb_model *m, const double *src, int64_t step, int on_device);
 
@@ -149,17 +169,56 @@ int64_t nb_mixed_fp32_step(const nb_model *m);
  * device step counter" (n_steps >= 1) on the bound stream (which must not be the NULL
  * stream) into a graph held by the model; nb_graph_launch replays it and checks the
  * status word.  Every replay continues from where the previous one stopped and stops at
- * r_end.  Rebinding, autotuning or destroying the model drops the graph.  Inside the graph
- * the stepping kernel is an ordinary launch whose grid never exceeds the resident
- * capacity measured at nb_bind. */
+ * r_end.  Rebinding, changing the launch shape (nb_autotune, nb_set_tuning) or destroying
+ * the model drops the graph.  Inside the graph the stepping kernel is an ordinary launch,
+ * which makes progress only while all its blocks are resident at once: nb_graph_launch
+ * refuses (NB_EINVAL) a recorded grid above the resident capacity the device reports at
+ * the time of the launch, and work that other streams run meanwhile can still stall it --
+ * the barrier waits then end at their 20 s limit or at nb_cancel with NB_ETIMEOUT. */
 int nb_graph_capture(nb_model *m, int64_t n_steps);
 int nb_graph_launch(nb_model *m);
 
-/* Autotuner: for each candidate launch shape (block count; for batches also the per-row
- * overhead of the cost model that splits the rows among wavefronts) time trial_steps from
- * the initial state with HIP events, keep the fastest, then reset the model.  *best_ms
- * (may be NULL) receives the winning time.  Results never change the arithmetic. */
-int nb_autotune(nb_model *m, int32_t trial_steps, double *best_ms);
+/* Cancel: while on != 0, every persistent launch of the model (stepping, graph replays,
+ * adaptive, adjoint) that starts returns at once without touching the state, and one that
+ * is waiting in a grid barrier gives up within about a millisecond; both end in
+ * NB_ETIMEOUT ("cancelled by the host").  on = 0 lets launches run again.  The flag is a
+ * word of fine-grained pinned host memory: this call may come from any host thread at any
+ * time, including while another thread is inside nb_step or nb_graph_launch of the model.
+ * Requires a bound model. */
+int nb_cancel(nb_model *m, int32_t on);
+
+/* Launch shape of the fixed-step kernels (single models and batches; the adaptive and
+ * adjoint kernels keep their own).  A beam's arithmetic does not depend on it, and the
+ * moments are exact integer sums, so every shape gives the same bits. */
+typedef struct {
+  int32_t block_threads;  /* threads per block: 512 (8 wavefronts) or 256 (4) */
+  int32_t blocks;         /* block cap of a launch (nb_set_tuning: 0 = the resident capacity);
+                             a launch uses at most one wavefront per row */
+  double row_cost;        /* batches: per-row overhead, in 64-lane chunks, of the cost model
+                             that splits the rows among wavefronts (default 1) */
+  double ms;              /* nb_autotune: time of the winning trial (on a cache hit: as stored) */
+  int32_t from_cache;     /* nb_autotune: 1 if the shape came from the cache file */
+  int32_t candidates;     /* nb_autotune: launch shapes timed (0 on a cache hit) */
+} nb_tuning;
+
+/* Autotuner.  With cache_path (a JSON file; NULL or "": no cache) it first looks up the
+ * key of this device and shape -- architecture, CU count, flavours, N_E, N_u, azimuthal
+ * bins, species rows, precision, max_blocks, and for batches the model count, rows, beams
+ * and a hash of every member's (N_E, N_u) -- and applies a stored shape without timing
+ * anything.  Otherwise it times trial_steps steps from the initial state (best of two,
+ * HIP events) for every candidate: 512 and 256 threads per block, each at the full
+ * resident grid, 3/4 and 1/2 of it, and for batches row costs 0.25, 1 and 3; keeps the
+ * fastest and adds it to the cache (written to a temporary file, then renamed over it).
+ * The model is then reset to step 0.  *out (may be NULL) receives the shape.  NB_EIO if
+ * the cache cannot be read, is not such a JSON object, or cannot be written (a malformed
+ * file is left as it is); not capturable. */
+int nb_autotune(nb_model *m, int32_t trial_steps, const char *cache_path, nb_tuning *out);
+/* Apply a launch shape (block_threads, blocks, row_cost; the other fields are ignored).
+ * NB_EINVAL if the stepping kernels cannot be resident at that block size or blocks
+ * exceeds the resident capacity.  Keeps the state and the step index. */
+int nb_set_tuning(nb_model *m, const nb_tuning *t);
+/* The shape in use: block_threads, blocks of a launch, row_cost; other fields zero. */
+int nb_get_tuning(const nb_model *m, nb_tuning *t);
 
 /* Reverse-mode adjoint of the radial integration (2 flavours, FP64, single model created
  * with adjoint_ckpt > 0).  The gradients are those of the final survival probabilities
@@ -209,16 +268,6 @@ int nb_run_adaptive(nb_model *m, double tol, double h_max_km, int64_t max_attemp
 int nb_host_tables(const nb_model *m, double *out, int64_t cap);
 
 const char *nb_last_error(void);
-
-/* ---- test hooks: the arithmetic primitives of the stepper, one element per thread ----
- * dev_* are device arrays of n elements (n * 9 for k9, n * 6 for psi6, n * 3 for x3/p3). */
-int nb_test_sincos(const double *dev_x, int64_t n, double *dev_s, double *dev_c, void *stream);
-int nb_test_sqrt_div(const double *dev_a, const double *dev_b, int64_t n, double *dev_sqrt,
-                     double *dev_div, void *stream);
-int nb_test_exp3(const double *dev_k9, const double *dev_psi6, int64_t n, double *dev_out6,
-                 void *stream);
-int nb_test_rotate(const double *dev_x3, const double *dev_p3, int64_t n, double *dev_out3,
-                   void *stream);
 
 #ifdef __cplusplus
 }

@@ -13,17 +13,17 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnubulb.so")
 
-NB_OK, NB_EINVAL, NB_EUNBOUND, NB_EWORKSPACE, NB_EHIP, NB_ENUMERIC, NB_ETIMEOUT, NB_ESTEP = (
-    0, -1, -2, -3, -4, -5, -6, -7)
+NB_OK, NB_EINVAL, NB_EUNBOUND, NB_EWORKSPACE, NB_EHIP, NB_ENUMERIC, NB_ETIMEOUT, NB_ESTEP, NB_EIO = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
 NB_FP64, NB_FP32_STATE = 0, 1
 
 EXPORTS = [
     "nb_model_create", "nb_batch_create", "nb_model_destroy", "nb_n_beams", "nb_n_models",
     "nb_state_comps", "nb_pee_offsets", "nb_workspace_bytes", "nb_bind", "nb_reset",
     "nb_step", "nb_run", "nb_step_index", "nb_read_pee", "nb_get_state", "nb_set_state",
-    "nb_adjoint", "nb_host_tables", "nb_last_error", "nb_test_sincos", "nb_test_sqrt_div",
-    "nb_test_exp3", "nb_test_rotate", "nb_graph_capture", "nb_graph_launch", "nb_autotune",
-    "nb_mixed_fp32_step", "nb_run_adaptive", "nb_step_static",
+    "nb_adjoint", "nb_host_tables", "nb_last_error", "nb_graph_capture", "nb_graph_launch",
+    "nb_autotune", "nb_set_tuning", "nb_get_tuning", "nb_cancel", "nb_mixed_fp32_step",
+    "nb_run_adaptive", "nb_step_static",
 ]
 
 
@@ -45,6 +45,14 @@ class Params(C.Structure):
 class AdaptiveStats(C.Structure):
     _fields_ = [("accepted", C.c_int64), ("rejected", C.c_int64), ("attempts", C.c_int64),
                 ("h_last_km", C.c_double)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("block_threads", C.c_int32), ("blocks", C.c_int32), ("row_cost", C.c_double),
+                ("ms", C.c_double), ("from_cache", C.c_int32), ("candidates", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class NubulbError(RuntimeError):
@@ -90,13 +98,12 @@ def lib():
         L.nb_adjoint.argtypes = [vp, vp, dp, C.c_int32, vp]
         L.nb_host_tables.argtypes = [vp, dp, i64]
         L.nb_last_error.restype = C.c_char_p
-        L.nb_test_sincos.argtypes = [vp, i64, vp, vp, vp]
-        L.nb_test_sqrt_div.argtypes = [vp, vp, i64, vp, vp, vp]
-        L.nb_test_exp3.argtypes = [vp, vp, i64, vp, vp]
-        L.nb_test_rotate.argtypes = [vp, vp, i64, vp, vp]
         L.nb_graph_capture.argtypes = [vp, i64]
         L.nb_graph_launch.argtypes = [vp]
-        L.nb_autotune.argtypes = [vp, C.c_int32, dp]
+        L.nb_autotune.argtypes = [vp, C.c_int32, C.c_char_p, C.POINTER(Tuning)]
+        L.nb_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.nb_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.nb_cancel.argtypes = [vp, C.c_int32]
         L.nb_run_adaptive.argtypes = [vp, C.c_double, C.c_double, i64, C.POINTER(AdaptiveStats)]
         _lib = L
     return _lib
@@ -139,6 +146,10 @@ def _stream_ptr(stream=None):
     torch = _torch()
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
 
 
 class HostModel:
@@ -259,10 +270,40 @@ class Model(HostModel):
     def graph_launch(self):
         _check(lib().nb_graph_launch(self.h), "nb_graph_launch")
 
-    def autotune(self, trial_steps: int = 10) -> float:
-        best = C.c_double()
-        _check(lib().nb_autotune(self.h, int(trial_steps), C.byref(best)), "nb_autotune")
-        return float(best.value)
+    def autotune(self, trial_steps: int = 10, cache: str | None = None) -> dict:
+        """nb_autotune; returns the chosen shape (block_threads, blocks, row_cost, ms,
+        from_cache, candidates)."""
+        t = Tuning()
+        path = None if cache is None else os.fsencode(cache)
+        _check(lib().nb_autotune(self.h, int(trial_steps), path, C.byref(t)), "nb_autotune")
+        return t.as_dict()
+
+    def set_tuning(self, block_threads: int, blocks: int = 0, row_cost: float = 1.0):
+        t = Tuning(block_threads=int(block_threads), blocks=int(blocks), row_cost=float(row_cost))
+        _check(lib().nb_set_tuning(self.h, C.byref(t)), "nb_set_tuning")
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        _check(lib().nb_get_tuning(self.h, C.byref(t)), "nb_get_tuning")
+        return t.as_dict()
+
+    def cancel(self, on: bool = True):
+        """nb_cancel: make the model's launches give up (on) or run again (off)."""
+        _check(lib().nb_cancel(self.h, int(bool(on))), "nb_cancel")
+
+    def get_state_host(self):
+        """State planes [nsc][nb] as a float64 numpy array (host path of nb_get_state)."""
+        import numpy as np
+        out = np.empty((self.nsc, self.nb), np.float64)
+        _check(lib().nb_get_state(self.h, out.ctypes.data_as(C.c_void_p), 0), "nb_get_state")
+        return out
+
+    def set_state_host(self, x, step: int):
+        import numpy as np
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        assert x.size == self.nsc * self.nb
+        _check(lib().nb_set_state(self.h, x.ctypes.data_as(C.c_void_p), int(step), 0),
+               "nb_set_state")
 
     def set_state(self, x, step: int):
         torch = _torch()
@@ -332,40 +373,3 @@ def bulb_pee(x, d: dict, ckpt: int = 64):
     """Differentiable final P_ee (device tensor [nb]) of the two-flavour model d with its
     luminosities, theta_v and n0 replaced by the float64 tensor x (5 entries, CPU)."""
     return _bulb_fn().apply(x, d, ckpt)
-
-
-# ------------------------------------------------------------------ test hooks
-def _ptr(t):
-    return C.c_void_p(t.data_ptr())
-
-
-def test_sincos(x):
-    torch = _torch()
-    s = torch.empty_like(x); c = torch.empty_like(x)
-    _check(lib().nb_test_sincos(_ptr(x), x.numel(), _ptr(s), _ptr(c), _stream_ptr()),
-           "nb_test_sincos")
-    return s, c
-
-
-def test_sqrt_div(a, b):
-    torch = _torch()
-    sq = torch.empty_like(a); dv = torch.empty_like(a)
-    _check(lib().nb_test_sqrt_div(_ptr(a), _ptr(b), a.numel(), _ptr(sq), _ptr(dv),
-                                  _stream_ptr()), "nb_test_sqrt_div")
-    return sq, dv
-
-
-def test_exp3(k9, psi6):
-    torch = _torch()
-    out = torch.empty_like(psi6)
-    _check(lib().nb_test_exp3(_ptr(k9), _ptr(psi6), psi6.shape[0], _ptr(out), _stream_ptr()),
-           "nb_test_exp3")
-    return out
-
-
-def test_rotate(x3, p3):
-    torch = _torch()
-    out = torch.empty_like(p3)
-    _check(lib().nb_test_rotate(_ptr(x3), _ptr(p3), p3.shape[0], _ptr(out), _stream_ptr()),
-           "nb_test_rotate")
-    return out

@@ -1,4 +1,5 @@
-"""Build libnubulb.so (HIP, gfx950) in-tree with hipcc.
+"""Build libnubulb.so (the stepper) and libnubulb_testhooks.so (its arithmetic primitives,
+for tests) in-tree with hipcc for gfx950.
 
 Flags: -ffp-contract=off keeps the arithmetic specification (no implicit fma);
 -packed-fp32-ops is disabled for all device code.
@@ -15,6 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnubulb.so")
 SOURCES = ["nb_kernels.hip", "nb_adjoint.hip", "nb_api.hip"]
+HOOKS_LIB = os.path.join(HERE, "libnubulb_testhooks.so")
+HOOKS_SOURCES = ["nb_testhooks.hip"]
 ARCH = os.environ.get("NB_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
@@ -36,16 +39,22 @@ def _compile(src: str, bdir: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    bdir = os.path.join(HERE, "_build")
-    os.makedirs(bdir, exist_ok=True)
-    with ThreadPoolExecutor(len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, bdir, verbose), SOURCES))
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs]
+def _link(lib: str, objs: list, verbose: bool) -> None:
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", lib + ".tmp", *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(lib + ".tmp", lib)
+
+
+def build(verbose: bool = False) -> str:
+    bdir = os.path.join(HERE, "_build")
+    os.makedirs(bdir, exist_ok=True)
+    srcs = SOURCES + HOOKS_SOURCES
+    with ThreadPoolExecutor(len(srcs)) as ex:
+        objs = dict(zip(srcs, ex.map(lambda s: _compile(s, bdir, verbose), srcs)))
+    _link(LIB, [objs[s] for s in SOURCES], verbose)
+    _link(HOOKS_LIB, [objs[s] for s in HOOKS_SOURCES], verbose)
     return LIB
 
 

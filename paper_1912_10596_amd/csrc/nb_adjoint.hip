@@ -151,7 +151,7 @@ __device__ bool grid_sum(const AdjArgs& a, unsigned epoch, double (&v)[NV], doub
       for (unsigned it = 1;; ++it) {
         x = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if ((unsigned)(x >> 32) == want) break;
-        if ((it & 31u) == 0u && give_up(a.sync, t0, a.timeout_ticks)) {
+        if ((it & 31u) == 0u && give_up(a.sync, a.cancel, t0, a.timeout_ticks, it)) {
           ok = 0;
           break;
         }
@@ -193,7 +193,7 @@ __device__ bool grid_sum(const AdjArgs& a, unsigned epoch, double (&v)[NV], doub
 #pragma unroll
       for (int i = 0; i < kFly; ++i)
         if ((pend & (1u << i)) && (unsigned)(w[i] >> 32) == want) pend &= ~(1u << i);
-      if (pend && (it & 31u) == 0u && give_up(a.sync, t0, a.timeout_ticks)) ok = 0;
+      if (pend && (it & 31u) == 0u && give_up(a.sync, a.cancel, t0, a.timeout_ticks, it)) ok = 0;
       if (pend && ok) __builtin_amdgcn_s_sleep(1);
     }
     // the two threads of a pair share g, so they run the same iterations of this loop
@@ -496,6 +496,7 @@ __global__ void __launch_bounds__(kBlock) k_adjoint2(AdjArgs a) {
   __shared__ double sw[kBlock / 64][8];
   __shared__ double sred[kBlock];
   constexpr int NQ = BPT > 0 ? BPT : 1;
+  if (launch_aborted(a.sync)) return;
   const int tid = threadIdx.x;
   const long long nthr = (long long)gridDim.x * kBlock;
   const long long gt = (long long)blockIdx.x * kBlock + tid;

@@ -1,12 +1,17 @@
 // nb_api.hip -- host runtime behind include/nubulb.h: parameter validation, host tables,
-// workspace layout, cooperative launches, status checks and the test hooks.
+// workspace layout, cooperative launches, status checks, the autotuner and its cache.
 #include <hip/hip_runtime.h>
 
+#include <unistd.h>
+
 #include <algorithm>
+#include <cerrno>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -16,14 +21,15 @@
 #include "nb_internal.h"
 
 namespace nb {
-template <int NF, typename ST, bool TLDS, bool F32, bool EXT>
+template <int NF, typename ST, bool TLDS, bool F32, bool EXT, int BS>
 __global__ void k_advance(StepArgs a);
+template <int BS>
 __global__ void k_batch2(BatchArgs a);
 template <int BPT>
 __global__ void k_adjoint2(AdjArgs a);
 template <int NF, bool TLDS>
 __global__ void k_adaptive(StepArgs a);
-__global__ void k_zero_sync(unsigned int* sync, int keep_status);
+__global__ void k_zero_sync(unsigned int* sync, int keep_status, const unsigned* cancel);
 __global__ void k_zero_u64(unsigned long long* p, long long n);
 __global__ void k_set_step(long long* step_ctl, long long step);
 __global__ void k_status_out(const unsigned int* sync, const long long* step_ctl, long long* host);
@@ -34,10 +40,6 @@ template <typename ST>
 __global__ void k_read_pee(const ST* X, long long nb, long long plane, int nsc, double* out);
 template <typename ST>
 __global__ void k_state_xfer(ST* X, long long nb, long long plane, int nsc, double* buf, int dir);
-__global__ void k_test_sincos(const double* x, long long n, double* s, double* c);
-__global__ void k_test_sqrt_div(const double* a, const double* b, long long n, double* sq, double* dv);
-__global__ void k_test_exp3(const double* k9, const double* psi6, long long n, double* out6);
-__global__ void k_test_rotate(const double* x3, const double* p3, long long n, double* out3);
 }  // namespace nb
 
 using namespace nb;
@@ -60,6 +62,42 @@ static int fail(int code, const char* fmt, ...) {
   } while (0)
 
 extern "C" const char* nb_last_error(void) { return g_err.c_str(); }
+
+// --------------------------------------------------------------- cancel words
+// Every bound model owns one 32-bit word of fine-grained (coherent) pinned host memory:
+// nb_cancel writes it from any host thread, the sync-word clear before each persistent
+// launch reads it, and waiting blocks poll it.  Words come from pages allocated once per
+// process and never freed (a freed model's word is reused).
+constexpr int kCancelPage = 1024;
+static std::mutex g_cancel_mu;
+static std::vector<unsigned*> g_cancel_free;
+static int cancel_word_take(unsigned** host, const unsigned** dev) {
+  std::lock_guard<std::mutex> lock(g_cancel_mu);
+  if (g_cancel_free.empty()) {
+    void* page = nullptr;
+    NB_HIP(hipHostMalloc(&page, sizeof(unsigned) * kCancelPage,
+                         hipHostMallocPortable | hipHostMallocMapped | hipHostMallocCoherent));
+    unsigned* w = (unsigned*)page;
+    for (int i = kCancelPage - 1; i >= 0; --i) {
+      w[i] = 0u;
+      g_cancel_free.push_back(w + i);
+    }
+  }
+  unsigned* w = g_cancel_free.back();
+  void* d = nullptr;
+  NB_HIP(hipHostGetDevicePointer(&d, w, 0));
+  g_cancel_free.pop_back();
+  __atomic_store_n(w, 0u, __ATOMIC_SEQ_CST);
+  *host = w;
+  *dev = (const unsigned*)d;
+  return NB_OK;
+}
+static void cancel_word_give(unsigned* w) {
+  if (!w) return;
+  std::lock_guard<std::mutex> lock(g_cancel_mu);
+  __atomic_store_n(w, 0u, __ATOMIC_SEQ_CST);
+  g_cancel_free.push_back(w);
+}
 
 // --------------------------------------------------------------- constants
 // sqrt(2) G_F (hbar c)^3 in km^-1 cm^3 with G_F = 1.1663787e-5 GeV^-2 and
@@ -102,14 +140,20 @@ struct nb_model {
   std::vector<Sub> subs;
   std::vector<double> tab;           // concatenated device table image
   long long step = 0;
-  // tuning (autotuner results): block cap and the per-row overhead of the batch partition
+  // launch shape of the fixed-step kernels (autotuner results or nb_set_tuning): threads per
+  // block, block cap and the per-row overhead of the batch partition's cost model
+  int bs = kBlock;
   int tune_blocks = 0;
   double tune_row_cost = 1.0;
   // bound state
   char* ws = nullptr;
   size_t ws_bytes = 0;
   hipStream_t stream = nullptr;
-  int device = 0, cus = 0, max_blocks = 0, nblocks = 0;
+  int device = 0, cus = 0, nblocks = 0;
+  int cap512 = 0, cap256 = 0;        // resident blocks of the fixed-step kernels at 512 / 256 threads
+  int cap_adaptive = 0;              // resident blocks of the adaptive kernel (512 threads)
+  unsigned* cancel = nullptr;        // this model's cancel word (fine-grained host memory)
+  const unsigned* cancel_dev = nullptr;  // its device address
   unsigned long long ticks_per_s = 0;
   size_t off_X = 0, off_tab = 0, off_sync = 0, off_ctl = 0;
   size_t off_models = 0, off_waves = 0, off_acc = 0, need = 0;
@@ -120,6 +164,7 @@ struct nb_model {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   long long graph_steps = 0;
+  int graph_bs = 0, graph_blocks = 0;   // launch shape recorded in the graph
   // set only inside nb_step_static: barrier words and batch accumulators taken from the
   // static scratch array instead of the workspace
   unsigned int* sync_static = nullptr;
@@ -437,6 +482,7 @@ extern "C" void nb_model_destroy(nb_model* m) {
   if (!m) return;
   drop_graph(m);
   if (m->pinned) (void)hipHostFree(m->pinned);
+  cancel_word_give(m->cancel);
   delete m;
 }
 
@@ -541,24 +587,32 @@ static const void* adaptive_kernel(const nb_model* m) {
   return l ? (const void*)&k_adaptive<3, true> : (const void*)&k_adaptive<3, false>;
 }
 
-static const void* advance_kernel(const nb_model* m) {
-  if (m->batch) return (const void*)&k_batch2;
+// The fixed-step kernel of a model at bs threads per block (512 or 256).
+template <int BS>
+static const void* advance_kernel_bs(const nb_model* m) {
+  if (m->batch) return (const void*)&k_batch2<BS>;
   const bool l = tab_in_lds(m);
   if (m->nf == 2)
     return m->p.n_phi > 0
-               ? (l ? (const void*)&k_advance<2, double, true, false, true> : (const void*)&k_advance<2, double, false, false, true>)
-               : (l ? (const void*)&k_advance<2, double, true, false, false> : (const void*)&k_advance<2, double, false, false, false>);
+               ? (l ? (const void*)&k_advance<2, double, true, false, true, BS> : (const void*)&k_advance<2, double, false, false, true, BS>)
+               : (l ? (const void*)&k_advance<2, double, true, false, false, BS> : (const void*)&k_advance<2, double, false, false, false, BS>);
   if (state_fp32(m))
-    return l ? (const void*)&k_advance<3, float, true, false, false> : (const void*)&k_advance<3, float, false, false, false>;
+    return l ? (const void*)&k_advance<3, float, true, false, false, BS> : (const void*)&k_advance<3, float, false, false, false, BS>;
   if (m->p.n_phi > 0)
-    return l ? (const void*)&k_advance<3, double, true, false, true> : (const void*)&k_advance<3, double, false, false, true>;
-  return l ? (const void*)&k_advance<3, double, true, false, false> : (const void*)&k_advance<3, double, false, false, false>;
+    return l ? (const void*)&k_advance<3, double, true, false, true, BS> : (const void*)&k_advance<3, double, false, false, true, BS>;
+  return l ? (const void*)&k_advance<3, double, true, false, false, BS> : (const void*)&k_advance<3, double, false, false, false, BS>;
+}
+static const void* advance_kernel(const nb_model* m, int bs) {
+  return bs == kBlockSmall ? advance_kernel_bs<kBlockSmall>(m) : advance_kernel_bs<kBlock>(m);
 }
 // The FP32-arithmetic stepping kernel of the mixed-precision mode (nullptr otherwise).
-static const void* advance_kernel_f32(const nb_model* m) {
+static const void* advance_kernel_f32(const nb_model* m, int bs) {
   if (m->batch || !state_fp32(m)) return nullptr;
-  return f32_tab_in_lds(m) ? (const void*)&k_advance<3, float, true, true, false>
-                           : (const void*)&k_advance<3, float, false, true, false>;
+  if (bs == kBlockSmall)
+    return f32_tab_in_lds(m) ? (const void*)&k_advance<3, float, true, true, false, kBlockSmall>
+                             : (const void*)&k_advance<3, float, false, true, false, kBlockSmall>;
+  return f32_tab_in_lds(m) ? (const void*)&k_advance<3, float, true, true, false, kBlock>
+                           : (const void*)&k_advance<3, float, false, true, false, kBlock>;
 }
 
 static int launch_1d(const void* fn, long long n, void** args, hipStream_t s) {
@@ -585,7 +639,8 @@ static int set_device_step(nb_model* m, long long step) {
 // Clear the barrier words, optionally keeping the status word (a kernel: capturable).
 static int zero_sync(nb_model* m, int keep) {
   unsigned int* sync = sync_words(m);
-  void* zargs[] = {&sync, &keep};
+  const unsigned* cancel = m->cancel_dev;
+  void* zargs[] = {&sync, &keep, &cancel};
   NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(256), dim3(256), zargs, 0, m->stream));
   return NB_OK;
 }
@@ -611,19 +666,22 @@ extern "C" int nb_reset(nb_model* m) {
   return NB_OK;
 }
 
-// Blocks of one stepping launch: at most one wavefront per row, at most the resident
-// capacity, at most the autotuned cap.
-static int launch_blocks(const nb_model* m) {
-  const int wpb = kBlock / 64;
-  long long want = (m->rows + wpb - 1) / wpb;
-  int nb_ = (int)std::min<long long>(want, m->max_blocks);
-  if (m->tune_blocks > 0) nb_ = std::min(nb_, m->tune_blocks);
+// Resident blocks of the fixed-step kernels at bs threads per block (bind-time occupancy).
+static int capacity(const nb_model* m, int bs) { return bs == kBlockSmall ? m->cap256 : m->cap512; }
+// Blocks of one fixed-step launch at bs threads per block: at most one wavefront per row, at
+// most the resident capacity, at most cap (> 0).
+static int blocks_for(const nb_model* m, int bs, int cap) {
+  const int wpb = bs / 64;
+  const long long want = (m->rows + wpb - 1) / wpb;
+  int nb_ = (int)std::min<long long>(want, capacity(m, bs));
+  if (cap > 0) nb_ = std::min(nb_, cap);
   return std::max(1, nb_);
 }
+static int launch_blocks(const nb_model* m) { return blocks_for(m, m->bs, m->tune_blocks); }
 
 // Contiguous row ranges per wavefront with balanced cost (64-lane chunks + row overhead).
 static int upload_partition(nb_model* m) {
-  const int waves = m->nblocks * (kBlock / 64);
+  const int waves = m->nblocks * (m->bs / 64);
   std::vector<double> cost;
   double total = 0.0;
   for (const Sub& s : m->subs) {
@@ -649,31 +707,45 @@ static int upload_partition(nb_model* m) {
   return NB_OK;
 }
 
+// Resident blocks of the model's fixed-step kernels at bs threads per block: the least
+// per-CU occupancy over the kernels its launches use (with their dynamic LDS) times the CUs,
+// at most kMaxBlocks and p.max_blocks; 0 if one of them cannot be resident at that size.
+static int fixed_step_capacity(const nb_model* m, int cus, int bs, int* out) {
+  int per = 0;
+  NB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, advance_kernel(m, bs), bs, advance_dyn_lds(m)));
+  if (advance_kernel_f32(m, bs)) {
+    int p32 = 0;
+    NB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&p32, advance_kernel_f32(m, bs), bs, f32_dyn_lds(m)));
+    per = std::min(per, p32);
+  }
+  int cap = std::min(cus * per, kMaxBlocks);
+  if (m->p.max_blocks > 0) cap = std::min(cap, (int)m->p.max_blocks);
+  *out = std::max(0, cap);
+  return NB_OK;
+}
+
 extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream) {
   if (!m || !dev_ws) return fail(NB_EINVAL, "NULL model or workspace");
   if (((uintptr_t)dev_ws) % 256) return fail(NB_EWORKSPACE, "workspace must be 256-byte aligned");
   int dev = 0;
   NB_HIP(hipGetDevice(&dev));
-  int cus = 0, khz = 0, nbpm = 0;
+  int cus = 0, khz = 0;
   NB_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   NB_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
-  NB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nbpm, advance_kernel(m), kBlock,
-                                                       advance_dyn_lds(m)));
-  if (advance_kernel_f32(m)) {
-    int nb32 = 0;
-    NB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb32, advance_kernel_f32(m), kBlock,
-                                                         f32_dyn_lds(m)));
-    nbpm = std::min(nbpm, nb32);
+  int cap[2] = {0, 0}, cap_adaptive = 0;
+  for (int i = 0; i < 2; ++i) {
+    int rc = fixed_step_capacity(m, cus, i == 0 ? kBlock : kBlockSmall, &cap[i]);
+    if (rc) return rc;
   }
+  if (cap[0] < 1) return fail(NB_EHIP, "stepping kernel cannot be resident");
   if (adaptive_kernel(m)) {
     int nba = 0;
     NB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nba, adaptive_kernel(m), kBlock,
                                                          advance_dyn_lds(m)));
-    nbpm = std::min(nbpm, nba);
+    if (nba < 1) return fail(NB_EHIP, "adaptive kernel cannot be resident");
+    cap_adaptive = std::min(cus * nba, kMaxBlocks);
+    if (m->p.max_blocks > 0) cap_adaptive = std::min(cap_adaptive, (int)m->p.max_blocks);
   }
-  if (nbpm < 1) return fail(NB_EHIP, "stepping kernel cannot be resident");
-  int max_blocks = std::min(cus * nbpm, kMaxBlocks);
-  if (m->p.max_blocks > 0) max_blocks = std::min(max_blocks, (int)m->p.max_blocks);
   const Layout L = layout_of(m);
   if (bytes < L.need)
     return fail(NB_EWORKSPACE, "workspace too small: %zu < %zu bytes", bytes, L.need);
@@ -727,8 +799,16 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
   m->stream = (hipStream_t)hip_stream;
   m->device = dev;
   m->cus = cus;
-  m->max_blocks = max_blocks;
+  m->cap512 = cap[0];
+  m->cap256 = cap[1];
+  m->cap_adaptive = cap_adaptive;
+  if (capacity(m, m->bs) < 1) m->bs = kBlock;   // a tuned block size this device cannot hold
+  if (m->tune_blocks > capacity(m, m->bs)) m->tune_blocks = 0;
   m->nblocks = launch_blocks(m);
+  if (!m->cancel) {
+    int rc = cancel_word_take(&m->cancel, &m->cancel_dev);
+    if (rc) return rc;
+  }
   m->ticks_per_s = (unsigned long long)(khz > 0 ? khz : 100000) * 1000ull;
   if (!m->pinned) NB_HIP(hipHostMalloc((void**)&m->pinned, 256, hipHostMallocDefault));
   NB_HIP(hipMemcpyAsync(m->ws + m->off_tab, m->tab.data(), tab_bytes(m), hipMemcpyHostToDevice,
@@ -750,7 +830,8 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
   }
   unsigned int* sync = (unsigned int*)(m->ws + m->off_sync);
   int keep = 0;
-  void* zargs[] = {&sync, &keep};
+  const unsigned* no_cancel = nullptr;
+  void* zargs[] = {&sync, &keep, &no_cancel};
   NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(256), dim3(256), zargs, 0, m->stream));
   NB_HIP(hipStreamSynchronize(m->stream));
   return nb_reset(m);
@@ -770,10 +851,15 @@ static int check_status(nb_model* m) {
   m->step = m->pinned[1];
   if (st) {
     int keep = 0;
-    void* zargs[] = {&sync, &keep};
+    const unsigned* no_cancel = nullptr;
+    void* zargs[] = {&sync, &keep, &no_cancel};
     NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(256), dim3(256), zargs, 0, m->stream));
     NB_HIP(hipStreamSynchronize(m->stream));
+    if (st & 4u) return fail(NB_ETIMEOUT, "cancelled by the host (nb_cancel)");
     if (st & 2u) return fail(NB_ETIMEOUT, "grid barrier time limit exceeded");
+    if (st & 8u)
+      return fail(NB_ENUMERIC, "renormalisation factor far from 1 (|state|^2 off 1 by more than %g)",
+                  state_fp32(m) ? 1e-5 : 1e-8);
     return fail(NB_ENUMERIC, "moment contribution out of fixed-point range (NaN or overflow)");
   }
   return NB_OK;
@@ -787,9 +873,8 @@ static long long launch_chunk(const nb_model* m) {
 // Enqueue one stepping launch of k steps (from the device step counter) on the stream.
 static int enqueue_advance(nb_model* m, long long k) {
   unsigned int* sync = sync_words(m);
-  int keep = 1;
-  void* zargs[] = {&sync, &keep};
-  NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(256), dim3(256), zargs, 0, m->stream));
+  int rc0 = zero_sync(m, 1);
+  if (rc0) return rc0;
   const unsigned long long timeout = m->ticks_per_s * 20ull;
   if (m->batch) {
     unsigned long long* acc = acc_words(m);
@@ -815,13 +900,15 @@ static int enqueue_advance(nb_model* m, long long k) {
     a.ne_power = m->p.ne_power;
     a.renorm = m->p.renorm;
     a.timeout_ticks = timeout;
+    a.cancel = m->cancel_dev;
     void* args[] = {&a};
     // Inside graph capture the kernel node is an ordinary launch: the grid never exceeds
-    // the resident capacity measured at bind time, and every barrier wait is time-limited.
+    // the resident capacity measured at bind time (checked again at every graph launch),
+    // and every barrier wait is time-limited and cancellable from the host.
     const hipError_t e =
         capturing(m->stream)
-            ? hipLaunchKernel((const void*)&k_batch2, dim3(m->nblocks), dim3(kBlock), args, 0, m->stream)
-            : hipLaunchCooperativeKernel((const void*)&k_batch2, dim3(m->nblocks), dim3(kBlock), args, 0,
+            ? hipLaunchKernel(advance_kernel(m, m->bs), dim3(m->nblocks), dim3(m->bs), args, 0, m->stream)
+            : hipLaunchCooperativeKernel(advance_kernel(m, m->bs), dim3(m->nblocks), dim3(m->bs), args, 0,
                                          m->stream);
     if (e != hipSuccess) return fail(NB_EHIP, "batch launch: %s", hipGetErrorString(e));
     return NB_OK;
@@ -851,17 +938,18 @@ static int enqueue_advance(nb_model* m, long long k) {
   a.p2e0 = s.p2e0;
   for (int q = 0; q < 6; ++q) a.v0[q] = s.v0[q];
   a.timeout_ticks = timeout;
+  a.cancel = m->cancel_dev;
   a.Jhist = m->jhist;
   auto launch = [&](const void* fn, size_t lds) -> int {
     void* args[] = {&a};
     const hipError_t e =
         capturing(m->stream)
-            ? hipLaunchKernel(fn, dim3(m->nblocks), dim3(kBlock), args, lds, m->stream)
-            : hipLaunchCooperativeKernel(fn, dim3(m->nblocks), dim3(kBlock), args, (unsigned)lds, m->stream);
+            ? hipLaunchKernel(fn, dim3(m->nblocks), dim3(m->bs), args, lds, m->stream)
+            : hipLaunchCooperativeKernel(fn, dim3(m->nblocks), dim3(m->bs), args, (unsigned)lds, m->stream);
     if (e != hipSuccess) return fail(NB_EHIP, "stepping launch: %s", hipGetErrorString(e));
     return NB_OK;
   };
-  if (!advance_kernel_f32(m)) return launch(advance_kernel(m), advance_dyn_lds(m));
+  if (!advance_kernel_f32(m, m->bs)) return launch(advance_kernel(m, m->bs), advance_dyn_lds(m));
   // Mixed precision: FP64-arithmetic steps before fp32_from, FP32-arithmetic steps after,
   // as two windowed launches sharing one target of k steps from the device counter.
   {
@@ -873,13 +961,13 @@ static int enqueue_advance(nb_model* m, long long k) {
   a.use_window = 1;
   a.win_lo = 0;
   a.win_hi = s.fp32_from;
-  int rc = launch(advance_kernel(m), advance_dyn_lds(m));
+  int rc = launch(advance_kernel(m, m->bs), advance_dyn_lds(m));
   if (rc) return rc;
   rc = zero_sync(m, 1);
   if (rc) return rc;
   a.win_lo = s.fp32_from;
   a.win_hi = m->p.n_steps;
-  return launch(advance_kernel_f32(m), f32_dyn_lds(m));
+  return launch(advance_kernel_f32(m, m->bs), f32_dyn_lds(m));
 }
 
 static int advance(nb_model* m, long long n) {
@@ -1017,13 +1105,16 @@ extern "C" int nb_run_adaptive(nb_model* m, double tol, double h_max_km, int64_t
   a.p2e0 = s.p2e0;
   for (int q = 0; q < 6; ++q) a.v0[q] = s.v0[q];
   a.timeout_ticks = m->ticks_per_s * 20ull;
+  a.cancel = m->cancel_dev;
   a.tol2 = tol * tol;
   a.hmax = (h_max_km > 0.0) ? h_max_km : span;
   a.hmin = std::ldexp(s.h, -40);
   a.r_end = m->p.r_end_km;
   a.max_attempts = max_attempts;
   void* args[] = {&a};
-  const hipError_t e = hipLaunchCooperativeKernel(adaptive_kernel(m), dim3(m->nblocks), dim3(kBlock), args,
+  // one wavefront per row at most, at most the adaptive kernel's resident capacity
+  const int ablocks = (int)std::max<long long>(1, std::min<long long>((m->rows + 7) / 8, m->cap_adaptive));
+  const hipError_t e = hipLaunchCooperativeKernel(adaptive_kernel(m), dim3(ablocks), dim3(kBlock), args,
                                                   (unsigned)advance_dyn_lds(m), m->stream);
   if (e != hipSuccess) return fail(NB_EHIP, "adaptive launch: %s", hipGetErrorString(e));
   long long out[8];
@@ -1069,72 +1160,401 @@ extern "C" int nb_graph_capture(nb_model* m, int64_t n_steps) {
   }
   m->graph = g;
   m->graph_steps = n_steps;
+  m->graph_bs = m->bs;
+  m->graph_blocks = m->nblocks;
   return NB_OK;
 }
 
 extern "C" int nb_graph_launch(nb_model* m) {
   if (!m) return fail(NB_EINVAL, "model is NULL");
   if (!m->graph_exec) return fail(NB_EINVAL, "no graph captured");
+  // Inside the graph the persistent kernel is an ordinary launch, which makes progress only
+  // if all its blocks are resident at once: check the recorded grid against the occupancy
+  // the device reports now.
+  int cur = 0, cus = 0, cap = 0;
+  NB_HIP(hipGetDevice(&cur));
+  if (cur != m->device) return fail(NB_EINVAL, "graph launch on device %d, model bound on %d", cur, m->device);
+  NB_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cur));
+  int rc = fixed_step_capacity(m, cus, m->graph_bs, &cap);
+  if (rc) return rc;
+  if (m->graph_blocks > cap)
+    return fail(NB_EINVAL, "captured grid of %d blocks of %d threads exceeds the resident capacity %d",
+                m->graph_blocks, m->graph_bs, cap);
   NB_HIP(hipGraphLaunch(m->graph_exec, m->stream));
   return check_status(m);
 }
 
+extern "C" int nb_cancel(nb_model* m, int32_t on) {
+  if (!m) return fail(NB_EINVAL, "model is NULL");
+  if (!m->cancel) return fail(NB_EUNBOUND, "no workspace bound");
+  __atomic_store_n(m->cancel, on ? 1u : 0u, __ATOMIC_SEQ_CST);
+  return NB_OK;
+}
+
 // ------------------------------------------------------------------ autotuner
-// Times trial_steps from the initial state for each candidate launch shape (block cap;
-// for batches also the per-row overhead of the row partition), keeps the fastest and
-// resets the model.
-extern "C" int nb_autotune(nb_model* m, int32_t trial_steps, double* best_ms) {
+// Launch shapes of the fixed-step kernels: threads per block (512 or 256), a block cap and,
+// for batches, the per-row overhead of the cost model that splits the rows among
+// wavefronts.  A beam's arithmetic does not depend on the shape and the moments are exact
+// integer sums, so every shape gives the same bits.
+
+// Shape -> model (bound, not capturing): block count and, for batches, the row partition.
+static int apply_shape(nb_model* m, int bs, int blocks, double row_cost) {
+  drop_graph(m);
+  m->bs = bs;
+  m->tune_blocks = blocks;
+  m->tune_row_cost = row_cost;
+  m->nblocks = launch_blocks(m);
+  return m->batch ? upload_partition(m) : NB_OK;
+}
+
+static int check_shape(const nb_model* m, int bs, int blocks, double row_cost) {
+  if (bs != kBlock && bs != kBlockSmall) return fail(NB_EINVAL, "block_threads must be 512 or 256");
+  if (capacity(m, bs) < 1) return fail(NB_EINVAL, "the stepping kernels cannot be resident at %d threads", bs);
+  if (blocks < 0 || blocks > capacity(m, bs))
+    return fail(NB_EINVAL, "blocks must be in 0..%d (the resident capacity at %d threads)", capacity(m, bs), bs);
+  if (m->batch && !(row_cost > 0.0 && row_cost < 1e6)) return fail(NB_EINVAL, "row_cost must be in (0, 1e6)");
+  return NB_OK;
+}
+
+extern "C" int nb_set_tuning(nb_model* m, const nb_tuning* t) {
+  if (!m || !t) return fail(NB_EINVAL, "NULL argument");
+  if (!m->ws) return fail(NB_EUNBOUND, "no workspace bound");
+  if (capturing(m->stream)) return fail(NB_EINVAL, "the launch shape cannot change during capture");
+  const double rc_ = m->batch ? t->row_cost : m->tune_row_cost;
+  int rc = check_shape(m, t->block_threads, t->blocks, rc_);
+  if (rc) return rc;
+  return apply_shape(m, t->block_threads, t->blocks, rc_);
+}
+
+extern "C" int nb_get_tuning(const nb_model* m, nb_tuning* t) {
+  if (!m || !t) return fail(NB_EINVAL, "NULL argument");
+  if (!m->ws) return fail(NB_EUNBOUND, "no workspace bound");
+  *t = nb_tuning{};
+  t->block_threads = m->bs;
+  t->blocks = m->nblocks;
+  t->row_cost = m->tune_row_cost;
+  return NB_OK;
+}
+
+// --- the tuning cache: a JSON object mapping a shape key to its winning launch shape,
+// {"<key>": {"block_threads": 512, "blocks": 256, "row_cost": 1, "ms": 0.93, "trial_steps": 10}, ...}
+struct TuneRec {
+  int bs = 0, blocks = 0;
+  double row_cost = 1.0, ms = 0.0;
+  long long trial = 0;
+};
+
+// Key: device (architecture and CU count) and the model's shape -- flavours, N_E, N_u,
+// azimuthal bins, species rows, precision, block limit; for batches the model count, rows,
+// beams and an FNV-1a hash of every member's (N_E, N_u).
+static int tuning_key(const nb_model* m, std::string* key) {
+  hipDeviceProp_t prop;
+  NB_HIP(hipGetDeviceProperties(&prop, m->device));
+  std::string arch;
+  for (const char* c = prop.gcnArchName; *c && arch.size() < 64; ++c)
+    if (*c != '"' && *c != '\\' && (unsigned char)*c >= 0x20 && (unsigned char)*c < 0x7f) arch += *c;
+  const Sub& s = m->subs[0];
+  char buf[320];
+  snprintf(buf, sizeof buf, "%s/cu%d/nf%d/ne%lld/nu%lld/nphi%lld/ns%d/%s/maxb%d", arch.c_str(), m->cus, m->nf,
+           s.NE, s.NU, s.NP, s.NS, state_fp32(m) ? "fp32state" : "fp64", (int)m->p.max_blocks);
+  *key = buf;
+  if (m->batch) {
+    unsigned long long h = 1469598103934665603ull;
+    for (const Sub& x : m->subs)
+      for (long long v : {x.NE, x.NU})
+        for (int b = 0; b < 8; ++b) h = (h ^ (unsigned long long)((v >> (8 * b)) & 0xff)) * 1099511628211ull;
+    snprintf(buf, sizeof buf, "/batch%d/rows%lld/beams%lld/h%016llx", m->nmodels, m->rows, m->nb, h);
+    *key += buf;
+  }
+  return NB_OK;
+}
+
+class JsonIn {
+ public:
+  explicit JsonIn(const std::string& t) : t_(t) {}
+  void ws() {
+    while (i_ < t_.size() && (t_[i_] == ' ' || t_[i_] == '\t' || t_[i_] == '\n' || t_[i_] == '\r')) ++i_;
+  }
+  bool lit(char c) {
+    ws();
+    if (i_ < t_.size() && t_[i_] == c) {
+      ++i_;
+      return true;
+    }
+    return false;
+  }
+  bool at_end() {
+    ws();
+    return i_ == t_.size();
+  }
+  bool str(std::string& out) {
+    if (!lit('"')) return false;
+    out.clear();
+    while (i_ < t_.size() && t_[i_] != '"') {
+      char c = t_[i_++];
+      if (c == '\\') {
+        if (i_ >= t_.size()) return false;
+        const char e = t_[i_++];
+        if (e == '"' || e == '\\' || e == '/') c = e;
+        else if (e == 'n') c = '\n';
+        else if (e == 't') c = '\t';
+        else if (e == 'r') c = '\r';
+        else if (e == 'b') c = '\b';
+        else if (e == 'f') c = '\f';
+        else if (e == 'u') {   // \u00XX only (keys are ASCII)
+          if (i_ + 4 > t_.size()) return false;
+          unsigned v = 0;
+          for (int k = 0; k < 4; ++k) {
+            const char h = t_[i_++];
+            int d = -1;
+            if (h >= '0' && h <= '9') d = h - '0';
+            else if (h >= 'a' && h <= 'f') d = h - 'a' + 10;
+            else if (h >= 'A' && h <= 'F') d = h - 'A' + 10;
+            if (d < 0) return false;
+            v = v * 16 + (unsigned)d;
+          }
+          if (v >= 0x80) return false;
+          c = (char)v;
+        } else {
+          return false;
+        }
+      }
+      out += c;
+    }
+    return lit('"');
+  }
+  bool num(double& v) {
+    ws();
+    const char* b = t_.c_str() + i_;
+    char* e = nullptr;
+    v = std::strtod(b, &e);
+    if (e == b) return false;
+    i_ += (size_t)(e - b);
+    return true;
+  }
+  // any value (unknown fields): string, number, literal, or nested object/array
+  bool skip() {
+    ws();
+    if (i_ >= t_.size()) return false;
+    const char c = t_[i_];
+    if (c == '"') {
+      std::string tmp;
+      return str(tmp);
+    }
+    if (c == '{' || c == '[') {
+      const char close = (c == '{') ? '}' : ']';
+      ++i_;
+      if (lit(close)) return true;
+      do {
+        if (c == '{') {
+          std::string k;
+          if (!str(k) || !lit(':')) return false;
+        }
+        if (!skip()) return false;
+      } while (lit(','));
+      return lit(close);
+    }
+    for (const char* w : {"true", "false", "null"})
+      if (t_.compare(i_, std::strlen(w), w) == 0) {
+        i_ += std::strlen(w);
+        return true;
+      }
+    double v;
+    return num(v);
+  }
+
+ private:
+  const std::string& t_;
+  size_t i_ = 0;
+};
+
+// Read the cache (a missing file is an empty cache).  NB_EIO if it cannot be read or is
+// not a tuning cache; it is then left as it is.
+static int read_cache(const char* path, std::map<std::string, TuneRec>* recs) {
+  FILE* f = std::fopen(path, "rb");
+  if (!f) {
+    if (errno == ENOENT) return NB_OK;
+    return fail(NB_EIO, "tuning cache %s: %s", path, std::strerror(errno));
+  }
+  std::string text;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, n);
+  const bool err = std::ferror(f) != 0;
+  std::fclose(f);
+  if (err) return fail(NB_EIO, "tuning cache %s: read error", path);
+  if (text.size() > (64u << 20)) return fail(NB_EIO, "tuning cache %s: larger than 64 MiB", path);
+  JsonIn in(text);
+  if (in.at_end()) return NB_OK;   // empty file
+  if (!in.lit('{')) return fail(NB_EIO, "tuning cache %s: not a JSON object", path);
+  if (!in.lit('}')) {
+    do {
+      std::string key;
+      if (!in.str(key) || !in.lit(':') || !in.lit('{'))
+        return fail(NB_EIO, "tuning cache %s: malformed entry", path);
+      TuneRec r;
+      bool have_bs = false, have_blocks = false;
+      if (!in.lit('}')) {
+        do {
+          std::string f2;
+          if (!in.str(f2) || !in.lit(':')) return fail(NB_EIO, "tuning cache %s: malformed field", path);
+          double v = 0.0;
+          const bool known = f2 == "block_threads" || f2 == "blocks" || f2 == "row_cost" || f2 == "ms" ||
+                             f2 == "trial_steps";
+          if (known ? !in.num(v) : !in.skip())
+            return fail(NB_EIO, "tuning cache %s: bad value of %s", path, f2.c_str());
+          if (f2 == "block_threads") { r.bs = (int)v; have_bs = true; }
+          else if (f2 == "blocks") { r.blocks = (int)v; have_blocks = true; }
+          else if (f2 == "row_cost") r.row_cost = v;
+          else if (f2 == "ms") r.ms = v;
+          else if (f2 == "trial_steps") r.trial = (long long)v;
+        } while (in.lit(','));
+        if (!in.lit('}')) return fail(NB_EIO, "tuning cache %s: unterminated entry", path);
+      }
+      if (have_bs && have_blocks) (*recs)[key] = r;
+    } while (in.lit(','));
+    if (!in.lit('}')) return fail(NB_EIO, "tuning cache %s: unterminated object", path);
+  }
+  if (!in.at_end()) return fail(NB_EIO, "tuning cache %s: trailing characters", path);
+  return NB_OK;
+}
+
+// Write the cache: a temporary file beside it, then renamed over it (readers see the old
+// or the new file, never a partial one).
+static int write_cache(const char* path, const std::map<std::string, TuneRec>& recs) {
+  std::string out = "{\n";
+  size_t i = 0;
+  for (const auto& kv : recs) {
+    std::string k;
+    for (char c : kv.first) {
+      if (c == '"' || c == '\\') k += '\\';
+      k += c;
+    }
+    char buf[256];
+    snprintf(buf, sizeof buf,
+             "\": {\"block_threads\": %d, \"blocks\": %d, \"row_cost\": %.17g, \"ms\": %.17g, \"trial_steps\": %lld}",
+             kv.second.bs, kv.second.blocks, kv.second.row_cost, kv.second.ms, kv.second.trial);
+    out += "  \"" + k + buf + (++i < recs.size() ? ",\n" : "\n");
+  }
+  out += "}\n";
+  const std::string tmp = std::string(path) + ".tmp." + std::to_string((long long)getpid());
+  FILE* f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return fail(NB_EIO, "tuning cache %s: %s", tmp.c_str(), std::strerror(errno));
+  const bool ok = std::fwrite(out.data(), 1, out.size(), f) == out.size();
+  const bool closed = std::fclose(f) == 0;
+  if (!ok || !closed || std::rename(tmp.c_str(), path) != 0) {
+    const int e = errno;
+    std::remove(tmp.c_str());
+    return fail(NB_EIO, "tuning cache %s: write failed (%s)", path, std::strerror(e));
+  }
+  return NB_OK;
+}
+
+// Times trial_steps steps from the initial state (best of two runs, after a one-step
+// warm-up launch) for every candidate shape: 512 and 256 threads per block, each at the
+// full resident grid, 3/4 and 1/2 of it; for batches each with row costs 0.25, 1 and 3
+// chunks.  Keeps the fastest, then resets the model.
+extern "C" int nb_autotune(nb_model* m, int32_t trial_steps, const char* cache_path, nb_tuning* out) {
   if (!m) return fail(NB_EINVAL, "model is NULL");
   if (!m->ws) return fail(NB_EUNBOUND, "no workspace bound");
   if (trial_steps < 1) return fail(NB_EINVAL, "trial_steps must be >= 1");
+  if (capturing(m->stream)) return fail(NB_EINVAL, "the autotuner cannot run under capture");
   drop_graph(m);
-  std::vector<std::pair<int, double>> cands;
-  const int full = launch_blocks(m);
-  std::vector<int> blocks = {full};
-  if (full >= 8) blocks.push_back(std::max(1, full * 3 / 4));
-  if (full >= 8) blocks.push_back(std::max(1, full / 2));
-  std::vector<double> costs = {m->tune_row_cost};
-  if (m->batch) costs = {0.25, 1.0, 3.0};
-  for (int b : blocks)
-    for (double c : costs) cands.push_back({b, c});
+  std::map<std::string, TuneRec> recs;
+  std::string key;
+  const bool use_cache = cache_path && *cache_path;
+  if (use_cache) {
+    int rc = tuning_key(m, &key);
+    if (!rc) rc = read_cache(cache_path, &recs);
+    if (rc) return rc;
+    const auto it = recs.find(key);
+    if (it != recs.end() && it->second.blocks >= 1 &&
+        check_shape(m, it->second.bs, it->second.blocks, it->second.row_cost) == NB_OK) {
+      const TuneRec& r = it->second;
+      rc = apply_shape(m, r.bs, r.blocks, m->batch ? r.row_cost : m->tune_row_cost);
+      if (!rc) rc = nb_reset(m);
+      if (rc) return rc;
+      if (out) {
+        nb_get_tuning(m, out);
+        out->ms = r.ms;
+        out->from_cache = 1;
+        out->candidates = 0;
+      }
+      return NB_OK;
+    }
+  }
+  struct Cand {
+    int bs, blocks;
+    double cost;
+  };
+  std::vector<Cand> cands;
+  const std::vector<double> costs = m->batch ? std::vector<double>{0.25, 1.0, 3.0}
+                                             : std::vector<double>{m->tune_row_cost};
+  for (int bs : {kBlock, kBlockSmall}) {
+    if (capacity(m, bs) < 1) continue;
+    const int full = blocks_for(m, bs, 0);
+    std::vector<int> bl = {full};
+    if (full >= 8) {
+      bl.push_back(full * 3 / 4);
+      bl.push_back(full / 2);
+    }
+    for (int b : bl)
+      for (double c : costs) cands.push_back({bs, b, c});
+  }
   hipEvent_t e0, e1;
   NB_HIP(hipEventCreate(&e0));
   NB_HIP(hipEventCreate(&e1));
   float best = 1e30f;
-  std::pair<int, double> pick = cands[0];
+  Cand pick = cands[0];
   int rc = NB_OK;
   const long long steps = std::min<long long>(trial_steps, m->p.n_steps);
-  for (const auto& c : cands) {
-    m->nblocks = c.first;
-    m->tune_row_cost = c.second;
-    if (m->batch && (rc = upload_partition(m))) break;
-    if ((rc = nb_reset(m))) break;
-    if ((rc = nb_step(m, 1))) break;       // warm-up launch
-    if ((rc = nb_reset(m))) break;
-    NB_HIP(hipEventRecord(e0, m->stream));
-    if ((rc = nb_step(m, steps))) break;
-    NB_HIP(hipEventRecord(e1, m->stream));
-    NB_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    NB_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best) {
-      best = ms;
+  for (const Cand& c : cands) {
+    if ((rc = apply_shape(m, c.bs, c.blocks, c.cost))) break;
+    if ((rc = nb_reset(m)) || (rc = nb_step(m, 1))) break;      // warm-up launch
+    float mine = 1e30f;
+    for (int rep = 0; rep < 2 && !rc; ++rep) {
+      if ((rc = nb_reset(m))) break;
+      hipError_t e = hipEventRecord(e0, m->stream);
+      if (e == hipSuccess && !(rc = nb_step(m, steps))) {
+        e = hipEventRecord(e1, m->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess) mine = std::min(mine, ms);
+      }
+      if (e != hipSuccess && !rc) rc = fail(NB_EHIP, "autotune timing: %s", hipGetErrorString(e));
+    }
+    if (rc) break;
+    if (mine < best) {
+      best = mine;
       pick = c;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  m->nblocks = pick.first;
-  m->tune_blocks = pick.first;
-  m->tune_row_cost = pick.second;
-  if (m->batch) {
-    int r2 = upload_partition(m);
-    if (!rc) rc = r2;
-  }
+  int r2 = apply_shape(m, pick.bs, pick.blocks, pick.cost);
+  if (!rc) rc = r2;
   int r3 = nb_reset(m);
   if (!rc) rc = r3;
-  if (best_ms) *best_ms = best;
-  return rc;
+  if (rc) return rc;
+  if (use_cache) {
+    TuneRec r;
+    r.bs = pick.bs;
+    r.blocks = pick.blocks;
+    r.row_cost = pick.cost;
+    r.ms = best;
+    r.trial = steps;
+    recs[key] = r;
+    rc = write_cache(cache_path, recs);
+    if (rc) return rc;
+  }
+  if (out) {
+    nb_get_tuning(m, out);
+    out->ms = best;
+    out->from_cache = 0;
+    out->candidates = (int32_t)cands.size();
+  }
+  return NB_OK;
 }
 
 extern "C" int nb_read_pee(const nb_model* m, double* dev_out) {
@@ -1160,47 +1580,53 @@ static int xfer(nb_model* m, double* buf, int dir) {
                    m->nb, args, m->stream);
 }
 
+// Host <-> state planes without a device buffer: FP64 states as one strided copy of the
+// nsc planes (pitch plane -> nb beams); FP32 states through a host buffer, converted on the
+// host (double -> float rounds to nearest, as the kernels do).
+static int host_xfer(nb_model* m, double* host, int dir) {
+  const size_t es = state_fp32(m) ? sizeof(float) : sizeof(double);
+  char* X = m->ws + m->off_X;
+  const size_t nbb = (size_t)m->nb, rows = (size_t)m->nsc;
+  std::vector<float> f;
+  void* hbuf = host;
+  if (es == sizeof(float)) {
+    f.resize(nbb * rows);
+    if (dir == 1)
+      for (size_t i = 0; i < f.size(); ++i) f[i] = (float)host[i];
+    hbuf = f.data();
+  }
+  hipError_t e = (dir == 0)
+                     ? hipMemcpy2DAsync(hbuf, es * nbb, X, es * (size_t)m->plane, es * nbb, rows,
+                                        hipMemcpyDeviceToHost, m->stream)
+                     : hipMemcpy2DAsync(X, es * (size_t)m->plane, hbuf, es * nbb, es * nbb, rows,
+                                        hipMemcpyHostToDevice, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  if (e != hipSuccess) return fail(NB_EHIP, "state copy: %s", hipGetErrorString(e));
+  if (es == sizeof(float) && dir == 0)
+    for (size_t i = 0; i < f.size(); ++i) host[i] = (double)f[i];
+  return NB_OK;
+}
+
 extern "C" int nb_get_state(const nb_model* mc, double* dst, int on_device) {
   nb_model* m = const_cast<nb_model*>(mc);
   if (!m || !dst) return fail(NB_EINVAL, "NULL argument");
   if (!m->ws) return fail(NB_EUNBOUND, "no workspace bound");
-  const size_t bytes = sizeof(double) * (size_t)m->nb * m->nsc;
-  if (on_device) {
-    int rc = xfer(m, dst, 0);
-    if (rc) return rc;
-    NB_HIP(hipStreamSynchronize(m->stream));
-    return NB_OK;
-  }
-  double* tmp = nullptr;
-  NB_HIP(hipMallocAsync((void**)&tmp, bytes, m->stream));
-  int rc = xfer(m, tmp, 0);
-  if (!rc) {
-    hipError_t e = hipMemcpyAsync(dst, tmp, bytes, hipMemcpyDeviceToHost, m->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
-    if (e != hipSuccess) rc = fail(NB_EHIP, "state copy failed: %s", hipGetErrorString(e));
-  }
-  (void)hipFreeAsync(tmp, m->stream);
-  (void)hipStreamSynchronize(m->stream);
-  return rc;
+  if (capturing(m->stream)) return fail(NB_EINVAL, "state exchange cannot be captured");
+  if (!on_device) return host_xfer(m, dst, 0);
+  int rc = xfer(m, dst, 0);
+  if (rc) return rc;
+  NB_HIP(hipStreamSynchronize(m->stream));
+  return NB_OK;
 }
 
 extern "C" int nb_set_state(nb_model* m, const double* src, int64_t step, int on_device) {
   if (!m || !src) return fail(NB_EINVAL, "NULL argument");
   if (!m->ws) return fail(NB_EUNBOUND, "no workspace bound");
   if (step < 0 || step > m->p.n_steps) return fail(NB_EINVAL, "step out of range");
-  const size_t bytes = sizeof(double) * (size_t)m->nb * m->nsc;
-  if (on_device) {
-    int rc = xfer(m, const_cast<double*>(src), 1);
-    if (rc) return rc;
-  } else {
-    double* tmp = nullptr;
-    NB_HIP(hipMallocAsync((void**)&tmp, bytes, m->stream));
-    hipError_t e = hipMemcpyAsync(tmp, src, bytes, hipMemcpyHostToDevice, m->stream);
-    int rc = (e == hipSuccess) ? xfer(m, tmp, 1) : fail(NB_EHIP, "copy: %s", hipGetErrorString(e));
-    (void)hipFreeAsync(tmp, m->stream);
-    if (rc) return rc;
-  }
-  int rc = set_device_step(m, step);
+  if (capturing(m->stream)) return fail(NB_EINVAL, "state exchange cannot be captured");
+  int rc = on_device ? xfer(m, const_cast<double*>(src), 1) : host_xfer(m, const_cast<double*>(src), 1);
+  if (rc) return rc;
+  rc = set_device_step(m, step);
   if (rc) return rc;
   NB_HIP(hipStreamSynchronize(m->stream));
   m->step = step;
@@ -1243,9 +1669,8 @@ extern "C" int nb_adjoint(nb_model* m, const double* dev_dl_dpee, double* grad_o
   m->jhist = nullptr;
   // reverse pass
   unsigned int* sync = (unsigned int*)(m->ws + m->off_sync);
-  int keep = 1;
-  void* zargs[] = {&sync, &keep};
-  NB_HIP(hipLaunchKernel((const void*)&k_zero_sync, dim3(256), dim3(256), zargs, 0, m->stream));
+  int rc0 = zero_sync(m, 1);
+  if (rc0) return rc0;
   const Sub& s = m->subs[0];
   AdjArgs a{};
   a.tab = (const double*)(m->ws + m->off_tab);
@@ -1275,6 +1700,7 @@ extern "C" int nb_adjoint(nb_model* m, const double* dev_dl_dpee, double* grad_o
   a.ne_power = m->p.ne_power;
   a.renorm = m->p.renorm;
   a.timeout_ticks = m->ticks_per_s * 20ull;
+  a.cancel = m->cancel_dev;
   void* args[] = {&a};
   const void* fn = m->adj_bpt == 1 ? (const void*)&k_adjoint2<1>
                  : m->adj_bpt == 2 ? (const void*)&k_adjoint2<2>
@@ -1318,44 +1744,5 @@ extern "C" int nb_host_tables(const nb_model* m, double* out, int64_t cap) {
   out[o++] = s.p2e0;
   out[o++] = s.e1;
   out[o++] = s.e0;
-  return NB_OK;
-}
-
-// ------------------------------------------------------------------ test hooks
-extern "C" int nb_test_sincos(const double* x, int64_t n, double* s, double* c, void* stream) {
-  if (n < 0 || (n > 0 && (!x || !s || !c))) return fail(NB_EINVAL, "bad arguments");
-  long long nn = n;
-  void* args[] = {&x, &nn, &s, &c};
-  int rc = launch_1d((const void*)&k_test_sincos, n, args, (hipStream_t)stream);
-  if (rc) return rc;
-  NB_HIP(hipStreamSynchronize((hipStream_t)stream));
-  return NB_OK;
-}
-extern "C" int nb_test_sqrt_div(const double* a, const double* b, int64_t n, double* sq, double* dv,
-                                void* stream) {
-  if (n < 0 || (n > 0 && (!a || !b || !sq || !dv))) return fail(NB_EINVAL, "bad arguments");
-  long long nn = n;
-  void* args[] = {&a, &b, &nn, &sq, &dv};
-  int rc = launch_1d((const void*)&k_test_sqrt_div, n, args, (hipStream_t)stream);
-  if (rc) return rc;
-  NB_HIP(hipStreamSynchronize((hipStream_t)stream));
-  return NB_OK;
-}
-extern "C" int nb_test_exp3(const double* k9, const double* psi6, int64_t n, double* out6, void* stream) {
-  if (n < 0 || (n > 0 && (!k9 || !psi6 || !out6))) return fail(NB_EINVAL, "bad arguments");
-  long long nn = n;
-  void* args[] = {&k9, &psi6, &nn, &out6};
-  int rc = launch_1d((const void*)&k_test_exp3, n, args, (hipStream_t)stream);
-  if (rc) return rc;
-  NB_HIP(hipStreamSynchronize((hipStream_t)stream));
-  return NB_OK;
-}
-extern "C" int nb_test_rotate(const double* x3, const double* p3, int64_t n, double* out3, void* stream) {
-  if (n < 0 || (n > 0 && (!x3 || !p3 || !out3))) return fail(NB_EINVAL, "bad arguments");
-  long long nn = n;
-  void* args[] = {&x3, &p3, &nn, &out3};
-  int rc = launch_1d((const void*)&k_test_rotate, n, args, (hipStream_t)stream);
-  if (rc) return rc;
-  NB_HIP(hipStreamSynchronize((hipStream_t)stream));
   return NB_OK;
 }

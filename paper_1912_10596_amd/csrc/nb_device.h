@@ -121,10 +121,17 @@ __device__ __forceinline__ double i128_to_double(I128 x) {
 }
 // trunc(v * scale) as an integer; flags values outside (-limit, limit) (NaN included).
 // Used for the per-angle J0 terms (limit 2^62).
+// Status bits a lane reports (the kernels OR them into the status word at the end of a
+// launch): 1 = a moment contribution left its fixed-point range (or a state norm reached 2,
+// NaN included); 8 = a renormalisation met |psi|^2 (|P|^2) further from 1 than the
+// rounding of a unitary step can explain: kRenormTol for FP64 states, kRenormTol32 for
+// FP32-stored states (their own rounding is ~6e-8).
+constexpr double kRenormTol = 1e-8;
+constexpr double kRenormTol32 = 1e-5;
 __device__ __forceinline__ long long to_fix(double v, double scale, double limit, int& err) {
   const double x = v * scale;
   if (!(fabs(x) < limit)) {
-    err = 1;
+    err |= 1;
     return 0;
   }
   return (long long)x;

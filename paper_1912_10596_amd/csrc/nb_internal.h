@@ -15,7 +15,9 @@ constexpr int kMaxBlocks = 2048;  // upper bound on blocks of one stepping launc
 constexpr int kLineWords = 32;
 constexpr int kFlagCopies = 8;
 constexpr int kSyncAbort = 1 * kLineWords;   // set when any block gives up waiting
-constexpr int kSyncStatus = 2 * kLineWords;  // bit 0: fixed-point range error, bit 1: barrier timeout
+constexpr int kSyncStatus = 2 * kLineWords;  // bit 0: fixed-point range error, bit 1: barrier timeout,
+                                             // bit 2: cancelled by the host, bit 3: renormalisation
+                                             // factor far from 1
 constexpr int kSyncFlag = 4 * kLineWords;    // [kFlagCopies] lines: epoch + 1 of the last release
 constexpr int kSyncArrive = kSyncFlag + kFlagCopies * kLineWords;  // [kMaxBlocks] lines
 // Tagged 64-bit words of the moment reductions (every word carries the barrier epoch it
@@ -30,7 +32,9 @@ constexpr int kSyncWords = kSyncPart + 2 * kMaxBlocks * kTagLines * kLineWords;
 constexpr int kTagWords64 = kTagLines * kLineWords / 2;   // 64-bit words per copy or slot
 
 constexpr int kVacRows3 = 7;    // 3f table rows before the weights: 6 vacuum entries and e_k
-constexpr int kBlock = 512;       // threads per block of the stepping kernels (8 waves)
+constexpr int kBlock = 512;       // threads per block: the most a stepping launch uses (8 waves),
+                                  // the size of their per-block LDS arrays
+constexpr int kBlockSmall = 256;  // the other block size of the fixed-step kernels (4 waves)
 
 // Arguments of the single-model stepping kernel (passed by value).
 struct StepArgs {
@@ -52,6 +56,7 @@ struct StepArgs {
   double s1, s0, p2e1, p2e0;  // fixed-point scales 2^e1, 2^e0, 2^-e1, 2^-e0
   double v0[6];            // 3f: the vacuum Hamiltonian times E (entries of bin k = e_k v0)
   unsigned long long timeout_ticks;
+  const unsigned* cancel;  // the model's cancel word (fine-grained host memory), or nullptr
   double* Jhist;           // nullptr, or [step][4][2*NC]: every stage's moments (adjoint tape)
   int use_window;          // 0: advance min(nsteps, total - step) steps; 1: the window below
   long long win_lo, win_hi;// windowed launch: only steps in [win_lo, win_hi), up to step_ctl[1]
@@ -99,6 +104,7 @@ struct BatchArgs {
   double rs, h, R;
   int ne_power, renorm;
   unsigned long long timeout_ticks;
+  const unsigned* cancel;
 };
 
 // Arguments of the two-flavour reverse (adjoint) kernel.  Beam b belongs to thread
@@ -122,6 +128,7 @@ struct AdjArgs {
   double rs, h, R, lam0, s2gf;
   int ne_power, renorm;
   unsigned long long timeout_ticks;
+  const unsigned* cancel;
 };
 
 }  // namespace nb

@@ -10,8 +10,8 @@
 //   4. accumulates the beam's moment contribution as a 64-bit fixed-point integer; the
 //      row's energy sum is a wavefront butterfly of 128-bit integers, then the angle sum
 //      (1/cos weighting for J0) is added to per-lane totals,
-// then the block folds its waves through LDS and the grid meets at a barrier whose last
-// arriving block folds all block partials into J^(i) (agent-scope release/acquire).
+// then the block folds its waves through LDS, publishes its partial as epoch-tagged words,
+// and every block gathers all partials into J^(i) (no release flag; agent-scope atomics).
 // Four barriers per step; the final pass writes rho_{n+1} and also produces the next
 // step's stage-1 moments.
 #include "nb_device.h"
@@ -63,11 +63,13 @@ __device__ __forceinline__ long long chunk_value(unsigned long long field, int k
 // the values); every block takes the largest field, which lands in *sE.
 // NM moment groups of NV / NM components: J0 | J1 (| J_sc | J_ss); J1 is at scale 2^e1,
 // the others at 2^e0.
-template <int NV, bool MAXE, int NM = 2>
+// BS: threads per block (the launch's block size), so that the thread groups and every
+// poll address are compile-time constants.
+template <int NV, bool MAXE, int NM, int BS>
 __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, long long own,
                             unsigned long long efield, double* sJ, long long* sacc, double* sE) {
   constexpr int W = 2 * NV + (MAXE ? 1 : 0);   // words per partial
-  constexpr int G = kBlock / W;                // thread groups, one chunk position per thread
+  constexpr int G = BS / W;                    // thread groups, one chunk position per thread
   static_assert(W <= kTagWords64, "tagged slot too small");
   const int tid = threadIdx.x;
   const unsigned want = epoch + 1u;
@@ -108,7 +110,7 @@ __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, long lo
           }
         }
         if (!pend) break;
-        if ((it & 31u) == 0u && give_up(a.sync, t0, a.timeout_ticks)) {
+        if ((it & 31u) == 0u && give_up(a.sync, a.cancel, t0, a.timeout_ticks, it)) {
           ok = 0;
           break;
         }
@@ -138,11 +140,11 @@ __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, long lo
 
 // Fold the waves' per-lane totals (lane v holds value v) and run the grid reduction.
 // MAXE: also the largest of the lanes' error estimates emax (then swm holds one double per
-// wave and the grid's largest estimate lands in *sE).
-template <int NV, bool MAXE = false, int NM = 2>
-__device__ bool finish_stage(const StepArgs& a, unsigned epoch, I128 T, I128 (*sw)[NV],
-                             long long* sacc, double* sJ, double emax = 0.0, double* swm = nullptr,
-                             double* sE = nullptr) {
+// wave and the grid's largest estimate lands in *sE).  BS: threads per block.
+template <int NV, bool MAXE, int NM, int BS>
+__device__ bool finish_stage_bs(const StepArgs& a, unsigned epoch, I128 T, I128 (*sw)[NV],
+                                long long* sacc, double* sJ, double emax, double* swm, double* sE) {
+  constexpr int WPB = BS / 64;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane < NV) sw[wid][lane] = T;
   if constexpr (MAXE) {
@@ -158,22 +160,23 @@ __device__ bool finish_stage(const StepArgs& a, unsigned epoch, I128 T, I128 (*s
   long long own = 0;
   unsigned long long efield = 0;
   if (threadIdx.x < NV)
-    for (int w = 0; w < kBlock / 64; ++w) blk = i128_add(blk, sw[w][threadIdx.x]);
+    for (int w = 0; w < WPB; ++w) blk = i128_add(blk, sw[w][threadIdx.x]);
   if (blockIdx.x == 0 && threadIdx.x < 2 * NV) {
     I128 c = i128_zero();
-    for (int w = 0; w < kBlock / 64; ++w) c = i128_add(c, sw[w][threadIdx.x >> 1]);
+    for (int w = 0; w < WPB; ++w) c = i128_add(c, sw[w][threadIdx.x >> 1]);
     own = chunk_value(chunk_field(c, threadIdx.x & 1), threadIdx.x & 1);
   }
   if constexpr (MAXE) {
     if (threadIdx.x == NV || (blockIdx.x == 0 && threadIdx.x == 2 * NV)) {
       double m = 0.0;
-      for (int w = 0; w < kBlock / 64; ++w) m = (swm[w] > m) ? swm[w] : m;
+      for (int w = 0; w < WPB; ++w) m = (swm[w] > m) ? swm[w] : m;
       efield = as_bits(m) >> 16;
       if (threadIdx.x == 2 * NV) own = (long long)efield;
     }
   }
-  return grid_reduce<NV, MAXE, NM>(a, epoch, blk, own, efield, sJ, sacc, sE);
+  return grid_reduce<NV, MAXE, NM, BS>(a, epoch, blk, own, efield, sJ, sacc, sE);
 }
+
 
 // Radii and length of one step: stage radii r0, rm = r0 + h/2 and r1.  On the fixed grid
 // r1 = r_start + (n + 1) h (not r0 + h), as in the serial definition.
@@ -418,6 +421,7 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
           rotate2<true>(t0, t1, t2, P0, P1, P2, sct);
           if (renorm) {
             const double nrm2 = (P0 * P0 + P1 * P1) + P2 * P2;
+            if (!(fabs(nrm2 - 1.0) <= kRenormTol)) err |= 8;
             const double inv = fma(-0.5, nrm2, 1.5);   // one Newton step for 1/sqrt from 1
             P0 = P0 * inv;
             P1 = P1 * inv;
@@ -429,7 +433,7 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
         }
       }
       // rho~: rho for neutrinos, -rho^* (Bloch (-x, y, -z)) for antineutrinos
-      if (!(fma(P0, P0, fma(P1, P1, P2 * P2)) < 2.0)) err = 1;
+      if (!(fma(P0, P0, fma(P1, P1, P2 * P2)) < 2.0)) err |= 1;
       const double ws = G[k] * cb[kC2Sc + 0];
       const double wa = an ? -ws : ws;
       acc[0] += fix_bits(P0, wa);
@@ -711,6 +715,7 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
           exp3_apply(Th, ps);
           if (a.renorm) {
             const double nrm2 = (norm2(ps[0]) + norm2(ps[1])) + norm2(ps[2]);
+            if (!(fabs(nrm2 - 1.0) <= (sizeof(ST) == 8 ? kRenormTol : kRenormTol32))) err |= 8;
             const double inv = fma(-0.5, nrm2, 1.5);   // one Newton step for 1/sqrt from 1
 #pragma unroll
             for (int c = 0; c < 3; ++c) ps[c] = mk(ps[c].re * inv, ps[c].im * inv);
@@ -730,7 +735,7 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
       const double n0 = norm2(ps[0]), nm = norm2(ps[1]), nt = norm2(ps[2]);
       const cplx em = cmul_conjb(ps[0], ps[1]), et = cmul_conjb(ps[0], ps[2]), mt = cmul_conjb(ps[1], ps[2]);
       const double v8[8] = {n0 - nt, nm - nt, em.re, em.im, et.re, et.im, mt.re, mt.im};
-      if (!((n0 + nm) + nt < 2.0)) err = 1;
+      if (!((n0 + nm) + nt < 2.0)) err |= 1;
       const double ws = G[k] * a.s1;
       const double wa = an ? -ws : ws;    // the negated components of -rho^*
 #pragma unroll
@@ -877,6 +882,7 @@ __device__ __forceinline__ void row3m(const StepArgs& a, long long row, const Ra
           // 1/sqrt(nrm2) by one Newton step from 1: nrm2 = 1 + d with |d| ~ 1e-7 (a unit
           // FP32-stored state and an increment accurate to FP32), so the error 3 d^2 / 8 is
           // far below FP32 storage precision
+          if (a.renorm && !(fabs(nrm2 - 1.0) <= kRenormTol32)) err |= 8;
           const double inv = fma(-0.5, nrm2, 1.5);
           const float o[6] = {(float)(re0 * inv), (float)(im0 * inv), (float)(re1 * inv),
                               (float)(im1 * inv), (float)(re2 * inv), (float)(im2 * inv)};
@@ -934,34 +940,37 @@ __device__ __forceinline__ void stage3m(const StepArgs& a, const StepGeo& G, con
 // The energy tables (vacuum terms and weights) are staged into LDS once per launch
 // when TLDS (they are read by every row).
 // EXT: the extended bulb model (azimuthal bins, four moments); FP64 only.
-template <int NF, typename ST, bool TLDS, bool F32, bool EXT>
+// BS: threads per block (512 or 256; every array and loop bound below is a constant).
+template <int NF, typename ST, bool TLDS, bool F32, bool EXT, int BS>
 __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   constexpr int NC = (NF == 2) ? 3 : 8;
   constexpr int NM = EXT ? 4 : 2;
   constexpr int NV = NM * NC;
+  constexpr int WPB = BS / 64;
   __shared__ double sJ[4][NV];
-  __shared__ I128 sw[kBlock / 64][NV];
-  __shared__ long long sacc[kBlock];
+  __shared__ I128 sw[WPB][NV];
+  __shared__ long long sacc[BS];
   // per wavefront: row constants (mixed: then 32 floats), then the first row's geometry
-  __shared__ double snn_all[kBlock / 64][F32 ? 64 : 48];
-  __shared__ long long sfold[kBlock / 64][(NC + 2) * 64];
+  __shared__ double snn_all[WPB][F32 ? 64 : 48];
+  __shared__ long long sfold[WPB][(NC + 2) * 64];
   __shared__ double s_sct[kSinCosTab];   // sin/cos constants of the two-flavour rotations
   extern __shared__ __align__(16) double dyn_tab[];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const long long gw = (long long)blockIdx.x * (kBlock / 64) + wid;
-  const long long nw = (long long)gridDim.x * (kBlock / 64);
+  const long long gw = (long long)blockIdx.x * WPB + wid;
+  const long long nw = (long long)gridDim.x * WPB;
   const double* tab = a.tab;
   const float* ftab = nullptr;
+  if (launch_aborted(a.sync)) return;
   if (NF == 2 && threadIdx.x == 0) sincos_coefs(s_sct);
   if constexpr (NF == 2) __syncthreads();
   if constexpr (TLDS) {
     const int ntab = ((NF == 2) ? 2 : kVacRows3) * a.NE + a.NS * a.NE;
-    for (int i = threadIdx.x; i < ntab; i += kBlock) dyn_tab[i] = a.tab[i];
+    for (int i = threadIdx.x; i < ntab; i += BS) dyn_tab[i] = a.tab[i];
     if constexpr (F32) {
       // the FP32 copy of the vacuum rows and e_k, eight floats per energy, after the table
       // (at a 16-byte boundary)
       float* ft = reinterpret_cast<float*>(dyn_tab + ((ntab + 1) & ~1));
-      for (int i = threadIdx.x; i < 8 * a.NE; i += kBlock) {
+      for (int i = threadIdx.x; i < 8 * a.NE; i += BS) {
         const int k = i >> 3, c = i & 7;
         ft[i] = (c < 7) ? (float)a.tab[c * a.NE + k] : 0.0f;
       }
@@ -1002,7 +1011,7 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
     if constexpr (NF == 2) stage2<0, false, EXT>(a, geo_fixed(a, step0), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct);
     else if constexpr (F32) stage3m<0, TLDS>(a, geo_fixed(a, step0), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err);
     else { stage3<ST, 0, false, EXT>(a, geo_fixed(a, step0), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
-    ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[0]);
+    ok = finish_stage_bs<NV, false, NM, BS>(a, epoch++, T, sw, sacc, sJ[0], 0.0, nullptr, nullptr);
   }
   // the adjoint's forward pass records every stage's moments: [step][slot][NV]
   auto record = [&](long long step, int slot) {
@@ -1015,28 +1024,28 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
     if constexpr (NF == 2) stage2<1, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, true);
     else if constexpr (F32) stage3m<1, TLDS>(a, geo_fixed(a, n), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err, gc);
     else { stage3<ST, 1, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
-    if (!(ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[1]))) break;
+    if (!(ok = finish_stage_bs<NV, false, NM, BS>(a, epoch++, T, sw, sacc, sJ[1], 0.0, nullptr, nullptr))) break;
     record(n, 1);
     T = i128_zero();
     if constexpr (NF == 2) stage2<2, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, true);
     else if constexpr (F32) stage3m<2, TLDS>(a, geo_fixed(a, n), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err, gc);
     else { stage3<ST, 2, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
-    if (!(ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[2]))) break;
+    if (!(ok = finish_stage_bs<NV, false, NM, BS>(a, epoch++, T, sw, sacc, sJ[2], 0.0, nullptr, nullptr))) break;
     record(n, 2);
     T = i128_zero();
     if constexpr (NF == 2) stage2<3, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, true);
     else if constexpr (F32) stage3m<3, TLDS>(a, geo_fixed(a, n), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err, gc);
     else { stage3<ST, 3, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
-    if (!(ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[3]))) break;
+    if (!(ok = finish_stage_bs<NV, false, NM, BS>(a, epoch++, T, sw, sacc, sJ[3], 0.0, nullptr, nullptr))) break;
     record(n, 3);
     T = i128_zero();
     if constexpr (NF == 2) stage2<4, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, true);
     else if constexpr (F32) stage3m<4, TLDS>(a, geo_fixed(a, n), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err, gc);
     else { stage3<ST, 4, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
-    ok = finish_stage<NV, false, NM>(a, epoch++, T, sw, sacc, sJ[0]);
+    ok = finish_stage_bs<NV, false, NM, BS>(a, epoch++, T, sw, sacc, sJ[0], 0.0, nullptr, nullptr);
     record(n + 1, 0);
   }
-  if (err) __hip_atomic_fetch_or(a.sync + kSyncStatus, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (err) __hip_atomic_fetch_or(a.sync + kSyncStatus, (unsigned)err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   // every block read the start step before the first barrier; block 0 passes the last, and
   // leaves the moments of the new state for the next launch
   if (ok && blockIdx.x == 0) {
@@ -1049,18 +1058,30 @@ __global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
   }
 }
 
-template __global__ void k_advance<2, double, true, false, false>(StepArgs);
-template __global__ void k_advance<2, double, false, false, false>(StepArgs);
-template __global__ void k_advance<3, double, true, false, false>(StepArgs);
-template __global__ void k_advance<3, double, false, false, false>(StepArgs);
-template __global__ void k_advance<3, float, true, false, false>(StepArgs);
-template __global__ void k_advance<3, float, false, false, false>(StepArgs);
-template __global__ void k_advance<3, float, true, true, false>(StepArgs);
-template __global__ void k_advance<3, float, false, true, false>(StepArgs);
-template __global__ void k_advance<2, double, true, false, true>(StepArgs);
-template __global__ void k_advance<2, double, false, false, true>(StepArgs);
-template __global__ void k_advance<3, double, true, false, true>(StepArgs);
-template __global__ void k_advance<3, double, false, false, true>(StepArgs);
+template __global__ void k_advance<2, double, true, false, false, kBlock>(StepArgs);
+template __global__ void k_advance<2, double, false, false, false, kBlock>(StepArgs);
+template __global__ void k_advance<3, double, true, false, false, kBlock>(StepArgs);
+template __global__ void k_advance<3, double, false, false, false, kBlock>(StepArgs);
+template __global__ void k_advance<3, float, true, false, false, kBlock>(StepArgs);
+template __global__ void k_advance<3, float, false, false, false, kBlock>(StepArgs);
+template __global__ void k_advance<3, float, true, true, false, kBlock>(StepArgs);
+template __global__ void k_advance<3, float, false, true, false, kBlock>(StepArgs);
+template __global__ void k_advance<2, double, true, false, true, kBlock>(StepArgs);
+template __global__ void k_advance<2, double, false, false, true, kBlock>(StepArgs);
+template __global__ void k_advance<3, double, true, false, true, kBlock>(StepArgs);
+template __global__ void k_advance<3, double, false, false, true, kBlock>(StepArgs);
+template __global__ void k_advance<2, double, true, false, false, kBlockSmall>(StepArgs);
+template __global__ void k_advance<2, double, false, false, false, kBlockSmall>(StepArgs);
+template __global__ void k_advance<3, double, true, false, false, kBlockSmall>(StepArgs);
+template __global__ void k_advance<3, double, false, false, false, kBlockSmall>(StepArgs);
+template __global__ void k_advance<3, float, true, false, false, kBlockSmall>(StepArgs);
+template __global__ void k_advance<3, float, false, false, false, kBlockSmall>(StepArgs);
+template __global__ void k_advance<3, float, true, true, false, kBlockSmall>(StepArgs);
+template __global__ void k_advance<3, float, false, true, false, kBlockSmall>(StepArgs);
+template __global__ void k_advance<2, double, true, false, true, kBlockSmall>(StepArgs);
+template __global__ void k_advance<2, double, false, false, true, kBlockSmall>(StepArgs);
+template __global__ void k_advance<3, double, true, false, true, kBlockSmall>(StepArgs);
+template __global__ void k_advance<3, double, false, false, true, kBlockSmall>(StepArgs);
 
 // --------------------------------------------------------------- adaptive step control
 // One persistent launch integrates from r (step_ctl[kCtlR]) with the step length
@@ -1087,6 +1108,7 @@ __global__ void __launch_bounds__(kBlock) k_adaptive(StepArgs a) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const long long gw = (long long)blockIdx.x * (kBlock / 64) + wid;
   const long long nw = (long long)gridDim.x * (kBlock / 64);
+  if (launch_aborted(a.sync)) return;
   const double* tab = a.tab;
   if (NF == 2 && threadIdx.x == 0) sincos_coefs(s_sct);
   if constexpr (NF == 2) __syncthreads();
@@ -1120,7 +1142,7 @@ __global__ void __launch_bounds__(kBlock) k_adaptive(StepArgs a) {
   using K3 = std::integral_constant<int, 3>;
   using K4 = std::integral_constant<int, 4>;
   stage(K0{}, StepGeo{r, r, r, 0.0});
-  bool ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[0]);
+  bool ok = finish_stage_bs<NV, false, 2, kBlock>(a, epoch++, T, sw, sacc, sJ[0], 0.0, nullptr, nullptr);
   if (threadIdx.x < NV) sJsave[threadIdx.x] = sJ[0][threadIdx.x];
   while (ok) {
     const bool last = (r + h >= a.r_end);
@@ -1128,17 +1150,17 @@ __global__ void __launch_bounds__(kBlock) k_adaptive(StepArgs a) {
     const StepGeo G{r, r + 0.5 * hs, last ? a.r_end : r + hs, hs};
     T = i128_zero();
     stage(K1{}, G);
-    if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[1]))) break;
+    if (!(ok = finish_stage_bs<NV, false, 2, kBlock>(a, epoch++, T, sw, sacc, sJ[1], 0.0, nullptr, nullptr))) break;
     T = i128_zero();
     stage(K2{}, G);
-    if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[2]))) break;
+    if (!(ok = finish_stage_bs<NV, false, 2, kBlock>(a, epoch++, T, sw, sacc, sJ[2], 0.0, nullptr, nullptr))) break;
     T = i128_zero();
     stage(K3{}, G);
-    if (!(ok = finish_stage<NV>(a, epoch++, T, sw, sacc, sJ[3]))) break;
+    if (!(ok = finish_stage_bs<NV, false, 2, kBlock>(a, epoch++, T, sw, sacc, sJ[3], 0.0, nullptr, nullptr))) break;
     T = i128_zero();
     emax = 0.0;
     stage(K4{}, G);
-    if (!(ok = finish_stage<NV, true>(a, epoch++, T, sw, sacc, sJ[0], emax, swm, sE))) break;
+    if (!(ok = finish_stage_bs<NV, true, 2, kBlock>(a, epoch++, T, sw, sacc, sJ[0], emax, swm, sE))) break;
     ++natt;
     const double E = *sE;
     if (E <= a.tol2) {
@@ -1174,7 +1196,7 @@ __global__ void __launch_bounds__(kBlock) k_adaptive(StepArgs a) {
 #pragma unroll
         for (int c = 0; c < nsc; ++c) D[row * a.NE + k + c * a.plane] = X[row * a.NE + k + c * a.plane];
   }
-  if (err) __hip_atomic_fetch_or(a.sync + kSyncStatus, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (err) __hip_atomic_fetch_or(a.sync + kSyncStatus, (unsigned)err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (ok && blockIdx.x == 0 && threadIdx.x == 0) {
     ctl[kCtlR] = (long long)as_bits(r);
     ctl[kCtlH] = (long long)as_bits(h);
@@ -1228,8 +1250,8 @@ __device__ __forceinline__ unsigned long long* acc_slot(const BatchArgs& a, unsi
 // agent-scope atomics before the workgroup barrier inside the arrival).
 __device__ bool grid_barrier(const BatchArgs& a, unsigned epoch) {
   const unsigned want = epoch + 1u;
-  if (blockIdx.x != 0) return arrive_and_wait(a.sync, a.timeout_ticks, want);
-  if (!wait_arrivals(a.sync, a.timeout_ticks, want)) return false;
+  if (blockIdx.x != 0) return arrive_and_wait(a.sync, a.cancel, a.timeout_ticks, want);
+  if (!wait_arrivals(a.sync, a.cancel, a.timeout_ticks, want)) return false;
   release_grid(a.sync, want);
   return true;
 }
@@ -1294,7 +1316,7 @@ __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, lon
   // clear the set the next epoch will collect into
   if (blockIdx.x == 0) {
     unsigned long long* z = a.acc + (size_t)((epoch + 1u) % kAccSets) * a.nmodels * 6 * kAccLimbs;
-    for (int i = threadIdx.x; i < a.nmodels * 6 * kAccLimbs; i += kBlock)
+    for (int i = threadIdx.x; i < a.nmodels * 6 * kAccLimbs; i += blockDim.x)
       __hip_atomic_store(z + i, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -1302,16 +1324,18 @@ __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, lon
 // Four wavefronts per SIMD (128 VGPRs): the rows of a batch are short (50-400 energies),
 // so a wave spends much of its time on row set-up and the first load of each row, which
 // more wavefronts hide (measured: 4.35 -> 4.20 ms per step on the 256-model batch).
+template <int BS>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_batch2(BatchArgs a) {
-  __shared__ double sJw[kBlock / 64][4][6];
-  __shared__ long long sfold[kBlock / 64][(3 + 2) * 64];
-  __shared__ double scb[kBlock / 64][kC2Size];
+  __shared__ double sJw[BS / 64][4][6];
+  __shared__ long long sfold[BS / 64][(3 + 2) * 64];
+  __shared__ double scb[BS / 64][kC2Size];
   __shared__ double s_sct[kSinCosTab];   // sin/cos constants of the rotations
+  if (launch_aborted(a.sync)) return;
   if (threadIdx.x == 0) sincos_coefs(s_sct);
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   double (*Jv)[6] = sJw[wid];
-  const long long w = (long long)blockIdx.x * (kBlock / 64) + wid;
+  const long long w = (long long)blockIdx.x * (BS / 64) + wid;
   const long long r0w = min(max(a.wave_row0[w], 0LL), a.total_rows);
   const long long r1w = min(max(a.wave_row0[w + 1], r0w), a.total_rows);
   const long long step0 = *a.step_ctl;
@@ -1331,9 +1355,11 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     batch_stage<4>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], scb[wid], s_sct, err);
     ok = grid_barrier(a, epoch++);
   }
-  if (err) __hip_atomic_fetch_or(a.sync + kSyncStatus, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (err) __hip_atomic_fetch_or(a.sync + kSyncStatus, (unsigned)err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (ok && blockIdx.x == 0 && threadIdx.x == 0) *a.step_ctl = step0 + nsteps;
 }
+template __global__ void k_batch2<kBlock>(BatchArgs);
+template __global__ void k_batch2<kBlockSmall>(BatchArgs);
 
 // ----------------------------------------------------------------- small kernels
 __global__ void k_zero_u64(unsigned long long* p, long long n) {
@@ -1356,9 +1382,23 @@ __global__ void k_set_target(long long* step_ctl, long long k, long long total) 
   step_ctl[1] = min(step_ctl[0] + k, total);
 }
 
-__global__ void k_zero_sync(unsigned int* sync, int keep_status) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kSyncWords; i += gridDim.x * blockDim.x)
-    if (!(keep_status && i == kSyncStatus)) sync[i] = 0u;
+// Clear the barrier and reduction words before a persistent launch (keep_status: keep the
+// status bits of earlier launches of the same call).  If the host has set the model's
+// cancel word (fine-grained host memory; nullptr: none), the abort word is set instead of
+// cleared, with status bit 2, so that the next persistent launch returns at once.
+__global__ void k_zero_sync(unsigned int* sync, int keep_status, const unsigned* cancel) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kSyncWords; i += gridDim.x * blockDim.x) {
+    if (i == kSyncStatus) continue;   // written with the abort word
+    if (i == kSyncAbort) {
+      const unsigned c =
+          cancel ? __hip_atomic_load(cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) : 0u;
+      const unsigned st = keep_status ? sync[kSyncStatus] : 0u;
+      sync[kSyncAbort] = c ? 1u : 0u;
+      sync[kSyncStatus] = st | (c ? 4u : 0u);
+      continue;
+    }
+    sync[i] = 0u;
+  }
 }
 
 // Initial flavour eigenstates (Sec. 3.4): species row s = b / per_species is born in
@@ -1405,44 +1445,5 @@ __global__ void k_state_xfer(ST* X, long long nb, long long plane, int nsc, doub
 }
 template __global__ void k_state_xfer<double>(double*, long long, long long, int, double*, int);
 template __global__ void k_state_xfer<float>(float*, long long, long long, int, double*, int);
-
-// ------------------------------------------------------------------- test hooks
-__global__ void k_test_sincos(const double* x, long long n, double* s, double* c) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double a, b;
-  sincos_nb(x[i], a, b);
-  s[i] = a;
-  c[i] = b;
-}
-__global__ void k_test_sqrt_div(const double* a, const double* b, long long n, double* sq, double* dv) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  sq[i] = sqrt(a[i]);
-  dv[i] = a[i] / b[i];
-}
-__global__ void k_test_exp3(const double* k9, const double* psi6, long long n, double* out6) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double* k = k9 + 9 * i;
-  const Herm3 K{k[0], k[1], k[2], mk(k[3], k[4]), mk(k[5], k[6]), mk(k[7], k[8])};
-  const double* p = psi6 + 6 * i;
-  cplx ps[3] = {mk(p[0], p[1]), mk(p[2], p[3]), mk(p[4], p[5])};
-  exp3_apply(K, ps);
-  double* o = out6 + 6 * i;
-  for (int c = 0; c < 3; ++c) {
-    o[2 * c] = ps[c].re;
-    o[2 * c + 1] = ps[c].im;
-  }
-}
-__global__ void k_test_rotate(const double* x3, const double* p3, long long n, double* out3) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double P0 = p3[3 * i], P1 = p3[3 * i + 1], P2 = p3[3 * i + 2];
-  rotate2(x3[3 * i], x3[3 * i + 1], x3[3 * i + 2], P0, P1, P2);
-  out3[3 * i] = P0;
-  out3[3 * i + 1] = P1;
-  out3[3 * i + 2] = P2;
-}
 
 }  // namespace nb

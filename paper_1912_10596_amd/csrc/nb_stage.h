@@ -35,37 +35,50 @@ __device__ __forceinline__ unsigned long long as_bits(double d) { return (unsign
 // published data only after it has read the word that announces them.  So the barrier
 // needs no cache maintenance at all: the state written in the same stage stays in L2.
 
-// Checked every 32nd poll of a wait: true if another block has aborted, or if this wait,
-// begun at t0, has passed the launch's time limit (then it sets the abort word and status
-// bit 1 so that every other waiter gives up too).
-__device__ __forceinline__ bool give_up(unsigned* sync, unsigned long long t0,
-                                        unsigned long long timeout_ticks) {
+// Checked every 32nd poll (it) of a wait: true if another block has aborted, or if this
+// wait, begun at t0, has passed the launch's time limit (then it sets the abort word and
+// status bit 1 so that every other waiter gives up too), or -- every 1024th poll -- if the
+// host has set the model's cancel word, a word of fine-grained host memory (then it sets
+// the abort word and status bit 2).
+__device__ __forceinline__ bool give_up(unsigned* sync, const unsigned* cancel, unsigned long long t0,
+                                        unsigned long long timeout_ticks, unsigned it) {
   if (__hip_atomic_load(sync + kSyncAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return true;
-  if (wall_clock64() - t0 > timeout_ticks) {
-    __hip_atomic_store(sync + kSyncAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_or(sync + kSyncStatus, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return true;
-  }
-  return false;
+  unsigned bit = 0u;
+  if (wall_clock64() - t0 > timeout_ticks) bit = 2u;
+  else if (cancel && (it & 1023u) == 0u &&
+           __hip_atomic_load(cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))
+    bit = 4u;
+  if (!bit) return false;
+  __hip_atomic_store(sync + kSyncAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_or(sync + kSyncStatus, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return true;
+}
+// Read at the start of a persistent launch (all threads of the block call this; thread 0
+// reads, the block shares its answer): the abort word, set before the launch by the
+// sync-word clear when the host had cancelled the model (every block then returns at once,
+// leaving the state as it was), or during it by a block that gave up.
+__device__ __forceinline__ bool launch_aborted(const unsigned* sync) {
+  return __syncthreads_or(threadIdx.x == 0 &&
+                          __hip_atomic_load(sync + kSyncAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u);
 }
 
 // Poll *w (relaxed) until it reaches want; gives up when another block has aborted or the
 // launch's time limit passes (then it sets the abort word and status bit 1).  The abort
 // word and the clock are read only every 32nd poll, so a poll costs one load round trip.
-__device__ __forceinline__ bool poll_until(unsigned* sync, unsigned long long timeout_ticks, unsigned* w,
-                                           unsigned want) {
+__device__ __forceinline__ bool poll_until(unsigned* sync, const unsigned* cancel,
+                                           unsigned long long timeout_ticks, unsigned* w, unsigned want) {
   const unsigned long long t0 = wall_clock64();
   for (unsigned it = 1;; ++it) {
     if (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want) return true;
-    if ((it & 31u) == 0u && give_up(sync, t0, timeout_ticks)) return false;
+    if ((it & 31u) == 0u && give_up(sync, cancel, t0, timeout_ticks, it)) return false;
     __builtin_amdgcn_s_sleep(1);
   }
 }
 // Block 0 of a barrier (all its threads call this): the first wavefront polls every other
 // block's arrival word, all of a lane's words per round so that their loads overlap.
 // Returns false on give-up.
-__device__ __forceinline__ bool wait_arrivals(unsigned* sync, unsigned long long timeout_ticks,
-                                              unsigned want) {
+__device__ __forceinline__ bool wait_arrivals(unsigned* sync, const unsigned* cancel,
+                                              unsigned long long timeout_ticks, unsigned want) {
   int ok = 1;
   if (threadIdx.x < 64) {
     const unsigned long long t0 = wall_clock64();
@@ -75,7 +88,7 @@ __device__ __forceinline__ bool wait_arrivals(unsigned* sync, unsigned long long
         lowest = min(lowest, __hip_atomic_load(sync + kSyncArrive + b * kLineWords, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT));
       if (lowest >= want) break;
-      if ((it & 31u) == 0u && give_up(sync, t0, timeout_ticks)) {
+      if ((it & 31u) == 0u && give_up(sync, cancel, t0, timeout_ticks, it)) {
         ok = 0;
         break;
       }
@@ -86,15 +99,15 @@ __device__ __forceinline__ bool wait_arrivals(unsigned* sync, unsigned long long
 }
 // A non-zero block arrives (all its threads call this, after their partial stores) and
 // waits for block 0's release flag.  Returns false on give-up.
-__device__ __forceinline__ bool arrive_and_wait(unsigned* sync, unsigned long long timeout_ticks,
-                                                unsigned want) {
+__device__ __forceinline__ bool arrive_and_wait(unsigned* sync, const unsigned* cancel,
+                                                unsigned long long timeout_ticks, unsigned want) {
   __shared__ int s_ok;
   __syncthreads();
   if (threadIdx.x == 0) {
     __hip_atomic_store(sync + kSyncArrive + blockIdx.x * kLineWords, want, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
-    s_ok = poll_until(sync, timeout_ticks, sync + kSyncFlag + (blockIdx.x % kFlagCopies) * kLineWords, want)
-               ? 1 : 0;
+    s_ok = poll_until(sync, cancel, timeout_ticks, sync + kSyncFlag + (blockIdx.x % kFlagCopies) * kLineWords,
+                      want) ? 1 : 0;
   }
   __syncthreads();
   return s_ok != 0;

@@ -20,14 +20,34 @@ def nb():
     return nb
 
 
-def test_every_declared_symbol_is_exported(nb):
-    hdr = open(os.path.join(ROOT, "include", "nubulb.h")).read()
+def _declared(header):
+    hdr = open(os.path.join(ROOT, "include", header)).read()
     declared = set(re.findall(r"\b(nb_[a-z0-9_]+)\s*\(", hdr))
     assert declared, "no declarations found"
+    return declared
+
+
+def test_every_declared_symbol_is_exported(nb):
+    declared = _declared("nubulb.h")
     L = nb.lib()
     for name in sorted(declared):
         assert hasattr(L, name), f"{name} not exported"
     assert declared == set(nb.EXPORTS)
+    # the arithmetic test hooks live in their own library, not in the stepper's ABI
+    assert not any(n.startswith("nb_test_") for n in declared)
+
+
+def test_test_hook_library_exports_its_header():
+    from paper_1912_10596_amd import testhooks
+    if not os.path.exists(testhooks.LIB_PATH):
+        pytest.fail("libnubulb_testhooks.so not built (run __graft_entry__.build())")
+    declared = _declared("nubulb_testhooks.h")
+    L = testhooks.lib()
+    for name in sorted(declared):
+        assert hasattr(L, name), f"{name} not exported"
+    assert declared == set(testhooks.EXPORTS)
+    import paper_1912_10596_amd as nb
+    assert not hasattr(nb.lib(), "nb_test_sincos")
 
 
 XBAR = dict(lum_xbar_erg_s=2.3e51, temp_xbar_mev=5.1)
@@ -125,6 +145,13 @@ def test_unbound_calls_fail_cleanly(nb):
     assert L.nb_read_pee(m.h, C.c_void_p(16)) == nb.NB_EUNBOUND
     assert L.nb_step(None, 1) == nb.NB_EINVAL
     assert m.workspace_bytes() > 3 * 8 * m.nb
+    t = nb.Tuning(block_threads=512)
+    assert L.nb_cancel(m.h, 1) == nb.NB_EUNBOUND
+    assert L.nb_cancel(None, 1) == nb.NB_EINVAL
+    assert L.nb_set_tuning(m.h, C.byref(t)) == nb.NB_EUNBOUND
+    assert L.nb_get_tuning(m.h, C.byref(t)) == nb.NB_EUNBOUND
+    assert L.nb_autotune(m.h, 4, None, None) == nb.NB_EUNBOUND
+    assert L.nb_autotune(m.h, 4, b"/nonexistent/cache.json", None) == nb.NB_EUNBOUND
 
 
 def test_product_path_has_no_oracle_dependency():

@@ -31,44 +31,51 @@ def nb():
     return nb
 
 
+@pytest.fixture(scope="module")
+def hooks():
+    from paper_1912_10596_amd import testhooks
+    testhooks.lib()
+    return testhooks
+
+
 def _dev(a):
     import torch
     return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
 # ------------------------------------------------------------- primitives
-def test_sqrt_and_division_correctly_rounded(nb):
+def test_sqrt_and_division_correctly_rounded(hooks):
     rng = np.random.default_rng(1)
     a = np.abs(rng.normal(size=200000)) * 10.0 ** rng.uniform(-300, 300, 200000)
     b = rng.normal(size=200000) * 10.0 ** rng.uniform(-150, 150, 200000)
-    sq, dv = nb.test_sqrt_div(_dev(a), _dev(b))
+    sq, dv = hooks.test_sqrt_div(_dev(a), _dev(b))
     np.testing.assert_array_equal(sq.cpu().numpy(), np.sqrt(a))
     np.testing.assert_array_equal(dv.cpu().numpy(), a / b)
 
 
-def test_sincos_bitwise(nb, oracle):
+def test_sincos_bitwise(hooks, oracle):
     rng = np.random.default_rng(2)
     x = np.concatenate([np.linspace(-10, 10, 100001), rng.uniform(-4e6, 4e6, 100000),
                         rng.normal(size=10000) * 1e-8, [0.0, -0.0]])
-    s, c = nb.test_sincos(_dev(x))
+    s, c = hooks.test_sincos(_dev(x))
     so, co = oracle.sincos(x)
     np.testing.assert_array_equal(s.cpu().numpy(), so)
     np.testing.assert_array_equal(c.cpu().numpy(), co)
 
 
-def test_rotation_bitwise(nb, oracle):
+def test_rotation_bitwise(hooks, oracle):
     rng = np.random.default_rng(3)
     n = 3000
     x = rng.normal(size=(n, 3)) * 10.0 ** rng.uniform(-6, 6, (n, 1))
     x[0] = 0.0
     p = rng.normal(size=(n, 3))
     p /= np.linalg.norm(p, axis=1, keepdims=True)
-    got = nb.test_rotate(_dev(x), _dev(p)).cpu().numpy()
+    got = hooks.test_rotate(_dev(x), _dev(p)).cpu().numpy()
     want = np.stack([oracle.rotate(x[i], p[i]) for i in range(n)])
     np.testing.assert_array_equal(got, want)
 
 
-def test_exp3_bitwise(nb, oracle):
+def test_exp3_bitwise(hooks, oracle):
     rng = np.random.default_rng(4)
     ks, ps = [], []
     for scale in (0.0, 1e-6, 0.2, 3.0, 500.0, 3e6):
@@ -116,7 +123,7 @@ def test_exp3_bitwise(nb, oracle):
         p = rng.normal(size=6)
         ks.append(k9); ps.append(p / np.linalg.norm(p))
     ks, ps = np.array(ks), np.array(ps)
-    got = nb.test_exp3(_dev(ks), _dev(ps)).cpu().numpy()
+    got = hooks.test_exp3(_dev(ks), _dev(ps)).cpu().numpy()
     want = np.stack([oracle.exp3_apply(ks[i], ps[i]) for i in range(len(ks))])
     np.testing.assert_array_equal(got, want)
 
@@ -209,3 +216,46 @@ def test_nan_state_reports_numeric_error(nb):
     m.reset()
     m.run()                       # the model is usable again afterwards
     assert torch.isfinite(m.pee()).all()
+
+
+@pytest.mark.parametrize("case", ["2f", "3f", "3f_fp32_state", "3f_fp32_arith", "batch", "2f_ext"])
+def test_renormalisation_factor_far_from_one_reports_numeric_error(nb, case):
+    """A state off unit norm by far more than a unitary step's rounding (here 2e-3 in
+    |state|^2) is reported as NB_ENUMERIC by the renormalisation; a state off by 2e-10 (FP64)
+    is not, and with renormalisation off nothing is checked."""
+    import torch
+    kw = {}
+    if case.startswith("2f"):
+        d = workloads.small_params(n_flavor=2, n_energy=40, n_u=3, n_steps=6)
+        if case == "2f_ext":
+            d["n_phi"] = 2
+    elif case == "batch":
+        d = [workloads.small_params(n_flavor=2, n_energy=20 + 7 * i, n_u=2 + i, n_steps=6)
+             for i in range(3)]
+    else:
+        d = workloads.small_params(n_flavor=3, n_energy=40, n_u=3, n_steps=6)
+        if case != "3f":
+            kw["precision"] = nb.NB_FP32_STATE
+            # the FP32-arithmetic kernel from step 0: the 6M workload's step length at 600 km
+            if case == "3f_fp32_arith":
+                d6 = workloads.three_flavor_6m()
+                h6 = (d6["r_end_km"] - d6["r_start_km"]) / d6["n_steps"]
+                d.update(r_start_km=600.0, r_end_km=600.0 + 6 * h6)
+    m = nb.Model(d, **kw)
+    if case == "3f_fp32_arith":
+        assert m.mixed_fp32_step() == 0
+    x = m.get_state()
+    m.set_state(x * 1.001, 0)
+    with pytest.raises(nb.NubulbError) as e:
+        m.step(1)
+    assert e.value.code == nb.NB_ENUMERIC and "renormalisation" in str(e.value)
+    m.reset()
+    m.run()
+    assert torch.isfinite(m.pee()).all()
+    if not kw:
+        m.set_state(x * (1.0 + 1e-10), 0)    # within the bound: accepted and renormalised
+        m.step(2)
+    if not isinstance(d, list):
+        off = nb.Model(dict(d, renorm=0), **kw)
+        off.set_state(x * 1.001, 0)
+        off.step(1)
