@@ -253,3 +253,24 @@ def test_adjoint_200k_prefix(nb, oracle):
     g = m.adjoint()
     _say(f"grad gpu {g} oracle {go}")
     np.testing.assert_allclose(g, go, rtol=RTOL, atol=0)
+
+
+@pytest.mark.parametrize("name", ["fd104", "ragged1260", "dense_nunu"])
+def test_adjoint_dot_product_with_forward_mode(nb, name):
+    """<J v, w> = <v, J^T w>: the GPU adjoint (J^T w: parameter gradient and state_bar)
+    against forward-mode directional derivatives J v of the two-flavour Bloch form by
+    complex-step differentiation (oracle/bloch2.py), for random v (parameters and start
+    state) and random cotangents w."""
+    import torch
+    sys.path.insert(0, __import__("os").path.dirname(__file__))
+    from test_oracle_bloch2 import CASES as BCASES, _dot_test
+    d = BCASES["dense_nunu"] if name == "dense_nunu" else CASES[name][0]
+
+    def gpu_adjoint(dd, w):
+        m = nb.Model(dd, adjoint_ckpt=16)
+        g, sb = m.adjoint(torch.as_tensor(w, device="cuda"), want_state_bar=True)
+        return g, sb.cpu().numpy()
+
+    worst = _dot_test(gpu_adjoint, d, seed=23)
+    _say(f"dot product {name}: worst relative mismatch {worst:.2e}")
+    assert worst <= 1e-9, worst
