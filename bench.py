@@ -326,6 +326,46 @@ def track_all_timing(nb, workloads):
     return out
 
 
+def conditioning(nb, workloads, delta: float = 1e-10):
+    """Measured conditioning of the discrete evolution, per configuration: every component
+    of the start state perturbed by delta * N(0, 1) (then renormalised), both states
+    advanced the same steps, kappa = max_b |dP_ee| / delta.  Two correct FP64
+    implementations that differ by rounding (~1e-16 per operation) can then disagree by
+    about kappa * 1e-16; a dP_ee of order 0.1 or more means the perturbation has saturated
+    (kappa is then a lower bound)."""
+    import torch
+    cases = [
+        ("3f 800k literal (10 km start)", workloads.three_flavor_800k(), (100, 2000), None),
+        ("3f 800k resolved (600 km start)", workloads.resolved(workloads.three_flavor_800k(), 600.0),
+         (30, 2000), None),
+        ("2f 200k literal (10 km start)", workloads.adjoint_200k(), (200, 5000), None),
+        ("2f 200k resolved (500 km start)", workloads.adjoint_200k_resolved(), (200, 5000), None),
+        ("2f 1024-beam literal (10 km start)", workloads.two_flavor_small(), (100, 2000), None),
+        ("3f 6M resolved (600 km start)", workloads.three_flavor_6m_resolved(), (2000,), None),
+        ("3f 6M literal (10 km start)", workloads.three_flavor_6m(), (2000,), None),
+    ]
+    out = []
+    for label, d, marks, prec in cases:
+        a = nb.Model(d, precision=prec)
+        b = nb.Model(d, precision=prec)
+        x = b.get_state()
+        g = torch.Generator(device=x.device).manual_seed(7)
+        x = x + delta * torch.randn(x.shape, generator=g, device=x.device, dtype=x.dtype)
+        x = x / torch.sqrt((x * x).sum(dim=0, keepdim=True))
+        b.set_state(x, 0)
+        done = 0
+        for n in marks:
+            a.step(n - done)
+            b.step(n - done)
+            done = n
+            dp = float((a.pee() - b.pee()).abs().max().item())
+            out.append(dict(config=label, beams=a.nb, steps=n, max_dpee=dp, kappa=dp / delta,
+                            saturated=dp >= 0.1))
+        del a, b, x
+        torch.cuda.empty_cache()
+    return dict(delta=delta, probes=out)
+
+
 def cpu_baseline(d: dict, seconds: float):
     """The oracle as it stands, on this host's cores, over a bounded prefix of the same
     workload (whole steps of every beam until `seconds` of CPU time have passed)."""
@@ -341,9 +381,27 @@ def cpu_baseline(d: dict, seconds: float):
         el = time.perf_counter() - t0
         if el >= seconds or n >= 200:
             break
-    return dict(value=n * nb / el, unit="beam-steps/s", cores=oracle.get_threads(),
-                kind="oracle", sample=f"{n} radial steps of all {nb} beams (steps 2..{n + 1}) "
-                f"of the same workload, {el:.1f} s wall")
+    cores = oracle.get_threads()
+    out = dict(value=n * nb / el, unit="beam-steps/s", cores=cores,
+               kind="oracle", sample=f"{n} radial steps of all {nb} beams (steps 2..{n + 1}) "
+               f"of the same workload, {el:.1f} s wall")
+    # the same oracle on one thread, continuing from where the timed run stopped
+    oracle.set_threads(1)
+    try:
+        n1 = 0
+        t0 = time.perf_counter()
+        while True:
+            m.step(1)
+            n1 += 1
+            el1 = time.perf_counter() - t0
+            if el1 >= seconds / 3 or n1 >= 50:
+                break
+    finally:
+        oracle.set_threads(cores)
+    out["single_thread"] = dict(value=n1 * nb / el1, unit="beam-steps/s", cores=1,
+                                sample=f"{n1} radial steps of all {nb} beams (steps {n + 2}.."
+                                f"{n + n1 + 1}), {el1:.1f} s wall")
+    return out
 
 
 def main():
@@ -356,7 +414,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint and mixed-precision measurements")
     ap.add_argument("--mixed-literal-steps", type=int, default=2000)
-    ap.add_argument("--section", choices=["batch", "extended", "adjoint", "track_all"],
+    ap.add_argument("--section", choices=["batch", "extended", "adjoint", "track_all", "conditioning"],
                     help="run only this measurement and print its result (for profiling "
                          "runs; no benchmark line)")
     args = ap.parse_args()
@@ -375,7 +433,8 @@ def main():
         fn = {"batch": lambda: batch_timing(nb, workloads, 40),
               "extended": lambda: extended_timing(nb, workloads),
               "adjoint": lambda: adjoint_timing(nb, workloads),
-              "track_all": lambda: track_all_timing(nb, workloads)}[args.section]
+              "track_all": lambda: track_all_timing(nb, workloads),
+              "conditioning": lambda: conditioning(nb, workloads)}[args.section]
         res = fn()
         gc.collect()
         torch.cuda.synchronize()
