@@ -942,7 +942,11 @@ __device__ __forceinline__ void stage3m(const StepArgs& a, const StepGeo& G, con
 // EXT: the extended bulb model (azimuthal bins, four moments); FP64 only.
 // BS: threads per block (512 or 256; every array and loop bound below is a constant).
 template <int NF, typename ST, bool TLDS, bool F32, bool EXT, int BS>
-__global__ void __launch_bounds__(kBlock) k_advance(StepArgs a) {
+// Register budget: the two-flavour instantiations at 256 threads per block are held to 168
+// VGPRs (three wavefronts per SIMD, three blocks per CU); the others keep the compiler's
+// choice under the 512-thread bound (two wavefronts per SIMD).
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NF == 2 && BS == 256) ? 3 : 1)))
+k_advance(StepArgs a) {
   constexpr int NC = (NF == 2) ? 3 : 8;
   constexpr int NM = EXT ? 4 : 2;
   constexpr int NV = NM * NC;
@@ -1325,7 +1329,7 @@ __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, lon
 // so a wave spends much of its time on row set-up and the first load of each row, which
 // more wavefronts hide (measured: 4.35 -> 4.20 ms per step on the 256-model batch).
 template <int BS>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_batch2(BatchArgs a) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BS == 256 ? 3 : 4))) k_batch2(BatchArgs a) {
   __shared__ double sJw[BS / 64][4][6];
   __shared__ long long sfold[BS / 64][(3 + 2) * 64];
   __shared__ double scb[BS / 64][kC2Size];

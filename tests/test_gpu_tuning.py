@@ -68,11 +68,14 @@ def test_every_launch_shape_gives_the_same_bits(nb, case):
 
 def test_set_tuning_rejects_bad_shapes(nb):
     m = nb.Model(workloads.small_params(n_flavor=2, n_energy=40, n_u=3, n_steps=4))
+    assert m.get_tuning()["block_threads"] == 256        # the two-flavour default
+    assert nb.Model(workloads.small_params(n_flavor=3, n_energy=40, n_u=3, n_steps=4)
+                    ).get_tuning()["block_threads"] == 512
     for bs, blocks in ((128, 0), (1024, 0), (512, -1), (512, 100000)):
         with pytest.raises(nb.NubulbError) as e:
             m.set_tuning(bs, blocks)
         assert e.value.code == nb.NB_EINVAL
-    assert m.get_tuning()["block_threads"] == 512
+    assert m.get_tuning()["block_threads"] == 256
 
 
 @pytest.mark.parametrize("case", ["3f_130x7", "batch9"])
