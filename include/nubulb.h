@@ -190,9 +190,8 @@ int nb_cancel(nb_model *m, int32_t on);
 /* Launch shape of the fixed-step kernels (single models and batches; the adaptive and
  * adjoint kernels keep their own).  A beam's arithmetic does not depend on it, and the
  * moments are exact integer sums, so every shape gives the same bits.  Default (until
- * nb_autotune or nb_set_tuning): 256 threads per block for the two-flavour bulb model
- * (single or batched), 512 for the extended model and for three flavours, at the full
- * resident grid. */
+ * nb_autotune or nb_set_tuning): 256 threads per block for two flavours, 512 for three, at
+ * the full resident grid. */
 typedef struct {
   int32_t block_threads;  /* threads per block: 512 (8 wavefronts) or 256 (4) */
   int32_t blocks;         /* block cap of a launch (nb_set_tuning: 0 = the resident capacity);

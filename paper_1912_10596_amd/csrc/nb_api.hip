@@ -803,11 +803,11 @@ extern "C" int nb_bind(nb_model* m, void* dev_ws, size_t bytes, void* hip_stream
   m->cap512 = cap[0];
   m->cap256 = cap[1];
   m->cap_adaptive = cap_adaptive;
-  // Default shape: the two-flavour bulb model (single or batched) at 256 threads per block
+  // Default shape: two flavours (single, batched or extended) at 256 threads per block
   // (three wavefronts per SIMD, and small models spread over twice as many CUs: 16 % faster
-  // on the 256-model batch and the 200k model); the extended model and three flavours at
-  // 512 (the 256-thread variants measured 3 % and 19 % slower there).
-  if (!m->tuned) m->bs = (m->nf == 2 && m->p.n_phi == 0 && m->cap256 > 0) ? kBlockSmall : kBlock;
+  // on the 256-model batch and the 200k model, 9 % on the 60M extended model); three
+  // flavours at 512 (the 256-thread variant measured 19 % slower on the 800k model).
+  if (!m->tuned) m->bs = (m->nf == 2 && m->cap256 > 0) ? kBlockSmall : kBlock;
   if (capacity(m, m->bs) < 1) m->bs = kBlock;   // a tuned block size this device cannot hold
   if (m->tune_blocks > capacity(m, m->bs)) m->tune_blocks = 0;
   m->nblocks = launch_blocks(m);

@@ -296,7 +296,10 @@ constexpr int kC2Sc = 9;     // fixed-point scales s1, s0, p2e1, p2e0 (4)
 constexpr int kC2Row = 13;   // generator i = 1..4: h/cos, lam, nu-nu term (3): 5 each (20);
                              // then 1/cos at the moments' radius and the azimuthal factors (3)
 constexpr int kC2Geo = 36;   // the wavefront's first row's stage geometry (11, stage_geo)
-constexpr int kC2Size = 48;
+constexpr int kC2Geo2 = 48;  // extended model: the stage geometry of the wave's previous row
+                             // (c0 cm c1 hc0 hcm hc1, 1/cos at the moments' radius, sin at the
+                             // three radii: 10), reused by the next rows of the same emission bin
+constexpr int kC2Size = 60;
 // Stage-wide constants: the radial profiles at the three stage radii and the scales.
 __device__ __forceinline__ void put_stage2(double* cb, int lane, const Radial& g0, const Radial& gm,
                                            const Radial& g1, const Scales& sc) {
@@ -331,7 +334,8 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
                                      int s, double u, double h, const double* tab, double* cb,
                                      const double* const* J, int renorm, int lane, long long* fl, I128& T,
                                      int& err, double& emax, double cp = 0.0, double sp = 0.0,
-                                     int an = -1, bool geo = false, const double* sct = nullptr) {
+                                     int an = -1, bool geo = false, const double* sct = nullptr,
+                                     bool reuse = false) {
   // sct: the block's sin/cos constants (sincos_coefs, in LDS)
   constexpr int NM = EXT ? 4 : 2;
   // the lane's first beam of the row, loaded before the row set-up so that the set-up
@@ -350,7 +354,17 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
     const Radial g1{cb[kC2Rad + 6], cb[kC2Rad + 7], cb[kC2Rad + 8], 0.0};
     RowGeo rg;
     double icmom, sn0, snm, sn1;
-    stage_geo<KIND, EXT>(u, h, g0, gm, g1, geo ? cb + kC2Geo : nullptr, rg, icmom, sn0, snm, sn1);
+    double* g2 = cb + kC2Geo2;
+    if (EXT && reuse) {   // the previous row of this stage had the same emission bin
+      rg.c0 = g2[0]; rg.cm = g2[1]; rg.c1 = g2[2]; rg.hc0 = g2[3]; rg.hcm = g2[4]; rg.hc1 = g2[5];
+      icmom = g2[6]; sn0 = g2[7]; snm = g2[8]; sn1 = g2[9];
+    } else {
+      stage_geo<KIND, EXT>(u, h, g0, gm, g1, geo ? cb + kC2Geo : nullptr, rg, icmom, sn0, snm, sn1);
+      if (EXT && lane == 0) {
+        g2[0] = rg.c0; g2[1] = rg.cm; g2[2] = rg.c1; g2[3] = rg.hc0; g2[4] = rg.hcm; g2[5] = rg.hc1;
+        g2[6] = icmom; g2[7] = sn0; g2[8] = snm; g2[9] = sn1;
+      }
+    }
     double n[3];
     if (KIND == 1 || KIND == 2 || KIND == 4) {
       nunu_row<3, EXT>(J[0], g0.mu, rg.c0, sn0, cp, sp, n);
@@ -456,17 +470,23 @@ __device__ __forceinline__ void stage2(const StepArgs& a, const StepGeo& G, cons
              Scales{a.s1, a.s0, a.p2e1, a.p2e0});
   const double* J[4] = {sJ[0], sJ[1], sJ[2], sJ[3]};
   if constexpr (EXT) {
-    // rows (s, j, p): species, emission bin, azimuthal bin
+    // rows (s, j, p): species, emission bin, azimuthal bin.  Each wavefront takes a
+    // contiguous range of rows, so that the n_phi rows of one (s, j) follow each other and
+    // share the stage geometry (computed for the first, reused by the others).
     const double* phi = a.tab + (size_t)(2 + a.NS) * a.NE;
     const long long nrow = (long long)a.NS * a.NU * a.NP;
-    for (long long row = gw; row < nrow; row += nw) {
+    const long long per = (nrow + nw - 1) / nw;
+    const long long rbeg = gw * per, rend = min(nrow, rbeg + per);
+    long long sj_prev = -1;
+    for (long long row = rbeg; row < rend; ++row) {
       const long long sj = row / a.NP;
       const int p = (int)(row - sj * a.NP);
       const int s = (int)(sj / a.NU);
       const int j = (int)(sj - (long long)s * a.NU);
       row2<KIND, ADAPT, true>(X, Xo, a.plane, row * a.NE, a.NE, s, u_of(j, a.NU), G.h, tab, cb, J,
                               a.renorm, lane, fl, T, err, emax, phi[p], phi[a.NP + p],
-                              s >= (a.NS >> 1), geo && row == gw, sct);
+                              s >= (a.NS >> 1), geo && row == rbeg, sct, sj == sj_prev);
+      sj_prev = sj;
     }
   } else {
     const long long nrow = (long long)a.NS * a.NU;
@@ -955,7 +975,7 @@ k_advance(StepArgs a) {
   __shared__ I128 sw[WPB][NV];
   __shared__ long long sacc[BS];
   // per wavefront: row constants (mixed: then 32 floats), then the first row's geometry
-  __shared__ double snn_all[WPB][F32 ? 64 : 48];
+  __shared__ double snn_all[WPB][F32 ? 64 : (NF == 2 ? kC2Size : 48)];
   __shared__ long long sfold[WPB][(NC + 2) * 64];
   __shared__ double s_sct[kSinCosTab];   // sin/cos constants of the two-flavour rotations
   extern __shared__ __align__(16) double dyn_tab[];
@@ -1105,7 +1125,7 @@ __global__ void __launch_bounds__(kBlock) k_adaptive(StepArgs a) {
   __shared__ double swm[kBlock / 64];
   __shared__ I128 sw[kBlock / 64][NV];
   __shared__ long long sacc[kBlock];
-  __shared__ double snn_all[kBlock / 64][48];   // row constants, then the first row's geometry
+  __shared__ double snn_all[kBlock / 64][NF == 2 ? kC2Size : 48];   // row constants, then the first row's geometry
   __shared__ long long sfold[kBlock / 64][(NC + 2) * 64];
   __shared__ double s_sct[kSinCosTab];   // sin/cos constants of the two-flavour rotations
   extern __shared__ __align__(16) double dyn_tab[];
