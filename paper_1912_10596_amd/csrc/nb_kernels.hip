@@ -979,7 +979,9 @@ k_advance(StepArgs a) {
   __shared__ long long sfold[WPB][(NC + 2) * 64];
   __shared__ double s_sct[kSinCosTab];   // sin/cos constants of the two-flavour rotations
   extern __shared__ __align__(16) double dyn_tab[];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // the wavefront index as a wave-uniform (scalar) value: the row indices, their divisions
+  // and the row base offsets derived from it then live in scalar registers
+  const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const long long gw = (long long)blockIdx.x * WPB + wid;
   const long long nw = (long long)gridDim.x * WPB;
   const double* tab = a.tab;
@@ -1129,7 +1131,9 @@ __global__ void __launch_bounds__(kBlock) k_adaptive(StepArgs a) {
   __shared__ long long sfold[kBlock / 64][(NC + 2) * 64];
   __shared__ double s_sct[kSinCosTab];   // sin/cos constants of the two-flavour rotations
   extern __shared__ __align__(16) double dyn_tab[];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // the wavefront index as a wave-uniform (scalar) value: the row indices, their divisions
+  // and the row base offsets derived from it then live in scalar registers
+  const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const long long gw = (long long)blockIdx.x * (kBlock / 64) + wid;
   const long long nw = (long long)gridDim.x * (kBlock / 64);
   if (launch_aborted(a.sync)) return;
@@ -1345,11 +1349,13 @@ __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, lon
   }
 }
 
-// Four wavefronts per SIMD (128 VGPRs): the rows of a batch are short (50-400 energies),
-// so a wave spends much of its time on row set-up and the first load of each row, which
-// more wavefronts hide (measured: 4.35 -> 4.20 ms per step on the 256-model batch).
+// Four wavefronts per SIMD (128 VGPRs, a 16-byte spill): the rows of a batch are short
+// (50-400 energies), so a wave spends much of its time on row set-up and the first load of
+// each row, which more wavefronts hide.  Measured on the 256-model batch: 4.35 (two
+// wavefronts per SIMD) -> 4.20 (four, 512 threads, 224-byte spill) -> 3.52 (three, 256
+// threads) -> 3.19 ms per step (four, 256 threads, with the wavefront index scalar).
 template <int BS>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BS == 256 ? 3 : 4))) k_batch2(BatchArgs a) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_batch2(BatchArgs a) {
   __shared__ double sJw[BS / 64][4][6];
   __shared__ long long sfold[BS / 64][(3 + 2) * 64];
   __shared__ double scb[BS / 64][kC2Size];
@@ -1357,7 +1363,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BS 
   if (launch_aborted(a.sync)) return;
   if (threadIdx.x == 0) sincos_coefs(s_sct);
   __syncthreads();
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // the wavefront index as a wave-uniform (scalar) value: the row indices, their divisions
+  // and the row base offsets derived from it then live in scalar registers
+  const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double (*Jv)[6] = sJw[wid];
   const long long w = (long long)blockIdx.x * (BS / 64) + wid;
   const long long r0w = min(max(a.wave_row0[w], 0LL), a.total_rows);
