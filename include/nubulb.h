@@ -123,7 +123,7 @@ int nb_reset(nb_model *m);
 /* Advance n radial steps of the fixed grid r_k = r_start + k (r_end - r_start)/n_steps
  * (bounded by n_steps - current step): each step is the RKMK4 step of Eq. U with the
  * Hamiltonian of Eq. eom rebuilt at every stage from the moments of Eqs. Hnu and F (see
- * the preamble).  One persistent cooperative launch per chunk of steps (so that the barrier
+ * the preamble).  One persistent launch per chunk of steps (so that the barrier
  * epochs of a launch stay within 32 bits); returns after the stream has drained and the
  * kernels' status word was checked.  NB_ENUMERIC: a moment contribution left its
  * fixed-point range (NaN or overflow), or a state's norm was off 1 by more than a unitary
@@ -170,11 +170,12 @@ int64_t nb_mixed_fp32_step(const nb_model *m);
  * stream) into a graph held by the model; nb_graph_launch replays it and checks the
  * status word.  Every replay continues from where the previous one stopped and stops at
  * r_end.  Rebinding, changing the launch shape (nb_autotune, nb_set_tuning) or destroying
- * the model drops the graph.  Inside the graph the stepping kernel is an ordinary launch,
- * which makes progress only while all its blocks are resident at once: nb_graph_launch
- * refuses (NB_EINVAL) a recorded grid above the resident capacity the device reports at
- * the time of the launch, and work that other streams run meanwhile can still stall it --
- * the barrier waits then end at their 20 s limit or at nb_cancel with NB_ETIMEOUT. */
+ * the model drops the graph.  Every persistent launch of the library (eager or in a graph)
+ * is an ordinary kernel launch whose grid never exceeds the resident capacity measured at
+ * nb_bind, which makes progress while all its blocks are resident at once: nb_graph_launch
+ * also refuses (NB_EINVAL) a recorded grid above the capacity the device reports at the
+ * time of the launch, and work that other streams run meanwhile can still stall a launch
+ * -- the barrier waits then end at their 20 s limit or at nb_cancel with NB_ETIMEOUT. */
 int nb_graph_capture(nb_model *m, int64_t n_steps);
 int nb_graph_launch(nb_model *m);
 

@@ -1,5 +1,5 @@
 // nb_api.hip -- host runtime behind include/nubulb.h: parameter validation, host tables,
-// workspace layout, cooperative launches, status checks, the autotuner and its cache.
+// workspace layout, persistent launches, status checks, the autotuner and its cache.
 #include <hip/hip_runtime.h>
 
 #include <unistd.h>
@@ -876,6 +876,14 @@ static long long launch_chunk(const nb_model* m) {
   return std::max<long long>(1, (long long)(3.5e9 / ((double)m->nblocks * 4.0)) - 2);
 }
 
+// Persistent launches (stepping, adaptive, adjoint) are ordinary launches whose grid never
+// exceeds the resident capacity measured at nb_bind (one block per CU slot the occupancy
+// calculator reports; a graph launch checks it again), so every block is resident while no
+// other work holds the CUs, and every barrier wait is time-limited and cancellable from the
+// host.  hipLaunchCooperativeKernel would only repeat the capacity check: on this runtime it
+// cost 15-18 us more per call, and processes that had made cooperative launches crashed in
+// the runtime's exit handler under rocprofv3 (ordinary launches exit cleanly).
+//
 // Enqueue one stepping launch of k steps (from the device step counter) on the stream.
 static int enqueue_advance(nb_model* m, long long k) {
   unsigned int* sync = sync_words(m);
@@ -908,14 +916,8 @@ static int enqueue_advance(nb_model* m, long long k) {
     a.timeout_ticks = timeout;
     a.cancel = m->cancel_dev;
     void* args[] = {&a};
-    // Inside graph capture the kernel node is an ordinary launch: the grid never exceeds
-    // the resident capacity measured at bind time (checked again at every graph launch),
-    // and every barrier wait is time-limited and cancellable from the host.
     const hipError_t e =
-        capturing(m->stream)
-            ? hipLaunchKernel(advance_kernel(m, m->bs), dim3(m->nblocks), dim3(m->bs), args, 0, m->stream)
-            : hipLaunchCooperativeKernel(advance_kernel(m, m->bs), dim3(m->nblocks), dim3(m->bs), args, 0,
-                                         m->stream);
+        hipLaunchKernel(advance_kernel(m, m->bs), dim3(m->nblocks), dim3(m->bs), args, 0, m->stream);
     if (e != hipSuccess) return fail(NB_EHIP, "batch launch: %s", hipGetErrorString(e));
     return NB_OK;
   }
@@ -948,10 +950,7 @@ static int enqueue_advance(nb_model* m, long long k) {
   a.Jhist = m->jhist;
   auto launch = [&](const void* fn, size_t lds) -> int {
     void* args[] = {&a};
-    const hipError_t e =
-        capturing(m->stream)
-            ? hipLaunchKernel(fn, dim3(m->nblocks), dim3(m->bs), args, lds, m->stream)
-            : hipLaunchCooperativeKernel(fn, dim3(m->nblocks), dim3(m->bs), args, (unsigned)lds, m->stream);
+    const hipError_t e = hipLaunchKernel(fn, dim3(m->nblocks), dim3(m->bs), args, lds, m->stream);
     if (e != hipSuccess) return fail(NB_EHIP, "stepping launch: %s", hipGetErrorString(e));
     return NB_OK;
   };
@@ -1120,8 +1119,8 @@ extern "C" int nb_run_adaptive(nb_model* m, double tol, double h_max_km, int64_t
   void* args[] = {&a};
   // one wavefront per row at most, at most the adaptive kernel's resident capacity
   const int ablocks = (int)std::max<long long>(1, std::min<long long>((m->rows + 7) / 8, m->cap_adaptive));
-  const hipError_t e = hipLaunchCooperativeKernel(adaptive_kernel(m), dim3(ablocks), dim3(kBlock), args,
-                                                  (unsigned)advance_dyn_lds(m), m->stream);
+  const hipError_t e = hipLaunchKernel(adaptive_kernel(m), dim3(ablocks), dim3(kBlock), args,
+                                      advance_dyn_lds(m), m->stream);
   if (e != hipSuccess) return fail(NB_EHIP, "adaptive launch: %s", hipGetErrorString(e));
   long long out[8];
   NB_HIP(hipMemcpyAsync(out, ctl, sizeof(out), hipMemcpyDeviceToHost, m->stream));
@@ -1713,7 +1712,7 @@ extern "C" int nb_adjoint(nb_model* m, const double* dev_dl_dpee, double* grad_o
                  : m->adj_bpt == 2 ? (const void*)&k_adjoint2<2>
                  : m->adj_bpt == 4 ? (const void*)&k_adjoint2<4>
                                    : (const void*)&k_adjoint2<0>;
-  const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(m->adj_blocks), dim3(kBlock), args, 0, m->stream);
+  const hipError_t e = hipLaunchKernel(fn, dim3(m->adj_blocks), dim3(kBlock), args, 0, m->stream);
   if (e != hipSuccess) return fail(NB_EHIP, "adjoint launch: %s", hipGetErrorString(e));
   const long long before = m->step;
   int rc = check_status(m);

@@ -1,6 +1,6 @@
 // nb_kernels.hip -- persistent CDNA4 kernels of the bulb-model radial stepper.
 //
-// One cooperative launch advances every beam by `nsteps` radial steps.  Work unit: one
+// One persistent launch advances every beam by `nsteps` radial steps.  Work unit: one
 // (species, emission-bin) row of N_E beams per wavefront -- the paper's NBeam with its
 // SIMD loop over energy bins (Sec. 3.3) mapped onto 64 lanes.  Per RK stage each wave
 //   1. streams its rows' state planes (SoA, coalesced 64 x 8 B per load),
