@@ -318,6 +318,54 @@ __device__ __forceinline__ void gen2c(int an, double bx, double bz, const double
   gen2(an, bx, bz, c[1], nn, c[0], f);
 }
 
+// The constants of one row for a stage (the arithmetic every beam of the row shares):
+// rc[5 (i - 1) ...] = h/cos, lam and the nu-nu term (3) of stage generator i, then rc[20] =
+// 1/cos at the moments' radius and rc[21..22] the extended model's azimuthal factors.
+// gcache: the wavefront's first-row geometry slot (or nullptr); reuse: take the geometry of
+// the previous row (extended model, same emission bin) from slot kC2Geo2.  Values are
+// written to rc (and the geometry to kC2Geo2) only where write is true.
+template <int KIND, bool EXT>
+__device__ __forceinline__ void row_setup2(double u, double h, double* cb, const double* const* J,
+                                           double cp, double sp, double* gcache, bool reuse,
+                                           bool write, double* rc) {
+  const Radial g0{cb[kC2Rad + 0], cb[kC2Rad + 1], cb[kC2Rad + 2], 0.0};
+  const Radial gm{cb[kC2Rad + 3], cb[kC2Rad + 4], cb[kC2Rad + 5], 0.0};
+  const Radial g1{cb[kC2Rad + 6], cb[kC2Rad + 7], cb[kC2Rad + 8], 0.0};
+  RowGeo rg;
+  double icmom, sn0, snm, sn1;
+  double* g2 = cb + kC2Geo2;
+  if (EXT && reuse) {   // the previous row of this stage had the same emission bin
+    rg.c0 = g2[0]; rg.cm = g2[1]; rg.c1 = g2[2]; rg.hc0 = g2[3]; rg.hcm = g2[4]; rg.hc1 = g2[5];
+    icmom = g2[6]; sn0 = g2[7]; snm = g2[8]; sn1 = g2[9];
+  } else {
+    stage_geo<KIND, EXT>(u, h, g0, gm, g1, gcache, rg, icmom, sn0, snm, sn1);
+    if (EXT && write) {
+      g2[0] = rg.c0; g2[1] = rg.cm; g2[2] = rg.c1; g2[3] = rg.hc0; g2[4] = rg.hcm; g2[5] = rg.hc1;
+      g2[6] = icmom; g2[7] = sn0; g2[8] = snm; g2[9] = sn1;
+    }
+  }
+  double n[3];
+  if (KIND == 1 || KIND == 2 || KIND == 4) {
+    nunu_row<3, EXT>(J[0], g0.mu, rg.c0, sn0, cp, sp, n);
+    if (write) { rc[0] = rg.hc0; rc[1] = g0.lam; rc[2] = n[0]; rc[3] = n[1]; rc[4] = n[2]; }
+  }
+  if (KIND == 2 || KIND == 4) {
+    nunu_row<3, EXT>(J[1], gm.mu, rg.cm, snm, cp, sp, n);
+    if (write) { rc[5] = rg.hcm; rc[6] = gm.lam; rc[7] = n[0]; rc[8] = n[1]; rc[9] = n[2]; }
+  }
+  if (KIND >= 3) {
+    nunu_row<3, EXT>(J[2], gm.mu, rg.cm, snm, cp, sp, n);
+    if (write) { rc[10] = rg.hcm; rc[11] = gm.lam; rc[12] = n[0]; rc[13] = n[1]; rc[14] = n[2]; }
+  }
+  if (KIND == 4) {
+    nunu_row<3, EXT>(J[3], g1.mu, rg.c1, sn1, cp, sp, n);
+    if (write) { rc[15] = rg.hc1; rc[16] = g1.lam; rc[17] = n[0]; rc[18] = n[1]; rc[19] = n[2]; }
+  }
+  const double snmom = (KIND == 0) ? sn0 : ((KIND <= 2) ? snm : sn1);
+  if (write) { rc[20] = icmom; rc[21] = (snmom * icmom) * cp; rc[22] = (snmom * icmom) * sp; }
+}
+constexpr int kRowC = 24;    // doubles per row-constant block (23 used)
+
 // Stage stencil for one (species s, emission bin u) row of NE beams starting at beam rb.
 // KIND: 0 moments of rho_n at r_n; 1 stage Y2 (moments at r_n + h/2); 2 stage Y3
 // (r_n + h/2); 3 stage Y4 (r_{n+1}); 4 final update, store and moments at r_{n+1}.
@@ -329,13 +377,14 @@ __device__ __forceinline__ void gen2c(int an, double bx, double bz, const double
 // largest embedded error estimate |Theta - f2|^2 of the lane's beams.
 // EXT: extended bulb model, azimuth (cp, sp) = (cos, sin) of the row's azimuthal bin.
 // geo: this row is the wavefront's first (its stage geometry is cached across stages).
-template <int KIND, bool ADAPT = false, bool EXT = false>
+// PRE: the row's constants were computed beforehand (row_setup2) and sit at rcp.
+template <int KIND, bool ADAPT = false, bool EXT = false, bool PRE = false>
 __device__ __forceinline__ void row2(const double* X, double* Xo, long long plane, long long rb, int NE,
                                      int s, double u, double h, const double* tab, double* cb,
                                      const double* const* J, int renorm, int lane, long long* fl, I128& T,
                                      int& err, double& emax, double cp = 0.0, double sp = 0.0,
                                      int an = -1, bool geo = false, const double* sct = nullptr,
-                                     bool reuse = false) {
+                                     bool reuse = false, double* rcp = nullptr) {
   // sct: the block's sin/cos constants (sincos_coefs, in LDS)
   constexpr int NM = EXT ? 4 : 2;
   // the lane's first beam of the row, loaded before the row set-up so that the set-up
@@ -346,45 +395,10 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
   }
   // species row s, antiparticle flag an (default: s itself, two tracked species)
   if (an < 0) an = s;
-  double* rc = cb + kC2Row;
+  double* rc = PRE ? rcp : cb + kC2Row;
   __asm__ volatile("" ::: "memory");   // stage constants re-read from LDS for every row
-  {
-    const Radial g0{cb[kC2Rad + 0], cb[kC2Rad + 1], cb[kC2Rad + 2], 0.0};
-    const Radial gm{cb[kC2Rad + 3], cb[kC2Rad + 4], cb[kC2Rad + 5], 0.0};
-    const Radial g1{cb[kC2Rad + 6], cb[kC2Rad + 7], cb[kC2Rad + 8], 0.0};
-    RowGeo rg;
-    double icmom, sn0, snm, sn1;
-    double* g2 = cb + kC2Geo2;
-    if (EXT && reuse) {   // the previous row of this stage had the same emission bin
-      rg.c0 = g2[0]; rg.cm = g2[1]; rg.c1 = g2[2]; rg.hc0 = g2[3]; rg.hcm = g2[4]; rg.hc1 = g2[5];
-      icmom = g2[6]; sn0 = g2[7]; snm = g2[8]; sn1 = g2[9];
-    } else {
-      stage_geo<KIND, EXT>(u, h, g0, gm, g1, geo ? cb + kC2Geo : nullptr, rg, icmom, sn0, snm, sn1);
-      if (EXT && lane == 0) {
-        g2[0] = rg.c0; g2[1] = rg.cm; g2[2] = rg.c1; g2[3] = rg.hc0; g2[4] = rg.hcm; g2[5] = rg.hc1;
-        g2[6] = icmom; g2[7] = sn0; g2[8] = snm; g2[9] = sn1;
-      }
-    }
-    double n[3];
-    if (KIND == 1 || KIND == 2 || KIND == 4) {
-      nunu_row<3, EXT>(J[0], g0.mu, rg.c0, sn0, cp, sp, n);
-      if (lane == 0) { rc[0] = rg.hc0; rc[1] = g0.lam; rc[2] = n[0]; rc[3] = n[1]; rc[4] = n[2]; }
-    }
-    if (KIND == 2 || KIND == 4) {
-      nunu_row<3, EXT>(J[1], gm.mu, rg.cm, snm, cp, sp, n);
-      if (lane == 0) { rc[5] = rg.hcm; rc[6] = gm.lam; rc[7] = n[0]; rc[8] = n[1]; rc[9] = n[2]; }
-    }
-    if (KIND >= 3) {
-      nunu_row<3, EXT>(J[2], gm.mu, rg.cm, snm, cp, sp, n);
-      if (lane == 0) { rc[10] = rg.hcm; rc[11] = gm.lam; rc[12] = n[0]; rc[13] = n[1]; rc[14] = n[2]; }
-    }
-    if (KIND == 4) {
-      nunu_row<3, EXT>(J[3], g1.mu, rg.c1, sn1, cp, sp, n);
-      if (lane == 0) { rc[15] = rg.hc1; rc[16] = g1.lam; rc[17] = n[0]; rc[18] = n[1]; rc[19] = n[2]; }
-    }
-    const double snmom = (KIND == 0) ? sn0 : ((KIND <= 2) ? snm : sn1);
-    if (lane == 0) { rc[20] = icmom; rc[21] = (snmom * icmom) * cp; rc[22] = (snmom * icmom) * sp; }
-  }
+  if constexpr (!PRE)
+    row_setup2<KIND, EXT>(u, h, cb, J, cp, sp, geo ? cb + kC2Geo : nullptr, reuse, lane == 0, rc);
   __asm__ volatile("" ::: "memory");
   const double* G = tab + (size_t)(2 + s) * NE;
   I128 mine = i128_zero();
@@ -1284,10 +1298,14 @@ __device__ bool grid_barrier(const BatchArgs& a, unsigned epoch) {
   return true;
 }
 
+// Rows are taken in groups of up to kGroup rows of one model: lane l first computes the
+// constants of the group's row l (row_setup2, the arithmetic every lane of the row would
+// otherwise repeat) into the wave's table rt, then the rows run one after the other.
+constexpr int kGroup = 16;
 template <int KIND>
 __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, long long r0w,
                             long long r1w, int lane, double (*Jv)[6], long long* fl, double* cb,
-                            const double* sct, int& err) {
+                            double* rt, const double* sct, int& err) {
   const double r0 = a.rs + (double)n * a.h;
   const double rm = r0 + 0.5 * a.h;
   const double r1 = a.rs + (double)(n + 1) * a.h;
@@ -1297,7 +1315,7 @@ __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, lon
   int mNE = 0, mNU = 1;
   const double* J[4] = {Jv[0], Jv[1], Jv[2], Jv[3]};   // this wave's LDS block
   I128 T = i128_zero();
-  for (long long row = r0w; row < r1w; ++row) {
+  for (long long row = r0w; row < r1w;) {
     if (m < 0 || row >= mrow1) {
       if (m >= 0 && lane < 6) acc_add(acc_slot(a, epoch, m) + lane * kAccLimbs, T);
       T = i128_zero();
@@ -1333,12 +1351,24 @@ __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, lon
           Jv[i][v] = i128_to_double(acc_read(sl + v * kAccLimbs)) * (v < 3 ? sc.p2e0 : sc.p2e1);
       }
     }
-    const long long lr = row - mrow0;
-    const int s = (int)(lr / mNU);
-    const int j = (int)(lr - (long long)s * mNU);
-    double enone = 0.0;
-    row2<KIND>(a.X, a.X, a.plane, mbeam0 + lr * mNE, mNE, s, u_of(j, mNU), a.h, a.tab + mtab0, cb, J,
-               a.renorm, lane, fl, T, err, enone, 0.0, 0.0, -1, false, sct);
+    const long long gend = min(min(r1w, mrow1), row + (long long)kGroup);
+    const int gn = (int)(gend - row);
+    __asm__ volatile("" ::: "memory");   // the previous group's rows have read their blocks
+    if (lane < gn) {
+      const int lr = (int)(row + lane - mrow0);
+      const int s = lr / mNU;
+      const int j = lr - s * mNU;
+      row_setup2<KIND, false>(u_of(j, mNU), a.h, cb, J, 0.0, 0.0, nullptr, false, true, rt + lane * kRowC);
+    }
+    __asm__ volatile("" ::: "memory");
+    for (int i = 0; i < gn; ++i, ++row) {
+      const long long lr = row - mrow0;
+      const int s = (int)(lr / mNU);
+      double enone = 0.0;
+      row2<KIND, false, false, true>(a.X, a.X, a.plane, mbeam0 + lr * mNE, mNE, s, 0.0, a.h, a.tab + mtab0,
+                                     cb, J, a.renorm, lane, fl, T, err, enone, 0.0, 0.0, -1, false, sct,
+                                     false, rt + i * kRowC);
+    }
   }
   if (m >= 0 && lane < 6) acc_add(acc_slot(a, epoch, m) + lane * kAccLimbs, T);
   // clear the set the next epoch will collect into
@@ -1359,6 +1389,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
   __shared__ double sJw[BS / 64][4][6];
   __shared__ long long sfold[BS / 64][(3 + 2) * 64];
   __shared__ double scb[BS / 64][kC2Size];
+  __shared__ double srt[BS / 64][kGroup * kRowC];   // each wave's row-constant table
   __shared__ double s_sct[kSinCosTab];   // sin/cos constants of the rotations
   if (launch_aborted(a.sync)) return;
   if (threadIdx.x == 0) sincos_coefs(s_sct);
@@ -1375,16 +1406,16 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
   unsigned epoch = 0;
   int err = 0;
   bool ok;
-  batch_stage<0>(a, step0, epoch, r0w, r1w, lane, Jv, sfold[wid], scb[wid], s_sct, err);
+  batch_stage<0>(a, step0, epoch, r0w, r1w, lane, Jv, sfold[wid], scb[wid], srt[wid], s_sct, err);
   ok = grid_barrier(a, epoch++);
   for (long long n = step0; ok && n < step0 + nsteps; ++n) {
-    batch_stage<1>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], scb[wid], s_sct, err);
+    batch_stage<1>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], scb[wid], srt[wid], s_sct, err);
     if (!(ok = grid_barrier(a, epoch++))) break;
-    batch_stage<2>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], scb[wid], s_sct, err);
+    batch_stage<2>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], scb[wid], srt[wid], s_sct, err);
     if (!(ok = grid_barrier(a, epoch++))) break;
-    batch_stage<3>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], scb[wid], s_sct, err);
+    batch_stage<3>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], scb[wid], srt[wid], s_sct, err);
     if (!(ok = grid_barrier(a, epoch++))) break;
-    batch_stage<4>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], scb[wid], s_sct, err);
+    batch_stage<4>(a, n, epoch, r0w, r1w, lane, Jv, sfold[wid], scb[wid], srt[wid], s_sct, err);
     ok = grid_barrier(a, epoch++);
   }
   if (err) __hip_atomic_fetch_or(a.sync + kSyncStatus, (unsigned)err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
