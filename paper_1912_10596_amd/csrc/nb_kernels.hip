@@ -296,10 +296,7 @@ constexpr int kC2Sc = 9;     // fixed-point scales s1, s0, p2e1, p2e0 (4)
 constexpr int kC2Row = 13;   // generator i = 1..4: h/cos, lam, nu-nu term (3): 5 each (20);
                              // then 1/cos at the moments' radius and the azimuthal factors (3)
 constexpr int kC2Geo = 36;   // the wavefront's first row's stage geometry (11, stage_geo)
-constexpr int kC2Geo2 = 48;  // extended model: the stage geometry of the wave's previous row
-                             // (c0 cm c1 hc0 hcm hc1, 1/cos at the moments' radius, sin at the
-                             // three radii: 10), reused by the next rows of the same emission bin
-constexpr int kC2Size = 60;
+constexpr int kC2Size = 48;
 // Stage-wide constants: the radial profiles at the three stage radii and the scales.
 __device__ __forceinline__ void put_stage2(double* cb, int lane, const Radial& g0, const Radial& gm,
                                            const Radial& g1, const Scales& sc) {
@@ -321,29 +318,17 @@ __device__ __forceinline__ void gen2c(int an, double bx, double bz, const double
 // The constants of one row for a stage (the arithmetic every beam of the row shares):
 // rc[5 (i - 1) ...] = h/cos, lam and the nu-nu term (3) of stage generator i, then rc[20] =
 // 1/cos at the moments' radius and rc[21..22] the extended model's azimuthal factors.
-// gcache: the wavefront's first-row geometry slot (or nullptr); reuse: take the geometry of
-// the previous row (extended model, same emission bin) from slot kC2Geo2.  Values are
-// written to rc (and the geometry to kC2Geo2) only where write is true.
+// gcache: the wavefront's first-row geometry slot (or nullptr).  Values are written to rc
+// only where write is true.
 template <int KIND, bool EXT>
 __device__ __forceinline__ void row_setup2(double u, double h, double* cb, const double* const* J,
-                                           double cp, double sp, double* gcache, bool reuse,
-                                           bool write, double* rc) {
+                                           double cp, double sp, double* gcache, bool write, double* rc) {
   const Radial g0{cb[kC2Rad + 0], cb[kC2Rad + 1], cb[kC2Rad + 2], 0.0};
   const Radial gm{cb[kC2Rad + 3], cb[kC2Rad + 4], cb[kC2Rad + 5], 0.0};
   const Radial g1{cb[kC2Rad + 6], cb[kC2Rad + 7], cb[kC2Rad + 8], 0.0};
   RowGeo rg;
   double icmom, sn0, snm, sn1;
-  double* g2 = cb + kC2Geo2;
-  if (EXT && reuse) {   // the previous row of this stage had the same emission bin
-    rg.c0 = g2[0]; rg.cm = g2[1]; rg.c1 = g2[2]; rg.hc0 = g2[3]; rg.hcm = g2[4]; rg.hc1 = g2[5];
-    icmom = g2[6]; sn0 = g2[7]; snm = g2[8]; sn1 = g2[9];
-  } else {
-    stage_geo<KIND, EXT>(u, h, g0, gm, g1, gcache, rg, icmom, sn0, snm, sn1);
-    if (EXT && write) {
-      g2[0] = rg.c0; g2[1] = rg.cm; g2[2] = rg.c1; g2[3] = rg.hc0; g2[4] = rg.hcm; g2[5] = rg.hc1;
-      g2[6] = icmom; g2[7] = sn0; g2[8] = snm; g2[9] = sn1;
-    }
-  }
+  stage_geo<KIND, EXT>(u, h, g0, gm, g1, gcache, rg, icmom, sn0, snm, sn1);
   double n[3];
   if (KIND == 1 || KIND == 2 || KIND == 4) {
     nunu_row<3, EXT>(J[0], g0.mu, rg.c0, sn0, cp, sp, n);
@@ -384,7 +369,7 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
                                      const double* const* J, int renorm, int lane, long long* fl, I128& T,
                                      int& err, double& emax, double cp = 0.0, double sp = 0.0,
                                      int an = -1, bool geo = false, const double* sct = nullptr,
-                                     bool reuse = false, double* rcp = nullptr) {
+                                     double* rcp = nullptr) {
   // sct: the block's sin/cos constants (sincos_coefs, in LDS)
   constexpr int NM = EXT ? 4 : 2;
   // the lane's first beam of the row, loaded before the row set-up so that the set-up
@@ -398,7 +383,7 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
   double* rc = PRE ? rcp : cb + kC2Row;
   __asm__ volatile("" ::: "memory");   // stage constants re-read from LDS for every row
   if constexpr (!PRE)
-    row_setup2<KIND, EXT>(u, h, cb, J, cp, sp, geo ? cb + kC2Geo : nullptr, reuse, lane == 0, rc);
+    row_setup2<KIND, EXT>(u, h, cb, J, cp, sp, geo ? cb + kC2Geo : nullptr, lane == 0, rc);
   __asm__ volatile("" ::: "memory");
   const double* G = tab + (size_t)(2 + s) * NE;
   I128 mine = i128_zero();
@@ -475,32 +460,46 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
                    err, rc[21], rc[22]);
 }
 
+// rt (extended model): the wavefront's row-constant table of kGroup2 blocks of kRowC.
+constexpr int kGroup2 = 16;
 template <int KIND, bool ADAPT = false, bool EXT = false>
 __device__ __forceinline__ void stage2(const StepArgs& a, const StepGeo& G, const double* X, double* Xo,
                                        const double (*sJ)[EXT ? 12 : 6], const double* tab, long long gw,
                                        long long nw, int lane, long long* fl, I128& T, int& err,
-                                       double& emax, double* cb, const double* sct, bool geo = false) {
+                                       double& emax, double* cb, const double* sct, bool geo = false,
+                                       double* rt = nullptr) {
   put_stage2(cb, lane, radial_at(a, G.r0), radial_at(a, G.rm), radial_at(a, G.r1),
              Scales{a.s1, a.s0, a.p2e1, a.p2e0});
   const double* J[4] = {sJ[0], sJ[1], sJ[2], sJ[3]};
   if constexpr (EXT) {
     // rows (s, j, p): species, emission bin, azimuthal bin.  Each wavefront takes a
-    // contiguous range of rows, so that the n_phi rows of one (s, j) follow each other and
-    // share the stage geometry (computed for the first, reused by the others).
+    // contiguous range of rows, in groups of up to kGroup2: lane l computes the constants of
+    // the group's row l (row_setup2: geometry, nu-nu terms with the row's azimuth) into the
+    // table rt, then the rows run one after the other.
     const double* phi = a.tab + (size_t)(2 + a.NS) * a.NE;
     const long long nrow = (long long)a.NS * a.NU * a.NP;
     const long long per = (nrow + nw - 1) / nw;
     const long long rbeg = gw * per, rend = min(nrow, rbeg + per);
-    long long sj_prev = -1;
-    for (long long row = rbeg; row < rend; ++row) {
-      const long long sj = row / a.NP;
-      const int p = (int)(row - sj * a.NP);
-      const int s = (int)(sj / a.NU);
-      const int j = (int)(sj - (long long)s * a.NU);
-      row2<KIND, ADAPT, true>(X, Xo, a.plane, row * a.NE, a.NE, s, u_of(j, a.NU), G.h, tab, cb, J,
-                              a.renorm, lane, fl, T, err, emax, phi[p], phi[a.NP + p],
-                              s >= (a.NS >> 1), geo && row == rbeg, sct, sj == sj_prev);
-      sj_prev = sj;
+    for (long long row = rbeg; row < rend;) {
+      const int gn = (int)min(rend - row, (long long)kGroup2);
+      __asm__ volatile("" ::: "memory");   // the previous group's rows have read their blocks
+      if (lane < gn) {
+        const long long r = row + lane;
+        const long long sj = r / a.NP;
+        const int p = (int)(r - sj * a.NP);
+        const int s = (int)(sj / a.NU);
+        const int j = (int)(sj - (long long)s * a.NU);
+        row_setup2<KIND, true>(u_of(j, a.NU), G.h, cb, J, phi[p], phi[a.NP + p], nullptr, true,
+                               rt + lane * kRowC);
+      }
+      __asm__ volatile("" ::: "memory");
+      for (int i = 0; i < gn; ++i, ++row) {
+        const long long sj = row / a.NP;
+        const int s = (int)(sj / a.NU);
+        row2<KIND, ADAPT, true, true>(X, Xo, a.plane, row * a.NE, a.NE, s, 0.0, G.h, tab, cb, J,
+                                      a.renorm, lane, fl, T, err, emax, 0.0, 0.0, s >= (a.NS >> 1), false,
+                                      sct, rt + i * kRowC);
+      }
     }
   } else {
     const long long nrow = (long long)a.NS * a.NU;
@@ -989,9 +988,11 @@ k_advance(StepArgs a) {
   __shared__ I128 sw[WPB][NV];
   __shared__ long long sacc[BS];
   // per wavefront: row constants (mixed: then 32 floats), then the first row's geometry
-  __shared__ double snn_all[WPB][F32 ? 64 : (NF == 2 ? kC2Size : 48)];
+  __shared__ double snn_all[WPB][F32 ? 64 : 48];
   __shared__ long long sfold[WPB][(NC + 2) * 64];
   __shared__ double s_sct[kSinCosTab];   // sin/cos constants of the two-flavour rotations
+  // extended two-flavour model: each wave's row-constant table
+  __shared__ double srt[(NF == 2 && EXT) ? WPB : 1][(NF == 2 && EXT) ? kGroup2 * kRowC : 1];
   extern __shared__ __align__(16) double dyn_tab[];
   // the wavefront index as a wave-uniform (scalar) value: the row indices, their divisions
   // and the row base offsets derived from it then live in scalar registers
@@ -1048,7 +1049,7 @@ k_advance(StepArgs a) {
     if (threadIdx.x < NV) sJ[0][threadIdx.x] = as_double((unsigned long long)a.step_ctl[kCtlMom + threadIdx.x]);
     __syncthreads();
   } else {
-    if constexpr (NF == 2) stage2<0, false, EXT>(a, geo_fixed(a, step0), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct);
+    if constexpr (NF == 2) stage2<0, false, EXT>(a, geo_fixed(a, step0), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, false, srt[EXT ? wid : 0]);
     else if constexpr (F32) stage3m<0, TLDS>(a, geo_fixed(a, step0), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err);
     else { stage3<ST, 0, false, EXT>(a, geo_fixed(a, step0), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     ok = finish_stage_bs<NV, false, NM, BS>(a, epoch++, T, sw, sacc, sJ[0], 0.0, nullptr, nullptr);
@@ -1061,25 +1062,25 @@ k_advance(StepArgs a) {
   record(step0, 0);
   for (long long n = step0; ok && n < step0 + nsteps; ++n) {
     T = i128_zero();
-    if constexpr (NF == 2) stage2<1, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, true);
+    if constexpr (NF == 2) stage2<1, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, true, srt[EXT ? wid : 0]);
     else if constexpr (F32) stage3m<1, TLDS>(a, geo_fixed(a, n), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err, gc);
     else { stage3<ST, 1, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     if (!(ok = finish_stage_bs<NV, false, NM, BS>(a, epoch++, T, sw, sacc, sJ[1], 0.0, nullptr, nullptr))) break;
     record(n, 1);
     T = i128_zero();
-    if constexpr (NF == 2) stage2<2, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, true);
+    if constexpr (NF == 2) stage2<2, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, true, srt[EXT ? wid : 0]);
     else if constexpr (F32) stage3m<2, TLDS>(a, geo_fixed(a, n), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err, gc);
     else { stage3<ST, 2, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     if (!(ok = finish_stage_bs<NV, false, NM, BS>(a, epoch++, T, sw, sacc, sJ[2], 0.0, nullptr, nullptr))) break;
     record(n, 2);
     T = i128_zero();
-    if constexpr (NF == 2) stage2<3, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, true);
+    if constexpr (NF == 2) stage2<3, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, true, srt[EXT ? wid : 0]);
     else if constexpr (F32) stage3m<3, TLDS>(a, geo_fixed(a, n), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err, gc);
     else { stage3<ST, 3, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     if (!(ok = finish_stage_bs<NV, false, NM, BS>(a, epoch++, T, sw, sacc, sJ[3], 0.0, nullptr, nullptr))) break;
     record(n, 3);
     T = i128_zero();
-    if constexpr (NF == 2) stage2<4, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, true);
+    if constexpr (NF == 2) stage2<4, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, true, srt[EXT ? wid : 0]);
     else if constexpr (F32) stage3m<4, TLDS>(a, geo_fixed(a, n), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err, gc);
     else { stage3<ST, 4, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     ok = finish_stage_bs<NV, false, NM, BS>(a, epoch++, T, sw, sacc, sJ[0], 0.0, nullptr, nullptr);
@@ -1141,7 +1142,7 @@ __global__ void __launch_bounds__(kBlock) k_adaptive(StepArgs a) {
   __shared__ double swm[kBlock / 64];
   __shared__ I128 sw[kBlock / 64][NV];
   __shared__ long long sacc[kBlock];
-  __shared__ double snn_all[kBlock / 64][NF == 2 ? kC2Size : 48];   // row constants, then the first row's geometry
+  __shared__ double snn_all[kBlock / 64][48];   // row constants, then the first row's geometry
   __shared__ long long sfold[kBlock / 64][(NC + 2) * 64];
   __shared__ double s_sct[kSinCosTab];   // sin/cos constants of the two-flavour rotations
   extern __shared__ __align__(16) double dyn_tab[];
@@ -1358,7 +1359,7 @@ __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, lon
       const int lr = (int)(row + lane - mrow0);
       const int s = lr / mNU;
       const int j = lr - s * mNU;
-      row_setup2<KIND, false>(u_of(j, mNU), a.h, cb, J, 0.0, 0.0, nullptr, false, true, rt + lane * kRowC);
+      row_setup2<KIND, false>(u_of(j, mNU), a.h, cb, J, 0.0, 0.0, nullptr, true, rt + lane * kRowC);
     }
     __asm__ volatile("" ::: "memory");
     for (int i = 0; i < gn; ++i, ++row) {
@@ -1367,7 +1368,7 @@ __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, lon
       double enone = 0.0;
       row2<KIND, false, false, true>(a.X, a.X, a.plane, mbeam0 + lr * mNE, mNE, s, 0.0, a.h, a.tab + mtab0,
                                      cb, J, a.renorm, lane, fl, T, err, enone, 0.0, 0.0, -1, false, sct,
-                                     false, rt + i * kRowC);
+                                     rt + i * kRowC);
     }
   }
   if (m >= 0 && lane < 6) acc_add(acc_slot(a, epoch, m) + lane * kAccLimbs, T);
