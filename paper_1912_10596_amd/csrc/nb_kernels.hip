@@ -349,7 +349,7 @@ __device__ __forceinline__ void row_setup2(double u, double h, double* cb, const
   const double snmom = (KIND == 0) ? sn0 : ((KIND <= 2) ? snm : sn1);
   if (write) { rc[20] = icmom; rc[21] = (snmom * icmom) * cp; rc[22] = (snmom * icmom) * sp; }
 }
-constexpr int kRowC = 24;    // doubles per row-constant block (23 used)
+constexpr int kRowC = 26;    // doubles per row-constant block (25 used)
 
 // Stage stencil for one (species s, emission bin u) row of NE beams starting at beam rb.
 // KIND: 0 moments of rho_n at r_n; 1 stage Y2 (moments at r_n + h/2); 2 stage Y3
@@ -460,6 +460,125 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
                    err, rc[21], rc[22]);
 }
 
+// A group of gn rows of one model whose beams are contiguous from beam gb0 (NE energies a
+// row), streamed as full 64-lane chunks: lane l of chunk c takes the group's beam
+// f = 64 c + l, row i = f / NE, energy k = f - i NE, and reads its row's constants from the
+// group table rt (row i's block; [kRowS] = species row, [kRowA] = antiparticle flag).  The
+// last chunk of one row and the first of the next share a wavefront instead of leaving
+// lanes idle.  A row's exact sum is folded in the chunk where the row ends (its lanes fold,
+// the others go on with the next row), so every row adds the same integer sum as in row2
+// and the moments keep their bits.  A lane adds at most ceil(NE / 64) + 1 contributions
+// to a row, so with NE <= kGroupMaxNE its 64-bit sums stay below 2^56 as fold_segment needs.
+constexpr int kRowS = 23, kRowA = 24;
+constexpr int kGroupMaxNE = 64 * 31;
+template <int KIND, bool EXT>
+__device__ __forceinline__ void group2(double* X, long long plane, long long gb0, int NE, int gn,
+                                       const double* tab, double* cb, const double* rt, int renorm,
+                                       int lane, long long* fl, I128& T, int& err, const double* sct) {
+  constexpr int NM = EXT ? 4 : 2;
+  const int nbeam = gn * NE;
+  const int nchunk = (nbeam + 63) >> 6;
+  int i = lane / NE;                 // the lane's row and energy in the current chunk
+  int k = lane - i * NE;
+  double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+  if (lane < nbeam) {
+    q0 = X[gb0 + lane]; q1 = X[gb0 + lane + plane]; q2 = X[gb0 + lane + 2 * plane];
+  }
+  unsigned long long acc[3] = {0ull, 0ull, 0ull};
+  unsigned long long cnt = 0;        // contributions in acc (each carries kFixMagic)
+  int r = 0;                         // the oldest unfinished row (wave-uniform)
+  for (int c = 0; c < nchunk; ++c) {
+    const int f = (c << 6) + lane;
+    const bool on = f < nbeam;
+    double P0 = q0, P1 = q1, P2 = q2;
+    if (f + 64 < nbeam) {    // prefetch the lane's next beam
+      q0 = X[gb0 + f + 64]; q1 = X[gb0 + f + 64 + plane]; q2 = X[gb0 + f + 64 + 2 * plane];
+    }
+    __asm__ volatile("" ::: "memory");   // the row constants are re-read from LDS per beam
+    unsigned long long x0 = 0ull, x1 = 0ull, x2 = 0ull;
+    if (on) {
+      const double* rc = rt + i * kRowC;
+      const int sr = (int)rc[kRowS], an = (int)rc[kRowA];
+      if (KIND >= 1) {
+        const double bx = tab[k], bz = tab[NE + k];
+        double f1[3], f2[3], f3[3], f4[3];
+        if (KIND != 3) gen2c(an, bx, bz, rc + 0, f1);
+        if (KIND == 1) {
+          rotate2<true>(0.5 * f1[0], 0.5 * f1[1], 0.5 * f1[2], P0, P1, P2, sct);
+        } else if (KIND == 2) {
+          gen2c(an, bx, bz, rc + 5, f2);
+          const double cr0 = f1[1] * f2[2] - f1[2] * f2[1];
+          const double cr1 = f1[2] * f2[0] - f1[0] * f2[2];
+          const double cr2 = f1[0] * f2[1] - f1[1] * f2[0];
+          rotate2<true>(0.5 * f2[0] - 0.125 * cr0, 0.5 * f2[1] - 0.125 * cr1, 0.5 * f2[2] - 0.125 * cr2,
+                        P0, P1, P2, sct);
+        } else if (KIND == 3) {
+          gen2c(an, bx, bz, rc + 10, f3);
+          rotate2<true>(f3[0], f3[1], f3[2], P0, P1, P2, sct);
+        } else {
+          gen2c(an, bx, bz, rc + 5, f2);
+          gen2c(an, bx, bz, rc + 10, f3);
+          gen2c(an, bx, bz, rc + 15, f4);
+          const double cr0 = f1[1] * f4[2] - f1[2] * f4[1];
+          const double cr1 = f1[2] * f4[0] - f1[0] * f4[2];
+          const double cr2 = f1[0] * f4[1] - f1[1] * f4[0];
+          const double t0 = (((f1[0] + 2.0 * f2[0]) + 2.0 * f3[0]) + f4[0]) * (1.0 / 6.0) - cr0 * (1.0 / 12.0);
+          const double t1 = (((f1[1] + 2.0 * f2[1]) + 2.0 * f3[1]) + f4[1]) * (1.0 / 6.0) - cr1 * (1.0 / 12.0);
+          const double t2 = (((f1[2] + 2.0 * f2[2]) + 2.0 * f3[2]) + f4[2]) * (1.0 / 6.0) - cr2 * (1.0 / 12.0);
+          rotate2<true>(t0, t1, t2, P0, P1, P2, sct);
+          if (renorm) {
+            const double nrm2 = (P0 * P0 + P1 * P1) + P2 * P2;
+            if (!(fabs(nrm2 - 1.0) <= kRenormTol)) err |= 8;
+            const double inv = fma(-0.5, nrm2, 1.5);   // one Newton step for 1/sqrt from 1
+            P0 = P0 * inv;
+            P1 = P1 * inv;
+            P2 = P2 * inv;
+          }
+          X[gb0 + f] = P0;
+          X[gb0 + f + plane] = P1;
+          X[gb0 + f + 2 * plane] = P2;
+        }
+      }
+      // rho~: rho for neutrinos, -rho^* (Bloch (-x, y, -z)) for antineutrinos
+      if (!(fma(P0, P0, fma(P1, P1, P2 * P2)) < 2.0)) err |= 1;
+      const double ws = tab[(size_t)(2 + sr) * NE + k] * cb[kC2Sc + 0];
+      const double wa = an ? -ws : ws;
+      x0 = fix_bits(P0, wa);
+      x1 = fix_bits(P1, ws);
+      x2 = fix_bits(P2, wa);
+    }
+    // fold every row that ends in this chunk (its lanes add their contribution first)
+    const int fend = min(nbeam, (c + 1) << 6);
+    while (r < gn && (r + 1) * NE <= fend) {
+      if (on && i == r) {
+        acc[0] += x0; acc[1] += x1; acc[2] += x2;
+        ++cnt;
+      }
+      const unsigned long long bias = cnt * kFixMagic;
+      const long long sums[3] = {(long long)(acc[0] - bias), (long long)(acc[1] - bias),
+                                 (long long)(acc[2] - bias)};
+      I128 mine = i128_zero();
+      fold_segment<3, NM>(sums, lane, fl, mine);
+      __asm__ volatile("" ::: "memory");
+      const double* rr = rt + r * kRowC;
+      close_row<3, NM>(Scales{cb[kC2Sc + 0], cb[kC2Sc + 1], cb[kC2Sc + 2], cb[kC2Sc + 3]}, lane, mine,
+                       rr[20], T, err, rr[21], rr[22]);
+      acc[0] = acc[1] = acc[2] = 0ull;
+      cnt = 0;
+      ++r;
+    }
+    if (on && i == r) {      // the row that goes on into the next chunk
+      acc[0] += x0; acc[1] += x1; acc[2] += x2;
+      ++cnt;
+    }
+    k += 64;                 // the lane's beam in the next chunk
+    while (k >= NE) {
+      k -= NE;
+      ++i;
+    }
+  }
+}
+
 // rt (extended model): the wavefront's row-constant table of kGroup2 blocks of kRowC.
 constexpr int kGroup2 = 16;
 template <int KIND, bool ADAPT = false, bool EXT = false>
@@ -491,14 +610,21 @@ __device__ __forceinline__ void stage2(const StepArgs& a, const StepGeo& G, cons
         const int j = (int)(sj - (long long)s * a.NU);
         row_setup2<KIND, true>(u_of(j, a.NU), G.h, cb, J, phi[p], phi[a.NP + p], nullptr, true,
                                rt + lane * kRowC);
+        rt[lane * kRowC + kRowS] = (double)s;
+        rt[lane * kRowC + kRowA] = (double)(s >= (a.NS >> 1));
       }
       __asm__ volatile("" ::: "memory");
-      for (int i = 0; i < gn; ++i, ++row) {
-        const long long sj = row / a.NP;
-        const int s = (int)(sj / a.NU);
-        row2<KIND, ADAPT, true, true>(X, Xo, a.plane, row * a.NE, a.NE, s, 0.0, G.h, tab, cb, J,
-                                      a.renorm, lane, fl, T, err, emax, 0.0, 0.0, s >= (a.NS >> 1), false,
-                                      sct, rt + i * kRowC);
+      if (!ADAPT && a.NE <= kGroupMaxNE) {
+        group2<KIND, true>(Xo, a.plane, row * a.NE, a.NE, gn, tab, cb, rt, a.renorm, lane, fl, T, err, sct);
+        row += gn;
+      } else {
+        for (int i = 0; i < gn; ++i, ++row) {
+          const long long sj = row / a.NP;
+          const int s = (int)(sj / a.NU);
+          row2<KIND, ADAPT, true, true>(X, Xo, a.plane, row * a.NE, a.NE, s, 0.0, G.h, tab, cb, J,
+                                        a.renorm, lane, fl, T, err, emax, 0.0, 0.0, s >= (a.NS >> 1), false,
+                                        sct, rt + i * kRowC);
+        }
       }
     }
   } else {
@@ -1360,15 +1486,23 @@ __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, lon
       const int s = lr / mNU;
       const int j = lr - s * mNU;
       row_setup2<KIND, false>(u_of(j, mNU), a.h, cb, J, 0.0, 0.0, nullptr, true, rt + lane * kRowC);
+      rt[lane * kRowC + kRowS] = (double)s;
+      rt[lane * kRowC + kRowA] = (double)s;   // two tracked species: row s is anti iff s = 1
     }
     __asm__ volatile("" ::: "memory");
-    for (int i = 0; i < gn; ++i, ++row) {
-      const long long lr = row - mrow0;
-      const int s = (int)(lr / mNU);
-      double enone = 0.0;
-      row2<KIND, false, false, true>(a.X, a.X, a.plane, mbeam0 + lr * mNE, mNE, s, 0.0, a.h, a.tab + mtab0,
-                                     cb, J, a.renorm, lane, fl, T, err, enone, 0.0, 0.0, -1, false, sct,
-                                     rt + i * kRowC);
+    if (mNE <= kGroupMaxNE) {
+      group2<KIND, false>(a.X, a.plane, mbeam0 + (row - mrow0) * mNE, mNE, gn, a.tab + mtab0, cb, rt,
+                          a.renorm, lane, fl, T, err, sct);
+      row += gn;
+    } else {
+      for (int i = 0; i < gn; ++i, ++row) {
+        const long long lr = row - mrow0;
+        const int s = (int)(lr / mNU);
+        double enone = 0.0;
+        row2<KIND, false, false, true>(a.X, a.X, a.plane, mbeam0 + lr * mNE, mNE, s, 0.0, a.h, a.tab + mtab0,
+                                       cb, J, a.renorm, lane, fl, T, err, enone, 0.0, 0.0, -1, false, sct,
+                                       rt + i * kRowC);
+      }
     }
   }
   if (m >= 0 && lane < 6) acc_add(acc_slot(a, epoch, m) + lane * kAccLimbs, T);
