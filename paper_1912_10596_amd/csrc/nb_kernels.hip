@@ -66,7 +66,7 @@ __device__ __forceinline__ long long chunk_value(unsigned long long field, int k
 // BS: threads per block (the launch's block size), so that the thread groups and every
 // poll address are compile-time constants.
 template <int NV, bool MAXE, int NM, int BS>
-__device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, long long own,
+__device__ __forceinline__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, long long own,
                             unsigned long long efield, double* sJ, long long* sacc, double* sE) {
   constexpr int W = 2 * NV + (MAXE ? 1 : 0);   // words per partial
   constexpr int G = BS / W;                    // thread groups, one chunk position per thread
@@ -141,8 +141,10 @@ __device__ bool grid_reduce(const StepArgs& a, unsigned epoch, I128 blk, long lo
 // Fold the waves' per-lane totals (lane v holds value v) and run the grid reduction.
 // MAXE: also the largest of the lanes' error estimates emax (then swm holds one double per
 // wave and the grid's largest estimate lands in *sE).  BS: threads per block.
+// (always inlined: a call would take the address of the launch arguments and make the
+// compiler keep a private copy of them)
 template <int NV, bool MAXE, int NM, int BS>
-__device__ bool finish_stage_bs(const StepArgs& a, unsigned epoch, I128 T, I128 (*sw)[NV],
+__device__ __forceinline__ bool finish_stage_bs(const StepArgs& a, unsigned epoch, I128 T, I128 (*sw)[NV],
                                 long long* sacc, double* sJ, double emax, double* swm, double* sE) {
   constexpr int WPB = BS / 64;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -595,8 +597,13 @@ __device__ __forceinline__ void stage2(const StepArgs& a, const StepGeo& G, cons
     // contiguous range of rows, in groups of up to kGroup2: lane l computes the constants of
     // the group's row l (row_setup2: geometry, nu-nu terms with the row's azimuth) into the
     // table rt, then the rows run one after the other.
-    const double* phi = a.tab + (size_t)(2 + a.NS) * a.NE;
-    const long long nrow = (long long)a.NS * a.NU * a.NP;
+    // (the launch arguments are read into locals first: the LDS-order barriers below would
+    // otherwise make the compiler re-read them from a private copy of the argument block)
+    const int NE = a.NE, NU = a.NU, NP = a.NP, NS = a.NS, renorm = a.renorm;
+    const long long plane = a.plane;
+    const double h = G.h;
+    const double* phi = a.tab + (size_t)(2 + NS) * NE;
+    const long long nrow = (long long)NS * NU * NP;
     const long long per = (nrow + nw - 1) / nw;
     const long long rbeg = gw * per, rend = min(nrow, rbeg + per);
     for (long long row = rbeg; row < rend;) {
@@ -604,26 +611,24 @@ __device__ __forceinline__ void stage2(const StepArgs& a, const StepGeo& G, cons
       __asm__ volatile("" ::: "memory");   // the previous group's rows have read their blocks
       if (lane < gn) {
         const long long r = row + lane;
-        const long long sj = r / a.NP;
-        const int p = (int)(r - sj * a.NP);
-        const int s = (int)(sj / a.NU);
-        const int j = (int)(sj - (long long)s * a.NU);
-        row_setup2<KIND, true>(u_of(j, a.NU), G.h, cb, J, phi[p], phi[a.NP + p], nullptr, true,
-                               rt + lane * kRowC);
+        const long long sj = r / NP;
+        const int p = (int)(r - sj * NP);
+        const int s = (int)(sj / NU);
+        const int j = (int)(sj - (long long)s * NU);
+        row_setup2<KIND, true>(u_of(j, NU), h, cb, J, phi[p], phi[NP + p], nullptr, true, rt + lane * kRowC);
         rt[lane * kRowC + kRowS] = (double)s;
-        rt[lane * kRowC + kRowA] = (double)(s >= (a.NS >> 1));
+        rt[lane * kRowC + kRowA] = (double)(s >= (NS >> 1));
       }
       __asm__ volatile("" ::: "memory");
-      if (!ADAPT && a.NE <= kGroupMaxNE) {
-        group2<KIND, true>(Xo, a.plane, row * a.NE, a.NE, gn, tab, cb, rt, a.renorm, lane, fl, T, err, sct);
+      if (!ADAPT && NE <= kGroupMaxNE) {
+        group2<KIND, true>(Xo, plane, row * NE, NE, gn, tab, cb, rt, renorm, lane, fl, T, err, sct);
         row += gn;
       } else {
         for (int i = 0; i < gn; ++i, ++row) {
-          const long long sj = row / a.NP;
-          const int s = (int)(sj / a.NU);
-          row2<KIND, ADAPT, true, true>(X, Xo, a.plane, row * a.NE, a.NE, s, 0.0, G.h, tab, cb, J,
-                                        a.renorm, lane, fl, T, err, emax, 0.0, 0.0, s >= (a.NS >> 1), false,
-                                        sct, rt + i * kRowC);
+          const long long sj = row / NP;
+          const int s = (int)(sj / NU);
+          row2<KIND, ADAPT, true, true>(X, Xo, plane, row * NE, NE, s, 0.0, h, tab, cb, J, renorm, lane, fl, T,
+                                        err, emax, 0.0, 0.0, s >= (NS >> 1), false, sct, rt + i * kRowC);
         }
       }
     }
