@@ -473,11 +473,62 @@ __device__ __forceinline__ void row2(const double* X, double* Xo, long long plan
 // to a row, so with NE <= kGroupMaxNE its 64-bit sums stay below 2^56 as fold_segment needs.
 constexpr int kRowS = 23, kRowA = 24;
 constexpr int kGroupMaxNE = 64 * 31;
-template <int KIND, bool EXT>
+// Rows folded together by group2.  The extended model's rows (100 energies) end in most
+// chunks, and a fold and close of one row costs about as many issue slots as of four, so its
+// wavefront folds four rows at a time (60M beams: 2.79 -> 2.45 ms per step).  The batch
+// kernel folds one: its rows are longer (50-400 energies) and at 128 VGPRs the staged
+// totals spill (two rows at a time: 2.88 -> 4.63 ms).
+constexpr int kFoldRowsExt = 4, kFoldRowsBatch = 1;
+// LDS words of a wavefront's fold scratch for group2 with R rows per fold
+__host__ __device__ constexpr int fold2_words(int R) { return (3 * R + 1) * 64; }
+
+// Fold of up to R rows whose lane sums were staged as they ended: component c of slot q in
+// fl[(q * 3 + c) * 64 + lane], q < nrows.  The same integer reduction as fold_segment over
+// 3 R components at once; then lane m * 3 R + q * 3 + c closes moment m, component c of the
+// row in slot q (the row constants rr0 + q * kRowC) exactly as close_row does, into Tq.
+// One set of instructions folds and closes R rows, instead of one per row.
+template <int R, int NM>
+__device__ __forceinline__ void fold_rows2(int lane, long long* fl, int nrows, const double* rr0,
+                                           const Scales& sc, I128& Tq, int& err) {
+  constexpr int NCR = 3 * R, G = 64 / NCR, L = (64 + G - 1) / G;
+  long long* gs = fl + NCR * 64;
+  __asm__ volatile("" ::: "memory");   // the wave's LDS operations complete in program order
+  const int cc = lane % NCR, g = lane / NCR;
+  if (g < G) {
+    long long part = 0;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      const int src = g * L + i;
+      if (src < 64) part += fl[cc * 64 + src];
+    }
+    gs[g * NCR + cc] = part;
+  }
+  __asm__ volatile("" ::: "memory");
+  if (lane < NM * NCR) {
+    const int m = lane / NCR, qc = lane - m * NCR, q = qc / 3;
+    if (q < nrows) {
+      long long t = 0;
+#pragma unroll
+      for (int gg = 0; gg < G; ++gg) t += gs[gg * NCR + qc];
+      const double* rr = rr0 + q * kRowC;
+      if (m == 1) {
+        Tq = i128_add(Tq, i128_from(t));
+      } else {
+        const double f = (m == 0) ? rr[20] : ((m == 2) ? rr[21] : rr[22]);
+        Tq = i128_add(Tq, i128_from(to_fix(f * (i128_to_double(i128_from(t)) * sc.p2e1), sc.s0, kTwo62, err)));
+      }
+    }
+  }
+  __asm__ volatile("" ::: "memory");
+}
+
+template <int KIND, bool EXT, int R>
 __device__ __forceinline__ void group2(double* X, long long plane, long long gb0, int NE, int gn,
                                        const double* tab, double* cb, const double* rt, int renorm,
                                        int lane, long long* fl, I128& T, int& err, const double* sct) {
   constexpr int NM = EXT ? 4 : 2;
+  constexpr int NCR = 3 * R;
+  const Scales sc{cb[kC2Sc + 0], cb[kC2Sc + 1], cb[kC2Sc + 2], cb[kC2Sc + 3]};
   const int nbeam = gn * NE;
   const int nchunk = (nbeam + 63) >> 6;
   int i = lane / NE;                 // the lane's row and energy in the current chunk
@@ -489,6 +540,8 @@ __device__ __forceinline__ void group2(double* X, long long plane, long long gb0
   unsigned long long acc[3] = {0ull, 0ull, 0ull};
   unsigned long long cnt = 0;        // contributions in acc (each carries kFixMagic)
   int r = 0;                         // the oldest unfinished row (wave-uniform)
+  int ns = 0;                        // ended rows staged for the next fold (wave-uniform)
+  I128 Tq = i128_zero();             // closed rows, lane m * 3 R + q * 3 + c (fold_rows2)
   for (int c = 0; c < nchunk; ++c) {
     const int f = (c << 6) + lane;
     const bool on = f < nbeam;
@@ -549,7 +602,8 @@ __device__ __forceinline__ void group2(double* X, long long plane, long long gb0
       x1 = fix_bits(P1, ws);
       x2 = fix_bits(P2, wa);
     }
-    // fold every row that ends in this chunk (its lanes add their contribution first)
+    // stage every row that ends in this chunk (its lanes add their contribution first);
+    // fold R staged rows at a time
     const int fend = min(nbeam, (c + 1) << 6);
     while (r < gn && (r + 1) * NE <= fend) {
       if (on && i == r) {
@@ -557,17 +611,17 @@ __device__ __forceinline__ void group2(double* X, long long plane, long long gb0
         ++cnt;
       }
       const unsigned long long bias = cnt * kFixMagic;
-      const long long sums[3] = {(long long)(acc[0] - bias), (long long)(acc[1] - bias),
-                                 (long long)(acc[2] - bias)};
-      I128 mine = i128_zero();
-      fold_segment<3, NM>(sums, lane, fl, mine);
-      __asm__ volatile("" ::: "memory");
-      const double* rr = rt + r * kRowC;
-      close_row<3, NM>(Scales{cb[kC2Sc + 0], cb[kC2Sc + 1], cb[kC2Sc + 2], cb[kC2Sc + 3]}, lane, mine,
-                       rr[20], T, err, rr[21], rr[22]);
+      long long* slot = fl + ns * 3 * 64 + lane;
+      slot[0] = (long long)(acc[0] - bias);
+      slot[64] = (long long)(acc[1] - bias);
+      slot[128] = (long long)(acc[2] - bias);
       acc[0] = acc[1] = acc[2] = 0ull;
       cnt = 0;
       ++r;
+      if (++ns == R) {
+        fold_rows2<R, NM>(lane, fl, R, rt + (r - R) * kRowC, sc, Tq, err);
+        ns = 0;
+      }
     }
     if (on && i == r) {      // the row that goes on into the next chunk
       acc[0] += x0; acc[1] += x1; acc[2] += x2;
@@ -579,6 +633,23 @@ __device__ __forceinline__ void group2(double* X, long long plane, long long gb0
       ++i;
     }
   }
+  if (ns) fold_rows2<R, NM>(lane, fl, ns, rt + (r - ns) * kRowC, sc, Tq, err);
+  // the closed rows' totals (lane m * 3 R + q * 3 + c) into T (lane m * 3 + c): integer sums
+  __asm__ volatile("" ::: "memory");
+  if (lane < NM * NCR) {
+    fl[2 * lane] = (long long)Tq.lo;
+    fl[2 * lane + 1] = Tq.hi;
+  }
+  __asm__ volatile("" ::: "memory");
+  if (lane < NM * 3) {
+    const int m = lane / 3, c = lane - 3 * m;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int src = m * NCR + q * 3 + c;
+      T = i128_add(T, I128{(unsigned long long)fl[2 * src], fl[2 * src + 1]});
+    }
+  }
+  __asm__ volatile("" ::: "memory");
 }
 
 // rt (extended model): the wavefront's row-constant table of kGroup2 blocks of kRowC.
@@ -621,7 +692,7 @@ __device__ __forceinline__ void stage2(const StepArgs& a, const StepGeo& G, cons
       }
       __asm__ volatile("" ::: "memory");
       if (!ADAPT && NE <= kGroupMaxNE) {
-        group2<KIND, true>(Xo, plane, row * NE, NE, gn, tab, cb, rt, renorm, lane, fl, T, err, sct);
+        group2<KIND, true, kFoldRowsExt>(Xo, plane, row * NE, NE, gn, tab, cb, rt, renorm, lane, fl, T, err, sct);
         row += gn;
       } else {
         for (int i = 0; i < gn; ++i, ++row) {
@@ -1120,7 +1191,8 @@ k_advance(StepArgs a) {
   __shared__ long long sacc[BS];
   // per wavefront: row constants (mixed: then 32 floats), then the first row's geometry
   __shared__ double snn_all[WPB][F32 ? 64 : 48];
-  __shared__ long long sfold[WPB][(NC + 2) * 64];
+  // the two-flavour extended model's rows fold kFoldRowsExt at a time (group2)
+  __shared__ long long sfold[WPB][(NF == 2 && EXT) ? fold2_words(kFoldRowsExt) : (NC + 2) * 64];
   __shared__ double s_sct[kSinCosTab];   // sin/cos constants of the two-flavour rotations
   // extended two-flavour model: each wave's row-constant table
   __shared__ double srt[(NF == 2 && EXT) ? WPB : 1][(NF == 2 && EXT) ? kGroup2 * kRowC : 1];
@@ -1496,7 +1568,7 @@ __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, lon
     }
     __asm__ volatile("" ::: "memory");
     if (mNE <= kGroupMaxNE) {
-      group2<KIND, false>(a.X, a.plane, mbeam0 + (row - mrow0) * mNE, mNE, gn, a.tab + mtab0, cb, rt,
+      group2<KIND, false, kFoldRowsBatch>(a.X, a.plane, mbeam0 + (row - mrow0) * mNE, mNE, gn, a.tab + mtab0, cb, rt,
                           a.renorm, lane, fl, T, err, sct);
       row += gn;
     } else {
@@ -1527,7 +1599,8 @@ __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, lon
 template <int BS>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_batch2(BatchArgs a) {
   __shared__ double sJw[BS / 64][4][6];
-  __shared__ long long sfold[BS / 64][(3 + 2) * 64];
+  // (fold2_words(R) >= 4 * 64 also covers row2's fold_segment<3>: 3 * 64 + 63 words)
+  __shared__ long long sfold[BS / 64][fold2_words(kFoldRowsBatch)];
   __shared__ double scb[BS / 64][kC2Size];
   __shared__ double srt[BS / 64][kGroup * kRowC];   // each wave's row-constant table
   __shared__ double s_sct[kSinCosTab];   // sin/cos constants of the rotations
