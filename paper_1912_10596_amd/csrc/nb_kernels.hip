@@ -479,29 +479,56 @@ constexpr int kGroupMaxNE = 64 * 31;
 // kernel folds one: its rows are longer (50-400 energies) and at 128 VGPRs the staged
 // totals spill (two rows at a time: 2.88 -> 4.63 ms).
 constexpr int kFoldRowsExt = 4, kFoldRowsBatch = 1;
-// LDS words of a wavefront's fold scratch for group2 with R rows per fold
-__host__ __device__ constexpr int fold2_words(int R) { return (3 * R + 1) * 64; }
+// A wavefront's fold scratch for group2 with R rows per fold: 3 R staged components, each
+// in a run of fold2_stride(R) words, then the 3 R G partial sums (G = 64 / 3 R per
+// component).  With R > 1 a run is 64 + G words and lane g of component c adds words g,
+// g + G, ...: the padding puts component c's run G banks after component c - 1's, so these
+// reads meet no bank conflicts (the extended model's 12 components would otherwise read
+// one bank 12-fold; 60M beams 2.43 -> 2.35 ms per step).  With R = 1 (3 components) the
+// plain layout is kept: its index arithmetic costs the batch kernel more in spills than
+// the conflicts (2.89 against 3.04 ms).
+__host__ __device__ constexpr int fold2_stride(int R) { return (R > 1) ? 64 + 64 / (3 * R) : 64; }
+__host__ __device__ constexpr int fold2_words(int R) { return 3 * R * fold2_stride(R) + 64; }
 
 // Fold of up to R rows whose lane sums were staged as they ended: component c of slot q in
-// fl[(q * 3 + c) * 64 + lane], q < nrows.  The same integer reduction as fold_segment over
-// 3 R components at once; then lane m * 3 R + q * 3 + c closes moment m, component c of the
-// row in slot q (the row constants rr0 + q * kRowC) exactly as close_row does, into Tq.
-// One set of instructions folds and closes R rows, instead of one per row.
+// fl[(q * 3 + c) * S + lane], q < nrows, S = fold2_stride(R).  The same integer reduction as
+// fold_segment over 3 R components at once (G partial sums per component, each over every
+// G-th word (R > 1) or over a run of words (R = 1); lane v then adds the G partial sums of
+// its component); then lane
+// m * 3 R + q * 3 + c closes moment m, component c of the row in slot q (the row constants
+// rr0 + q * kRowC) exactly as close_row does, into Tq.  One set of instructions folds and
+// closes R rows, instead of one per row.
 template <int R, int NM>
 __device__ __forceinline__ void fold_rows2(int lane, long long* fl, int nrows, const double* rr0,
                                            const Scales& sc, I128& Tq, int& err) {
-  constexpr int NCR = 3 * R, G = 64 / NCR, L = (64 + G - 1) / G;
-  long long* gs = fl + NCR * 64;
+  constexpr int NCR = 3 * R, G = 64 / NCR, L = (64 + G - 1) / G, S = fold2_stride(R);
+  constexpr bool PAD = R > 1;
+  long long* gs = fl + NCR * S;
   __asm__ volatile("" ::: "memory");   // the wave's LDS operations complete in program order
-  const int cc = lane % NCR, g = lane / NCR;
-  if (g < G) {
-    long long part = 0;
+  // lane (cc, g): partial sum g of component cc, stored at gs[cc * G + g] (R > 1) or
+  // gs[g * NCR + cc] (R = 1)
+  if (PAD) {
+    const int cc = lane / G, g = lane - cc * G;
+    if (cc < NCR) {
+      long long part = 0;
 #pragma unroll
-    for (int i = 0; i < L; ++i) {
-      const int src = g * L + i;
-      if (src < 64) part += fl[cc * 64 + src];
+      for (int i = 0; i < L; ++i) {
+        const int src = i * G + g;
+        if (src < 64) part += fl[cc * S + src];
+      }
+      gs[cc * G + g] = part;
     }
-    gs[g * NCR + cc] = part;
+  } else {
+    const int cc = lane % NCR, g = lane / NCR;
+    if (g < G) {
+      long long part = 0;
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        const int src = g * L + i;
+        if (src < 64) part += fl[cc * S + src];
+      }
+      gs[g * NCR + cc] = part;
+    }
   }
   __asm__ volatile("" ::: "memory");
   if (lane < NM * NCR) {
@@ -509,7 +536,7 @@ __device__ __forceinline__ void fold_rows2(int lane, long long* fl, int nrows, c
     if (q < nrows) {
       long long t = 0;
 #pragma unroll
-      for (int gg = 0; gg < G; ++gg) t += gs[gg * NCR + qc];
+      for (int gg = 0; gg < G; ++gg) t += gs[PAD ? qc * G + gg : gg * NCR + qc];
       const double* rr = rr0 + q * kRowC;
       if (m == 1) {
         Tq = i128_add(Tq, i128_from(t));
@@ -527,7 +554,7 @@ __device__ __forceinline__ void group2(double* X, long long plane, long long gb0
                                        const double* tab, double* cb, const double* rt, int renorm,
                                        int lane, long long* fl, I128& T, int& err, const double* sct) {
   constexpr int NM = EXT ? 4 : 2;
-  constexpr int NCR = 3 * R;
+  constexpr int NCR = 3 * R, S = fold2_stride(R);
   const Scales sc{cb[kC2Sc + 0], cb[kC2Sc + 1], cb[kC2Sc + 2], cb[kC2Sc + 3]};
   const int nbeam = gn * NE;
   const int nchunk = (nbeam + 63) >> 6;
@@ -611,10 +638,10 @@ __device__ __forceinline__ void group2(double* X, long long plane, long long gb0
         ++cnt;
       }
       const unsigned long long bias = cnt * kFixMagic;
-      long long* slot = fl + ns * 3 * 64 + lane;
+      long long* slot = fl + ns * 3 * S + lane;
       slot[0] = (long long)(acc[0] - bias);
-      slot[64] = (long long)(acc[1] - bias);
-      slot[128] = (long long)(acc[2] - bias);
+      slot[S] = (long long)(acc[1] - bias);
+      slot[2 * S] = (long long)(acc[2] - bias);
       acc[0] = acc[1] = acc[2] = 0ull;
       cnt = 0;
       ++r;
@@ -1599,7 +1626,7 @@ __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, lon
 template <int BS>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_batch2(BatchArgs a) {
   __shared__ double sJw[BS / 64][4][6];
-  // (fold2_words(R) >= 4 * 64 also covers row2's fold_segment<3>: 3 * 64 + 63 words)
+  // (fold2_words(R) also covers row2's fold_segment<3>: 3 * 64 + 63 words)
   __shared__ long long sfold[BS / 64][fold2_words(kFoldRowsBatch)];
   __shared__ double scb[BS / 64][kC2Size];
   __shared__ double srt[BS / 64][kGroup * kRowC];   // each wave's row-constant table
