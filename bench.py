@@ -414,7 +414,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint and mixed-precision measurements")
     ap.add_argument("--mixed-literal-steps", type=int, default=2000)
-    ap.add_argument("--section", choices=["batch", "extended", "adjoint", "track_all", "conditioning"],
+    ap.add_argument("--section", choices=["batch", "extended", "adjoint", "track_all", "conditioning",
+                                          "mixed", "adaptive"],
                     help="run only this measurement and print its result (for profiling "
                          "runs; no benchmark line)")
     args = ap.parse_args()
@@ -434,7 +435,9 @@ def main():
               "extended": lambda: extended_timing(nb, workloads),
               "adjoint": lambda: adjoint_timing(nb, workloads),
               "track_all": lambda: track_all_timing(nb, workloads),
-              "conditioning": lambda: conditioning(nb, workloads)}[args.section]
+              "conditioning": lambda: conditioning(nb, workloads),
+              "mixed": lambda: mixed_precision(nb, workloads, args.mixed_literal_steps),
+              "adaptive": lambda: adaptive_timing(nb, workloads)}[args.section]
         res = fn()
         gc.collect()
         torch.cuda.synchronize()
