@@ -492,12 +492,11 @@ __host__ __device__ constexpr int fold2_words(int R) { return 3 * R * fold2_stri
 
 // Fold of up to R rows whose lane sums were staged as they ended: component c of slot q in
 // fl[(q * 3 + c) * S + lane], q < nrows, S = fold2_stride(R).  The same integer reduction as
-// fold_segment over 3 R components at once (G partial sums per component, each over every
-// G-th word (R > 1) or over a run of words (R = 1); lane v then adds the G partial sums of
-// its component); then lane
-// m * 3 R + q * 3 + c closes moment m, component c of the row in slot q (the row constants
-// rr0 + q * kRowC) exactly as close_row does, into Tq.  One set of instructions folds and
-// closes R rows, instead of one per row.
+// fold_segment over 3 R components at once: G partial sums per component, each over every
+// G-th word (R > 1) or over a run of words (R = 1), then lane v adds the G partial sums of
+// its component.  Lane m * 3 R + q * 3 + c then closes moment m, component c of the row in
+// slot q (its row constants at rr0 + q * kRowC) exactly as close_row does, into Tq.  One
+// set of instructions folds and closes R rows, instead of one per row.
 template <int R, int NM>
 __device__ __forceinline__ void fold_rows2(int lane, long long* fl, int nrows, const double* rr0,
                                            const Scales& sc, I128& Tq, int& err) {
@@ -563,7 +562,7 @@ __device__ __forceinline__ void group2(double* X, long long plane, long long gb0
   double q0 = 0.0, q1 = 0.0, q2 = 0.0;
   // PF (batches): the energy tables of a batch's models stay in HBM, so the lane's table
   // values (vacuum terms and weight) for its beam in the next chunk are loaded with that
-  // beam's state, instead of at their use (256-model batch 2.90 -> 2.61 ms per step).  The
+  // beam's state, instead of at their use (256-model batch 2.90 -> 2.53 ms per step).  The
   // extended model reads its tables from LDS.
   constexpr bool PF = !EXT;
   double tx = 0.0, tz = 0.0, tw = 0.0;
