@@ -56,6 +56,31 @@ def test_batch_equals_single_runs_and_oracle(nb, oracle):
             np.testing.assert_array_equal(parts[i], o.pee().reshape(-1), err_msg=f"oracle {i}")
 
 
+def test_batch_short_rows_equal_single_runs(nb, oracle):
+    """Rows shorter than a 64-lane chunk (down to one energy): a chunk holds several rows,
+    a lane's next beam (whose state and table values the batch kernel loads one chunk
+    ahead) lies one or more rows further on, and rows end in every chunk."""
+    ds = []
+    for i, d in enumerate(workloads.batch_256(8)):
+        d = dict(d)
+        d.update(n_energy=(1, 3, 7, 20, 31, 33, 64, 65)[i], n_u=2 + i % 5, n_steps=15,
+                 r_start_km=10.0, r_end_km=10.8)
+        ds.append(d)
+    b = nb.Model(ds)
+    b.run()
+    parts = _split(b.pee().cpu().numpy(), b.offsets())
+    for i, d in enumerate(ds):
+        s = nb.Model(d)
+        s.run()
+        np.testing.assert_array_equal(parts[i], s.pee().cpu().numpy(),
+                                      err_msg=f"model {i} (N_E {d['n_energy']})")
+        if i in (0, 2, 4):
+            o = oracle.Model(d)
+            o.run()
+            np.testing.assert_array_equal(parts[i], o.pee().reshape(-1), err_msg=f"oracle {i}")
+    _say("short-row batch: every model equals its single run")
+
+
 def test_batch_resolved_and_repeatable(nb):
     ds = small_batch(n=9, steps=30, r_start=60.0, r_end=63.0)
     a = nb.Model(ds); a.run()
