@@ -70,6 +70,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        # the library works on torch's device memory and streams, so it must bind to the HIP
+        # runtime torch loads: import torch first (loading the library first would bring in
+        # a second runtime, which then finds no device)
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, dp, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int64
         L.nb_model_create.argtypes = [C.POINTER(Params), C.POINTER(vp)]

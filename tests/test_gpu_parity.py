@@ -139,6 +139,12 @@ CASES = [
     (3, 70, 3, 10, 10.0, 10.5, 0),       # literal bulb start, 2 chunks, ragged tail
     (3, 64, 1, 6, 10.0, 10.3, 1),        # one block
     (3, 129, 4, 4, 40.0, 40.4, 2),
+    # one row per wavefront (2 N_u a multiple of 8, as in the benchmark's launch) with short
+    # last passes of 1-32 busy lanes
+    (3, 80, 4, 12, 10.0, 10.6, 0),       # last pass 16 lanes, one block, literal bulb start
+    (3, 96, 8, 8, 40.0, 40.8, 0),        # 32 lanes, two blocks
+    (3, 400, 4, 6, 10.0, 10.3, 0),       # the benchmark's row length (16 lanes)
+    (3, 65, 12, 6, 60.0, 60.6, 0),       # 1 lane, three blocks
     (2, 2200, 1, 4, 30.0, 30.4, 0),      # rows of two 2048-energy segments
     (3, 2100, 1, 3, 40.0, 40.3, 0),      # two segments; tables (151 KB) read from HBM, not LDS
 ]
