@@ -1635,11 +1635,14 @@ __device__ void batch_stage(const BatchArgs& a, long long n, unsigned epoch, lon
   }
 }
 
-// Four wavefronts per SIMD (128 VGPRs, a 16-byte spill): the rows of a batch are short
-// (50-400 energies), so a wave spends much of its time on row set-up and the first load of
-// each row, which more wavefronts hide.  Measured on the 256-model batch: 4.35 (two
-// wavefronts per SIMD) -> 4.20 (four, 512 threads, 224-byte spill) -> 3.52 (three, 256
-// threads) -> 3.19 ms per step (four, 256 threads, with the wavefront index scalar).
+// Four wavefronts per SIMD (128 VGPRs; the row groups' set-up spills about 230 bytes per
+// lane, outside the chunk loop): the rows of a batch are short (50-400 energies), so a wave
+// spends much of its time on row set-up and the first load of each row, which more
+// wavefronts hide.  Measured on the 256-model batch: 4.35 (two wavefronts per SIMD) -> 4.20
+// (four, 512 threads, 224-byte spill) -> 3.52 (three, 256 threads) -> 3.19 ms per step
+// (four, 256 threads, with the wavefront index scalar); with the lane-parallel row groups,
+// the chunks streamed across rows and the table prefetch 2.53 ms (three wavefronts per SIMD
+// then measure 2.65).
 template <int BS>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_batch2(BatchArgs a) {
   __shared__ double sJw[BS / 64][4][6];
