@@ -21,7 +21,7 @@
 #include "nb_internal.h"
 
 namespace nb {
-template <int NF, typename ST, bool TLDS, bool F32, bool EXT, int BS>
+template <int NF, typename ST, bool TLDS, bool F32, bool EXT, int BS, bool PK>
 __global__ void k_advance(StepArgs a);
 template <int BS>
 __global__ void k_batch2(BatchArgs a);
@@ -588,6 +588,20 @@ static const void* adaptive_kernel(const nb_model* m) {
   return l ? (const void*)&k_adaptive<3, true> : (const void*)&k_adaptive<3, false>;
 }
 
+// Packed row tails (k_advance<..., PK = true>): three flavours with FP64 state and
+// arithmetic, the bulb model, 512 threads, one row per wavefront of a launch of nblocks
+// blocks, N_E = 64 m + t with 1 <= t <= 32 and N_E <= 2048.  The kernel ends with a range
+// error (it does not wait) if launched otherwise.
+static bool packed_tails(const nb_model* m, int nblocks) {
+  const long long ne = m->p.n_energy;
+  return !m->batch && m->nf == 3 && !state_fp32(m) && m->p.n_phi == 0 && nblocks > 0 &&
+         (long long)nblocks * (kBlock / 64) == m->rows && ne > 64 && ne <= 64 * 32 && (ne % 64) != 0 &&
+         (ne % 64) <= 32;
+}
+static const void* packed_kernel(const nb_model* m) {
+  return tab_in_lds(m) ? (const void*)&k_advance<3, double, true, false, false, kBlock, true>
+                       : (const void*)&k_advance<3, double, false, false, false, kBlock, true>;
+}
 // The fixed-step kernel of a model at bs threads per block (512 or 256).
 template <int BS>
 static const void* advance_kernel_bs(const nb_model* m) {
@@ -595,13 +609,16 @@ static const void* advance_kernel_bs(const nb_model* m) {
   const bool l = tab_in_lds(m);
   if (m->nf == 2)
     return m->p.n_phi > 0
-               ? (l ? (const void*)&k_advance<2, double, true, false, true, BS> : (const void*)&k_advance<2, double, false, false, true, BS>)
-               : (l ? (const void*)&k_advance<2, double, true, false, false, BS> : (const void*)&k_advance<2, double, false, false, false, BS>);
+               ? (l ? (const void*)&k_advance<2, double, true, false, true, BS, false> : (const void*)&k_advance<2, double, false, false, true, BS, false>)
+               : (l ? (const void*)&k_advance<2, double, true, false, false, BS, false> : (const void*)&k_advance<2, double, false, false, false, BS, false>);
   if (state_fp32(m))
-    return l ? (const void*)&k_advance<3, float, true, false, false, BS> : (const void*)&k_advance<3, float, false, false, false, BS>;
+    return l ? (const void*)&k_advance<3, float, true, false, false, BS, false> : (const void*)&k_advance<3, float, false, false, false, BS, false>;
   if (m->p.n_phi > 0)
-    return l ? (const void*)&k_advance<3, double, true, false, true, BS> : (const void*)&k_advance<3, double, false, false, true, BS>;
-  return l ? (const void*)&k_advance<3, double, true, false, false, BS> : (const void*)&k_advance<3, double, false, false, false, BS>;
+    return l ? (const void*)&k_advance<3, double, true, false, true, BS, false> : (const void*)&k_advance<3, double, false, false, true, BS, false>;
+  if constexpr (BS == kBlock) {
+    if (packed_tails(m, m->nblocks)) return packed_kernel(m);
+  }
+  return l ? (const void*)&k_advance<3, double, true, false, false, BS, false> : (const void*)&k_advance<3, double, false, false, false, BS, false>;
 }
 static const void* advance_kernel(const nb_model* m, int bs) {
   return bs == kBlockSmall ? advance_kernel_bs<kBlockSmall>(m) : advance_kernel_bs<kBlock>(m);
@@ -610,10 +627,10 @@ static const void* advance_kernel(const nb_model* m, int bs) {
 static const void* advance_kernel_f32(const nb_model* m, int bs) {
   if (m->batch || !state_fp32(m)) return nullptr;
   if (bs == kBlockSmall)
-    return f32_tab_in_lds(m) ? (const void*)&k_advance<3, float, true, true, false, kBlockSmall>
-                             : (const void*)&k_advance<3, float, false, true, false, kBlockSmall>;
-  return f32_tab_in_lds(m) ? (const void*)&k_advance<3, float, true, true, false, kBlock>
-                           : (const void*)&k_advance<3, float, false, true, false, kBlock>;
+    return f32_tab_in_lds(m) ? (const void*)&k_advance<3, float, true, true, false, kBlockSmall, false>
+                             : (const void*)&k_advance<3, float, false, true, false, kBlockSmall, false>;
+  return f32_tab_in_lds(m) ? (const void*)&k_advance<3, float, true, true, false, kBlock, false>
+                           : (const void*)&k_advance<3, float, false, true, false, kBlock, false>;
 }
 
 static int launch_1d(const void* fn, long long n, void** args, hipStream_t s) {
@@ -714,6 +731,11 @@ static int upload_partition(nb_model* m) {
 static int fixed_step_capacity(const nb_model* m, int cus, int bs, int* out) {
   int per = 0;
   NB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, advance_kernel(m, bs), bs, advance_dyn_lds(m)));
+  if (bs == kBlock && !m->batch && m->nf == 3 && !state_fp32(m) && m->p.n_phi == 0) {
+    int ppk = 0;   // the packed-tail variant may take any of these launches
+    NB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&ppk, packed_kernel(m), bs, advance_dyn_lds(m)));
+    per = std::min(per, ppk);
+  }
   if (advance_kernel_f32(m, bs)) {
     int p32 = 0;
     NB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&p32, advance_kernel_f32(m, bs), bs, f32_dyn_lds(m)));

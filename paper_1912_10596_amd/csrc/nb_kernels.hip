@@ -912,12 +912,26 @@ __device__ __forceinline__ double row_lin3(const StepArgs& a, int an, const RowG
 // ADAPT (final update only): the new state goes to Xo instead of X, and emax keeps the
 // largest embedded error estimate |Theta - K2|^2 (traceless part, Frobenius norm).
 // EXT: extended bulb model; rows are (s, j, p) with the azimuth table of the tables.
-template <typename ST, int KIND, bool ADAPT = false, bool EXT = false>
+//
+// PK (packed row tails; three flavours, FP64 fixed steps, stages 1-4, one row per
+// wavefront, 512-thread blocks, N_E = 64 m + t with 1 <= t <= 32 and N_E <= 2048): a row
+// takes m full passes and one pass with t busy lanes.  Wavefronts w and w + 4 of a block
+// share a SIMD (the placement measured on this device), so wavefront w < 4 (the owner) also
+// runs its partner's tail: after its m passes it runs one pass with lanes 0-31 on its own
+// beams 64 m + l and lanes 32-63 on the partner's beams 64 m + l - 32 (with the partner's
+// row constants), and the SIMD issues 2 m + 1 passes instead of 2 m + 2.  The owner adds its
+// tail's contributions to its own lane sums and hands the partner's over through the
+// partner's fold scratch flp as exact integers, so every row adds the same integer sum and
+// the moments keep their bits.  Block barriers: after the row constants (the owner reads
+// its partner's, snp) and before the partner's fold (the handed-over sums).
+template <typename ST, int KIND, bool ADAPT = false, bool EXT = false, bool PK = false>
 __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, long long row, double h,
                                      const Radial& g0, const Radial& gm, const Radial& g1,
                                      const double (*sJ)[EXT ? 32 : 16], const double* tab, double* snn,
                                      int lane, long long* fl, I128& T, int& err, double& emax,
-                                     const ST* pre = nullptr, double* gc = nullptr) {
+                                     const ST* pre = nullptr, double* gc = nullptr, const double* snp = nullptr,
+                                     long long* flp = nullptr, bool owner = false) {
+  static_assert(!PK || (!ADAPT && !EXT && sizeof(ST) == 8 && KIND >= 1), "packed tails: FP64 fixed steps");
   constexpr int NM = EXT ? 4 : 2;
   const long long plane = a.plane;
   const int NE = a.NE;
@@ -944,11 +958,23 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
   if constexpr (KIND >= 1)
     alpha = row_lin3<KIND, ADAPT, EXT>(a, an, rg, g0, gm, g1, sJ[0], sJ[1], sJ[2], sJ[3], sn0, snm, sn1,
                                        cp, sp, snn, alphaE, lane, reinterpret_cast<double*>(fl));
+  if constexpr (PK) {
+    if (lane == 0) {
+      snn[28] = alpha;
+      snn[29] = (double)s;
+    }
+    __syncthreads();   // every row's constants are in place (the owner reads its partner's)
+  }
   const double* G = tab + (size_t)(kVacRows3 + s) * NE;
   const long long rb = row * NE;
+  // PK: the full passes end at kmain; the owner's packed pass takes lane l to beam
+  // kmain + (l & 31) of its own row (l < 32) or its partner's (row + 4)
+  const int kmain = NE & ~63;
+  const bool ton = PK && owner && (lane & 31) < NE - kmain;
+  const long long rbt = (lane >> 5) ? rb + 4LL * NE : rb;
   I128 mine = i128_zero();
   for (int k0 = lane; k0 - lane < NE; k0 += 64 * 32) {
-    const int kend = min(NE, k0 + 64 * 32);
+    const int kend = PK ? kmain : min(NE, k0 + 64 * 32);
     const unsigned long long base = fix_base(k0, kend);
     unsigned long long acc[8] = {base, base, base, base, base, base, base, base};
     ST q[6];
@@ -967,6 +993,9 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
       if (k + 64 < kend) {    // prefetch the lane's next beam
 #pragma unroll
         for (int c = 0; c < 6; ++c) q[c] = X[rb + k + 64 + c * plane];
+      } else if (PK && ton) {   // the lane's beam of the packed pass
+#pragma unroll
+        for (int c = 0; c < 6; ++c) q[c] = X[rbt + kmain + (lane & 31) + c * plane];
       }
       __asm__ volatile("" ::: "memory");   // re-read the row's nn terms from LDS per beam
       if (KIND >= 1) {
@@ -1020,24 +1049,96 @@ __device__ __forceinline__ void row3(const StepArgs& a, const ST* X, ST* Xo, lon
 #pragma unroll
       for (int i = 0; i < 8; ++i) acc[i] += fix_bits(v8[i], (i < 3 || i == 4 || i == 6) ? wa : ws);
     }
-    fold_segment<8, NM>(reinterpret_cast<const long long*>(acc), lane, fl, mine);
+    if constexpr (PK) {
+      if (owner) {
+        // the packed pass: the same arithmetic as a full pass, with each lane's row constants
+        __asm__ volatile("" ::: "memory");
+        unsigned long long x[8] = {kFixMagic, kFixMagic, kFixMagic, kFixMagic,
+                                   kFixMagic, kFixMagic, kFixMagic, kFixMagic};
+        if (ton) {
+          const int hf = lane >> 5, k = kmain + (lane & 31);
+          const double* sl = hf ? snp : snn;
+          const double al = hf ? snp[28] : alpha;
+          const int sh = hf ? (int)snp[29] : s;
+          const int anl = (sh >= (a.NS >> 1)) ? 1 : 0;
+          cplx ps[3] = {mk((double)q[0], (double)q[1]), mk((double)q[2], (double)q[3]),
+                        mk((double)q[4], (double)q[5])};
+          double v[6];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) v[c] = tab[c * NE + k];
+          if (KIND == 1 || KIND == 3) {
+            exp3_apply(lin3q(al, sl, v), ps);
+          } else if (KIND == 2) {
+            exp3_apply(lin3p(al, sl + 9, sl, v, tab[6 * NE + k]), ps);
+          } else {
+            const double ek = tab[6 * NE + k];
+            exp3_apply(lin3p(al, sl + 9, sl, v, ek), ps);
+            if (a.renorm) {
+              const double nrm2 = (norm2(ps[0]) + norm2(ps[1])) + norm2(ps[2]);
+              if (!(fabs(nrm2 - 1.0) <= kRenormTol)) err |= 8;
+              const double inv = fma(-0.5, nrm2, 1.5);   // one Newton step for 1/sqrt from 1
+#pragma unroll
+              for (int c = 0; c < 3; ++c) ps[c] = mk(ps[c].re * inv, ps[c].im * inv);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              Xo[rbt + k + (2 * c) * plane] = (ST)ps[c].re;
+              Xo[rbt + k + (2 * c + 1) * plane] = (ST)ps[c].im;
+            }
+          }
+          const double n0 = norm2(ps[0]), nm = norm2(ps[1]), nt = norm2(ps[2]);
+          const cplx em = cmul_conjb(ps[0], ps[1]), et = cmul_conjb(ps[0], ps[2]), mt = cmul_conjb(ps[1], ps[2]);
+          const double v8[8] = {n0 - nt, nm - nt, em.re, em.im, et.re, et.im, mt.re, mt.im};
+          if (!((n0 + nm) + nt < 2.0)) err |= 1;
+          const double ws = tab[(size_t)(kVacRows3 + sh) * NE + k] * a.s1;
+          const double wa = anl ? -ws : ws;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) x[i] = fix_bits(v8[i], (i < 3 || i == 4 || i == 6) ? wa : ws);
+        }
+        // contributions as integers (less the kFixMagic each carries); idle lanes give 0
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const unsigned long long xv = x[i] - kFixMagic;
+          if (lane >> 5) flp[i * 32 + (lane & 31)] = (long long)xv;
+          else acc[i] += xv;
+        }
+        fold_segment<8, NM>(reinterpret_cast<const long long*>(acc), lane, fl, mine);
+      }
+      __syncthreads();   // the owner's handed-over contributions are in the partner's scratch
+      if (!owner) {
+        if (lane < 32) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) acc[i] += (unsigned long long)fl[i * 32 + lane];
+        }
+        __asm__ volatile("" ::: "memory");
+        fold_segment<8, NM>(reinterpret_cast<const long long*>(acc), lane, fl, mine);
+      }
+    } else {
+      fold_segment<8, NM>(reinterpret_cast<const long long*>(acc), lane, fl, mine);
+    }
   }
   const double snmom = (KIND == 0) ? sn0 : ((KIND <= 2) ? snm : sn1);
   close_row<8, NM>(Scales{a.s1, a.s0, a.p2e1, a.p2e0}, lane, mine, icmom, T, err, (snmom * icmom) * cp,
                    (snmom * icmom) * sp);
 }
 
-template <typename ST, int KIND, bool ADAPT = false, bool EXT = false>
+template <typename ST, int KIND, bool ADAPT = false, bool EXT = false, bool PK = false>
 __device__ __forceinline__ void stage3(const StepArgs& a, const StepGeo& G, const ST* X, ST* Xo,
                                        const double (*sJ)[EXT ? 32 : 16], const double* tab, double* snn,
                                        long long gw, long long nw, int lane, long long* fl, I128& T,
                                        int& err, double& emax, const ST* pre = nullptr,
-                                       double* gc = nullptr) {
+                                       double* gc = nullptr, const double* snp = nullptr,
+                                       long long* flp = nullptr, bool owner = false) {
   const Radial g0 = radial_at(a, G.r0), gm = radial_at(a, G.rm), g1 = radial_at(a, G.r1);
   const long long nrow = (long long)a.NS * a.NU * (EXT ? a.NP : 1);
-  for (long long row = gw; row < nrow; row += nw)
-    row3<ST, KIND, ADAPT, EXT>(a, X, Xo, row, G.h, g0, gm, g1, sJ, tab, snn, lane, fl, T, err, emax,
-                               row == gw ? pre : nullptr, row == gw ? gc : nullptr);
+  if constexpr (PK) {   // one row per wavefront
+    row3<ST, KIND, false, false, true>(a, X, Xo, gw, G.h, g0, gm, g1, sJ, tab, snn, lane, fl, T, err, emax,
+                                       pre, gc, snp, flp, owner);
+  } else {
+    for (long long row = gw; row < nrow; row += nw)
+      row3<ST, KIND, ADAPT, EXT>(a, X, Xo, row, G.h, g0, gm, g1, sJ, tab, snn, lane, fl, T, err, emax,
+                                 row == gw ? pre : nullptr, row == gw ? gc : nullptr);
+  }
 }
 // Load the lane's first beam of the wavefront's first row (the next stage starts there),
 // so that the load completes while the wavefront waits at the grid barrier.
@@ -1220,7 +1321,9 @@ __device__ __forceinline__ void stage3m(const StepArgs& a, const StepGeo& G, con
 // when TLDS (they are read by every row).
 // EXT: the extended bulb model (azimuthal bins, four moments); FP64 only.
 // BS: threads per block (512 or 256; every array and loop bound below is a constant).
-template <int NF, typename ST, bool TLDS, bool F32, bool EXT, int BS>
+// PK: packed row tails (row3); the host launches this variant only when every wavefront of
+// the grid owns exactly one row and the row length qualifies.
+template <int NF, typename ST, bool TLDS, bool F32, bool EXT, int BS, bool PK = false>
 // Register budget: the two-flavour instantiations at 256 threads per block are held to 168
 // VGPRs (three wavefronts per SIMD, three blocks per CU); the others keep the compiler's
 // choice under the 512-thread bound (two wavefronts per SIMD).
@@ -1287,6 +1390,19 @@ k_advance(StepArgs a) {
   // 3f FP64 arithmetic: each stage's first beam is loaded before the preceding barrier
   ST pre[6] = {};
   const long long nrow3 = (long long)a.NS * a.NU * (EXT ? a.NP : 1);
+  if constexpr (PK) {
+    // the packed variant's block barriers need one row per wavefront (uniform over the grid):
+    // a launch that breaks it ends at once with a range error instead of waiting
+    if (!(nrow3 == nw && a.NE > 64 && a.NE <= 64 * 32 && (a.NE & 63) <= 32 && (a.NE & 63) != 0)) {
+      if (threadIdx.x == 0)
+        __hip_atomic_fetch_or(a.sync + kSyncStatus, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+  }
+  // the partner wavefront's constant block and fold scratch (packed tails)
+  const double* snp = snn_all[wid ^ (WPB / 2)];
+  long long* flp = sfold[wid ^ (WPB / 2)];
+  const bool owner = wid < WPB / 2;
   // the stage-1 moments of the current state: left by the previous launch of this variant
   // if it ended at this step (the same values the initial pass would compute), else the
   // initial moment pass
@@ -1311,25 +1427,25 @@ k_advance(StepArgs a) {
     T = i128_zero();
     if constexpr (NF == 2) stage2<1, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, true, srt[EXT ? wid : 0]);
     else if constexpr (F32) stage3m<1, TLDS>(a, geo_fixed(a, n), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err, gc);
-    else { stage3<ST, 1, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
+    else { stage3<ST, 1, false, EXT, PK>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc, snp, flp, owner); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     if (!(ok = finish_stage_bs<NV, false, NM, BS>(a, epoch++, T, sw, sacc, sJ[1], 0.0, nullptr, nullptr))) break;
     record(n, 1);
     T = i128_zero();
     if constexpr (NF == 2) stage2<2, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, true, srt[EXT ? wid : 0]);
     else if constexpr (F32) stage3m<2, TLDS>(a, geo_fixed(a, n), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err, gc);
-    else { stage3<ST, 2, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
+    else { stage3<ST, 2, false, EXT, PK>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc, snp, flp, owner); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     if (!(ok = finish_stage_bs<NV, false, NM, BS>(a, epoch++, T, sw, sacc, sJ[2], 0.0, nullptr, nullptr))) break;
     record(n, 2);
     T = i128_zero();
     if constexpr (NF == 2) stage2<3, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, true, srt[EXT ? wid : 0]);
     else if constexpr (F32) stage3m<3, TLDS>(a, geo_fixed(a, n), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err, gc);
-    else { stage3<ST, 3, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
+    else { stage3<ST, 3, false, EXT, PK>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc, snp, flp, owner); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     if (!(ok = finish_stage_bs<NV, false, NM, BS>(a, epoch++, T, sw, sacc, sJ[3], 0.0, nullptr, nullptr))) break;
     record(n, 3);
     T = i128_zero();
     if constexpr (NF == 2) stage2<4, false, EXT>(a, geo_fixed(a, n), (const double*)a.X, (double*)a.X, sJ, tab, gw, nw, lane, fl, T, err, enone, snn, s_sct, true, srt[EXT ? wid : 0]);
     else if constexpr (F32) stage3m<4, TLDS>(a, geo_fixed(a, n), sJ, tab, ftab, snn, gw, nw, lane, fl, T, err, gc);
-    else { stage3<ST, 4, false, EXT>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
+    else { stage3<ST, 4, false, EXT, PK>(a, geo_fixed(a, n), (const ST*)a.X, (ST*)a.X, sJ, tab, snn, gw, nw, lane, fl, T, err, enone, pre, gc, snp, flp, owner); prefetch_first<ST>(a, gw, nrow3, lane, pre); }
     ok = finish_stage_bs<NV, false, NM, BS>(a, epoch++, T, sw, sacc, sJ[0], 0.0, nullptr, nullptr);
     record(n + 1, 0);
   }
@@ -1370,6 +1486,8 @@ template __global__ void k_advance<2, double, true, false, true, kBlockSmall>(St
 template __global__ void k_advance<2, double, false, false, true, kBlockSmall>(StepArgs);
 template __global__ void k_advance<3, double, true, false, true, kBlockSmall>(StepArgs);
 template __global__ void k_advance<3, double, false, false, true, kBlockSmall>(StepArgs);
+template __global__ void k_advance<3, double, true, false, false, kBlock, true>(StepArgs);
+template __global__ void k_advance<3, double, false, false, false, kBlock, true>(StepArgs);
 
 // --------------------------------------------------------------- adaptive step control
 // One persistent launch integrates from r (step_ctl[kCtlR]) with the step length
