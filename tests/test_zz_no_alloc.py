@@ -49,6 +49,15 @@ def test_static_scratch_equals_workspace_scratch_two_calls(nb):
         np.testing.assert_array_equal(a.pee().cpu().numpy(), b.pee().cpu().numpy())
 
 
+def test_static_scratch_packed_row_tails(nb):
+    """A three-flavour model with one row per wavefront and a short last pass (130 energies,
+    16 rows in two blocks): the stepper's packed-row-tail variant through both entry points."""
+    d = workloads.small_params(n_flavor=3, n_energy=130, n_u=8, n_steps=12, r_start_km=10.0,
+                               r_end_km=10.6)
+    a, b = _pair(nb, d, 12)
+    np.testing.assert_array_equal(a.get_state().cpu().numpy(), b.get_state().cpu().numpy())
+
+
 def test_static_scratch_split_calls_and_batch(nb):
     ds = []
     for d in workloads.batch_256(5):
