@@ -24,6 +24,13 @@ psi 120 B, 2f Bloch vector 120 B.  The same five passes over a full density matr
 reals per beam) would move 360 B for 3f FP64; the line reports that accounting beside
 the one of the stored state.  A device-to-device copy of 1 GiB, timed the same way, gives
 the bandwidth a streaming kernel can reach on the box: the second ceiling.
+
+Clock warm-up: while the device idles (model set-up, host work) its shader clock falls to
+about 2.0 GHz, and it climbs back to the loaded 2.3-2.4 GHz only over the first ~20 ms of
+stepping; the cycles per step stay the same.  Before each timed measurement the model is
+therefore stepped, untimed, for --clock-warmup seconds and then reset to step 0; the W
+warm-up steps and the K timed steps follow from step 0 as without it.  The line records
+the untimed steps and launches this took.
 """
 from __future__ import annotations
 
@@ -47,6 +54,7 @@ KERNEL_SOURCES = ["paper_1912_10596_amd/csrc/nb_kernels.hip",
                   "paper_1912_10596_amd/csrc/nb_device32.h",
                   "paper_1912_10596_amd/csrc/nb_stage.h",
                   "paper_1912_10596_amd/csrc/nb_internal.h"]
+CLOCK_WARMUP_S = 0.3           # --clock-warmup
 
 
 def log(*a):
@@ -64,6 +72,26 @@ def kernel_source_hash() -> str:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def warm_clock(m, seconds: float) -> dict:
+    """Untimed stepping of model m for about `seconds` (launches of 1, 2, 4, ... 32
+    steps, each one nb_step call and one launch), then nb_reset: the shader clock is at
+    its loaded level when the caller's timed launches start from step 0."""
+    steps = launches = 0
+    n_max = min(int(x["n_steps"]) for x in m.ds)
+    t0 = time.perf_counter()
+    k = 1
+    while time.perf_counter() - t0 < seconds:
+        s0 = m.step_index()
+        if s0 + k > n_max:
+            break
+        m.step(k)
+        launches += 1
+        steps += m.step_index() - s0
+        k = min(2 * k, 32)
+    m.reset()
+    return dict(seconds=round(time.perf_counter() - t0, 3), steps=steps, launches=launches)
 
 
 def timed_steps(m, K: int, W: int):
@@ -161,8 +189,7 @@ def batch_timing(nb, workloads, steps: int):
     s = torch.cuda.Stream()
     m = nb.Model(ds, stream=s)
     with torch.cuda.stream(s):
-        m.step(2)                      # warm-up launch
-        m.reset()
+        cw = warm_clock(m, CLOCK_WARMUP_S)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -283,6 +310,7 @@ def extended_timing(nb, workloads):
     for n_u, K in ((10000, 20), (30000, 10)):
         d = workloads.extended_paper(n_u)
         m = nb.Model(d)
+        cw = warm_clock(m, CLOCK_WARMUP_S)
         m.step(2)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -295,7 +323,8 @@ def extended_timing(nb, workloads):
         out[f"n_u_{n_u}"] = dict(
             workload=f"2-flavour extended bulb model, 10 phi x 100 E x {n_u} u x 2 = {m.nb} beams",
             steps=K, ms_per_step=round(s / K * 1e3, 4), beam_steps_per_s=m.nb * K / s,
-            hbm_gbs_algorithmic=round(m.nb * K * bytes_per_beam_step(2, False) / s / 1e9, 1))
+            hbm_gbs_algorithmic=round(m.nb * K * bytes_per_beam_step(2, False) / s / 1e9, 1),
+            clock_warmup=cw)
         del m
         torch.cuda.empty_cache()
     return out
@@ -405,6 +434,7 @@ def cpu_baseline(d: dict, seconds: float):
 
 
 def main():
+    global CLOCK_WARMUP_S
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3000)
@@ -414,11 +444,15 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint and mixed-precision measurements")
     ap.add_argument("--mixed-literal-steps", type=int, default=2000)
+    ap.add_argument("--clock-warmup", type=float, default=CLOCK_WARMUP_S,
+                    help="seconds of untimed stepping (then a reset to step 0) before the "
+                         "headline, batch and extended-model timings; 0 turns it off")
     ap.add_argument("--section", choices=["batch", "extended", "adjoint", "track_all", "conditioning",
                                           "mixed", "adaptive"],
                     help="run only this measurement and print its result (for profiling "
                          "runs; no benchmark line)")
     args = ap.parse_args()
+    CLOCK_WARMUP_S = max(0.0, args.clock_warmup)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this stepper runs on one GPU only (no multi-GPU path is built); "
               "use --gpus 1", file=sys.stderr)
@@ -450,6 +484,7 @@ def main():
         raise SystemExit(f"steps + warmup must be <= {d['n_steps']}")
     m = nb.Model(d)
     log(f"3-flavour model: {m.nb} beams, warmup {W}, timed {K} steps")
+    cw = warm_clock(m, CLOCK_WARMUP_S)
     wall, ev = timed_steps(m, K, W)
     beam_steps = float(m.nb) * K
     value = beam_steps / wall
@@ -491,6 +526,8 @@ def main():
                    "n_flavor": 3, "n_energy": 400, "n_u": 1000, "beams": m.nb,
                    "n0_cm3": d["n0_cm3"], "state": "psi, FP64"},
         "hbm_gbs_algorithmic": round(gbs, 1),
+        "clock_warmup": dict(cw, note="untimed stepping before the W warm-up steps, then the "
+                                      "model reset to step 0"),
         "adjoint_forward_ratio": None,
         "roofline": roof,
     }

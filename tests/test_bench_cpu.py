@@ -59,3 +59,37 @@ def test_traffic_is_used_only_with_matching_sources(monkeypatch):
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
     assert bench.traffic_from_profile("k_advance_3f_fp64_800k", 20, 800000) is None
     assert bench.traffic_from_profile("no_such_kernel", 20, 800000) is None
+
+
+class _CountingModel:
+    """Stands in for a model: counts the steps and resets the clock warm-up asks for."""
+
+    def __init__(self, n_steps):
+        self.ds = [{"n_steps": n_steps}]
+        self.i, self.calls, self.resets = 0, [], 0
+
+    def step_index(self):
+        return self.i
+
+    def step(self, k):
+        self.calls.append(k)
+        self.i = min(self.i + k, self.ds[0]["n_steps"])
+
+    def reset(self):
+        self.resets += 1
+        self.i = 0
+
+
+def test_clock_warmup_stays_within_the_run_and_resets():
+    m = _CountingModel(100)
+    cw = bench.warm_clock(m, 10.0)     # the run's end stops it long before 10 s
+    assert m.calls == [1, 2, 4, 8, 16, 32, 32]
+    assert cw["steps"] == 95 and cw["launches"] == 7
+    assert m.resets == 1 and m.step_index() == 0
+
+
+def test_clock_warmup_off():
+    m = _CountingModel(100)
+    cw = bench.warm_clock(m, 0.0)
+    assert m.calls == [] and cw["steps"] == 0 and cw["launches"] == 0
+    assert m.resets == 1 and m.step_index() == 0
