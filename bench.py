@@ -214,7 +214,7 @@ def batch_timing(nb, workloads, steps: int):
     return dict(workload=f"256 two-flavour models, {beams} beams in one launch, 10 -> 300 km, "
                          f"{steps} of 5000 steps", beam_steps_per_s_eager=beams * steps / eager,
                 ms_per_step_eager=round(eager * 1e3 / steps, 4),
-                ms_per_step_graph=round(graph * 1e3 / (4 * (steps // 4)), 4))
+                ms_per_step_graph=round(graph * 1e3 / (4 * (steps // 4)), 4), clock_warmup=cw)
 
 
 def mixed_precision(nb, workloads, literal_steps: int):
