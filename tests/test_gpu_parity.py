@@ -186,6 +186,20 @@ def test_three_flavor_800k_prefix(nb, oracle):
     np.testing.assert_array_equal(g.get_state().cpu().numpy(), o.get_state())
 
 
+def test_three_flavor_6m_prefix(nb, oracle):
+    """The 6M-beam workload (1000 E x 3000 u x 2, 3 flavours, FP64) in its own launch
+    configuration -- rows of 15 full 64-energy passes and a 40-energy tail, the stepper
+    without packed tails -- for its first 10 steps from the neutrinosphere, every beam bit
+    for bit."""
+    d = workloads.three_flavor_6m()
+    g = nb.Model(d); g.step(10)
+    _say("6M: 10 GPU steps done; oracle")
+    o = oracle.Model(d); o.step(10)
+    pg, po = g.pee().cpu().numpy(), o.pee().reshape(-1)
+    _say(f"6M prefix: min P_ee {po.min():.4f}, max |dPee| = {np.max(np.abs(pg - po)):.3e}")
+    np.testing.assert_array_equal(g.get_state().cpu().numpy(), o.get_state())
+
+
 def test_step_split_and_state_roundtrip_bitwise(nb):
     d = workloads.small_params(n_flavor=3, n_energy=50, n_u=6, n_steps=30)
     a = nb.Model(d); a.run()

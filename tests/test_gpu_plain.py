@@ -50,6 +50,8 @@ def _case(name):
         return workloads.resolved(workloads.three_flavor_800k(), 600.0), 30
     if name == "2f_200k_500km_200st":    # adjoint workload shape, resolved variant
         return workloads.adjoint_200k_resolved(), 200
+    if name == "3f_6m_shape_600km_200st":  # the 6M workload's energy grid and step, 30 angles
+        return dict(workloads.three_flavor_6m_resolved(), n_u=30), 200
     if name == "3f_ext_5phi":
         return workloads.small_params(n_flavor=3, n_energy=11, n_u=4, n_phi=5, n_steps=800,
                                       r_start_km=600.0, r_end_km=1000.0), None
@@ -65,7 +67,8 @@ def _case(name):
 
 
 CASES = ["2f_1024_60_1000km", "3f_37x5_600_1000km", "3f_130x7_two_chunks", "3f_ext_5phi",
-         "3f_track_all", "2f_track_all_xbar", "2f_200k_500km_200st", "3f_800k_600km_30st"]
+         "3f_track_all", "2f_track_all_xbar", "2f_200k_500km_200st", "3f_800k_600km_30st",
+         "3f_6m_shape_600km_200st"]
 
 
 @pytest.mark.parametrize("name", CASES)
