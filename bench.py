@@ -29,8 +29,9 @@ Clock warm-up: while the device idles (model set-up, host work) its shader clock
 about 2.0 GHz, and it climbs back to the loaded 2.3-2.4 GHz only over the first ~20 ms of
 stepping; the cycles per step stay the same.  Before each timed measurement the model is
 therefore stepped, untimed, for --clock-warmup seconds and then reset to step 0; the W
-warm-up steps and the K timed steps follow from step 0 as without it.  The line records
-the untimed steps and launches this took.
+warm-up steps and the K timed steps follow from step 0 as without it.  The batch,
+extended-model and adjoint timings start the same way.  The line records the untimed
+steps and launches this took.
 """
 from __future__ import annotations
 
@@ -158,8 +159,7 @@ def adjoint_timing(nb, workloads):
     import torch
     d = workloads.adjoint_200k_resolved()
     m = nb.Model(d, adjoint_ckpt=64)
-    m.step(8)                          # warm-up launch
-    m.reset()
+    cw = warm_clock(m, CLOCK_WARMUP_S)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     m.run()
@@ -178,7 +178,8 @@ def adjoint_timing(nb, workloads):
                 ckpt=64, forward_s=round(tf, 4), adjoint_s=round(ta, 4),
                 ratio=round(ta / tf, 3), loss="sum of dE/N_u Pee over all beams",
                 grad={k: float(v) for k, v in zip(nb.PARAM_NAMES, g)},
-                grad_times_param={k: float(v * xi) for k, v, xi in zip(nb.PARAM_NAMES, g, x)})
+                grad_times_param={k: float(v * xi) for k, v, xi in zip(nb.PARAM_NAMES, g, x)},
+                clock_warmup=cw)
 
 
 def batch_timing(nb, workloads, steps: int):
@@ -446,7 +447,7 @@ def main():
     ap.add_argument("--mixed-literal-steps", type=int, default=2000)
     ap.add_argument("--clock-warmup", type=float, default=CLOCK_WARMUP_S,
                     help="seconds of untimed stepping (then a reset to step 0) before the "
-                         "headline, batch and extended-model timings; 0 turns it off")
+                         "headline, adjoint, batch and extended-model timings; 0 turns it off")
     ap.add_argument("--section", choices=["batch", "extended", "adjoint", "track_all", "conditioning",
                                           "mixed", "adaptive"],
                     help="run only this measurement and print its result (for profiling "
